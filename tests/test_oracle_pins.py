@@ -1,0 +1,578 @@
+"""Pins of the FP64 oracle against facts fixed outside it.
+
+Every check here compares the oracle with something it does not compute
+itself: crystallographic shell counts, all-pairs enumeration, hand-derived
+region fixtures, library special functions (scipy), closed forms (Racah's
+formula for Gaunt coefficients, the spherical-harmonic addition theorem, the
+Legendre form of the product basis), finite differences, symmetries and
+exact limits of the mixing scheme.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.special as sps
+from scipy.interpolate import BSpline
+
+import oracle as O
+from gen import workloads as W
+from gen.lattice import bcc_cubic, A_W
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ------------------------------------------------------------ neighbours
+
+def test_neighbors_cells_equal_all_pairs():
+    for w in (W.tiny(), W.c1(), W.tiny(periodic=(1, 0, 1), vacuum=3.0, seed=7)):
+        rl = O.r_list(w["model"])
+        o1, n1 = O.neighbors(w["pos"], w["L"], w["periodic"], rl, method=0)
+        o2, n2 = O.neighbors(w["pos"], w["L"], w["periodic"], rl, method=1)
+        assert np.array_equal(o1, o2) and np.array_equal(n1, n2)
+
+
+@pytest.mark.parametrize("r_list,count", [(2.9, 8), (3.3, 14), (4.6, 26), (5.3, 50),
+                                           (5.6, 58), (6.2, 58), (6.4, 64), (6.7, 64)])
+def test_bcc_shell_counts(r_list, count):
+    # bcc shells: 8 @ a*sqrt3/2, 6 @ a, 12 @ a*sqrt2, 24 @ a*sqrt11/2, 8 @ a*sqrt3, 6 @ 2a
+    pos = bcc_cubic(6, 6, 6)
+    L = np.array([6 * A_W] * 3)
+    offs, nbr = O.neighbors(pos, L, [1, 1, 1], r_list)
+    assert np.all(np.diff(offs) == count)
+
+
+def test_neighbor_rows_symmetric():
+    w = W.c1()
+    offs, nbr = O.neighbors(w["pos"], w["L"], w["periodic"], 6.0)
+    pairs = set()
+    for i in range(len(w["pos"])):
+        for j in nbr[offs[i]:offs[i + 1]]:
+            pairs.add((i, int(j)))
+    assert all((j, i) in pairs for (i, j) in pairs)
+
+
+# ----------------------------------------------------------- regions
+
+def _region_fixture():
+    with open(os.path.join(GOLD, "chain_regions.json")) as f:
+        g = json.load(f)
+    regs = [dict(type=r["type"], axis=r["axis"], follow_atom=r["follow_atom"],
+                 center=np.array(r["center"], float), r_core=r["r_core"], r_blend=r["r_blend"])
+            for r in g["regions"]]
+    return g, regs
+
+
+def test_chain_fixture_algorithms_1_to_3():
+    g, regs = _region_fixture()
+    pos = np.array(g["pos"], float)
+    lam, flags = O.lambda_flags(pos, g["L"], g["periodic"], regs)
+    offs, nbr = O.neighbors(pos, g["L"], g["periodic"], g["r_list"])
+    flags = O.buffer_flags(pos, g["L"], g["periodic"], offs, nbr, g["r_buffer"], lam, flags)
+    np.testing.assert_allclose(lam, g["lambda"], rtol=0, atol=1e-15)
+    assert flags.tolist() == g["flags"]
+    assert np.nonzero(flags & 5)[0].tolist() == g["S"]
+
+
+def _closed_form_lambda(pos, L, per, regs):
+    lam = np.zeros(len(pos))
+    for r in regs:
+        c = pos[r["follow_atom"]] if r["follow_atom"] >= 0 else r["center"]
+        d = pos - c
+        for k in range(3):
+            if per[k]:
+                d[:, k] -= L[k] * np.round(d[:, k] / L[k])
+        if r["type"] == 1:
+            d[:, r["axis"]] = 0
+        dist = np.linalg.norm(d, axis=1)
+        b = np.clip(1.0 - (dist - r["r_core"]) / r["r_blend"], 0.0, 1.0) if r["r_blend"] > 0 \
+            else (dist < r["r_core"]).astype(float)
+        lam = np.maximum(lam, b)
+    return lam
+
+
+def test_lambda_closed_form_random_regions():
+    rng = np.random.default_rng(3)
+    w = W.c2()
+    L, per = w["L"], w["periodic"]
+    regs = [W.sphere(rng.uniform(0, 50, 3), rng.uniform(2, 8), rng.uniform(0.5, 3)) for _ in range(4)]
+    regs += [W.cylinder(rng.uniform(0, 50, 3), 1, 5.0, 2.0), W.sphere([0, 0, 0], 4.0, 0.0),
+             W.sphere(None, 3.0, 2.0, follow_atom=17)]
+    regs[-1]["center"] = np.zeros(3)
+    lam, flags = O.lambda_flags(w["pos"], L, per, regs)
+    ref = _closed_form_lambda(w["pos"], L, per, regs)
+    np.testing.assert_allclose(lam, ref, rtol=0, atol=1e-13)
+    assert np.array_equal((flags & 1) != 0, lam > 0)
+    assert np.array_equal((flags & 2) != 0, lam == 1.0)
+
+
+def test_lambda_set_sizes_on_perfect_lattice():
+    # sigma = 0 lattice: |{lambda > 0}| is the number of lattice points strictly
+    # inside the outer sphere, |{lambda == 1}| inside the core sphere.
+    pos = bcc_cubic(10, 10, 10)
+    L = np.array([10 * A_W] * 3)
+    c = np.array([5 * A_W + 0.01, 5 * A_W + 0.02, 5 * A_W + 0.03])
+    lam, flags = O.lambda_flags(pos, L, [1, 1, 1], [W.sphere(c, 6.0, 2.0)])
+    dd = np.linalg.norm(pos - c, axis=1)
+    assert int((flags & 1).astype(bool).sum()) == int((dd < 8.0).sum())
+    assert int(((flags & 2) != 0).sum()) == int((dd < 6.0).sum())
+
+
+def test_buffer_brute_force_all_pairs():
+    for w in (W.c1(), W.tiny(seed=99)):
+        rl = O.r_list(w["model"])
+        offs, nbr = O.neighbors(w["pos"], w["L"], w["periodic"], rl)
+        lam, flags = O.lambda_flags(w["pos"], w["L"], w["periodic"], w["regions"])
+        fb = O.buffer_flags(w["pos"], w["L"], w["periodic"], offs, nbr, w["r_buffer"], lam, flags)
+        pos = w["pos"]
+        d = pos[:, None, :] - pos[None, :, :]
+        for k in range(3):
+            if w["periodic"][k]:
+                d[..., k] -= w["L"][k] * np.round(d[..., k] / w["L"][k])
+        r2 = (d ** 2).sum(-1)
+        np.fill_diagonal(r2, np.inf)
+        inM = lam > 0
+        ref = (~inM) & np.any((r2 < w["r_buffer"] ** 2) & inM[None, :], axis=1)
+        assert np.array_equal((fb & 4) != 0, ref)
+        assert not np.any(((fb & 4) != 0) & inM)
+
+
+# ------------------------------------------------------ special functions
+
+def test_radial_is_chebyshev_times_envelope():
+    rc = 5.0
+    for r in np.linspace(0.3, 4.99, 23):
+        R, dR = O.radial(10, rc, r)
+        x = 2 * r / rc - 1
+        env = (1 - (r / rc) ** 2) ** 2
+        ref = np.cos(np.arange(10) * np.arccos(x)) * env
+        np.testing.assert_allclose(R, ref, atol=1e-13)
+        h = 1e-6
+        Rp, _ = O.radial(10, rc, r + h)
+        Rm, _ = O.radial(10, rc, r - h)
+        np.testing.assert_allclose(dR, (Rp - Rm) / (2 * h), atol=1e-7)
+
+
+def _scipy_real_ylm(lmax, u):
+    th = math.acos(max(-1.0, min(1.0, u[2])))
+    ph = math.atan2(u[1], u[0])
+    out = np.zeros((lmax + 1) ** 2)
+    for l in range(lmax + 1):
+        for m in range(-l, l + 1):
+            mu = abs(m)
+            Yp = complex(sps.sph_harm_y(l, mu, th, ph))   # Condon-Shortley phase included
+            Ym = complex(sps.sph_harm_y(l, -mu, th, ph))
+            if m > 0:
+                v = ((-1) ** mu * Yp + Ym) / math.sqrt(2)
+            elif m < 0:
+                v = ((-1) ** mu * Yp - Ym) / (1j * math.sqrt(2))
+            else:
+                v = Yp
+            assert abs(v.imag) < 1e-12
+            out[l * l + l + m] = v.real
+    return out
+
+
+def test_ylm_matches_scipy_and_gradient():
+    rng = np.random.default_rng(1)
+    for _ in range(20):
+        v = rng.normal(size=3)
+        u = v / np.linalg.norm(v)
+        Y, g = O.ylm(5, u)
+        np.testing.assert_allclose(Y, _scipy_real_ylm(5, u), atol=1e-12)
+        # gradient of Y(r/|r|) with respect to r, projected as the oracle does
+        r = np.linalg.norm(v)
+        G = (g - np.outer((g @ u), u)) / r
+        h = 1e-6
+        for k in range(3):
+            vp = v.copy(); vp[k] += h
+            vm = v.copy(); vm[k] -= h
+            fd = (O.ylm(5, vp / np.linalg.norm(vp))[0] - O.ylm(5, vm / np.linalg.norm(vm))[0]) / (2 * h)
+            np.testing.assert_allclose(G[:, k], fd, atol=1e-7)
+
+
+def test_ylm_addition_theorem_and_orthonormality():
+    rng = np.random.default_rng(2)
+    for _ in range(10):
+        u = rng.normal(size=3); u /= np.linalg.norm(u)
+        Y, _ = O.ylm(6, u)
+        for l in range(7):
+            s = (Y[l * l:(l + 1) ** 2] ** 2).sum()
+            assert abs(s - (2 * l + 1) / (4 * math.pi)) < 1e-13
+    # orthonormality with an independent quadrature (Gauss-Legendre x uniform)
+    x, wx = np.polynomial.legendre.leggauss(12)
+    nph = 24
+    M = np.zeros((36, 36))
+    for zi, wi in zip(x, wx):
+        for k in range(nph):
+            ph = 2 * math.pi * k / nph
+            st = math.sqrt(1 - zi * zi)
+            Y, _ = O.ylm(5, np.array([st * math.cos(ph), st * math.sin(ph), zi]))
+            M += wi * (2 * math.pi / nph) * np.outer(Y, Y)
+    np.testing.assert_allclose(M, np.eye(36), atol=1e-13)
+
+
+def _w3j(j1, j2, j3, m1, m2, m3):
+    """Wigner 3j symbol from Racah's closed form."""
+    if m1 + m2 + m3 != 0 or j3 > j1 + j2 or j3 < abs(j1 - j2):
+        return 0.0
+    if abs(m1) > j1 or abs(m2) > j2 or abs(m3) > j3:
+        return 0.0
+    f = math.factorial
+    tri = f(j1 + j2 - j3) * f(j1 - j2 + j3) * f(-j1 + j2 + j3) / f(j1 + j2 + j3 + 1)
+    pre = math.sqrt(tri * f(j1 + m1) * f(j1 - m1) * f(j2 + m2) * f(j2 - m2) * f(j3 + m3) * f(j3 - m3))
+    s = 0.0
+    for k in range(0, j1 + j2 + j3 + 1):
+        a = [k, j3 - j2 + k + m1, j3 - j1 + k - m2, j1 + j2 - j3 - k, j1 - k - m1, j2 - k + m2]
+        if min(a) < 0:
+            continue
+        s += (-1) ** k / (f(a[0]) * f(a[1]) * f(a[2]) * f(a[3]) * f(a[4]) * f(a[5]))
+    return (-1) ** (j1 - j2 - m3) * pre * s
+
+
+def _U(l):
+    """Real (no Condon-Shortley) from complex (with it) harmonics: Y^R = U Y^C."""
+    U = np.zeros((2 * l + 1, 2 * l + 1), dtype=complex)
+    for m in range(-l, l + 1):
+        i = m + l
+        mu = abs(m)
+        if m > 0:
+            U[i, mu + l] = (-1) ** mu / math.sqrt(2)
+            U[i, -mu + l] = 1 / math.sqrt(2)
+        elif m < 0:
+            U[i, mu + l] = (-1) ** mu / (1j * math.sqrt(2))
+            U[i, -mu + l] = -1 / (1j * math.sqrt(2))
+        else:
+            U[i, l] = 1.0
+    return U
+
+
+def test_gaunt_matches_racah_closed_form():
+    lmax = 4
+    G = O.gaunt_table(lmax)
+    for l1 in range(lmax + 1):
+        for l2 in range(lmax + 1):
+            for l3 in range(lmax + 1):
+                Gc = np.zeros((2 * l1 + 1, 2 * l2 + 1, 2 * l3 + 1))
+                pre = math.sqrt((2 * l1 + 1) * (2 * l2 + 1) * (2 * l3 + 1) / (4 * math.pi)) \
+                    * _w3j(l1, l2, l3, 0, 0, 0)
+                for m1 in range(-l1, l1 + 1):
+                    for m2 in range(-l2, l2 + 1):
+                        for m3 in range(-l3, l3 + 1):
+                            Gc[m1 + l1, m2 + l2, m3 + l3] = pre * _w3j(l1, l2, l3, m1, m2, m3)
+                Gr = np.einsum("ai,bj,ck,ijk->abc", _U(l1), _U(l2), _U(l3), Gc)
+                assert np.abs(Gr.imag).max() < 1e-13
+                sub = G[l1 * l1:(l1 + 1) ** 2, l2 * l2:(l2 + 1) ** 2, l3 * l3:(l3 + 1) ** 2]
+                np.testing.assert_allclose(sub, Gr.real, atol=1e-13)
+
+
+# ----------------------------------------------------- ACE-style potential
+
+def _env(w, i, in_S=None):
+    """Displacements from atom i to its S-neighbours within the expensive cutoff."""
+    m = w["model"]
+    rc = m["ace"]["rcut"]
+    pos = w["pos"]
+    d = pos - pos[i]
+    for k in range(3):
+        if w["periodic"][k]:
+            d[:, k] -= w["L"][k] * np.round(d[:, k] / w["L"][k])
+    r = np.linalg.norm(d, axis=1)
+    sel = (r < rc) & (np.arange(len(pos)) != i)
+    if in_S is not None:
+        sel &= in_S
+    return d[sel], r[sel], w["species"][sel]
+
+
+def _np_radial(n_rad, rc, r):
+    x = 2 * r / rc - 1
+    T = np.polynomial.chebyshev.chebvander(x, n_rad - 1)
+    return T * ((1 - (r / rc) ** 2) ** 2)[:, None]
+
+
+def _model_with_orders(w, keep):
+    import copy
+    w2 = dict(w)
+    m = copy.deepcopy(w["model"])
+    a = m["ace"]
+    if 1 not in keep:
+        a["c1"] = a["c1"] * 0
+    if 2 not in keep:
+        a["c2"] = a["c2"] * 0
+    if 3 not in keep:
+        a["c3"] = a["c3"] * 0
+    w2["model"] = m
+    return w2
+
+
+def test_order1_is_pair_potential():
+    w = _model_with_orders(W.tiny(n_species=2, seed=5), {1})
+    out = O.mixed(w, O.MODE_ALL_EXPENSIVE)
+    a = w["model"]["ace"]
+    for i in range(0, len(w["pos"]), 7):
+        d, r, z = _env(w, i)
+        R = _np_radial(a["n_rad"], a["rcut"], r)
+        E = a["c0"][w["species"][i]]
+        for j in range(len(r)):
+            E += (a["c1"][w["species"][i], z[j] * a["n_rad"]:(z[j] + 1) * a["n_rad"]] * R[j]).sum() \
+                / math.sqrt(4 * math.pi)
+        assert abs(E - out["e_exp"][i]) < 1e-12
+
+
+def test_order2_legendre_closed_form():
+    # sum_m A_alm A_blm = (2l+1)/(4 pi) sum_{j,k} R_a(r_ij) R_b(r_ik) P_l(cos theta_jik)
+    w = _model_with_orders(W.tiny(n_species=2, seed=6), {2})
+    out = O.mixed(w, O.MODE_ALL_EXPENSIVE)
+    a = w["model"]["ace"]
+    nr, lmax = a["n_rad"], a["lmax"]
+    nchan = w["model"]["n_species"] * nr
+    for i in range(0, len(w["pos"]), 5):
+        d, r, z = _env(w, i)
+        u = d / r[:, None]
+        R = _np_radial(nr, a["rcut"], r)
+        phi = np.zeros((len(r), nchan))
+        for j in range(len(r)):
+            phi[j, z[j] * nr:(z[j] + 1) * nr] = R[j]
+        cos = np.clip(u @ u.T, -1, 1)
+        E = a["c0"][w["species"][i]]
+        for l in range(lmax + 1):
+            P = sps.eval_legendre(l, cos) * (2 * l + 1) / (4 * math.pi)
+            Bab = phi.T @ P @ phi
+            for aa in range(nchan):
+                for bb in range(aa, nchan):
+                    E += a["c2"][w["species"][i], l, aa, bb] * Bab[aa, bb]
+        assert abs(E - out["e_exp"][i]) < 1e-11 * max(1.0, abs(E))
+
+
+def test_order3_sphere_integral_form():
+    # sum_m G Y Y Y over three atomic bases equals the sphere integral of the
+    # product of three Legendre-weighted densities:
+    # B = int dO prod_k [ (2l_k+1)/(4pi) sum_j R_{a_k}(r_j) P_{l_k}(u_j . O) ].
+    w = _model_with_orders(W.tiny(seed=8, lmax=2, n_rad=3), {3})
+    out = O.mixed(w, O.MODE_ALL_EXPENSIVE)
+    a = w["model"]["ace"]
+    nr, lmax = a["n_rad"], a["lmax"]
+    L1 = lmax + 1
+    K = nr * L1
+    x, wx = np.polynomial.legendre.leggauss(2 * lmax + 4)
+    nph = 4 * lmax + 6
+    dirs, wts = [], []
+    for zi, wi in zip(x, wx):
+        for k in range(nph):
+            ph = 2 * math.pi * k / nph
+            st = math.sqrt(1 - zi * zi)
+            dirs.append([st * math.cos(ph), st * math.sin(ph), zi])
+            wts.append(wi * 2 * math.pi / nph)
+    dirs = np.array(dirs)
+    wts = np.array(wts)
+    for i in range(0, len(w["pos"]), 9):
+        d, r, z = _env(w, i)
+        u = d / r[:, None]
+        R = _np_radial(nr, a["rcut"], r)
+        cos = u @ dirs.T
+        rho = np.zeros((K, len(dirs)))
+        for aa in range(nr):
+            for l in range(L1):
+                rho[aa * L1 + l] = (2 * l + 1) / (4 * math.pi) * (R[:, aa][:, None] * sps.eval_legendre(l, cos)).sum(0)
+        E = a["c0"][0]
+        for p in range(K):
+            for q in range(p, K):
+                for s in range(q, K):
+                    l1, l2, l3 = p % L1, q % L1, s % L1
+                    if (l1 + l2 + l3) % 2 or l3 > l1 + l2 or l3 < abs(l1 - l2):
+                        continue
+                    E += a["c3"][0, p, q, s] * (wts * rho[p] * rho[q] * rho[s]).sum()
+        assert abs(E - out["e_exp"][i]) < 1e-11 * max(1.0, abs(E))
+
+
+def _fd_forces(w, which, idx, h=1e-5, in_S=None):
+    m = w["model"]
+    rl = O.r_list(m)
+    res = []
+    for i in idx:
+        row = []
+        for k in range(3):
+            Es = []
+            for sgn in (1, -1):
+                p = w["pos"].copy()
+                p[i, k] += sgn * h
+                offs, nbr = O.neighbors(p, w["L"], w["periodic"], rl)
+                if which == "exp":
+                    e, _ = O.ace(m, p, w["species"], w["L"], w["periodic"], offs, nbr, in_S=in_S)
+                    if in_S is not None:
+                        e = e[in_S]
+                else:
+                    e, _ = O.uf3(m, p, w["species"], w["L"], w["periodic"], offs, nbr)
+                Es.append(e.sum())
+            row.append(-(Es[0] - Es[1]) / (2 * h))
+        res.append(row)
+    return np.array(res)
+
+
+@pytest.mark.parametrize("which", ["exp", "cheap"])
+def test_forces_are_minus_gradient(which):
+    w = W.tiny(n_species=2, seed=11)
+    out = O.mixed(w, O.MODE_ALL_EXPENSIVE if which == "exp" else O.MODE_ALL_CHEAP)
+    F = out["f_exp"] if which == "exp" else out["f_cheap"]
+    idx = [0, 3, 20, 41]
+    fd = _fd_forces(w, which, idx)
+    scale = np.abs(F).max()
+    np.testing.assert_allclose(F[idx], fd, atol=2e-8 * max(scale, 1.0))
+
+
+def test_subsystem_forces_are_gradient_of_subsystem_energy():
+    # Algorithm 4 / Fig. 10: with S frozen, F_exp on S is -grad of sum_{i in S} E_i^S.
+    w = W.tiny(seed=13)
+    out = O.mixed(w)
+    in_S = (out["flags"] & 5) != 0
+    S = np.nonzero(in_S)[0]
+    idx = list(S[[0, len(S) // 2, -1]])
+    fd = _fd_forces(w, "exp", idx, in_S=in_S)
+    np.testing.assert_allclose(out["f_exp"][idx], fd, atol=1e-7)
+    assert np.all(out["f_exp"][~in_S] == 0)
+
+
+def test_zero_net_force_and_translation():
+    w = W.tiny(n_species=2, seed=17)
+    for mode, key in ((O.MODE_ALL_EXPENSIVE, "f_exp"), (O.MODE_ALL_CHEAP, "f_cheap")):
+        out = O.mixed(w, mode)
+        assert np.abs(out[key].sum(0)).max() < 1e-11
+        shift = np.array([0.37, -1.21, 2.05])
+        w2 = dict(w)
+        w2["pos"] = w["pos"] + shift
+        for k in range(3):
+            w2["pos"][:, k] %= w["L"][k]
+        w2["regions"] = [dict(r, center=r["center"] + shift) for r in w["regions"]]
+        out2 = O.mixed(w2, mode)
+        np.testing.assert_allclose(out2[key], out[key], atol=1e-11)
+    out = O.mixed(w)
+    assert np.abs(out["f_exp"].sum(0)).max() < 1e-11   # subsystem net force
+
+
+def test_rotation_and_permutation_of_cluster():
+    w = W.tiny(n_species=2, seed=19, periodic=(0, 0, 0), vacuum=30.0)
+    out = O.mixed(w, O.MODE_ALL_EXPENSIVE)
+    outc = O.mixed(w, O.MODE_ALL_CHEAP)
+    rng = np.random.default_rng(0)
+    q, _ = np.linalg.qr(rng.normal(size=(3, 3)))
+    if np.linalg.det(q) < 0:
+        q[:, 0] *= -1
+    c = w["L"] / 2
+    w2 = dict(w)
+    w2["pos"] = (w["pos"] - c) @ q.T + c
+    o2 = O.mixed(w2, O.MODE_ALL_EXPENSIVE)
+    np.testing.assert_allclose(o2["e_exp"], out["e_exp"], atol=1e-11)
+    np.testing.assert_allclose(o2["f_exp"], out["f_exp"] @ q.T, atol=1e-11)
+    o2c = O.mixed(w2, O.MODE_ALL_CHEAP)
+    np.testing.assert_allclose(o2c["e_cheap"], outc["e_cheap"], atol=1e-11)
+    np.testing.assert_allclose(o2c["f_cheap"], outc["f_cheap"] @ q.T, atol=1e-11)
+    perm = rng.permutation(len(w["pos"]))
+    w3 = dict(w)
+    w3["pos"] = w["pos"][perm]
+    w3["species"] = w["species"][perm]
+    o3 = O.mixed(w3, O.MODE_ALL_EXPENSIVE)
+    np.testing.assert_allclose(o3["f_exp"], out["f_exp"][perm], atol=1e-11)
+
+
+def test_mixing_limits_and_locality():
+    w = W.c1()
+    all_e = O.mixed(w, O.MODE_ALL_EXPENSIVE)
+    all_c = O.mixed(w, O.MODE_ALL_CHEAP)
+    # lambda == 1 everywhere: F = F_exp of the whole system, exactly
+    w1 = dict(w, regions=[W.sphere(w["L"] / 2, 100.0, 1.0)])
+    o1 = O.mixed(w1)
+    assert np.all(o1["lam"] == 1.0)
+    assert np.array_equal(o1["forces"], all_e["f_exp"])
+    # lambda == 0 everywhere: F = F_cheap, exactly
+    w0 = dict(w, regions=[W.sphere(w["L"] / 2, 0.1, 0.1)])
+    o0 = O.mixed(w0)
+    assert len(o0["S"]) == 0
+    assert np.array_equal(o0["forces"], all_c["f_cheap"])
+    # locality (buffer equation and the receptive-field remark): atoms with
+    # lambda = 1 whose 2 r_c ball lies in S get the all-expensive force, and
+    # atoms with lambda = 0 get exactly the cheap force.
+    w5 = W.c2()
+    o = O.mixed(w5)
+    rc = w5["model"]["ace"]["rcut"]
+    in_S = (o["flags"] & 5) != 0
+    e_all = O.mixed(w5, O.MODE_ALL_EXPENSIVE, target=(o["lam"] == 1.0).astype(np.uint8))
+    pos = w5["pos"]
+    checked = 0
+    for i in np.nonzero(o["lam"] == 1.0)[0]:
+        d = pos - pos[i]
+        d -= w5["L"] * np.round(d / w5["L"])
+        ball = np.linalg.norm(d, axis=1) < 2 * rc
+        if np.all(in_S[ball]):
+            np.testing.assert_allclose(o["forces"][i], e_all["f_exp"][i], atol=1e-11)
+            checked += 1
+    assert checked > 10
+    zero = o["lam"] == 0
+    assert np.array_equal(o["forces"][zero], o["f_cheap"][zero])
+
+
+# --------------------------------------------------------- UF3-style cheap
+
+def test_bspline_matches_scipy_and_partition_of_unity():
+    for n_pts, top in ((12, 5.0), (6, 3.5), (6, 7.0), (16, 5.5)):
+        t = O.clamped_knots(n_pts, top)
+        assert t[0] == t[3] == 0.0 and t[-1] == t[-4] == top
+        nb = len(t) - 4
+        for x in np.linspace(0.0, top * 0.9999, 37):
+            B, dB = O.bspline(t, x)
+            assert abs(B.sum() - 1.0) < 1e-14
+            for k in range(nb):
+                c = np.zeros(nb); c[k] = 1.0
+                s = BSpline(t, c, 3, extrapolate=False)
+                assert abs(s(x) - B[k]) < 1e-13
+                assert abs(s.derivative()(x) - dB[k]) < 1e-11
+
+
+def test_uf3_tensor_of_ones_counts_pairs_and_triplets():
+    w = W.tiny(seed=23)
+    import copy
+    m = copy.deepcopy(w["model"])
+    u = m["uf3"]
+    u["c2"] = np.ones_like(u["c2"])
+    u["c3"] = np.zeros_like(u["c3"])
+    w2 = dict(w, model=m)
+    rl = O.r_list(m)
+    offs, nbr = O.neighbors(w["pos"], w["L"], w["periodic"], rl)
+    e, _ = O.uf3(m, w["pos"], w["species"], w["L"], w["periodic"], offs, nbr)
+    d, r = [], []
+    for i in range(len(w["pos"])):
+        _, ri, _ = _env(dict(w2, model=dict(m, ace=dict(m["ace"], rcut=u["rcut2"]))), i)
+        assert abs(e[i] - 0.5 * len(ri)) < 1e-12
+    u["c2"] = np.zeros_like(u["c2"])
+    u["c3"] = np.ones_like(u["c3"])
+    e, _ = O.uf3(m, w["pos"], w["species"], w["L"], w["periodic"], offs, nbr)
+    for i in range(len(w["pos"])):
+        _, ri, _ = _env(dict(w2, model=dict(m, ace=dict(m["ace"], rcut=u["rcut3"]))), i)
+        k = len(ri)
+        assert abs(e[i] - k * (k - 1) / 2) < 1e-11
+
+
+# ---------------------------------------------------------- velocity Verlet
+
+def test_vv_time_reversal_and_dt_squared_drift():
+    w = W.tiny(seed=29, sigma=0.05)
+    v0 = w["vel"] * 3.0
+    p1, v1, _ = O.velocity_verlet(w, w["pos"], v0, 1.0, 20, mode=O.MODE_ALL_CHEAP)
+    p2, v2, _ = O.velocity_verlet(w, p1, -v1, 1.0, 20, mode=O.MODE_ALL_CHEAP)
+    d = p2 - w["pos"]
+    d -= w["L"] * np.round(d / w["L"])
+    assert np.abs(d).max() < 1e-9
+    assert np.abs(v2 + v0).max() < 1e-10
+
+    def drift(dt, nsteps):
+        es = []
+
+        def cb(step, pos, vel, out):
+            es.append(out["e_cheap"].sum() + O.kinetic(w, vel))
+        out0 = O.mixed(w, O.MODE_ALL_CHEAP)
+        e0 = out0["e_cheap"].sum() + O.kinetic(w, v0)
+        O.velocity_verlet(w, w["pos"], v0, dt, nsteps, mode=O.MODE_ALL_CHEAP, callback=cb)
+        return max(abs(e - e0) for e in es)
+    d1 = drift(4.0, 10)
+    d2 = drift(2.0, 20)
+    assert 2.5 < d1 / d2 < 6.0   # energy error scales as dt^2 (ratio 4)
