@@ -1,0 +1,230 @@
+/*
+ * mlmix.h — C ABI of the MI355X (gfx950) library for the spatially mixed
+ * force evaluation of ML-MIX (Birks et al., arXiv 2502.19081).
+ *
+ * One call evaluates, on one HIP stream and without a host synchronisation:
+ *   cell-list neighbour search (the neighbour lists the paper's region fix
+ *   reuses; Methods, "Region tracking"),
+ *   the mixing weight lambda_i and masks (Algorithms 1-2, with geometric
+ *   core regions; lambda = max over regions as in Algorithm 2),
+ *   the buffer set (Algorithm 3 and the buffer-set equation of "Spatial
+ *   potential mixing"), stream compaction of S = {lambda > 0} + buffer,
+ *   the expensive ACE-style potential on the induced subsystem S only
+ *   (Algorithm 4 and Fig. 10) with its hand-written adjoint forces
+ *   (forces = minus the derivative of the summed site energies, the
+ *   force/site-energy equation of "Spatial potential mixing"),
+ *   the cheap UF3-style 2+3-body potential on every atom, and the blend
+ *   F_i = lambda_i F_exp,i + (1 - lambda_i) F_cheap,i (Algorithm 4).
+ *
+ * Conventions shared by every entry point
+ *  - Units: Angstrom, eV, amu, fs.
+ *  - Device pointers: every array argument marked [dev] is device memory
+ *    owned by the caller; the library reads inputs and writes outputs and
+ *    keeps no reference after the call returns (work is enqueued on
+ *    `stream`, so the arrays must stay alive until the stream reaches it).
+ *  - Layout: per-atom 3-vectors are SoA, 3 x n doubles: x[0..n), y[0..n),
+ *    z[0..n).
+ *  - stream: a hipStream_t cast to void* (NULL = the null stream).
+ *  - Workspace: caller-owned device memory of at least
+ *    mlmix_workspace_size() bytes, cleared once by mlmix_workspace_init().
+ *    It holds the neighbour list and every intermediate; one workspace per
+ *    independent system (replica). The library allocates no device memory
+ *    except the model tables at mlmix_create().
+ *  - Return value: MLMIX_OK or a negative MLMIX_E_* code for errors detected
+ *    on the host (argument checks). Conditions found on the device
+ *    (neighbour overflow, atom outside a non-periodic box, non-finite
+ *    input) are recorded in the workspace and reported by mlmix_status().
+ *    Nothing aborts or throws across the ABI; mlmix_last_error() gives a
+ *    thread-local message for the last failing call.
+ */
+#ifndef MLMIX_H
+#define MLMIX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MLMIX_OK 0
+#define MLMIX_E_ARG (-1)
+#define MLMIX_E_HIP (-2)
+#define MLMIX_E_WORKSPACE (-3)
+#define MLMIX_E_NEIGH_OVERFLOW (-4)
+#define MLMIX_E_BOX (-5)
+#define MLMIX_E_NONFINITE (-6)
+#define MLMIX_E_STATE (-7)
+
+/* Arithmetic of the two potentials. Positions, lambda, the blend, energy
+ * sums and the integrator are FP64 in every mode. */
+#define MLMIX_FP64 0
+#define MLMIX_FP32 1
+
+/* Evaluation modes (low byte) and flags. */
+#define MLMIX_MODE_MIXED 0          /* lambda from regions, S = {lambda>0} + buffer */
+#define MLMIX_MODE_ALL_EXPENSIVE 1  /* lambda = 1, S = every atom, cheap skipped */
+#define MLMIX_MODE_ALL_CHEAP 2      /* lambda = 0, S empty, expensive skipped */
+#define MLMIX_FORCE_REBUILD 0x100u  /* rebuild the neighbour list now */
+#define MLMIX_ENERGY_ONLY 0x200u    /* stop after the expensive site energies */
+
+/* Device status bits reported by mlmix_status(). */
+#define MLMIX_STATUS_NEIGH_OVERFLOW 1
+#define MLMIX_STATUS_OUT_OF_BOX 2
+#define MLMIX_STATUS_NONFINITE 4
+#define MLMIX_STATUS_TRIPLET_OVERFLOW 8
+#define MLMIX_STATUS_BAD_SPECIES 16
+
+/* Model description (host memory; copied by mlmix_create).
+ *
+ * Expensive ACE-style model (a synthetic stand-in: the paper cites ACE but
+ * does not define it). For a centre atom i of species z_i and neighbours j
+ * in S closer than ace_rcut:
+ *   R_n(r) = T_n(2r/rc - 1) (1 - (r/rc)^2)^2, n < ace_n_rad (Chebyshev T_n)
+ *   A_{a,l,m} = sum_j R_n(r_ij) Y_lm(r_ij/|r_ij|), a = z_j*n_rad + n,
+ *   Y_lm real orthonormal spherical harmonics, l <= ace_lmax;
+ *   E_i = c0[z] + sum_a c1[z][a] A_{a00}
+ *       + sum_{l, a<=b} c2[z][l][a][b] sum_m A_{alm} A_{blm}            (order>=2)
+ *       + sum_{p<=q<=r} c3[z][p][q][r] sum_m G A_{p,m1} A_{q,m2} A_{r,m3} (order 3)
+ *   with p = a*(lmax+1)+l, G the real Gaunt coefficients, and only l-triples
+ *   of even sum that satisfy the triangle rule.
+ *   Arrays (row-major doubles): c0[ns], c1[ns][nchan], c2[ns][lmax+1][nchan]
+ *   [nchan], c3[ns][K][K][K] with nchan = ns*n_rad, K = nchan*(lmax+1);
+ *   entries outside a<=b resp. p<=q<=r are ignored; c3 may be NULL when
+ *   order < 3.
+ * Cheap UF3-style model: clamped uniform cubic B-splines, n_knots points on
+ *   [0, rcut] (n_knots + 2 basis functions).
+ *   E_i = 1/2 sum_j V2^{z_i z_j}(r_ij) + sum_{j<k} V3^{z_i}(r_ij, r_ik, r_jk),
+ *   c2[ns][ns][n_knots2+2] (must be symmetric in the species pair),
+ *   c3[ns][nb][nb][nb] (nb = n_knots3+2; the r_jk axis spans [0, 2 rcut3];
+ *   must be symmetric in its first two basis indices); n_knots3 = 0 turns
+ *   the 3-body term off (c3 may then be NULL). */
+typedef struct {
+    int32_t n_species;
+    int32_t precision; /* MLMIX_FP64 or MLMIX_FP32 */
+    double skin;       /* neighbour-list skin; list radius = max cutoff + skin */
+    int32_t ace_n_rad, ace_lmax, ace_order, ace_pad;
+    double ace_rcut;
+    const double *ace_c0, *ace_c1, *ace_c2, *ace_c3;
+    int32_t uf3_n_knots2, uf3_n_knots3;
+    double uf3_rcut2, uf3_rcut3;
+    const double *uf3_c2, *uf3_c3;
+} mlmix_model_desc;
+
+/* Orthorhombic box [0, L) per dimension. Periodic dimensions need
+ * L >= 2 * list radius; positions must already be wrapped into [0, L)
+ * there. Along non-periodic dimensions atoms must stay inside [0, L). */
+typedef struct {
+    double L[3];
+    int32_t periodic[3];
+    int32_t pad;
+} mlmix_box;
+
+/* Core region (device array of these, 56 bytes each). type 0: sphere about
+ * `center`; type 1: infinite cylinder along coordinate axis `axis` through
+ * `center`. follow_atom >= 0 replaces the centre by that atom's current
+ * position. lambda = 1 for d < r_core, 1 - (d - r_core)/r_blend for
+ * r_core <= d < r_core + r_blend (linear blend of Algorithm 2), else 0;
+ * the atom's lambda is the maximum over regions. */
+typedef struct {
+    int32_t type;
+    int32_t axis;
+    int32_t follow_atom;
+    int32_t pad;
+    double center[3];
+    double r_core;
+    double r_blend;
+} mlmix_region;
+
+typedef struct mlmix_ctx mlmix_ctx;
+
+/* Builds the model tables on the current HIP device. Returns MLMIX_E_ARG for
+ * inconsistent sizes (n_rad 1..16, lmax 0..6, order 1..3, knots >= 4) or
+ * non-symmetric cheap coefficients. */
+int mlmix_create(const mlmix_model_desc *desc, mlmix_ctx **out);
+int mlmix_destroy(mlmix_ctx *ctx);
+
+/* List radius (max cutoff + skin) of the model. */
+double mlmix_list_radius(const mlmix_ctx *ctx);
+
+/* Bytes of workspace for n_atoms atoms, a neighbour-row capacity of nbr_cap
+ * (1..256) and the given box (the cell grid depends on it). */
+int mlmix_workspace_size(const mlmix_ctx *ctx, int32_t n_atoms, int32_t nbr_cap,
+                         const mlmix_box *box, size_t *bytes);
+
+/* Clears the workspace header (status, neighbour-list state) on `stream`.
+ * Must be called once before the first mlmix_compute on a workspace and
+ * again whenever n_atoms, nbr_cap or the box size changes. */
+int mlmix_workspace_init(mlmix_ctx *ctx, void *stream, void *ws, size_t ws_bytes,
+                         int32_t n_atoms, int32_t nbr_cap, const mlmix_box *box);
+
+/* The mixed force evaluation.
+ *  pos [dev] 3 x n double (SoA), species [dev] int32[n] in [0, n_species),
+ *  regions [dev] mlmix_region[n_regions] (ignored unless mode is MIXED),
+ *  r_buffer: buffer radius (Algorithm 3), 0 <= r_buffer <= list radius.
+ * Outputs [dev]: forces 3 x n double (blended; may be NULL with
+ *  MLMIX_ENERGY_ONLY), e_exp[n] (expensive site energies on S, 0 elsewhere),
+ *  e_cheap[n] (cheap site energies, 0 in ALL_EXPENSIVE mode), lambda[n],
+ *  flags[n] (bit0 lambda>0, bit1 lambda==1, bit2 buffer), n_expensive
+ *  int32[2] (|S|, |{lambda>0}|). f_exp and f_cheap (3 x n double) are
+ *  optional (NULL) copies of the two unblended force fields.
+ * The neighbour list is rebuilt when MLMIX_FORCE_REBUILD is set, on the first
+ * call after mlmix_workspace_init, or when an atom moved more than skin/2
+ * since the last rebuild (decided on the device). */
+int mlmix_compute(mlmix_ctx *ctx, void *stream, void *ws, int32_t n_atoms,
+                  const double *pos, const int32_t *species, const mlmix_box *box,
+                  const mlmix_region *regions, int32_t n_regions, double r_buffer,
+                  uint32_t mode, double *forces, double *e_exp, double *e_cheap,
+                  double *lambda, uint8_t *flags, int32_t *n_expensive,
+                  double *f_exp, double *f_cheap);
+
+/* Adjoint of the expensive site energies: grad_pos = d(sum_i w_i E_i)/dx
+ * (3 x n double [dev]) for weights w = grad_e [dev] double[n], using S, the
+ * neighbour list and dE/dA from the last mlmix_compute on this workspace
+ * (the per-neighbour basis is recomputed, not stored). */
+int mlmix_backward(mlmix_ctx *ctx, void *stream, void *ws, int32_t n_atoms,
+                   const double *pos, const int32_t *species, const mlmix_box *box,
+                   const double *grad_e, double *grad_pos);
+
+/* One velocity-Verlet step (FP64): v += dt/2 kappa F/m; x += dt v; wrap;
+ * F = mlmix_compute(x); v += dt/2 kappa F/m. `forces` must hold F(x) on
+ * entry and holds the new forces on return. mass [dev] double[n] (amu),
+ * dt in fs, kappa = 9.648533212e-3 A fs^-2 per eV A^-1 amu^-1.
+ * energies [dev] double[3] receives (sum e_exp, sum e_cheap, kinetic) of
+ * the new state (may be NULL). Other arguments as in mlmix_compute. */
+int mlmix_vv_step(mlmix_ctx *ctx, void *stream, void *ws, int32_t n_atoms, double *pos,
+                  double *vel, const double *mass, const int32_t *species, double dt,
+                  const mlmix_box *box, const mlmix_region *regions, int32_t n_regions,
+                  double r_buffer, uint32_t mode, double *forces, double *e_exp,
+                  double *e_cheap, double *lambda, uint8_t *flags, int32_t *n_expensive,
+                  double *energies);
+
+/* FP64 sums (sum e_exp, sum e_cheap, kinetic energy from vel and mass; vel
+ * and mass may be NULL, kinetic is then 0) into energies [dev] double[3]. */
+int mlmix_energy_reduce(mlmix_ctx *ctx, void *stream, void *ws, int32_t n_atoms,
+                        const double *e_exp, const double *e_cheap, const double *vel,
+                        const double *mass, double *energies);
+
+/* Waits for `stream`, then reads the device status word of the workspace:
+ * *status_bits receives MLMIX_STATUS_* bits, *required_cap the largest
+ * neighbour count seen (for regrowing nbr_cap). Returns MLMIX_OK when no
+ * bit is set, else the matching negative code (overflow first). */
+int mlmix_status(mlmix_ctx *ctx, void *stream, void *ws, int32_t *status_bits,
+                 int32_t *required_cap);
+
+/* Test hooks (device -> device copies, enqueued on stream): the neighbour
+ * rows (int32[n][nbr_cap], ascending j, unused slots -1) and counts, and
+ * the compacted index sets S and M (ascending, int32[n] each, valid up to
+ * the counts written to n_expensive by mlmix_compute). */
+int mlmix_get_neighbors(mlmix_ctx *ctx, void *stream, void *ws, int32_t n_atoms,
+                        int32_t *nbr_out, int32_t *cnt_out);
+int mlmix_get_index_sets(mlmix_ctx *ctx, void *stream, void *ws, int32_t n_atoms,
+                         int32_t *S_out, int32_t *M_out);
+
+/* Thread-local description of the last error. */
+const char *mlmix_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MLMIX_H */

@@ -1,0 +1,197 @@
+"""Python face of the HIP library: a Model (the two potentials' tables on the
+device) and a System (one workspace: the neighbour list and intermediates of
+one set of atoms). Torch tensors carry device memory and streams only; all
+arithmetic runs in libmlmix.so.
+"""
+import ctypes
+
+import numpy as np
+import torch
+
+from . import binding as B
+
+
+def _p(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def make_box(L, periodic):
+    b = B.Box()
+    for k in range(3):
+        b.L[k] = float(L[k])
+        b.periodic[k] = int(periodic[k])
+    return b
+
+
+def pack_regions(regions, device="cuda"):
+    """Region dictionaries (type, axis, follow_atom, center, r_core, r_blend)
+    -> a device byte tensor of mlmix_region structs."""
+    n = max(len(regions), 1)
+    arr = (B.Region * n)()
+    for k, r in enumerate(regions):
+        arr[k].type = int(r["type"])
+        arr[k].axis = int(r["axis"])
+        arr[k].follow_atom = int(r["follow_atom"])
+        for q in range(3):
+            arr[k].center[q] = float(r["center"][q])
+        arr[k].r_core = float(r["r_core"])
+        arr[k].r_blend = float(r["r_blend"])
+    raw = np.frombuffer(bytes(arr), dtype=np.uint8).copy()
+    return torch.from_numpy(raw).to(device)
+
+
+class Model:
+    """Device tables of the ACE-style and UF3-style potentials."""
+
+    def __init__(self, model, precision="fp64"):
+        a, u = model["ace"], model["uf3"]
+        self._keep = [np.ascontiguousarray(x, dtype=np.float64) for x in
+                      (a["c0"], a["c1"], a["c2"], a["c3"], u["c2"], u["c3"])]
+        c0, c1, c2, c3, u2, u3 = self._keep
+        d = B.ModelDesc()
+        d.n_species = int(model["n_species"])
+        d.precision = B.FP64 if precision == "fp64" else B.FP32
+        d.skin = float(model["skin"])
+        d.ace_n_rad, d.ace_lmax, d.ace_order = int(a["n_rad"]), int(a["lmax"]), int(a["order"])
+        d.ace_rcut = float(a["rcut"])
+        d.ace_c0, d.ace_c1, d.ace_c2 = c0.ctypes.data, c1.ctypes.data, c2.ctypes.data
+        d.ace_c3 = c3.ctypes.data if a["order"] >= 3 else None
+        d.uf3_n_knots2, d.uf3_n_knots3 = int(u["n_knots2"]), int(u["n_knots3"])
+        d.uf3_rcut2, d.uf3_rcut3 = float(u["rcut2"]), float(u["rcut3"])
+        d.uf3_c2 = u2.ctypes.data
+        d.uf3_c3 = u3.ctypes.data if u["n_knots3"] > 0 else None
+        self.precision = precision
+        self.n_species = d.n_species
+        h = ctypes.c_void_p()
+        B.check(B.lib().mlmix_create(ctypes.byref(d), ctypes.byref(h)))
+        self.handle = h
+        self.r_list = B.lib().mlmix_list_radius(h)
+
+    def close(self):
+        if self.handle:
+            B.lib().mlmix_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class System:
+    """One workspace: n atoms in an orthorhombic box with a neighbour-row
+    capacity `cap`. Outputs are allocated once and reused between calls."""
+
+    def __init__(self, model, n, L, periodic, cap=128, device="cuda"):
+        self.model = model
+        self.n = int(n)
+        self.cap = int(cap)
+        self.box = make_box(L, periodic)
+        self.device = device
+        sz = ctypes.c_size_t()
+        B.check(B.lib().mlmix_workspace_size(model.handle, self.n, self.cap,
+                                             ctypes.byref(self.box), ctypes.byref(sz)))
+        self.ws_bytes = int(sz.value)
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
+        B.check(B.lib().mlmix_workspace_init(model.handle, _stream(), _p(self.ws), self.ws_bytes,
+                                             self.n, self.cap, ctypes.byref(self.box)))
+        z = dict(dtype=torch.float64, device=device)
+        self.forces = torch.zeros(3, self.n, **z)
+        self.e_exp = torch.zeros(self.n, **z)
+        self.e_cheap = torch.zeros(self.n, **z)
+        self.lam = torch.zeros(self.n, **z)
+        self.flags = torch.zeros(self.n, dtype=torch.uint8, device=device)
+        self.n_exp = torch.zeros(2, dtype=torch.int32, device=device)
+        self.energies = torch.zeros(3, **z)
+        self.regions = pack_regions([], device)
+        self.n_regions = 0
+
+    def set_regions(self, regions):
+        self.regions = pack_regions(regions, self.device)
+        self.n_regions = len(regions)
+
+    def compute(self, pos, species, r_buffer=0.0, mode=B.MODE_MIXED, force_rebuild=False,
+                split=False, energy_only=False):
+        """pos: (3, n) float64 device tensor; species: (n,) int32 device tensor."""
+        assert pos.shape == (3, self.n) and pos.dtype == torch.float64 and pos.is_contiguous()
+        assert species.shape == (self.n,) and species.dtype == torch.int32
+        flags = mode | (B.FORCE_REBUILD if force_rebuild else 0) | (B.ENERGY_ONLY if energy_only else 0)
+        fe = fc = None
+        if split:
+            fe = torch.zeros(3, self.n, dtype=torch.float64, device=self.device)
+            fc = torch.zeros(3, self.n, dtype=torch.float64, device=self.device)
+        B.check(B.lib().mlmix_compute(self.model.handle, _stream(), _p(self.ws), self.n, _p(pos),
+                                      _p(species), ctypes.byref(self.box), _p(self.regions),
+                                      self.n_regions, float(r_buffer), flags,
+                                      None if energy_only else _p(self.forces), _p(self.e_exp),
+                                      _p(self.e_cheap), _p(self.lam), _p(self.flags),
+                                      _p(self.n_exp), _p(fe), _p(fc)))
+        out = dict(forces=self.forces, e_exp=self.e_exp, e_cheap=self.e_cheap, lam=self.lam,
+                   flags=self.flags, n_exp=self.n_exp)
+        if split:
+            out["f_exp"], out["f_cheap"] = fe, fc
+        return out
+
+    def backward(self, pos, species, grad_e, grad_pos):
+        B.check(B.lib().mlmix_backward(self.model.handle, _stream(), _p(self.ws), self.n, _p(pos),
+                                       _p(species), ctypes.byref(self.box), _p(grad_e),
+                                       _p(grad_pos)))
+        return grad_pos
+
+    def vv_step(self, pos, vel, mass, species, dt, r_buffer=0.0, mode=B.MODE_MIXED,
+                force_rebuild=False, energies=True):
+        flags = mode | (B.FORCE_REBUILD if force_rebuild else 0)
+        B.check(B.lib().mlmix_vv_step(self.model.handle, _stream(), _p(self.ws), self.n, _p(pos),
+                                      _p(vel), _p(mass), _p(species), float(dt),
+                                      ctypes.byref(self.box), _p(self.regions), self.n_regions,
+                                      float(r_buffer), flags, _p(self.forces), _p(self.e_exp),
+                                      _p(self.e_cheap), _p(self.lam), _p(self.flags),
+                                      _p(self.n_exp), _p(self.energies) if energies else None))
+
+    def energy_reduce(self, vel=None, mass=None):
+        B.check(B.lib().mlmix_energy_reduce(self.model.handle, _stream(), _p(self.ws), self.n,
+                                            _p(self.e_exp), _p(self.e_cheap), _p(vel), _p(mass),
+                                            _p(self.energies)))
+        return self.energies
+
+    def status(self, raise_on_error=True):
+        bits = ctypes.c_int32()
+        req = ctypes.c_int32()
+        rc = B.lib().mlmix_status(self.model.handle, _stream(), _p(self.ws), ctypes.byref(bits),
+                                  ctypes.byref(req))
+        if raise_on_error:
+            B.check(rc)
+        return int(bits.value), int(req.value), rc
+
+    def neighbors(self):
+        nbr = torch.empty(self.n, self.cap, dtype=torch.int32, device=self.device)
+        cnt = torch.empty(self.n, dtype=torch.int32, device=self.device)
+        B.check(B.lib().mlmix_get_neighbors(self.model.handle, _stream(), _p(self.ws), self.n,
+                                            _p(nbr), _p(cnt)))
+        return nbr, cnt
+
+    def index_sets(self):
+        S = torch.empty(self.n, dtype=torch.int32, device=self.device)
+        M = torch.empty(self.n, dtype=torch.int32, device=self.device)
+        B.check(B.lib().mlmix_get_index_sets(self.model.handle, _stream(), _p(self.ws), self.n,
+                                             _p(S), _p(M)))
+        ns, nm = [int(x) for x in self.n_exp.cpu()]
+        return S[:ns], M[:nm]
+
+
+def system_for(w, model=None, cap=128, device="cuda"):
+    """Model + System + device inputs for a workload dictionary of
+    gen.workloads."""
+    if model is None:
+        model = Model(w["model"], precision=w.get("precision", "fp64"))
+    n = len(w["pos"])
+    sys_ = System(model, n, w["L"], w["periodic"], cap=cap, device=device)
+    sys_.set_regions(w["regions"])
+    pos = torch.from_numpy(np.ascontiguousarray(w["pos"].T)).to(device)
+    species = torch.from_numpy(w["species"].astype(np.int32)).to(device)
+    return model, sys_, pos, species

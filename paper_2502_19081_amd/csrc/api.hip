@@ -1,0 +1,740 @@
+// C ABI of the library: model tables, workspace layout, argument checks and
+// the launch sequence of one mixed force evaluation (see include/mlmix.h).
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "basis.h"
+#include "internal.h"
+
+using namespace mlmix;
+
+struct mlmix_ctx {
+    Ctx c;
+    std::mutex mu;
+    std::unordered_map<void *, WsLayout> ws;
+};
+
+static thread_local std::string g_err;
+
+static int fail(int code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+extern "C" const char *mlmix_last_error(void) { return g_err.c_str(); }
+
+#define HIP_OK(expr)                                                                     \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return fail(MLMIX_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+namespace mlmix {
+
+// ------------------------------------------------------------ tabulation
+
+// Gauss-Legendre nodes and weights on [-1, 1] (Newton on P_N).
+static void gauss_legendre(int N, std::vector<double> &x, std::vector<double> &w)
+{
+    x.resize(N);
+    w.resize(N);
+    for (int i = 0; i < N; ++i) {
+        double z = std::cos(M_PI * (i + 0.75) / (N + 0.5));
+        double dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = z;
+            for (int k = 2; k <= N; ++k) {
+                double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = N * (z * p1 - p0) / (z * z - 1.0);
+            double dz = p1 / dp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-16)
+                break;
+        }
+        double p0 = 1.0, p1 = z;
+        for (int k = 2; k <= N; ++k) {
+            double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+            p0 = p1;
+            p1 = p2;
+        }
+        dp = N * (z * p1 - p0) / (z * z - 1.0);
+        x[i] = z;
+        w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+}
+
+static std::vector<double> ylm_norm(int lmax)
+{
+    int L2 = (lmax + 1) * (lmax + 1);
+    std::vector<double> K(L2);
+    for (int l = 0; l <= lmax; ++l)
+        for (int m = -l; m <= l; ++m) {
+            int am = m < 0 ? -m : m;
+            double r = 1.0;  // (l-|m|)!/(l+|m|)!
+            for (int q = l - am + 1; q <= l + am; ++q)
+                r /= q;
+            double N = std::sqrt((2.0 * l + 1.0) / (4.0 * M_PI) * r);
+            K[l * l + l + m] = (m == 0) ? N : std::sqrt(2.0) * N;
+        }
+    return K;
+}
+
+// Real Gaunt coefficients G[lm1][lm2][lm3] by product quadrature (Gauss-
+// Legendre in cos(theta), uniform in phi), with the same harmonics the
+// kernels evaluate.
+static std::vector<double> gaunt(int lmax, const std::vector<double> &K)
+{
+    int L2 = (lmax + 1) * (lmax + 1);
+    int Nz = 2 * lmax + 3, Np = 4 * lmax + 5;
+    std::vector<double> zx, zw;
+    gauss_legendre(Nz, zx, zw);
+    std::vector<double> G((size_t)L2 * L2 * L2, 0.0), Y(L2);
+    for (int a = 0; a < Nz; ++a)
+        for (int b = 0; b < Np; ++b) {
+            double ph = 2.0 * M_PI * b / Np;
+            double st = std::sqrt(1.0 - zx[a] * zx[a]);
+            double w = zw[a] * 2.0 * M_PI / Np;
+            ylm_stream<double>(lmax, st * std::cos(ph), st * std::sin(ph), zx[a], K.data(),
+                               [&](int lm, double v, double, double, double) { Y[lm] = v; });
+            for (int i = 0; i < L2; ++i)
+                for (int j = 0; j < L2; ++j) {
+                    double wij = w * Y[i] * Y[j];
+                    for (int k = 0; k < L2; ++k)
+                        G[((size_t)i * L2 + j) * L2 + k] += wij * Y[k];
+                }
+        }
+    return G;
+}
+
+struct HostTables {
+    std::vector<double> K, c0, c1, c2s, W, gval, u2, u3;
+    std::vector<PBlock> pb;
+    std::vector<int> gm3, gidx;
+    int w_per_species = 0;
+};
+
+static int build_tables(const mlmix_model_desc &d, HostTables &t)
+{
+    const int ns = d.n_species, nr = d.ace_n_rad, lmax = d.ace_lmax;
+    const int L1 = lmax + 1, L2 = L1 * L1, nch = ns * nr, K3 = nch * L1;
+    t.K = ylm_norm(lmax);
+    t.c0.assign(d.ace_c0, d.ace_c0 + ns);
+    t.c1.assign(d.ace_c1, d.ace_c1 + (size_t)ns * nch);
+    t.c2s.assign((size_t)ns * L1 * nch * nch, 0.0);
+    if (d.ace_order >= 2) {
+        for (int z = 0; z < ns; ++z)
+            for (int l = 0; l < L1; ++l)
+                for (int a = 0; a < nch; ++a)
+                    for (int b = 0; b < nch; ++b) {
+                        int lo = std::min(a, b), hi = std::max(a, b);
+                        double v = d.ace_c2[(((size_t)z * L1 + l) * nch + lo) * nch + hi];
+                        t.c2s[(((size_t)z * L1 + l) * nch + a) * nch + b] = (a == b) ? v : 0.5 * v;
+                    }
+    }
+    if (d.ace_order >= 3) {
+        std::vector<double> G = gaunt(lmax, t.K);
+        for (int l3 = 0; l3 <= lmax; ++l3)
+            for (int l1 = 0; l1 <= lmax; ++l1)
+                for (int l2 = l1; l2 <= lmax; ++l2) {
+                    if ((l1 + l2 + l3) & 1)
+                        continue;
+                    if (l3 > l1 + l2 || l3 < l2 - l1)
+                        continue;
+                    PBlock p{};
+                    p.l1 = l1;
+                    p.l2 = l2;
+                    p.l3 = l3;
+                    p.w_off = t.w_per_species;
+                    p.gm3_off = (int)t.gm3.size();
+                    for (int m3 = 0; m3 < 2 * l3 + 1; ++m3) {
+                        t.gm3.push_back((int)t.gidx.size());
+                        for (int m1 = 0; m1 < 2 * l1 + 1; ++m1)
+                            for (int m2 = 0; m2 < 2 * l2 + 1; ++m2) {
+                                double v = G[((size_t)(l1 * l1 + m1) * L2 + (l2 * l2 + m2)) * L2 +
+                                             (l3 * l3 + m3)];
+                                if (std::fabs(v) > 1e-12) {
+                                    t.gidx.push_back(m1 | (m2 << 8));
+                                    t.gval.push_back(v);
+                                }
+                            }
+                    }
+                    t.gm3.push_back((int)t.gidx.size());
+                    t.pb.push_back(p);
+                    t.w_per_species += nch * nch * nch;
+                }
+        // W[z][block][ab][c]: the symmetric coefficient C_{alpha beta gamma} =
+        // c3[sorted] / (number of distinct orderings), doubled for l1 < l2 (the
+        // (l2, l1) ordering gives the same contribution).
+        t.W.assign((size_t)ns * t.w_per_species, 0.0);
+        for (int z = 0; z < ns; ++z)
+            for (const PBlock &p : t.pb)
+                for (int a = 0; a < nch; ++a)
+                    for (int b = 0; b < nch; ++b)
+                        for (int c = 0; c < nch; ++c) {
+                            int al = a * L1 + p.l1, be = b * L1 + p.l2, ga = c * L1 + p.l3;
+                            int s[3] = {al, be, ga};
+                            std::sort(s, s + 3);
+                            int mult = (s[0] == s[2]) ? 1 : ((s[0] == s[1] || s[1] == s[2]) ? 3 : 6);
+                            double v = d.ace_c3[(((size_t)z * K3 + s[0]) * K3 + s[1]) * K3 + s[2]] / mult;
+                            if (p.l1 < p.l2)
+                                v *= 2.0;
+                            t.W[(size_t)z * t.w_per_species + p.w_off + ((size_t)a * nch + b) * nch + c] = v;
+                        }
+    }
+    // cheap model
+    int nb2 = d.uf3_n_knots2 + 2;
+    t.u2.assign(d.uf3_c2, d.uf3_c2 + (size_t)ns * ns * nb2);
+    for (int a = 0; a < ns; ++a)
+        for (int b = 0; b < ns; ++b)
+            for (int q = 0; q < nb2; ++q)
+                if (t.u2[((size_t)a * ns + b) * nb2 + q] != t.u2[((size_t)b * ns + a) * nb2 + q])
+                    return fail(MLMIX_E_ARG, "uf3_c2 is not symmetric in the species pair");
+    if (d.uf3_n_knots3 > 0) {
+        int nb3 = d.uf3_n_knots3 + 2;
+        t.u3.assign(d.uf3_c3, d.uf3_c3 + (size_t)ns * nb3 * nb3 * nb3);
+        for (int z = 0; z < ns; ++z)
+            for (int p = 0; p < nb3; ++p)
+                for (int q = 0; q < nb3; ++q)
+                    for (int s = 0; s < nb3; ++s)
+                        if (t.u3[(((size_t)z * nb3 + p) * nb3 + q) * nb3 + s] !=
+                            t.u3[(((size_t)z * nb3 + q) * nb3 + p) * nb3 + s])
+                            return fail(MLMIX_E_ARG, "uf3_c3 is not symmetric in its first two indices");
+    }
+    return MLMIX_OK;
+}
+
+template <typename T>
+static void append(std::vector<char> &blob, size_t &off, const std::vector<double> &v)
+{
+    off = (blob.size() + 255) & ~(size_t)255;
+    blob.resize(off + v.size() * sizeof(T) + 16);
+    T *p = reinterpret_cast<T *>(blob.data() + off);
+    for (size_t i = 0; i < v.size(); ++i)
+        p[i] = T(v[i]);
+}
+
+template <typename I>
+static void append_raw(std::vector<char> &blob, size_t &off, const std::vector<I> &v)
+{
+    off = (blob.size() + 255) & ~(size_t)255;
+    blob.resize(off + v.size() * sizeof(I) + 16);
+    if (!v.empty())
+        std::memcpy(blob.data() + off, v.data(), v.size() * sizeof(I));
+}
+
+template <typename T>
+static std::vector<char> pack(const HostTables &t, DevModel &m)
+{
+    std::vector<char> blob;
+    append<T>(blob, m.ylmK, t.K);
+    append<T>(blob, m.c0, t.c0);
+    append<T>(blob, m.c1, t.c1);
+    append<T>(blob, m.c2s, t.c2s);
+    append<T>(blob, m.W, t.W);
+    append<T>(blob, m.gval, t.gval);
+    append_raw(blob, m.pb, t.pb);
+    append_raw(blob, m.gm3, t.gm3);
+    append_raw(blob, m.gidx, t.gidx);
+    append<T>(blob, m.u2, t.u2);
+    append<T>(blob, m.u3, t.u3);
+    return blob;
+}
+
+void pb_ranges(const Ctx &c, int *lo, int *hi)
+{
+    for (int l = 0; l <= kMaxLmax; ++l) {
+        lo[l] = 0;
+        hi[l] = 0;
+    }
+    // blocks are ordered by l3; the per-l3 ranges are stored at creation
+    for (int l = 0; l <= c.m.lmax; ++l) {
+        lo[l] = c.m_pb_lo[l];
+        hi[l] = c.m_pb_hi[l];
+    }
+}
+
+Grid make_grid(const Ctx &c, const Box &b)
+{
+    Grid g;
+    double half = 0.5 * c.r_list;
+    g.ncell = 1;
+    for (int k = 0; k < 3; ++k) {
+        int nc = (int)std::floor(b.L[k] / half);
+        if (nc < 1)
+            nc = 1;
+        g.nc[k] = nc;
+        g.cs[k] = b.L[k] / nc;
+        g.ncell *= nc;
+    }
+    return g;
+}
+
+static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+WsLayout make_layout(const Ctx &c, int n, int cap, const Box &b)
+{
+    WsLayout L{};
+    L.n = n;
+    L.cap = cap;
+    int P = 1;
+    while (P < cap)
+        P <<= 1;
+    L.P = P;
+    L.grid = make_grid(c, b);
+    size_t tsz = c.prec == MLMIX_FP64 ? 8 : 4;
+    size_t off = 0;
+    auto take = [&](size_t &field, size_t bytes) {
+        field = off;
+        off = align_up(off + bytes);
+    };
+    size_t nn = (size_t)(n > 0 ? n : 1);
+    int nbc = (L.grid.ncell + kScanTile - 1) / kScanTile;
+    int nba = (n + kScanTile - 1) / kScanTile;
+    int nsp = std::max(nbc, 2 * nba) + 2;
+    take(L.hdr, H_COUNT * sizeof(int));
+    take(L.cell_count, (size_t)L.grid.ncell * sizeof(int));
+    take(L.cell_cursor, (size_t)L.grid.ncell * sizeof(int));
+    take(L.cell_start, (size_t)(L.grid.ncell + 1) * sizeof(int));
+    take(L.cell_of, nn * sizeof(int));
+    take(L.cell_atoms, nn * sizeof(int));
+    take(L.scan_part, (size_t)nsp * sizeof(int));
+    take(L.nbr, nn * cap * sizeof(int));
+    take(L.rev, nn * cap * sizeof(int));
+    take(L.cnt, nn * sizeof(int));
+    take(L.ref_pos, 3 * nn * sizeof(double));
+    take(L.S_idx, nn * sizeof(int));
+    take(L.M_idx, nn * sizeof(int));
+    take(L.S_local, nn * sizeof(int));
+    take(L.cand, nn);
+    take(L.A, nn * c.m.KA * tsz);
+    take(L.dEdA, nn * c.m.KA * tsz);
+    take(L.g, nn * cap * 3 * tsz);
+    take(L.h, nn * cap * 3 * tsz);
+    take(L.red, kReduceBlocks * 3 * sizeof(double));
+    L.total = off;
+    return L;
+}
+
+__global__ void k_zero_i32(int *p, int n)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n)
+        p[i] = 0;
+}
+
+}  // namespace mlmix
+
+// ------------------------------------------------------------------ ABI
+
+static int check_box(const mlmix_ctx *ctx, const mlmix_box *box, Box &b)
+{
+    if (!box)
+        return fail(MLMIX_E_ARG, "box is NULL");
+    for (int k = 0; k < 3; ++k) {
+        if (!(box->L[k] > 0.0) || !std::isfinite(box->L[k]))
+            return fail(MLMIX_E_BOX, "box length must be positive and finite");
+        if (box->periodic[k] && box->L[k] < 2.0 * ctx->c.r_list)
+            return fail(MLMIX_E_BOX, "periodic box length below twice the list radius");
+        b.L[k] = box->L[k];
+        b.per[k] = box->periodic[k] ? 1 : 0;
+    }
+    return MLMIX_OK;
+}
+
+extern "C" int mlmix_create(const mlmix_model_desc *desc, mlmix_ctx **out)
+{
+    if (!desc || !out)
+        return fail(MLMIX_E_ARG, "NULL argument");
+    *out = nullptr;
+    const mlmix_model_desc &d = *desc;
+    if (d.n_species < 1 || d.n_species > 8)
+        return fail(MLMIX_E_ARG, "n_species must be 1..8");
+    if (d.precision != MLMIX_FP64 && d.precision != MLMIX_FP32)
+        return fail(MLMIX_E_ARG, "precision must be MLMIX_FP64 or MLMIX_FP32");
+    if (d.ace_n_rad < 1 || d.ace_n_rad > kMaxNrad || d.ace_lmax < 0 || d.ace_lmax > kMaxLmax ||
+        d.ace_order < 1 || d.ace_order > 3 || !(d.ace_rcut > 0.0))
+        return fail(MLMIX_E_ARG, "ACE sizes out of range (n_rad 1..16, lmax 0..6, order 1..3)");
+    if (!d.ace_c0 || !d.ace_c1 || (d.ace_order >= 2 && !d.ace_c2) || (d.ace_order >= 3 && !d.ace_c3))
+        return fail(MLMIX_E_ARG, "missing ACE coefficient array");
+    if (d.uf3_n_knots2 < 4 || d.uf3_n_knots2 > 64 || !(d.uf3_rcut2 > 0.0) || !d.uf3_c2)
+        return fail(MLMIX_E_ARG, "UF3 2-body needs 4..64 knots, rcut2 > 0 and coefficients");
+    if (d.uf3_n_knots3 != 0 && (d.uf3_n_knots3 < 4 || d.uf3_n_knots3 > 16 || !(d.uf3_rcut3 > 0.0) ||
+                                !d.uf3_c3))
+        return fail(MLMIX_E_ARG, "UF3 3-body needs 4..16 knots, rcut3 > 0 and coefficients");
+    if (!(d.skin >= 0.0))
+        return fail(MLMIX_E_ARG, "skin must be >= 0");
+    int nch = d.n_species * d.ace_n_rad;
+    int L2 = (d.ace_lmax + 1) * (d.ace_lmax + 1);
+    if (nch * L2 > 1024)
+        return fail(MLMIX_E_ARG, "atomic basis larger than 1024 entries");
+    if (nch * (2 * d.ace_lmax + 1) > 8 * 64)
+        return fail(MLMIX_E_ARG, "order-3 output block larger than 512 entries");
+
+    mlmix_ctx *ctx = new mlmix_ctx();
+    Ctx &c = ctx->c;
+    c.d = d;
+    c.prec = d.precision;
+    double rmax = std::max(d.ace_rcut, d.uf3_rcut2);
+    if (d.uf3_n_knots3 > 0)
+        rmax = std::max(rmax, d.uf3_rcut3);
+    c.r_list = rmax + d.skin;
+    HIP_OK(hipGetDevice(&c.device));
+    HostTables t;
+    int rc = build_tables(d, t);
+    if (rc != MLMIX_OK) {
+        delete ctx;
+        return rc;
+    }
+    DevModel &m = c.m;
+    m.ns = d.n_species;
+    m.nrad = d.ace_n_rad;
+    m.lmax = d.ace_lmax;
+    m.order = d.ace_order;
+    m.nchan = nch;
+    m.L2 = L2;
+    m.KA = nch * L2;
+    m.rc_exp = d.ace_rcut;
+    m.rc2 = d.uf3_rcut2;
+    m.rc3 = d.uf3_rcut3;
+    m.nk2 = d.uf3_n_knots2;
+    m.nk3 = d.uf3_n_knots3;
+    m.nb2 = d.uf3_n_knots2 + 2;
+    m.nb3 = d.uf3_n_knots3 > 0 ? d.uf3_n_knots3 + 2 : 0;
+    m.n_pb = (int)t.pb.size();
+    m.w_per_species = t.w_per_species;
+    for (int l = 0; l <= kMaxLmax; ++l) {
+        c.m_pb_lo[l] = 0;
+        c.m_pb_hi[l] = 0;
+    }
+    for (int p = 0; p < (int)t.pb.size(); ++p) {
+        int l3 = t.pb[p].l3;
+        if (c.m_pb_hi[l3] == 0)
+            c.m_pb_lo[l3] = p;
+        c.m_pb_hi[l3] = p + 1;
+    }
+    std::vector<char> blob = c.prec == MLMIX_FP64 ? pack<double>(t, m) : pack<float>(t, m);
+    m.bytes = blob.size();
+    hipError_t e = hipMalloc(&m.base, m.bytes);
+    if (e != hipSuccess) {
+        delete ctx;
+        return fail(MLMIX_E_HIP, std::string("hipMalloc(model): ") + hipGetErrorString(e));
+    }
+    e = hipMemcpy(m.base, blob.data(), m.bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(m.base);
+        delete ctx;
+        return fail(MLMIX_E_HIP, std::string("hipMemcpy(model): ") + hipGetErrorString(e));
+    }
+    *out = ctx;
+    return MLMIX_OK;
+}
+
+extern "C" int mlmix_destroy(mlmix_ctx *ctx)
+{
+    if (!ctx)
+        return MLMIX_OK;
+    if (ctx->c.m.base)
+        (void)hipFree(ctx->c.m.base);
+    delete ctx;
+    return MLMIX_OK;
+}
+
+extern "C" double mlmix_list_radius(const mlmix_ctx *ctx) { return ctx ? ctx->c.r_list : 0.0; }
+
+extern "C" int mlmix_workspace_size(const mlmix_ctx *ctx, int32_t n_atoms, int32_t nbr_cap,
+                                    const mlmix_box *box, size_t *bytes)
+{
+    if (!ctx || !bytes)
+        return fail(MLMIX_E_ARG, "NULL argument");
+    if (n_atoms < 0 || nbr_cap < 1 || nbr_cap > kMaxCap)
+        return fail(MLMIX_E_ARG, "n_atoms >= 0 and 1 <= nbr_cap <= 256 required");
+    Box b;
+    int rc = check_box(ctx, box, b);
+    if (rc)
+        return rc;
+    *bytes = make_layout(ctx->c, n_atoms, nbr_cap, b).total;
+    return MLMIX_OK;
+}
+
+extern "C" int mlmix_workspace_init(mlmix_ctx *ctx, void *stream, void *ws, size_t ws_bytes,
+                                    int32_t n_atoms, int32_t nbr_cap, const mlmix_box *box)
+{
+    if (!ctx || !ws)
+        return fail(MLMIX_E_ARG, "NULL argument");
+    if (n_atoms < 0 || nbr_cap < 1 || nbr_cap > kMaxCap)
+        return fail(MLMIX_E_ARG, "n_atoms >= 0 and 1 <= nbr_cap <= 256 required");
+    Box b;
+    int rc = check_box(ctx, box, b);
+    if (rc)
+        return rc;
+    WsLayout L = make_layout(ctx->c, n_atoms, nbr_cap, b);
+    if (ws_bytes < L.total)
+        return fail(MLMIX_E_WORKSPACE, "workspace smaller than mlmix_workspace_size()");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    k_zero_i32<<<1, H_COUNT, 0, s>>>(at<int>(ws, L.hdr), H_COUNT);
+    HIP_OK(hipGetLastError());
+    std::lock_guard<std::mutex> g(ctx->mu);
+    ctx->ws[ws] = L;
+    return MLMIX_OK;
+}
+
+static int lookup(mlmix_ctx *ctx, void *ws, int n, const mlmix_box *box, WsLayout &L, Box &b)
+{
+    int rc = check_box(ctx, box, b);
+    if (rc)
+        return rc;
+    {
+        std::lock_guard<std::mutex> g(ctx->mu);
+        auto it = ctx->ws.find(ws);
+        if (it == ctx->ws.end())
+            return fail(MLMIX_E_STATE, "workspace was not initialised with mlmix_workspace_init");
+        L = it->second;
+    }
+    if (L.n != n)
+        return fail(MLMIX_E_ARG, "n_atoms differs from the workspace's");
+    Grid g = make_grid(ctx->c, b);
+    if (g.nc[0] != L.grid.nc[0] || g.nc[1] != L.grid.nc[1] || g.nc[2] != L.grid.nc[2])
+        return fail(MLMIX_E_ARG, "box grid changed: call mlmix_workspace_init again");
+    L.grid = g;
+    return MLMIX_OK;
+}
+
+static int compute_impl(mlmix_ctx *ctx, hipStream_t s, void *ws, const WsLayout &L, const Box &b,
+                        const double *pos, const int32_t *species, const mlmix_region *regions,
+                        int32_t n_regions, double r_buffer, uint32_t mode, double *forces,
+                        double *e_exp, double *e_cheap, double *lambda, uint8_t *flags,
+                        int32_t *n_expensive, double *f_exp, double *f_cheap)
+{
+    const Ctx &c = ctx->c;
+    int m = (int)(mode & 0xff);
+    bool energy_only = (mode & MLMIX_ENERGY_ONLY) != 0;
+    launch_prepare(s, ws, L, (mode & MLMIX_FORCE_REBUILD) ? 1 : 0, pos, c.d.skin);
+    launch_neighbors(s, ws, L, b, c.r_list, pos);
+    launch_regions(s, ws, L, b, m, pos, species, c.m.ns, regions, n_regions, r_buffer, lambda, flags);
+    launch_compact(s, ws, L, flags, n_expensive);
+    if (m != MLMIX_MODE_ALL_CHEAP) {
+        launch_ace_forward(s, c, ws, L, b, pos, species, e_exp);
+        if (!energy_only)
+            launch_ace_pairgrad(s, c, ws, L, b, pos, species, nullptr);
+    }
+    if (energy_only) {
+        launch_gather_blend(s, c, ws, L, 0, 0, lambda, nullptr, e_exp, nullptr, nullptr, 1.0);
+        HIP_OK(hipGetLastError());
+        return MLMIX_OK;
+    }
+    if (m != MLMIX_MODE_ALL_EXPENSIVE)
+        launch_uf3(s, c, ws, L, b, pos, species, e_cheap);
+    else
+        launch_fill_f64(s, e_cheap, 0.0, (size_t)L.n);
+    launch_gather_blend(s, c, ws, L, m != MLMIX_MODE_ALL_CHEAP, m != MLMIX_MODE_ALL_EXPENSIVE,
+                        lambda, forces, e_exp, f_exp, f_cheap, 1.0);
+    HIP_OK(hipGetLastError());
+    return MLMIX_OK;
+}
+
+static int check_compute_args(mlmix_ctx *ctx, const double *pos, const int32_t *species,
+                              const mlmix_region *regions, int32_t n_regions, double r_buffer,
+                              uint32_t mode, double *forces, double *e_exp, double *e_cheap,
+                              double *lambda, uint8_t *flags)
+{
+    int m = (int)(mode & 0xff);
+    if (m != MLMIX_MODE_MIXED && m != MLMIX_MODE_ALL_EXPENSIVE && m != MLMIX_MODE_ALL_CHEAP)
+        return fail(MLMIX_E_ARG, "unknown mode");
+    if (mode & ~(0xffu | MLMIX_FORCE_REBUILD | MLMIX_ENERGY_ONLY))
+        return fail(MLMIX_E_ARG, "unknown mode flag");
+    if (!pos || !species || !e_exp || !lambda || !flags)
+        return fail(MLMIX_E_ARG, "NULL array argument");
+    if (!(mode & MLMIX_ENERGY_ONLY) && (!forces || !e_cheap))
+        return fail(MLMIX_E_ARG, "forces and e_cheap are required unless MLMIX_ENERGY_ONLY");
+    if (m == MLMIX_MODE_MIXED) {
+        if (n_regions < 0 || (n_regions > 0 && !regions))
+            return fail(MLMIX_E_ARG, "bad region array");
+        if (!(r_buffer >= 0.0) || r_buffer > ctx->c.r_list)
+            return fail(MLMIX_E_ARG, "r_buffer must lie in [0, list radius]");
+    }
+    return MLMIX_OK;
+}
+
+extern "C" int mlmix_compute(mlmix_ctx *ctx, void *stream, void *ws, int32_t n_atoms,
+                             const double *pos, const int32_t *species, const mlmix_box *box,
+                             const mlmix_region *regions, int32_t n_regions, double r_buffer,
+                             uint32_t mode, double *forces, double *e_exp, double *e_cheap,
+                             double *lambda, uint8_t *flags, int32_t *n_expensive,
+                             double *f_exp, double *f_cheap)
+{
+    if (!ctx || !ws)
+        return fail(MLMIX_E_ARG, "NULL context or workspace");
+    WsLayout L;
+    Box b;
+    int rc = lookup(ctx, ws, n_atoms, box, L, b);
+    if (rc)
+        return rc;
+    rc = check_compute_args(ctx, pos, species, regions, n_regions, r_buffer, mode, forces, e_exp,
+                            e_cheap, lambda, flags);
+    if (rc)
+        return rc;
+    return compute_impl(ctx, static_cast<hipStream_t>(stream), ws, L, b, pos, species, regions,
+                        n_regions, r_buffer, mode, forces, e_exp, e_cheap, lambda, flags,
+                        n_expensive, f_exp, f_cheap);
+}
+
+extern "C" int mlmix_backward(mlmix_ctx *ctx, void *stream, void *ws, int32_t n_atoms,
+                              const double *pos, const int32_t *species, const mlmix_box *box,
+                              const double *grad_e, double *grad_pos)
+{
+    if (!ctx || !ws || !pos || !species || !grad_e || !grad_pos)
+        return fail(MLMIX_E_ARG, "NULL argument");
+    WsLayout L;
+    Box b;
+    int rc = lookup(ctx, ws, n_atoms, box, L, b);
+    if (rc)
+        return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    launch_ace_pairgrad(s, ctx->c, ws, L, b, pos, species, grad_e);
+    launch_gather_blend(s, ctx->c, ws, L, 1, 0, nullptr, grad_pos, nullptr, nullptr, nullptr, -1.0);
+    HIP_OK(hipGetLastError());
+    return MLMIX_OK;
+}
+
+extern "C" int mlmix_energy_reduce(mlmix_ctx *ctx, void *stream, void *ws, int32_t n_atoms,
+                                   const double *e_exp, const double *e_cheap, const double *vel,
+                                   const double *mass, double *energies)
+{
+    if (!ctx || !ws || !energies)
+        return fail(MLMIX_E_ARG, "NULL argument");
+    WsLayout L;
+    {
+        std::lock_guard<std::mutex> g(ctx->mu);
+        auto it = ctx->ws.find(ws);
+        if (it == ctx->ws.end())
+            return fail(MLMIX_E_STATE, "workspace was not initialised");
+        L = it->second;
+    }
+    if (L.n != n_atoms)
+        return fail(MLMIX_E_ARG, "n_atoms differs from the workspace's");
+    launch_reduce(static_cast<hipStream_t>(stream), ws, L, e_exp, e_cheap, vel, mass, energies);
+    HIP_OK(hipGetLastError());
+    return MLMIX_OK;
+}
+
+extern "C" int mlmix_vv_step(mlmix_ctx *ctx, void *stream, void *ws, int32_t n_atoms, double *pos,
+                             double *vel, const double *mass, const int32_t *species, double dt,
+                             const mlmix_box *box, const mlmix_region *regions, int32_t n_regions,
+                             double r_buffer, uint32_t mode, double *forces, double *e_exp,
+                             double *e_cheap, double *lambda, uint8_t *flags,
+                             int32_t *n_expensive, double *energies)
+{
+    if (!ctx || !ws || !vel || !mass)
+        return fail(MLMIX_E_ARG, "NULL argument");
+    if (mode & MLMIX_ENERGY_ONLY)
+        return fail(MLMIX_E_ARG, "MLMIX_ENERGY_ONLY is not valid for an MD step");
+    if (!(dt > 0.0))
+        return fail(MLMIX_E_ARG, "dt must be positive");
+    WsLayout L;
+    Box b;
+    int rc = lookup(ctx, ws, n_atoms, box, L, b);
+    if (rc)
+        return rc;
+    rc = check_compute_args(ctx, pos, species, regions, n_regions, r_buffer, mode, forces, e_exp,
+                            e_cheap, lambda, flags);
+    if (rc)
+        return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    launch_vv_kick_drift(s, ws, L, b, pos, vel, mass, forces, dt, 1);
+    rc = compute_impl(ctx, s, ws, L, b, pos, species, regions, n_regions, r_buffer, mode, forces,
+                      e_exp, e_cheap, lambda, flags, n_expensive, nullptr, nullptr);
+    if (rc)
+        return rc;
+    launch_vv_kick_drift(s, ws, L, b, pos, vel, mass, forces, dt, 0);
+    if (energies)
+        launch_reduce(s, ws, L, e_exp, e_cheap, vel, mass, energies);
+    HIP_OK(hipGetLastError());
+    return MLMIX_OK;
+}
+
+extern "C" int mlmix_status(mlmix_ctx *ctx, void *stream, void *ws, int32_t *status_bits,
+                            int32_t *required_cap)
+{
+    if (!ctx || !ws)
+        return fail(MLMIX_E_ARG, "NULL argument");
+    WsLayout L;
+    {
+        std::lock_guard<std::mutex> g(ctx->mu);
+        auto it = ctx->ws.find(ws);
+        if (it == ctx->ws.end())
+            return fail(MLMIX_E_STATE, "workspace was not initialised");
+        L = it->second;
+    }
+    HIP_OK(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
+    int hdr[H_COUNT];
+    HIP_OK(hipMemcpy(hdr, at<int>(ws, L.hdr), sizeof hdr, hipMemcpyDeviceToHost));
+    if (status_bits)
+        *status_bits = hdr[H_STATUS];
+    if (required_cap)
+        *required_cap = hdr[H_REQCAP];
+    int st = hdr[H_STATUS];
+    if (st & (MLMIX_STATUS_NEIGH_OVERFLOW | MLMIX_STATUS_TRIPLET_OVERFLOW))
+        return fail(MLMIX_E_NEIGH_OVERFLOW, "neighbour row capacity exceeded");
+    if (st & MLMIX_STATUS_NONFINITE)
+        return fail(MLMIX_E_NONFINITE, "non-finite position");
+    if (st & MLMIX_STATUS_BAD_SPECIES)
+        return fail(MLMIX_E_ARG, "species index outside [0, n_species)");
+    if (st & MLMIX_STATUS_OUT_OF_BOX)
+        return fail(MLMIX_E_BOX, "atom outside a non-periodic box dimension");
+    return MLMIX_OK;
+}
+
+extern "C" int mlmix_get_neighbors(mlmix_ctx *ctx, void *stream, void *ws, int32_t n_atoms,
+                                   int32_t *nbr_out, int32_t *cnt_out)
+{
+    if (!ctx || !ws || !nbr_out || !cnt_out)
+        return fail(MLMIX_E_ARG, "NULL argument");
+    WsLayout L;
+    {
+        std::lock_guard<std::mutex> g(ctx->mu);
+        auto it = ctx->ws.find(ws);
+        if (it == ctx->ws.end())
+            return fail(MLMIX_E_STATE, "workspace was not initialised");
+        L = it->second;
+    }
+    if (L.n != n_atoms)
+        return fail(MLMIX_E_ARG, "n_atoms differs from the workspace's");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    launch_copy_i32(s, nbr_out, at<int>(ws, L.nbr), (size_t)L.n * L.cap);
+    launch_copy_i32(s, cnt_out, at<int>(ws, L.cnt), (size_t)L.n);
+    HIP_OK(hipGetLastError());
+    return MLMIX_OK;
+}
+
+extern "C" int mlmix_get_index_sets(mlmix_ctx *ctx, void *stream, void *ws, int32_t n_atoms,
+                                    int32_t *S_out, int32_t *M_out)
+{
+    if (!ctx || !ws || !S_out || !M_out)
+        return fail(MLMIX_E_ARG, "NULL argument");
+    WsLayout L;
+    {
+        std::lock_guard<std::mutex> g(ctx->mu);
+        auto it = ctx->ws.find(ws);
+        if (it == ctx->ws.end())
+            return fail(MLMIX_E_STATE, "workspace was not initialised");
+        L = it->second;
+    }
+    if (L.n != n_atoms)
+        return fail(MLMIX_E_ARG, "n_atoms differs from the workspace's");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    launch_copy_i32(s, S_out, at<int>(ws, L.S_idx), (size_t)L.n);
+    launch_copy_i32(s, M_out, at<int>(ws, L.M_idx), (size_t)L.n);
+    HIP_OK(hipGetLastError());
+    return MLMIX_OK;
+}

@@ -1,0 +1,645 @@
+// Geometry stage of the mixed force evaluation on gfx950:
+// neighbour-list rebuild decision, cell binning, neighbour rows, reverse
+// slots, the mixing weight lambda and masks (Algorithms 1-2 with geometric
+// core regions), the buffer set (Algorithm 3 / buffer-set equation) and the
+// ordered stream compaction of S = {lambda > 0} + buffer.
+//
+// Every geometric decision (pair inside a radius, lambda, membership) is made
+// in FP64 without FMA contraction so that it reproduces the CPU reference
+// bit for bit.
+#include "internal.h"
+
+namespace mlmix {
+
+#pragma clang fp contract(off)
+
+__device__ __forceinline__ void pair_disp(const double *__restrict__ pos, int n, int i, int j,
+                                          const Box &b, double d[3])
+{
+#pragma clang fp contract(off)
+    for (int k = 0; k < 3; ++k) {
+        double dx = pos[k * n + j] - pos[k * n + i];
+        if (b.per[k]) {
+            double h = 0.5 * b.L[k];
+            if (dx > h)
+                dx = dx - b.L[k];
+            else if (dx < -h)
+                dx = dx + b.L[k];
+        }
+        d[k] = dx;
+    }
+}
+
+__device__ __forceinline__ double norm2(const double d[3])
+{
+#pragma clang fp contract(off)
+    double s = d[0] * d[0];
+    s = s + d[1] * d[1];
+    s = s + d[2] * d[2];
+    return s;
+}
+
+__device__ __forceinline__ int cell_coord(double x, const Grid &g, int k)
+{
+    int q = (int)floor(x / g.cs[k]);
+    if (q < 0)
+        q = 0;
+    if (q >= g.nc[k])
+        q = g.nc[k] - 1;
+    return q;
+}
+
+// ---------------------------------------------------------------- scans
+
+__device__ __forceinline__ int wave_incl_scan(int x)
+{
+    int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        int t = __shfl_up(x, d);
+        if (lane >= d)
+            x += t;
+    }
+    return x;
+}
+
+// Exclusive scan across a 256-thread block.
+__device__ __forceinline__ int block_excl_scan(int v, int *sh, int &total)
+{
+    int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int x = wave_incl_scan(v);
+    if (lane == 63)
+        sh[w] = x;
+    __syncthreads();
+    int off = 0;
+    total = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        int s = sh[k];
+        if (k < w)
+            off += s;
+        total += s;
+    }
+    __syncthreads();
+    return off + x - v;
+}
+
+constexpr int kPer = kScanTile / 256;
+
+__global__ void __launch_bounds__(256) k_scan_blocksum(const int *__restrict__ in, int n,
+                                                       int *__restrict__ part, const int *gate)
+{
+    if (gate && *gate == 0)
+        return;
+    __shared__ int sh[4];
+    int base = blockIdx.x * kScanTile + threadIdx.x * kPer;
+    int s = 0;
+    for (int k = 0; k < kPer; ++k)
+        if (base + k < n)
+            s += in[base + k];
+    int tot;
+    block_excl_scan(s, sh, tot);
+    if (threadIdx.x == 0)
+        part[blockIdx.x] = tot;
+}
+
+// Exclusive scan of the block sums in place (one block); *total = sum.
+__global__ void __launch_bounds__(256) k_scan_top(int *__restrict__ part, int nb, int *total,
+                                                  const int *gate)
+{
+    if (gate && *gate == 0)
+        return;
+    __shared__ int sh[4];
+    int carry = 0;
+    for (int base = 0; base < nb; base += 256) {
+        int i = base + threadIdx.x;
+        int v = i < nb ? part[i] : 0;
+        int tot;
+        int ex = block_excl_scan(v, sh, tot);
+        if (i < nb)
+            part[i] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0)
+        *total = carry;
+}
+
+__global__ void __launch_bounds__(256) k_scan_apply(const int *__restrict__ in, int n,
+                                                    const int *__restrict__ part,
+                                                    int *__restrict__ out, const int *gate)
+{
+    if (gate && *gate == 0)
+        return;
+    __shared__ int sh[4];
+    int base = blockIdx.x * kScanTile + threadIdx.x * kPer;
+    int v[kPer];
+    int s = 0;
+    for (int k = 0; k < kPer; ++k) {
+        v[k] = (base + k < n) ? in[base + k] : 0;
+        s += v[k];
+    }
+    int tot;
+    int ex = block_excl_scan(s, sh, tot) + part[blockIdx.x];
+    for (int k = 0; k < kPer; ++k) {
+        if (base + k < n)
+            out[base + k] = ex;
+        ex += v[k];
+    }
+}
+
+static void device_excl_scan(hipStream_t s, const int *in, int n, int *part, int *out,
+                             const int *gate)
+{
+    // out has n+1 entries; out[n] = total
+    int nb = (n + kScanTile - 1) / kScanTile;
+    if (nb < 1)
+        nb = 1;
+    k_scan_blocksum<<<nb, 256, 0, s>>>(in, n, part, gate);
+    k_scan_top<<<1, 256, 0, s>>>(part, nb, out + n, gate);
+    k_scan_apply<<<nb, 256, 0, s>>>(in, n, part, out, gate);
+}
+
+// ------------------------------------------------------ rebuild decision
+
+__global__ void k_prepare(int *hdr, int force)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0)
+        hdr[H_REBUILD] = (force || hdr[H_BUILT] == 0) ? 1 : 0;
+}
+
+__global__ void __launch_bounds__(256) k_displacement(const double *__restrict__ pos,
+                                                      const double *__restrict__ ref, int n,
+                                                      double thr2, int *hdr)
+{
+#pragma clang fp contract(off)
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    // positions in periodic dimensions may have wrapped: fold the difference
+    double d2 = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        double d = pos[k * n + i] - ref[k * n + i];
+        d2 = d2 + d * d;
+    }
+    // a wrapped atom shows a displacement of about L, which also (and
+    // harmlessly) triggers a rebuild
+    if (!(d2 <= thr2))
+        hdr[H_REBUILD] = 1;
+}
+
+// ------------------------------------------------------------ cell lists
+
+__global__ void __launch_bounds__(256) k_cell_zero(int *__restrict__ count, int *__restrict__ cursor,
+                                                   int ncell, const int *gate)
+{
+    if (*gate == 0)
+        return;
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < ncell) {
+        count[c] = 0;
+        cursor[c] = 0;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_cell_count(const double *__restrict__ pos, int n, Box b,
+                                                    Grid g, int *__restrict__ cell_of,
+                                                    int *__restrict__ count, int *hdr)
+{
+    if (hdr[H_REBUILD] == 0)
+        return;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    int c[3];
+    bool bad = false;
+    for (int k = 0; k < 3; ++k) {
+        double x = pos[k * n + i];
+        if (!(x == x) || x < -1.0e300 || x > 1.0e300)
+            bad = true;
+        if (!b.per[k] && (x < 0.0 || x >= b.L[k]))
+            atomicOr(&hdr[H_STATUS], MLMIX_STATUS_OUT_OF_BOX);
+        c[k] = cell_coord(x, g, k);
+    }
+    if (bad)
+        atomicOr(&hdr[H_STATUS], MLMIX_STATUS_NONFINITE);
+    int cell = (c[2] * g.nc[1] + c[1]) * g.nc[0] + c[0];
+    cell_of[i] = cell;
+    atomicAdd(&count[cell], 1);
+}
+
+__global__ void __launch_bounds__(256) k_cell_fill(int n, const int *__restrict__ cell_of,
+                                                   const int *__restrict__ start,
+                                                   int *__restrict__ cursor,
+                                                   int *__restrict__ atoms, const int *hdr)
+{
+    if (hdr[H_REBUILD] == 0)
+        return;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    int c = cell_of[i];
+    int slot = start[c] + atomicAdd(&cursor[c], 1);
+    atoms[slot] = i;
+}
+
+// One wavefront per atom: visit the (up to) 5x5x5 stencil of half-radius
+// cells, keep partners closer than the list radius, sort the row ascending
+// (bitonic sort in LDS) and store it.
+__global__ void __launch_bounds__(64) k_neighbors(const double *__restrict__ pos, int n, Box b,
+                                                  Grid g, const int *__restrict__ start,
+                                                  const int *__restrict__ atoms, double rl2,
+                                                  int cap, int P, int *__restrict__ nbr,
+                                                  int *__restrict__ cnt,
+                                                  double *__restrict__ ref, int *hdr)
+{
+#pragma clang fp contract(off)
+    if (hdr[H_REBUILD] == 0)
+        return;
+    __shared__ int row[kMaxCap];
+    __shared__ int count;
+    int i = blockIdx.x;
+    int lane = threadIdx.x;
+    if (lane == 0)
+        count = 0;
+    for (int t = lane; t < P; t += 64)
+        row[t] = 0x7fffffff;
+    __syncthreads();
+    int ci[3], nst[3];
+    for (int k = 0; k < 3; ++k) {
+        ci[k] = cell_coord(pos[k * n + i], g, k);
+        nst[k] = (b.per[k] && g.nc[k] < 5) ? g.nc[k] : 5;
+    }
+    int total = nst[0] * nst[1] * nst[2];
+    for (int t = lane; t < total; t += 64) {
+        int o[3] = {t % nst[0] - 2, (t / nst[0]) % nst[1] - 2, t / (nst[0] * nst[1]) - 2};
+        int q[3];
+        bool ok = true;
+        for (int k = 0; k < 3; ++k) {
+            int v = ci[k] + o[k];
+            if (b.per[k]) {
+                v %= g.nc[k];
+                if (v < 0)
+                    v += g.nc[k];
+            } else if (v < 0 || v >= g.nc[k]) {
+                ok = false;
+            }
+            q[k] = v;
+        }
+        if (!ok)
+            continue;
+        int cell = (q[2] * g.nc[1] + q[1]) * g.nc[0] + q[0];
+        int e = start[cell + 1];
+        for (int s = start[cell]; s < e; ++s) {
+            int j = atoms[s];
+            if (j == i)
+                continue;
+            double d[3];
+            pair_disp(pos, n, i, j, b, d);
+            if (norm2(d) < rl2) {
+                int slot = atomicAdd(&count, 1);
+                if (slot < P)
+                    row[slot] = j;
+            }
+        }
+    }
+    __syncthreads();
+    int c = count;
+    for (int k = 2; k <= P; k <<= 1) {
+        for (int jj = k >> 1; jj > 0; jj >>= 1) {
+            for (int t = lane; t < P; t += 64) {
+                int l = t ^ jj;
+                if (l > t) {
+                    int a = row[t], bb = row[l];
+                    bool up = (t & k) == 0;
+                    if ((a > bb) == up) {
+                        row[t] = bb;
+                        row[l] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    int keep = c < cap ? c : cap;
+    for (int s = lane; s < cap; s += 64)
+        nbr[(size_t)i * cap + s] = s < keep ? row[s] : -1;
+    if (lane == 0) {
+        cnt[i] = keep;
+        if (c > cap) {
+            atomicOr(&hdr[H_STATUS], MLMIX_STATUS_NEIGH_OVERFLOW);
+        }
+        atomicMax(&hdr[H_REQCAP], c);
+    }
+    if (lane < 3)
+        ref[lane * n + i] = pos[lane * n + i];
+}
+
+// rev[i][s] = slot of i in the row of j = nbr[i][s] (rows are ascending).
+__global__ void __launch_bounds__(256) k_reverse(int n, int cap, const int *__restrict__ nbr,
+                                                 const int *__restrict__ cnt,
+                                                 int *__restrict__ rev, int *hdr)
+{
+    if (hdr[H_REBUILD] == 0)
+        return;
+    size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (size_t)n * cap)
+        return;
+    int i = (int)(t / cap), s = (int)(t % cap);
+    int r = -1;
+    if (s < cnt[i]) {
+        int j = nbr[t];
+        const int *rowj = nbr + (size_t)j * cap;
+        int lo = 0, hi = cnt[j] - 1;
+        while (lo <= hi) {
+            int mid = (lo + hi) >> 1;
+            int v = rowj[mid];
+            if (v == i) {
+                r = mid;
+                break;
+            }
+            if (v < i)
+                lo = mid + 1;
+            else
+                hi = mid - 1;
+        }
+    }
+    rev[t] = r;
+}
+
+__global__ void k_finish_rebuild(int *hdr)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0 && hdr[H_REBUILD])
+        hdr[H_BUILT] = 1;
+}
+
+void launch_prepare(hipStream_t s, void *ws, const WsLayout &L, int force_rebuild,
+                    const double *pos, double skin)
+{
+    int *hdr = at<int>(ws, L.hdr);
+    k_prepare<<<1, 64, 0, s>>>(hdr, force_rebuild);
+    if (!force_rebuild) {
+        double thr = 0.5 * skin;
+        k_displacement<<<(L.n + 255) / 256, 256, 0, s>>>(pos, at<double>(ws, L.ref_pos), L.n,
+                                                         thr * thr, hdr);
+    }
+}
+
+void launch_neighbors(hipStream_t s, void *ws, const WsLayout &L, const Box &b, double r_list,
+                      const double *pos)
+{
+    int *hdr = at<int>(ws, L.hdr);
+    const Grid &g = L.grid;
+    int *count = at<int>(ws, L.cell_count);
+    int *cursor = at<int>(ws, L.cell_cursor);
+    int *start = at<int>(ws, L.cell_start);
+    int n = L.n;
+    if (n == 0)
+        return;
+    k_cell_zero<<<(g.ncell + 255) / 256, 256, 0, s>>>(count, cursor, g.ncell, hdr + H_REBUILD);
+    k_cell_count<<<(n + 255) / 256, 256, 0, s>>>(pos, n, b, g, at<int>(ws, L.cell_of), count, hdr);
+    device_excl_scan(s, count, g.ncell, at<int>(ws, L.scan_part), start, hdr + H_REBUILD);
+    k_cell_fill<<<(n + 255) / 256, 256, 0, s>>>(n, at<int>(ws, L.cell_of), start, cursor,
+                                                at<int>(ws, L.cell_atoms), hdr);
+    k_neighbors<<<n, 64, 0, s>>>(pos, n, b, g, start, at<int>(ws, L.cell_atoms), r_list * r_list,
+                                 L.cap, L.P, at<int>(ws, L.nbr), at<int>(ws, L.cnt),
+                                 at<double>(ws, L.ref_pos), hdr);
+    size_t tot = (size_t)n * L.cap;
+    k_reverse<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(n, L.cap, at<int>(ws, L.nbr),
+                                                           at<int>(ws, L.cnt), at<int>(ws, L.rev),
+                                                           hdr);
+    k_finish_rebuild<<<1, 64, 0, s>>>(hdr);
+}
+
+// --------------------------------------------------------- lambda / masks
+
+__global__ void __launch_bounds__(256) k_lambda(const double *__restrict__ pos, int n, Box b,
+                                                const int32_t *__restrict__ species, int ns, int *hdr,
+                                                int mode, const mlmix_region *__restrict__ reg,
+                                                int nreg, double r_buffer,
+                                                double *__restrict__ lam,
+                                                uint8_t *__restrict__ flags,
+                                                uint8_t *__restrict__ cand)
+{
+#pragma clang fp contract(off)
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    int z = species[i];
+    if (z < 0 || z >= ns)
+        atomicOr(&hdr[H_STATUS], MLMIX_STATUS_BAD_SPECIES);
+    if (mode == MLMIX_MODE_ALL_EXPENSIVE) {
+        lam[i] = 1.0;
+        flags[i] = 3;
+        cand[i] = 0;
+        return;
+    }
+    if (mode == MLMIX_MODE_ALL_CHEAP) {
+        lam[i] = 0.0;
+        flags[i] = 0;
+        cand[i] = 0;
+        return;
+    }
+    double best = 0.0;
+    bool near = false;
+    double xi[3] = {pos[i], pos[n + i], pos[2 * n + i]};
+    for (int g = 0; g < nreg; ++g) {
+        mlmix_region r = reg[g];
+        double c[3] = {r.center[0], r.center[1], r.center[2]};
+        if (r.follow_atom >= 0 && r.follow_atom < n) {
+            c[0] = pos[r.follow_atom];
+            c[1] = pos[n + r.follow_atom];
+            c[2] = pos[2 * n + r.follow_atom];
+        }
+        double d[3];
+        for (int k = 0; k < 3; ++k) {
+            double dx = xi[k] - c[k];
+            if (b.per[k]) {
+                double h = 0.5 * b.L[k];
+                if (dx > h)
+                    dx = dx - b.L[k];
+                else if (dx < -h)
+                    dx = dx + b.L[k];
+            }
+            d[k] = dx;
+        }
+        if (r.type == 1 && r.axis >= 0 && r.axis < 3)
+            d[r.axis] = 0.0;
+        double d2 = norm2(d);
+        double rc = r.r_core, rb = r.r_blend;
+        double outer = rc + rb;
+        double v;
+        if (d2 < rc * rc) {
+            v = 1.0;
+        } else if (d2 < outer * outer) {
+            double dist = sqrt(d2);
+            double t = (dist - rc) / rb;
+            v = 1.0 - t;
+        } else {
+            v = 0.0;
+        }
+        if (v > best)
+            best = v;
+        // buffer prefilter: a buffer atom lies within r_buffer of an atom
+        // with lambda > 0, hence (triangle inequality) within
+        // r_core + r_blend + r_buffer of some region; a margin keeps the
+        // test conservative under rounding
+        double far = outer + r_buffer + 1.0e-6;
+        if (d2 < far * far)
+            near = true;
+    }
+    lam[i] = best;
+    uint8_t f = 0;
+    if (best > 0.0)
+        f |= 1;
+    if (best == 1.0)
+        f |= 2;
+    flags[i] = f;
+    cand[i] = (best == 0.0 && near) ? 1 : 0;
+}
+
+__global__ void __launch_bounds__(256) k_buffer(const double *__restrict__ pos, int n, Box b,
+                                                int cap, const int *__restrict__ nbr,
+                                                const int *__restrict__ cnt, double rb2,
+                                                uint8_t *__restrict__ flags,
+                                                const uint8_t *__restrict__ cand)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || !cand[i])
+        return;
+    int c = cnt[i];
+    const int *row = nbr + (size_t)i * cap;
+    for (int s = 0; s < c; ++s) {
+        int j = row[s];
+        if (!(flags[j] & 1))
+            continue;
+        double d[3];
+        pair_disp(pos, n, i, j, b, d);
+        if (norm2(d) < rb2) {
+            flags[i] = (uint8_t)(flags[i] | 4);
+            return;
+        }
+    }
+}
+
+void launch_regions(hipStream_t s, void *ws, const WsLayout &L, const Box &b, int mode,
+                    const double *pos, const int32_t *species, int ns, const mlmix_region *reg,
+                    int nreg, double r_buffer, double *lambda, uint8_t *flags)
+{
+    int n = L.n;
+    if (n == 0)
+        return;
+    uint8_t *cand = at<uint8_t>(ws, L.cand);
+    k_lambda<<<(n + 255) / 256, 256, 0, s>>>(pos, n, b, species, ns, at<int>(ws, L.hdr), mode, reg,
+                                            nreg, r_buffer, lambda, flags, cand);
+    if (mode == MLMIX_MODE_MIXED)
+        k_buffer<<<(n + 255) / 256, 256, 0, s>>>(pos, n, b, L.cap, at<int>(ws, L.nbr),
+                                                at<int>(ws, L.cnt), r_buffer * r_buffer, flags,
+                                                cand);
+}
+
+// ------------------------------------------------------------ compaction
+
+__global__ void __launch_bounds__(256) k_cmp_blocksum(const uint8_t *__restrict__ flags, int n,
+                                                      int *__restrict__ partS,
+                                                      int *__restrict__ partM)
+{
+    __shared__ int sh[4];
+    int base = blockIdx.x * kScanTile + threadIdx.x * kPer;
+    int s = 0, m = 0;
+    for (int k = 0; k < kPer; ++k)
+        if (base + k < n) {
+            uint8_t f = flags[base + k];
+            s += (f & 5) ? 1 : 0;
+            m += (f & 1) ? 1 : 0;
+        }
+    int ts, tm;
+    block_excl_scan(s, sh, ts);
+    block_excl_scan(m, sh, tm);
+    if (threadIdx.x == 0) {
+        partS[blockIdx.x] = ts;
+        partM[blockIdx.x] = tm;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_cmp_top(int *__restrict__ partS, int *__restrict__ partM,
+                                                 int nb, int *hdr, int32_t *n_expensive)
+{
+    __shared__ int sh[4];
+    int cs = 0, cm = 0;
+    for (int base = 0; base < nb; base += 256) {
+        int i = base + threadIdx.x;
+        int vs = i < nb ? partS[i] : 0;
+        int vm = i < nb ? partM[i] : 0;
+        int ts, tm;
+        int es = block_excl_scan(vs, sh, ts);
+        int em = block_excl_scan(vm, sh, tm);
+        if (i < nb) {
+            partS[i] = cs + es;
+            partM[i] = cm + em;
+        }
+        cs += ts;
+        cm += tm;
+    }
+    if (threadIdx.x == 0) {
+        hdr[H_NS] = cs;
+        hdr[H_NM] = cm;
+        if (n_expensive) {
+            n_expensive[0] = cs;
+            n_expensive[1] = cm;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256) k_cmp_apply(const uint8_t *__restrict__ flags, int n,
+                                                   const int *__restrict__ partS,
+                                                   const int *__restrict__ partM,
+                                                   int *__restrict__ S_idx,
+                                                   int *__restrict__ M_idx,
+                                                   int *__restrict__ S_local)
+{
+    __shared__ int sh[4];
+    int base = blockIdx.x * kScanTile + threadIdx.x * kPer;
+    uint8_t f[kPer];
+    int s = 0, m = 0;
+    for (int k = 0; k < kPer; ++k) {
+        f[k] = (base + k < n) ? flags[base + k] : 0;
+        s += (f[k] & 5) ? 1 : 0;
+        m += (f[k] & 1) ? 1 : 0;
+    }
+    int ts, tm;
+    int es = block_excl_scan(s, sh, ts) + partS[blockIdx.x];
+    int em = block_excl_scan(m, sh, tm) + partM[blockIdx.x];
+    for (int k = 0; k < kPer; ++k) {
+        int i = base + k;
+        if (i >= n)
+            break;
+        if (f[k] & 5) {
+            S_idx[es] = i;
+            S_local[i] = es;
+            es++;
+        } else {
+            S_local[i] = -1;
+        }
+        if (f[k] & 1) {
+            M_idx[em] = i;
+            em++;
+        }
+    }
+}
+
+void launch_compact(hipStream_t s, void *ws, const WsLayout &L, uint8_t *flags,
+                    int32_t *n_expensive)
+{
+    int n = L.n;
+    int nb = (n + kScanTile - 1) / kScanTile;
+    if (nb < 1)
+        nb = 1;
+    int *partS = at<int>(ws, L.scan_part);
+    int *partM = partS + nb;
+    k_cmp_blocksum<<<nb, 256, 0, s>>>(flags, n, partS, partM);
+    k_cmp_top<<<1, 256, 0, s>>>(partS, partM, nb, at<int>(ws, L.hdr), n_expensive);
+    k_cmp_apply<<<nb, 256, 0, s>>>(flags, n, partS, partM, at<int>(ws, L.S_idx),
+                                   at<int>(ws, L.M_idx), at<int>(ws, L.S_local));
+}
+
+}  // namespace mlmix

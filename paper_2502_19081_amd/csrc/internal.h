@@ -1,0 +1,128 @@
+// Internal declarations of the HIP library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "mlmix.h"
+
+namespace mlmix {
+
+constexpr int kWave = 64;
+constexpr int kMaxLmax = 6;
+constexpr int kMaxL2 = (kMaxLmax + 1) * (kMaxLmax + 1);
+constexpr int kMaxNrad = 16;
+constexpr int kMaxCap = 256;
+constexpr int kMaxTriplet = 64;   // neighbours inside the 3-body cutoff per centre
+constexpr int kScanTile = 2048;   // elements per block in the device scans
+constexpr int kReduceBlocks = 256;
+
+// Header words at the start of every workspace (int32 unless noted).
+enum HeaderWord {
+    H_BUILT = 0,      // a neighbour list exists
+    H_REBUILD = 1,    // rebuild requested for the current call
+    H_STATUS = 2,     // MLMIX_STATUS_* bits
+    H_REQCAP = 3,     // largest neighbour count seen
+    H_NS = 4,         // |S|
+    H_NM = 5,         // |{lambda > 0}|
+    H_FWD = 6,        // a forward pass with dE/dA exists
+    H_COUNT = 64
+};
+
+struct Box {
+    double L[3];
+    int per[3];
+};
+
+// Cell grid of edge >= list radius / 2 (a +-2 cell stencil covers the radius).
+struct Grid {
+    int nc[3];
+    double cs[3];
+    int ncell;
+};
+
+struct WsLayout {
+    int n, cap, P;  // atoms, row capacity, capacity rounded up to a power of two
+    Grid grid;
+    int n_scan_blk;  // blocks of the atom-sized scans
+    size_t hdr, cell_count, cell_cursor, cell_start, cell_of, cell_atoms, scan_part;
+    size_t nbr, cnt, rev, ref_pos, S_idx, M_idx, S_local, cand;
+    size_t A, dEdA, g, h, red;
+    size_t total;
+};
+
+// Model tables on the device, in the arithmetic type of the context.
+struct DevModel {
+    int ns, nrad, lmax, order, nchan, KA, L2;
+    double rc_exp, rc2, rc3;
+    int nb2, nb3, nk2, nk3;
+    int n_pb;  // (l1 <= l2, l3) blocks of the order-3 contraction
+    void *base;
+    size_t bytes;
+    // offsets (bytes) into base
+    size_t ylmK, c0, c1, c2s, W, pb, gm3, gidx, gval, u2, u3;
+    int w_per_species;  // entries of W per centre species
+    int gm3_total, g_total;
+};
+
+// One (l1 <= l2, l3) block of the order-3 contraction.
+struct PBlock {
+    int l1, l2, l3;
+    int w_off;   // offset of the block's W[nchan*nchan][nchan] inside one species' W
+    int gm3_off; // offset into gm3: 2*l3+2 entry offsets (entries grouped by m3)
+    int pad[3];
+};
+
+struct Ctx {
+    mlmix_model_desc d;  // pointers inside are not kept
+    int prec;
+    double r_list;
+    DevModel m;
+    int m_pb_lo[kMaxLmax + 1], m_pb_hi[kMaxLmax + 1];  // order-3 blocks per l3
+    int device;
+};
+
+WsLayout make_layout(const Ctx &c, int n, int cap, const Box &b);
+Grid make_grid(const Ctx &c, const Box &b);
+
+// Species index clamped into the model's range (invalid input is reported by
+// a status bit; clamping keeps every table read in bounds).
+__host__ __device__ inline int sp_clamp(int z, int ns) { return z < 0 ? 0 : (z >= ns ? ns - 1 : z); }
+
+template <typename T>
+inline T *at(void *ws, size_t off) { return reinterpret_cast<T *>(static_cast<char *>(ws) + off); }
+
+// ---- launchers (geom.hip) ----
+void launch_prepare(hipStream_t s, void *ws, const WsLayout &L, int force_rebuild, const double *pos,
+                    double skin);
+void launch_neighbors(hipStream_t s, void *ws, const WsLayout &L, const Box &b, double r_list,
+                      const double *pos);
+void launch_regions(hipStream_t s, void *ws, const WsLayout &L, const Box &b, int mode,
+                    const double *pos, const int32_t *species, int ns, const mlmix_region *reg,
+                    int nreg, double r_buffer, double *lambda, uint8_t *flags);
+void launch_compact(hipStream_t s, void *ws, const WsLayout &L, uint8_t *flags, int32_t *n_expensive);
+
+// ---- ace.hip ----
+void launch_ace_forward(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L, const Box &b,
+                        const double *pos, const int32_t *species, double *e_exp);
+void launch_ace_pairgrad(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L, const Box &b,
+                         const double *pos, const int32_t *species, const double *weights);
+
+// ---- uf3.hip ----
+void launch_uf3(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L, const Box &b,
+                const double *pos, const int32_t *species, double *e_cheap);
+
+// ---- tail.hip ----
+void launch_gather_blend(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L, int use_exp,
+                         int use_cheap, const double *lambda, double *forces, double *e_exp,
+                         double *f_exp, double *f_cheap, double sign);
+void launch_fill_f64(hipStream_t s, double *p, double v, size_t n);
+void launch_reduce(hipStream_t s, void *ws, const WsLayout &L, const double *e_exp,
+                   const double *e_cheap, const double *vel, const double *mass, double *out);
+void launch_vv_kick_drift(hipStream_t s, void *ws, const WsLayout &L, const Box &b, double *pos,
+                          double *vel, const double *mass, const double *forces, double dt,
+                          int drift);
+void launch_copy_i32(hipStream_t s, int32_t *dst, const int32_t *src, size_t n);
+
+}  // namespace mlmix

@@ -1,0 +1,249 @@
+// Force gather + blend (Algorithm 4), FP64 energy sums and the FP64
+// velocity-Verlet kernels, on gfx950.
+//
+// Gather: with g_ij = dE_i/dd_ij stored per (centre, row slot), the force is
+// F_i = sum_j (g_ij - g_ji), where g_ji sits in j's row at the reverse slot.
+// One wavefront per atom (lanes over row slots, fixed-order butterfly sum):
+// no atomics, so repeated runs and replicas evaluated alone or in a batch
+// give the same bits. The blend F = lambda F_exp + (1 - lambda) F_cheap is
+// fused into the same pass.
+#include "internal.h"
+
+namespace mlmix {
+
+__device__ __forceinline__ double wave_sum_d(double v)
+{
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1)
+        v += __shfl_xor(v, d);
+    return v;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_gather_blend(int n, int cap, const int *__restrict__ nbr, const int *__restrict__ cnt,
+                   const int *__restrict__ rev, const int *__restrict__ S_local,
+                   const T *__restrict__ g, const T *__restrict__ h, int use_exp, int use_cheap,
+                   const double *__restrict__ lambda, double *__restrict__ forces,
+                   double *__restrict__ e_exp, double *__restrict__ f_exp,
+                   double *__restrict__ f_cheap, double sign)
+{
+    int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+    int lane = threadIdx.x & 63;
+    if (i >= n)
+        return;
+    int c = cnt[i];
+    int si = S_local[i];
+    double fe0 = 0.0, fe1 = 0.0, fe2 = 0.0, fc0 = 0.0, fc1 = 0.0, fc2 = 0.0;
+    const size_t rowo = (size_t)i * cap;
+    for (int slot = lane; slot < c; slot += 64) {
+        int j = nbr[rowo + slot];
+        int r = rev[rowo + slot];
+        if (r < 0)
+            continue;
+        if (use_exp && si >= 0) {
+            int sj = S_local[j];
+            if (sj >= 0) {
+                const T *a = g + ((size_t)si * cap + slot) * 3;
+                const T *bb = g + ((size_t)sj * cap + r) * 3;
+                fe0 += (double)a[0] - (double)bb[0];
+                fe1 += (double)a[1] - (double)bb[1];
+                fe2 += (double)a[2] - (double)bb[2];
+            }
+        }
+        if (use_cheap) {
+            const T *a = h + (rowo + slot) * 3;
+            const T *bb = h + ((size_t)j * cap + r) * 3;
+            fc0 += (double)a[0] - (double)bb[0];
+            fc1 += (double)a[1] - (double)bb[1];
+            fc2 += (double)a[2] - (double)bb[2];
+        }
+    }
+    fe0 = wave_sum_d(fe0);
+    fe1 = wave_sum_d(fe1);
+    fe2 = wave_sum_d(fe2);
+    fc0 = wave_sum_d(fc0);
+    fc1 = wave_sum_d(fc1);
+    fc2 = wave_sum_d(fc2);
+    if (lane == 0) {
+        double lam = lambda ? lambda[i] : 1.0;
+        double om = 1.0 - lam;
+        if (forces) {
+            forces[i] = sign * (lam * fe0 + om * fc0);
+            forces[n + i] = sign * (lam * fe1 + om * fc1);
+            forces[2 * n + i] = sign * (lam * fe2 + om * fc2);
+        }
+        if (f_exp) {
+            f_exp[i] = fe0;
+            f_exp[n + i] = fe1;
+            f_exp[2 * n + i] = fe2;
+        }
+        if (f_cheap) {
+            f_cheap[i] = fc0;
+            f_cheap[n + i] = fc1;
+            f_cheap[2 * n + i] = fc2;
+        }
+        if (e_exp && si < 0)
+            e_exp[i] = 0.0;
+    }
+}
+
+void launch_gather_blend(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L, int use_exp,
+                         int use_cheap, const double *lambda, double *forces, double *e_exp,
+                         double *f_exp, double *f_cheap, double sign)
+{
+    int n = L.n;
+    if (n == 0)
+        return;
+    unsigned nb = (n + 3) / 4;
+    if (c.prec == MLMIX_FP64)
+        k_gather_blend<double><<<nb, 256, 0, s>>>(n, L.cap, at<int>(ws, L.nbr), at<int>(ws, L.cnt),
+                                                  at<int>(ws, L.rev), at<int>(ws, L.S_local),
+                                                  at<double>(ws, L.g), at<double>(ws, L.h), use_exp,
+                                                  use_cheap, lambda, forces, e_exp, f_exp, f_cheap,
+                                                  sign);
+    else
+        k_gather_blend<float><<<nb, 256, 0, s>>>(n, L.cap, at<int>(ws, L.nbr), at<int>(ws, L.cnt),
+                                                 at<int>(ws, L.rev), at<int>(ws, L.S_local),
+                                                 at<float>(ws, L.g), at<float>(ws, L.h), use_exp,
+                                                 use_cheap, lambda, forces, e_exp, f_exp, f_cheap,
+                                                 sign);
+}
+
+__global__ void __launch_bounds__(256) k_fill_f64(double *p, double v, size_t n)
+{
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n)
+        p[i] = v;
+}
+
+void launch_fill_f64(hipStream_t s, double *p, double v, size_t n)
+{
+    if (n == 0)
+        return;
+    k_fill_f64<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(p, v, n);
+}
+
+__global__ void __launch_bounds__(256) k_copy_i32(int32_t *dst, const int32_t *src, size_t n)
+{
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n)
+        dst[i] = src[i];
+}
+
+void launch_copy_i32(hipStream_t s, int32_t *dst, const int32_t *src, size_t n)
+{
+    if (n == 0)
+        return;
+    k_copy_i32<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(dst, src, n);
+}
+
+// ------------------------------------------------------------ reductions
+
+constexpr double kKappa = 9.648533212e-3;
+
+__global__ void __launch_bounds__(256)
+    k_reduce_partial(int n, const double *__restrict__ e_exp, const double *__restrict__ e_cheap,
+                     const double *__restrict__ vel, const double *__restrict__ mass,
+                     double *__restrict__ part)
+{
+    __shared__ double sh[3][4];
+    double a = 0.0, bsum = 0.0, k = 0.0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        if (e_exp)
+            a += e_exp[i];
+        if (e_cheap)
+            bsum += e_cheap[i];
+        if (vel && mass) {
+            double v2 = vel[i] * vel[i] + vel[n + i] * vel[n + i] + vel[2 * n + i] * vel[2 * n + i];
+            k += 0.5 * mass[i] * v2;
+        }
+    }
+    a = wave_sum_d(a);
+    bsum = wave_sum_d(bsum);
+    k = wave_sum_d(k);
+    int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        sh[0][w] = a;
+        sh[1][w] = bsum;
+        sh[2][w] = k;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int q = 0; q < 3; ++q)
+            part[blockIdx.x * 3 + q] = (sh[q][0] + sh[q][1]) + (sh[q][2] + sh[q][3]);
+    }
+}
+
+__global__ void __launch_bounds__(256) k_reduce_final(const double *__restrict__ part, int nb,
+                                                      double *__restrict__ out)
+{
+    __shared__ double sh[3][4];
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < nb; b += blockDim.x)
+        for (int q = 0; q < 3; ++q)
+            v[q] += part[b * 3 + q];
+    for (int q = 0; q < 3; ++q)
+        v[q] = wave_sum_d(v[q]);
+    int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0)
+        for (int q = 0; q < 3; ++q)
+            sh[q][w] = v[q];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int q = 0; q < 3; ++q)
+            out[q] = (sh[q][0] + sh[q][1]) + (sh[q][2] + sh[q][3]);
+        out[2] /= kKappa;
+    }
+}
+
+void launch_reduce(hipStream_t s, void *ws, const WsLayout &L, const double *e_exp,
+                   const double *e_cheap, const double *vel, const double *mass, double *out)
+{
+    double *part = at<double>(ws, L.red);
+    int nb = (L.n + 255) / 256;
+    if (nb > kReduceBlocks)
+        nb = kReduceBlocks;
+    if (nb < 1)
+        nb = 1;
+    k_reduce_partial<<<nb, 256, 0, s>>>(L.n, e_exp, e_cheap, vel, mass, part);
+    k_reduce_final<<<1, 256, 0, s>>>(part, nb, out);
+}
+
+// -------------------------------------------------------- velocity Verlet
+
+__global__ void __launch_bounds__(256) k_vv(int n, Box b, double *__restrict__ pos,
+                                            double *__restrict__ vel,
+                                            const double *__restrict__ mass,
+                                            const double *__restrict__ f, double dt, int drift)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    double c = 0.5 * dt * kKappa / mass[i];
+    for (int k = 0; k < 3; ++k) {
+        double v = vel[k * n + i] + c * f[k * n + i];
+        vel[k * n + i] = v;
+        if (drift) {
+            double x = pos[k * n + i] + dt * v;
+            if (b.per[k]) {
+                x = x - b.L[k] * floor(x / b.L[k]);
+                if (x >= b.L[k])
+                    x -= b.L[k];
+            }
+            pos[k * n + i] = x;
+        }
+    }
+}
+
+void launch_vv_kick_drift(hipStream_t s, void *ws, const WsLayout &L, const Box &b, double *pos,
+                          double *vel, const double *mass, const double *forces, double dt,
+                          int drift)
+{
+    (void)ws;
+    if (L.n == 0)
+        return;
+    k_vv<<<(L.n + 255) / 256, 256, 0, s>>>(L.n, b, pos, vel, mass, forces, dt, drift);
+}
+
+}  // namespace mlmix

@@ -1,0 +1,51 @@
+"""CPU-side checks of the C ABI: the built library loads and exports every
+function include/mlmix.h declares, and the ctypes structures match the
+header's layout. No compute call is made (there is no GPU here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "mlmix.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(mlmix_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2502_19081_amd import binding as B
+    lib = B.lib()
+    names = _declared()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(lib, n), n
+        assert n in B.SIGNATURES, n
+
+
+def test_struct_layouts():
+    from paper_2502_19081_amd import binding as B
+    assert ctypes.sizeof(B.Region) == 56
+    assert ctypes.sizeof(B.Box) == 40
+    assert B.ModelDesc.uf3_c3.offset == ctypes.sizeof(B.ModelDesc) - 8
+
+
+def test_product_path_does_not_touch_the_oracle():
+    pkg = os.path.join(ROOT, "paper_2502_19081_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "oracle" not in text.lower().replace("or_", ""), f
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    import importlib
+    from paper_2502_19081_amd import binding as B
+    monkeypatch.setattr(B, "LIB_PATH", str(tmp_path / "nope.so"))
+    monkeypatch.setattr(B, "_lib", None)
+    with pytest.raises(RuntimeError):
+        B.lib()

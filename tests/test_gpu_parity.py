@@ -1,0 +1,96 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Bar: neighbour rows, lambda, masks and the compacted index sets S and M are
+bit-exact; FP64 forces agree to 1e-10 relative to the largest reference
+force; FP32 forces to 1e-4 eV/A absolute; site energies to the same bounds.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from gen import workloads as W
+from tests.gpu_common import run_gpu, assert_neighbors_equal, rel_force_err
+
+pytestmark = pytest.mark.gpu
+
+MODES = {"mixed": O.MODE_MIXED, "all_expensive": O.MODE_ALL_EXPENSIVE, "all_cheap": O.MODE_ALL_CHEAP}
+
+
+def _check(w, mode, precision, ref=None, f_tol=None):
+    print(f"case {w['name']} seed={w['seed']} n={len(w['pos'])} mode={mode} prec={precision}", flush=True)
+    ref = ref or O.mixed(w, MODES[mode])
+    g = run_gpu(w, MODES[mode], precision=precision)
+    assert_neighbors_equal(g, ref)
+    assert np.array_equal(g["lam"], ref["lam"])
+    assert np.array_equal(g["flags"], ref["flags"])
+    assert np.array_equal(g["S"], ref["S"])
+    assert np.array_equal(g["M"], ref["M"])
+    assert g["n_exp"].tolist() == [len(ref["S"]), len(ref["M"])]
+    if precision == "fp64":
+        for key, rk in (("forces", "forces"), ("f_exp", "f_exp"), ("f_cheap", "f_cheap")):
+            if np.abs(ref[rk]).max() > 0:
+                assert rel_force_err(g[key], ref[rk]) < 1e-10, key
+            else:
+                assert np.abs(g[key]).max() == 0
+        scale = max(1.0, np.abs(ref["e_exp"]).max(), np.abs(ref["e_cheap"]).max())
+        assert np.abs(g["e_exp"] - ref["e_exp"]).max() < 1e-10 * scale
+        assert np.abs(g["e_cheap"] - ref["e_cheap"]).max() < 1e-10 * scale
+    else:
+        tol = f_tol or 1e-4
+        err = np.abs(g["forces"] - ref["forces"]).max()
+        print(f"  fp32 max |dF| = {err:.3e} eV/A", flush=True)
+        assert err < tol
+        assert np.abs(g["e_exp"] - ref["e_exp"]).max() < 1e-3
+        assert np.abs(g["e_cheap"] - ref["e_cheap"]).max() < 1e-3
+    # atoms outside S carry no expensive force or energy
+    outside = np.ones(len(w["pos"]), bool)
+    outside[ref["S"]] = False
+    assert np.all(g["f_exp"][outside] == 0) and np.all(g["e_exp"][outside] == 0)
+    return g, ref
+
+
+@pytest.mark.parametrize("mode", ["mixed", "all_expensive", "all_cheap"])
+def test_c1_fp64(mode):
+    _check(W.c1(), mode, "fp64")
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_tiny_two_species_order3_fp64(seed):
+    w = W.tiny(seed=seed, n_species=2)
+    _check(w, "mixed", "fp64")
+    _check(w, "all_expensive", "fp64")
+
+
+def test_tiny_nonperiodic_cylinder_fp64():
+    w = W.tiny(seed=4, periodic=(1, 0, 0), vacuum=4.0, n_species=2)
+    w["regions"] = [W.cylinder(w["L"] / 2, 0, 2.0, 1.5), W.sphere(None, 1.5, 1.0, follow_atom=3)]
+    w["regions"][1]["center"] = np.zeros(3)
+    _check(w, "mixed", "fp64")
+
+
+def test_c2_fp32_mixed():
+    _check(W.c2(), "mixed", "fp32")
+
+
+def test_c2_fp64_mixed():
+    _check(W.c2(), "mixed", "fp64")
+
+
+def test_c2_fp32_all_expensive():
+    _check(W.c2(), "all_expensive", "fp32")
+
+
+def test_c4_replica_two_species_fp32():
+    w = W.c4_replica(3, n_target=2500)
+    _check(w, "mixed", "fp32")
+
+
+def test_repeat_is_bitwise_and_rebuild_decision():
+    # deterministic accumulation: a second call (list reused, no rebuild)
+    # reproduces the first bit for bit
+    w = W.c2()
+    g1 = run_gpu(w, 0, precision="fp32")
+    sy, pos, sp = g1["system"]
+    g2 = run_gpu(w, 0, precision="fp32", system=(sy, pos, sp), force_rebuild=False)
+    assert np.array_equal(g1["forces"], g2["forces"])
+    assert np.array_equal(g1["e_exp"], g2["e_exp"])
