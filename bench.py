@@ -1,0 +1,275 @@
+"""Benchmark of the mixed force evaluation on one MI355X.
+
+One step = one velocity-Verlet MD step of the whole hot path on the device:
+half kick + drift, neighbour-list rebuild (forced every step), lambda and
+masks, buffer, compaction of S, expensive ACE-style forward + adjoint on S,
+cheap UF3-style potential on every atom, gather + blend, half kick, FP64
+energy sums. Inputs are resident in HBM before the timed region.
+
+Prints ONE JSON line: mixed atom-steps/s (value), the all-expensive rate on
+the same GPU and their ratio, the upper-bound speedup of the paper's cost
+model, p50/p99 step latency, the force error against the FP64 CPU
+reference, the roofline position of the dominant kernel and the CPU
+baseline (the FP64 reference timed on this host).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP32_VALU_TFLOPS = 157.3
+FP64_VALU_TFLOPS = 78.6
+
+WORKLOADS = {
+    "c2": "c2: bcc W 16x16x16 cells + <111> dumbbell, 8193 atoms, sigma 0.08 A; "
+          "ACE-style n_rad 12 lmax 4 order 3 rc 5.5; UF3-style 2-body 16 knots rc 5.5 + "
+          "3-body 8x8x8 rc 3.5; sphere core 8 A + 2 A blend, buffer 5.5 A; FP32 potentials",
+    "c1": "c1: bcc W 5x5x5 cells - vacancy, 249 atoms; ACE-style 8/3/2 rc 5; UF3 pair 12 knots; FP64",
+    "c5": "c5: bcc W 80^3 cells - 200 vacancies, 1,023,800 atoms; ACE-style 16/5/3 rc 5.0; "
+          "7 + 2 A spheres; FP32",
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--config", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default=None)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    return ap.parse_args()
+
+
+def make_workload(name):
+    from gen import workloads as W
+    return getattr(W, name)()
+
+
+def pair_counts(w, nbr, cnt, S_mask):
+    """Counts that scale the per-unit work: expensive pairs inside S within
+    the expensive cutoff, cheap pairs within the 2-body cutoff, ordered
+    cheap leg pairs within the 3-body cutoff, average list length."""
+    pos = w["pos"]
+    L = w["L"]
+    per = w["periodic"].astype(bool)
+    n = len(pos)
+    rows = np.repeat(np.arange(n), cnt)
+    cols = np.concatenate([nbr[i, :cnt[i]] for i in range(n)]) if n else np.zeros(0, int)
+    d = pos[cols] - pos[rows]
+    for k in range(3):
+        if per[k]:
+            d[:, k] -= L[k] * np.round(d[:, k] / L[k])
+    r2 = (d ** 2).sum(1)
+    m = w["model"]
+    rce, rc2, rc3 = m["ace"]["rcut"], m["uf3"]["rcut2"], m["uf3"]["rcut3"]
+    exp_pairs = int(np.sum(S_mask[rows] & S_mask[cols] & (r2 < rce ** 2)))
+    cheap2 = int(np.sum(r2 < rc2 ** 2))
+    k3 = np.bincount(rows[r2 < rc3 ** 2], minlength=n) if m["uf3"]["n_knots3"] > 0 else np.zeros(n, int)
+    cheap3 = int(np.sum(k3 * (k3 - 1)))
+    return dict(exp_pairs=exp_pairs, cheap_pairs=cheap2, cheap_triplets=cheap3,
+                list_pairs=int(cnt.sum()), n=n)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+                          "(the multi-GPU design is described in DESIGN.md)"}))
+        sys.exit(2)
+    import torch
+    from gen.workloads import KAPPA  # noqa: F401
+    from paper_2502_19081_amd import binding as B
+    from paper_2502_19081_amd import core
+
+    cfg = args.config
+    w = make_workload(cfg)
+    prec = args.precision or w.get("precision", "fp32")
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    n = len(w["pos"])
+    print(f"bench: {cfg} n={n} precision={prec}", file=sys.stderr, flush=True)
+    model = core.Model(w["model"], precision=prec)
+    vel0 = w.get("vel")
+    if vel0 is None:
+        from gen.workloads import maxwell
+        vel0 = maxwell(np.random.default_rng(w["seed"] + 17), w["species"], 300.0)
+    mass = torch.from_numpy(w["masses"][w["species"]].astype(np.float64)).to(dev)
+
+    def fresh(mode):
+        _, sy, pos, sp = core.system_for(w, model=model, cap=128, device=dev)
+        vel = torch.from_numpy(np.ascontiguousarray(vel0.T)).to(dev)
+        sy.compute(pos, sp, r_buffer=w["r_buffer"], mode=mode, force_rebuild=True)
+        return sy, pos, vel, sp
+
+    dt = float(w.get("dt", 1.0))
+
+    def step(sy, pos, vel, sp, mode):
+        sy.vv_step(pos, vel, mass, sp, dt, r_buffer=w["r_buffer"], mode=mode, force_rebuild=True)
+
+    def run(mode, steps, warmup, stage_mask=0, latency=False, graph=False):
+        """Times `steps` steps. graph=True captures one step in a HIP graph
+        and replays it; otherwise the step's kernels are launched eagerly."""
+        sy, pos, vel, sp = fresh(mode)
+        for _ in range(warmup):
+            step(sy, pos, vel, sp, mode)
+        sy.status()
+        g = None
+        if graph:
+            g = torch.cuda.CUDAGraph()
+            cs = torch.cuda.Stream()
+            cs.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(cs):
+                with torch.cuda.graph(g, stream=cs):
+                    step(sy, pos, vel, sp, mode)
+            torch.cuda.current_stream().wait_stream(cs)
+            for _ in range(3):
+                g.replay()
+        model.profile_read()
+        model.profile_enable(stage_mask)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lat = []
+        for _ in range(steps):
+            ts = time.perf_counter()
+            if g is not None:
+                g.replay()
+            else:
+                step(sy, pos, vel, sp, mode)
+            if latency:
+                torch.cuda.synchronize()
+                lat.append(time.perf_counter() - ts)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        model.profile_enable(0)
+        prof = model.profile_read()
+        sy.status()
+        return (t1 - t0), prof, lat, sy
+
+    # 1. per-stage breakdown (every stage bracketed) to find the dominant kernel
+    _, prof_all, _, sy_m = run(B.MODE_MIXED, max(10, args.steps // 4), args.warmup,
+                               stage_mask=(1 << B.N_STAGES) - 1)
+    stage_ms = {k: v[0] / max(v[1], 1) for k, v in prof_all.items() if v[1]}
+    dominant = max(stage_ms, key=lambda k: stage_ms[k] * prof_all[k][1])
+    dom_bit = [B.lib().mlmix_profile_stage_name(i).decode() for i in range(B.N_STAGES)].index(dominant)
+
+    # 2. the dominant kernel's duration: K eager steps with only that stage
+    # bracketed by HIP events on the launch stream
+    el_eager, prof, _, _ = run(B.MODE_MIXED, args.steps, args.warmup, stage_mask=1 << dom_bit)
+    dom_ms, dom_cnt = prof[dominant]
+    dom_avg_ms = dom_ms / max(dom_cnt, 1)
+
+    # 3. timed region: K mixed steps replayed from one captured HIP graph
+    el, _, _, _ = run(B.MODE_MIXED, args.steps, args.warmup, graph=True)
+    ms_step = 1e3 * el / args.steps
+    value = n * args.steps / el
+
+    # 4. all-expensive and all-cheap rates on the same GPU, same method
+    el_e, _, _, _ = run(B.MODE_ALL_EXPENSIVE, args.steps, args.warmup, graph=True)
+    el_c, _, _, _ = run(B.MODE_ALL_CHEAP, args.steps, args.warmup, graph=True)
+    rate_e = n * args.steps / el_e
+    rate_c = n * args.steps / el_c
+
+    # 5. step latency (each replay waited for)
+    _, _, lat, _ = run(B.MODE_MIXED, args.steps, 5, latency=True, graph=True)
+    lat_ms = np.array(lat) * 1e3
+
+    # work counts of the initial configuration (for the roofline)
+    sy, pos, vel, sp = fresh(B.MODE_MIXED)
+    out = sy.compute(pos, sp, r_buffer=w["r_buffer"], mode=B.MODE_MIXED, force_rebuild=True)
+    torch.cuda.synchronize()
+    nS, nM = [int(x) for x in out["n_exp"].cpu()]
+    S_idx, _ = sy.index_sets()
+    S_mask = np.zeros(n, bool)
+    S_mask[S_idx.cpu().numpy()] = True
+    nbr, cnt = sy.neighbors()
+    pc = pair_counts(w, nbr.cpu().numpy(), cnt.cpu().numpy(), S_mask)
+    fl = np.zeros(6)
+    import ctypes
+    B.check(B.lib().mlmix_model_flops(model.handle, fl.ctypes.data_as(ctypes.c_void_p)))
+    gpu_forces = out["forces"].cpu().numpy().T.copy()
+
+    tsz = 8 if prec == "fp64" else 4
+    work = {
+        # flops per launch
+        "ace_contract": ("flops", fl[0] * nS),
+        "ace_basis": ("flops", fl[1] * pc["exp_pairs"]),
+        "ace_pairgrad": ("flops", fl[2] * pc["exp_pairs"]),
+        "uf3": ("flops", fl[3] * pc["cheap_pairs"] + fl[4] * pc["cheap_triplets"]),
+        # HBM bytes per launch
+        "neighbours": ("bytes", 24 * n + 8 * pc["list_pairs"] + 8 * n),
+        "regions": ("bytes", 33 * n),
+        "compaction": ("bytes", 9 * n + 4 * nS),
+        "gather_blend": ("bytes", 44 * n + 8 * pc["list_pairs"] + 2 * 3 * tsz * pc["list_pairs"]
+                         + 2 * 3 * tsz * pc["exp_pairs"]),
+        "integrator": ("bytes", 2 * 88 * n),
+        "energy_sums": ("bytes", 48 * n),
+    }
+    kind, units = work[dominant]
+    if kind == "flops":
+        peak = FP64_VALU_TFLOPS if prec == "fp64" else FP32_VALU_TFLOPS
+        achieved = units / (dom_avg_ms * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                "frac": achieved / peak, "traffic": None, "kernel": dominant,
+                "avg_ms": dom_avg_ms, "launches": dom_cnt, "algorithmic_per_launch": units}
+    else:
+        achieved = units / (dom_avg_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": dominant,
+                "avg_ms": dom_avg_ms, "launches": dom_cnt, "algorithmic_per_launch": units}
+
+    # 6. CPU baseline: the FP64 reference on this host, bounded sample of the
+    # same workload (its first force call also gives the force error)
+    cpu = None
+    ferr = None
+    if not args.no_cpu_baseline:
+        import oracle as O
+        t0 = time.perf_counter()
+        ref = O.mixed(w, O.MODE_MIXED)
+        t_first = time.perf_counter() - t0
+        ferr = float(np.abs(gpu_forces - ref["forces"]).max())
+        n_cpu = max(1, int(args.cpu_seconds / max(t_first, 1e-3)))
+        t0 = time.perf_counter()
+        O.velocity_verlet(w, w["pos"], vel0, float(w.get("dt", 1.0)), n_cpu, mode=O.MODE_MIXED)
+        t_cpu = time.perf_counter() - t0
+        cpu = {"value": n * n_cpu / t_cpu, "unit": "atom-steps/s", "cores": O.num_threads(),
+               "kind": "oracle",
+               "sample": f"{n_cpu} velocity-Verlet steps of the same {cfg} workload in mixed mode "
+                         f"(plus one initial force call), FP64, neighbour list rebuilt every step"}
+
+    S_CE = rate_c / rate_e
+    s_ul = n * S_CE / (nS * S_CE + n)
+    res = {
+        "metric": "mixed atom-steps/s vs all-expensive at stated force error; p99 step latency",
+        "value": value, "unit": "atom-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32" if prec == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": WORKLOADS[cfg], "n_atoms": n, "mode": "mixed",
+                   "precision": prec, "neighbour_rebuild": "every step", "n_S": nS, "n_lambda_pos": nM,
+                   "launch": "one captured HIP graph per step, replayed"},
+        "eager_atom_steps_per_s": n * args.steps / el_eager,
+        "all_expensive_atom_steps_per_s": rate_e,
+        "all_cheap_atom_steps_per_s": rate_c,
+        "mixed_over_all_expensive": value / rate_e,
+        "S_UL": s_ul,
+        "force_err_max_eV_per_A": ferr,
+        "p50_step_ms": float(np.percentile(lat_ms, 50)),
+        "p99_step_ms": float(np.percentile(lat_ms, 99)),
+        "stage_ms_per_step": {k: round(v, 5) for k, v in stage_ms.items()},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

@@ -207,7 +207,8 @@ int mlmix_energy_reduce(mlmix_ctx *ctx, void *stream, void *ws, int32_t n_atoms,
 
 /* Waits for `stream`, then reads the device status word of the workspace:
  * *status_bits receives MLMIX_STATUS_* bits, *required_cap the largest
- * neighbour count seen (for regrowing nbr_cap). Returns MLMIX_OK when no
+ * neighbour count of an overflowing row (0 without overflow; for regrowing
+ * nbr_cap). Returns MLMIX_OK when no
  * bit is set, else the matching negative code (overflow first). */
 int mlmix_status(mlmix_ctx *ctx, void *stream, void *ws, int32_t *status_bits,
                  int32_t *required_cap);
@@ -220,6 +221,27 @@ int mlmix_get_neighbors(mlmix_ctx *ctx, void *stream, void *ws, int32_t n_atoms,
                         int32_t *nbr_out, int32_t *cnt_out);
 int mlmix_get_index_sets(mlmix_ctx *ctx, void *stream, void *ws, int32_t n_atoms,
                          int32_t *S_out, int32_t *M_out);
+
+/* Stage timing for benchmarks. Stages (bit i of the mask, name from
+ * mlmix_profile_stage_name(i)): 0 neighbours (cells, rows, reverse slots),
+ * 1 regions (lambda, masks, buffer), 2 compaction, 3 expensive atomic basis,
+ * 4 expensive contraction + dE/dA, 5 expensive pair adjoint, 6 cheap
+ * potential, 7 gather + blend, 8 integrator, 9 energy sums.
+ * mlmix_profile_enable(ctx, mask) brackets each selected stage of later
+ * calls with HIP events recorded on the caller's stream (no host wait);
+ * mlmix_profile_read() waits for those events and returns, per stage, the
+ * summed milliseconds and the number of bracketed launches since the last
+ * read (arrays of MLMIX_N_STAGES entries). */
+#define MLMIX_N_STAGES 10
+int mlmix_profile_enable(mlmix_ctx *ctx, uint32_t stage_mask);
+int mlmix_profile_read(mlmix_ctx *ctx, double *ms, int64_t *count);
+const char *mlmix_profile_stage_name(int32_t stage);
+
+/* Operation counts of the kernels as written, for roofline reporting
+ * (out[6]): [0] expensive contraction + dE/dA per S atom, [1] atomic basis
+ * per expensive pair, [2] pair adjoint per expensive pair, [3] cheap 2-body
+ * per pair, [4] cheap 3-body per ordered pair of legs, [5] reserved. */
+int mlmix_model_flops(const mlmix_ctx *ctx, double *out);
 
 /* Thread-local description of the last error. */
 const char *mlmix_last_error(void);

@@ -18,6 +18,7 @@ FP64, FP32 = 0, 1
 MODE_MIXED, MODE_ALL_EXPENSIVE, MODE_ALL_CHEAP = 0, 1, 2
 FORCE_REBUILD = 0x100
 ENERGY_ONLY = 0x200
+N_STAGES = 10
 STATUS_NEIGH_OVERFLOW, STATUS_OUT_OF_BOX, STATUS_NONFINITE, STATUS_TRIPLET_OVERFLOW, STATUS_BAD_SPECIES = 1, 2, 4, 8, 16
 
 
@@ -69,6 +70,10 @@ SIGNATURES = {
     "mlmix_status": (ctypes.c_int, [_vp, _vp, _vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
     "mlmix_get_neighbors": (ctypes.c_int, [_vp, _vp, _vp, _i32, _vp, _vp]),
     "mlmix_get_index_sets": (ctypes.c_int, [_vp, _vp, _vp, _i32, _vp, _vp]),
+    "mlmix_model_flops": (ctypes.c_int, [_vp, _vp]),
+    "mlmix_profile_enable": (ctypes.c_int, [_vp, _u32]),
+    "mlmix_profile_read": (ctypes.c_int, [_vp, _vp, _vp]),
+    "mlmix_profile_stage_name": (ctypes.c_char_p, [_i32]),
     "mlmix_last_error": (ctypes.c_char_p, []),
 }
 

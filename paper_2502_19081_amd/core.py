@@ -71,6 +71,18 @@ class Model:
         self.handle = h
         self.r_list = B.lib().mlmix_list_radius(h)
 
+    def profile_enable(self, stage_mask):
+        """Bracket the selected stages (bit i = stage i) with HIP events."""
+        B.check(B.lib().mlmix_profile_enable(self.handle, int(stage_mask)))
+
+    def profile_read(self):
+        """{stage name: (milliseconds, launches)} since the last read."""
+        ms = (ctypes.c_double * B.N_STAGES)()
+        cnt = (ctypes.c_int64 * B.N_STAGES)()
+        B.check(B.lib().mlmix_profile_read(self.handle, ms, cnt))
+        return {B.lib().mlmix_profile_stage_name(i).decode(): (ms[i], cnt[i])
+                for i in range(B.N_STAGES)}
+
     def close(self):
         if self.handle:
             B.lib().mlmix_destroy(self.handle)

@@ -1,15 +1,19 @@
 // Expensive ACE-style potential on the induced subsystem S (Algorithm 4 and
 // Fig. 10: atoms outside S are removed from every neighbour list), on gfx950.
 //
-//  k_ace_basis    atomic basis A_i[a][lm] = sum_{j in S, r<rc} R_n(r) Y_lm(u)
+// Per-atom arrays A and dE/dA are stored channel-fastest: X[s][lm][c] with
+// c < nchp (channels padded to a multiple of four, padding zero).
+//
+//  k_ace_basis    atomic basis A_i[lm][a] = sum_{j in S, r<rc} R_n(r) Y_lm(u)
 //                 (one wavefront per S atom; per-neighbour R, Y staged in LDS;
-//                 lanes own (channel, lm) accumulators, summed in row order)
-//  k_ace_contract site energy and its adjoint dE/dA in one pass. The order-3
-//                 readout is a symmetric cubic form E3 = sum_p A_p D_p with
-//                 D_{c,l3,m3} = sum_{l1<=l2} sum_{ab} W[ab][c] P_{ab,m3},
-//                 P_{ab,m3} = sum_{m1 m2} G A_{a l1 m1} A_{b l2 m2} (sparse
-//                 Gaunt stage, LDS) and W the symmetrised coefficients (dense
-//                 stage); dE3/dA = 3 D. Order 2 likewise: dE2/dA = 2 D2.
+//                 lanes own (lm, channel) accumulators, summed in row order)
+//  k_ace_blocks   order-3 readout as a symmetric cubic form, per block
+//                 (l1 <= l2, l3): P_{ab,m3} = sum_{m1 m2} G A_{a l1 m1} A_{b l2 m2}
+//                 (sparse Gaunt stage, VALU/LDS) and D_{c,l3 m3} = sum_ab
+//                 P_{ab,m3} W_{ab,c} (dense stage on MFMA for single-species
+//                 models; W holds the symmetrised coefficients)
+//  k_ace_finalize D3 = sum of the l3 blocks, D2 for order 2, then
+//                 dE/dA = c1 + 2 D2 + 3 D3 and E = c0 + sum A (c1 + D2 + D3)
 //  k_ace_pairgrad hand-written adjoint of the atomic basis: per pair,
 //                 g_ij = dE_i/dd_ij = sum_{n,lm} dE/dA (R_n' u Y + R_n grad Y),
 //                 recomputing R, Y and grad Y instead of storing them.
@@ -21,12 +25,12 @@ namespace mlmix {
 
 template <typename T>
 struct AceArgs {
-    int ns, nrad, lmax, order, nchan, KA, L2, L1;
+    int ns, nrad, lmax, order, nchan, nchp, KAt, L2, L1;
     T rc;
     double rc2;
     const T *K, *c0, *c1, *c2s, *W, *gval;
     const PBlock *pb;
-    const int *gm3, *gidx;
+    const int *gm3, *gofs;
     int pb_lo[kMaxLmax + 1], pb_hi[kMaxLmax + 1];
     int w_per_species;
 };
@@ -35,14 +39,14 @@ __device__ __forceinline__ void pair_disp_d(const double *__restrict__ pos, int 
                                             const Box &b, double d[3])
 {
 #pragma clang fp contract(off)
+    // issue the six loads before any folding so that they overlap
+    const double xj[3] = {pos[j], pos[n + j], pos[2 * n + j]};
+    const double xi[3] = {pos[i], pos[n + i], pos[2 * n + i]};
     for (int k = 0; k < 3; ++k) {
-        double dx = pos[k * n + j] - pos[k * n + i];
+        double dx = xj[k] - xi[k];
         if (b.per[k]) {
             double h = 0.5 * b.L[k];
-            if (dx > h)
-                dx = dx - b.L[k];
-            else if (dx < -h)
-                dx = dx + b.L[k];
+            dx = dx > h ? dx - b.L[k] : (dx < -h ? dx + b.L[k] : dx);
         }
         d[k] = dx;
     }
@@ -57,38 +61,54 @@ __device__ __forceinline__ double norm2_d(const double d[3])
     return s;
 }
 
-constexpr int kMaxOwn = 16;  // (channel, lm) entries per lane: KA <= 1024
+constexpr int kMaxOwn = 16;  // (lm, channel) entries per lane: L2 * nchp <= 1024
 
+// wpb atoms per block (one wavefront each). The neighbour-chunk loop runs to
+// the block's longest row so that the waves meet at every barrier.
 template <typename T>
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(256)
     k_ace_basis(const double *__restrict__ pos, int n, Box b, const int32_t *__restrict__ species,
                 int cap, const int *__restrict__ nbr, const int *__restrict__ cnt,
                 const int *__restrict__ S_idx, const int *__restrict__ S_local,
-                const int *__restrict__ hdr, AceArgs<T> a, T *__restrict__ A)
+                const int *__restrict__ hdr, AceArgs<T> a, int wpb, T *__restrict__ A)
 {
-    int s = blockIdx.x;
-    if (s >= hdr[H_NS])
-        return;
-    extern __shared__ char smem_raw[];
-    T *Rt = reinterpret_cast<T *>(smem_raw);
+    const int nS = hdr[H_NS];
+    if (blockIdx.x * wpb >= nS)
+        return;  // uniform across the block
+    const int w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int s = blockIdx.x * wpb + w;
+    const bool valid = s < nS;
+    extern __shared__ __align__(16) char smem_raw[];
+    const size_t slice = (size_t)64 * (a.nrad + a.L2);
+    T *Rt = reinterpret_cast<T *>(smem_raw) + (size_t)w * slice;
     T *Yt = Rt + 64 * a.nrad;
-    int *zt = reinterpret_cast<int *>(Yt + 64 * a.L2);
-    int lane = threadIdx.x;
-    int i = S_idx[s];
-    int c = cnt[i];
+    int *zt = reinterpret_cast<int *>(reinterpret_cast<T *>(smem_raw) + (size_t)wpb * slice) + w * 64;
+    __shared__ int cm[4];
+    const int i = valid ? S_idx[s] : 0;
+    const int c = valid ? cnt[i] : 0;
+    if (lane == 0)
+        cm[w] = c;
     const int *row = nbr + (size_t)i * cap;
+    // lane owns entries e = lane + 64 k of the layout [lm][nchp]
     T acc[kMaxOwn];
     int own_z[kMaxOwn], own_n[kMaxOwn], own_lm[kMaxOwn];
 #pragma unroll
     for (int k = 0; k < kMaxOwn; ++k) {
         acc[k] = T(0);
         int e = lane + 64 * k;
-        int ch = e / a.L2;
-        own_lm[k] = e - ch * a.L2;
-        own_z[k] = (e < a.KA) ? ch / a.nrad : -2;
+        int lm = e / a.nchp;
+        int ch = e - lm * a.nchp;
+        own_lm[k] = lm < a.L2 ? lm : 0;
+        own_z[k] = (lm < a.L2 && ch < a.nchan) ? ch / a.nrad : -2;
         own_n[k] = ch % a.nrad;
     }
-    for (int base = 0; base < c; base += 64) {
+    __syncthreads();
+    int cmax = 0;
+    for (int q = 0; q < wpb; ++q)
+        cmax = max(cmax, cm[q]);
+    const int nown = (a.KAt + 63) >> 6;
+    for (int base = 0; base < cmax; base += 64) {
         int slot = base + lane;
         int zj = -1;
         if (slot < c) {
@@ -99,8 +119,9 @@ __global__ void __launch_bounds__(64)
                 double r2 = norm2_d(d);
                 if (r2 < a.rc2) {
                     double rd = sqrt(r2);
+                    double ird = 1.0 / rd;
                     T r = T(rd);
-                    T ux = T(d[0] / rd), uy = T(d[1] / rd), uz = T(d[2] / rd);
+                    T ux = T(d[0] * ird), uy = T(d[1] * ird), uz = T(d[2] * ird);
                     T R[kMaxNrad], dR[kMaxNrad];
                     radial<T>(a.nrad, r, a.rc, R, dR);
 #pragma unroll
@@ -121,164 +142,287 @@ __global__ void __launch_bounds__(64)
             int z = zt[t];
             if (z < 0)
                 continue;
+            const T *Rr = Rt + t * a.nrad;
+            const T *Yr = Yt + t * a.L2;
 #pragma unroll
-            for (int k = 0; k < kMaxOwn; ++k)
+            for (int k = 0; k < kMaxOwn; ++k) {
+                if (k >= nown)
+                    break;
                 if (own_z[k] == z)
-                    acc[k] += Rt[t * a.nrad + own_n[k]] * Yt[t * a.L2 + own_lm[k]];
+                    acc[k] += Rr[own_n[k]] * Yr[own_lm[k]];
+            }
         }
         __syncthreads();
     }
-    T *As = A + (size_t)s * a.KA;
+    if (!valid)
+        return;
+    T *As = A + (size_t)s * a.KAt;
 #pragma unroll
     for (int k = 0; k < kMaxOwn; ++k) {
         int e = lane + 64 * k;
-        if (e < a.KA)
-            As[e] = acc[k];
+        if (e < a.KAt)
+            As[e] = acc[k];  // padded channels stay zero
     }
 }
 
 template <typename T>
-__device__ __forceinline__ T wave_sum(T v)
+struct Mfma;
+template <>
+struct Mfma<float> {
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ v4 op(float x, float y, v4 c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(x, y, c, 0, 0, 0);
+    }
+};
+template <>
+struct Mfma<double> {
+    typedef double v4 __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ v4 op(double x, double y, v4 c)
+    {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, c, 0, 0, 0);
+    }
+};
+
+// Rows of the P tile (atoms x m3, padded to 16) and its row stride (odd, so
+// that 16 consecutive rows fall into distinct LDS banks).
+__host__ __device__ inline int blocks_rows(int ta, int lmax) { return ((ta * (2 * lmax + 1) + 15) / 16) * 16; }
+__host__ __device__ inline int blocks_kstride(int nch, int nchp) { return nch * nchp + 1; }
+
+// Order-3 contraction. A persistent grid walks the work items (tile of TA
+// atoms of S, block (l1 <= l2, l3)); consecutive items share the tile.
+// Sparse Gaunt stage: items (atom, m3, a, four b) accumulate
+// sum G A_{a,l1 m1} A_{b..b+3,l2 m2} over the block's entries into the P
+// tile [row = atom*d3 + m3][k = a*nchp + b]. Dense stage: D[row][c] =
+// sum_k P[row][k] W[k][c] as 16x16 MFMA tiles (weights staged in LDS,
+// single-species models) or VALU groups of four channels (weights read
+// through the cache, indexed by each atom's species). The block's D goes
+// to Dpart; k_ace_finalize sums the blocks of one l3 in a fixed order.
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_ace_blocks(const int32_t *__restrict__ species, const int *__restrict__ S_idx,
+                 const int *__restrict__ hdr, AceArgs<T> a, int TA, int n_pb, int max_ent,
+                 int use_mfma, const int *__restrict__ dp_off, int dp_stride,
+                 const T *__restrict__ A, T *__restrict__ Dpart)
 {
+    const int nS = hdr[H_NS];
+    const int ntile = (nS + TA - 1) / TA;
+    const int nitems = ntile * n_pb;
+    if ((int)blockIdx.x >= nitems)
+        return;  // uniform across the block
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wv = tid >> 6;
+    const int nch = a.nchan, nchp = a.nchp, KAt = a.KAt;
+    const int Kp = nch * nchp;
+    const int Ks = blocks_kstride(nch, nchp);
+    const int rowsp = blocks_rows(TA, a.lmax);
+    extern __shared__ __align__(16) char smem_raw[];
+    T *At = reinterpret_cast<T *>(smem_raw);  // [TA][L2][nchp]
+    T *P = At + (size_t)TA * KAt;              // [rowsp][Ks]
+    T *Ws = P + (size_t)rowsp * Ks;            // [Kp][nchp] when MFMA
+    T *gv = Ws + (use_mfma ? (size_t)Kp * nchp : 0);
+    int *gi = reinterpret_cast<int *>(gv + max_ent);
+    int *g3 = gi + max_ent;
+    __shared__ int zt[16];
+    int cur_tile = -1;
+    for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
+        const int tile = item / n_pb, p = item - tile * n_pb;
+        const int s0 = tile * TA;
+        const int na = (nS - s0) < TA ? (nS - s0) : TA;
+        const PBlock pb = a.pb[p];
+        const int d3 = 2 * pb.l3 + 1;
+        const int nrows = na * d3;
+        __syncthreads();  // the previous item's readers are done with LDS
+        if (tile != cur_tile) {
+            if (tid < na)
+                zt[tid] = sp_clamp(species[S_idx[s0 + tid]], a.ns);
+            const T *src = A + (size_t)s0 * KAt;
+            for (int e = tid; e < na * KAt; e += 256)
+                At[e] = src[e];
+            cur_tile = tile;
+        }
+        const int e_lo = a.gm3[pb.gm3_off];
+        const int e_hi = a.gm3[pb.gm3_off + d3];
+        for (int e = tid; e < e_hi - e_lo; e += 256) {
+            gv[e] = a.gval[e_lo + e];
+            gi[e] = a.gofs[e_lo + e];
+        }
+        for (int e = tid; e <= d3; e += 256)
+            g3[e] = a.gm3[pb.gm3_off + e] - e_lo;
+        if (use_mfma) {
+            const T *src = a.W + pb.w_off;
+            for (int e = tid; e < Kp * nchp; e += 256)
+                Ws[e] = src[e];
+        }
+        __syncthreads();
+        // sparse Gaunt stage. Thread -> (a, four b) once; rows advance by a
+        // fixed stride, so no per-item integer division is needed.
+        const int ncb = nchp >> 2;
+        const int Q = nch * ncb;
+        const int rstep = Q <= 256 ? 256 / Q : 1;
+        for (int q = (Q <= 256 ? (tid < rstep * Q ? tid % Q : Q) : tid); q < Q; q += 256) {
+            const int aa = q / ncb, bq = q - aa * ncb;
+            int r = Q <= 256 ? tid / Q : 0;
+            int t = r / d3, m3 = r - t * d3;
+            for (; r < nrows; r += rstep) {
+                const T *Att = At + (size_t)t * KAt;
+                T p0 = T(0), p1 = T(0), p2 = T(0), p3 = T(0);
+                const int e1 = g3[m3 + 1];
+                for (int e = g3[m3]; e < e1; ++e) {
+                    int of = gi[e];
+                    T ga = gv[e] * Att[(of & 0xffff) + aa];
+                    const T *Bb = Att + (of >> 16) + bq * 4;
+                    p0 += ga * Bb[0];
+                    p1 += ga * Bb[1];
+                    p2 += ga * Bb[2];
+                    p3 += ga * Bb[3];
+                }
+                T *Pr = P + (size_t)r * Ks + aa * nchp + bq * 4;
+                Pr[0] = p0;
+                Pr[1] = p1;
+                Pr[2] = p2;
+                Pr[3] = p3;
+                m3 += rstep;
+                while (m3 >= d3) {
+                    m3 -= d3;
+                    ++t;
+                }
+            }
+        }
+        __syncthreads();
+        T *Dbase = Dpart + dp_off[p];
+        if (use_mfma) {
+            // D[row][c] = sum_k P[row][k] Ws[k][c]: 16x16 tiles over 4 waves
+            const int nrt = (nrows + 15) >> 4, nct = (nch + 15) >> 4;
+            for (int tt = wv; tt < nrt * nct; tt += 4) {
+                const int rt = tt / nct, ct = tt - rt * nct;
+                const int row = rt * 16 + (lane & 15);
+                const int col = ct * 16 + (lane & 15);
+                const int kk = lane >> 4;
+                const bool rv = row < nrows, cv = col < nch;
+                const T *Pr = P + (size_t)row * Ks;
+                typename Mfma<T>::v4 acc = {T(0), T(0), T(0), T(0)};
+                for (int k0 = 0; k0 < Kp; k0 += 4) {
+                    int k = k0 + kk;
+                    T av = rv ? Pr[k] : T(0);
+                    T bv = cv ? Ws[k * nchp + col] : T(0);
+                    acc = Mfma<T>::op(av, bv, acc);
+                }
 #pragma unroll
-    for (int d = 32; d > 0; d >>= 1)
-        v += __shfl_xor(v, d);
-    return v;
+                for (int v = 0; v < 4; ++v) {
+                    int r = rt * 16 + 4 * kk + v;
+                    if (r < nrows && cv) {
+                        int t = r / d3, m3 = r - t * d3;
+                        Dbase[(size_t)(s0 + t) * dp_stride + col * d3 + m3] = acc[v];
+                    }
+                }
+            }
+        } else {
+            // VALU: groups (row, four channels); weights per atom species
+            for (int g = tid; g < nrows * ncb; g += 256) {
+                int r = g / ncb, cb = g - r * ncb;
+                int t = r / d3, m3 = r - t * d3;
+                const T *Pr = P + (size_t)r * Ks;
+                const T *Wc = a.W + (size_t)zt[t] * a.w_per_species + pb.w_off + cb * 4;
+                T s0v = T(0), s1v = T(0), s2v = T(0), s3v = T(0);
+                for (int k = 0; k < Kp; ++k) {
+                    T pv = Pr[k];
+                    const T *w = Wc + (size_t)k * nchp;
+                    s0v += pv * w[0];
+                    s1v += pv * w[1];
+                    s2v += pv * w[2];
+                    s3v += pv * w[3];
+                }
+                T vals[4] = {s0v, s1v, s2v, s3v};
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    int c = cb * 4 + q;
+                    if (c < nch)
+                        Dbase[(size_t)(s0 + t) * dp_stride + c * d3 + m3] = vals[q];
+                }
+            }
+        }
+    }
 }
 
-constexpr int kMaxOut = 8;  // order-3 outputs (c, m3) per lane
-
+// One wavefront per S atom, lanes over the atomic-basis entries (lm, c):
+// D3 = sum over the l-blocks' partial D (fixed order), D2 from the order-2
+// coefficients, dE/dA = c1 + 2 D2 + 3 D3 and E = c0 + sum A (c1 + D2 + D3).
 template <typename T>
-__global__ void __launch_bounds__(64)
-    k_ace_contract(const int32_t *__restrict__ species, const int *__restrict__ S_idx,
-                   const int *__restrict__ hdr, AceArgs<T> a, const T *__restrict__ A,
+__global__ void __launch_bounds__(256)
+    k_ace_finalize(const int32_t *__restrict__ species, const int *__restrict__ S_idx,
+                   const int *__restrict__ hdr, AceArgs<T> a, const int *__restrict__ dp_off,
+                   int dp_stride, const T *__restrict__ A, const T *__restrict__ Dpart,
                    T *__restrict__ dEdA, double *__restrict__ e_exp)
 {
-    int s = blockIdx.x;
+    const int s = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     if (s >= hdr[H_NS])
         return;
-    extern __shared__ char smem_raw[];
-    T *As = reinterpret_cast<T *>(smem_raw);
-    T *dAs = As + a.KA;
-    T *Ps = dAs + a.KA;
-    int lane = threadIdx.x;
-    int i = S_idx[s];
-    int z = sp_clamp(species[i], a.ns);
-    const int nch = a.nchan, L2 = a.L2;
-    for (int e = lane; e < a.KA; e += 64) {
-        As[e] = A[(size_t)s * a.KA + e];
-        dAs[e] = T(0);
-    }
-    __syncthreads();
-    T Ep = T(0);
-    // order 1: E1 = sum_a c1_a A_{a,00}
-    for (int ch = lane; ch < nch; ch += 64) {
-        T c = a.c1[z * nch + ch];
-        dAs[ch * L2] += c;
-        Ep += c * As[ch * L2];
-    }
-    __syncthreads();
-    // order 2: D2_{a,lm} = sum_b C2_{ab,l} A_{b,lm}; E2 = A.D2; dE2/dA = 2 D2
-    if (a.order >= 2) {
-        for (int e = lane; e < a.KA; e += 64) {
-            int ch = e / L2, lm = e - ch * L2;
-            int l = 0;
-            while ((l + 1) * (l + 1) <= lm)
-                ++l;
-            const T *C = a.c2s + (((size_t)z * a.L1 + l) * nch + ch) * nch;
-            T D = T(0);
+    const int i = S_idx[s];
+    const int z = sp_clamp(species[i], a.ns);
+    const int nch = a.nchan, nchp = a.nchp;
+    const T *As = A + (size_t)s * a.KAt;
+    const T *Ds = Dpart + (size_t)s * dp_stride;
+    double es = 0.0;
+    for (int e = lane; e < a.KAt; e += 64) {
+        int lm = e / nchp, c = e - lm * nchp;
+        if (c >= nch) {
+            dEdA[(size_t)s * a.KAt + e] = T(0);
+            continue;
+        }
+        int l = 0;
+        while ((l + 1) * (l + 1) <= lm)
+            ++l;
+        int m3 = lm - l * l;
+        T c1t = (l == 0) ? a.c1[z * nch + c] : T(0);
+        T D2 = T(0);
+        if (a.order >= 2) {
+            const T *C = a.c2s + (((size_t)z * a.L1 + l) * nch + c) * nch;
+            const T *Al = As + lm * nchp;
             for (int bb = 0; bb < nch; ++bb)
-                D += C[bb] * As[bb * L2 + lm];
-            dAs[e] += T(2) * D;
-            Ep += As[e] * D;
+                D2 += C[bb] * Al[bb];
         }
+        T D3 = T(0);
+        if (a.order >= 3)
+            for (int p = a.pb_lo[l]; p < a.pb_hi[l]; ++p)
+                D3 += Ds[dp_off[p] + c * (2 * l + 1) + m3];
+        T Av = As[e];
+        dEdA[(size_t)s * a.KAt + e] = c1t + T(2) * D2 + T(3) * D3;
+        es += (double)(Av * (c1t + D2 + D3));
     }
-    __syncthreads();
-    if (a.order >= 3) {
-        const T *Wz = a.W + (size_t)z * a.w_per_species;
-        const int nab = nch * nch;
-        for (int l3 = 0; l3 <= a.lmax; ++l3) {
-            if (a.pb_lo[l3] >= a.pb_hi[l3])
-                continue;
-            const int d3 = 2 * l3 + 1;
-            const int nout = nch * d3;
-            T acc[kMaxOut];
 #pragma unroll
-            for (int k = 0; k < kMaxOut; ++k)
-                acc[k] = T(0);
-            for (int p = a.pb_lo[l3]; p < a.pb_hi[l3]; ++p) {
-                const PBlock pb = a.pb[p];
-                const int o1 = pb.l1 * pb.l1, o2 = pb.l2 * pb.l2;
-                // sparse Gaunt stage: P_{ab,m3}
-                for (int ab = lane; ab < nab; ab += 64) {
-                    int aa = ab / nch, bb = ab - aa * nch;
-                    const T *Aa = As + aa * L2 + o1;
-                    const T *Ab = As + bb * L2 + o2;
-                    for (int m3 = 0; m3 < d3; ++m3) {
-                        int e0 = a.gm3[pb.gm3_off + m3], e1 = a.gm3[pb.gm3_off + m3 + 1];
-                        T pv = T(0);
-                        for (int e = e0; e < e1; ++e) {
-                            int mm = a.gidx[e];
-                            pv += a.gval[e] * Aa[mm & 0xff] * Ab[mm >> 8];
-                        }
-                        Ps[ab * d3 + m3] = pv;
-                    }
-                }
-                __syncthreads();
-                // dense stage: D_{c,m3} += sum_ab W[ab][c] P_{ab,m3}
-                const T *Wb = Wz + pb.w_off;
-#pragma unroll
-                for (int k = 0; k < kMaxOut; ++k) {
-                    int o = lane + 64 * k;
-                    if (o < nout) {
-                        int cc = o / d3, m3 = o - cc * d3;
-                        T sacc = acc[k];
-                        for (int ab = 0; ab < nab; ++ab)
-                            sacc += Wb[(size_t)ab * nch + cc] * Ps[ab * d3 + m3];
-                        acc[k] = sacc;
-                    }
-                }
-                __syncthreads();
-            }
-#pragma unroll
-            for (int k = 0; k < kMaxOut; ++k) {
-                int o = lane + 64 * k;
-                if (o < nout) {
-                    int cc = o / d3, m3 = o - cc * d3;
-                    int idx = cc * L2 + l3 * l3 + m3;
-                    dAs[idx] += T(3) * acc[k];
-                    Ep += As[idx] * acc[k];
-                }
-            }
-            __syncthreads();
-        }
-    }
-    T E = wave_sum(Ep);
+    for (int d = 32; d > 0; d >>= 1)
+        es += __shfl_xor(es, d);
     if (lane == 0)
-        e_exp[i] = (double)a.c0[z] + (double)E;
-    for (int e = lane; e < a.KA; e += 64)
-        dEdA[(size_t)s * a.KA + e] = dAs[e];
+        e_exp[i] = (double)a.c0[z] + es;
 }
 
 template <typename T>
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(256)
     k_ace_pairgrad(const double *__restrict__ pos, int n, Box b, const int32_t *__restrict__ species,
                    int cap, const int *__restrict__ nbr, const int *__restrict__ cnt,
                    const int *__restrict__ S_idx, const int *__restrict__ S_local,
-                   const int *__restrict__ hdr, AceArgs<T> a, const T *__restrict__ dEdA,
+                   const int *__restrict__ hdr, AceArgs<T> a, int wpb, const T *__restrict__ dEdA,
                    const double *__restrict__ weights, T *__restrict__ g)
 {
-    int s = blockIdx.x;
-    if (s >= hdr[H_NS])
-        return;
-    extern __shared__ char smem_raw[];
-    T *dAs = reinterpret_cast<T *>(smem_raw);
-    int lane = threadIdx.x;
-    int i = S_idx[s];
-    T w = weights ? T(weights[i]) : T(1);
-    for (int e = lane; e < a.KA; e += 64)
-        dAs[e] = dEdA[(size_t)s * a.KA + e] * w;
-    __syncthreads();
+    const int nS = hdr[H_NS];
+    const int w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int s = blockIdx.x * wpb + w;
+    if (s >= nS)
+        return;  // no barrier in this kernel
+    extern __shared__ __align__(16) char smem_raw[];
+    T *dAs = reinterpret_cast<T *>(smem_raw) + (size_t)w * a.KAt;
+    const int i = S_idx[s];
+    T wgt = weights ? T(weights[i]) : T(1);
+    for (int e = lane; e < a.KAt; e += 64)
+        dAs[e] = dEdA[(size_t)s * a.KAt + e] * wgt;
+    // the wave reads back only its own slice: order the LDS writes before
+    // the reads of other lanes of the same wave
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     int c = cnt[i];
     const int *row = nbr + (size_t)i * cap;
     T *gs = g + (size_t)s * cap * 3;
@@ -294,19 +438,21 @@ __global__ void __launch_bounds__(64)
             double r2 = norm2_d(d);
             if (r2 < a.rc2) {
                 double rd = sqrt(r2);
+                double ird = 1.0 / rd;
                 T r = T(rd);
-                T ux = T(d[0] / rd), uy = T(d[1] / rd), uz = T(d[2] / rd);
+                T ux = T(d[0] * ird), uy = T(d[1] * ird), uz = T(d[2] * ird);
                 T R[kMaxNrad], dR[kMaxNrad];
                 radial<T>(a.nrad, r, a.rc, R, dR);
-                const T *col = dAs + sp_clamp(species[j], a.ns) * a.nrad * a.L2;
+                const T *col = dAs + sp_clamp(species[j], a.ns) * a.nrad;
                 T rad = T(0), vx = T(0), vy = T(0), vz = T(0);
-                const int L2 = a.L2, nrad = a.nrad;
+                const int nchp = a.nchp, nrad = a.nrad;
                 ylm_stream<T>(a.lmax, ux, uy, uz, a.K, [&](int lm, T Y, T yx, T yy, T yz) {
                     T sR = T(0), sD = T(0);
+                    const T *cl = col + lm * nchp;
 #pragma unroll
                     for (int k = 0; k < kMaxNrad; ++k)
                         if (k < nrad) {
-                            T v = col[k * L2 + lm];
+                            T v = cl[k];
                             sR += v * R[k];
                             sD += v * dR[k];
                         }
@@ -317,7 +463,7 @@ __global__ void __launch_bounds__(64)
                 });
                 // grad of Y(d/|d|) w.r.t. d is (I - u u^T) grad_u Y / r
                 T ud = ux * vx + uy * vy + uz * vz;
-                T ir = T(1) / r;
+                T ir = T(ird);
                 gx = rad * ux + (vx - ux * ud) * ir;
                 gy = rad * uy + (vy - uy * ud) * ir;
                 gz = rad * uz + (vz - uz * ud) * ir;
@@ -339,7 +485,8 @@ static AceArgs<T> make_args(const Ctx &c)
     a.lmax = m.lmax;
     a.order = m.order;
     a.nchan = m.nchan;
-    a.KA = m.KA;
+    a.nchp = m.nchp;
+    a.KAt = m.KAt;
     a.L2 = m.L2;
     a.L1 = m.lmax + 1;
     a.rc = T(m.rc_exp);
@@ -353,7 +500,7 @@ static AceArgs<T> make_args(const Ctx &c)
     a.gval = reinterpret_cast<const T *>(base + m.gval);
     a.pb = reinterpret_cast<const PBlock *>(base + m.pb);
     a.gm3 = reinterpret_cast<const int *>(base + m.gm3);
-    a.gidx = reinterpret_cast<const int *>(base + m.gidx);
+    a.gofs = reinterpret_cast<const int *>(base + m.gofs);
     a.w_per_species = m.w_per_species;
     return a;
 }
@@ -362,20 +509,72 @@ static AceArgs<T> make_args(const Ctx &c)
 extern void pb_ranges(const Ctx &c, int *lo, int *hi);
 
 template <typename T>
-static void forward_t(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L, const Box &b,
-                      const double *pos, const int32_t *species, double *e_exp)
+static void basis_t(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L, const Box &b,
+                    const double *pos, const int32_t *species)
+{
+    AceArgs<T> a = make_args<T>(c);
+    int n = L.n;
+    int wpb = 4;
+    while (wpb > 1 && (size_t)wpb * 64 * ((a.nrad + a.L2) * sizeof(T) + sizeof(int)) > 48 * 1024)
+        wpb >>= 1;
+    size_t sm = (size_t)wpb * 64 * ((a.nrad + a.L2) * sizeof(T) + sizeof(int)) + 16;
+    k_ace_basis<T><<<(n + wpb - 1) / wpb, 64 * wpb, sm, s>>>(
+        pos, n, b, species, L.cap, at<int>(ws, L.nbr), at<int>(ws, L.cnt), at<int>(ws, L.S_idx),
+        at<int>(ws, L.S_local), at<int>(ws, L.hdr), a, wpb, at<T>(ws, L.A));
+}
+
+// LDS bytes of one order-3 block workgroup of ta atoms.
+static size_t blocks_lds(const Ctx &c, int ta, size_t tsz, int use_mfma)
+{
+    const DevModel &m = c.m;
+    size_t b = (size_t)ta * m.KAt * tsz;
+    b += (size_t)blocks_rows(ta, m.lmax) * blocks_kstride(m.nchan, m.nchp) * tsz;
+    if (use_mfma)
+        b += (size_t)m.nchan * m.nchp * m.nchp * tsz;
+    b += (size_t)c.max_ent_pb * (tsz + sizeof(int)) + (2 * m.lmax + 2) * sizeof(int) + 32;
+    return b;
+}
+
+// Tile of up to 8 atoms within 64 KiB of LDS; MFMA dense stage (weights in
+// LDS) for single-species FP32 models when the tile still holds 2 atoms.
+// FP64 (the verification precision) keeps the VALU dense stage.
+static void blocks_shape(const Ctx &c, size_t tsz, int &ta_out, int &mfma_out)
+{
+    const DevModel &m = c.m;
+    const size_t lim = 64 * 1024;
+    for (int mf = (m.ns == 1 && tsz == 4 ? 1 : 0); mf >= 0; --mf)
+        for (int ta = 8; ta >= (mf ? 2 : 1); ta >>= 1)
+            if (blocks_lds(c, ta, tsz, mf) <= lim) {
+                ta_out = ta;
+                mfma_out = mf;
+                return;
+            }
+    ta_out = 1;
+    mfma_out = 0;
+}
+
+template <typename T>
+static void contract_t(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L,
+                       const int32_t *species, double *e_exp)
 {
     AceArgs<T> a = make_args<T>(c);
     pb_ranges(c, a.pb_lo, a.pb_hi);
-    int n = L.n;
-    const int *hdr = at<int>(ws, L.hdr);
-    size_t sm_basis = (size_t)64 * (a.nrad + a.L2) * sizeof(T) + 64 * sizeof(int);
-    k_ace_basis<T><<<n, 64, sm_basis, s>>>(pos, n, b, species, L.cap, at<int>(ws, L.nbr),
-                                           at<int>(ws, L.cnt), at<int>(ws, L.S_idx),
-                                           at<int>(ws, L.S_local), hdr, a, at<T>(ws, L.A));
-    size_t sm_c = (size_t)(2 * a.KA + a.nchan * a.nchan * (2 * a.lmax + 1)) * sizeof(T);
-    k_ace_contract<T><<<n, 64, sm_c, s>>>(species, at<int>(ws, L.S_idx), hdr, a, at<T>(ws, L.A),
-                                          at<T>(ws, L.dEdA), e_exp);
+    const int *dp_off = reinterpret_cast<const int *>(static_cast<char *>(c.m.base) + c.m.dpoff);
+    T *Dpart = at<T>(ws, L.dpart);
+    if (a.order >= 3 && c.m.n_pb > 0) {
+        int TA, mf;
+        blocks_shape(c, sizeof(T), TA, mf);
+        size_t sm = blocks_lds(c, TA, sizeof(T), mf);
+        long items = (long)((L.n + TA - 1) / TA) * c.m.n_pb;
+        int grid = (int)(items < 4096 ? items : 4096);
+        k_ace_blocks<T><<<grid, 256, sm, s>>>(species, at<int>(ws, L.S_idx), at<int>(ws, L.hdr), a,
+                                              TA, c.m.n_pb, c.max_ent_pb, mf, dp_off,
+                                              c.m.dp_stride, at<T>(ws, L.A), Dpart);
+    }
+    k_ace_finalize<T><<<(L.n + 3) / 4, 256, 0, s>>>(species, at<int>(ws, L.S_idx),
+                                                    at<int>(ws, L.hdr), a, dp_off, c.m.dp_stride,
+                                                    at<T>(ws, L.A), Dpart, at<T>(ws, L.dEdA),
+                                                    e_exp);
 }
 
 template <typename T>
@@ -384,22 +583,34 @@ static void pairgrad_t(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L,
 {
     AceArgs<T> a = make_args<T>(c);
     int n = L.n;
-    size_t sm = (size_t)a.KA * sizeof(T);
-    k_ace_pairgrad<T><<<n, 64, sm, s>>>(pos, n, b, species, L.cap, at<int>(ws, L.nbr),
-                                        at<int>(ws, L.cnt), at<int>(ws, L.S_idx),
-                                        at<int>(ws, L.S_local), at<int>(ws, L.hdr), a,
-                                        at<T>(ws, L.dEdA), weights, at<T>(ws, L.g));
+    const int wpb = 4;
+    size_t sm = (size_t)wpb * a.KAt * sizeof(T) + 16;
+    k_ace_pairgrad<T><<<(n + wpb - 1) / wpb, 64 * wpb, sm, s>>>(
+        pos, n, b, species, L.cap, at<int>(ws, L.nbr), at<int>(ws, L.cnt), at<int>(ws, L.S_idx),
+        at<int>(ws, L.S_local), at<int>(ws, L.hdr), a, wpb, at<T>(ws, L.dEdA), weights,
+        at<T>(ws, L.g));
 }
 
-void launch_ace_forward(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L, const Box &b,
-                        const double *pos, const int32_t *species, double *e_exp)
+void launch_ace_basis(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L, const Box &b,
+                      const double *pos, const int32_t *species)
 {
     if (L.n == 0)
         return;
     if (c.prec == MLMIX_FP64)
-        forward_t<double>(s, c, ws, L, b, pos, species, e_exp);
+        basis_t<double>(s, c, ws, L, b, pos, species);
     else
-        forward_t<float>(s, c, ws, L, b, pos, species, e_exp);
+        basis_t<float>(s, c, ws, L, b, pos, species);
+}
+
+void launch_ace_contract(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L,
+                         const int32_t *species, double *e_exp)
+{
+    if (L.n == 0)
+        return;
+    if (c.prec == MLMIX_FP64)
+        contract_t<double>(s, c, ws, L, species, e_exp);
+    else
+        contract_t<float>(s, c, ws, L, species, e_exp);
 }
 
 void launch_ace_pairgrad(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L, const Box &b,

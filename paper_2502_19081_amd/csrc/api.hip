@@ -14,10 +14,66 @@
 
 using namespace mlmix;
 
+struct PendingEvent {
+    int stage;
+    hipEvent_t a, b;
+};
+
 struct mlmix_ctx {
     Ctx c;
     std::mutex mu;
     std::unordered_map<void *, WsLayout> ws;
+    uint32_t prof_mask = 0;
+    double flops[6] = {0, 0, 0, 0, 0, 0};
+    std::vector<PendingEvent> pending;
+    std::vector<hipEvent_t> pool;
+};
+
+static const char *kStageNames[MLMIX_N_STAGES] = {
+    "neighbours", "regions", "compaction", "ace_basis", "ace_contract",
+    "ace_pairgrad", "uf3", "gather_blend", "integrator", "energy_sums"};
+
+enum { ST_NBR, ST_REG, ST_CMP, ST_BASIS, ST_CONTRACT, ST_PAIR, ST_UF3, ST_GATHER, ST_VV, ST_RED };
+
+static hipEvent_t take_event(mlmix_ctx *ctx)
+{
+    if (!ctx->pool.empty()) {
+        hipEvent_t e = ctx->pool.back();
+        ctx->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess)
+        return nullptr;
+    return e;
+}
+
+// Brackets one stage with events when its bit is set in the profile mask.
+struct StageTimer {
+    mlmix_ctx *ctx;
+    hipStream_t s;
+    int stage;
+    hipEvent_t a = nullptr;
+    StageTimer(mlmix_ctx *c, hipStream_t st, int stg) : ctx(c), s(st), stage(stg)
+    {
+        if (ctx->prof_mask & (1u << stage)) {
+            a = take_event(ctx);
+            if (a)
+                (void)hipEventRecord(a, s);
+        }
+    }
+    ~StageTimer()
+    {
+        if (a) {
+            hipEvent_t b = take_event(ctx);
+            if (b) {
+                (void)hipEventRecord(b, s);
+                ctx->pending.push_back({stage, a, b});
+            } else {
+                ctx->pool.push_back(a);
+            }
+        }
+    }
 };
 
 static thread_local std::string g_err;
@@ -120,14 +176,16 @@ static std::vector<double> gaunt(int lmax, const std::vector<double> &K)
 struct HostTables {
     std::vector<double> K, c0, c1, c2s, W, gval, u2, u3;
     std::vector<PBlock> pb;
-    std::vector<int> gm3, gidx;
+    std::vector<int> gm3, gidx, gofs, dpoff;
     int w_per_species = 0;
+    int dp_stride = 0;
 };
 
 static int build_tables(const mlmix_model_desc &d, HostTables &t)
 {
     const int ns = d.n_species, nr = d.ace_n_rad, lmax = d.ace_lmax;
     const int L1 = lmax + 1, L2 = L1 * L1, nch = ns * nr, K3 = nch * L1;
+    const int nchp = (nch + 3) & ~3;  // W columns padded to a multiple of four
     t.K = ylm_norm(lmax);
     t.c0.assign(d.ace_c0, d.ace_c0 + ns);
     t.c1.assign(d.ace_c1, d.ace_c1 + (size_t)ns * nch);
@@ -165,13 +223,19 @@ static int build_tables(const mlmix_model_desc &d, HostTables &t)
                                              (l3 * l3 + m3)];
                                 if (std::fabs(v) > 1e-12) {
                                     t.gidx.push_back(m1 | (m2 << 8));
+                                    // LDS offsets of A_{., l1 m1} and A_{., l2 m2} in the
+                                    // channel-fastest layout [lm][nchp]
+                                    t.gofs.push_back(((l1 * l1 + m1) * nchp) |
+                                                     (((l2 * l2 + m2) * nchp) << 16));
                                     t.gval.push_back(v);
                                 }
                             }
                     }
                     t.gm3.push_back((int)t.gidx.size());
+                    t.dpoff.push_back(t.dp_stride);
+                    t.dp_stride += nch * (2 * l3 + 1);
                     t.pb.push_back(p);
-                    t.w_per_species += nch * nch * nch;
+                    t.w_per_species += nch * nchp * nchp;
                 }
         // W[z][block][ab][c]: the symmetric coefficient C_{alpha beta gamma} =
         // c3[sorted] / (number of distinct orderings), doubled for l1 < l2 (the
@@ -189,7 +253,7 @@ static int build_tables(const mlmix_model_desc &d, HostTables &t)
                             double v = d.ace_c3[(((size_t)z * K3 + s[0]) * K3 + s[1]) * K3 + s[2]] / mult;
                             if (p.l1 < p.l2)
                                 v *= 2.0;
-                            t.W[(size_t)z * t.w_per_species + p.w_off + ((size_t)a * nch + b) * nch + c] = v;
+                            t.W[(size_t)z * t.w_per_species + p.w_off + ((size_t)a * nchp + b) * nchp + c] = v;
                         }
     }
     // cheap model
@@ -239,6 +303,7 @@ static std::vector<char> pack(const HostTables &t, DevModel &m)
     std::vector<char> blob;
     append<T>(blob, m.ylmK, t.K);
     append<T>(blob, m.c0, t.c0);
+    append<double>(blob, m.c0d, t.c0);
     append<T>(blob, m.c1, t.c1);
     append<T>(blob, m.c2s, t.c2s);
     append<T>(blob, m.W, t.W);
@@ -246,8 +311,10 @@ static std::vector<char> pack(const HostTables &t, DevModel &m)
     append_raw(blob, m.pb, t.pb);
     append_raw(blob, m.gm3, t.gm3);
     append_raw(blob, m.gidx, t.gidx);
+    append_raw(blob, m.gofs, t.gofs);
     append<T>(blob, m.u2, t.u2);
     append<T>(blob, m.u3, t.u3);
+    append_raw(blob, m.dpoff, t.dpoff);
     return blob;
 }
 
@@ -307,7 +374,7 @@ WsLayout make_layout(const Ctx &c, int n, int cap, const Box &b)
     take(L.cell_cursor, (size_t)L.grid.ncell * sizeof(int));
     take(L.cell_start, (size_t)(L.grid.ncell + 1) * sizeof(int));
     take(L.cell_of, nn * sizeof(int));
-    take(L.cell_atoms, nn * sizeof(int));
+    take(L.cell_atoms, nn * sizeof(CellAtom));
     take(L.scan_part, (size_t)nsp * sizeof(int));
     take(L.nbr, nn * cap * sizeof(int));
     take(L.rev, nn * cap * sizeof(int));
@@ -317,11 +384,12 @@ WsLayout make_layout(const Ctx &c, int n, int cap, const Box &b)
     take(L.M_idx, nn * sizeof(int));
     take(L.S_local, nn * sizeof(int));
     take(L.cand, nn);
-    take(L.A, nn * c.m.KA * tsz);
-    take(L.dEdA, nn * c.m.KA * tsz);
+    take(L.A, nn * c.m.KAt * tsz);
+    take(L.dEdA, nn * c.m.KAt * tsz);
     take(L.g, nn * cap * 3 * tsz);
     take(L.h, nn * cap * 3 * tsz);
     take(L.red, kReduceBlocks * 3 * sizeof(double));
+    take(L.dpart, nn * (size_t)(c.m.dp_stride > 0 ? c.m.dp_stride : 1) * tsz);
     L.total = off;
     return L;
 }
@@ -376,8 +444,8 @@ extern "C" int mlmix_create(const mlmix_model_desc *desc, mlmix_ctx **out)
         return fail(MLMIX_E_ARG, "skin must be >= 0");
     int nch = d.n_species * d.ace_n_rad;
     int L2 = (d.ace_lmax + 1) * (d.ace_lmax + 1);
-    if (nch * L2 > 1024)
-        return fail(MLMIX_E_ARG, "atomic basis larger than 1024 entries");
+    if (((nch + 3) & ~3) * L2 > 1024)
+        return fail(MLMIX_E_ARG, "atomic basis larger than 1024 entries (channels padded to 4)");
     if (nch * (2 * d.ace_lmax + 1) > 8 * 64)
         return fail(MLMIX_E_ARG, "order-3 output block larger than 512 entries");
 
@@ -404,6 +472,8 @@ extern "C" int mlmix_create(const mlmix_model_desc *desc, mlmix_ctx **out)
     m.nchan = nch;
     m.L2 = L2;
     m.KA = nch * L2;
+    m.nchp = (nch + 3) & ~3;
+    m.KAt = L2 * m.nchp;
     m.rc_exp = d.ace_rcut;
     m.rc2 = d.uf3_rcut2;
     m.rc3 = d.uf3_rcut3;
@@ -422,6 +492,44 @@ extern "C" int mlmix_create(const mlmix_model_desc *desc, mlmix_ctx **out)
         if (c.m_pb_hi[l3] == 0)
             c.m_pb_lo[l3] = p;
         c.m_pb_hi[l3] = p + 1;
+    }
+    {
+        // Operation counts of the kernels as written (a multiply-add counts
+        // two, a division or square root one).
+        double KA = m.KA, nr = m.nrad, L2d = L2;
+        double con = 4.0 * nch;
+        if (d.ace_order >= 2)
+            con += KA * (2.0 * nch + 4.0);
+        if (d.ace_order >= 3) {
+            double nab = (double)nch * nch;
+            for (const PBlock &p : t.pb) {
+                int nnz = t.gm3[p.gm3_off + 2 * p.l3 + 1] - t.gm3[p.gm3_off];
+                con += 3.0 * nab * nnz + 2.0 * nab * nch * (2 * p.l3 + 1);
+            }
+            for (int l = 0; l <= d.ace_lmax; ++l)
+                if (c.m_pb_hi[l] > c.m_pb_lo[l])
+                    con += 4.0 * nch * (2 * l + 1);
+        }
+        ctx->flops[0] = con;                                  // contraction, per S atom
+        ctx->flops[1] = 16.0 + 6.0 * nr + 8.0 * L2d + 2.0 * nr * L2d;   // atomic basis, per pair
+        ctx->flops[2] = 31.0 + 10.0 * nr + L2d * (4.0 * nr + 24.0);     // pair adjoint, per pair
+        ctx->flops[3] = 96.0;                                 // cheap 2-body, per pair
+        ctx->flops[4] = 495.0;                                // cheap 3-body, per ordered leg pair
+        ctx->flops[5] = 0.0;
+    }
+    c.max_ent = 0;
+    c.max_gm3 = 0;
+    c.max_ent_pb = 0;
+    m.dp_stride = t.dp_stride;
+    for (const PBlock &p : t.pb)
+        c.max_ent_pb = std::max(c.max_ent_pb, t.gm3[p.gm3_off + 2 * p.l3 + 1] - t.gm3[p.gm3_off]);
+    for (int l = 0; l <= d.ace_lmax; ++l) {
+        if (c.m_pb_hi[l] <= c.m_pb_lo[l])
+            continue;
+        const PBlock &f = t.pb[c.m_pb_lo[l]], &la = t.pb[c.m_pb_hi[l] - 1];
+        int g_lo = f.gm3_off, g_hi = la.gm3_off + 2 * l + 2;
+        c.max_gm3 = std::max(c.max_gm3, g_hi - g_lo);
+        c.max_ent = std::max(c.max_ent, t.gm3[g_hi - 1] - t.gm3[g_lo]);
     }
     std::vector<char> blob = c.prec == MLMIX_FP64 ? pack<double>(t, m) : pack<float>(t, m);
     m.bytes = blob.size();
@@ -444,6 +552,12 @@ extern "C" int mlmix_destroy(mlmix_ctx *ctx)
 {
     if (!ctx)
         return MLMIX_OK;
+    for (PendingEvent &p : ctx->pending) {
+        (void)hipEventDestroy(p.a);
+        (void)hipEventDestroy(p.b);
+    }
+    for (hipEvent_t e : ctx->pool)
+        (void)hipEventDestroy(e);
     if (ctx->c.m.base)
         (void)hipFree(ctx->c.m.base);
     delete ctx;
@@ -519,26 +633,50 @@ static int compute_impl(mlmix_ctx *ctx, hipStream_t s, void *ws, const WsLayout 
     const Ctx &c = ctx->c;
     int m = (int)(mode & 0xff);
     bool energy_only = (mode & MLMIX_ENERGY_ONLY) != 0;
-    launch_prepare(s, ws, L, (mode & MLMIX_FORCE_REBUILD) ? 1 : 0, pos, c.d.skin);
-    launch_neighbors(s, ws, L, b, c.r_list, pos);
-    launch_regions(s, ws, L, b, m, pos, species, c.m.ns, regions, n_regions, r_buffer, lambda, flags);
-    launch_compact(s, ws, L, flags, n_expensive);
+    {
+        StageTimer t(ctx, s, ST_NBR);
+        launch_prepare(s, ws, L, (mode & MLMIX_FORCE_REBUILD) ? 1 : 0, pos, c.d.skin);
+        launch_neighbors(s, ws, L, b, c.r_list, pos);
+    }
+    {
+        StageTimer t(ctx, s, ST_REG);
+        launch_regions(s, ws, L, b, m, pos, species, c.m.ns, regions, n_regions, r_buffer, lambda,
+                       flags);
+    }
+    {
+        StageTimer t(ctx, s, ST_CMP);
+        launch_compact(s, ws, L, flags, n_expensive);
+    }
     if (m != MLMIX_MODE_ALL_CHEAP) {
-        launch_ace_forward(s, c, ws, L, b, pos, species, e_exp);
-        if (!energy_only)
+        {
+            StageTimer t(ctx, s, ST_BASIS);
+            launch_ace_basis(s, c, ws, L, b, pos, species);
+        }
+        {
+            StageTimer t(ctx, s, ST_CONTRACT);
+            launch_ace_contract(s, c, ws, L, species, e_exp);
+        }
+        if (!energy_only) {
+            StageTimer t(ctx, s, ST_PAIR);
             launch_ace_pairgrad(s, c, ws, L, b, pos, species, nullptr);
+        }
     }
     if (energy_only) {
         launch_gather_blend(s, c, ws, L, 0, 0, lambda, nullptr, e_exp, nullptr, nullptr, 1.0);
         HIP_OK(hipGetLastError());
         return MLMIX_OK;
     }
-    if (m != MLMIX_MODE_ALL_EXPENSIVE)
+    if (m != MLMIX_MODE_ALL_EXPENSIVE) {
+        StageTimer t(ctx, s, ST_UF3);
         launch_uf3(s, c, ws, L, b, pos, species, e_cheap);
-    else
+    } else {
         launch_fill_f64(s, e_cheap, 0.0, (size_t)L.n);
-    launch_gather_blend(s, c, ws, L, m != MLMIX_MODE_ALL_CHEAP, m != MLMIX_MODE_ALL_EXPENSIVE,
-                        lambda, forces, e_exp, f_exp, f_cheap, 1.0);
+    }
+    {
+        StageTimer t(ctx, s, ST_GATHER);
+        launch_gather_blend(s, c, ws, L, m != MLMIX_MODE_ALL_CHEAP, m != MLMIX_MODE_ALL_EXPENSIVE,
+                            lambda, forces, e_exp, f_exp, f_cheap, 1.0);
+    }
     HIP_OK(hipGetLastError());
     return MLMIX_OK;
 }
@@ -651,14 +789,22 @@ extern "C" int mlmix_vv_step(mlmix_ctx *ctx, void *stream, void *ws, int32_t n_a
     if (rc)
         return rc;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    launch_vv_kick_drift(s, ws, L, b, pos, vel, mass, forces, dt, 1);
+    {
+        StageTimer t(ctx, s, ST_VV);
+        launch_vv_kick_drift(s, ws, L, b, pos, vel, mass, forces, dt, 1);
+    }
     rc = compute_impl(ctx, s, ws, L, b, pos, species, regions, n_regions, r_buffer, mode, forces,
                       e_exp, e_cheap, lambda, flags, n_expensive, nullptr, nullptr);
     if (rc)
         return rc;
-    launch_vv_kick_drift(s, ws, L, b, pos, vel, mass, forces, dt, 0);
-    if (energies)
+    {
+        StageTimer t(ctx, s, ST_VV);
+        launch_vv_kick_drift(s, ws, L, b, pos, vel, mass, forces, dt, 0);
+    }
+    if (energies) {
+        StageTimer t(ctx, s, ST_RED);
         launch_reduce(s, ws, L, e_exp, e_cheap, vel, mass, energies);
+    }
     HIP_OK(hipGetLastError());
     return MLMIX_OK;
 }
@@ -736,5 +882,54 @@ extern "C" int mlmix_get_index_sets(mlmix_ctx *ctx, void *stream, void *ws, int3
     launch_copy_i32(s, S_out, at<int>(ws, L.S_idx), (size_t)L.n);
     launch_copy_i32(s, M_out, at<int>(ws, L.M_idx), (size_t)L.n);
     HIP_OK(hipGetLastError());
+    return MLMIX_OK;
+}
+
+extern "C" int mlmix_profile_enable(mlmix_ctx *ctx, uint32_t stage_mask)
+{
+    if (!ctx)
+        return fail(MLMIX_E_ARG, "NULL context");
+    ctx->prof_mask = stage_mask & ((1u << MLMIX_N_STAGES) - 1u);
+    return MLMIX_OK;
+}
+
+extern "C" int mlmix_profile_read(mlmix_ctx *ctx, double *ms, int64_t *count)
+{
+    if (!ctx || !ms || !count)
+        return fail(MLMIX_E_ARG, "NULL argument");
+    for (int i = 0; i < MLMIX_N_STAGES; ++i) {
+        ms[i] = 0.0;
+        count[i] = 0;
+    }
+    int rc = MLMIX_OK;
+    for (PendingEvent &p : ctx->pending) {
+        float t = 0.0f;
+        hipError_t e = hipEventSynchronize(p.b);
+        if (e == hipSuccess)
+            e = hipEventElapsedTime(&t, p.a, p.b);
+        if (e != hipSuccess)
+            rc = fail(MLMIX_E_HIP, std::string("profile events: ") + hipGetErrorString(e));
+        ms[p.stage] += t;
+        count[p.stage] += 1;
+        ctx->pool.push_back(p.a);
+        ctx->pool.push_back(p.b);
+    }
+    ctx->pending.clear();
+    return rc;
+}
+
+extern "C" const char *mlmix_profile_stage_name(int32_t stage)
+{
+    if (stage < 0 || stage >= MLMIX_N_STAGES)
+        return "";
+    return kStageNames[stage];
+}
+
+extern "C" int mlmix_model_flops(const mlmix_ctx *ctx, double *out)
+{
+    if (!ctx || !out)
+        return fail(MLMIX_E_ARG, "NULL argument");
+    for (int i = 0; i < 6; ++i)
+        out[i] = ctx->flops[i];
     return MLMIX_OK;
 }

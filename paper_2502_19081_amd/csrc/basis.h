@@ -45,6 +45,30 @@ __host__ __device__ inline void radial(int nrad, T r, T rc, T *R, T *dR)
     }
 }
 
+// 1/k for the small integers of the Legendre recurrence (k <= 2 lmax + 1).
+template <typename T>
+__host__ __device__ inline T inv_small(int k)
+{
+    switch (k) {
+    case 1:
+        return T(1.0);
+    case 2:
+        return T(0.5);
+    case 3:
+        return T(1.0 / 3.0);
+    case 4:
+        return T(0.25);
+    case 5:
+        return T(0.2);
+    case 6:
+        return T(1.0 / 6.0);
+    case 7:
+        return T(1.0 / 7.0);
+    default:
+        return T(1) / T(k);
+    }
+}
+
 // Real orthonormal spherical harmonics of the unit vector (x, y, z) and their
 // gradients with respect to (x, y, z) of the polynomial extension, streamed
 // in (m, l) order: Y_lm = K_lm Q_l^|m|(z) {C_m, 1, S_|m|}, Q_l^m = d^m P_l/dz^m
@@ -68,9 +92,12 @@ __host__ __device__ inline void ylm_stream(int lmax, T x, T y, T z, const T *__r
         T dfm1 = dfm * T(2 * m + 1);
         T qa1 = T(0), qa2 = T(0), qb1 = T(0), qb2 = T(0);
         for (int l = m; l <= lmax; ++l) {
-            T qa = (l == m) ? dfm : (T(2 * l - 1) * z * qa1 - T(l + m - 1) * qa2) / T(l - m);
+            T qa = (l == m) ? dfm
+                            : (T(2 * l - 1) * z * qa1 - T(l + m - 1) * qa2) * inv_small<T>(l - m);
             T qb = (l == m) ? T(0)
-                            : (l == m + 1 ? dfm1 : (T(2 * l - 1) * z * qb1 - T(l + m) * qb2) / T(l - m - 1));
+                            : (l == m + 1 ? dfm1
+                                          : (T(2 * l - 1) * z * qb1 - T(l + m) * qb2) *
+                                                inv_small<T>(l - m - 1));
             int base = l * l + l;
             if (m == 0) {
                 T k0 = K[base];

@@ -17,14 +17,14 @@ __device__ __forceinline__ void pair_disp(const double *__restrict__ pos, int n,
                                           const Box &b, double d[3])
 {
 #pragma clang fp contract(off)
+    // issue the six loads before any folding so that they overlap
+    const double xj[3] = {pos[j], pos[n + j], pos[2 * n + j]};
+    const double xi[3] = {pos[i], pos[n + i], pos[2 * n + i]};
     for (int k = 0; k < 3; ++k) {
-        double dx = pos[k * n + j] - pos[k * n + i];
+        double dx = xj[k] - xi[k];
         if (b.per[k]) {
             double h = 0.5 * b.L[k];
-            if (dx > h)
-                dx = dx - b.L[k];
-            else if (dx < -h)
-                dx = dx + b.L[k];
+            dx = dx > h ? dx - b.L[k] : (dx < -h ? dx + b.L[k] : dx);
         }
         d[k] = dx;
     }
@@ -227,10 +227,11 @@ __global__ void __launch_bounds__(256) k_cell_count(const double *__restrict__ p
     atomicAdd(&count[cell], 1);
 }
 
-__global__ void __launch_bounds__(256) k_cell_fill(int n, const int *__restrict__ cell_of,
+__global__ void __launch_bounds__(256) k_cell_fill(const double *__restrict__ pos, int n,
+                                                   const int *__restrict__ cell_of,
                                                    const int *__restrict__ start,
                                                    int *__restrict__ cursor,
-                                                   int *__restrict__ atoms, const int *hdr)
+                                                   CellAtom *__restrict__ atoms, const int *hdr)
 {
     if (hdr[H_REBUILD] == 0)
         return;
@@ -239,71 +240,127 @@ __global__ void __launch_bounds__(256) k_cell_fill(int n, const int *__restrict_
         return;
     int c = cell_of[i];
     int slot = start[c] + atomicAdd(&cursor[c], 1);
-    atoms[slot] = i;
+    CellAtom r;
+    r.x = pos[i];
+    r.y = pos[n + i];
+    r.z = pos[2 * n + i];
+    r.j = i;
+    r.pad = 0;
+    atoms[slot] = r;
 }
 
-// One wavefront per atom: visit the (up to) 5x5x5 stencil of half-radius
-// cells, keep partners closer than the list radius, sort the row ascending
-// (bitonic sort in LDS) and store it.
-__global__ void __launch_bounds__(64) k_neighbors(const double *__restrict__ pos, int n, Box b,
-                                                  Grid g, const int *__restrict__ start,
-                                                  const int *__restrict__ atoms, double rl2,
-                                                  int cap, int P, int *__restrict__ nbr,
-                                                  int *__restrict__ cnt,
-                                                  double *__restrict__ ref, int *hdr)
+// One wavefront per atom, four atoms per 256-thread block. The (up to)
+// 5x5x5 stencil of half-radius cells is flattened: lanes first look up the
+// stencil cells' ranges and prefix-sum their sizes, then sweep the candidate
+// list 64 at a time (one 32-byte cell-ordered record per candidate), keep
+// partners closer than the list radius by ballot compaction, and finally
+// sort the row ascending (bitonic sort in the wave's LDS slice). Barriers
+// are placed where all four waves pass them.
+__global__ void __launch_bounds__(256) k_neighbors(const double *__restrict__ pos, int n, Box b,
+                                                   Grid g, const int *__restrict__ start,
+                                                   const CellAtom *__restrict__ atoms, double rl2,
+                                                   int cap, int P, int *__restrict__ nbr,
+                                                   int *__restrict__ cnt,
+                                                   double *__restrict__ ref, int *hdr)
 {
 #pragma clang fp contract(off)
     if (hdr[H_REBUILD] == 0)
         return;
-    __shared__ int row[kMaxCap];
-    __shared__ int count;
-    int i = blockIdx.x;
-    int lane = threadIdx.x;
-    if (lane == 0)
-        count = 0;
+    __shared__ int rows[4][kMaxCap];
+    __shared__ int cbeg[4][128];
+    __shared__ int coff[4][129];
+    const int w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int i = blockIdx.x * 4 + w;
+    const bool valid = i < n;
+    int *row = rows[w];
     for (int t = lane; t < P; t += 64)
         row[t] = 0x7fffffff;
-    __syncthreads();
-    int ci[3], nst[3];
-    for (int k = 0; k < 3; ++k) {
-        ci[k] = cell_coord(pos[k * n + i], g, k);
+    int nst[3];
+    for (int k = 0; k < 3; ++k)
         nst[k] = (b.per[k] && g.nc[k] < 5) ? g.nc[k] : 5;
-    }
-    int total = nst[0] * nst[1] * nst[2];
-    for (int t = lane; t < total; t += 64) {
-        int o[3] = {t % nst[0] - 2, (t / nst[0]) % nst[1] - 2, t / (nst[0] * nst[1]) - 2};
-        int q[3];
-        bool ok = true;
+    const int total = nst[0] * nst[1] * nst[2];  // <= 125
+    double xi[3] = {0.0, 0.0, 0.0};
+    int ci[3] = {0, 0, 0};
+    if (valid)
         for (int k = 0; k < 3; ++k) {
-            int v = ci[k] + o[k];
-            if (b.per[k]) {
-                v %= g.nc[k];
-                if (v < 0)
-                    v += g.nc[k];
-            } else if (v < 0 || v >= g.nc[k]) {
-                ok = false;
-            }
-            q[k] = v;
+            xi[k] = pos[k * n + i];
+            ci[k] = cell_coord(xi[k], g, k);
         }
-        if (!ok)
-            continue;
-        int cell = (q[2] * g.nc[1] + q[1]) * g.nc[0] + q[0];
-        int e = start[cell + 1];
-        for (int s = start[cell]; s < e; ++s) {
-            int j = atoms[s];
-            if (j == i)
-                continue;
-            double d[3];
-            pair_disp(pos, n, i, j, b, d);
-            if (norm2(d) < rl2) {
-                int slot = atomicAdd(&count, 1);
-                if (slot < P)
-                    row[slot] = j;
+    // stencil cells t = lane and t = lane + 64: first slot and size
+    int sz[2], bg[2];
+    for (int h = 0; h < 2; ++h) {
+        int t = lane + 64 * h;
+        sz[h] = 0;
+        bg[h] = 0;
+        if (valid && t < total) {
+            int o[3] = {t % nst[0] - 2, (t / nst[0]) % nst[1] - 2, t / (nst[0] * nst[1]) - 2};
+            int q[3];
+            bool ok = true;
+            for (int k = 0; k < 3; ++k) {
+                int v = ci[k] + o[k];
+                if (b.per[k]) {
+                    v %= g.nc[k];
+                    if (v < 0)
+                        v += g.nc[k];
+                } else if (v < 0 || v >= g.nc[k]) {
+                    ok = false;
+                }
+                q[k] = v;
+            }
+            if (ok) {
+                int cell = (q[2] * g.nc[1] + q[1]) * g.nc[0] + q[0];
+                bg[h] = start[cell];
+                sz[h] = start[cell + 1] - bg[h];
             }
         }
+    }
+    int inc0 = wave_incl_scan(sz[0]);
+    int tot0 = __shfl(inc0, 63);
+    int inc1 = wave_incl_scan(sz[1]);
+    int ncand = tot0 + __shfl(inc1, 63);
+    cbeg[w][lane] = bg[0];
+    cbeg[w][lane + 64] = bg[1];
+    coff[w][lane] = inc0 - sz[0];
+    coff[w][lane + 64] = tot0 + inc1 - sz[1];
+    if (lane == 0)
+        coff[w][128] = ncand;
+    __syncthreads();
+    int c = 0;
+    for (int r0 = 0; r0 < ncand; r0 += 64) {
+        int q = r0 + lane;
+        bool hit = false;
+        int j = 0;
+        if (q < ncand) {
+            // stencil cell u with coff[u] <= q < coff[u+1] (empty cells repeat offsets)
+            int lo = 0, hi = 127;
+            while (lo < hi) {
+                int mid = (lo + hi + 1) >> 1;
+                if (coff[w][mid] <= q)
+                    lo = mid;
+                else
+                    hi = mid - 1;
+            }
+            CellAtom rec = atoms[cbeg[w][lo] + (q - coff[w][lo])];
+            j = rec.j;
+            double d[3] = {rec.x - xi[0], rec.y - xi[1], rec.z - xi[2]};
+            for (int k = 0; k < 3; ++k) {
+                if (b.per[k]) {
+                    double h = 0.5 * b.L[k];
+                    double dx = d[k];
+                    dx = dx > h ? dx - b.L[k] : (dx < -h ? dx + b.L[k] : dx);
+                    d[k] = dx;
+                }
+            }
+            hit = (j != i) && norm2(d) < rl2;
+        }
+        unsigned long long m = __ballot(hit);
+        int p = c + __popcll(m & ((1ull << lane) - 1ull));
+        if (hit && p < P)
+            row[p] = j;
+        c += __popcll(m);
     }
     __syncthreads();
-    int c = count;
     for (int k = 2; k <= P; k <<= 1) {
         for (int jj = k >> 1; jj > 0; jj >>= 1) {
             for (int t = lane; t < P; t += 64) {
@@ -320,15 +377,19 @@ __global__ void __launch_bounds__(64) k_neighbors(const double *__restrict__ pos
             __syncthreads();
         }
     }
+    if (!valid)
+        return;
     int keep = c < cap ? c : cap;
-    for (int s = lane; s < cap; s += 64)
-        nbr[(size_t)i * cap + s] = s < keep ? row[s] : -1;
+    for (int s2 = lane; s2 < cap; s2 += 64)
+        nbr[(size_t)i * cap + s2] = s2 < keep ? row[s2] : -1;
     if (lane == 0) {
         cnt[i] = keep;
+        // same-address device atomics serialise across the whole grid: only
+        // an overflowing row records its length
         if (c > cap) {
             atomicOr(&hdr[H_STATUS], MLMIX_STATUS_NEIGH_OVERFLOW);
+            atomicMax(&hdr[H_REQCAP], c);
         }
-        atomicMax(&hdr[H_REQCAP], c);
     }
     if (lane < 3)
         ref[lane * n + i] = pos[lane * n + i];
@@ -398,9 +459,9 @@ void launch_neighbors(hipStream_t s, void *ws, const WsLayout &L, const Box &b, 
     k_cell_zero<<<(g.ncell + 255) / 256, 256, 0, s>>>(count, cursor, g.ncell, hdr + H_REBUILD);
     k_cell_count<<<(n + 255) / 256, 256, 0, s>>>(pos, n, b, g, at<int>(ws, L.cell_of), count, hdr);
     device_excl_scan(s, count, g.ncell, at<int>(ws, L.scan_part), start, hdr + H_REBUILD);
-    k_cell_fill<<<(n + 255) / 256, 256, 0, s>>>(n, at<int>(ws, L.cell_of), start, cursor,
-                                                at<int>(ws, L.cell_atoms), hdr);
-    k_neighbors<<<n, 64, 0, s>>>(pos, n, b, g, start, at<int>(ws, L.cell_atoms), r_list * r_list,
+    k_cell_fill<<<(n + 255) / 256, 256, 0, s>>>(pos, n, at<int>(ws, L.cell_of), start, cursor,
+                                                at<CellAtom>(ws, L.cell_atoms), hdr);
+    k_neighbors<<<(n + 3) / 4, 256, 0, s>>>(pos, n, b, g, start, at<CellAtom>(ws, L.cell_atoms), r_list * r_list,
                                  L.cap, L.P, at<int>(ws, L.nbr), at<int>(ws, L.cnt),
                                  at<double>(ws, L.ref_pos), hdr);
     size_t tot = (size_t)n * L.cap;
@@ -497,28 +558,33 @@ __global__ void __launch_bounds__(256) k_lambda(const double *__restrict__ pos, 
     cand[i] = (best == 0.0 && near) ? 1 : 0;
 }
 
+// One wavefront per atom (lanes over row slots): an atom with lambda == 0
+// near a region joins the buffer when any neighbour with lambda > 0 lies
+// strictly inside r_buffer.
 __global__ void __launch_bounds__(256) k_buffer(const double *__restrict__ pos, int n, Box b,
                                                 int cap, const int *__restrict__ nbr,
                                                 const int *__restrict__ cnt, double rb2,
                                                 uint8_t *__restrict__ flags,
                                                 const uint8_t *__restrict__ cand)
 {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     if (i >= n || !cand[i])
         return;
-    int c = cnt[i];
+    const int c = cnt[i];
     const int *row = nbr + (size_t)i * cap;
-    for (int s = 0; s < c; ++s) {
+    bool hit = false;
+    for (int s = lane; s < c; s += 64) {
         int j = row[s];
-        if (!(flags[j] & 1))
-            continue;
-        double d[3];
-        pair_disp(pos, n, i, j, b, d);
-        if (norm2(d) < rb2) {
-            flags[i] = (uint8_t)(flags[i] | 4);
-            return;
+        if (flags[j] & 1) {
+            double d[3];
+            pair_disp(pos, n, i, j, b, d);
+            if (norm2(d) < rb2)
+                hit = true;
         }
     }
+    if (__ballot(hit) != 0ull && lane == 0)
+        flags[i] = (uint8_t)(flags[i] | 4);
 }
 
 void launch_regions(hipStream_t s, void *ws, const WsLayout &L, const Box &b, int mode,
@@ -532,7 +598,7 @@ void launch_regions(hipStream_t s, void *ws, const WsLayout &L, const Box &b, in
     k_lambda<<<(n + 255) / 256, 256, 0, s>>>(pos, n, b, species, ns, at<int>(ws, L.hdr), mode, reg,
                                             nreg, r_buffer, lambda, flags, cand);
     if (mode == MLMIX_MODE_MIXED)
-        k_buffer<<<(n + 255) / 256, 256, 0, s>>>(pos, n, b, L.cap, at<int>(ws, L.nbr),
+        k_buffer<<<(n + 3) / 4, 256, 0, s>>>(pos, n, b, L.cap, at<int>(ws, L.nbr),
                                                 at<int>(ws, L.cnt), r_buffer * r_buffer, flags,
                                                 cand);
 }

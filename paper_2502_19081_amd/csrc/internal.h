@@ -30,6 +30,13 @@ enum HeaderWord {
     H_COUNT = 64
 };
 
+// Cell-ordered copy of an atom written during binning: the neighbour search
+// reads one 32-byte record per candidate.
+struct CellAtom {
+    double x, y, z;
+    int j, pad;
+};
+
 struct Box {
     double L[3];
     int per[3];
@@ -48,20 +55,22 @@ struct WsLayout {
     int n_scan_blk;  // blocks of the atom-sized scans
     size_t hdr, cell_count, cell_cursor, cell_start, cell_of, cell_atoms, scan_part;
     size_t nbr, cnt, rev, ref_pos, S_idx, M_idx, S_local, cand;
-    size_t A, dEdA, g, h, red;
+    size_t A, dEdA, g, h, red, dpart;
     size_t total;
 };
 
 // Model tables on the device, in the arithmetic type of the context.
 struct DevModel {
     int ns, nrad, lmax, order, nchan, KA, L2;
+    int nchp, KAt;  // channels padded to a multiple of 4; per-atom entries L2 * nchp
     double rc_exp, rc2, rc3;
     int nb2, nb3, nk2, nk3;
     int n_pb;  // (l1 <= l2, l3) blocks of the order-3 contraction
     void *base;
     size_t bytes;
     // offsets (bytes) into base
-    size_t ylmK, c0, c1, c2s, W, pb, gm3, gidx, gval, u2, u3;
+    size_t ylmK, c0, c0d, c1, c2s, W, pb, gm3, gidx, gofs, gval, u2, u3, dpoff;
+    int dp_stride;  // partial-D entries per S atom (sum over blocks of nchan*(2 l3 + 1))
     int w_per_species;  // entries of W per centre species
     int gm3_total, g_total;
 };
@@ -80,6 +89,8 @@ struct Ctx {
     double r_list;
     DevModel m;
     int m_pb_lo[kMaxLmax + 1], m_pb_hi[kMaxLmax + 1];  // order-3 blocks per l3
+    int max_ent, max_gm3;  // Gaunt entries / m3 offsets of the largest l3 group
+    int max_ent_pb;        // Gaunt entries of the largest single block
     int device;
 };
 
@@ -104,8 +115,10 @@ void launch_regions(hipStream_t s, void *ws, const WsLayout &L, const Box &b, in
 void launch_compact(hipStream_t s, void *ws, const WsLayout &L, uint8_t *flags, int32_t *n_expensive);
 
 // ---- ace.hip ----
-void launch_ace_forward(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L, const Box &b,
-                        const double *pos, const int32_t *species, double *e_exp);
+void launch_ace_basis(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L, const Box &b,
+                      const double *pos, const int32_t *species);
+void launch_ace_contract(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L,
+                         const int32_t *species, double *e_exp);
 void launch_ace_pairgrad(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L, const Box &b,
                          const double *pos, const int32_t *species, const double *weights);
 

@@ -73,14 +73,13 @@ __device__ __forceinline__ double pair_disp_u(const double *__restrict__ pos, in
                                               const Box &b, double d[3])
 {
 #pragma clang fp contract(off)
+    const double xj[3] = {pos[j], pos[n + j], pos[2 * n + j]};
+    const double xi[3] = {pos[i], pos[n + i], pos[2 * n + i]};
     for (int k = 0; k < 3; ++k) {
-        double dx = pos[k * n + j] - pos[k * n + i];
+        double dx = xj[k] - xi[k];
         if (b.per[k]) {
             double hh = 0.5 * b.L[k];
-            if (dx > hh)
-                dx = dx - b.L[k];
-            else if (dx < -hh)
-                dx = dx + b.L[k];
+            dx = dx > hh ? dx - b.L[k] : (dx < -hh ? dx + b.L[k] : dx);
         }
         d[k] = dx;
     }
@@ -99,38 +98,69 @@ __device__ __forceinline__ T wave_sum_t(T v)
     return v;
 }
 
+// Per-wave LDS slice of the cheap kernel, in elements of T (ints stored in
+// T-sized slots are avoided: the integer arrays follow the T arrays).
+struct Uf3Slice {
+    int hs, d3, r3, B3, dB3, c3s, nT;  // offsets of the T arrays and their total
+};
+
+__host__ __device__ inline Uf3Slice uf3_slice(int cap, int nb3c)
+{
+    Uf3Slice l;
+    l.hs = 0;
+    l.d3 = l.hs + 3 * cap;
+    l.r3 = l.d3 + 3 * kMaxTriplet;
+    l.B3 = l.r3 + kMaxTriplet;
+    l.dB3 = l.B3 + 4 * kMaxTriplet;
+    l.c3s = l.dB3 + 4 * kMaxTriplet;
+    l.nT = l.c3s + nb3c;
+    return l;
+}
+
+// Four centre atoms per 256-thread block, one wavefront each. The loops run
+// to the block's maximum row length so that the four waves meet at every
+// barrier; each wave works in its own LDS slice.
 template <typename T>
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(256)
     k_uf3(const double *__restrict__ pos, int n, Box b, const int32_t *__restrict__ species,
           int cap, const int *__restrict__ nbr, const int *__restrict__ cnt, Uf3Args<T> a,
           T *__restrict__ hout, double *__restrict__ e_cheap, int *hdr)
 {
-    extern __shared__ char smem_raw[];
-    T *hs = reinterpret_cast<T *>(smem_raw);          // [cap][3]
-    T *d3 = hs + 3 * cap;                             // [64][3]
-    T *r3 = d3 + 3 * kMaxTriplet;                     // [64]
-    T *B3 = r3 + kMaxTriplet;                         // [64][4]
-    T *dB3 = B3 + 4 * kMaxTriplet;                    // [64][4]
-    T *c3s = dB3 + 4 * kMaxTriplet;                   // [nb3^3]
-    int *f3 = reinterpret_cast<int *>(c3s + (a.nb3 > 0 ? a.nb3 * a.nb3 * a.nb3 : 0));  // [64]
-    int *sl3 = f3 + kMaxTriplet;                      // [64]
-    __shared__ int count3;
-    int i = blockIdx.x;
-    int lane = threadIdx.x;
-    int zi = sp_clamp(species[i], a.ns);
-    int c = cnt[i];
-    const int *row = nbr + (size_t)i * cap;
-    if (lane == 0)
-        count3 = 0;
-    const int nb3c = a.nb3 * a.nb3 * a.nb3;
+    const int nb3c = a.nb3 > 0 ? a.nb3 * a.nb3 * a.nb3 : 0;
+    const Uf3Slice sl = uf3_slice(cap, nb3c);
+    const int w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int i = blockIdx.x * 4 + w;
+    const bool valid = i < n;
+    extern __shared__ __align__(16) char smem_raw[];
+    T *base = reinterpret_cast<T *>(smem_raw) + (size_t)w * sl.nT;
+    T *hs = base + sl.hs;
+    T *d3 = base + sl.d3;
+    T *r3 = base + sl.r3;
+    T *B3 = base + sl.B3;
+    T *dB3 = base + sl.dB3;
+    T *c3s = base + sl.c3s;
+    int *ibase = reinterpret_cast<int *>(reinterpret_cast<T *>(smem_raw) + 4 * (size_t)sl.nT);
+    int *f3 = ibase + w * 2 * kMaxTriplet;
+    int *sl3 = f3 + kMaxTriplet;
+    __shared__ int count3[4];
+    __shared__ int cmax_s[4];
+    const int zi = valid ? sp_clamp(species[i], a.ns) : 0;
+    const int c = valid ? cnt[i] : 0;
+    const int *row = nbr + (size_t)(valid ? i : 0) * cap;
+    if (lane == 0) {
+        count3[w] = 0;
+        cmax_s[w] = c;
+    }
     for (int e = lane; e < nb3c; e += 64)
         c3s[e] = a.c3[(size_t)zi * nb3c + e];
     for (int e = lane; e < 3 * c; e += 64)
         hs[e] = T(0);
     __syncthreads();
+    const int cmax = max(max(cmax_s[0], cmax_s[1]), max(cmax_s[2], cmax_s[3]));
     T Ep = T(0);
-    for (int base = 0; base < c; base += 64) {
-        int slot = base + lane;
+    for (int base0 = 0; base0 < cmax; base0 += 64) {
+        int slot = base0 + lane;
         bool in3 = false;
         double d[3] = {0.0, 0.0, 0.0};
         double r2 = 0.0;
@@ -160,7 +190,7 @@ __global__ void __launch_bounds__(64)
         }
         unsigned long long mask = __ballot(in3);
         int before = __popcll(mask & ((1ull << lane) - 1ull));
-        int p = count3 + before;
+        int p = count3[w] + before;
         if (in3 && p < kMaxTriplet) {
             double rd = sqrt(r2);
             d3[p * 3 + 0] = T(d[0]);
@@ -180,68 +210,86 @@ __global__ void __launch_bounds__(64)
         }
         __syncthreads();
         if (lane == 0)
-            count3 += __popcll(mask);
+            count3[w] += __popcll(mask);
         __syncthreads();
     }
-    int n3 = count3;
+    int n3 = count3[w];
     if (n3 > kMaxTriplet) {
         if (lane == 0)
             atomicOr(&hdr[H_STATUS], MLMIX_STATUS_TRIPLET_OVERFLOW);
         n3 = kMaxTriplet;
     }
-    if (a.nb3 > 0 && lane < n3) {
-        const int t = lane;
-        T dj0 = d3[t * 3], dj1 = d3[t * 3 + 1], dj2 = d3[t * 3 + 2];
-        T rj = r3[t];
-        int fj = f3[t];
-        T Bj[4], dBj[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            Bj[q] = B3[t * 4 + q];
-            dBj[q] = dB3[t * 4 + q];
-        }
-        T hx = T(0), hy = T(0), hz = T(0);
+    if (a.nb3 > 0) {
+        // lane = leg j (low four bits) + k residue class kc (high two bits):
+        // lane (j, kc) sums the triplets (j, k) with k = kc (mod 4), then the
+        // four partial sums of leg j meet in a fixed shuffle order.
+        const int jl = lane & 15, kc = lane >> 4;
         const int nb = a.nb3;
-        for (int k = 0; k < n3; ++k) {
-            if (k == t)
-                continue;
-            T e0 = d3[k * 3] - dj0, e1 = d3[k * 3 + 1] - dj1, e2 = d3[k * 3 + 2] - dj2;
-            T rjk = sqrt(e0 * e0 + e1 * e1 + e2 * e2);
-            int fs;
-            T Ns[4], dNs[4];
-            bspline4<T>(rjk, a.h3c, a.ih3c, a.nk3, fs, Ns, dNs);
-            int fk = f3[k];
-            T V = T(0), V1 = T(0), V3 = T(0);
-#pragma unroll
-            for (int p = 0; p < 4; ++p) {
+        for (int jb = 0; jb < n3; jb += 16) {
+            const int t = jb + jl;
+            T hx = T(0), hy = T(0), hz = T(0);
+            if (t < n3) {
+                T dj0 = d3[t * 3], dj1 = d3[t * 3 + 1], dj2 = d3[t * 3 + 2];
+                T rj = r3[t];
+                int fj = f3[t];
+                T Bj[4], dBj[4];
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    const T *cr = c3s + ((fj + p) * nb + (fk + q)) * nb + fs;
-                    T bk = B3[k * 4 + q];
-                    T s0 = T(0), s1 = T(0);
+                    Bj[q] = B3[t * 4 + q];
+                    dBj[q] = dB3[t * 4 + q];
+                }
+                for (int k = kc; k < n3; k += 4) {
+                    if (k == t)
+                        continue;
+                    T e0 = d3[k * 3] - dj0, e1 = d3[k * 3 + 1] - dj1, e2 = d3[k * 3 + 2] - dj2;
+                    T rjk = sqrt(e0 * e0 + e1 * e1 + e2 * e2);
+                    int fs;
+                    T Ns[4], dNs[4];
+                    bspline4<T>(rjk, a.h3c, a.ih3c, a.nk3, fs, Ns, dNs);
+                    int fk = f3[k];
+                    T V = T(0), V1 = T(0), V3 = T(0);
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        s0 += cr[u] * Ns[u];
-                        s1 += cr[u] * dNs[u];
+                    for (int pp = 0; pp < 4; ++pp) {
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const T *cr = c3s + ((fj + pp) * nb + (fk + q)) * nb + fs;
+                            T bk = B3[k * 4 + q];
+                            T s0 = T(0), s1 = T(0);
+#pragma unroll
+                            for (int u = 0; u < 4; ++u) {
+                                s0 += cr[u] * Ns[u];
+                                s1 += cr[u] * dNs[u];
+                            }
+                            V += Bj[pp] * bk * s0;
+                            V1 += dBj[pp] * bk * s0;
+                            V3 += Bj[pp] * bk * s1;
+                        }
                     }
-                    V += Bj[p] * bk * s0;
-                    V1 += dBj[p] * bk * s0;
-                    V3 += Bj[p] * bk * s1;
+                    Ep += T(0.5) * V;
+                    T a1 = V1 / rj;
+                    T a3 = V3 / rjk;
+                    hx += a1 * dj0 - a3 * e0;
+                    hy += a1 * dj1 - a3 * e1;
+                    hz += a1 * dj2 - a3 * e2;
                 }
             }
-            Ep += T(0.5) * V;
-            T a1 = V1 / rj;
-            T a3 = V3 / rjk;
-            hx += a1 * dj0 - a3 * e0;
-            hy += a1 * dj1 - a3 * e1;
-            hz += a1 * dj2 - a3 * e2;
+            hx += __shfl_xor(hx, 16);
+            hy += __shfl_xor(hy, 16);
+            hz += __shfl_xor(hz, 16);
+            hx += __shfl_xor(hx, 32);
+            hy += __shfl_xor(hy, 32);
+            hz += __shfl_xor(hz, 32);
+            if (kc == 0 && t < n3) {
+                int slt = sl3[t];
+                hs[slt * 3 + 0] += hx;
+                hs[slt * 3 + 1] += hy;
+                hs[slt * 3 + 2] += hz;
+            }
         }
-        int sl = sl3[t];
-        hs[sl * 3 + 0] += hx;
-        hs[sl * 3 + 1] += hy;
-        hs[sl * 3 + 2] += hz;
     }
     __syncthreads();
+    if (!valid)
+        return;
     T *ho = hout + (size_t)i * cap * 3;
     for (int e = lane; e < 3 * c; e += 64)
         ho[e] = hs[e];
@@ -275,9 +323,9 @@ static void uf3_t(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L, cons
     a.c2 = reinterpret_cast<const T *>(base + m.u2);
     a.c3 = reinterpret_cast<const T *>(base + m.u3);
     int nb3c = m.nb3 > 0 ? m.nb3 * m.nb3 * m.nb3 : 0;
-    size_t sm = (size_t)(3 * L.cap + 3 * kMaxTriplet + kMaxTriplet + 8 * kMaxTriplet + nb3c) * sizeof(T) +
-                2 * kMaxTriplet * sizeof(int) + 16;
-    k_uf3<T><<<L.n, 64, sm, s>>>(pos, L.n, b, species, L.cap, at<int>(ws, L.nbr),
+    Uf3Slice sl = uf3_slice(L.cap, nb3c);
+    size_t sm = 4 * ((size_t)sl.nT * sizeof(T) + 2 * kMaxTriplet * sizeof(int)) + 16;
+    k_uf3<T><<<(L.n + 3) / 4, 256, sm, s>>>(pos, L.n, b, species, L.cap, at<int>(ws, L.nbr),
                                  at<int>(ws, L.cnt), a, at<T>(ws, L.h), e_cheap,
                                  at<int>(ws, L.hdr));
 }
