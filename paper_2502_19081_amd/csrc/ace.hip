@@ -202,14 +202,15 @@ template <typename T>
 __global__ void __launch_bounds__(256)
     k_ace_blocks(const int32_t *__restrict__ species, const int *__restrict__ S_idx,
                  const int *__restrict__ hdr, AceArgs<T> a, int TA, int n_pb, int max_ent,
-                 int use_mfma, const int *__restrict__ dp_off, int dp_stride,
+                 int use_mfma, int stage_w, const int *__restrict__ dp_off, int dp_stride,
                  const T *__restrict__ A, T *__restrict__ Dpart)
 {
     const int nS = hdr[H_NS];
     const int ntile = (nS + TA - 1) / TA;
     const int nitems = ntile * n_pb;
     if ((int)blockIdx.x >= nitems)
-        return;  // uniform across the block
+        return;  // uniform across the block (the chunking below leaves
+                 // workgroups with blockIdx.x >= nitems without work)
     const int tid = threadIdx.x;
     const int lane = tid & 63, wv = tid >> 6;
     const int nch = a.nchan, nchp = a.nchp, KAt = a.KAt;
@@ -219,13 +220,17 @@ __global__ void __launch_bounds__(256)
     extern __shared__ __align__(16) char smem_raw[];
     T *At = reinterpret_cast<T *>(smem_raw);  // [TA][L2][nchp]
     T *P = At + (size_t)TA * KAt;              // [rowsp][Ks]
-    T *Ws = P + (size_t)rowsp * Ks;            // [Kp][nchp] when MFMA
-    T *gv = Ws + (use_mfma ? (size_t)Kp * nchp : 0);
+    T *Ws = P + (size_t)rowsp * Ks;            // [Kp][nchp] when staged
+    T *gv = Ws + (stage_w ? (size_t)Kp * nchp : 0);
     int *gi = reinterpret_cast<int *>(gv + max_ent);
     int *g3 = gi + max_ent;
     __shared__ int zt[16];
     int cur_tile = -1;
-    for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
+    // contiguous chunk of items per workgroup: consecutive items share a tile
+    const int per = (nitems + gridDim.x - 1) / gridDim.x;
+    const int i_lo = blockIdx.x * per;
+    const int i_hi = min(nitems, i_lo + per);
+    for (int item = i_lo; item < i_hi; ++item) {
         const int tile = item / n_pb, p = item - tile * n_pb;
         const int s0 = tile * TA;
         const int na = (nS - s0) < TA ? (nS - s0) : TA;
@@ -249,15 +254,57 @@ __global__ void __launch_bounds__(256)
         }
         for (int e = tid; e <= d3; e += 256)
             g3[e] = a.gm3[pb.gm3_off + e] - e_lo;
-        if (use_mfma) {
-            const T *src = a.W + pb.w_off;
+        const T *Wb = a.W + pb.w_off;  // single-species weights of the block
+        if (stage_w) {
             for (int e = tid; e < Kp * nchp; e += 256)
-                Ws[e] = src[e];
+                Ws[e] = Wb[e];
+            Wb = Ws;
         }
         __syncthreads();
-        // sparse Gaunt stage. Thread -> (a, four b) once; rows advance by a
-        // fixed stride, so no per-item integer division is needed.
         const int ncb = nchp >> 2;
+        if (use_mfma) {
+            // sparse Gaunt stage on MFMA: for each row (atom t, m3),
+            // P[a][b] = sum_e (g_e A[o1_e][a]) A[o2_e][b], i.e. a 16x16 product
+            // with K = the m3 group's Gaunt entries, four per instruction.
+            const int nat = (nch + 15) >> 4;
+            const int kk = lane >> 4;
+            for (int rr = wv; rr < nrows; rr += 4) {
+                const int t = rr / d3, m3 = rr - t * d3;
+                const T *Att = At + (size_t)t * KAt;
+                const int e0 = g3[m3], e1 = g3[m3 + 1];
+                for (int at_ = 0; at_ < nat; ++at_)
+                    for (int bt = 0; bt < nat; ++bt) {
+                        const int ar = at_ * 16 + (lane & 15);
+                        const int bc = bt * 16 + (lane & 15);
+                        typename Mfma<T>::v4 acc = {T(0), T(0), T(0), T(0)};
+                        for (int k0 = e0; k0 < e1; k0 += 4) {
+                            const int e = k0 + kk;
+                            T av = T(0), bv = T(0);
+                            if (e < e1) {
+                                const int of = gi[e];
+                                if (ar < nch)
+                                    av = gv[e] * Att[(of & 0xffff) + ar];
+                                if (bc < nch)
+                                    bv = Att[(of >> 16) + bc];
+                            }
+                            acc = Mfma<T>::op(av, bv, acc);
+                        }
+                        // lane holds P[a = at_*16 + 4 kk + v][b = bc]; padded
+                        // columns nch <= b < nchp are written as zeros
+                        if (bc < nchp) {
+                            T *Pr = P + (size_t)rr * Ks + bc;
+#pragma unroll
+                            for (int v = 0; v < 4; ++v) {
+                                const int a2 = at_ * 16 + 4 * kk + v;
+                                if (a2 < nch)
+                                    Pr[a2 * nchp] = bc < nch ? acc[v] : T(0);
+                            }
+                        }
+                    }
+            }
+        } else {
+        // sparse Gaunt stage on VALU. Thread -> (a, four b) once; rows advance
+        // by a fixed stride, so no per-item integer division is needed.
         const int Q = nch * ncb;
         const int rstep = Q <= 256 ? 256 / Q : 1;
         for (int q = (Q <= 256 ? (tid < rstep * Q ? tid % Q : Q) : tid); q < Q; q += 256) {
@@ -289,6 +336,7 @@ __global__ void __launch_bounds__(256)
                 }
             }
         }
+        }
         __syncthreads();
         T *Dbase = Dpart + dp_off[p];
         if (use_mfma) {
@@ -305,7 +353,7 @@ __global__ void __launch_bounds__(256)
                 for (int k0 = 0; k0 < Kp; k0 += 4) {
                     int k = k0 + kk;
                     T av = rv ? Pr[k] : T(0);
-                    T bv = cv ? Ws[k * nchp + col] : T(0);
+                    T bv = cv ? Wb[k * nchp + col] : T(0);
                     acc = Mfma<T>::op(av, bv, acc);
                 }
 #pragma unroll
@@ -524,33 +572,33 @@ static void basis_t(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L, co
 }
 
 // LDS bytes of one order-3 block workgroup of ta atoms.
-static size_t blocks_lds(const Ctx &c, int ta, size_t tsz, int use_mfma)
+static size_t blocks_lds(const Ctx &c, int ta, size_t tsz, int stage_w)
 {
     const DevModel &m = c.m;
     size_t b = (size_t)ta * m.KAt * tsz;
     b += (size_t)blocks_rows(ta, m.lmax) * blocks_kstride(m.nchan, m.nchp) * tsz;
-    if (use_mfma)
+    if (stage_w)
         b += (size_t)m.nchan * m.nchp * m.nchp * tsz;
     b += (size_t)c.max_ent_pb * (tsz + sizeof(int)) + (2 * m.lmax + 2) * sizeof(int) + 32;
     return b;
 }
 
-// Tile of up to 8 atoms within 64 KiB of LDS; MFMA dense stage (weights in
-// LDS) for single-species FP32 models when the tile still holds 2 atoms.
-// FP64 (the verification precision) keeps the VALU dense stage.
-static void blocks_shape(const Ctx &c, size_t tsz, int &ta_out, int &mfma_out)
+// Launch shape of the order-3 blocks: MFMA stages for single-species FP32
+// models (FP64, the verification precision, and multi-species models keep
+// the VALU stages); tile of c.ace_tile atoms (default 4) with the block's
+// weights staged in LDS (c.ace_stage_w, default on) — the best of a sweep
+// over 1-8 atoms with and without staging on the 8,193-atom workload; the
+// tile shrinks until the LDS tile fits 64 KiB.
+static void blocks_shape(const Ctx &c, size_t tsz, int &ta, int &mfma, int &stage)
 {
     const DevModel &m = c.m;
-    const size_t lim = 64 * 1024;
-    for (int mf = (m.ns == 1 && tsz == 4 ? 1 : 0); mf >= 0; --mf)
-        for (int ta = 8; ta >= (mf ? 2 : 1); ta >>= 1)
-            if (blocks_lds(c, ta, tsz, mf) <= lim) {
-                ta_out = ta;
-                mfma_out = mf;
-                return;
-            }
-    ta_out = 1;
-    mfma_out = 0;
+    mfma = (m.ns == 1 && tsz == 4) ? 1 : 0;
+    stage = mfma ? c.ace_stage_w : 0;
+    for (ta = c.ace_tile; ta > 1; ta >>= 1)
+        if (blocks_lds(c, ta, tsz, stage) <= 64 * 1024)
+            break;
+    if (blocks_lds(c, ta, tsz, stage) > 64 * 1024)
+        stage = 0;
 }
 
 template <typename T>
@@ -562,13 +610,13 @@ static void contract_t(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L,
     const int *dp_off = reinterpret_cast<const int *>(static_cast<char *>(c.m.base) + c.m.dpoff);
     T *Dpart = at<T>(ws, L.dpart);
     if (a.order >= 3 && c.m.n_pb > 0) {
-        int TA, mf;
-        blocks_shape(c, sizeof(T), TA, mf);
-        size_t sm = blocks_lds(c, TA, sizeof(T), mf);
+        int TA, mf, stage;
+        blocks_shape(c, sizeof(T), TA, mf, stage);
+        size_t sm = blocks_lds(c, TA, sizeof(T), stage);
         long items = (long)((L.n + TA - 1) / TA) * c.m.n_pb;
-        int grid = (int)(items < 4096 ? items : 4096);
+        int grid = (int)(items < 8192 ? items : 8192);
         k_ace_blocks<T><<<grid, 256, sm, s>>>(species, at<int>(ws, L.S_idx), at<int>(ws, L.hdr), a,
-                                              TA, c.m.n_pb, c.max_ent_pb, mf, dp_off,
+                                              TA, c.m.n_pb, c.max_ent_pb, mf, stage, dp_off,
                                               c.m.dp_stride, at<T>(ws, L.A), Dpart);
     }
     k_ace_finalize<T><<<(L.n + 3) / 4, 256, 0, s>>>(species, at<int>(ws, L.S_idx),

@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -453,6 +454,14 @@ extern "C" int mlmix_create(const mlmix_model_desc *desc, mlmix_ctx **out)
     Ctx &c = ctx->c;
     c.d = d;
     c.prec = d.precision;
+    // tuning overrides of the order-3 launch shape (benchmark sweeps)
+    if (const char *e = std::getenv("MLMIX_ACE_TILE")) {
+        int v = std::atoi(e);
+        if (v == 1 || v == 2 || v == 4 || v == 8 || v == 16)
+            c.ace_tile = v;
+    }
+    if (const char *e = std::getenv("MLMIX_ACE_STAGE_W"))
+        c.ace_stage_w = std::atoi(e) ? 1 : 0;
     double rmax = std::max(d.ace_rcut, d.uf3_rcut2);
     if (d.uf3_n_knots3 > 0)
         rmax = std::max(rmax, d.uf3_rcut3);

@@ -91,6 +91,8 @@ struct Ctx {
     int m_pb_lo[kMaxLmax + 1], m_pb_hi[kMaxLmax + 1];  // order-3 blocks per l3
     int max_ent, max_gm3;  // Gaunt entries / m3 offsets of the largest l3 group
     int max_ent_pb;        // Gaunt entries of the largest single block
+    int ace_tile = 4;      // atoms per order-3 block workgroup (tuning)
+    int ace_stage_w = 1;   // stage the block's weights in LDS (tuning)
     int device;
 };
 
