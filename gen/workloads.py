@@ -38,8 +38,10 @@ BASE_SEED = 2502190810
 ACE_SCALE = {
     "c1": (0.6, 0.3, 0.0),
     "c2": (0.2, 0.02, 0.01),
-    "c3": (0.2, 0.02, 0.01),
-    "c4": (0.5, 0.15, 0.06),
+    # MD workloads: 20x weaker random parts (forces ~0.05 eV/A) so that the
+    # 1-ps runs stay near the crystal instead of collapsing
+    "c3": (0.01, 0.001, 0.0005),
+    "c4": (0.025, 0.0075, 0.003),
     "c5": (0.3, 0.008, 0.017),
     "tiny": (1.7, 2.8, 1.9),
 }
@@ -72,7 +74,8 @@ def ace_params(rng, n_species, n_rad, lmax, order, rcut, scales):
                 c0=c0, c1=c1, c2=c2, c3=c3)
 
 
-def uf3_params(rng, n_species, n_knots2, rcut2, n_knots3=0, rcut3=3.5):
+def uf3_params(rng, n_species, n_knots2, rcut2, n_knots3=0, rcut3=3.5,
+               scale2=UF3_SCALE2, scale3=UF3_SCALE3):
     """Random clamped-cubic-B-spline coefficients.
 
     c2[zi][zj][n] (symmetric in zi, zj), n_knots2 + 2 coefficients per pair,
@@ -84,13 +87,13 @@ def uf3_params(rng, n_species, n_knots2, rcut2, n_knots3=0, rcut3=3.5):
     c2 = np.zeros((n_species, n_species, nb2))
     for a in range(n_species):
         for b in range(a, n_species):
-            v = rng.normal(0.0, UF3_SCALE2, size=nb2)
+            v = rng.normal(0.0, scale2, size=nb2)
             v[-3:] = 0.0
             c2[a, b] = v
             c2[b, a] = v
     if n_knots3 > 0:
         nb3 = n_knots3 + 2
-        c3 = rng.normal(0.0, UF3_SCALE3, size=(n_species, nb3, nb3, nb3))
+        c3 = rng.normal(0.0, scale3, size=(n_species, nb3, nb3, nb3))
         c3 = 0.5 * (c3 + c3.transpose(0, 2, 1, 3))
         c3[:, -3:, :, :] = 0.0
         c3[:, :, -3:, :] = 0.0
@@ -148,11 +151,12 @@ def c1(seed=BASE_SEED + 0, sigma=0.05):
                  [sphere(centre, 6.0, 2.0)], 5.0, model, precision="fp64")
 
 
-def c2_model(rng_ace, rng_uf3, n_species=1, rcut_exp=5.5, scales=None):
+def c2_model(rng_ace, rng_uf3, n_species=1, rcut_exp=5.5, scales=None, uf3_scale=1.0):
     return dict(n_species=n_species, skin=1.0,
                 ace=ace_params(rng_ace, n_species, 12, 4, 3, rcut_exp,
                                scales or ACE_SCALE["c2"]),
-                uf3=uf3_params(rng_uf3, n_species, 16, 5.5, 6, 3.5))
+                uf3=uf3_params(rng_uf3, n_species, 16, 5.5, 6, 3.5,
+                               UF3_SCALE2 * uf3_scale, UF3_SCALE3 * uf3_scale))
 
 
 def c2(seed=BASE_SEED + 1, sigma=0.08):
@@ -186,7 +190,7 @@ def c3(seed=BASE_SEED + 2, T=300.0, margin=12.0, ncell=(30, 15, 20)):
     pos[:, 1] += margin
     pos = wrap(pos, L, [0, 0, 1])
     species = np.zeros(len(pos), dtype=np.int32)
-    model = c2_model(r[1], r[2])
+    model = c2_model(r[1], r[2], scales=ACE_SCALE["c3"], uf3_scale=0.05)
     vel = maxwell(r[3], species, T)
     centre = np.array([core[0] + margin, core[1] + margin, 0.0])
     return _pack("c3", seed, pos, species, L, [0, 0, 1],
@@ -194,11 +198,28 @@ def c3(seed=BASE_SEED + 2, T=300.0, margin=12.0, ncell=(30, 15, 20)):
                  precision="fp32", dt=1.0, T=T)
 
 
+HE_WALL = 100.0  # eV; weight of the smooth He-W repulsion in both potentials
+
+
 def c4_model(seed=BASE_SEED + 3):
+    """Two species (W = 0, He = 1). Random weak parts as the other MD
+    workload, plus a smooth He-W repulsion in both potentials so that 10-80 eV
+    He atoms reflect or stop: in the ACE-style model the order-1 weight of the
+    n = 0 radial function of the unlike channel (R_0 is the decreasing
+    envelope), in the UF3-style model a decreasing ramp on the He-W pair
+    spline."""
     r = _streams(seed)
-    return dict(n_species=2, skin=1.0,
-                ace=ace_params(r[1], 2, 12, 4, 3, 5.0, ACE_SCALE["c4"]),
-                uf3=uf3_params(r[2], 2, 16, 6.0, 6, 3.5))
+    ace = ace_params(r[1], 2, 12, 4, 3, 5.0, ACE_SCALE["c4"])
+    nr = ace["n_rad"]
+    ace["c1"][0, 1 * nr + 0] = HE_WALL   # W centre, He neighbours
+    ace["c1"][1, 0 * nr + 0] = HE_WALL   # He centre, W neighbours
+    uf3 = uf3_params(r[2], 2, 16, 6.0, 6, 3.5, UF3_SCALE2 * 0.05, UF3_SCALE3 * 0.05)
+    nb2 = uf3["c2"].shape[-1]
+    ramp = np.maximum(0.0, 1.0 - np.arange(nb2) / 7.0) ** 2 * 20.0
+    ramp[-3:] = 0.0
+    uf3["c2"][0, 1] += ramp
+    uf3["c2"][1, 0] += ramp
+    return dict(n_species=2, skin=1.0, ace=ace, uf3=uf3)
 
 
 def c4_replica(index, seed=BASE_SEED + 3, n_min=2000, n_max=20000, T=1000.0,

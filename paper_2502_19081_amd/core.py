@@ -122,6 +122,7 @@ class System:
         self.energies = torch.zeros(3, **z)
         self.regions = pack_regions([], device)
         self.n_regions = 0
+        self.generation = 0  # bumped by every evaluation on this workspace
 
     def set_regions(self, regions):
         self.regions = pack_regions(regions, self.device)
@@ -133,6 +134,7 @@ class System:
         assert pos.shape == (3, self.n) and pos.dtype == torch.float64 and pos.is_contiguous()
         assert species.shape == (self.n,) and species.dtype == torch.int32
         flags = mode | (B.FORCE_REBUILD if force_rebuild else 0) | (B.ENERGY_ONLY if energy_only else 0)
+        self.generation += 1
         fe = fc = None
         if split:
             fe = torch.zeros(3, self.n, dtype=torch.float64, device=self.device)
@@ -157,6 +159,7 @@ class System:
 
     def vv_step(self, pos, vel, mass, species, dt, r_buffer=0.0, mode=B.MODE_MIXED,
                 force_rebuild=False, energies=True):
+        self.generation += 1
         flags = mode | (B.FORCE_REBUILD if force_rebuild else 0)
         B.check(B.lib().mlmix_vv_step(self.model.handle, _stream(), _p(self.ws), self.n, _p(pos),
                                       _p(vel), _p(mass), _p(species), float(dt),
