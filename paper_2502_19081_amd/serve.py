@@ -1,0 +1,261 @@
+"""Continuous batching of independent MD replicas (the He-impact serving
+workload) on one GPU.
+
+Each replica keeps its positions, velocities, forces, neighbour list and
+every intermediate resident in its own workspace. Requests arrive over time
+(Poisson arrivals); whenever a slot and enough HBM are free, waiting requests
+are admitted. Whenever the set of active replicas changes, one HIP graph is
+captured that holds one velocity-Verlet step of every active replica, each in
+its own stream branch (fork from the capture stream, join back), so the
+replicas' kernels overlap on the device and a tick costs one graph launch.
+Finished replicas are retired (state copied to the host, memory released)
+and their slots refilled at the next tick.
+
+Latency of a replica step = wall time of the tick it ran in, including the
+wait for the other replicas of the batch (host timestamps around the replay
+and its completion).
+
+CLI: python -m paper_2502_19081_amd.serve --replicas 64 --steps 500
+"""
+import argparse
+import ctypes
+import json
+import sys
+import time
+
+import numpy as np
+import torch
+
+from . import binding as B
+from . import core
+
+
+class Replica:
+    def __init__(self, rid, w, steps, dt, arrival, mode=B.MODE_MIXED):
+        self.rid = rid
+        self.w = w
+        self.n = len(w["pos"])
+        self.steps = steps
+        self.dt = dt
+        self.arrival = arrival
+        self.mode = mode
+        self.done = 0
+        self.admitted_at = None
+        self.finished_at = None
+        self.latencies = []
+        self.result = None
+        self.error = None
+
+    def footprint(self, model, cap):
+        """Device bytes of this replica: workspace plus resident state."""
+        sz = ctypes.c_size_t()
+        box = core.make_box(self.w["L"], self.w["periodic"])
+        B.check(B.lib().mlmix_workspace_size(model.handle, self.n, cap, ctypes.byref(box),
+                                             ctypes.byref(sz)))
+        state = self.n * (3 * 8 * 4 + 8 * 4 + 4 + 1) + 4096
+        return int(sz.value) + state
+
+    def load(self, model, cap, device):
+        w = self.w
+        _, self.sy, self.pos, self.sp = core.system_for(w, model=model, cap=cap, device=device)
+        self.vel = torch.from_numpy(np.ascontiguousarray(w["vel"].T)).to(device)
+        self.mass = torch.from_numpy(w["masses"][w["species"]].astype(np.float64)).to(device)
+        self.sy.compute(self.pos, self.sp, r_buffer=w["r_buffer"], mode=self.mode, force_rebuild=True)
+
+    def step(self):
+        self.sy.vv_step(self.pos, self.vel, self.mass, self.sp, self.dt,
+                        r_buffer=self.w["r_buffer"], mode=self.mode)
+
+    def retire(self):
+        bits, _, rc = self.sy.status(raise_on_error=False)
+        self.error = None if rc == B.MLMIX_OK else (rc, bits)
+        self.result = dict(pos=self.pos.cpu().numpy().T.copy(), vel=self.vel.cpu().numpy().T.copy(),
+                           energies=self.sy.energies.cpu().numpy().copy(),
+                           n_exp=self.sy.n_exp.cpu().numpy().copy())
+        del self.sy, self.pos, self.vel, self.mass, self.sp
+
+
+class Server:
+    """Continuous-batching server for replicas sharing one model."""
+
+    def __init__(self, model, hbm_budget=8 << 30, max_slots=16, n_streams=8, cap=128,
+                 device="cuda", use_graph=True, check_every=50):
+        self.model = model
+        self.budget = int(hbm_budget)
+        self.max_slots = max_slots
+        self.cap = cap
+        self.device = device
+        self.use_graph = use_graph
+        self.streams = [torch.cuda.Stream(device=device) for _ in range(n_streams)]
+        self.capture_stream = torch.cuda.Stream(device=device)
+        self.waiting = []
+        self.active = []
+        self.finished = []
+        self.in_use = 0
+        self.graph = None
+        self.recaptures = 0
+        self.ticks = []
+        self.check_every = check_every
+        self.failed = []
+
+    def submit(self, replica):
+        self.waiting.append(replica)
+        self.waiting.sort(key=lambda r: r.arrival)
+
+    def _admit(self, now):
+        changed = False
+        while self.waiting and self.waiting[0].arrival <= now and len(self.active) < self.max_slots:
+            r = self.waiting[0]
+            fp = r.footprint(self.model, self.cap)
+            if self.in_use + fp > self.budget:
+                if not self.active:
+                    raise RuntimeError(f"replica {r.rid} needs {fp} bytes, over the HBM budget")
+                break
+            self.waiting.pop(0)
+            r.load(self.model, self.cap, self.device)
+            r.admitted_at = now
+            r.fp = fp
+            self.in_use += fp
+            self.active.append(r)
+            changed = True
+        return changed
+
+    def _capture(self):
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        cs = self.capture_stream
+        cs.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(cs):
+            with torch.cuda.graph(g, stream=cs):
+                used = []
+                for k, r in enumerate(self.active):
+                    st = self.streams[k % len(self.streams)]
+                    st.wait_stream(cs)
+                    with torch.cuda.stream(st):
+                        r.step()
+                    used.append(st)
+                for st in used:
+                    cs.wait_stream(st)
+        torch.cuda.current_stream().wait_stream(cs)
+        self.graph = g
+        self.recaptures += 1
+
+    def _tick(self):
+        t0 = time.perf_counter()
+        if self.use_graph:
+            self.graph.replay()
+        else:
+            for k, r in enumerate(self.active):
+                with torch.cuda.stream(self.streams[k % len(self.streams)]):
+                    r.step()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        self.ticks.append((len(self.active), dt))
+        for r in self.active:
+            r.done += 1
+            r.latencies.append(dt)
+        return dt
+
+    def _evict_failed(self, now):
+        """Device status of every active replica; a replica whose status
+        reports an error (non-finite input, overflow, an atom outside a
+        non-periodic box) is evicted alone; the others continue."""
+        bad = []
+        for r in self.active:
+            bits, _, rc = r.sy.status(raise_on_error=False)
+            if rc != B.MLMIX_OK:
+                r.error = (rc, bits)
+                bad.append(r)
+        for r in bad:
+            r.finished_at = now
+            self.in_use -= r.fp
+            del r.sy, r.pos, r.vel, r.mass, r.sp
+            self.failed.append(r)
+        if bad:
+            self.active = [r for r in self.active if r not in bad]
+            self.graph = None
+
+    def run(self, clock=None):
+        """Serve until every submitted replica has finished. `clock()` gives
+        the time used for arrivals (wall time since start by default)."""
+        start = time.perf_counter()
+        clock = clock or (lambda: time.perf_counter() - start)
+        while self.waiting or self.active:
+            now = clock()
+            changed = self._admit(now)
+            if not self.active:
+                # idle until the next arrival
+                time.sleep(max(0.0, min(0.01, self.waiting[0].arrival - now)))
+                continue
+            if changed or self.graph is None:
+                if self.use_graph:
+                    self._capture()
+            self._tick()
+            if len(self.ticks) % self.check_every == 0:
+                self._evict_failed(clock())
+            done = [r for r in self.active if r.done >= r.steps]
+            if done:
+                for r in done:
+                    r.finished_at = clock()
+                    r.retire()
+                    self.in_use -= r.fp
+                    self.finished.append(r)
+                self.active = [r for r in self.active if r.done < r.steps]
+                self.graph = None
+        return self.finished
+
+    def report(self, wall):
+        lat = np.concatenate([np.array(r.latencies) for r in self.finished]) * 1e3
+        atom_steps = sum(r.n * r.steps for r in self.finished)
+        waits = [r.admitted_at - r.arrival for r in self.finished]
+        return {"replicas": len(self.finished), "atom_steps": atom_steps,
+                "wall_s": wall, "replica_atom_steps_per_s": atom_steps / wall,
+                "p50_step_ms": float(np.percentile(lat, 50)),
+                "p99_step_ms": float(np.percentile(lat, 99)),
+                "mean_queue_wait_s": float(np.mean(waits)),
+                "max_batch": max(a for a, _ in self.ticks), "graph_captures": self.recaptures}
+
+
+def replicas_c4(count, steps, seed_rate=None, rate_hz=None, dt=0.2, n_range=(2000, 20000), seed=0):
+    """Replica requests of the He-impact workload with Poisson arrivals."""
+    from gen import workloads as W
+    rng = np.random.default_rng(np.random.SeedSequence([W.BASE_SEED + 3, 99, seed]))
+    gaps = rng.exponential(1.0 / rate_hz, size=count) if rate_hz else np.zeros(count)
+    t = np.cumsum(gaps)
+    out = []
+    for k in range(count):
+        w = W.c4_replica(k, n_min=n_range[0], n_max=n_range[1])
+        out.append(Replica(k, w, steps, dt, float(t[k])))
+    return out
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--replicas", type=int, default=64)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--rate", type=float, default=0.0, help="Poisson arrival rate (1/s); 0 = all at t=0")
+    ap.add_argument("--slots", type=int, default=16)
+    ap.add_argument("--hbm-gb", type=float, default=16.0)
+    ap.add_argument("--no-graph", action="store_true")
+    args = ap.parse_args(argv)
+    from gen import workloads as W
+    model = core.Model(W.c4_model(), precision="fp32")
+    srv = Server(model, hbm_budget=args.hbm_gb * (1 << 30), max_slots=args.slots,
+                 use_graph=not args.no_graph)
+    reps = replicas_c4(args.replicas, args.steps, rate_hz=args.rate or None)
+    for r in reps:
+        srv.submit(r)
+    t0 = time.perf_counter()
+    srv.run()
+    wall = time.perf_counter() - t0
+    rep = srv.report(wall)
+    rep.update({"workload": "c4: W(001)+He impact replicas, log-uniform 2,000-20,000 atoms, "
+                            "dt 0.2 fs, 8 A sphere following He, FP32 potentials",
+                "steps_per_replica": args.steps, "arrival_rate_hz": args.rate,
+                "slots": args.slots, "graph": not args.no_graph})
+    print(json.dumps(rep))
+    return rep
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:])

@@ -1,0 +1,77 @@
+"""Continuous batching of He-impact replicas: a replica gives the same bits
+alone and in a changing mix; admission respects the HBM budget; a replica
+with a non-finite position is evicted alone."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def _model():
+    from gen import workloads as W
+    from paper_2502_19081_amd import core
+    return core.Model(W.c4_model(), precision="fp32")
+
+
+def _rep(k, steps, arrival, n_target):
+    from gen import workloads as W
+    from paper_2502_19081_amd.serve import Replica
+    return Replica(k, W.c4_replica(k, n_target=n_target), steps, 0.2, arrival)
+
+
+def test_alone_equals_in_mix():
+    from paper_2502_19081_amd.serve import Server
+    model = _model()
+    print("case serving alone vs mix (c4 replicas, 40 steps)", flush=True)
+    alone = Server(model, max_slots=4)
+    a = _rep(5, 40, 0.0, 3000)
+    alone.submit(a)
+    alone.run(clock=lambda: 0.0)
+    mix = Server(model, max_slots=3)
+    ticks = {"t": 0}
+
+    def clock():  # arrivals in tick units: the mix changes while replica 5 runs
+        return float(len(mix.ticks))
+    b = _rep(5, 40, 0.0, 3000)
+    others = [_rep(1, 25, 0.0, 2000), _rep(2, 30, 5.0, 4500), _rep(3, 10, 12.0, 2500),
+              _rep(4, 20, 20.0, 6000)]
+    for r in [b] + others:
+        mix.submit(r)
+    mix.run(clock=clock)
+    assert mix.recaptures >= 3
+    assert max(n for n, _ in mix.ticks) == 3
+    assert a.error is None and b.error is None
+    for key in ("pos", "vel", "energies"):
+        assert np.array_equal(a.result[key], b.result[key]), key
+
+
+def test_admission_by_hbm_budget():
+    from paper_2502_19081_amd.serve import Server
+    model = _model()
+    reps = [_rep(k, 5, 0.0, 2000) for k in range(6)]
+    fp = max(r.footprint(model, 128) for r in reps)
+    srv = Server(model, hbm_budget=int(2.5 * fp), max_slots=8)
+    for r in reps:
+        srv.submit(r)
+    srv.run(clock=lambda: 0.0)
+    assert len(srv.finished) == 6
+    assert max(n for n, _ in srv.ticks) == 2
+
+
+def test_nonfinite_replica_is_evicted_alone():
+    import torch
+    from paper_2502_19081_amd.serve import Server
+    model = _model()
+    srv = Server(model, max_slots=4, check_every=2)
+    good = [_rep(k, 8, 0.0, 2000) for k in (7, 8)]
+    bad = _rep(9, 8, 0.0, 2000)
+    bad.w = dict(bad.w)
+    p = bad.w["pos"].copy()
+    p[10, 0] = np.nan
+    bad.w["pos"] = p
+    for r in good + [bad]:
+        srv.submit(r)
+    srv.run(clock=lambda: 0.0)
+    assert [r.rid for r in srv.failed] == [9]
+    assert sorted(r.rid for r in srv.finished) == [7, 8]
+    assert all(r.error is None for r in srv.finished)
