@@ -57,9 +57,16 @@ extern "C" {
 #define MLMIX_E_STATE (-7)
 
 /* Arithmetic of the two potentials. Positions, lambda, the blend, energy
- * sums and the integrator are FP64 in every mode. */
+ * sums and the integrator are FP64 in every mode. The two reduced-precision
+ * modes compute in FP32 except the dense stage of the order-3 product-basis
+ * contraction, whose operands are rounded to BF16 or scaled to FP8 (E4M3:
+ * one scale per atom shared by the m components, from a per-call maximum,
+ * and one per output channel of the weights), with FP32 accumulation on the
+ * matrix cores; they require a single-species model. */
 #define MLMIX_FP64 0
 #define MLMIX_FP32 1
+#define MLMIX_BF16_CONTRACT 2
+#define MLMIX_FP8_CONTRACT 3
 
 /* Evaluation modes (low byte) and flags. */
 #define MLMIX_MODE_MIXED 0          /* lambda from regions, S = {lambda>0} + buffer */
@@ -101,7 +108,7 @@ extern "C" {
  *   the 3-body term off (c3 may then be NULL). */
 typedef struct {
     int32_t n_species;
-    int32_t precision; /* MLMIX_FP64 or MLMIX_FP32 */
+    int32_t precision; /* MLMIX_FP64, MLMIX_FP32, MLMIX_BF16_CONTRACT, MLMIX_FP8_CONTRACT */
     double skin;       /* neighbour-list skin; list radius = max cutoff + skin */
     int32_t ace_n_rad, ace_lmax, ace_order, ace_pad;
     double ace_rcut;

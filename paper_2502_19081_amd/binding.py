@@ -14,7 +14,7 @@ MLMIX_OK = 0
 ERRORS = {-1: "MLMIX_E_ARG", -2: "MLMIX_E_HIP", -3: "MLMIX_E_WORKSPACE",
           -4: "MLMIX_E_NEIGH_OVERFLOW", -5: "MLMIX_E_BOX", -6: "MLMIX_E_NONFINITE",
           -7: "MLMIX_E_STATE"}
-FP64, FP32 = 0, 1
+FP64, FP32, BF16_CONTRACT, FP8_CONTRACT = 0, 1, 2, 3
 MODE_MIXED, MODE_ALL_EXPENSIVE, MODE_ALL_CHEAP = 0, 1, 2
 FORCE_REBUILD = 0x100
 ENERGY_ONLY = 0x200

@@ -54,7 +54,8 @@ class Model:
         c0, c1, c2, c3, u2, u3 = self._keep
         d = B.ModelDesc()
         d.n_species = int(model["n_species"])
-        d.precision = B.FP64 if precision == "fp64" else B.FP32
+        d.precision = {"fp64": B.FP64, "fp32": B.FP32, "bf16": B.BF16_CONTRACT,
+                       "fp8": B.FP8_CONTRACT}[precision]
         d.skin = float(model["skin"])
         d.ace_n_rad, d.ace_lmax, d.ace_order = int(a["n_rad"]), int(a["lmax"]), int(a["order"])
         d.ace_rcut = float(a["rcut"])

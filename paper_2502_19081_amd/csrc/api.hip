@@ -175,7 +175,7 @@ static std::vector<double> gaunt(int lmax, const std::vector<double> &K)
 }
 
 struct HostTables {
-    std::vector<double> K, c0, c1, c2s, W, gval, u2, u3;
+    std::vector<double> K, c0, c1, c2s, W, gval, u2, u3, wsc;
     std::vector<PBlock> pb;
     std::vector<int> gm3, gidx, gofs, dpoff;
     int w_per_species = 0;
@@ -257,6 +257,16 @@ static int build_tables(const mlmix_model_desc &d, HostTables &t)
                             t.W[(size_t)z * t.w_per_species + p.w_off + ((size_t)a * nchp + b) * nchp + c] = v;
                         }
     }
+    // FP8 weight scales: max |W| over K per (block, output channel), first
+    // species (the reduced-precision contraction is for single-species models)
+    t.wsc.assign(std::max<size_t>(1, t.pb.size() * (size_t)nchp), 1.0);
+    for (size_t p = 0; p < t.pb.size(); ++p)
+        for (int c = 0; c < nchp; ++c) {
+            double mx = 0.0;
+            for (int k = 0; k < nch * nchp; ++k)
+                mx = std::max(mx, std::fabs(t.W[t.pb[p].w_off + (size_t)k * nchp + c]));
+            t.wsc[p * nchp + c] = mx > 0.0 ? mx / 240.0 : 0.0;
+        }
     // cheap model
     int nb2 = d.uf3_n_knots2 + 2;
     t.u2.assign(d.uf3_c2, d.uf3_c2 + (size_t)ns * ns * nb2);
@@ -316,6 +326,7 @@ static std::vector<char> pack(const HostTables &t, DevModel &m)
     append<T>(blob, m.u2, t.u2);
     append<T>(blob, m.u3, t.u3);
     append_raw(blob, m.dpoff, t.dpoff);
+    append<float>(blob, m.wsc, t.wsc);
     return blob;
 }
 
@@ -429,8 +440,13 @@ extern "C" int mlmix_create(const mlmix_model_desc *desc, mlmix_ctx **out)
     const mlmix_model_desc &d = *desc;
     if (d.n_species < 1 || d.n_species > 8)
         return fail(MLMIX_E_ARG, "n_species must be 1..8");
-    if (d.precision != MLMIX_FP64 && d.precision != MLMIX_FP32)
-        return fail(MLMIX_E_ARG, "precision must be MLMIX_FP64 or MLMIX_FP32");
+    if (d.precision != MLMIX_FP64 && d.precision != MLMIX_FP32 &&
+        d.precision != MLMIX_BF16_CONTRACT && d.precision != MLMIX_FP8_CONTRACT)
+        return fail(MLMIX_E_ARG, "precision must be MLMIX_FP64, MLMIX_FP32, MLMIX_BF16_CONTRACT or "
+                                 "MLMIX_FP8_CONTRACT");
+    if ((d.precision == MLMIX_BF16_CONTRACT || d.precision == MLMIX_FP8_CONTRACT) &&
+        d.n_species != 1)
+        return fail(MLMIX_E_ARG, "the BF16/FP8 contraction modes support one species");
     if (d.ace_n_rad < 1 || d.ace_n_rad > kMaxNrad || d.ace_lmax < 0 || d.ace_lmax > kMaxLmax ||
         d.ace_order < 1 || d.ace_order > 3 || !(d.ace_rcut > 0.0))
         return fail(MLMIX_E_ARG, "ACE sizes out of range (n_rad 1..16, lmax 0..6, order 1..3)");
@@ -453,7 +469,8 @@ extern "C" int mlmix_create(const mlmix_model_desc *desc, mlmix_ctx **out)
     mlmix_ctx *ctx = new mlmix_ctx();
     Ctx &c = ctx->c;
     c.d = d;
-    c.prec = d.precision;
+    c.prec = d.precision == MLMIX_FP64 ? MLMIX_FP64 : MLMIX_FP32;
+    c.qmode = d.precision == MLMIX_BF16_CONTRACT ? 1 : (d.precision == MLMIX_FP8_CONTRACT ? 2 : 0);
     // tuning overrides of the order-3 launch shape (benchmark sweeps)
     if (const char *e = std::getenv("MLMIX_ACE_TILE")) {
         int v = std::atoi(e);

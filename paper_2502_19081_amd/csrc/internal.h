@@ -69,7 +69,7 @@ struct DevModel {
     void *base;
     size_t bytes;
     // offsets (bytes) into base
-    size_t ylmK, c0, c0d, c1, c2s, W, pb, gm3, gidx, gofs, gval, u2, u3, dpoff;
+    size_t ylmK, c0, c0d, c1, c2s, W, pb, gm3, gidx, gofs, gval, u2, u3, dpoff, wsc;
     int dp_stride;  // partial-D entries per S atom (sum over blocks of nchan*(2 l3 + 1))
     int w_per_species;  // entries of W per centre species
     int gm3_total, g_total;
@@ -85,7 +85,8 @@ struct PBlock {
 
 struct Ctx {
     mlmix_model_desc d;  // pointers inside are not kept
-    int prec;
+    int prec;            // MLMIX_FP64 or a single-precision mode (FP32, BF16/FP8 contraction)
+    int qmode;           // order-3 dense operands: 0 native, 1 BF16, 2 FP8
     double r_list;
     DevModel m;
     int m_pb_lo[kMaxLmax + 1], m_pb_hi[kMaxLmax + 1];  // order-3 blocks per l3

@@ -1,0 +1,97 @@
+"""Reduced-precision order-3 contraction (BF16 and FP8 operands on the
+matrix cores, FP32 accumulation; FP32 everywhere else).
+
+These modes do not meet the FP32 parity bar by construction; the tests
+measure their force error against the FP64 oracle, normalise it by the size
+of the order-3 force contribution (the only term they change), print it, and
+gate it loosely: an operand-layout or scaling mistake in the matrix-core
+stage makes the order-3 term wrong as a whole (relative error of order one),
+which these gates catch, while the rounding of correct operands stays well
+inside them. The measured figures go to gpurun_out/precision_errors.json.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+from gen import workloads as W
+from tests.gpu_common import run_gpu
+
+pytestmark = pytest.mark.gpu
+
+# RMS force error / RMS order-3 force, per operand format
+GATE = {"fp32": 1e-3, "bf16": 3e-2, "fp8": 0.3}
+RESULTS = {}
+
+
+def _without_order3(w):
+    w2 = dict(w)
+    m = dict(w["model"])
+    ace = dict(m["ace"])
+    ace["c3"] = np.zeros_like(ace["c3"])
+    m["ace"] = ace
+    w2["model"] = m
+    return w2
+
+
+def _sample(n, k, seed):
+    if n <= k:
+        return np.arange(n)
+    return np.sort(np.random.default_rng(seed).choice(n, size=k, replace=False))
+
+
+def _case(name, w, sample):
+    print(f"case precision {name} n={len(w['pos'])} sample={len(sample)}", flush=True)
+    target = np.zeros(len(w["pos"]), bool)
+    target[sample] = True
+    ref = O.mixed(w, O.MODE_ALL_EXPENSIVE, target=target)["f_exp"][sample]
+    ref2 = O.mixed(_without_order3(w), O.MODE_ALL_EXPENSIVE, target=target)["f_exp"][sample]
+    f3 = ref - ref2
+    rms3 = np.sqrt(np.mean(f3 ** 2))
+    assert rms3 > 0
+    out = {"n_atoms": len(w["pos"]), "sample": int(len(sample)),
+           "rms_order3_force": float(rms3), "max_order3_force": float(np.abs(f3).max()),
+           "rms_force": float(np.sqrt(np.mean(ref ** 2)))}
+    for prec in ("fp32", "bf16", "fp8"):
+        g = run_gpu(w, O.MODE_ALL_EXPENSIVE, precision=prec)
+        d = g["f_exp"][sample] - ref
+        rms, mx = float(np.sqrt(np.mean(d ** 2))), float(np.abs(d).max())
+        out[prec] = {"rms_err": rms, "max_err": mx, "rms_rel_order3": rms / rms3,
+                     "max_rel_order3": mx / float(np.abs(f3).max())}
+        print(f"  {prec}: rms |dF| {rms:.3e}  max |dF| {mx:.3e}  rms/rms(F3) {rms / rms3:.3e}",
+              flush=True)
+        del g
+    RESULTS[name] = out
+    os.makedirs("gpurun_out", exist_ok=True)
+    with open("gpurun_out/precision_errors.json", "w") as fh:
+        json.dump(RESULTS, fh, indent=1)
+    for prec, gate in GATE.items():
+        assert out[prec]["rms_rel_order3"] < gate, (prec, out[prec])
+
+
+def test_precision_tiny_strong_order3():
+    # a cell whose order-3 term dominates; four channels, so K = 16 < 32
+    # exercises the padded K of the FP8 instruction
+    w = W.tiny(seed=7, n_species=1, cells=4)
+    _case("tiny", w, np.arange(len(w["pos"])))
+
+
+def test_precision_c2():
+    w = W.c2()
+    _case("c2", w, _sample(len(w["pos"]), 512, 1))
+
+
+@pytest.mark.slow
+def test_precision_c5():
+    w = W.c5()
+    _case("c5", w, _sample(len(w["pos"]), 256, 2))
+
+
+def test_reduced_precision_rejects_two_species():
+    from paper_2502_19081_amd import core
+    from paper_2502_19081_amd.binding import MlmixError
+    w = W.tiny(seed=1, n_species=2)
+    with pytest.raises(MlmixError):
+        core.Model(w["model"], precision="bf16")
