@@ -18,8 +18,6 @@
 //                 g_ij = dE_i/dd_ij = sum_{n,lm} dE/dA (R_n' u Y + R_n grad Y),
 //                 recomputing R, Y and grad Y instead of storing them.
 // Forces follow from g in the gather kernel: F_i = sum_j (g_ij - g_ji).
-#include <type_traits>
-
 #include "internal.h"
 #include "basis.h"
 
@@ -35,31 +33,8 @@ struct AceArgs {
     const int *gm3, *gofs;
     int pb_lo[kMaxLmax + 1], pb_hi[kMaxLmax + 1];
     int w_per_species;
-    int qmode;          // order-3 dense operands: 0 FP32, 1 BF16, 2 FP8 (E4M3)
-    const float *wsc;   // FP8 weight scale per (block, output channel)
 };
 
-typedef short v4s __attribute__((ext_vector_type(4)));
-
-// float -> bfloat16, round to nearest even (finite inputs)
-__device__ __forceinline__ short f2bf(float x)
-{
-    unsigned u = __float_as_uint(x);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (short)(u >> 16);
-}
-
-// eight floats (already divided by their scale) -> eight FP8 E4M3 bytes
-__device__ __forceinline__ long pack_fp8(const float v[8])
-{
-    int lo = __builtin_amdgcn_cvt_pk_fp8_f32(v[0], v[1], 0, false);
-    lo = __builtin_amdgcn_cvt_pk_fp8_f32(v[2], v[3], lo, true);
-    int hi = __builtin_amdgcn_cvt_pk_fp8_f32(v[4], v[5], 0, false);
-    hi = __builtin_amdgcn_cvt_pk_fp8_f32(v[6], v[7], hi, true);
-    return (long)(((unsigned long)(unsigned)hi << 32) | (unsigned)lo);
-}
-
-constexpr float kFp8Max = 240.0f;  // largest magnitude mapped (inside both E4M3 variants)
 
 __device__ __forceinline__ void pair_disp_d(const double *__restrict__ pos, int n, int i, int j,
                                             const Box &b, double d[3])
@@ -251,7 +226,6 @@ __global__ void __launch_bounds__(256)
     int *gi = reinterpret_cast<int *>(gv + max_ent);
     int *g3 = gi + max_ent;
     __shared__ int zt[16];
-    __shared__ int pmax[16];  // FP8: |P| maximum per atom of the tile (float bits)
     int cur_tile = -1;
     // contiguous chunk of items per workgroup: consecutive items share a tile
     const int per = (nitems + gridDim.x - 1) / gridDim.x;
@@ -281,8 +255,6 @@ __global__ void __launch_bounds__(256)
         }
         for (int e = tid; e <= d3; e += 256)
             g3[e] = a.gm3[pb.gm3_off + e] - e_lo;
-        if (tid < 16)
-            pmax[tid] = 0;
         const T *Wb = a.W + pb.w_off;  // single-species weights of the block
         if (stage_w) {
             for (int e = tid; e < Kp * nchp; e += 256)
@@ -322,18 +294,12 @@ __global__ void __launch_bounds__(256)
                         // columns nch <= b < nchp are written as zeros
                         if (bc < nchp) {
                             T *Pr = P + (size_t)rr * Ks + bc;
-                            float mx = 0.0f;
 #pragma unroll
                             for (int v = 0; v < 4; ++v) {
                                 const int a2 = at_ * 16 + 4 * kk + v;
-                                if (a2 < nch) {
-                                    T pv = bc < nch ? acc[v] : T(0);
-                                    Pr[a2 * nchp] = pv;
-                                    mx = fmaxf(mx, fabsf((float)pv));
-                                }
+                                if (a2 < nch)
+                                    Pr[a2 * nchp] = bc < nch ? acc[v] : T(0);
                             }
-                            if (a.qmode == 2)
-                                atomicMax(&pmax[t], __float_as_int(mx));  // max of |P|: order-free
                         }
                     }
             }
@@ -385,63 +351,18 @@ __global__ void __launch_bounds__(256)
                 const bool rv = row < nrows, cv = col < nch;
                 const T *Pr = P + (size_t)row * Ks;
                 typename Mfma<T>::v4 acc = {T(0), T(0), T(0), T(0)};
-                T osc[4] = {T(1), T(1), T(1), T(1)};  // output scale per row of this lane
-                if constexpr (std::is_same<T, float>::value) {
-                    if (a.qmode == 1) {
-                        // BF16 operands, FP32 accumulation: K = 16 per instruction
-                        for (int k0 = 0; k0 < Kp; k0 += 16) {
-                            v4s av, bv;
-#pragma unroll
-                            for (int j = 0; j < 4; ++j) {
-                                const int k = k0 + 4 * kk + j;
-                                const bool kv = k < Kp;
-                                av[j] = f2bf((rv && kv) ? Pr[k] : 0.0f);
-                                bv[j] = f2bf((cv && kv) ? Wb[k * nchp + col] : 0.0f);
-                            }
-                            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
-                        }
-                    } else if (a.qmode == 2) {
-                        // FP8 operands: P scaled per atom (shared by its m3 rows), W per
-                        // output channel; K = 32 per instruction
-                        const int ta_row = rv ? row / d3 : 0;
-                        const float sp = __int_as_float(pmax[ta_row]) / kFp8Max;
-                        const float isp = sp > 0.0f ? 1.0f / sp : 0.0f;
-                        const float sw = cv ? a.wsc[p * nchp + col] : 0.0f;
-                        const float isw = sw > 0.0f ? 1.0f / sw : 0.0f;
-                        for (int k0 = 0; k0 < Kp; k0 += 32) {
-                            float va[8], vb[8];
-#pragma unroll
-                            for (int j = 0; j < 8; ++j) {
-                                const int k = k0 + 8 * kk + j;
-                                const bool kv = k < Kp;
-                                va[j] = (rv && kv) ? Pr[k] * isp : 0.0f;
-                                vb[j] = (cv && kv) ? Wb[k * nchp + col] * isw : 0.0f;
-                            }
-                            acc = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(pack_fp8(va), pack_fp8(vb),
-                                                                              acc, 0, 0, 0);
-                        }
-#pragma unroll
-                        for (int v = 0; v < 4; ++v) {
-                            const int r = rt * 16 + 4 * kk + v;
-                            const int tr = r < nrows ? r / d3 : 0;
-                            osc[v] = (__int_as_float(pmax[tr]) / kFp8Max) * sw;
-                        }
-                    }
-                }
-                if (a.qmode == 0) {
-                    for (int k0 = 0; k0 < Kp; k0 += 4) {
-                        int k = k0 + kk;
-                        T av = rv ? Pr[k] : T(0);
-                        T bv = cv ? Wb[k * nchp + col] : T(0);
-                        acc = Mfma<T>::op(av, bv, acc);
-                    }
+                for (int k0 = 0; k0 < Kp; k0 += 4) {
+                    int k = k0 + kk;
+                    T av = rv ? Pr[k] : T(0);
+                    T bv = cv ? Wb[k * nchp + col] : T(0);
+                    acc = Mfma<T>::op(av, bv, acc);
                 }
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     int r = rt * 16 + 4 * kk + v;
                     if (r < nrows && cv) {
                         int t = r / d3, m3 = r - t * d3;
-                        Dbase[(size_t)(s0 + t) * dp_stride + col * d3 + m3] = acc[v] * osc[v];
+                        Dbase[(size_t)(s0 + t) * dp_stride + m3 * nch + col] = acc[v];
                     }
                 }
             }
@@ -466,7 +387,7 @@ __global__ void __launch_bounds__(256)
                 for (int q = 0; q < 4; ++q) {
                     int c = cb * 4 + q;
                     if (c < nch)
-                        Dbase[(size_t)(s0 + t) * dp_stride + c * d3 + m3] = vals[q];
+                        Dbase[(size_t)(s0 + t) * dp_stride + m3 * nch + c] = vals[q];
                 }
             }
         }
@@ -514,7 +435,7 @@ __global__ void __launch_bounds__(256)
         T D3 = T(0);
         if (a.order >= 3)
             for (int p = a.pb_lo[l]; p < a.pb_hi[l]; ++p)
-                D3 += Ds[dp_off[p] + c * (2 * l + 1) + m3];
+                D3 += Ds[dp_off[p] + m3 * nch + c];
         T Av = As[e];
         dEdA[(size_t)s * a.KAt + e] = c1t + T(2) * D2 + T(3) * D3;
         es += (double)(Av * (c1t + D2 + D3));
@@ -630,8 +551,6 @@ static AceArgs<T> make_args(const Ctx &c)
     a.gm3 = reinterpret_cast<const int *>(base + m.gm3);
     a.gofs = reinterpret_cast<const int *>(base + m.gofs);
     a.w_per_species = m.w_per_species;
-    a.qmode = c.qmode;
-    a.wsc = reinterpret_cast<const float *>(base + m.wsc);
     return a;
 }
 
@@ -691,7 +610,9 @@ static void contract_t(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L,
     pb_ranges(c, a.pb_lo, a.pb_hi);
     const int *dp_off = reinterpret_cast<const int *>(static_cast<char *>(c.m.base) + c.m.dpoff);
     T *Dpart = at<T>(ws, L.dpart);
-    if (a.order >= 3 && c.m.n_pb > 0) {
+    if (a.order >= 3 && c.m.n_pb > 0 && c.o3 && sizeof(T) == 4) {
+        launch_ace_o3(s, c, ws, L);
+    } else if (a.order >= 3 && c.m.n_pb > 0) {
         int TA, mf, stage;
         blocks_shape(c, sizeof(T), TA, mf, stage);
         size_t sm = blocks_lds(c, TA, sizeof(T), stage);

@@ -180,7 +180,126 @@ struct HostTables {
     std::vector<int> gm3, gidx, gofs, dpoff;
     int w_per_species = 0;
     int dp_stride = 0;
+    // matrix-core order-3 kernel
+    bool o3 = false;
+    int o3_nch2 = 0;
+    std::vector<double> o3g, o3w, o3sw, o3gs;
+    std::vector<int> o3o, o3mt, o3base, o3order, o3wbeg;
 };
+
+// Tables of the per-wave matrix-core order-3 kernel (single-species models
+// of at most 16 channels in a single-precision mode):
+//  - Gaunt entries of each (block, m3), padded with zero entries to a
+//    multiple of four (one MFMA K step): coefficient and the packed offsets
+//    (l1 m1)*16 | (l2 m2)*16 << 16 of the two A rows in the kernel's
+//    16-channel LDS layout; (start, groups) per (block, m3);
+//  - the block weights as per-lane MFMA fragments: for lane (c = l % 16,
+//    q = l / 16) element f = 4 i + j holds W[a = i][b = 4 q + j][c], stored
+//    [block][i][lane][4] so that a wave loads them as 16-byte rows; in the
+//    FP8 mode divided by the per-(block, c) scale max|W| / 240;
+//  - longest-processing-time assignments of the blocks to 4 G bins (four
+//    waves of each of G workgroups sharing a tile), G = 1, 2, 4, 8;
+//  - per (block, m3) the sum of |g|, for the FP8 row-scale bound.
+static void build_o3(const mlmix_model_desc &d, HostTables &t)
+{
+    const int nch = d.n_species * d.ace_n_rad, lmax = d.ace_lmax;
+    const int nchp = (nch + 3) & ~3;
+    const bool narrow = d.precision == MLMIX_BF16_CONTRACT || d.precision == MLMIX_FP8_CONTRACT;
+    t.o3 = false;
+    if (d.ace_order < 3 || d.n_species != 1 || nch > 16 || t.pb.empty() ||
+        d.precision == MLMIX_FP64)
+        return;
+    const int nch2 = (nch + 1) & ~1;
+    std::vector<int> cost(t.pb.size(), 0);
+    for (size_t p = 0; p < t.pb.size(); ++p) {
+        const PBlock &b = t.pb[p];
+        t.o3base.push_back((int)t.o3mt.size() / 2);
+        for (int m3 = 0; m3 < 2 * b.l3 + 1; ++m3) {
+            int e0 = t.gm3[b.gm3_off + m3], e1 = t.gm3[b.gm3_off + m3 + 1];
+            int n_e = e1 - e0, ng = (n_e + 3) / 4;
+            if (ng > 8)
+                return;  // more than 32 entries in one row: keep the general kernel
+            t.o3mt.push_back((int)t.o3g.size());
+            t.o3mt.push_back(ng);
+            for (int e = e0; e < e0 + 4 * ng; ++e) {
+                if (e < e1) {
+                    int m1 = t.gidx[e] & 0xff, m2 = t.gidx[e] >> 8;
+                    int o1 = (b.l1 * b.l1 + m1) * 16, o2 = (b.l2 * b.l2 + m2) * 16;
+                    t.o3o.push_back(o1 | (o2 << 16));
+                    t.o3g.push_back(t.gval[e]);
+                } else {
+                    t.o3o.push_back(0);
+                    t.o3g.push_back(0.0);
+                }
+            }
+            // MFMA steps per row tile: sparse 16 rows x groups, dense in
+            // units of a 16x16x4 FP32 step (narrow operands are 8x cheaper)
+            cost[p] += 16 * ng + (narrow ? std::max(1, nch2 / 8) : 4 * nch2) + 4;
+        }
+    }
+    (void)lmax;
+    // weight fragments (and FP8 column scales)
+    const size_t P = t.pb.size();
+    t.o3sw.assign(P * 16, 1.0);
+    if (d.precision == MLMIX_FP8_CONTRACT)
+        for (size_t p = 0; p < P; ++p)
+            for (int c = 0; c < 16; ++c)
+                t.o3sw[p * 16 + c] = c < nch ? t.wsc[p * nchp + c] : 0.0;
+    t.o3w.assign(P * nch2 * 64 * 4, 0.0);
+    for (size_t p = 0; p < P; ++p)
+        for (int i = 0; i < nch2; ++i)
+            for (int l = 0; l < 64; ++l)
+                for (int j = 0; j < 4; ++j) {
+                    int c = l & 15, q = l >> 4, a = i, b = 4 * q + j;
+                    double v = 0.0;
+                    if (a < nch && b < nch && c < nch) {
+                        v = t.W[t.pb[p].w_off + ((size_t)a * nchp + b) * nchp + c];
+                        if (d.precision == MLMIX_FP8_CONTRACT) {
+                            double sw = t.o3sw[p * 16 + c];
+                            v = sw > 0.0 ? v / sw : 0.0;
+                        }
+                    }
+                    t.o3w[(((p * nch2) + i) * 64 + l) * 4 + j] = v;
+                }
+    // blocks to waves, for a tile's block list split over G = 1, 2, 4, 8
+    // workgroups (4 G bins; longest first onto the least loaded bin)
+    std::vector<int> idx(P);
+    for (size_t p = 0; p < P; ++p)
+        idx[p] = (int)p;
+    std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+    t.o3order.clear();
+    t.o3wbeg.clear();
+    for (int G = 1; G <= kO3MaxSplit; G <<= 1) {
+        const int nb = 4 * G;
+        std::vector<std::vector<int>> lists(nb);
+        std::vector<long> load(nb, 0);
+        for (int p : idx) {
+            int w = 0;
+            for (int k = 1; k < nb; ++k)
+                if (load[k] < load[w])
+                    w = k;
+            lists[w].push_back(p);
+            load[w] += cost[p];
+        }
+        const int base = (int)t.o3order.size();
+        for (int w = 0; w < nb; ++w) {
+            t.o3wbeg.push_back((int)t.o3order.size() - base);
+            std::sort(lists[w].begin(), lists[w].end());
+            t.o3order.insert(t.o3order.end(), lists[w].begin(), lists[w].end());
+        }
+        t.o3wbeg.push_back((int)t.o3order.size() - base);
+    }
+    // FP8 row-scale bound: sum of |g| over the row's entries
+    t.o3gs.clear();
+    for (size_t r = 0; r < t.o3mt.size() / 2; ++r) {
+        double gs = 0.0;
+        for (int e = t.o3mt[2 * r]; e < t.o3mt[2 * r] + 4 * t.o3mt[2 * r + 1]; ++e)
+            gs += std::fabs(t.o3g[e]);
+        t.o3gs.push_back(gs);
+    }
+    t.o3_nch2 = nch2;
+    t.o3 = true;
+}
 
 static int build_tables(const mlmix_model_desc &d, HostTables &t)
 {
@@ -267,6 +386,7 @@ static int build_tables(const mlmix_model_desc &d, HostTables &t)
                 mx = std::max(mx, std::fabs(t.W[t.pb[p].w_off + (size_t)k * nchp + c]));
             t.wsc[p * nchp + c] = mx > 0.0 ? mx / 240.0 : 0.0;
         }
+    build_o3(d, t);
     // cheap model
     int nb2 = d.uf3_n_knots2 + 2;
     t.u2.assign(d.uf3_c2, d.uf3_c2 + (size_t)ns * ns * nb2);
@@ -327,6 +447,15 @@ static std::vector<char> pack(const HostTables &t, DevModel &m)
     append<T>(blob, m.u3, t.u3);
     append_raw(blob, m.dpoff, t.dpoff);
     append<float>(blob, m.wsc, t.wsc);
+    append<float>(blob, m.o3g, t.o3g);
+    append_raw(blob, m.o3o, t.o3o);
+    append_raw(blob, m.o3mt, t.o3mt);
+    append_raw(blob, m.o3base, t.o3base);
+    append<float>(blob, m.o3w, t.o3w);
+    append<float>(blob, m.o3sw, t.o3sw);
+    append_raw(blob, m.o3order, t.o3order);
+    append_raw(blob, m.o3wbeg, t.o3wbeg);
+    append<float>(blob, m.o3gs, t.o3gs);
     return blob;
 }
 
@@ -523,7 +652,7 @@ extern "C" int mlmix_create(const mlmix_model_desc *desc, mlmix_ctx **out)
         // Operation counts of the kernels as written (a multiply-add counts
         // two, a division or square root one).
         double KA = m.KA, nr = m.nrad, L2d = L2;
-        double con = 4.0 * nch;
+        double con = 4.0 * nch, dense = 0.0;
         if (d.ace_order >= 2)
             con += KA * (2.0 * nch + 4.0);
         if (d.ace_order >= 3) {
@@ -531,6 +660,7 @@ extern "C" int mlmix_create(const mlmix_model_desc *desc, mlmix_ctx **out)
             for (const PBlock &p : t.pb) {
                 int nnz = t.gm3[p.gm3_off + 2 * p.l3 + 1] - t.gm3[p.gm3_off];
                 con += 3.0 * nab * nnz + 2.0 * nab * nch * (2 * p.l3 + 1);
+                dense += 2.0 * nab * nch * (2 * p.l3 + 1);
             }
             for (int l = 0; l <= d.ace_lmax; ++l)
                 if (c.m_pb_hi[l] > c.m_pb_lo[l])
@@ -541,7 +671,7 @@ extern "C" int mlmix_create(const mlmix_model_desc *desc, mlmix_ctx **out)
         ctx->flops[2] = 31.0 + 10.0 * nr + L2d * (4.0 * nr + 24.0);     // pair adjoint, per pair
         ctx->flops[3] = 96.0;                                 // cheap 2-body, per pair
         ctx->flops[4] = 495.0;                                // cheap 3-body, per ordered leg pair
-        ctx->flops[5] = 0.0;
+        ctx->flops[5] = dense;                                // dense order-3 stage, per S atom
     }
     c.max_ent = 0;
     c.max_gm3 = 0;
@@ -556,6 +686,16 @@ extern "C" int mlmix_create(const mlmix_model_desc *desc, mlmix_ctx **out)
         int g_lo = f.gm3_off, g_hi = la.gm3_off + 2 * l + 2;
         c.max_gm3 = std::max(c.max_gm3, g_hi - g_lo);
         c.max_ent = std::max(c.max_ent, t.gm3[g_hi - 1] - t.gm3[g_lo]);
+    }
+    c.o3 = t.o3 ? 1 : 0;
+    c.o3_nch2 = t.o3_nch2;
+    if (const char *e = std::getenv("MLMIX_ACE_O3"))
+        if (!std::atoi(e))
+            c.o3 = 0;  // general block kernel (comparisons)
+    if (c.qmode != 0 && !c.o3) {
+        delete ctx;
+        return fail(MLMIX_E_ARG, "the BF16/FP8 contraction modes need a single-species model "
+                                 "with at most 16 radial channels and correlation order 3");
     }
     std::vector<char> blob = c.prec == MLMIX_FP64 ? pack<double>(t, m) : pack<float>(t, m);
     m.bytes = blob.size();

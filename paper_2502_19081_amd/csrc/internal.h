@@ -17,6 +17,7 @@ constexpr int kMaxCap = 256;
 constexpr int kMaxTriplet = 64;   // neighbours inside the 3-body cutoff per centre
 constexpr int kScanTile = 2048;   // elements per block in the device scans
 constexpr int kReduceBlocks = 256;
+constexpr int kO3MaxSplit = 8;    // workgroups sharing one 16-atom tile of the order-3 kernel
 
 // Header words at the start of every workspace (int32 unless noted).
 enum HeaderWord {
@@ -70,6 +71,8 @@ struct DevModel {
     size_t bytes;
     // offsets (bytes) into base
     size_t ylmK, c0, c0d, c1, c2s, W, pb, gm3, gidx, gofs, gval, u2, u3, dpoff, wsc;
+    // tables of the matrix-core order-3 kernel (single species, <= 16 channels)
+    size_t o3g, o3o, o3mt, o3base, o3w, o3sw, o3order, o3wbeg, o3gs;
     int dp_stride;  // partial-D entries per S atom (sum over blocks of nchan*(2 l3 + 1))
     int w_per_species;  // entries of W per centre species
     int gm3_total, g_total;
@@ -92,6 +95,8 @@ struct Ctx {
     int m_pb_lo[kMaxLmax + 1], m_pb_hi[kMaxLmax + 1];  // order-3 blocks per l3
     int max_ent, max_gm3;  // Gaunt entries / m3 offsets of the largest l3 group
     int max_ent_pb;        // Gaunt entries of the largest single block
+    int o3 = 0;            // order-3 contraction on the per-wave matrix-core kernel
+    int o3_nch2 = 0;       // channels rounded up to even (row width of that kernel)
     int ace_tile = 4;      // atoms per order-3 block workgroup (tuning)
     int ace_stage_w = 1;   // stage the block's weights in LDS (tuning)
     int device;
@@ -124,6 +129,10 @@ void launch_ace_contract(hipStream_t s, const Ctx &c, void *ws, const WsLayout &
                          const int32_t *species, double *e_exp);
 void launch_ace_pairgrad(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L, const Box &b,
                          const double *pos, const int32_t *species, const double *weights);
+
+// ---- o3.hip ----
+void launch_ace_o3(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L);
+size_t o3_lds_bytes(const Ctx &c);
 
 // ---- uf3.hip ----
 void launch_uf3(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L, const Box &b,

@@ -85,8 +85,9 @@ def test_precision_c2():
 
 @pytest.mark.slow
 def test_precision_c5():
+    # the ~4,000 atoms of a 40 A cube around the first vacancy
     w = W.c5()
-    _case("c5", w, _sample(len(w["pos"]), 256, 2))
+    _case("c5", w, W.subvolume(w, w["vacancy_centres"][0], 40.0))
 
 
 def test_reduced_precision_rejects_two_species():
