@@ -190,9 +190,10 @@ struct HostTables {
 // Tables of the per-wave matrix-core order-3 kernel (single-species models
 // of at most 16 channels in a single-precision mode):
 //  - Gaunt entries of each (block, m3), padded with zero entries to a
-//    multiple of four (one MFMA K step): coefficient and the packed offsets
+//    multiple of four (one MFMA K step), as pairs (packed offsets
 //    (l1 m1)*16 | (l2 m2)*16 << 16 of the two A rows in the kernel's
-//    16-channel LDS layout; (start, groups) per (block, m3);
+//    16-channel LDS layout, FP32 bits of the coefficient); (first entry,
+//    groups) per (block, m3);
 //  - the block weights as per-lane MFMA fragments: for lane (c = l % 16,
 //    q = l / 16) element f = 4 i + j holds W[a = i][b = 4 q + j][c], stored
 //    [block][i][lane][4] so that a wave loads them as 16-byte rows; in the
@@ -209,7 +210,7 @@ static void build_o3(const mlmix_model_desc &d, HostTables &t)
     if (d.ace_order < 3 || d.n_species != 1 || nch > 16 || t.pb.empty() ||
         d.precision == MLMIX_FP64)
         return;
-    const int nch2 = (nch + 1) & ~1;
+    const int nch2 = nchp;  // row width of the kernel: channels rounded up to 4
     std::vector<int> cost(t.pb.size(), 0);
     for (size_t p = 0; p < t.pb.size(); ++p) {
         const PBlock &b = t.pb[p];
@@ -219,18 +220,22 @@ static void build_o3(const mlmix_model_desc &d, HostTables &t)
             int n_e = e1 - e0, ng = (n_e + 3) / 4;
             if (ng > 8)
                 return;  // more than 32 entries in one row: keep the general kernel
-            t.o3mt.push_back((int)t.o3g.size());
+            t.o3mt.push_back((int)t.o3g.size());  // entry index (pairs in o3o)
             t.o3mt.push_back(ng);
             for (int e = e0; e < e0 + 4 * ng; ++e) {
+                int o = 0;
+                float g = 0.0f;
                 if (e < e1) {
                     int m1 = t.gidx[e] & 0xff, m2 = t.gidx[e] >> 8;
                     int o1 = (b.l1 * b.l1 + m1) * 16, o2 = (b.l2 * b.l2 + m2) * 16;
-                    t.o3o.push_back(o1 | (o2 << 16));
-                    t.o3g.push_back(t.gval[e]);
-                } else {
-                    t.o3o.push_back(0);
-                    t.o3g.push_back(0.0);
+                    o = o1 | (o2 << 16);
+                    g = (float)t.gval[e];
                 }
+                int gbits;
+                std::memcpy(&gbits, &g, sizeof(int));
+                t.o3o.push_back(o);
+                t.o3o.push_back(gbits);
+                t.o3g.push_back(g);
             }
             // MFMA steps per row tile: sparse 16 rows x groups, dense in
             // units of a 16x16x4 FP32 step (narrow operands are 8x cheaper)
@@ -447,7 +452,6 @@ static std::vector<char> pack(const HostTables &t, DevModel &m)
     append<T>(blob, m.u3, t.u3);
     append_raw(blob, m.dpoff, t.dpoff);
     append<float>(blob, m.wsc, t.wsc);
-    append<float>(blob, m.o3g, t.o3g);
     append_raw(blob, m.o3o, t.o3o);
     append_raw(blob, m.o3mt, t.o3mt);
     append_raw(blob, m.o3base, t.o3base);

@@ -72,7 +72,7 @@ struct DevModel {
     // offsets (bytes) into base
     size_t ylmK, c0, c0d, c1, c2s, W, pb, gm3, gidx, gofs, gval, u2, u3, dpoff, wsc;
     // tables of the matrix-core order-3 kernel (single species, <= 16 channels)
-    size_t o3g, o3o, o3mt, o3base, o3w, o3sw, o3order, o3wbeg, o3gs;
+    size_t o3o, o3mt, o3base, o3w, o3sw, o3order, o3wbeg, o3gs;
     int dp_stride;  // partial-D entries per S atom (sum over blocks of nchan*(2 l3 + 1))
     int w_per_species;  // entries of W per centre species
     int gm3_total, g_total;
@@ -96,7 +96,7 @@ struct Ctx {
     int max_ent, max_gm3;  // Gaunt entries / m3 offsets of the largest l3 group
     int max_ent_pb;        // Gaunt entries of the largest single block
     int o3 = 0;            // order-3 contraction on the per-wave matrix-core kernel
-    int o3_nch2 = 0;       // channels rounded up to even (row width of that kernel)
+    int o3_nch2 = 0;       // row width of that kernel (channels rounded up to 4)
     int ace_tile = 4;      // atoms per order-3 block workgroup (tuning)
     int ace_stage_w = 1;   // stage the block's weights in LDS (tuning)
     int device;
