@@ -243,6 +243,11 @@ static void build_o3(const mlmix_model_desc &d, HostTables &t)
         }
     }
     (void)lmax;
+    // the kernel reads eight groups of every row: pad past the end
+    for (int e = 0; e < 32; ++e) {
+        t.o3o.push_back(0);
+        t.o3o.push_back(0);
+    }
     // weight fragments (and FP8 column scales)
     const size_t P = t.pb.size();
     t.o3sw.assign(P * 16, 1.0);

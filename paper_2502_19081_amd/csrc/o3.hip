@@ -74,18 +74,70 @@ __device__ __forceinline__ void wave_sync_lds()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// this lane's (offsets, coefficient) of the four-entry groups of one row
-__device__ __forceinline__ void o3_load_row(const int *__restrict__ e, int e0, int q, int ng,
-                                            int (&oe)[kO3MaxGroups], float (&ge)[kO3MaxGroups])
+// this lane's (offsets, coefficient) of the four-entry groups of one row;
+// all eight groups are read (the table is padded past its end), so the loads
+// stay in flight while the previous row is computed
+__device__ __forceinline__ void o3_load_row(const int *__restrict__ e, int e0, int q,
+                                            int2 (&ent)[kO3MaxGroups])
 {
     const int2 *src = reinterpret_cast<const int2 *>(e) + e0 + q;
 #pragma unroll
     for (int k = 0; k < kO3MaxGroups; ++k)
-        if (k < ng) {
-            const int2 v = src[4 * k];
-            oe[k] = v.x;
-            ge[k] = __int_as_float(v.y);
+        ent[k] = src[4 * k];
+}
+
+// Sparse stage of one row for the 16 atoms with NG entry groups (unrolled):
+// P_t[a = m][b = 4 q + v] accumulates on the matrix cores and is written to
+// the wave's P rows in the operand format.
+template <int QM, int NC, int NG>
+__device__ __forceinline__ void o3_sparse(const float *__restrict__ At, int L2, int L1, int m,
+                                          int q, int lane, const int2 (&ent)[kO3MaxGroups],
+                                          char *Pw, float *sP, const float *amax, int l1, int l2,
+                                          float gsum)
+{
+    constexpr int rowb = o3_row_bytes(QM, NC);
+    for (int t = 0; t < kO3Atoms; t += 4) {
+        const float *A0 = At + (size_t)t * L2 * 16 + m;
+        f4v c[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            c[u] = (f4v){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int k = 0; k < NG; ++k) {
+            const int o1 = ent[k].x & 0xffff, o2 = ent[k].x >> 16;
+            const float g = __int_as_float(ent[k].y);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const float *Au = A0 + u * L2 * 16;
+                c[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(Au[o2], g * Au[o1], c[u], 0, 0, 0);
+            }
         }
+        // lane holds P[a = m][b = 4 q + v]; chunk (b / 4 = q, a = m)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const f4v cv = c[u];
+            char *dst = Pw + (size_t)(t + u) * rowb;
+            if constexpr (QM == 0) {
+                if (m < NC)
+                    *reinterpret_cast<f4v *>(dst + (q * NC + m) * 16) = cv;
+            } else if constexpr (QM == 1) {
+                const bf2v p0 = __builtin_convertvector((f2v){cv[0], cv[1]}, bf2v);
+                const bf2v p1 = __builtin_convertvector((f2v){cv[2], cv[3]}, bf2v);
+                if (m < NC)
+                    *reinterpret_cast<bf4v *>(dst + (q * NC + m) * 8) = (bf4v){p0[0], p0[1], p1[0], p1[1]};
+            } else {
+                const float *am = amax + (t + u) * L1;
+                const float sc = gsum * am[l1] * am[l2];  // >= max|P| / 240
+                const float inv = sc > 0.0f ? 1.0f / sc : 0.0f;
+                int pk = __builtin_amdgcn_cvt_pk_fp8_f32(cv[0] * inv, cv[1] * inv, 0, false);
+                pk = __builtin_amdgcn_cvt_pk_fp8_f32(cv[2] * inv, cv[3] * inv, pk, true);
+                if (m < NC)
+                    *reinterpret_cast<int *>(dst + (q * NC + m) * 4) = pk;
+                if (lane == 0)
+                    sP[t + u] = sc;
+            }
+        }
+    }
 }
 
 template <int QM, int NC>
@@ -186,63 +238,32 @@ __global__ void __launch_bounds__(256, 1)
             float *Dblk = Dpart + a.dp_off[p];
 
             // entries of the first row; each row prefetches the next one's
-            int oe[kO3MaxGroups], oe_n[kO3MaxGroups];
-            float ge[kO3MaxGroups], ge_n[kO3MaxGroups];
+            int2 ent[kO3MaxGroups], ent_n[kO3MaxGroups];
             int e0 = a.mt[2 * rbase], ng = a.mt[2 * rbase + 1];
-            o3_load_row(a.e, e0, q, ng, oe, ge);
+            o3_load_row(a.e, e0, q, ent);
             for (int m3 = 0; m3 < d3; ++m3) {
                 const int row = rbase + m3;
-                int e0n = 0, ngn = 0;
+                int ngn = 0;
                 if (m3 + 1 < d3) {
-                    e0n = a.mt[2 * row + 2];
                     ngn = a.mt[2 * row + 3];
-                    o3_load_row(a.e, e0n, q, ngn, oe_n, ge_n);
+                    o3_load_row(a.e, a.mt[2 * row + 2], q, ent_n);
                 }
                 const float gsum = QM == 2 ? a.gs[row] * (1.0f / 240.0f) : 0.0f;
                 // ---- sparse stage: P_t for the 16 atoms, four at a time
-                for (int t = 0; t < kO3Atoms; t += 4) {
-                    const float *A0 = At + (size_t)t * L2 * 16 + m;
-                    f4v c[4];
-#pragma unroll
-                    for (int u = 0; u < 4; ++u)
-                        c[u] = (f4v){0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                    for (int k = 0; k < kO3MaxGroups; ++k)
-                        if (k < ng) {
-                            const int o1 = oe[k] & 0xffff, o2 = oe[k] >> 16;
-#pragma unroll
-                            for (int u = 0; u < 4; ++u) {
-                                const float *Au = A0 + u * L2 * 16;
-                                c[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(Au[o2], ge[k] * Au[o1], c[u], 0, 0, 0);
-                            }
-                        }
-                    // lane holds P[a = m][b = 4 q + v]; chunk (b / 4 = q, a = m)
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const f4v cv = c[u];
-                        char *dst = Pw + (size_t)(t + u) * rowb;
-                        if constexpr (QM == 0) {
-                            if (m < NC)
-                                *reinterpret_cast<f4v *>(dst + (q * NC + m) * 16) = cv;
-                        } else if constexpr (QM == 1) {
-                            const bf2v p0 = __builtin_convertvector((f2v){cv[0], cv[1]}, bf2v);
-                            const bf2v p1 = __builtin_convertvector((f2v){cv[2], cv[3]}, bf2v);
-                            if (m < NC)
-                                *reinterpret_cast<bf4v *>(dst + (q * NC + m) * 8) =
-                                    (bf4v){p0[0], p0[1], p1[0], p1[1]};
-                        } else {
-                            const float *am = amax + (t + u) * L1;
-                            const float sc = gsum * am[pbk.l1] * am[pbk.l2];  // >= max|P| / 240
-                            const float inv = sc > 0.0f ? 1.0f / sc : 0.0f;
-                            int pk = __builtin_amdgcn_cvt_pk_fp8_f32(cv[0] * inv, cv[1] * inv, 0, false);
-                            pk = __builtin_amdgcn_cvt_pk_fp8_f32(cv[2] * inv, cv[3] * inv, pk, true);
-                            if (m < NC)
-                                *reinterpret_cast<int *>(dst + (q * NC + m) * 4) = pk;
-                            if (lane == 0)
-                                sP[t + u] = sc;
-                        }
-                    }
+#define O3_SPARSE(NGV)                                                                        \
+    o3_sparse<QM, NC, NGV>(At, L2, L1, m, q, lane, ent, Pw, sP, amax, pbk.l1, pbk.l2, gsum)
+                switch (ng) {
+                case 0: O3_SPARSE(0); break;
+                case 1: O3_SPARSE(1); break;
+                case 2: O3_SPARSE(2); break;
+                case 3: O3_SPARSE(3); break;
+                case 4: O3_SPARSE(4); break;
+                case 5: O3_SPARSE(5); break;
+                case 6: O3_SPARSE(6); break;
+                case 7: O3_SPARSE(7); break;
+                default: O3_SPARSE(8); break;
                 }
+#undef O3_SPARSE
                 wave_sync_lds();
                 // ---- dense stage: D[atom m-row][c] over the 16 atoms
                 f4v acc = {0.f, 0.f, 0.f, 0.f};
@@ -281,11 +302,8 @@ __global__ void __launch_bounds__(256, 1)
                 }
                 wave_sync_lds();  // P rows and scales are rewritten by the next m3
 #pragma unroll
-                for (int k = 0; k < kO3MaxGroups; ++k) {
-                    oe[k] = oe_n[k];
-                    ge[k] = ge_n[k];
-                }
-                e0 = e0n;
+                for (int k = 0; k < kO3MaxGroups; ++k)
+                    ent[k] = ent_n[k];
                 ng = ngn;
             }
         }
