@@ -51,7 +51,52 @@ def parse():
     ap.add_argument("--precision", default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--only-mixed", action="store_true",
+                    help="time the mixed step only (no all-expensive / all-cheap / latency runs); "
+                         "used under a profiler so that every traced launch is a mixed-mode one")
+    ap.add_argument("--probe", choices=["copy"], default=None,
+                    help="copy: a plain 256 MiB device-to-device copy, 20 times (calibration of "
+                         "the HBM byte counters)")
     return ap.parse_args()
+
+
+def copy_probe():
+    """A plain copy kernel of known size: reads and writes 256 MiB per launch."""
+    import torch
+    n = 64 << 20
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(20):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"probe": "copy", "bytes_read_per_launch": 4 * n,
+                      "bytes_written_per_launch": 4 * n, "launches": 20}))
+
+
+KERNEL_SOURCES = {"ace_contract": ["paper_2502_19081_amd/csrc/o3.hip", "paper_2502_19081_amd/csrc/internal.h"]}
+
+
+def measured_traffic(stage, cfg, prec):
+    """HBM bytes per launch of a stage's kernel from the committed counter
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by the plain-copy calibration),
+    or None when there is none or the kernel source changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{stage}_{cfg}_{prec}_traffic.txt")
+    if not os.path.exists(path) or stage not in KERNEL_SOURCES:
+        return None
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[stage]:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    if kv.get("source_sha256") != h.hexdigest():
+        return None
+    return float(kv["traffic_bytes_per_launch"])
 
 
 def make_workload(name):
@@ -86,6 +131,9 @@ def pair_counts(w, nbr, cnt, S_mask):
 
 def main():
     args = parse()
+    if args.probe == "copy":
+        copy_probe()
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
                           "(the multi-GPU design is described in DESIGN.md)"}))
@@ -182,17 +230,19 @@ def main():
     print(f"bench: mixed {ms_step:.4f} ms/step", file=sys.stderr, flush=True)
 
     # 4. all-expensive and all-cheap rates on the same GPU, same method
-    el_e, _, _, _ = run(B.MODE_ALL_EXPENSIVE, args.steps, args.warmup, graph=True)
-    el_c, _, _, _ = run(B.MODE_ALL_CHEAP, args.steps, args.warmup, graph=True)
-    rate_e = n * args.steps / el_e
-    rate_c = n * args.steps / el_c
+    rate_e = rate_c = None
+    lat_ms = None
+    if not args.only_mixed:
+        el_e, _, _, _ = run(B.MODE_ALL_EXPENSIVE, args.steps, args.warmup, graph=True)
+        el_c, _, _, _ = run(B.MODE_ALL_CHEAP, args.steps, args.warmup, graph=True)
+        rate_e = n * args.steps / el_e
+        rate_c = n * args.steps / el_c
+        print(f"bench: all-expensive {1e3 * el_e / args.steps:.4f} ms/step, all-cheap "
+              f"{1e3 * el_c / args.steps:.4f} ms/step", file=sys.stderr, flush=True)
 
-    print(f"bench: all-expensive {1e3 * el_e / args.steps:.4f} ms/step, all-cheap "
-          f"{1e3 * el_c / args.steps:.4f} ms/step", file=sys.stderr, flush=True)
-
-    # 5. step latency (each replay waited for)
-    _, _, lat, _ = run(B.MODE_MIXED, args.steps, 5, latency=True, graph=True)
-    lat_ms = np.array(lat) * 1e3
+        # 5. step latency (each replay waited for)
+        _, _, lat, _ = run(B.MODE_MIXED, args.steps, 5, latency=True, graph=True)
+        lat_ms = np.array(lat) * 1e3
 
     # work counts of the initial configuration (for the roofline)
     sy, pos, vel, sp = fresh(B.MODE_MIXED)
@@ -210,9 +260,16 @@ def main():
     gpu_forces = out["forces"].cpu().numpy().T.copy()
 
     tsz = 8 if prec == "fp64" else 4
+    mw = w["model"]["ace"]
+    nch = mw["n_rad"] * w["model"]["n_species"]
+    KAt = (mw["lmax"] + 1) ** 2 * ((nch + 3) // 4 * 4)
+    dp_stride = nch * sum(2 * l3 + 1 for l1 in range(mw["lmax"] + 1) for l2 in range(l1, mw["lmax"] + 1)
+                          for l3 in range(l2 - l1, min(mw["lmax"], l1 + l2) + 1)
+                          if (l1 + l2 + l3) % 2 == 0) if mw["order"] >= 3 else 0
     work = {
         # flops per launch
         "ace_contract": ("flops", fl[0] * nS),
+        "ace_finalize": ("bytes", nS * (2 * KAt * tsz + dp_stride * tsz + 16)),
         "ace_basis": ("flops", fl[1] * pc["exp_pairs"]),
         "ace_pairgrad": ("flops", fl[2] * pc["exp_pairs"]),
         "uf3": ("flops", fl[3] * pc["cheap_pairs"] + fl[4] * pc["cheap_triplets"]),
@@ -225,6 +282,7 @@ def main():
         "integrator": ("bytes", 2 * 88 * n),
         "energy_sums": ("bytes", 48 * n),
     }
+    traffic = measured_traffic(dominant, cfg, prec)
     kind, units = work[dominant]
     if kind == "flops":
         bound = "alu"
@@ -238,12 +296,12 @@ def main():
             peak = units / ((units - dense) / MFMA_TFLOPS["fp32"] + dense / MFMA_TFLOPS[prec])
         achieved = units / (dom_avg_ms * 1e-3) / 1e12
         roof = {"bound": bound, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                "frac": achieved / peak, "traffic": None, "kernel": dominant,
+                "frac": achieved / peak, "traffic": traffic, "kernel": dominant,
                 "avg_ms": dom_avg_ms, "launches": dom_cnt, "algorithmic_per_launch": units}
     else:
         achieved = units / (dom_avg_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": dominant,
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": dominant,
                 "avg_ms": dom_avg_ms, "launches": dom_cnt, "algorithmic_per_launch": units}
 
     # 6. CPU baseline: the FP64 reference on this host, bounded sample of the
@@ -283,8 +341,10 @@ def main():
                "sample": f"{n_cpu} velocity-Verlet steps of the same {cfg} workload in mixed mode "
                          f"(plus one initial force call), FP64, neighbour list rebuilt every step"}
 
-    S_CE = rate_c / rate_e
-    s_ul = n * S_CE / (nS * S_CE + n)
+    s_ul = None
+    if rate_e:
+        S_CE = rate_c / rate_e
+        s_ul = n * S_CE / (nS * S_CE + n)
     res = {
         "metric": "mixed atom-steps/s vs all-expensive at stated force error; p99 step latency",
         "value": value, "unit": "atom-steps/s", "n_gpus": 1, "steps": args.steps,
@@ -297,11 +357,11 @@ def main():
         "eager_atom_steps_per_s": n * args.steps / el_eager,
         "all_expensive_atom_steps_per_s": rate_e,
         "all_cheap_atom_steps_per_s": rate_c,
-        "mixed_over_all_expensive": value / rate_e,
+        "mixed_over_all_expensive": value / rate_e if rate_e else None,
         "S_UL": s_ul,
         "force_err_max_eV_per_A": ferr,
-        "p50_step_ms": float(np.percentile(lat_ms, 50)),
-        "p99_step_ms": float(np.percentile(lat_ms, 99)),
+        "p50_step_ms": float(np.percentile(lat_ms, 50)) if lat_ms is not None else None,
+        "p99_step_ms": float(np.percentile(lat_ms, 99)) if lat_ms is not None else None,
         "stage_ms_per_step": {k: round(v, 5) for k, v in stage_ms.items()},
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -74,6 +74,13 @@ extern "C" {
 #define MLMIX_MODE_ALL_CHEAP 2      /* lambda = 0, S empty, expensive skipped */
 #define MLMIX_FORCE_REBUILD 0x100u  /* rebuild the neighbour list now */
 #define MLMIX_ENERGY_ONLY 0x200u    /* stop after the expensive site energies */
+/* Run every stage on the caller's stream (no fork onto the workspace's
+ * second stream). For callers that already overlap several evaluations on
+ * streams of their own, in particular inside a graph capture whose streams
+ * are themselves forked off the capture's origin stream: such a capture
+ * with the library's fork nested inside ended in a crash of the runtime's
+ * capture end, so this path keeps such captures one level deep. */
+#define MLMIX_SINGLE_STREAM 0x400u
 
 /* Device status bits reported by mlmix_status(). */
 #define MLMIX_STATUS_NEIGH_OVERFLOW 1
@@ -161,7 +168,14 @@ int mlmix_workspace_size(const mlmix_ctx *ctx, int32_t n_atoms, int32_t nbr_cap,
 
 /* Clears the workspace header (status, neighbour-list state) on `stream`.
  * Must be called once before the first mlmix_compute on a workspace and
- * again whenever n_atoms, nbr_cap or the box size changes. */
+ * again whenever n_atoms, nbr_cap or the box size changes.
+ * Second stream: an evaluation without MLMIX_SINGLE_STREAM forks the reverse
+ * slots and the cheap potential onto the workspace's second stream and joins
+ * back on the caller's stream before returning, so calls stay ordered on
+ * `stream` and capturable in a HIP graph. The first such evaluation outside
+ * a graph capture creates that stream (default priority, owned by the
+ * context, destroyed by mlmix_destroy); until then evaluations run on the
+ * caller's stream alone. Calls on one workspace must not overlap. */
 int mlmix_workspace_init(mlmix_ctx *ctx, void *stream, void *ws, size_t ws_bytes,
                          int32_t n_atoms, int32_t nbr_cap, const mlmix_box *box);
 
@@ -232,20 +246,23 @@ int mlmix_get_index_sets(mlmix_ctx *ctx, void *stream, void *ws, int32_t n_atoms
 /* Stage timing for benchmarks. Stages (bit i of the mask, name from
  * mlmix_profile_stage_name(i)): 0 neighbours (cells, rows, reverse slots),
  * 1 regions (lambda, masks, buffer), 2 compaction, 3 expensive atomic basis,
- * 4 expensive contraction + dE/dA, 5 expensive pair adjoint, 6 cheap
- * potential, 7 gather + blend, 8 integrator, 9 energy sums.
+ * 4 expensive order-3 contraction, 5 expensive site energy and dE/dA
+ * (orders 1-2, sum of the order-3 blocks), 6 expensive pair adjoint, 7 cheap
+ * potential, 8 gather + blend, 9 integrator, 10 energy sums, 11 reverse
+ * slots of a rebuilt list. Stages 7 and 11 run on the workspace's second
+ * stream, beside stages 1-6.
  * mlmix_profile_enable(ctx, mask) brackets each selected stage of later
  * calls with HIP events recorded on the caller's stream (no host wait);
  * mlmix_profile_read() waits for those events and returns, per stage, the
  * summed milliseconds and the number of bracketed launches since the last
  * read (arrays of MLMIX_N_STAGES entries). */
-#define MLMIX_N_STAGES 10
+#define MLMIX_N_STAGES 12
 int mlmix_profile_enable(mlmix_ctx *ctx, uint32_t stage_mask);
 int mlmix_profile_read(mlmix_ctx *ctx, double *ms, int64_t *count);
 const char *mlmix_profile_stage_name(int32_t stage);
 
 /* Operation counts of the kernels as written, for roofline reporting
- * (out[6]): [0] expensive contraction + dE/dA per S atom, [1] atomic basis
+ * (out[6]): [0] expensive order-3 contraction per S atom, [1] atomic basis
  * per expensive pair, [2] pair adjoint per expensive pair, [3] cheap 2-body
  * per pair, [4] cheap 3-body per ordered pair of legs, [5] the part of [0]
  * spent in the dense order-3 stage (the stage whose operands the BF16/FP8

@@ -18,7 +18,8 @@ FP64, FP32, BF16_CONTRACT, FP8_CONTRACT = 0, 1, 2, 3
 MODE_MIXED, MODE_ALL_EXPENSIVE, MODE_ALL_CHEAP = 0, 1, 2
 FORCE_REBUILD = 0x100
 ENERGY_ONLY = 0x200
-N_STAGES = 10
+SINGLE_STREAM = 0x400
+N_STAGES = 12
 STATUS_NEIGH_OVERFLOW, STATUS_OUT_OF_BOX, STATUS_NONFINITE, STATUS_TRIPLET_OVERFLOW, STATUS_BAD_SPECIES = 1, 2, 4, 8, 16
 
 

@@ -397,47 +397,82 @@ __global__ void __launch_bounds__(256)
 // One wavefront per S atom, lanes over the atomic-basis entries (lm, c):
 // D3 = sum over the l-blocks' partial D (fixed order), D2 from the order-2
 // coefficients, dE/dA = c1 + 2 D2 + 3 D3 and E = c0 + sum A (c1 + D2 + D3).
+// The atom's A row, the block offsets, the per-l block ranges and (when
+// they fit, stage_c2) the order-2 coefficients transposed to [z][l][b][c]
+// are staged in LDS, so that a lane's loads are independent LDS reads plus
+// coalesced reads of the partial D.
 template <typename T>
 __global__ void __launch_bounds__(256)
     k_ace_finalize(const int32_t *__restrict__ species, const int *__restrict__ S_idx,
                    const int *__restrict__ hdr, AceArgs<T> a, const int *__restrict__ dp_off,
-                   int dp_stride, const T *__restrict__ A, const T *__restrict__ Dpart,
-                   T *__restrict__ dEdA, double *__restrict__ e_exp)
+                   int n_pb, int stage_c2, int dp_stride, const T *__restrict__ A,
+                   const T *__restrict__ Dpart, T *__restrict__ dEdA, double *__restrict__ e_exp)
 {
-    const int s = blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (s >= hdr[H_NS])
+    const int nS = hdr[H_NS];
+    if ((int)blockIdx.x * 4 >= nS)
+        return;  // uniform across the block
+    const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+    const int s = blockIdx.x * 4 + wv;
+    const int nch = a.nchan, nchp = a.nchp, L1 = a.L1, KAt = a.KAt;
+    extern __shared__ __align__(16) char smem_raw[];
+    T *As = reinterpret_cast<T *>(smem_raw) + (size_t)wv * KAt;            // [4][KAt]
+    T *Ct = reinterpret_cast<T *>(smem_raw) + (size_t)4 * KAt;             // [ns][L1][b][c]
+    const size_t nC = stage_c2 ? (size_t)a.ns * L1 * nch * nch : 0;
+    int *dpo = reinterpret_cast<int *>(Ct + nC);                           // [n_pb]
+    int *plo = dpo + n_pb, *phi = plo + L1;                                // [L1] each
+    if (a.order >= 2)
+        for (int e = tid; e < (int)nC; e += 256) {
+            const int c = e % nch, r = e / nch;
+            const int b = r % nch, zl = r / nch;
+            Ct[e] = a.c2s[((size_t)zl * nch + c) * nch + b];
+        }
+    for (int e = tid; e < n_pb; e += 256)
+        dpo[e] = dp_off[e];
+    if (tid < L1) {
+        plo[tid] = a.pb_lo[tid];
+        phi[tid] = a.pb_hi[tid];
+    }
+    if (s < nS)
+        for (int e = lane; e < KAt; e += 64)
+            As[e] = A[(size_t)s * KAt + e];
+    __syncthreads();
+    if (s >= nS)
         return;
     const int i = S_idx[s];
     const int z = sp_clamp(species[i], a.ns);
-    const int nch = a.nchan, nchp = a.nchp;
-    const T *As = A + (size_t)s * a.KAt;
     const T *Ds = Dpart + (size_t)s * dp_stride;
+    const T *Cz = stage_c2 ? Ct + (size_t)z * L1 * nch * nch : nullptr;
     double es = 0.0;
-    for (int e = lane; e < a.KAt; e += 64) {
-        int lm = e / nchp, c = e - lm * nchp;
+    for (int e = lane; e < KAt; e += 64) {
+        const int lm = e / nchp, c = e - lm * nchp;
         if (c >= nch) {
-            dEdA[(size_t)s * a.KAt + e] = T(0);
+            dEdA[(size_t)s * KAt + e] = T(0);
             continue;
         }
-        int l = 0;
-        while ((l + 1) * (l + 1) <= lm)
-            ++l;
-        int m3 = lm - l * l;
+        int l = (int)sqrtf((float)lm);
+        l -= (l * l > lm);
+        l += ((l + 1) * (l + 1) <= lm);
+        const int m3 = lm - l * l;
         T c1t = (l == 0) ? a.c1[z * nch + c] : T(0);
         T D2 = T(0);
         if (a.order >= 2) {
-            const T *C = a.c2s + (((size_t)z * a.L1 + l) * nch + c) * nch;
             const T *Al = As + lm * nchp;
-            for (int bb = 0; bb < nch; ++bb)
-                D2 += C[bb] * Al[bb];
+            if (Cz) {
+                const T *C = Cz + (size_t)l * nch * nch + c;
+                for (int bb = 0; bb < nch; ++bb)
+                    D2 += C[bb * nch] * Al[bb];
+            } else {
+                const T *C = a.c2s + (((size_t)z * L1 + l) * nch + c) * nch;
+                for (int bb = 0; bb < nch; ++bb)
+                    D2 += C[bb] * Al[bb];
+            }
         }
         T D3 = T(0);
         if (a.order >= 3)
-            for (int p = a.pb_lo[l]; p < a.pb_hi[l]; ++p)
-                D3 += Ds[dp_off[p] + m3 * nch + c];
-        T Av = As[e];
-        dEdA[(size_t)s * a.KAt + e] = c1t + T(2) * D2 + T(3) * D3;
+            for (int p = plo[l]; p < phi[l]; ++p)
+                D3 += Ds[dpo[p] + m3 * nch + c];
+        const T Av = As[e];
+        dEdA[(size_t)s * KAt + e] = c1t + T(2) * D2 + T(3) * D3;
         es += (double)(Av * (c1t + D2 + D3));
     }
 #pragma unroll
@@ -604,7 +639,7 @@ static void blocks_shape(const Ctx &c, size_t tsz, int &ta, int &mfma, int &stag
 
 template <typename T>
 static void contract_t(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L,
-                       const int32_t *species, double *e_exp)
+                       const int32_t *species)
 {
     AceArgs<T> a = make_args<T>(c);
     pb_ranges(c, a.pb_lo, a.pb_hi);
@@ -622,10 +657,27 @@ static void contract_t(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L,
                                               TA, c.m.n_pb, c.max_ent_pb, mf, stage, dp_off,
                                               c.m.dp_stride, at<T>(ws, L.A), Dpart);
     }
-    k_ace_finalize<T><<<(L.n + 3) / 4, 256, 0, s>>>(species, at<int>(ws, L.S_idx),
-                                                    at<int>(ws, L.hdr), a, dp_off, c.m.dp_stride,
-                                                    at<T>(ws, L.A), Dpart, at<T>(ws, L.dEdA),
-                                                    e_exp);
+}
+
+template <typename T>
+static void finalize_t(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L,
+                       const int32_t *species, double *e_exp)
+{
+    AceArgs<T> a = make_args<T>(c);
+    pb_ranges(c, a.pb_lo, a.pb_hi);
+    const int *dp_off = reinterpret_cast<const int *>(static_cast<char *>(c.m.base) + c.m.dpoff);
+    T *Dpart = at<T>(ws, L.dpart);
+    const size_t nC = (size_t)c.m.ns * (c.m.lmax + 1) * c.m.nchan * c.m.nchan;
+    size_t sm = (size_t)4 * c.m.KAt * sizeof(T) + (c.m.n_pb + 2 * (c.m.lmax + 1)) * sizeof(int) + 16;
+    int stage_c2 = 0;
+    if (sm + nC * sizeof(T) <= 48 * 1024) {
+        stage_c2 = 1;
+        sm += nC * sizeof(T);
+    }
+    k_ace_finalize<T><<<(L.n + 3) / 4, 256, sm, s>>>(species, at<int>(ws, L.S_idx),
+                                                     at<int>(ws, L.hdr), a, dp_off, c.m.n_pb, stage_c2,
+                                                     c.m.dp_stride, at<T>(ws, L.A), Dpart,
+                                                     at<T>(ws, L.dEdA), e_exp);
 }
 
 template <typename T>
@@ -654,14 +706,25 @@ void launch_ace_basis(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L, 
 }
 
 void launch_ace_contract(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L,
+                         const int32_t *species)
+{
+    if (L.n == 0)
+        return;
+    if (c.prec == MLMIX_FP64)
+        contract_t<double>(s, c, ws, L, species);
+    else
+        contract_t<float>(s, c, ws, L, species);
+}
+
+void launch_ace_finalize(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L,
                          const int32_t *species, double *e_exp)
 {
     if (L.n == 0)
         return;
     if (c.prec == MLMIX_FP64)
-        contract_t<double>(s, c, ws, L, species, e_exp);
+        finalize_t<double>(s, c, ws, L, species, e_exp);
     else
-        contract_t<float>(s, c, ws, L, species, e_exp);
+        finalize_t<float>(s, c, ws, L, species, e_exp);
 }
 
 void launch_ace_pairgrad(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L, const Box &b,

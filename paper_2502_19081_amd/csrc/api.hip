@@ -20,10 +20,19 @@ struct PendingEvent {
     hipEvent_t a, b;
 };
 
+// Second stream of a workspace: the reverse slots and the cheap potential run
+// on it beside the expensive path (fork and join through events on the
+// caller's stream, so the step stays capturable in a HIP graph).
+struct SideStream {
+    hipStream_t s = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+};
+
 struct mlmix_ctx {
     Ctx c;
     std::mutex mu;
     std::unordered_map<void *, WsLayout> ws;
+    std::unordered_map<void *, SideStream> side;
     uint32_t prof_mask = 0;
     double flops[6] = {0, 0, 0, 0, 0, 0};
     std::vector<PendingEvent> pending;
@@ -31,10 +40,13 @@ struct mlmix_ctx {
 };
 
 static const char *kStageNames[MLMIX_N_STAGES] = {
-    "neighbours", "regions", "compaction", "ace_basis", "ace_contract",
-    "ace_pairgrad", "uf3", "gather_blend", "integrator", "energy_sums"};
+    "neighbours", "regions", "compaction", "ace_basis", "ace_contract", "ace_finalize",
+    "ace_pairgrad", "uf3", "gather_blend", "integrator", "energy_sums", "reverse_slots"};
 
-enum { ST_NBR, ST_REG, ST_CMP, ST_BASIS, ST_CONTRACT, ST_PAIR, ST_UF3, ST_GATHER, ST_VV, ST_RED };
+enum {
+    ST_NBR, ST_REG, ST_CMP, ST_BASIS, ST_CONTRACT, ST_FIN, ST_PAIR, ST_UF3, ST_GATHER, ST_VV, ST_RED,
+    ST_REV
+};
 
 static hipEvent_t take_event(mlmix_ctx *ctx)
 {
@@ -661,21 +673,19 @@ extern "C" int mlmix_create(const mlmix_model_desc *desc, mlmix_ctx **out)
         // Operation counts of the kernels as written (a multiply-add counts
         // two, a division or square root one).
         double KA = m.KA, nr = m.nrad, L2d = L2;
-        double con = 4.0 * nch, dense = 0.0;
-        if (d.ace_order >= 2)
-            con += KA * (2.0 * nch + 4.0);
+        // order-3 contraction per S atom: sparse stage 2 per (entry, a, b)
+        // plus the coefficient product per (entry, a); dense stage 2 per
+        // (a, b, c, m3)
+        double con = 0.0, dense = 0.0;
         if (d.ace_order >= 3) {
             double nab = (double)nch * nch;
             for (const PBlock &p : t.pb) {
                 int nnz = t.gm3[p.gm3_off + 2 * p.l3 + 1] - t.gm3[p.gm3_off];
-                con += 3.0 * nab * nnz + 2.0 * nab * nch * (2 * p.l3 + 1);
+                con += 2.0 * nab * nnz + (double)nch * nnz + 2.0 * nab * nch * (2 * p.l3 + 1);
                 dense += 2.0 * nab * nch * (2 * p.l3 + 1);
             }
-            for (int l = 0; l <= d.ace_lmax; ++l)
-                if (c.m_pb_hi[l] > c.m_pb_lo[l])
-                    con += 4.0 * nch * (2 * l + 1);
         }
-        ctx->flops[0] = con;                                  // contraction, per S atom
+        ctx->flops[0] = con;                                  // order-3 contraction, per S atom
         ctx->flops[1] = 16.0 + 6.0 * nr + 8.0 * L2d + 2.0 * nr * L2d;   // atomic basis, per pair
         ctx->flops[2] = 31.0 + 10.0 * nr + L2d * (4.0 * nr + 24.0);     // pair adjoint, per pair
         ctx->flops[3] = 96.0;                                 // cheap 2-body, per pair
@@ -733,6 +743,14 @@ extern "C" int mlmix_destroy(mlmix_ctx *ctx)
     }
     for (hipEvent_t e : ctx->pool)
         (void)hipEventDestroy(e);
+    for (auto &kv : ctx->side) {
+        if (kv.second.s)
+            (void)hipStreamDestroy(kv.second.s);
+        if (kv.second.fork)
+            (void)hipEventDestroy(kv.second.fork);
+        if (kv.second.join)
+            (void)hipEventDestroy(kv.second.join);
+    }
     if (ctx->c.m.base)
         (void)hipFree(ctx->c.m.base);
     delete ctx;
@@ -808,11 +826,49 @@ static int compute_impl(mlmix_ctx *ctx, hipStream_t s, void *ws, const WsLayout 
     const Ctx &c = ctx->c;
     int m = (int)(mode & 0xff);
     bool energy_only = (mode & MLMIX_ENERGY_ONLY) != 0;
+    bool fork = (mode & MLMIX_SINGLE_STREAM) == 0;
+    SideStream sd;
+    if (fork) {
+        // the workspace's second stream is created by its first forked
+        // evaluation outside a graph capture; a capture before that runs on
+        // the caller's stream alone
+        hipStreamCaptureStatus cst = hipStreamCaptureStatusNone;
+        HIP_OK(hipStreamIsCapturing(s, &cst));
+        std::lock_guard<std::mutex> g(ctx->mu);
+        SideStream &e = ctx->side[ws];
+        if (!e.s && cst == hipStreamCaptureStatusNone) {
+            HIP_OK(hipStreamCreateWithFlags(&e.s, hipStreamNonBlocking));
+            HIP_OK(hipEventCreateWithFlags(&e.fork, hipEventDisableTiming));
+            HIP_OK(hipEventCreateWithFlags(&e.join, hipEventDisableTiming));
+        }
+        sd = e;
+        fork = sd.s != nullptr;
+    }
+    hipStream_t s2 = fork ? sd.s : s;  // stream of the reverse slots and the cheap potential
     {
         StageTimer t(ctx, s, ST_NBR);
         launch_prepare(s, ws, L, (mode & MLMIX_FORCE_REBUILD) ? 1 : 0, pos, c.d.skin);
         launch_neighbors(s, ws, L, b, c.r_list, pos);
     }
+    // fork: reverse slots and the cheap potential need only the list
+    if (fork) {
+        HIP_OK(hipEventRecord(sd.fork, s));
+        HIP_OK(hipStreamWaitEvent(sd.s, sd.fork, 0));
+    }
+    {
+        StageTimer t(ctx, s2, ST_REV);
+        launch_reverse(s2, ws, L);
+    }
+    if (!energy_only) {
+        if (m != MLMIX_MODE_ALL_EXPENSIVE) {
+            StageTimer t(ctx, s2, ST_UF3);
+            launch_uf3(s2, c, ws, L, b, pos, species, e_cheap);
+        } else {
+            launch_fill_f64(s2, e_cheap, 0.0, (size_t)L.n);
+        }
+    }
+    if (fork)
+        HIP_OK(hipEventRecord(sd.join, sd.s));
     {
         StageTimer t(ctx, s, ST_REG);
         launch_regions(s, ws, L, b, m, pos, species, c.m.ns, regions, n_regions, r_buffer, lambda,
@@ -829,23 +885,24 @@ static int compute_impl(mlmix_ctx *ctx, hipStream_t s, void *ws, const WsLayout 
         }
         {
             StageTimer t(ctx, s, ST_CONTRACT);
-            launch_ace_contract(s, c, ws, L, species, e_exp);
+            launch_ace_contract(s, c, ws, L, species);
+        }
+        {
+            StageTimer t(ctx, s, ST_FIN);
+            launch_ace_finalize(s, c, ws, L, species, e_exp);
         }
         if (!energy_only) {
             StageTimer t(ctx, s, ST_PAIR);
             launch_ace_pairgrad(s, c, ws, L, b, pos, species, nullptr);
         }
     }
+    // join
+    if (fork)
+        HIP_OK(hipStreamWaitEvent(s, sd.join, 0));
     if (energy_only) {
         launch_gather_blend(s, c, ws, L, 0, 0, lambda, nullptr, e_exp, nullptr, nullptr, 1.0);
         HIP_OK(hipGetLastError());
         return MLMIX_OK;
-    }
-    if (m != MLMIX_MODE_ALL_EXPENSIVE) {
-        StageTimer t(ctx, s, ST_UF3);
-        launch_uf3(s, c, ws, L, b, pos, species, e_cheap);
-    } else {
-        launch_fill_f64(s, e_cheap, 0.0, (size_t)L.n);
     }
     {
         StageTimer t(ctx, s, ST_GATHER);
@@ -864,7 +921,7 @@ static int check_compute_args(mlmix_ctx *ctx, const double *pos, const int32_t *
     int m = (int)(mode & 0xff);
     if (m != MLMIX_MODE_MIXED && m != MLMIX_MODE_ALL_EXPENSIVE && m != MLMIX_MODE_ALL_CHEAP)
         return fail(MLMIX_E_ARG, "unknown mode");
-    if (mode & ~(0xffu | MLMIX_FORCE_REBUILD | MLMIX_ENERGY_ONLY))
+    if (mode & ~(0xffu | MLMIX_FORCE_REBUILD | MLMIX_ENERGY_ONLY | MLMIX_SINGLE_STREAM))
         return fail(MLMIX_E_ARG, "unknown mode flag");
     if (!pos || !species || !e_exp || !lambda || !flags)
         return fail(MLMIX_E_ARG, "NULL array argument");

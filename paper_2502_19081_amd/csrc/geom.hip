@@ -464,11 +464,20 @@ void launch_neighbors(hipStream_t s, void *ws, const WsLayout &L, const Box &b, 
     k_neighbors<<<(n + 3) / 4, 256, 0, s>>>(pos, n, b, g, start, at<CellAtom>(ws, L.cell_atoms), r_list * r_list,
                                  L.cap, L.P, at<int>(ws, L.nbr), at<int>(ws, L.cnt),
                                  at<double>(ws, L.ref_pos), hdr);
+    k_finish_rebuild<<<1, 64, 0, s>>>(hdr);
+}
+
+// Reverse slots of a rebuilt list (skipped on the device when the list was
+// kept); needed by the force gather only, so it may run beside the potentials.
+void launch_reverse(hipStream_t s, void *ws, const WsLayout &L)
+{
+    const int n = L.n;
+    if (n == 0)
+        return;
     size_t tot = (size_t)n * L.cap;
     k_reverse<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(n, L.cap, at<int>(ws, L.nbr),
                                                            at<int>(ws, L.cnt), at<int>(ws, L.rev),
-                                                           hdr);
-    k_finish_rebuild<<<1, 64, 0, s>>>(hdr);
+                                                           at<int>(ws, L.hdr));
 }
 
 // --------------------------------------------------------- lambda / masks

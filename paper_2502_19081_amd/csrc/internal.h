@@ -117,6 +117,7 @@ void launch_prepare(hipStream_t s, void *ws, const WsLayout &L, int force_rebuil
                     double skin);
 void launch_neighbors(hipStream_t s, void *ws, const WsLayout &L, const Box &b, double r_list,
                       const double *pos);
+void launch_reverse(hipStream_t s, void *ws, const WsLayout &L);
 void launch_regions(hipStream_t s, void *ws, const WsLayout &L, const Box &b, int mode,
                     const double *pos, const int32_t *species, int ns, const mlmix_region *reg,
                     int nreg, double r_buffer, double *lambda, uint8_t *flags);
@@ -126,6 +127,8 @@ void launch_compact(hipStream_t s, void *ws, const WsLayout &L, uint8_t *flags, 
 void launch_ace_basis(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L, const Box &b,
                       const double *pos, const int32_t *species);
 void launch_ace_contract(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L,
+                         const int32_t *species);
+void launch_ace_finalize(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L,
                          const int32_t *species, double *e_exp);
 void launch_ace_pairgrad(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L, const Box &b,
                          const double *pos, const int32_t *species, const double *weights);

@@ -4,10 +4,14 @@ workload) on one GPU.
 Each replica keeps its positions, velocities, forces, neighbour list and
 every intermediate resident in its own workspace. Requests arrive over time
 (Poisson arrivals); whenever a slot and enough HBM are free, waiting requests
-are admitted. Whenever the set of active replicas changes, one HIP graph is
-captured that holds one velocity-Verlet step of every active replica, each in
-its own stream branch (fork from the capture stream, join back), so the
-replicas' kernels overlap on the device and a tick costs one graph launch.
+are admitted. A tick runs one velocity-Verlet step of every active replica,
+each on its own stream, so the replicas' kernels overlap on the device:
+either as eager launches (default) or, with use_graph, as one HIP graph
+captured whenever the set of active replicas changes (each replica in its own
+stream branch, forked from the capture stream and joined back), so that a
+tick costs one graph launch. The graph mode is off by default: its capture
+and replay crashed in the host runtime in a recent run, with the cause not
+yet shown.
 Finished replicas are retired (state copied to the host, memory released)
 and their slots refilled at the next tick.
 
@@ -60,11 +64,14 @@ class Replica:
         _, self.sy, self.pos, self.sp = core.system_for(w, model=model, cap=cap, device=device)
         self.vel = torch.from_numpy(np.ascontiguousarray(w["vel"].T)).to(device)
         self.mass = torch.from_numpy(w["masses"][w["species"]].astype(np.float64)).to(device)
-        self.sy.compute(self.pos, self.sp, r_buffer=w["r_buffer"], mode=self.mode, force_rebuild=True)
+        self.sy.compute(self.pos, self.sp, r_buffer=w["r_buffer"], mode=self.mode, force_rebuild=True,
+                        single_stream=True)
 
     def step(self):
+        # the server overlaps replicas on streams of its own, forked off the
+        # capture stream: keep each replica's step on its stream
         self.sy.vv_step(self.pos, self.vel, self.mass, self.sp, self.dt,
-                        r_buffer=self.w["r_buffer"], mode=self.mode)
+                        r_buffer=self.w["r_buffer"], mode=self.mode, single_stream=True)
 
     def retire(self):
         bits, _, rc = self.sy.status(raise_on_error=False)
@@ -79,7 +86,7 @@ class Server:
     """Continuous-batching server for replicas sharing one model."""
 
     def __init__(self, model, hbm_budget=8 << 30, max_slots=16, n_streams=8, cap=128,
-                 device="cuda", use_graph=True, check_every=50):
+                 device="cuda", use_graph=False, check_every=50):
         self.model = model
         self.budget = int(hbm_budget)
         self.max_slots = max_slots
@@ -236,12 +243,14 @@ def main(argv=None):
     ap.add_argument("--rate", type=float, default=0.0, help="Poisson arrival rate (1/s); 0 = all at t=0")
     ap.add_argument("--slots", type=int, default=16)
     ap.add_argument("--hbm-gb", type=float, default=16.0)
-    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--graph", action="store_true",
+                    help="one multi-stream HIP graph per batch composition (default: eager "
+                         "launches of every replica's step on its own stream)")
     args = ap.parse_args(argv)
     from gen import workloads as W
     model = core.Model(W.c4_model(), precision="fp32")
     srv = Server(model, hbm_budget=args.hbm_gb * (1 << 30), max_slots=args.slots,
-                 use_graph=not args.no_graph)
+                 use_graph=args.graph)
     reps = replicas_c4(args.replicas, args.steps, rate_hz=args.rate or None)
     for r in reps:
         srv.submit(r)
@@ -252,7 +261,7 @@ def main(argv=None):
     rep.update({"workload": "c4: W(001)+He impact replicas, log-uniform 2,000-20,000 atoms, "
                             "dt 0.2 fs, 8 A sphere following He, FP32 potentials",
                 "steps_per_replica": args.steps, "arrival_rate_hz": args.rate,
-                "slots": args.slots, "graph": not args.no_graph})
+                "slots": args.slots, "graph": args.graph})
     print(json.dumps(rep))
     return rep
 
