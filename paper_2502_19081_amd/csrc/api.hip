@@ -847,8 +847,8 @@ static int compute_impl(mlmix_ctx *ctx, hipStream_t s, void *ws, const WsLayout 
     hipStream_t s2 = fork ? sd.s : s;  // stream of the reverse slots and the cheap potential
     {
         StageTimer t(ctx, s, ST_NBR);
-        launch_prepare(s, ws, L, (mode & MLMIX_FORCE_REBUILD) ? 1 : 0, pos, c.d.skin);
-        launch_neighbors(s, ws, L, b, c.r_list, pos);
+        launch_neighbors(s, ws, L, b, c.r_list, pos, (mode & MLMIX_FORCE_REBUILD) ? 1 : 0,
+                         c.d.skin);
     }
     // fork: reverse slots and the cheap potential need only the list
     if (fork) {

@@ -84,6 +84,27 @@ __device__ __forceinline__ int block_excl_scan(int v, int *sh, int &total)
     return off + x - v;
 }
 
+// Exclusive scan across a 1024-thread block (16 waves).
+__device__ __forceinline__ int block1024_excl_scan(int v, int *sh, int &total)
+{
+    int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int x = wave_incl_scan(v);
+    if (lane == 63)
+        sh[w] = x;
+    __syncthreads();
+    int off = 0;
+    total = 0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        int s = sh[k];
+        if (k < w)
+            off += s;
+        total += s;
+    }
+    __syncthreads();
+    return off + x - v;
+}
+
 constexpr int kPer = kScanTile / 256;
 
 __global__ void __launch_bounds__(256) k_scan_blocksum(const int *__restrict__ in, int n,
@@ -247,6 +268,85 @@ __global__ void __launch_bounds__(256) k_cell_fill(const double *__restrict__ po
     r.j = i;
     r.pad = 0;
     atoms[slot] = r;
+}
+
+// Cell binning of a small system in one 1024-thread workgroup: counts in
+// LDS, exclusive scan, cell starts to HBM, records filled through LDS
+// cursors. On a forced rebuild it also raises the rebuild flag (otherwise
+// the flag comes from the displacement check before it) and, whenever the
+// list is rebuilt, marks the workspace as built. Order inside a cell
+// follows the atomics; the rows are sorted afterwards.
+__global__ void __launch_bounds__(1024) k_bin_small(const double *__restrict__ pos, int n, Box b,
+                                                    Grid g, int force, int *hdr,
+                                                    int *__restrict__ cell_of,
+                                                    int *__restrict__ start,
+                                                    CellAtom *__restrict__ atoms)
+{
+    extern __shared__ int cnt[];  // [ncell + 1]
+    __shared__ int sh[16];
+    const int tid = threadIdx.x;
+    const int rebuild = force ? 1 : hdr[H_REBUILD];
+    if (!rebuild)
+        return;  // uniform
+    const int ncell = g.ncell;
+    for (int c = tid; c <= ncell; c += 1024)
+        cnt[c] = 0;
+    __syncthreads();
+    int bad = 0, out = 0;
+    for (int i = tid; i < n; i += 1024) {
+        int c[3];
+        for (int k = 0; k < 3; ++k) {
+            double x = pos[k * n + i];
+            if (!(x == x) || x < -1.0e300 || x > 1.0e300)
+                bad = 1;
+            if (!b.per[k] && (x < 0.0 || x >= b.L[k]))
+                out = 1;
+            c[k] = cell_coord(x, g, k);
+        }
+        const int cell = (c[2] * g.nc[1] + c[1]) * g.nc[0] + c[0];
+        cell_of[i] = cell;
+        atomicAdd(&cnt[cell], 1);
+    }
+    if (bad)
+        atomicOr(&hdr[H_STATUS], MLMIX_STATUS_NONFINITE);
+    if (out)
+        atomicOr(&hdr[H_STATUS], MLMIX_STATUS_OUT_OF_BOX);
+    __syncthreads();
+    // exclusive scan: each thread owns a run of consecutive cells
+    const int per = (ncell + 1023) / 1024;
+    const int c0 = tid * per;
+    int sum = 0;
+    for (int k = 0; k < per; ++k)
+        if (c0 + k < ncell)
+            sum += cnt[c0 + k];
+    int tot;
+    int ex = block1024_excl_scan(sum, sh, tot);
+    for (int k = 0; k < per; ++k)
+        if (c0 + k < ncell) {
+            const int v = cnt[c0 + k];
+            cnt[c0 + k] = ex;
+            start[c0 + k] = ex;
+            ex += v;
+        }
+    if (tid == 0)
+        start[ncell] = tot;
+    __syncthreads();
+    for (int i = tid; i < n; i += 1024) {
+        const int cell = cell_of[i];
+        const int slot = atomicAdd(&cnt[cell], 1);
+        CellAtom r;
+        r.x = pos[i];
+        r.y = pos[n + i];
+        r.z = pos[2 * n + i];
+        r.j = i;
+        r.pad = 0;
+        atoms[slot] = r;
+    }
+    if (tid == 0) {
+        if (force)
+            hdr[H_REBUILD] = 1;
+        hdr[H_BUILT] = 1;
+    }
 }
 
 // One wavefront per atom, four atoms per 256-thread block. The (up to)
@@ -433,38 +533,46 @@ __global__ void k_finish_rebuild(int *hdr)
         hdr[H_BUILT] = 1;
 }
 
-void launch_prepare(hipStream_t s, void *ws, const WsLayout &L, int force_rebuild,
-                    const double *pos, double skin)
-{
-    int *hdr = at<int>(ws, L.hdr);
-    k_prepare<<<1, 64, 0, s>>>(hdr, force_rebuild);
-    if (!force_rebuild) {
-        double thr = 0.5 * skin;
-        k_displacement<<<(L.n + 255) / 256, 256, 0, s>>>(pos, at<double>(ws, L.ref_pos), L.n,
-                                                         thr * thr, hdr);
-    }
-}
+// Systems up to these sizes take the one-workgroup binning path.
+constexpr int kSmallAtoms = 65536;
+constexpr int kSmallCells = 16384;
 
 void launch_neighbors(hipStream_t s, void *ws, const WsLayout &L, const Box &b, double r_list,
-                      const double *pos)
+                      const double *pos, int force_rebuild, double skin)
 {
     int *hdr = at<int>(ws, L.hdr);
     const Grid &g = L.grid;
-    int *count = at<int>(ws, L.cell_count);
-    int *cursor = at<int>(ws, L.cell_cursor);
-    int *start = at<int>(ws, L.cell_start);
-    int n = L.n;
+    const int n = L.n;
+    const bool small = n <= kSmallAtoms && g.ncell <= kSmallCells;
+    if (!(small && force_rebuild)) {
+        k_prepare<<<1, 64, 0, s>>>(hdr, force_rebuild);
+        if (!force_rebuild && n > 0) {
+            double thr = 0.5 * skin;
+            k_displacement<<<(n + 255) / 256, 256, 0, s>>>(pos, at<double>(ws, L.ref_pos), n,
+                                                           thr * thr, hdr);
+        }
+    }
     if (n == 0)
         return;
-    k_cell_zero<<<(g.ncell + 255) / 256, 256, 0, s>>>(count, cursor, g.ncell, hdr + H_REBUILD);
-    k_cell_count<<<(n + 255) / 256, 256, 0, s>>>(pos, n, b, g, at<int>(ws, L.cell_of), count, hdr);
-    device_excl_scan(s, count, g.ncell, at<int>(ws, L.scan_part), start, hdr + H_REBUILD);
-    k_cell_fill<<<(n + 255) / 256, 256, 0, s>>>(pos, n, at<int>(ws, L.cell_of), start, cursor,
-                                                at<CellAtom>(ws, L.cell_atoms), hdr);
-    k_neighbors<<<(n + 3) / 4, 256, 0, s>>>(pos, n, b, g, start, at<CellAtom>(ws, L.cell_atoms), r_list * r_list,
-                                 L.cap, L.P, at<int>(ws, L.nbr), at<int>(ws, L.cnt),
-                                 at<double>(ws, L.ref_pos), hdr);
-    k_finish_rebuild<<<1, 64, 0, s>>>(hdr);
+    int *start = at<int>(ws, L.cell_start);
+    if (small) {
+        k_bin_small<<<1, 1024, (size_t)(g.ncell + 1) * sizeof(int), s>>>(
+            pos, n, b, g, force_rebuild, hdr, at<int>(ws, L.cell_of), start,
+            at<CellAtom>(ws, L.cell_atoms));
+    } else {
+        int *count = at<int>(ws, L.cell_count);
+        int *cursor = at<int>(ws, L.cell_cursor);
+        k_cell_zero<<<(g.ncell + 255) / 256, 256, 0, s>>>(count, cursor, g.ncell, hdr + H_REBUILD);
+        k_cell_count<<<(n + 255) / 256, 256, 0, s>>>(pos, n, b, g, at<int>(ws, L.cell_of), count, hdr);
+        device_excl_scan(s, count, g.ncell, at<int>(ws, L.scan_part), start, hdr + H_REBUILD);
+        k_cell_fill<<<(n + 255) / 256, 256, 0, s>>>(pos, n, at<int>(ws, L.cell_of), start, cursor,
+                                                    at<CellAtom>(ws, L.cell_atoms), hdr);
+    }
+    k_neighbors<<<(n + 3) / 4, 256, 0, s>>>(pos, n, b, g, start, at<CellAtom>(ws, L.cell_atoms),
+                                            r_list * r_list, L.cap, L.P, at<int>(ws, L.nbr),
+                                            at<int>(ws, L.cnt), at<double>(ws, L.ref_pos), hdr);
+    if (!small)
+        k_finish_rebuild<<<1, 64, 0, s>>>(hdr);
 }
 
 // Reverse slots of a rebuilt list (skipped on the device when the list was
@@ -702,10 +810,70 @@ __global__ void __launch_bounds__(256) k_cmp_apply(const uint8_t *__restrict__ f
     }
 }
 
+// Compaction of a small system in one 1024-thread workgroup (tiles of 8192
+// flags with a running offset): same outputs as the three-pass version.
+__global__ void __launch_bounds__(1024) k_cmp_small(const uint8_t *__restrict__ flags, int n,
+                                                    int *hdr, int32_t *n_expensive,
+                                                    int *__restrict__ S_idx,
+                                                    int *__restrict__ M_idx,
+                                                    int *__restrict__ S_local)
+{
+    __shared__ int sh[16];
+    constexpr int kP = 8;
+    int cs = 0, cm = 0;
+    for (int base0 = 0; base0 < n; base0 += 1024 * kP) {
+        const int base = base0 + threadIdx.x * kP;
+        uint8_t f[kP];
+        int sv = 0, mv = 0;
+#pragma unroll
+        for (int k = 0; k < kP; ++k) {
+            f[k] = (base + k < n) ? flags[base + k] : 0;
+            sv += (f[k] & 5) ? 1 : 0;
+            mv += (f[k] & 1) ? 1 : 0;
+        }
+        int ts, tm;
+        int es = block1024_excl_scan(sv, sh, ts) + cs;
+        int em = block1024_excl_scan(mv, sh, tm) + cm;
+#pragma unroll
+        for (int k = 0; k < kP; ++k) {
+            const int i = base + k;
+            if (i < n) {
+                if (f[k] & 5) {
+                    S_idx[es] = i;
+                    S_local[i] = es;
+                    es++;
+                } else {
+                    S_local[i] = -1;
+                }
+                if (f[k] & 1) {
+                    M_idx[em] = i;
+                    em++;
+                }
+            }
+        }
+        cs += ts;
+        cm += tm;
+    }
+    if (threadIdx.x == 0) {
+        hdr[H_NS] = cs;
+        hdr[H_NM] = cm;
+        if (n_expensive) {
+            n_expensive[0] = cs;
+            n_expensive[1] = cm;
+        }
+    }
+}
+
 void launch_compact(hipStream_t s, void *ws, const WsLayout &L, uint8_t *flags,
                     int32_t *n_expensive)
 {
     int n = L.n;
+    if (n <= kSmallAtoms) {
+        k_cmp_small<<<1, 1024, 0, s>>>(flags, n, at<int>(ws, L.hdr), n_expensive,
+                                       at<int>(ws, L.S_idx), at<int>(ws, L.M_idx),
+                                       at<int>(ws, L.S_local));
+        return;
+    }
     int nb = (n + kScanTile - 1) / kScanTile;
     if (nb < 1)
         nb = 1;

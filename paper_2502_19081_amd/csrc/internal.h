@@ -113,10 +113,8 @@ template <typename T>
 inline T *at(void *ws, size_t off) { return reinterpret_cast<T *>(static_cast<char *>(ws) + off); }
 
 // ---- launchers (geom.hip) ----
-void launch_prepare(hipStream_t s, void *ws, const WsLayout &L, int force_rebuild, const double *pos,
-                    double skin);
 void launch_neighbors(hipStream_t s, void *ws, const WsLayout &L, const Box &b, double r_list,
-                      const double *pos);
+                      const double *pos, int force_rebuild, double skin);
 void launch_reverse(hipStream_t s, void *ws, const WsLayout &L);
 void launch_regions(hipStream_t s, void *ws, const WsLayout &L, const Box &b, int mode,
                     const double *pos, const int32_t *species, int ns, const mlmix_region *reg,

@@ -152,6 +152,11 @@ class Server:
         if self.use_graph:
             self.graph.replay()
         else:
+            # admission evaluates new replicas on the current stream: order the
+            # replica streams after it before their steps
+            cur = torch.cuda.current_stream()
+            for st in self.streams[:min(len(self.active), len(self.streams))]:
+                st.wait_stream(cur)
             for k, r in enumerate(self.active):
                 with torch.cuda.stream(self.streams[k % len(self.streams)]):
                     r.step()
