@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--only-mixed", action="store_true",
                     help="time the mixed step only (no all-expensive / all-cheap / latency runs); "
                          "used under a profiler so that every traced launch is a mixed-mode one")
+    ap.add_argument("--single-stream", action="store_true",
+                    help="keep every stage on the caller's stream (no fork of the cheap potential)")
     ap.add_argument("--probe", choices=["copy"], default=None,
                     help="copy: a plain 256 MiB device-to-device copy, 20 times (calibration of "
                          "the HBM byte counters)")
@@ -166,7 +168,8 @@ def main():
     dt = float(w.get("dt", 1.0))
 
     def step(sy, pos, vel, sp, mode):
-        sy.vv_step(pos, vel, mass, sp, dt, r_buffer=w["r_buffer"], mode=mode, force_rebuild=True)
+        sy.vv_step(pos, vel, mass, sp, dt, r_buffer=w["r_buffer"], mode=mode, force_rebuild=True,
+                   single_stream=args.single_stream)
 
     def run(mode, steps, warmup, stage_mask=0, latency=False, graph=False):
         """Times `steps` steps. graph=True captures one step in a HIP graph

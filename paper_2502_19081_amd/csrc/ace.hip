@@ -592,6 +592,367 @@ static AceArgs<T> make_args(const Ctx &c)
 // pb_lo / pb_hi are filled by the host from the block list (sorted by l3).
 extern void pb_ranges(const Ctx &c, int *lo, int *hi);
 
+typedef float f4v_t __attribute__((ext_vector_type(4)));
+
+// Atomic basis on the matrix cores (FP32 potentials): one wave per S atom.
+// Lanes evaluate the radial functions and harmonics of 64 list slots at a
+// time; the valid pairs (partner in S, inside the cutoff) are compacted by
+// ballot into wave-private LDS rows (radial row masked by the partner's
+// species, so that channel (z, n) holds R_n only for z = z_j; rows padded
+// with zeros to a multiple of four), and A[(z, n)][lm] = sum_j R_zn,j Y_lm,j
+// accumulates as 16x16x4 MFMA tiles (MT channel tiles x NT lm tiles, K = the
+// compacted pairs). Row strides are odd so that the row writes of the 64
+// lanes and the tile reads are free of bank conflicts.
+template <int MT, int NT>
+__global__ void __launch_bounds__(256)
+    k_ace_basis_mfma(const double *__restrict__ pos, int n, Box b,
+                     const int32_t *__restrict__ species, int cap, const int *__restrict__ nbr,
+                     const int *__restrict__ cnt, const int *__restrict__ S_idx,
+                     const int *__restrict__ S_local, const int *__restrict__ hdr,
+                     AceArgs<float> a, int wpb, float *__restrict__ A)
+{
+    constexpr int RW = 16 * MT + 1, YW = 16 * NT + 1;
+    const int nS = hdr[H_NS];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int s = blockIdx.x * wpb + w;
+    if (s >= nS)
+        return;  // no barriers in this kernel
+    extern __shared__ __align__(16) char smem_raw[];
+    float *Rz = reinterpret_cast<float *>(smem_raw) + (size_t)w * 64 * (RW + YW);
+    float *Yt = Rz + 64 * RW;
+    const int m16 = lane & 15, kg = lane >> 4;
+    const int i = S_idx[s];
+    const int c = cnt[i];
+    const int *row = nbr + (size_t)i * cap;
+    const int nrad = a.nrad, nch = a.nchan, L2 = a.L2;
+    f4v_t acc[MT][NT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+            acc[mt][nt] = (f4v_t){0.f, 0.f, 0.f, 0.f};
+    for (int base = 0; base < c; base += 64) {
+        const int slot = base + lane;
+        bool ok = false;
+        float R[kMaxNrad], dR[kMaxNrad];
+        float ux = 0.f, uy = 0.f, uz = 0.f;
+        int zj = 0;
+        if (slot < c) {
+            const int j = row[slot];
+            if (S_local[j] >= 0) {
+                double d[3];
+                pair_disp_d(pos, n, i, j, b, d);
+                const double r2 = norm2_d(d);
+                if (r2 < a.rc2) {
+                    const double rd = sqrt(r2), ird = 1.0 / rd;
+                    radial<float>(nrad, float(rd), a.rc, R, dR);
+                    ux = float(d[0] * ird);
+                    uy = float(d[1] * ird);
+                    uz = float(d[2] * ird);
+                    zj = sp_clamp(species[j], a.ns);
+                    ok = true;
+                }
+            }
+        }
+        const unsigned long long mask = __ballot(ok);
+        const int nv = __popcll(mask);
+        const int nv4 = (nv + 3) & ~3;
+        const int p = __popcll(mask & ((1ull << lane) - 1ull));
+        if (ok) {
+            float *rr = Rz + p * RW;
+            for (int ch = 0; ch < 16 * MT; ++ch)
+                rr[ch] = 0.f;
+#pragma unroll
+            for (int k = 0; k < kMaxNrad; ++k)
+                if (k < nrad)
+                    rr[zj * nrad + k] = R[k];
+            float *yr = Yt + p * YW;
+            ylm_stream<float>(a.lmax, ux, uy, uz, a.K,
+                              [&](int lm, float Y, float, float, float) { yr[lm] = Y; });
+            for (int lm = L2; lm < 16 * NT; ++lm)
+                yr[lm] = 0.f;
+        }
+        if (lane >= nv && lane < nv4) {
+            // zero the rows that pad K to a multiple of four (rows nv.. are
+            // not written by the compaction, whichever lanes hold pairs)
+            for (int ch = 0; ch < 16 * MT; ++ch)
+                Rz[lane * RW + ch] = 0.f;
+            for (int lm = 0; lm < 16 * NT; ++lm)
+                Yt[lane * YW + lm] = 0.f;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (int k0 = 0; k0 < nv4; k0 += 4) {
+            const int kr = k0 + kg;
+            float xa[MT], yb[NT];
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+                xa[mt] = Rz[kr * RW + mt * 16 + m16];
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt)
+                yb[nt] = Yt[kr * YW + nt * 16 + m16];
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt)
+                    acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[mt], yb[nt], acc[mt][nt], 0, 0, 0);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    // lane holds A[ch = 16 mt + 4 kg + v][lm = 16 nt + m16]: four consecutive
+    // channels of one lm, stored as one 16-byte write (padded channels are 0)
+    float *As = A + (size_t)s * a.KAt;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            const int lm = nt * 16 + m16, ch0 = mt * 16 + 4 * kg;
+            if (lm < L2 && ch0 < a.nchp)
+                *reinterpret_cast<f4v_t *>(As + lm * a.nchp + ch0) = acc[mt][nt];
+        }
+}
+
+// Pair adjoint on the matrix cores (FP32 potentials): one wave per S atom.
+// G = dE/dA of the atom (times its weight) is staged transposed, [(z, n)][lm].
+// For 64 list slots at a time the valid pairs (partner in S, inside the
+// cutoff) are compacted by ballot into species-masked rows R and dR;
+// S_R = R G and S_D = dR G (pairs x lm) are 16x16x4 MFMA tiles (K =
+// channels); each pair's lane then contracts its rows with the harmonics and
+// their gradients, g = rad u + (v - u (u.v)) / r with rad = sum S_D Y and
+// v = sum S_R grad_u Y, and writes g to its list slot (0 for other slots).
+template <int MT, int NT>
+__global__ void __launch_bounds__(256)
+    k_ace_pairgrad_mfma(const double *__restrict__ pos, int n, Box b,
+                        const int32_t *__restrict__ species, int cap, const int *__restrict__ nbr,
+                        const int *__restrict__ cnt, const int *__restrict__ S_idx,
+                        const int *__restrict__ S_local, const int *__restrict__ hdr,
+                        AceArgs<float> a, int wpb, const float *__restrict__ dEdA,
+                        const double *__restrict__ weights, float *__restrict__ g)
+{
+    constexpr int RW = 16 * MT + 1, YW = 16 * NT + 1;
+    constexpr int PAIR = 64 * RW * 2 > 64 * YW * 2 ? 64 * RW * 2 : 64 * YW * 2;
+    const int nS = hdr[H_NS];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int s = blockIdx.x * wpb + w;
+    if (s >= nS)
+        return;  // no barriers in this kernel
+    extern __shared__ __align__(16) char smem_raw[];
+    float *base = reinterpret_cast<float *>(smem_raw) + (size_t)w * (PAIR + 16 * MT * YW);
+    float *Rr = base, *Dr = base + 64 * RW;           // [64][RW] each
+    float *SR = base, *SD = base + 64 * YW;           // [64][YW] each (after the MFMAs)
+    float *Gt = base + PAIR;                          // [16 MT][YW]
+    const int m16 = lane & 15, kg = lane >> 4;
+    const int i = S_idx[s];
+    const float wgt = weights ? float(weights[i]) : 1.0f;
+    const int nrad = a.nrad, nch = a.nchan, L2 = a.L2, nchp = a.nchp;
+    for (int e = lane; e < 16 * MT * 16 * NT; e += 64) {
+        const int ch = e / (16 * NT), lm = e - ch * (16 * NT);
+        Gt[ch * YW + lm] = (ch < nch && lm < L2) ? dEdA[(size_t)s * a.KAt + lm * nchp + ch] * wgt : 0.f;
+    }
+    const int c = cnt[i];
+    const int *row = nbr + (size_t)i * cap;
+    float *gs = g + (size_t)s * cap * 3;
+    for (int base0 = 0; base0 < c; base0 += 64) {
+        const int slot = base0 + lane;
+        bool ok = false;
+        float R[kMaxNrad], dR[kMaxNrad];
+        float ux = 0.f, uy = 0.f, uz = 0.f, ir = 0.f;
+        int zj = 0;
+        if (slot < c) {
+            const int j = row[slot];
+            if (S_local[j] >= 0) {
+                double d[3];
+                pair_disp_d(pos, n, i, j, b, d);
+                const double r2 = norm2_d(d);
+                if (r2 < a.rc2) {
+                    const double rd = sqrt(r2), ird = 1.0 / rd;
+                    radial<float>(nrad, float(rd), a.rc, R, dR);
+                    ux = float(d[0] * ird);
+                    uy = float(d[1] * ird);
+                    uz = float(d[2] * ird);
+                    ir = float(ird);
+                    zj = sp_clamp(species[j], a.ns);
+                    ok = true;
+                }
+            }
+        }
+        // valid pairs compacted into rows 0..nv-1; rows up to the next
+        // multiple of 16 (one MFMA row tile) are zero
+        const unsigned long long mask = __ballot(ok);
+        const int nv = __popcll(mask);
+        const int nrt = (nv + 15) >> 4;
+        const int p = __popcll(mask & ((1ull << lane) - 1ull));
+        if (ok) {
+            float *rr = Rr + p * RW, *dr = Dr + p * RW;
+            for (int ch = 0; ch < 16 * MT; ++ch) {
+                rr[ch] = 0.f;
+                dr[ch] = 0.f;
+            }
+#pragma unroll
+            for (int k = 0; k < kMaxNrad; ++k)
+                if (k < nrad) {
+                    rr[zj * nrad + k] = R[k];
+                    dr[zj * nrad + k] = dR[k];
+                }
+        }
+        if (lane >= nv && lane < 16 * nrt) {
+            float *rr = Rr + lane * RW, *dr = Dr + lane * RW;
+            for (int ch = 0; ch < 16 * MT; ++ch) {
+                rr[ch] = 0.f;
+                dr[ch] = 0.f;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // S tiles: rows = compacted pairs (nrt tiles of 16), cols = lm, K = channels
+        f4v_t sr[4][NT], sd[4][NT];
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+                sr[rt][nt] = (f4v_t){0.f, 0.f, 0.f, 0.f};
+                sd[rt][nt] = (f4v_t){0.f, 0.f, 0.f, 0.f};
+            }
+#pragma unroll
+        for (int k0 = 0; k0 < 16 * MT; k0 += 4) {
+            const int kc = k0 + kg;
+            float gb[NT];
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt)
+                gb[nt] = Gt[kc * YW + nt * 16 + m16];
+#pragma unroll
+            for (int rt = 0; rt < 4; ++rt)
+                if (rt < nrt) {
+                    const float xr = Rr[(rt * 16 + m16) * RW + kc];
+                    const float xd = Dr[(rt * 16 + m16) * RW + kc];
+#pragma unroll
+                    for (int nt = 0; nt < NT; ++nt) {
+                        sr[rt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(xr, gb[nt], sr[rt][nt], 0, 0, 0);
+                        sd[rt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(xd, gb[nt], sd[rt][nt], 0, 0, 0);
+                    }
+                }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // lane holds S[pair row = 16 rt + 4 kg + v][lm = 16 nt + m16]
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt)
+            if (rt < nrt) {
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int sl = rt * 16 + 4 * kg + v, lm = nt * 16 + m16;
+                        SR[sl * YW + lm] = sr[rt][nt][v];
+                        SD[sl * YW + lm] = sd[rt][nt][v];
+                    }
+            }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (slot < c) {
+            float gx = 0.f, gy = 0.f, gz = 0.f;
+            if (ok) {
+                const float *srow = SR + p * YW, *drow = SD + p * YW;
+                float rad = 0.f, vx = 0.f, vy = 0.f, vz = 0.f;
+                ylm_stream<float>(a.lmax, ux, uy, uz, a.K, [&](int lm, float Y, float yx, float yy, float yz) {
+                    const float sR = srow[lm], sD = drow[lm];
+                    rad += sD * Y;
+                    vx += sR * yx;
+                    vy += sR * yy;
+                    vz += sR * yz;
+                });
+                const float ud = ux * vx + uy * vy + uz * vz;
+                gx = rad * ux + (vx - ux * ud) * ir;
+                gy = rad * uy + (vy - uy * ud) * ir;
+                gz = rad * uz + (vz - uz * ud) * ir;
+            }
+            gs[slot * 3 + 0] = gx;
+            gs[slot * 3 + 1] = gy;
+            gs[slot * 3 + 2] = gz;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+}
+
+template <int MT, int NT>
+static size_t basis_mfma_lds() { return (size_t)64 * (16 * MT + 1 + 16 * NT + 1) * sizeof(float); }
+template <int MT, int NT>
+static size_t pairgrad_mfma_lds()
+{
+    constexpr int RW = 16 * MT + 1, YW = 16 * NT + 1;
+    constexpr int PAIR = 64 * RW * 2 > 64 * YW * 2 ? 64 * RW * 2 : 64 * YW * 2;
+    return (size_t)(PAIR + 16 * MT * YW) * sizeof(float);
+}
+
+// Waves per workgroup that keep a workgroup's LDS within 64 KiB.
+static int mfma_wpb(size_t per_wave)
+{
+    int wpb = 4;
+    while (wpb > 1 && per_wave * wpb > 64 * 1024)
+        wpb >>= 1;
+    return wpb;
+}
+
+template <int MT, int NT>
+static void basis_mfma_launch(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L, const Box &b,
+                              const double *pos, const int32_t *species, const AceArgs<float> &a)
+{
+    const size_t per = basis_mfma_lds<MT, NT>();
+    const int wpb = mfma_wpb(per);
+    k_ace_basis_mfma<MT, NT><<<(L.n + wpb - 1) / wpb, 64 * wpb, per * wpb, s>>>(
+        pos, L.n, b, species, L.cap, at<int>(ws, L.nbr), at<int>(ws, L.cnt), at<int>(ws, L.S_idx),
+        at<int>(ws, L.S_local), at<int>(ws, L.hdr), a, wpb, at<float>(ws, L.A));
+}
+
+template <int MT, int NT>
+static void pairgrad_mfma_launch(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L,
+                                 const Box &b, const double *pos, const int32_t *species,
+                                 const double *weights, const AceArgs<float> &a)
+{
+    const size_t per = pairgrad_mfma_lds<MT, NT>();
+    const int wpb = mfma_wpb(per);
+    k_ace_pairgrad_mfma<MT, NT><<<(L.n + wpb - 1) / wpb, 64 * wpb, per * wpb, s>>>(
+        pos, L.n, b, species, L.cap, at<int>(ws, L.nbr), at<int>(ws, L.cnt), at<int>(ws, L.S_idx),
+        at<int>(ws, L.S_local), at<int>(ws, L.hdr), a, wpb, at<float>(ws, L.dEdA), weights,
+        at<float>(ws, L.g));
+}
+
+// Dispatch over (channel tiles, lm tiles); false if the model is outside the
+// instantiated range (then the VALU kernels run).
+template <bool PAIR>
+static bool mfma_dispatch(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L, const Box &b,
+                          const double *pos, const int32_t *species, const double *weights)
+{
+    AceArgs<float> a = make_args<float>(c);
+    const int mt = (a.nchan + 15) / 16, nt = (a.L2 + 15) / 16;
+    // the adjoint's S rows take 64 x (16 nt + 1) floats per wave twice: from
+    // three lm tiles on (lmax >= 5) one wave fits a SIMD and the VALU kernel
+    // (2.3 KB per wave at lmax 5) measured faster (0.70 vs 1.49 ms on the
+    // 1,023,800-atom cell)
+    if (PAIR && nt > 2)
+        return false;
+#define O3_GO(M, N)                                                                    \
+    if (mt == M && nt == N) {                                                          \
+        if (PAIR)                                                                      \
+            pairgrad_mfma_launch<M, N>(s, c, ws, L, b, pos, species, weights, a);      \
+        else                                                                           \
+            basis_mfma_launch<M, N>(s, c, ws, L, b, pos, species, a);                  \
+        return true;                                                                   \
+    }
+    O3_GO(1, 1) O3_GO(1, 2) O3_GO(1, 3) O3_GO(1, 4)
+    O3_GO(2, 1) O3_GO(2, 2) O3_GO(2, 3) O3_GO(2, 4)
+#undef O3_GO
+    return false;
+}
+
 template <typename T>
 static void basis_t(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L, const Box &b,
                     const double *pos, const int32_t *species)
@@ -701,7 +1062,7 @@ void launch_ace_basis(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L, 
         return;
     if (c.prec == MLMIX_FP64)
         basis_t<double>(s, c, ws, L, b, pos, species);
-    else
+    else if (!(c.basis_mfma && mfma_dispatch<false>(s, c, ws, L, b, pos, species, nullptr)))
         basis_t<float>(s, c, ws, L, b, pos, species);
 }
 
@@ -734,7 +1095,7 @@ void launch_ace_pairgrad(hipStream_t s, const Ctx &c, void *ws, const WsLayout &
         return;
     if (c.prec == MLMIX_FP64)
         pairgrad_t<double>(s, c, ws, L, b, pos, species, weights);
-    else
+    else if (!(c.basis_mfma && mfma_dispatch<true>(s, c, ws, L, b, pos, species, weights)))
         pairgrad_t<float>(s, c, ws, L, b, pos, species, weights);
 }
 

@@ -708,6 +708,8 @@ extern "C" int mlmix_create(const mlmix_model_desc *desc, mlmix_ctx **out)
     }
     c.o3 = t.o3 ? 1 : 0;
     c.o3_nch2 = t.o3_nch2;
+    if (const char *e = std::getenv("MLMIX_BASIS_MFMA"))
+        c.basis_mfma = std::atoi(e) ? 1 : 0;  // VALU kernels (comparisons)
     if (const char *e = std::getenv("MLMIX_ACE_O3"))
         if (!std::atoi(e))
             c.o3 = 0;  // general block kernel (comparisons)

@@ -810,70 +810,10 @@ __global__ void __launch_bounds__(256) k_cmp_apply(const uint8_t *__restrict__ f
     }
 }
 
-// Compaction of a small system in one 1024-thread workgroup (tiles of 8192
-// flags with a running offset): same outputs as the three-pass version.
-__global__ void __launch_bounds__(1024) k_cmp_small(const uint8_t *__restrict__ flags, int n,
-                                                    int *hdr, int32_t *n_expensive,
-                                                    int *__restrict__ S_idx,
-                                                    int *__restrict__ M_idx,
-                                                    int *__restrict__ S_local)
-{
-    __shared__ int sh[16];
-    constexpr int kP = 8;
-    int cs = 0, cm = 0;
-    for (int base0 = 0; base0 < n; base0 += 1024 * kP) {
-        const int base = base0 + threadIdx.x * kP;
-        uint8_t f[kP];
-        int sv = 0, mv = 0;
-#pragma unroll
-        for (int k = 0; k < kP; ++k) {
-            f[k] = (base + k < n) ? flags[base + k] : 0;
-            sv += (f[k] & 5) ? 1 : 0;
-            mv += (f[k] & 1) ? 1 : 0;
-        }
-        int ts, tm;
-        int es = block1024_excl_scan(sv, sh, ts) + cs;
-        int em = block1024_excl_scan(mv, sh, tm) + cm;
-#pragma unroll
-        for (int k = 0; k < kP; ++k) {
-            const int i = base + k;
-            if (i < n) {
-                if (f[k] & 5) {
-                    S_idx[es] = i;
-                    S_local[i] = es;
-                    es++;
-                } else {
-                    S_local[i] = -1;
-                }
-                if (f[k] & 1) {
-                    M_idx[em] = i;
-                    em++;
-                }
-            }
-        }
-        cs += ts;
-        cm += tm;
-    }
-    if (threadIdx.x == 0) {
-        hdr[H_NS] = cs;
-        hdr[H_NM] = cm;
-        if (n_expensive) {
-            n_expensive[0] = cs;
-            n_expensive[1] = cm;
-        }
-    }
-}
-
 void launch_compact(hipStream_t s, void *ws, const WsLayout &L, uint8_t *flags,
                     int32_t *n_expensive)
 {
     int n = L.n;
-    if (n <= kSmallAtoms) {
-        k_cmp_small<<<1, 1024, 0, s>>>(flags, n, at<int>(ws, L.hdr), n_expensive,
-                                       at<int>(ws, L.S_idx), at<int>(ws, L.M_idx),
-                                       at<int>(ws, L.S_local));
-        return;
-    }
     int nb = (n + kScanTile - 1) / kScanTile;
     if (nb < 1)
         nb = 1;

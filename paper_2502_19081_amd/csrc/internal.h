@@ -96,6 +96,7 @@ struct Ctx {
     int max_ent, max_gm3;  // Gaunt entries / m3 offsets of the largest l3 group
     int max_ent_pb;        // Gaunt entries of the largest single block
     int o3 = 0;            // order-3 contraction on the per-wave matrix-core kernel
+    int basis_mfma = 1;    // atomic basis and pair adjoint on the matrix cores (FP32)
     int o3_nch2 = 0;       // row width of that kernel (channels rounded up to 4)
     int ace_tile = 4;      // atoms per order-3 block workgroup (tuning)
     int ace_stage_w = 1;   // stage the block's weights in LDS (tuning)

@@ -197,54 +197,9 @@ __global__ void __launch_bounds__(256) k_reduce_final(const double *__restrict__
     }
 }
 
-// Energy sums of a small system in one 1024-thread workgroup (fixed
-// summation order, as in the two-pass version).
-__global__ void __launch_bounds__(1024) k_reduce_small(int n, const double *__restrict__ e_exp,
-                                                       const double *__restrict__ e_cheap,
-                                                       const double *__restrict__ vel,
-                                                       const double *__restrict__ mass,
-                                                       double *__restrict__ out)
-{
-    __shared__ double sh[3][16];
-    double a = 0.0, bsum = 0.0, k = 0.0;
-    for (int i = threadIdx.x; i < n; i += 1024) {
-        if (e_exp)
-            a += e_exp[i];
-        if (e_cheap)
-            bsum += e_cheap[i];
-        if (vel && mass) {
-            double v2 = vel[i] * vel[i] + vel[n + i] * vel[n + i] + vel[2 * n + i] * vel[2 * n + i];
-            k += 0.5 * mass[i] * v2;
-        }
-    }
-    a = wave_sum_d(a);
-    bsum = wave_sum_d(bsum);
-    k = wave_sum_d(k);
-    int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) {
-        sh[0][w] = a;
-        sh[1][w] = bsum;
-        sh[2][w] = k;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int q = 0; q < 3; ++q) {
-            double t = 0.0;
-            for (int j = 0; j < 16; ++j)
-                t += sh[q][j];
-            out[q] = t;
-        }
-        out[2] /= kKappa;
-    }
-}
-
 void launch_reduce(hipStream_t s, void *ws, const WsLayout &L, const double *e_exp,
                    const double *e_cheap, const double *vel, const double *mass, double *out)
 {
-    if (L.n <= 32768) {
-        k_reduce_small<<<1, 1024, 0, s>>>(L.n, e_exp, e_cheap, vel, mass, out);
-        return;
-    }
     double *part = at<double>(ws, L.red);
     int nb = (L.n + 255) / 256;
     if (nb > kReduceBlocks)
