@@ -293,19 +293,34 @@ __global__ void __launch_bounds__(1024) k_bin_small(const double *__restrict__ p
         cnt[c] = 0;
     __syncthreads();
     int bad = 0, out = 0;
-    for (int i = tid; i < n; i += 1024) {
-        int c[3];
-        for (int k = 0; k < 3; ++k) {
-            double x = pos[k * n + i];
-            if (!(x == x) || x < -1.0e300 || x > 1.0e300)
-                bad = 1;
-            if (!b.per[k] && (x < 0.0 || x >= b.L[k]))
-                out = 1;
-            c[k] = cell_coord(x, g, k);
+    // batches of eight atoms per thread: all position loads issued first
+    for (int i0 = 0; i0 < n; i0 += 8 * 1024) {
+        double x[8][3];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = i0 + u * 1024 + tid;
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                x[u][k] = i < n ? pos[k * n + i] : 0.0;
         }
-        const int cell = (c[2] * g.nc[1] + c[1]) * g.nc[0] + c[0];
-        cell_of[i] = cell;
-        atomicAdd(&cnt[cell], 1);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = i0 + u * 1024 + tid;
+            if (i >= n)
+                continue;
+            int c[3];
+            for (int k = 0; k < 3; ++k) {
+                const double xv = x[u][k];
+                if (!(xv == xv) || xv < -1.0e300 || xv > 1.0e300)
+                    bad = 1;
+                if (!b.per[k] && (xv < 0.0 || xv >= b.L[k]))
+                    out = 1;
+                c[k] = cell_coord(xv, g, k);
+            }
+            const int cell = (c[2] * g.nc[1] + c[1]) * g.nc[0] + c[0];
+            cell_of[i] = cell;
+            atomicAdd(&cnt[cell], 1);
+        }
     }
     if (bad)
         atomicOr(&hdr[H_STATUS], MLMIX_STATUS_NONFINITE);
@@ -331,16 +346,31 @@ __global__ void __launch_bounds__(1024) k_bin_small(const double *__restrict__ p
     if (tid == 0)
         start[ncell] = tot;
     __syncthreads();
-    for (int i = tid; i < n; i += 1024) {
-        const int cell = cell_of[i];
-        const int slot = atomicAdd(&cnt[cell], 1);
-        CellAtom r;
-        r.x = pos[i];
-        r.y = pos[n + i];
-        r.z = pos[2 * n + i];
-        r.j = i;
-        r.pad = 0;
-        atoms[slot] = r;
+    for (int i0 = 0; i0 < n; i0 += 8 * 1024) {
+        int cl[8];
+        double x[8][3];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = i0 + u * 1024 + tid;
+            cl[u] = i < n ? cell_of[i] : 0;
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                x[u][k] = i < n ? pos[k * n + i] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = i0 + u * 1024 + tid;
+            if (i >= n)
+                continue;
+            const int slot = atomicAdd(&cnt[cl[u]], 1);
+            CellAtom r;
+            r.x = x[u][0];
+            r.y = x[u][1];
+            r.z = x[u][2];
+            r.j = i;
+            r.pad = 0;
+            atoms[slot] = r;
+        }
     }
     if (tid == 0) {
         if (force)
@@ -349,13 +379,76 @@ __global__ void __launch_bounds__(1024) k_bin_small(const double *__restrict__ p
     }
 }
 
-// One wavefront per atom, four atoms per 256-thread block. The (up to)
-// 5x5x5 stencil of half-radius cells is flattened: lanes first look up the
+__device__ __forceinline__ void wave_sync_lds()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Ascending bitonic sort of 64 V keys held V per lane (key e = V lane + v):
+// in-lane stages swap registers, cross-lane stages exchange with the lane
+// lane ^ (j / V) and keep the minimum or the maximum.
+template <int V>
+__device__ __forceinline__ void wave_bitonic_sort(int (&x)[V])
+{
+    const int lane = threadIdx.x & 63;
+    constexpr int N = 64 * V;
+#pragma unroll
+    for (int k = 2; k <= N; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            if (j < V) {
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    const int u = v ^ j;
+                    if (u > v) {
+                        const bool up = ((lane * V + v) & k) == 0;
+                        const int a = x[v], b = x[u];
+                        if ((a > b) == up) {
+                            x[v] = b;
+                            x[u] = a;
+                        }
+                    }
+                }
+            } else {
+                const int pl = j / V;
+                const bool lower = (lane & pl) == 0;
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    const int other = __shfl_xor(x[v], pl);
+                    const bool up = ((lane * V + v) & k) == 0;
+                    x[v] = (lower == up) ? min(x[v], other) : max(x[v], other);
+                }
+            }
+        }
+    }
+}
+
+template <int V>
+__device__ __forceinline__ void row_sort_store(const int *row, int lane, int keep, int cap,
+                                               int *__restrict__ out)
+{
+    int x[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v)
+        x[v] = row[lane * V + v];
+    wave_bitonic_sort<V>(x);
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        const int sl = lane * V + v;
+        if (sl < cap)
+            out[sl] = sl < keep ? x[v] : -1;
+    }
+}
+
+// One wavefront per atom, four atoms per 256-thread block, no block-level
+// barriers (each wave works in its own LDS slices). The (up to) 5x5x5
+// stencil of half-radius cells is flattened: lanes first look up the
 // stencil cells' ranges and prefix-sum their sizes, then sweep the candidate
 // list 64 at a time (one 32-byte cell-ordered record per candidate), keep
 // partners closer than the list radius by ballot compaction, and finally
-// sort the row ascending (bitonic sort in the wave's LDS slice). Barriers
-// are placed where all four waves pass them.
+// sort the row ascending in registers (bitonic over 64, 128 or 256 keys).
 __global__ void __launch_bounds__(256) k_neighbors(const double *__restrict__ pos, int n, Box b,
                                                    Grid g, const int *__restrict__ start,
                                                    const CellAtom *__restrict__ atoms, double rl2,
@@ -372,28 +465,29 @@ __global__ void __launch_bounds__(256) k_neighbors(const double *__restrict__ po
     const int w = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     const int i = blockIdx.x * 4 + w;
-    const bool valid = i < n;
+    if (i >= n)
+        return;
+    const int Pe = P < 64 ? 64 : P;  // keys sorted (64 V)
     int *row = rows[w];
-    for (int t = lane; t < P; t += 64)
+    for (int t = lane; t < Pe; t += 64)
         row[t] = 0x7fffffff;
     int nst[3];
     for (int k = 0; k < 3; ++k)
         nst[k] = (b.per[k] && g.nc[k] < 5) ? g.nc[k] : 5;
     const int total = nst[0] * nst[1] * nst[2];  // <= 125
-    double xi[3] = {0.0, 0.0, 0.0};
-    int ci[3] = {0, 0, 0};
-    if (valid)
-        for (int k = 0; k < 3; ++k) {
-            xi[k] = pos[k * n + i];
-            ci[k] = cell_coord(xi[k], g, k);
-        }
+    double xi[3];
+    int ci[3];
+    for (int k = 0; k < 3; ++k) {
+        xi[k] = pos[k * n + i];
+        ci[k] = cell_coord(xi[k], g, k);
+    }
     // stencil cells t = lane and t = lane + 64: first slot and size
     int sz[2], bg[2];
     for (int h = 0; h < 2; ++h) {
         int t = lane + 64 * h;
         sz[h] = 0;
         bg[h] = 0;
-        if (valid && t < total) {
+        if (t < total) {
             int o[3] = {t % nst[0] - 2, (t / nst[0]) % nst[1] - 2, t / (nst[0] * nst[1]) - 2};
             int q[3];
             bool ok = true;
@@ -425,7 +519,7 @@ __global__ void __launch_bounds__(256) k_neighbors(const double *__restrict__ po
     coff[w][lane + 64] = tot0 + inc1 - sz[1];
     if (lane == 0)
         coff[w][128] = ncand;
-    __syncthreads();
+    wave_sync_lds();
     int c = 0;
     for (int r0 = 0; r0 < ncand; r0 += 64) {
         int q = r0 + lane;
@@ -460,28 +554,15 @@ __global__ void __launch_bounds__(256) k_neighbors(const double *__restrict__ po
             row[p] = j;
         c += __popcll(m);
     }
-    __syncthreads();
-    for (int k = 2; k <= P; k <<= 1) {
-        for (int jj = k >> 1; jj > 0; jj >>= 1) {
-            for (int t = lane; t < P; t += 64) {
-                int l = t ^ jj;
-                if (l > t) {
-                    int a = row[t], bb = row[l];
-                    bool up = (t & k) == 0;
-                    if ((a > bb) == up) {
-                        row[t] = bb;
-                        row[l] = a;
-                    }
-                }
-            }
-            __syncthreads();
-        }
-    }
-    if (!valid)
-        return;
-    int keep = c < cap ? c : cap;
-    for (int s2 = lane; s2 < cap; s2 += 64)
-        nbr[(size_t)i * cap + s2] = s2 < keep ? row[s2] : -1;
+    wave_sync_lds();
+    const int keep = c < cap ? c : cap;
+    int *out = nbr + (size_t)i * cap;
+    if (Pe == 64)
+        row_sort_store<1>(row, lane, keep, cap, out);
+    else if (Pe == 128)
+        row_sort_store<2>(row, lane, keep, cap, out);
+    else
+        row_sort_store<4>(row, lane, keep, cap, out);
     if (lane == 0) {
         cnt[i] = keep;
         // same-address device atomics serialise across the whole grid: only
