@@ -708,6 +708,11 @@ extern "C" int mlmix_create(const mlmix_model_desc *desc, mlmix_ctx **out)
     }
     c.o3 = t.o3 ? 1 : 0;
     c.o3_nch2 = t.o3_nch2;
+    if (const char *e = std::getenv("MLMIX_O3_MAX_SPLIT")) {
+        int v = std::atoi(e);
+        if (v == 1 || v == 2 || v == 4 || v == 8)
+            c.o3_max_split = v;
+    }
     if (const char *e = std::getenv("MLMIX_BASIS_MFMA"))
         c.basis_mfma = std::atoi(e) ? 1 : 0;  // VALU kernels (comparisons)
     if (const char *e = std::getenv("MLMIX_ACE_O3"))

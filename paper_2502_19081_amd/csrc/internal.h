@@ -98,6 +98,9 @@ struct Ctx {
     int o3 = 0;            // order-3 contraction on the per-wave matrix-core kernel
     int basis_mfma = 1;    // atomic basis and pair adjoint on the matrix cores (FP32)
     int o3_nch2 = 0;       // row width of that kernel (channels rounded up to 4)
+    // largest tile split of that kernel: 4 measured best on the 8,193-atom
+    // cell (910 atoms in S: contraction 92 / 52 / 37 / 48 us at 1 / 2 / 4 / 8)
+    int o3_max_split = 4;
     int ace_tile = 4;      // atoms per order-3 block workgroup (tuning)
     int ace_stage_w = 1;   // stage the block's weights in LDS (tuning)
     int device;

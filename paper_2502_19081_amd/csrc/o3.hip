@@ -56,6 +56,7 @@ struct O3Args {
     const int *dp_off;    // per-block offset in the partial buffer
     const PBlock *pb;
     int n_pb, nch, L1, L2, KAt, dp_stride;
+    int max_split;  // largest G the kernel may choose (1, 2, 4 or 8)
 };
 
 constexpr int kO3Atoms = 16;
@@ -148,7 +149,7 @@ __global__ void __launch_bounds__(256, 1)
     const int nS = hdr[H_NS];
     const int ntile = (nS + kO3Atoms - 1) / kO3Atoms;
     int G = 1, lg = 0;
-    while (G < kO3MaxSplit && ntile * G < (int)gridDim.x) {
+    while (G < a.max_split && ntile * G < (int)gridDim.x) {
         G <<= 1;
         ++lg;
     }
@@ -339,6 +340,7 @@ void launch_ace_o3(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L)
     a.L2 = m.L2;
     a.KAt = m.KAt;
     a.dp_stride = m.dp_stride;
+    a.max_split = c.o3_max_split;
     const size_t lds = o3_lds_bytes(c);
     const int per_cu = lds <= 80 * 1024 ? 2 : 1;
     // persistent grid: one wave of resident workgroups; the kernel splits
