@@ -468,9 +468,20 @@ __global__ void __launch_bounds__(256)
             }
         }
         T D3 = T(0);
-        if (a.order >= 3)
-            for (int p = plo[l]; p < phi[l]; ++p)
+        if (a.order >= 3) {
+            // all block loads first (independent), then the sum in block order
+            constexpr int kPre = 16;
+            const int p0 = plo[l], np = phi[l] - p0;
+            T v[kPre];
+#pragma unroll
+            for (int k = 0; k < kPre; ++k)
+                v[k] = k < np ? Ds[dpo[p0 + k] + m3 * nch + c] : T(0);
+#pragma unroll
+            for (int k = 0; k < kPre; ++k)
+                D3 += v[k];
+            for (int p = p0 + kPre; p < phi[l]; ++p)
                 D3 += Ds[dpo[p] + m3 * nch + c];
+        }
         const T Av = As[e];
         dEdA[(size_t)s * KAt + e] = c1t + T(2) * D2 + T(3) * D3;
         es += (double)(Av * (c1t + D2 + D3));

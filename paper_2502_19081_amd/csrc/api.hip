@@ -1036,13 +1036,13 @@ extern "C" int mlmix_vv_step(mlmix_ctx *ctx, void *stream, void *ws, int32_t n_a
                       e_exp, e_cheap, lambda, flags, n_expensive, nullptr, nullptr);
     if (rc)
         return rc;
-    {
+    if (energies) {
+        // closing half kick fused with the energy partial sums
+        StageTimer t(ctx, s, ST_RED);
+        launch_vv_kick_sums(s, ws, L, vel, mass, forces, dt, e_exp, e_cheap, energies);
+    } else {
         StageTimer t(ctx, s, ST_VV);
         launch_vv_kick_drift(s, ws, L, b, pos, vel, mass, forces, dt, 0);
-    }
-    if (energies) {
-        StageTimer t(ctx, s, ST_RED);
-        launch_reduce(s, ws, L, e_exp, e_cheap, vel, mass, energies);
     }
     HIP_OK(hipGetLastError());
     return MLMIX_OK;

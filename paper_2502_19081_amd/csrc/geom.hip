@@ -825,43 +825,32 @@ __global__ void __launch_bounds__(256) k_cmp_blocksum(const uint8_t *__restrict_
     }
 }
 
-__global__ void __launch_bounds__(256) k_cmp_top(int *__restrict__ partS, int *__restrict__ partM,
-                                                 int nb, int *hdr, int32_t *n_expensive)
-{
-    __shared__ int sh[4];
-    int cs = 0, cm = 0;
-    for (int base = 0; base < nb; base += 256) {
-        int i = base + threadIdx.x;
-        int vs = i < nb ? partS[i] : 0;
-        int vm = i < nb ? partM[i] : 0;
-        int ts, tm;
-        int es = block_excl_scan(vs, sh, ts);
-        int em = block_excl_scan(vm, sh, tm);
-        if (i < nb) {
-            partS[i] = cs + es;
-            partM[i] = cm + em;
-        }
-        cs += ts;
-        cm += tm;
-    }
-    if (threadIdx.x == 0) {
-        hdr[H_NS] = cs;
-        hdr[H_NM] = cm;
-        if (n_expensive) {
-            n_expensive[0] = cs;
-            n_expensive[1] = cm;
-        }
-    }
-}
-
+// Second pass: each block adds the block totals before it (a fixed-order
+// reduction, so no third launch is needed) and writes its part of S and M;
+// the last block also publishes |S| and |M|.
 __global__ void __launch_bounds__(256) k_cmp_apply(const uint8_t *__restrict__ flags, int n,
                                                    const int *__restrict__ partS,
-                                                   const int *__restrict__ partM,
-                                                   int *__restrict__ S_idx,
+                                                   const int *__restrict__ partM, int *hdr,
+                                                   int32_t *n_expensive, int *__restrict__ S_idx,
                                                    int *__restrict__ M_idx,
                                                    int *__restrict__ S_local)
 {
     __shared__ int sh[4];
+    __shared__ int offs[2];
+    // offsets of this block: sums of partS/partM over the blocks before it
+    int os = 0, om = 0;
+    for (int b = threadIdx.x; b < (int)blockIdx.x; b += 256) {
+        os += partS[b];
+        om += partM[b];
+    }
+    int ts, tm;
+    block_excl_scan(os, sh, ts);
+    block_excl_scan(om, sh, tm);
+    if (threadIdx.x == 0) {
+        offs[0] = ts;
+        offs[1] = tm;
+    }
+    __syncthreads();
     int base = blockIdx.x * kScanTile + threadIdx.x * kPer;
     uint8_t f[kPer];
     int s = 0, m = 0;
@@ -870,9 +859,9 @@ __global__ void __launch_bounds__(256) k_cmp_apply(const uint8_t *__restrict__ f
         s += (f[k] & 5) ? 1 : 0;
         m += (f[k] & 1) ? 1 : 0;
     }
-    int ts, tm;
-    int es = block_excl_scan(s, sh, ts) + partS[blockIdx.x];
-    int em = block_excl_scan(m, sh, tm) + partM[blockIdx.x];
+    int bs, bm;
+    int es = block_excl_scan(s, sh, bs) + offs[0];
+    int em = block_excl_scan(m, sh, bm) + offs[1];
     for (int k = 0; k < kPer; ++k) {
         int i = base + k;
         if (i >= n)
@@ -889,6 +878,14 @@ __global__ void __launch_bounds__(256) k_cmp_apply(const uint8_t *__restrict__ f
             em++;
         }
     }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
+        hdr[H_NS] = offs[0] + bs;
+        hdr[H_NM] = offs[1] + bm;
+        if (n_expensive) {
+            n_expensive[0] = offs[0] + bs;
+            n_expensive[1] = offs[1] + bm;
+        }
+    }
 }
 
 void launch_compact(hipStream_t s, void *ws, const WsLayout &L, uint8_t *flags,
@@ -901,9 +898,9 @@ void launch_compact(hipStream_t s, void *ws, const WsLayout &L, uint8_t *flags,
     int *partS = at<int>(ws, L.scan_part);
     int *partM = partS + nb;
     k_cmp_blocksum<<<nb, 256, 0, s>>>(flags, n, partS, partM);
-    k_cmp_top<<<1, 256, 0, s>>>(partS, partM, nb, at<int>(ws, L.hdr), n_expensive);
-    k_cmp_apply<<<nb, 256, 0, s>>>(flags, n, partS, partM, at<int>(ws, L.S_idx),
-                                   at<int>(ws, L.M_idx), at<int>(ws, L.S_local));
+    k_cmp_apply<<<nb, 256, 0, s>>>(flags, n, partS, partM, at<int>(ws, L.hdr), n_expensive,
+                                   at<int>(ws, L.S_idx), at<int>(ws, L.M_idx),
+                                   at<int>(ws, L.S_local));
 }
 
 }  // namespace mlmix

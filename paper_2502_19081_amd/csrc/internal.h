@@ -148,6 +148,9 @@ void launch_gather_blend(hipStream_t s, const Ctx &c, void *ws, const WsLayout &
                          int use_cheap, const double *lambda, double *forces, double *e_exp,
                          double *f_exp, double *f_cheap, double sign);
 void launch_fill_f64(hipStream_t s, double *p, double v, size_t n);
+void launch_vv_kick_sums(hipStream_t s, void *ws, const WsLayout &L, double *vel,
+                         const double *mass, const double *forces, double dt, const double *e_exp,
+                         const double *e_cheap, double *out);
 void launch_reduce(hipStream_t s, void *ws, const WsLayout &L, const double *e_exp,
                    const double *e_cheap, const double *vel, const double *mass, double *out);
 void launch_vv_kick_drift(hipStream_t s, void *ws, const WsLayout &L, const Box &b, double *pos,

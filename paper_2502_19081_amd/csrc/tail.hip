@@ -236,6 +236,62 @@ __global__ void __launch_bounds__(256) k_vv(int n, Box b, double *__restrict__ p
     }
 }
 
+// Closing half kick of a step fused with the per-block energy partials
+// (same grid-stride partition and block reduction as k_reduce_partial; the
+// kinetic energy uses the kicked velocities).
+__global__ void __launch_bounds__(256) k_vv_kick_sums(int n, double *__restrict__ vel,
+                                                      const double *__restrict__ mass,
+                                                      const double *__restrict__ f, double dt,
+                                                      const double *__restrict__ e_exp,
+                                                      const double *__restrict__ e_cheap,
+                                                      double *__restrict__ part)
+{
+    __shared__ double sh[3][4];
+    double a = 0.0, bsum = 0.0, k = 0.0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const double c = 0.5 * dt * kKappa / mass[i];
+        double v2 = 0.0;
+        for (int q = 0; q < 3; ++q) {
+            const double v = vel[q * n + i] + c * f[q * n + i];
+            vel[q * n + i] = v;
+            v2 += v * v;
+        }
+        a += e_exp[i];
+        bsum += e_cheap[i];
+        k += 0.5 * mass[i] * v2;
+    }
+    a = wave_sum_d(a);
+    bsum = wave_sum_d(bsum);
+    k = wave_sum_d(k);
+    int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        sh[0][w] = a;
+        sh[1][w] = bsum;
+        sh[2][w] = k;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int q = 0; q < 3; ++q)
+            part[blockIdx.x * 3 + q] = (sh[q][0] + sh[q][1]) + (sh[q][2] + sh[q][3]);
+    }
+}
+
+void launch_vv_kick_sums(hipStream_t s, void *ws, const WsLayout &L, double *vel,
+                         const double *mass, const double *forces, double dt, const double *e_exp,
+                         const double *e_cheap, double *out)
+{
+    if (L.n == 0) {
+        launch_reduce(s, ws, L, e_exp, e_cheap, vel, mass, out);
+        return;
+    }
+    double *part = at<double>(ws, L.red);
+    int nb = (L.n + 255) / 256;
+    if (nb > kReduceBlocks)
+        nb = kReduceBlocks;
+    k_vv_kick_sums<<<nb, 256, 0, s>>>(L.n, vel, mass, forces, dt, e_exp, e_cheap, part);
+    k_reduce_final<<<1, 256, 0, s>>>(part, nb, out);
+}
+
 void launch_vv_kick_drift(hipStream_t s, void *ws, const WsLayout &L, const Box &b, double *pos,
                           double *vel, const double *mass, const double *forces, double dt,
                           int drift)
