@@ -270,6 +270,10 @@ __global__ void __launch_bounds__(256) k_cell_fill(const double *__restrict__ po
     atoms[slot] = r;
 }
 
+// Systems up to these sizes take the one-workgroup binning path.
+constexpr int kSmallAtoms = 16384;
+constexpr int kSmallCells = 16384;
+
 // Cell binning of a small system in one 1024-thread workgroup: counts in
 // LDS, exclusive scan, cell starts to HBM, records filled through LDS
 // cursors. On a forced rebuild it also raises the rebuild flag (otherwise
@@ -293,33 +297,27 @@ __global__ void __launch_bounds__(1024) k_bin_small(const double *__restrict__ p
         cnt[c] = 0;
     __syncthreads();
     int bad = 0, out = 0;
-    // batches of eight atoms per thread: all position loads issued first
-    for (int i0 = 0; i0 < n; i0 += 8 * 1024) {
-        double x[8][3];
+    // each thread owns up to 64 atoms (i = tid + 1024 u); their positions and
+    // cells stay in registers from the count pass to the fill pass
+    constexpr int kU = kSmallAtoms / 1024;
+    int cl[kU];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int i = i0 + u * 1024 + tid;
-#pragma unroll
-            for (int k = 0; k < 3; ++k)
-                x[u][k] = i < n ? pos[k * n + i] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int i = i0 + u * 1024 + tid;
-            if (i >= n)
-                continue;
+    for (int u = 0; u < kU; ++u) {
+        const int i = tid + 1024 * u;
+        cl[u] = -1;
+        if (i < n) {
             int c[3];
             for (int k = 0; k < 3; ++k) {
-                const double xv = x[u][k];
+                const double xv = pos[k * n + i];
                 if (!(xv == xv) || xv < -1.0e300 || xv > 1.0e300)
                     bad = 1;
                 if (!b.per[k] && (xv < 0.0 || xv >= b.L[k]))
                     out = 1;
                 c[k] = cell_coord(xv, g, k);
             }
-            const int cell = (c[2] * g.nc[1] + c[1]) * g.nc[0] + c[0];
-            cell_of[i] = cell;
-            atomicAdd(&cnt[cell], 1);
+            cl[u] = (c[2] * g.nc[1] + c[1]) * g.nc[0] + c[0];
+            cell_of[i] = cl[u];
+            atomicAdd(&cnt[cl[u]], 1);
         }
     }
     if (bad)
@@ -346,27 +344,15 @@ __global__ void __launch_bounds__(1024) k_bin_small(const double *__restrict__ p
     if (tid == 0)
         start[ncell] = tot;
     __syncthreads();
-    for (int i0 = 0; i0 < n; i0 += 8 * 1024) {
-        int cl[8];
-        double x[8][3];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int i = i0 + u * 1024 + tid;
-            cl[u] = i < n ? cell_of[i] : 0;
-#pragma unroll
-            for (int k = 0; k < 3; ++k)
-                x[u][k] = i < n ? pos[k * n + i] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int i = i0 + u * 1024 + tid;
-            if (i >= n)
-                continue;
+    for (int u = 0; u < kU; ++u) {
+        const int i = tid + 1024 * u;
+        if (cl[u] >= 0) {
             const int slot = atomicAdd(&cnt[cl[u]], 1);
             CellAtom r;
-            r.x = x[u][0];
-            r.y = x[u][1];
-            r.z = x[u][2];
+            r.x = pos[i];
+            r.y = pos[n + i];
+            r.z = pos[2 * n + i];
             r.j = i;
             r.pad = 0;
             atoms[slot] = r;
@@ -443,12 +429,11 @@ __device__ __forceinline__ void row_sort_store(const int *row, int lane, int kee
 }
 
 // One wavefront per atom, four atoms per 256-thread block, no block-level
-// barriers (each wave works in its own LDS slices). The (up to) 5x5x5
-// stencil of half-radius cells is flattened: lanes first look up the
-// stencil cells' ranges and prefix-sum their sizes, then sweep the candidate
-// list 64 at a time (one 32-byte cell-ordered record per candidate), keep
-// partners closer than the list radius by ballot compaction, and finally
-// sort the row ascending in registers (bitonic over 64, 128 or 256 keys).
+// barriers (each wave works in its own LDS slice). Each lane owns up to two
+// cells of the (up to) 5x5x5 stencil of half-radius cells and walks their
+// 32-byte cell-ordered records two at a time (loads issued first); partners
+// closer than the list radius are kept by ballot compaction, and the row is
+// finally sorted ascending in registers (bitonic over 64, 128 or 256 keys).
 __global__ void __launch_bounds__(256) k_neighbors(const double *__restrict__ pos, int n, Box b,
                                                    Grid g, const int *__restrict__ start,
                                                    const CellAtom *__restrict__ atoms, double rl2,
@@ -460,8 +445,6 @@ __global__ void __launch_bounds__(256) k_neighbors(const double *__restrict__ po
     if (hdr[H_REBUILD] == 0)
         return;
     __shared__ int rows[4][kMaxCap];
-    __shared__ int cbeg[4][128];
-    __shared__ int coff[4][129];
     const int w = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     const int i = blockIdx.x * 4 + w;
@@ -509,50 +492,47 @@ __global__ void __launch_bounds__(256) k_neighbors(const double *__restrict__ po
             }
         }
     }
-    int inc0 = wave_incl_scan(sz[0]);
-    int tot0 = __shfl(inc0, 63);
-    int inc1 = wave_incl_scan(sz[1]);
-    int ncand = tot0 + __shfl(inc1, 63);
-    cbeg[w][lane] = bg[0];
-    cbeg[w][lane + 64] = bg[1];
-    coff[w][lane] = inc0 - sz[0];
-    coff[w][lane + 64] = tot0 + inc1 - sz[1];
-    if (lane == 0)
-        coff[w][128] = ncand;
-    wave_sync_lds();
+    // every lane walks its own stencil cells (t and t + 64), kB records of
+    // each at a time with all their loads issued before the distance tests
+    int szmax = max(sz[0], sz[1]);
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1)
+        szmax = max(szmax, __shfl_xor(szmax, d));
     int c = 0;
-    for (int r0 = 0; r0 < ncand; r0 += 64) {
-        int q = r0 + lane;
-        bool hit = false;
-        int j = 0;
-        if (q < ncand) {
-            // stencil cell u with coff[u] <= q < coff[u+1] (empty cells repeat offsets)
-            int lo = 0, hi = 127;
-            while (lo < hi) {
-                int mid = (lo + hi + 1) >> 1;
-                if (coff[w][mid] <= q)
-                    lo = mid;
-                else
-                    hi = mid - 1;
-            }
-            CellAtom rec = atoms[cbeg[w][lo] + (q - coff[w][lo])];
-            j = rec.j;
-            double d[3] = {rec.x - xi[0], rec.y - xi[1], rec.z - xi[2]};
-            for (int k = 0; k < 3; ++k) {
-                if (b.per[k]) {
-                    double h = 0.5 * b.L[k];
-                    double dx = d[k];
-                    dx = dx > h ? dx - b.L[k] : (dx < -h ? dx + b.L[k] : dx);
-                    d[k] = dx;
+    constexpr int kB = 2;  // records per cell per round (register budget)
+    for (int k0 = 0; k0 < szmax; k0 += kB) {
+        CellAtom rec[2][kB];
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int u = 0; u < kB; ++u)
+                if (k0 + u < sz[h])
+                    rec[h][u] = atoms[bg[h] + k0 + u];
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int u = 0; u < kB; ++u) {
+                bool hit = false;
+                int j = 0;
+                if (k0 + u < sz[h]) {
+                    j = rec[h][u].j;
+                    double d[3] = {rec[h][u].x - xi[0], rec[h][u].y - xi[1], rec[h][u].z - xi[2]};
+                    for (int k = 0; k < 3; ++k) {
+                        if (b.per[k]) {
+                            double hh = 0.5 * b.L[k];
+                            double dx = d[k];
+                            dx = dx > hh ? dx - b.L[k] : (dx < -hh ? dx + b.L[k] : dx);
+                            d[k] = dx;
+                        }
+                    }
+                    hit = (j != i) && norm2(d) < rl2;
                 }
+                unsigned long long m = __ballot(hit);
+                int p = c + __popcll(m & ((1ull << lane) - 1ull));
+                if (hit && p < P)
+                    row[p] = j;
+                c += __popcll(m);
             }
-            hit = (j != i) && norm2(d) < rl2;
-        }
-        unsigned long long m = __ballot(hit);
-        int p = c + __popcll(m & ((1ull << lane) - 1ull));
-        if (hit && p < P)
-            row[p] = j;
-        c += __popcll(m);
     }
     wave_sync_lds();
     const int keep = c < cap ? c : cap;
@@ -614,9 +594,6 @@ __global__ void k_finish_rebuild(int *hdr)
         hdr[H_BUILT] = 1;
 }
 
-// Systems up to these sizes take the one-workgroup binning path.
-constexpr int kSmallAtoms = 65536;
-constexpr int kSmallCells = 16384;
 
 void launch_neighbors(hipStream_t s, void *ws, const WsLayout &L, const Box &b, double r_list,
                       const double *pos, int force_rebuild, double skin)
