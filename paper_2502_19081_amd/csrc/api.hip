@@ -187,7 +187,7 @@ static std::vector<double> gaunt(int lmax, const std::vector<double> &K)
 }
 
 struct HostTables {
-    std::vector<double> K, c0, c1, c2s, W, gval, u2, u3, wsc;
+    std::vector<double> K, c0, c1, c2s, W, gval, u2, u3, up2, up3, wsc;
     std::vector<PBlock> pb;
     std::vector<int> gm3, gidx, gofs, dpoff;
     int w_per_species = 0;
@@ -323,6 +323,81 @@ static void build_o3(const mlmix_model_desc &d, HostTables &t)
     t.o3 = true;
 }
 
+// Clamped uniform cubic B-splines on knots t(i) = clamp(i - 3, 0, npts - 1)
+// (unit spacing): the four non-zero basis values at x by the Cox-de Boor
+// recursion (host only: fits the per-span polynomials below).
+static void host_bspline4(double x, int npts, int &first, double N[4])
+{
+    int sp = (int)std::floor(x);
+    sp = sp < 0 ? 0 : (sp > npts - 2 ? npts - 2 : sp);
+    const int k = sp + 3;
+    auto t = [&](int q) -> double {
+        int v = q - 3;
+        v = v < 0 ? 0 : (v > npts - 1 ? npts - 1 : v);
+        return double(v);
+    };
+    double left[4], right[4], Nn[4];
+    Nn[0] = 1.0;
+    for (int j = 1; j <= 3; ++j) {
+        left[j] = x - t(k + 1 - j);
+        right[j] = t(k + j) - x;
+        double saved = 0.0;
+        for (int r = 0; r < j; ++r) {
+            double temp = Nn[r] / (right[r + 1] + left[j - r]);
+            Nn[r] = saved + right[r + 1] * temp;
+            saved = left[j - r] * temp;
+        }
+        Nn[j] = saved;
+    }
+    for (int r = 0; r < 4; ++r)
+        N[r] = Nn[r];
+    first = sp;
+}
+
+// Per-span cubic coefficients of the four basis functions in the local
+// coordinate t = x/h - span (knot spacing h drops out): values at four
+// interior points of each span, solved as a 4x4 Vandermonde system.
+static std::vector<double> bspline_span_poly(int npts)
+{
+    std::vector<double> out((size_t)std::max(0, npts - 1) * 16, 0.0);
+    const double tm[4] = {0.125, 0.375, 0.625, 0.875};
+    for (int sp = 0; sp + 1 < npts; ++sp) {
+        double Nv[4][4];  // [point][basis]
+        for (int q = 0; q < 4; ++q) {
+            int f;
+            host_bspline4(sp + tm[q], npts, f, Nv[q]);
+        }
+        for (int r = 0; r < 4; ++r) {
+            double A[4][5];
+            for (int q = 0; q < 4; ++q) {
+                double p = 1.0;
+                for (int e = 0; e < 4; ++e) {
+                    A[q][e] = p;
+                    p *= tm[q];
+                }
+                A[q][4] = Nv[q][r];
+            }
+            for (int c = 0; c < 4; ++c) {  // Gaussian elimination, partial pivoting
+                int piv = c;
+                for (int q = c + 1; q < 4; ++q)
+                    if (std::fabs(A[q][c]) > std::fabs(A[piv][c]))
+                        piv = q;
+                for (int e = 0; e < 5; ++e)
+                    std::swap(A[c][e], A[piv][e]);
+                for (int q = 0; q < 4; ++q)
+                    if (q != c) {
+                        double fct = A[q][c] / A[c][c];
+                        for (int e = c; e < 5; ++e)
+                            A[q][e] -= fct * A[c][e];
+                    }
+            }
+            for (int e = 0; e < 4; ++e)
+                out[(size_t)sp * 16 + r * 4 + e] = A[e][4] / A[e][e];
+        }
+    }
+    return out;
+}
+
 static int build_tables(const mlmix_model_desc &d, HostTables &t)
 {
     const int ns = d.n_species, nr = d.ace_n_rad, lmax = d.ace_lmax;
@@ -411,6 +486,8 @@ static int build_tables(const mlmix_model_desc &d, HostTables &t)
     build_o3(d, t);
     // cheap model
     int nb2 = d.uf3_n_knots2 + 2;
+    t.up2 = bspline_span_poly(d.uf3_n_knots2);
+    t.up3 = bspline_span_poly(d.uf3_n_knots3 > 0 ? d.uf3_n_knots3 : 2);
     t.u2.assign(d.uf3_c2, d.uf3_c2 + (size_t)ns * ns * nb2);
     for (int a = 0; a < ns; ++a)
         for (int b = 0; b < ns; ++b)
@@ -467,6 +544,8 @@ static std::vector<char> pack(const HostTables &t, DevModel &m)
     append_raw(blob, m.gofs, t.gofs);
     append<T>(blob, m.u2, t.u2);
     append<T>(blob, m.u3, t.u3);
+    append<T>(blob, m.up2, t.up2);
+    append<T>(blob, m.up3, t.up3);
     append_raw(blob, m.dpoff, t.dpoff);
     append<float>(blob, m.wsc, t.wsc);
     append_raw(blob, m.o3o, t.o3o);

@@ -19,52 +19,29 @@ struct Uf3Args {
     double rc2sq, rc3sq;
     T h2, ih2, h3, ih3, h3c, ih3c;
     const T *c2, *c3;
+    const T *p2, *p3;  // per-span B-spline polynomial coefficients [npts - 1][4][4]
 };
 
-// The four non-zero clamped uniform cubic B-splines at x (first index
-// `first`) and their derivatives; knots t(i) = h * clamp(i - 3, 0, npts - 1).
+// The four non-zero clamped uniform cubic B-splines at x and their
+// derivatives from the per-span cubic coefficients (Horner, no division):
+// span sp = clamp(floor(x / h), 0, npts - 2), t = x / h - sp, basis r of the
+// span = sum_e poly[16 sp + 4 r + e] t^e, derivative / h.
 template <typename T>
-__device__ __forceinline__ void bspline4(T x, T h, T ih, int npts, int &first, T N[4], T dN[4])
+__device__ __forceinline__ void bspline4p(T x, T ih, int npts, const T *__restrict__ poly, int &first,
+                                          T N[4], T dN[4])
 {
-    int sp = (int)floor(x * ih);
-    if (sp < 0)
-        sp = 0;
-    if (sp > npts - 2)
-        sp = npts - 2;
-    int k = sp + 3;
-    auto t = [&](int q) -> T {
-        int v = q - 3;
-        v = v < 0 ? 0 : (v > npts - 1 ? npts - 1 : v);
-        return h * T(v);
-    };
-    T left[4], right[4], Nn[4], N2[3];
-    Nn[0] = T(1);
-#pragma unroll
-    for (int j = 1; j <= 3; ++j) {
-        left[j] = x - t(k + 1 - j);
-        right[j] = t(k + j) - x;
-        T saved = T(0);
-#pragma unroll
-        for (int r = 0; r < j; ++r) {
-            T temp = Nn[r] / (right[r + 1] + left[j - r]);
-            Nn[r] = saved + right[r + 1] * temp;
-            saved = left[j - r] * temp;
-        }
-        Nn[j] = saved;
-        if (j == 2) {
-            N2[0] = Nn[0];
-            N2[1] = Nn[1];
-            N2[2] = Nn[2];
-        }
-    }
+    const T u = x * ih;
+    int sp = (int)floor(u);
+    sp = sp < 0 ? 0 : (sp > npts - 2 ? npts - 2 : sp);
+    const T t = u - T(sp);
+    const T *c = poly + 16 * sp;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        N[r] = Nn[r];
-        T a = (r >= 1) ? N2[r - 1] / (t(k + r) - t(k + r - 3)) : T(0);
-        T b = (r <= 2) ? N2[r] / (t(k + r + 1) - t(k + r - 2)) : T(0);
-        dN[r] = T(3) * (a - b);
+        const T a0 = c[4 * r], a1 = c[4 * r + 1], a2 = c[4 * r + 2], a3 = c[4 * r + 3];
+        N[r] = ((a3 * t + a2) * t + a1) * t + a0;
+        dN[r] = ((T(3) * a3 * t + T(2) * a2) * t + a1) * ih;
     }
-    first = k - 3;
+    first = sp;
 }
 
 // d = x_j - x_i folded once along periodic dimensions; returns |d|^2 (FP64,
@@ -143,6 +120,14 @@ __global__ void __launch_bounds__(256)
     int *ibase = reinterpret_cast<int *>(reinterpret_cast<T *>(smem_raw) + 4 * (size_t)sl.nT);
     int *f3 = ibase + w * 2 * kMaxTriplet;
     int *sl3 = f3 + kMaxTriplet;
+    // per-span B-spline polynomials, shared by the block
+    T *pp2 = reinterpret_cast<T *>(ibase + 4 * 2 * kMaxTriplet);
+    T *pp3 = pp2 + 16 * (a.nk2 - 1);
+    for (int e = threadIdx.x; e < 16 * (a.nk2 - 1); e += blockDim.x)
+        pp2[e] = a.p2[e];
+    if (a.nb3 > 0)
+        for (int e = threadIdx.x; e < 16 * (a.nk3 - 1); e += blockDim.x)
+            pp3[e] = a.p3[e];
     __shared__ int count3[4];
     __shared__ int cmax_s[4];
     const int zi = valid ? sp_clamp(species[i], a.ns) : 0;
@@ -172,7 +157,7 @@ __global__ void __launch_bounds__(256)
                 T r = T(rd);
                 int f;
                 T N[4], dN[4];
-                bspline4<T>(r, a.h2, a.ih2, a.nk2, f, N, dN);
+                bspline4p<T>(r, a.ih2, a.nk2, pp2, f, N, dN);
                 const T *cc = a.c2 + ((size_t)zi * a.ns + sp_clamp(species[j], a.ns)) * a.nb2 + f;
                 T V = T(0), dV = T(0);
 #pragma unroll
@@ -200,7 +185,7 @@ __global__ void __launch_bounds__(256)
             sl3[p] = slot;
             int f;
             T N[4], dN[4];
-            bspline4<T>(T(rd), a.h3, a.ih3, a.nk3, f, N, dN);
+            bspline4p<T>(T(rd), a.ih3, a.nk3, pp3, f, N, dN);
             f3[p] = f;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
@@ -245,7 +230,7 @@ __global__ void __launch_bounds__(256)
                     T rjk = sqrt(e0 * e0 + e1 * e1 + e2 * e2);
                     int fs;
                     T Ns[4], dNs[4];
-                    bspline4<T>(rjk, a.h3c, a.ih3c, a.nk3, fs, Ns, dNs);
+                    bspline4p<T>(rjk, a.ih3c, a.nk3, pp3, fs, Ns, dNs);
                     int fk = f3[k];
                     T V = T(0), V1 = T(0), V3 = T(0);
 #pragma unroll
@@ -322,9 +307,12 @@ static void uf3_t(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L, cons
     char *base = static_cast<char *>(m.base);
     a.c2 = reinterpret_cast<const T *>(base + m.u2);
     a.c3 = reinterpret_cast<const T *>(base + m.u3);
+    a.p2 = reinterpret_cast<const T *>(base + m.up2);
+    a.p3 = reinterpret_cast<const T *>(base + m.up3);
     int nb3c = m.nb3 > 0 ? m.nb3 * m.nb3 * m.nb3 : 0;
     Uf3Slice sl = uf3_slice(L.cap, nb3c);
-    size_t sm = 4 * ((size_t)sl.nT * sizeof(T) + 2 * kMaxTriplet * sizeof(int)) + 16;
+    size_t sm = 4 * ((size_t)sl.nT * sizeof(T) + 2 * kMaxTriplet * sizeof(int)) +
+                16 * ((size_t)(m.nk2 - 1) + (m.nb3 > 0 ? m.nk3 - 1 : 0)) * sizeof(T) + 16;
     k_uf3<T><<<(L.n + 3) / 4, 256, sm, s>>>(pos, L.n, b, species, L.cap, at<int>(ws, L.nbr),
                                  at<int>(ws, L.cnt), a, at<T>(ws, L.h), e_cheap,
                                  at<int>(ws, L.hdr));
