@@ -62,10 +62,11 @@ struct O3Args {
 constexpr int kO3Atoms = 16;
 constexpr int kO3MaxGroups = 8;  // entries of one (block, m3) row: at most 4 x 8
 
-// bytes of one P row per format (16-byte pad keeps rows 4 banks apart)
+// bytes of one P row per format (16-byte pad keeps rows 4 banks apart); the
+// FP32 rows hold half of the channels a at a time (at most 8)
 __host__ __device__ constexpr int o3_row_bytes(int qm, int nc)
 {
-    return 4 * nc * 4 * (qm == 0 ? 4 : (qm == 1 ? 2 : 1)) + 16;
+    return qm == 0 ? 4 * (nc < 8 ? nc : 8) * 16 + 16 : 4 * nc * 4 * (qm == 1 ? 2 : 1) + 16;
 }
 
 __device__ __forceinline__ void wave_sync_lds()
@@ -85,6 +86,32 @@ __device__ __forceinline__ void o3_load_row(const int *__restrict__ e, int e0, i
 #pragma unroll
     for (int k = 0; k < kO3MaxGroups; ++k)
         ent[k] = src[4 * k];
+}
+
+// FP32 sparse stage of one row: the 16 atoms' 16x16 tiles P_t[a = m][b =
+// 4 q + v] stay in registers (cc[t]); the dense stage then stages them half a
+// channel range at a time.
+template <int NG>
+__device__ __forceinline__ void o3_sparse_regs(const float *__restrict__ At, int L2, int m,
+                                               const int2 (&ent)[kO3MaxGroups], f4v (&cc)[kO3Atoms])
+{
+#pragma unroll
+    for (int t = 0; t < kO3Atoms; t += 4) {
+        const float *A0 = At + (size_t)t * L2 * 16 + m;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            cc[t + u] = (f4v){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int k = 0; k < NG; ++k) {
+            const int o1 = ent[k].x & 0xffff, o2 = ent[k].x >> 16;
+            const float g = __int_as_float(ent[k].y);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const float *Au = A0 + u * L2 * 16;
+                cc[t + u] = __builtin_amdgcn_mfma_f32_16x16x4f32(Au[o2], g * Au[o1], cc[t + u], 0, 0, 0);
+            }
+        }
+    }
 }
 
 // Sparse stage of one row for the 16 atoms with NG entry groups (unrolled):
@@ -249,46 +276,77 @@ __global__ void __launch_bounds__(256, 1)
                     ngn = a.mt[2 * row + 3];
                     o3_load_row(a.e, a.mt[2 * row + 2], q, ent_n);
                 }
-                const float gsum = QM == 2 ? a.gs[row] * (1.0f / 240.0f) : 0.0f;
-                // ---- sparse stage: P_t for the 16 atoms, four at a time
-#define O3_SPARSE(NGV)                                                                        \
-    o3_sparse<QM, NC, NGV>(At, L2, L1, m, q, lane, ent, Pw, sP, amax, pbk.l1, pbk.l2, gsum)
-                switch (ng) {
-                case 0: O3_SPARSE(0); break;
-                case 1: O3_SPARSE(1); break;
-                case 2: O3_SPARSE(2); break;
-                case 3: O3_SPARSE(3); break;
-                case 4: O3_SPARSE(4); break;
-                case 5: O3_SPARSE(5); break;
-                case 6: O3_SPARSE(6); break;
-                case 7: O3_SPARSE(7); break;
-                default: O3_SPARSE(8); break;
-                }
-#undef O3_SPARSE
-                wave_sync_lds();
-                // ---- dense stage: D[atom m-row][c] over the 16 atoms
                 f4v acc = {0.f, 0.f, 0.f, 0.f};
                 const char *Prow = Pw + (size_t)m * rowb;
                 if constexpr (QM == 0) {
-#pragma unroll
-                    for (int i = 0; i < NC; ++i) {
-                        const f4v pv = *reinterpret_cast<const f4v *>(Prow + (q * NC + i) * 16);
-                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(pv[0], wf[i][0], acc, 0, 0, 0);
-                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(pv[1], wf[i][1], acc, 0, 0, 0);
-                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(pv[2], wf[i][2], acc, 0, 0, 0);
-                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(pv[3], wf[i][3], acc, 0, 0, 0);
+                    // ---- sparse stage into registers, then dense stage in
+                    // halves of the channel range a (P rows [b / 4][a % HW][b % 4],
+                    // HW = min(NC, 8) channels per half)
+                    f4v cc[kO3Atoms];
+#define O3_SPARSE(NGV) o3_sparse_regs<NGV>(At, L2, m, ent, cc)
+                    switch (ng) {
+                    case 0: O3_SPARSE(0); break;
+                    case 1: O3_SPARSE(1); break;
+                    case 2: O3_SPARSE(2); break;
+                    case 3: O3_SPARSE(3); break;
+                    case 4: O3_SPARSE(4); break;
+                    case 5: O3_SPARSE(5); break;
+                    case 6: O3_SPARSE(6); break;
+                    case 7: O3_SPARSE(7); break;
+                    default: O3_SPARSE(8); break;
                     }
-                } else if constexpr (QM == 1) {
+#undef O3_SPARSE
 #pragma unroll
-                    for (int i = 0; i < NC / 2; ++i) {
-                        const bf8v pv = *reinterpret_cast<const bf8v *>(Prow + (q * NC + 2 * i) * 8);
-                        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(pv, wb[i], acc, 0, 0, 0);
+                    for (int a0 = 0; a0 < NC; a0 += 8) {
+                        constexpr int HW = NC < 8 ? NC : 8;
+                        const int hw = NC - a0 < HW ? NC - a0 : HW;
+                        if (m >= a0 && m < a0 + hw)
+#pragma unroll
+                            for (int t = 0; t < kO3Atoms; ++t)
+                                *reinterpret_cast<f4v *>(Pw + (size_t)t * rowb + (q * HW + m - a0) * 16) = cc[t];
+                        wave_sync_lds();
+#pragma unroll
+                        for (int i = 0; i < HW; ++i)
+                            if (i < hw) {
+                                const f4v pv = *reinterpret_cast<const f4v *>(Prow + (q * HW + i) * 16);
+                                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(pv[0], wf[a0 + i][0], acc, 0, 0, 0);
+                                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(pv[1], wf[a0 + i][1], acc, 0, 0, 0);
+                                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(pv[2], wf[a0 + i][2], acc, 0, 0, 0);
+                                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(pv[3], wf[a0 + i][3], acc, 0, 0, 0);
+                            }
+                        wave_sync_lds();  // the next half overwrites the rows
                     }
                 } else {
+                    const float gsum = QM == 2 ? a.gs[row] * (1.0f / 240.0f) : 0.0f;
+                    // ---- sparse stage: P_t for the 16 atoms, four at a time
+#define O3_SPARSE(NGV)                                                                        \
+    o3_sparse<QM, NC, NGV>(At, L2, L1, m, q, lane, ent, Pw, sP, amax, pbk.l1, pbk.l2, gsum)
+                    switch (ng) {
+                    case 0: O3_SPARSE(0); break;
+                    case 1: O3_SPARSE(1); break;
+                    case 2: O3_SPARSE(2); break;
+                    case 3: O3_SPARSE(3); break;
+                    case 4: O3_SPARSE(4); break;
+                    case 5: O3_SPARSE(5); break;
+                    case 6: O3_SPARSE(6); break;
+                    case 7: O3_SPARSE(7); break;
+                    default: O3_SPARSE(8); break;
+                    }
+#undef O3_SPARSE
+                    wave_sync_lds();
+                    // ---- dense stage: D[atom m-row][c] over the 16 atoms
+                    if constexpr (QM == 1) {
 #pragma unroll
-                    for (int i = 0; i < NC / 2; ++i) {
-                        const long pv = *reinterpret_cast<const long *>(Prow + (q * NC + 2 * i) * 4);
-                        acc = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(pv, w8[i], acc, 0, 0, 0);
+                        for (int i = 0; i < NC / 2; ++i) {
+                            const bf8v pv = *reinterpret_cast<const bf8v *>(Prow + (q * NC + 2 * i) * 8);
+                            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(pv, wb[i], acc, 0, 0, 0);
+                        }
+                    } else {
+#pragma unroll
+                        for (int i = 0; i < NC / 2; ++i) {
+                            const long pv = *reinterpret_cast<const long *>(Prow + (q * NC + 2 * i) * 4);
+                            acc = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(pv, w8[i], acc, 0, 0, 0);
+                        }
                     }
                 }
                 // lane holds D[atom = 4 q + v][c = m]
