@@ -787,6 +787,8 @@ extern "C" int mlmix_create(const mlmix_model_desc *desc, mlmix_ctx **out)
     }
     c.o3 = t.o3 ? 1 : 0;
     c.o3_nch2 = t.o3_nch2;
+    if (const char *e = std::getenv("MLMIX_FORK_AT"))
+        c.fork_at = std::atoi(e) ? 1 : 0;
     if (const char *e = std::getenv("MLMIX_O3_MAX_SPLIT")) {
         int v = std::atoi(e);
         if (v == 1 || v == 2 || v == 4 || v == 8)
@@ -936,25 +938,36 @@ static int compute_impl(mlmix_ctx *ctx, hipStream_t s, void *ws, const WsLayout 
         launch_neighbors(s, ws, L, b, c.r_list, pos, (mode & MLMIX_FORCE_REBUILD) ? 1 : 0,
                          c.d.skin);
     }
-    // fork: reverse slots and the cheap potential need only the list
-    if (fork) {
-        HIP_OK(hipEventRecord(sd.fork, s));
-        HIP_OK(hipStreamWaitEvent(sd.s, sd.fork, 0));
-    }
-    {
-        StageTimer t(ctx, s2, ST_REV);
-        launch_reverse(s2, ws, L);
-    }
-    if (!energy_only) {
-        if (m != MLMIX_MODE_ALL_EXPENSIVE) {
-            StageTimer t(ctx, s2, ST_UF3);
-            launch_uf3(s2, c, ws, L, b, pos, species, e_cheap);
-        } else {
-            launch_fill_f64(s2, e_cheap, 0.0, (size_t)L.n);
+    // fork: reverse slots and the cheap potential need only the list; they are
+    // started after the neighbour rows (fork_at 0) or after the atomic basis
+    // (fork_at 1, beside the matrix-core contraction)
+    auto fork_side = [&]() -> int {
+        if (fork) {
+            HIP_OK(hipEventRecord(sd.fork, s));
+            HIP_OK(hipStreamWaitEvent(sd.s, sd.fork, 0));
         }
+        {
+            StageTimer t(ctx, s2, ST_REV);
+            launch_reverse(s2, ws, L);
+        }
+        if (!energy_only) {
+            if (m != MLMIX_MODE_ALL_EXPENSIVE) {
+                StageTimer t(ctx, s2, ST_UF3);
+                launch_uf3(s2, c, ws, L, b, pos, species, e_cheap);
+            } else {
+                launch_fill_f64(s2, e_cheap, 0.0, (size_t)L.n);
+            }
+        }
+        if (fork)
+            HIP_OK(hipEventRecord(sd.join, sd.s));
+        return MLMIX_OK;
+    };
+    const bool late = c.fork_at == 1 && m != MLMIX_MODE_ALL_CHEAP;
+    if (!late) {
+        int rc = fork_side();
+        if (rc)
+            return rc;
     }
-    if (fork)
-        HIP_OK(hipEventRecord(sd.join, sd.s));
     {
         StageTimer t(ctx, s, ST_REG);
         launch_regions(s, ws, L, b, m, pos, species, c.m.ns, regions, n_regions, r_buffer, lambda,
@@ -968,6 +981,11 @@ static int compute_impl(mlmix_ctx *ctx, hipStream_t s, void *ws, const WsLayout 
         {
             StageTimer t(ctx, s, ST_BASIS);
             launch_ace_basis(s, c, ws, L, b, pos, species);
+        }
+        if (late) {
+            int rc = fork_side();
+            if (rc)
+                return rc;
         }
         {
             StageTimer t(ctx, s, ST_CONTRACT);

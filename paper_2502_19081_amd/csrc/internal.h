@@ -97,6 +97,7 @@ struct Ctx {
     int max_ent_pb;        // Gaunt entries of the largest single block
     int o3 = 0;            // order-3 contraction on the per-wave matrix-core kernel
     int basis_mfma = 1;    // atomic basis and pair adjoint on the matrix cores (FP32)
+    int fork_at = 0;       // second-stream fork after the rows (0) or the basis (1)
     int o3_nch2 = 0;       // row width of that kernel (channels rounded up to 4)
     // largest tile split of that kernel: 4 measured best on the 8,193-atom
     // cell (910 atoms in S: contraction 92 / 52 / 37 / 48 us at 1 / 2 / 4 / 8)
