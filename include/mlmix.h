@@ -88,6 +88,8 @@ extern "C" {
 #define MLMIX_STATUS_NONFINITE 4
 #define MLMIX_STATUS_TRIPLET_OVERFLOW 8
 #define MLMIX_STATUS_BAD_SPECIES 16
+#define MLMIX_STATUS_CELL_OVERFLOW 32 /* a cell held more atoms than its bucket
+                                         (4 x the mean occupancy + 8) */
 
 /* Model description (host memory; copied by mlmix_create).
  *

@@ -575,6 +575,7 @@ void pb_ranges(const Ctx &c, int *lo, int *hi)
 Grid make_grid(const Ctx &c, const Box &b)
 {
     Grid g;
+    g.bucket = 0;  // set with the workspace layout
     double half = 0.5 * c.r_list;
     g.ncell = 1;
     for (int k = 0; k < 3; ++k) {
@@ -600,6 +601,13 @@ WsLayout make_layout(const Ctx &c, int n, int cap, const Box &b)
         P <<= 1;
     L.P = P;
     L.grid = make_grid(c, b);
+    // cell buckets: four times the mean occupancy plus 8, at least 16
+    {
+        const double mean = (double)n / (double)L.grid.ncell;
+        int bk = (int)std::ceil(4.0 * mean + 8.0);
+        bk = (bk + 3) & ~3;
+        L.grid.bucket = bk < 16 ? 16 : bk;
+    }
     size_t tsz = c.prec == MLMIX_FP64 ? 8 : 4;
     size_t off = 0;
     auto take = [&](size_t &field, size_t bytes) {
@@ -607,15 +615,11 @@ WsLayout make_layout(const Ctx &c, int n, int cap, const Box &b)
         off = align_up(off + bytes);
     };
     size_t nn = (size_t)(n > 0 ? n : 1);
-    int nbc = (L.grid.ncell + kScanTile - 1) / kScanTile;
     int nba = (n + kScanTile - 1) / kScanTile;
-    int nsp = std::max(nbc, 2 * nba) + 2;
+    int nsp = 2 * nba + 2;  // compaction block totals
     take(L.hdr, H_COUNT * sizeof(int));
     take(L.cell_count, (size_t)L.grid.ncell * sizeof(int));
-    take(L.cell_cursor, (size_t)L.grid.ncell * sizeof(int));
-    take(L.cell_start, (size_t)(L.grid.ncell + 1) * sizeof(int));
-    take(L.cell_of, nn * sizeof(int));
-    take(L.cell_atoms, nn * sizeof(CellAtom));
+    take(L.cell_atoms, (size_t)L.grid.ncell * L.grid.bucket * sizeof(CellAtom));
     take(L.scan_part, (size_t)nsp * sizeof(int));
     take(L.nbr, nn * cap * sizeof(int));
     take(L.rev, nn * cap * sizeof(int));
@@ -878,6 +882,8 @@ extern "C" int mlmix_workspace_init(mlmix_ctx *ctx, void *stream, void *ws, size
         return fail(MLMIX_E_WORKSPACE, "workspace smaller than mlmix_workspace_size()");
     hipStream_t s = static_cast<hipStream_t>(stream);
     k_zero_i32<<<1, H_COUNT, 0, s>>>(at<int>(ws, L.hdr), H_COUNT);
+    // cell counts start at zero; afterwards every force gather clears them
+    k_zero_i32<<<(L.grid.ncell + 255) / 256, 256, 0, s>>>(at<int>(ws, L.cell_count), L.grid.ncell);
     HIP_OK(hipGetLastError());
     std::lock_guard<std::mutex> g(ctx->mu);
     ctx->ws[ws] = L;
@@ -901,6 +907,7 @@ static int lookup(mlmix_ctx *ctx, void *ws, int n, const mlmix_box *box, WsLayou
     Grid g = make_grid(ctx->c, b);
     if (g.nc[0] != L.grid.nc[0] || g.nc[1] != L.grid.nc[1] || g.nc[2] != L.grid.nc[2])
         return fail(MLMIX_E_ARG, "box grid changed: call mlmix_workspace_init again");
+    g.bucket = L.grid.bucket;
     L.grid = g;
     return MLMIX_OK;
 }
@@ -1168,6 +1175,9 @@ extern "C" int mlmix_status(mlmix_ctx *ctx, void *stream, void *ws, int32_t *sta
     int st = hdr[H_STATUS];
     if (st & (MLMIX_STATUS_NEIGH_OVERFLOW | MLMIX_STATUS_TRIPLET_OVERFLOW))
         return fail(MLMIX_E_NEIGH_OVERFLOW, "neighbour row capacity exceeded");
+    if (st & MLMIX_STATUS_CELL_OVERFLOW)
+        return fail(MLMIX_E_NEIGH_OVERFLOW, "cell bucket capacity exceeded (local density far "
+                                            "above the mean)");
     if (st & MLMIX_STATUS_NONFINITE)
         return fail(MLMIX_E_NONFINITE, "non-finite position");
     if (st & MLMIX_STATUS_BAD_SPECIES)

@@ -84,101 +84,7 @@ __device__ __forceinline__ int block_excl_scan(int v, int *sh, int &total)
     return off + x - v;
 }
 
-// Exclusive scan across a 1024-thread block (16 waves).
-__device__ __forceinline__ int block1024_excl_scan(int v, int *sh, int &total)
-{
-    int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    int x = wave_incl_scan(v);
-    if (lane == 63)
-        sh[w] = x;
-    __syncthreads();
-    int off = 0;
-    total = 0;
-#pragma unroll
-    for (int k = 0; k < 16; ++k) {
-        int s = sh[k];
-        if (k < w)
-            off += s;
-        total += s;
-    }
-    __syncthreads();
-    return off + x - v;
-}
-
 constexpr int kPer = kScanTile / 256;
-
-__global__ void __launch_bounds__(256) k_scan_blocksum(const int *__restrict__ in, int n,
-                                                       int *__restrict__ part, const int *gate)
-{
-    if (gate && *gate == 0)
-        return;
-    __shared__ int sh[4];
-    int base = blockIdx.x * kScanTile + threadIdx.x * kPer;
-    int s = 0;
-    for (int k = 0; k < kPer; ++k)
-        if (base + k < n)
-            s += in[base + k];
-    int tot;
-    block_excl_scan(s, sh, tot);
-    if (threadIdx.x == 0)
-        part[blockIdx.x] = tot;
-}
-
-// Exclusive scan of the block sums in place (one block); *total = sum.
-__global__ void __launch_bounds__(256) k_scan_top(int *__restrict__ part, int nb, int *total,
-                                                  const int *gate)
-{
-    if (gate && *gate == 0)
-        return;
-    __shared__ int sh[4];
-    int carry = 0;
-    for (int base = 0; base < nb; base += 256) {
-        int i = base + threadIdx.x;
-        int v = i < nb ? part[i] : 0;
-        int tot;
-        int ex = block_excl_scan(v, sh, tot);
-        if (i < nb)
-            part[i] = carry + ex;
-        carry += tot;
-    }
-    if (threadIdx.x == 0)
-        *total = carry;
-}
-
-__global__ void __launch_bounds__(256) k_scan_apply(const int *__restrict__ in, int n,
-                                                    const int *__restrict__ part,
-                                                    int *__restrict__ out, const int *gate)
-{
-    if (gate && *gate == 0)
-        return;
-    __shared__ int sh[4];
-    int base = blockIdx.x * kScanTile + threadIdx.x * kPer;
-    int v[kPer];
-    int s = 0;
-    for (int k = 0; k < kPer; ++k) {
-        v[k] = (base + k < n) ? in[base + k] : 0;
-        s += v[k];
-    }
-    int tot;
-    int ex = block_excl_scan(s, sh, tot) + part[blockIdx.x];
-    for (int k = 0; k < kPer; ++k) {
-        if (base + k < n)
-            out[base + k] = ex;
-        ex += v[k];
-    }
-}
-
-static void device_excl_scan(hipStream_t s, const int *in, int n, int *part, int *out,
-                             const int *gate)
-{
-    // out has n+1 entries; out[n] = total
-    int nb = (n + kScanTile - 1) / kScanTile;
-    if (nb < 1)
-        nb = 1;
-    k_scan_blocksum<<<nb, 256, 0, s>>>(in, n, part, gate);
-    k_scan_top<<<1, 256, 0, s>>>(part, nb, out + n, gate);
-    k_scan_apply<<<nb, 256, 0, s>>>(in, n, part, out, gate);
-}
 
 // ------------------------------------------------------ rebuild decision
 
@@ -210,158 +116,57 @@ __global__ void __launch_bounds__(256) k_displacement(const double *__restrict__
 
 // ------------------------------------------------------------ cell lists
 
-__global__ void __launch_bounds__(256) k_cell_zero(int *__restrict__ count, int *__restrict__ cursor,
-                                                   int ncell, const int *gate)
-{
-    if (*gate == 0)
-        return;
-    int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c < ncell) {
-        count[c] = 0;
-        cursor[c] = 0;
-    }
-}
-
-__global__ void __launch_bounds__(256) k_cell_count(const double *__restrict__ pos, int n, Box b,
-                                                    Grid g, int *__restrict__ cell_of,
-                                                    int *__restrict__ count, int *hdr)
-{
-    if (hdr[H_REBUILD] == 0)
-        return;
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n)
-        return;
-    int c[3];
-    bool bad = false;
-    for (int k = 0; k < 3; ++k) {
-        double x = pos[k * n + i];
-        if (!(x == x) || x < -1.0e300 || x > 1.0e300)
-            bad = true;
-        if (!b.per[k] && (x < 0.0 || x >= b.L[k]))
-            atomicOr(&hdr[H_STATUS], MLMIX_STATUS_OUT_OF_BOX);
-        c[k] = cell_coord(x, g, k);
-    }
-    if (bad)
-        atomicOr(&hdr[H_STATUS], MLMIX_STATUS_NONFINITE);
-    int cell = (c[2] * g.nc[1] + c[1]) * g.nc[0] + c[0];
-    cell_of[i] = cell;
-    atomicAdd(&count[cell], 1);
-}
-
-__global__ void __launch_bounds__(256) k_cell_fill(const double *__restrict__ pos, int n,
-                                                   const int *__restrict__ cell_of,
-                                                   const int *__restrict__ start,
-                                                   int *__restrict__ cursor,
-                                                   CellAtom *__restrict__ atoms, const int *hdr)
-{
-    if (hdr[H_REBUILD] == 0)
-        return;
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n)
-        return;
-    int c = cell_of[i];
-    int slot = start[c] + atomicAdd(&cursor[c], 1);
-    CellAtom r;
-    r.x = pos[i];
-    r.y = pos[n + i];
-    r.z = pos[2 * n + i];
-    r.j = i;
-    r.pad = 0;
-    atoms[slot] = r;
-}
-
-// Systems up to these sizes take the one-workgroup binning path.
-constexpr int kSmallAtoms = 16384;
-constexpr int kSmallCells = 16384;
-
-// Cell binning of a small system in one 1024-thread workgroup: counts in
-// LDS, exclusive scan, cell starts to HBM, records filled through LDS
-// cursors. On a forced rebuild it also raises the rebuild flag (otherwise
-// the flag comes from the displacement check before it) and, whenever the
-// list is rebuilt, marks the workspace as built. Order inside a cell
-// follows the atomics; the rows are sorted afterwards.
-__global__ void __launch_bounds__(1024) k_bin_small(const double *__restrict__ pos, int n, Box b,
+// Cell binning into fixed-capacity buckets (g.bucket records per cell):
+// cell index, one device atomic for the slot, one 32-byte record. Counts
+// must be zero on entry (cleared by the reverse-slot pass of the previous
+// rebuild and at workspace set-up). A full bucket drops the atom and raises
+// MLMIX_STATUS_CELL_OVERFLOW. On a forced rebuild it also raises the rebuild
+// flag (otherwise the flag comes from the displacement check before it) and,
+// whenever the list is rebuilt, marks the workspace as built. Order inside a
+// bucket follows the atomics; the rows are sorted afterwards.
+__global__ void __launch_bounds__(256) k_bin_bucket(const double *__restrict__ pos, int n, Box b,
                                                     Grid g, int force, int *hdr,
-                                                    int *__restrict__ cell_of,
-                                                    int *__restrict__ start,
+                                                    int *__restrict__ count,
                                                     CellAtom *__restrict__ atoms)
 {
-    extern __shared__ int cnt[];  // [ncell + 1]
-    __shared__ int sh[16];
-    const int tid = threadIdx.x;
     const int rebuild = force ? 1 : hdr[H_REBUILD];
     if (!rebuild)
         return;  // uniform
-    const int ncell = g.ncell;
-    for (int c = tid; c <= ncell; c += 1024)
-        cnt[c] = 0;
-    __syncthreads();
-    int bad = 0, out = 0;
-    // each thread owns up to 64 atoms (i = tid + 1024 u); their positions and
-    // cells stay in registers from the count pass to the fill pass
-    constexpr int kU = kSmallAtoms / 1024;
-    int cl[kU];
-#pragma unroll
-    for (int u = 0; u < kU; ++u) {
-        const int i = tid + 1024 * u;
-        cl[u] = -1;
-        if (i < n) {
-            int c[3];
-            for (int k = 0; k < 3; ++k) {
-                const double xv = pos[k * n + i];
-                if (!(xv == xv) || xv < -1.0e300 || xv > 1.0e300)
-                    bad = 1;
-                if (!b.per[k] && (xv < 0.0 || xv >= b.L[k]))
-                    out = 1;
-                c[k] = cell_coord(xv, g, k);
-            }
-            cl[u] = (c[2] * g.nc[1] + c[1]) * g.nc[0] + c[0];
-            cell_of[i] = cl[u];
-            atomicAdd(&cnt[cl[u]], 1);
-        }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (force)
+            hdr[H_REBUILD] = 1;
+        hdr[H_BUILT] = 1;
+    }
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    double x[3];
+    int c[3];
+    bool bad = false, out = false;
+    for (int k = 0; k < 3; ++k) {
+        x[k] = pos[k * n + i];
+        if (!(x[k] == x[k]) || x[k] < -1.0e300 || x[k] > 1.0e300)
+            bad = true;
+        if (!b.per[k] && (x[k] < 0.0 || x[k] >= b.L[k]))
+            out = true;
+        c[k] = cell_coord(x[k], g, k);
     }
     if (bad)
         atomicOr(&hdr[H_STATUS], MLMIX_STATUS_NONFINITE);
     if (out)
         atomicOr(&hdr[H_STATUS], MLMIX_STATUS_OUT_OF_BOX);
-    __syncthreads();
-    // exclusive scan: each thread owns a run of consecutive cells
-    const int per = (ncell + 1023) / 1024;
-    const int c0 = tid * per;
-    int sum = 0;
-    for (int k = 0; k < per; ++k)
-        if (c0 + k < ncell)
-            sum += cnt[c0 + k];
-    int tot;
-    int ex = block1024_excl_scan(sum, sh, tot);
-    for (int k = 0; k < per; ++k)
-        if (c0 + k < ncell) {
-            const int v = cnt[c0 + k];
-            cnt[c0 + k] = ex;
-            start[c0 + k] = ex;
-            ex += v;
-        }
-    if (tid == 0)
-        start[ncell] = tot;
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u < kU; ++u) {
-        const int i = tid + 1024 * u;
-        if (cl[u] >= 0) {
-            const int slot = atomicAdd(&cnt[cl[u]], 1);
-            CellAtom r;
-            r.x = pos[i];
-            r.y = pos[n + i];
-            r.z = pos[2 * n + i];
-            r.j = i;
-            r.pad = 0;
-            atoms[slot] = r;
-        }
-    }
-    if (tid == 0) {
-        if (force)
-            hdr[H_REBUILD] = 1;
-        hdr[H_BUILT] = 1;
+    const int cell = (c[2] * g.nc[1] + c[1]) * g.nc[0] + c[0];
+    const int slot = atomicAdd(&count[cell], 1);
+    if (slot < g.bucket) {
+        CellAtom r;
+        r.x = x[0];
+        r.y = x[1];
+        r.z = x[2];
+        r.j = i;
+        r.pad = 0;
+        atoms[(size_t)cell * g.bucket + slot] = r;
+    } else {
+        atomicOr(&hdr[H_STATUS], MLMIX_STATUS_CELL_OVERFLOW);
     }
 }
 
@@ -430,12 +235,12 @@ __device__ __forceinline__ void row_sort_store(const int *row, int lane, int kee
 
 // One wavefront per atom, four atoms per 256-thread block, no block-level
 // barriers (each wave works in its own LDS slice). Each lane owns up to two
-// cells of the (up to) 5x5x5 stencil of half-radius cells and walks their
-// 32-byte cell-ordered records two at a time (loads issued first); partners
+// cells of the (up to) 5x5x5 stencil of half-radius cells and walks the
+// 32-byte records of their buckets two at a time (loads issued first); partners
 // closer than the list radius are kept by ballot compaction, and the row is
 // finally sorted ascending in registers (bitonic over 64, 128 or 256 keys).
 __global__ void __launch_bounds__(256) k_neighbors(const double *__restrict__ pos, int n, Box b,
-                                                   Grid g, const int *__restrict__ start,
+                                                   Grid g, const int *__restrict__ count,
                                                    const CellAtom *__restrict__ atoms, double rl2,
                                                    int cap, int P, int *__restrict__ nbr,
                                                    int *__restrict__ cnt,
@@ -465,7 +270,8 @@ __global__ void __launch_bounds__(256) k_neighbors(const double *__restrict__ po
         ci[k] = cell_coord(xi[k], g, k);
     }
     // stencil cells t = lane and t = lane + 64: first slot and size
-    int sz[2], bg[2];
+    int sz[2];
+    size_t bg[2];
     for (int h = 0; h < 2; ++h) {
         int t = lane + 64 * h;
         sz[h] = 0;
@@ -487,8 +293,8 @@ __global__ void __launch_bounds__(256) k_neighbors(const double *__restrict__ po
             }
             if (ok) {
                 int cell = (q[2] * g.nc[1] + q[1]) * g.nc[0] + q[0];
-                bg[h] = start[cell];
-                sz[h] = start[cell + 1] - bg[h];
+                bg[h] = (size_t)cell * g.bucket;
+                sz[h] = min(count[cell], g.bucket);
             }
         }
     }
@@ -557,13 +363,18 @@ __global__ void __launch_bounds__(256) k_neighbors(const double *__restrict__ po
 }
 
 // rev[i][s] = slot of i in the row of j = nbr[i][s] (rows are ascending).
+// The bucket counts of the rebuild are no longer needed: they are cleared
+// here for the next one.
 __global__ void __launch_bounds__(256) k_reverse(int n, int cap, const int *__restrict__ nbr,
                                                  const int *__restrict__ cnt,
-                                                 int *__restrict__ rev, int *hdr)
+                                                 int *__restrict__ rev, int *__restrict__ count,
+                                                 int ncell, int *hdr)
 {
     if (hdr[H_REBUILD] == 0)
         return;
     size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (size_t c = t; c < (size_t)ncell; c += (size_t)gridDim.x * blockDim.x)
+        count[c] = 0;
     if (t >= (size_t)n * cap)
         return;
     int i = (int)(t / cap), s = (int)(t % cap);
@@ -588,49 +399,31 @@ __global__ void __launch_bounds__(256) k_reverse(int n, int cap, const int *__re
     rev[t] = r;
 }
 
-__global__ void k_finish_rebuild(int *hdr)
-{
-    if (threadIdx.x == 0 && blockIdx.x == 0 && hdr[H_REBUILD])
-        hdr[H_BUILT] = 1;
-}
-
-
 void launch_neighbors(hipStream_t s, void *ws, const WsLayout &L, const Box &b, double r_list,
                       const double *pos, int force_rebuild, double skin)
 {
     int *hdr = at<int>(ws, L.hdr);
     const Grid &g = L.grid;
     const int n = L.n;
-    const bool small = n <= kSmallAtoms && g.ncell <= kSmallCells;
-    if (!(small && force_rebuild)) {
-        k_prepare<<<1, 64, 0, s>>>(hdr, force_rebuild);
-        if (!force_rebuild && n > 0) {
+    if (!force_rebuild) {
+        k_prepare<<<1, 64, 0, s>>>(hdr, 0);
+        if (n > 0) {
             double thr = 0.5 * skin;
             k_displacement<<<(n + 255) / 256, 256, 0, s>>>(pos, at<double>(ws, L.ref_pos), n,
                                                            thr * thr, hdr);
         }
     }
-    if (n == 0)
+    if (n == 0) {
+        if (force_rebuild)
+            k_prepare<<<1, 64, 0, s>>>(hdr, 1);
         return;
-    int *start = at<int>(ws, L.cell_start);
-    if (small) {
-        k_bin_small<<<1, 1024, (size_t)(g.ncell + 1) * sizeof(int), s>>>(
-            pos, n, b, g, force_rebuild, hdr, at<int>(ws, L.cell_of), start,
-            at<CellAtom>(ws, L.cell_atoms));
-    } else {
-        int *count = at<int>(ws, L.cell_count);
-        int *cursor = at<int>(ws, L.cell_cursor);
-        k_cell_zero<<<(g.ncell + 255) / 256, 256, 0, s>>>(count, cursor, g.ncell, hdr + H_REBUILD);
-        k_cell_count<<<(n + 255) / 256, 256, 0, s>>>(pos, n, b, g, at<int>(ws, L.cell_of), count, hdr);
-        device_excl_scan(s, count, g.ncell, at<int>(ws, L.scan_part), start, hdr + H_REBUILD);
-        k_cell_fill<<<(n + 255) / 256, 256, 0, s>>>(pos, n, at<int>(ws, L.cell_of), start, cursor,
-                                                    at<CellAtom>(ws, L.cell_atoms), hdr);
     }
-    k_neighbors<<<(n + 3) / 4, 256, 0, s>>>(pos, n, b, g, start, at<CellAtom>(ws, L.cell_atoms),
+    int *count = at<int>(ws, L.cell_count);
+    k_bin_bucket<<<(n + 255) / 256, 256, 0, s>>>(pos, n, b, g, force_rebuild, hdr, count,
+                                                 at<CellAtom>(ws, L.cell_atoms));
+    k_neighbors<<<(n + 3) / 4, 256, 0, s>>>(pos, n, b, g, count, at<CellAtom>(ws, L.cell_atoms),
                                             r_list * r_list, L.cap, L.P, at<int>(ws, L.nbr),
                                             at<int>(ws, L.cnt), at<double>(ws, L.ref_pos), hdr);
-    if (!small)
-        k_finish_rebuild<<<1, 64, 0, s>>>(hdr);
 }
 
 // Reverse slots of a rebuilt list (skipped on the device when the list was
@@ -641,9 +434,9 @@ void launch_reverse(hipStream_t s, void *ws, const WsLayout &L)
     if (n == 0)
         return;
     size_t tot = (size_t)n * L.cap;
-    k_reverse<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(n, L.cap, at<int>(ws, L.nbr),
-                                                           at<int>(ws, L.cnt), at<int>(ws, L.rev),
-                                                           at<int>(ws, L.hdr));
+    k_reverse<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(
+        n, L.cap, at<int>(ws, L.nbr), at<int>(ws, L.cnt), at<int>(ws, L.rev),
+        at<int>(ws, L.cell_count), L.grid.ncell, at<int>(ws, L.hdr));
 }
 
 // --------------------------------------------------------- lambda / masks

@@ -48,13 +48,14 @@ struct Grid {
     int nc[3];
     double cs[3];
     int ncell;
+    int bucket;  // records per cell bucket
 };
 
 struct WsLayout {
     int n, cap, P;  // atoms, row capacity, capacity rounded up to a power of two
     Grid grid;
     int n_scan_blk;  // blocks of the atom-sized scans
-    size_t hdr, cell_count, cell_cursor, cell_start, cell_of, cell_atoms, scan_part;
+    size_t hdr, cell_count, cell_atoms, scan_part;
     size_t nbr, cnt, rev, ref_pos, S_idx, M_idx, S_local, cand;
     size_t A, dEdA, g, h, red, dpart;
     size_t total;
