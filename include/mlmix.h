@@ -246,8 +246,8 @@ int mlmix_get_index_sets(mlmix_ctx *ctx, void *stream, void *ws, int32_t n_atoms
                          int32_t *S_out, int32_t *M_out);
 
 /* Stage timing for benchmarks. Stages (bit i of the mask, name from
- * mlmix_profile_stage_name(i)): 0 neighbours (cells, rows, reverse slots),
- * 1 regions (lambda, masks, buffer), 2 compaction, 3 expensive atomic basis,
+ * mlmix_profile_stage_name(i)): 0 neighbours (lambda and masks, cells,
+ * rows), 1 regions (buffer), 2 compaction, 3 expensive atomic basis,
  * 4 expensive order-3 contraction, 5 expensive site energy and dE/dA
  * (orders 1-2, sum of the order-3 blocks), 6 expensive pair adjoint, 7 cheap
  * potential, 8 gather + blend, 9 integrator, 10 energy sums, 11 reverse

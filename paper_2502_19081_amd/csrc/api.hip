@@ -633,7 +633,8 @@ WsLayout make_layout(const Ctx &c, int n, int cap, const Box &b)
     take(L.dEdA, nn * c.m.KAt * tsz);
     take(L.g, nn * cap * 3 * tsz);
     take(L.h, nn * cap * 3 * tsz);
-    take(L.red, kReduceBlocks * 3 * sizeof(double));
+    take(L.red, (size_t)std::max(kReduceBlocks, n <= kGatherKickMax ? (n + 3) / 4 : 0) * 3 *
+                    sizeof(double));
     take(L.dpart, nn * (size_t)(c.m.dp_stride > 0 ? c.m.dp_stride : 1) * tsz);
     L.total = off;
     return L;
@@ -916,7 +917,8 @@ static int compute_impl(mlmix_ctx *ctx, hipStream_t s, void *ws, const WsLayout 
                         const double *pos, const int32_t *species, const mlmix_region *regions,
                         int32_t n_regions, double r_buffer, uint32_t mode, double *forces,
                         double *e_exp, double *e_cheap, double *lambda, uint8_t *flags,
-                        int32_t *n_expensive, double *f_exp, double *f_cheap)
+                        int32_t *n_expensive, double *f_exp, double *f_cheap,
+                        const KickArgs *kick = nullptr)
 {
     const Ctx &c = ctx->c;
     int m = (int)(mode & 0xff);
@@ -942,8 +944,9 @@ static int compute_impl(mlmix_ctx *ctx, hipStream_t s, void *ws, const WsLayout 
     hipStream_t s2 = fork ? sd.s : s;  // stream of the reverse slots and the cheap potential
     {
         StageTimer t(ctx, s, ST_NBR);
+        RegionArgs ra{m, species, c.m.ns, regions, n_regions, r_buffer, lambda, flags, nullptr};
         launch_neighbors(s, ws, L, b, c.r_list, pos, (mode & MLMIX_FORCE_REBUILD) ? 1 : 0,
-                         c.d.skin);
+                         c.d.skin, ra);
     }
     // fork: reverse slots and the cheap potential need only the list; they are
     // started after the neighbour rows (fork_at 0) or after the atomic basis
@@ -977,8 +980,7 @@ static int compute_impl(mlmix_ctx *ctx, hipStream_t s, void *ws, const WsLayout 
     }
     {
         StageTimer t(ctx, s, ST_REG);
-        launch_regions(s, ws, L, b, m, pos, species, c.m.ns, regions, n_regions, r_buffer, lambda,
-                       flags);
+        launch_regions(s, ws, L, b, m, pos, r_buffer, flags);
     }
     {
         StageTimer t(ctx, s, ST_CMP);
@@ -1018,7 +1020,7 @@ static int compute_impl(mlmix_ctx *ctx, hipStream_t s, void *ws, const WsLayout 
     {
         StageTimer t(ctx, s, ST_GATHER);
         launch_gather_blend(s, c, ws, L, m != MLMIX_MODE_ALL_CHEAP, m != MLMIX_MODE_ALL_EXPENSIVE,
-                            lambda, forces, e_exp, f_exp, f_cheap, 1.0);
+                            lambda, forces, e_exp, f_exp, f_cheap, 1.0, kick);
     }
     HIP_OK(hipGetLastError());
     return MLMIX_OK;
@@ -1136,15 +1138,19 @@ extern "C" int mlmix_vv_step(mlmix_ctx *ctx, void *stream, void *ws, int32_t n_a
         StageTimer t(ctx, s, ST_VV);
         launch_vv_kick_drift(s, ws, L, b, pos, vel, mass, forces, dt, 1);
     }
+    // small systems: closing half kick and energy partials inside the gather
+    const bool fused = energies && L.n > 0 && L.n <= kGatherKickMax;
+    KickArgs ka{vel, mass, dt, e_cheap, nullptr, energies};
     rc = compute_impl(ctx, s, ws, L, b, pos, species, regions, n_regions, r_buffer, mode, forces,
-                      e_exp, e_cheap, lambda, flags, n_expensive, nullptr, nullptr);
+                      e_exp, e_cheap, lambda, flags, n_expensive, nullptr, nullptr,
+                      fused ? &ka : nullptr);
     if (rc)
         return rc;
-    if (energies) {
+    if (!fused && energies) {
         // closing half kick fused with the energy partial sums
         StageTimer t(ctx, s, ST_RED);
         launch_vv_kick_sums(s, ws, L, vel, mass, forces, dt, e_exp, e_cheap, energies);
-    } else {
+    } else if (!fused) {
         StageTimer t(ctx, s, ST_VV);
         launch_vv_kick_drift(s, ws, L, b, pos, vel, mass, forces, dt, 0);
     }

@@ -114,10 +114,93 @@ __global__ void __launch_bounds__(256) k_displacement(const double *__restrict__
         hdr[H_REBUILD] = 1;
 }
 
-// ------------------------------------------------------------ cell lists
+// ------------------------------------------------ lambda, cell lists
 
-// Cell binning into fixed-capacity buckets (g.bucket records per cell):
-// cell index, one device atomic for the slot, one 32-byte record. Counts
+// Mixing weight of atom i: the largest linear blend over the regions
+// (Algorithms 1-2), its masks (bit 0: lambda > 0, bit 1: lambda == 1) and
+// whether it may join the buffer (lambda == 0 but near some region).
+__device__ __forceinline__ void atom_lambda(const double *__restrict__ pos, int n, const Box &b,
+                                            int i, const RegionArgs &ra, int *hdr)
+{
+#pragma clang fp contract(off)
+    int z = ra.species[i];
+    if (z < 0 || z >= ra.ns)
+        atomicOr(&hdr[H_STATUS], MLMIX_STATUS_BAD_SPECIES);
+    if (ra.mode == MLMIX_MODE_ALL_EXPENSIVE) {
+        ra.lam[i] = 1.0;
+        ra.flags[i] = 3;
+        ra.cand[i] = 0;
+        return;
+    }
+    if (ra.mode == MLMIX_MODE_ALL_CHEAP) {
+        ra.lam[i] = 0.0;
+        ra.flags[i] = 0;
+        ra.cand[i] = 0;
+        return;
+    }
+    double best = 0.0;
+    bool near = false;
+    double xi[3] = {pos[i], pos[n + i], pos[2 * n + i]};
+    for (int g = 0; g < ra.nreg; ++g) {
+        mlmix_region r = ra.reg[g];
+        double c[3] = {r.center[0], r.center[1], r.center[2]};
+        if (r.follow_atom >= 0 && r.follow_atom < n) {
+            c[0] = pos[r.follow_atom];
+            c[1] = pos[n + r.follow_atom];
+            c[2] = pos[2 * n + r.follow_atom];
+        }
+        double d[3];
+        for (int k = 0; k < 3; ++k) {
+            double dx = xi[k] - c[k];
+            if (b.per[k]) {
+                double h = 0.5 * b.L[k];
+                if (dx > h)
+                    dx = dx - b.L[k];
+                else if (dx < -h)
+                    dx = dx + b.L[k];
+            }
+            d[k] = dx;
+        }
+        if (r.type == 1 && r.axis >= 0 && r.axis < 3)
+            d[r.axis] = 0.0;
+        double d2 = norm2(d);
+        double rc = r.r_core, rb = r.r_blend;
+        double outer = rc + rb;
+        double v;
+        if (d2 < rc * rc) {
+            v = 1.0;
+        } else if (d2 < outer * outer) {
+            double dist = sqrt(d2);
+            double t = (dist - rc) / rb;
+            v = 1.0 - t;
+        } else {
+            v = 0.0;
+        }
+        if (v > best)
+            best = v;
+        // buffer prefilter: a buffer atom lies within r_buffer of an atom
+        // with lambda > 0, hence (triangle inequality) within
+        // r_core + r_blend + r_buffer of some region; a margin keeps the
+        // test conservative under rounding
+        double far = outer + ra.r_buffer + 1.0e-6;
+        if (d2 < far * far)
+            near = true;
+    }
+    ra.lam[i] = best;
+    uint8_t f = 0;
+    if (best > 0.0)
+        f |= 1;
+    if (best == 1.0)
+        f |= 2;
+    ra.flags[i] = f;
+    ra.cand[i] = (best == 0.0 && near) ? 1 : 0;
+}
+
+
+// One thread per atom: the mixing weight pass (every call), then, when the
+// list is rebuilt, cell binning into fixed-capacity buckets (g.bucket
+// records per cell): cell index, one device atomic for the slot, one 32-byte
+// record. Counts
 // must be zero on entry (cleared by the reverse-slot pass of the previous
 // rebuild and at workspace set-up). A full bucket drops the atom and raises
 // MLMIX_STATUS_CELL_OVERFLOW. On a forced rebuild it also raises the rebuild
@@ -127,8 +210,11 @@ __global__ void __launch_bounds__(256) k_displacement(const double *__restrict__
 __global__ void __launch_bounds__(256) k_bin_bucket(const double *__restrict__ pos, int n, Box b,
                                                     Grid g, int force, int *hdr,
                                                     int *__restrict__ count,
-                                                    CellAtom *__restrict__ atoms)
+                                                    CellAtom *__restrict__ atoms, RegionArgs ra)
 {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n)
+        atom_lambda(pos, n, b, i, ra, hdr);
     const int rebuild = force ? 1 : hdr[H_REBUILD];
     if (!rebuild)
         return;  // uniform
@@ -137,7 +223,6 @@ __global__ void __launch_bounds__(256) k_bin_bucket(const double *__restrict__ p
             hdr[H_REBUILD] = 1;
         hdr[H_BUILT] = 1;
     }
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n)
         return;
     double x[3];
@@ -400,7 +485,7 @@ __global__ void __launch_bounds__(256) k_reverse(int n, int cap, const int *__re
 }
 
 void launch_neighbors(hipStream_t s, void *ws, const WsLayout &L, const Box &b, double r_list,
-                      const double *pos, int force_rebuild, double skin)
+                      const double *pos, int force_rebuild, double skin, const RegionArgs &ra)
 {
     int *hdr = at<int>(ws, L.hdr);
     const Grid &g = L.grid;
@@ -419,8 +504,10 @@ void launch_neighbors(hipStream_t s, void *ws, const WsLayout &L, const Box &b, 
         return;
     }
     int *count = at<int>(ws, L.cell_count);
+    RegionArgs r = ra;
+    r.cand = at<uint8_t>(ws, L.cand);
     k_bin_bucket<<<(n + 255) / 256, 256, 0, s>>>(pos, n, b, g, force_rebuild, hdr, count,
-                                                 at<CellAtom>(ws, L.cell_atoms));
+                                                 at<CellAtom>(ws, L.cell_atoms), r);
     k_neighbors<<<(n + 3) / 4, 256, 0, s>>>(pos, n, b, g, count, at<CellAtom>(ws, L.cell_atoms),
                                             r_list * r_list, L.cap, L.P, at<int>(ws, L.nbr),
                                             at<int>(ws, L.cnt), at<double>(ws, L.ref_pos), hdr);
@@ -440,91 +527,6 @@ void launch_reverse(hipStream_t s, void *ws, const WsLayout &L)
 }
 
 // --------------------------------------------------------- lambda / masks
-
-__global__ void __launch_bounds__(256) k_lambda(const double *__restrict__ pos, int n, Box b,
-                                                const int32_t *__restrict__ species, int ns, int *hdr,
-                                                int mode, const mlmix_region *__restrict__ reg,
-                                                int nreg, double r_buffer,
-                                                double *__restrict__ lam,
-                                                uint8_t *__restrict__ flags,
-                                                uint8_t *__restrict__ cand)
-{
-#pragma clang fp contract(off)
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n)
-        return;
-    int z = species[i];
-    if (z < 0 || z >= ns)
-        atomicOr(&hdr[H_STATUS], MLMIX_STATUS_BAD_SPECIES);
-    if (mode == MLMIX_MODE_ALL_EXPENSIVE) {
-        lam[i] = 1.0;
-        flags[i] = 3;
-        cand[i] = 0;
-        return;
-    }
-    if (mode == MLMIX_MODE_ALL_CHEAP) {
-        lam[i] = 0.0;
-        flags[i] = 0;
-        cand[i] = 0;
-        return;
-    }
-    double best = 0.0;
-    bool near = false;
-    double xi[3] = {pos[i], pos[n + i], pos[2 * n + i]};
-    for (int g = 0; g < nreg; ++g) {
-        mlmix_region r = reg[g];
-        double c[3] = {r.center[0], r.center[1], r.center[2]};
-        if (r.follow_atom >= 0 && r.follow_atom < n) {
-            c[0] = pos[r.follow_atom];
-            c[1] = pos[n + r.follow_atom];
-            c[2] = pos[2 * n + r.follow_atom];
-        }
-        double d[3];
-        for (int k = 0; k < 3; ++k) {
-            double dx = xi[k] - c[k];
-            if (b.per[k]) {
-                double h = 0.5 * b.L[k];
-                if (dx > h)
-                    dx = dx - b.L[k];
-                else if (dx < -h)
-                    dx = dx + b.L[k];
-            }
-            d[k] = dx;
-        }
-        if (r.type == 1 && r.axis >= 0 && r.axis < 3)
-            d[r.axis] = 0.0;
-        double d2 = norm2(d);
-        double rc = r.r_core, rb = r.r_blend;
-        double outer = rc + rb;
-        double v;
-        if (d2 < rc * rc) {
-            v = 1.0;
-        } else if (d2 < outer * outer) {
-            double dist = sqrt(d2);
-            double t = (dist - rc) / rb;
-            v = 1.0 - t;
-        } else {
-            v = 0.0;
-        }
-        if (v > best)
-            best = v;
-        // buffer prefilter: a buffer atom lies within r_buffer of an atom
-        // with lambda > 0, hence (triangle inequality) within
-        // r_core + r_blend + r_buffer of some region; a margin keeps the
-        // test conservative under rounding
-        double far = outer + r_buffer + 1.0e-6;
-        if (d2 < far * far)
-            near = true;
-    }
-    lam[i] = best;
-    uint8_t f = 0;
-    if (best > 0.0)
-        f |= 1;
-    if (best == 1.0)
-        f |= 2;
-    flags[i] = f;
-    cand[i] = (best == 0.0 && near) ? 1 : 0;
-}
 
 // One wavefront per atom (lanes over row slots): an atom with lambda == 0
 // near a region joins the buffer when any neighbour with lambda > 0 lies
@@ -555,16 +557,15 @@ __global__ void __launch_bounds__(256) k_buffer(const double *__restrict__ pos, 
         flags[i] = (uint8_t)(flags[i] | 4);
 }
 
+// Buffer pass of the region stage (lambda and the masks come from the
+// binning kernel of the neighbour stage).
 void launch_regions(hipStream_t s, void *ws, const WsLayout &L, const Box &b, int mode,
-                    const double *pos, const int32_t *species, int ns, const mlmix_region *reg,
-                    int nreg, double r_buffer, double *lambda, uint8_t *flags)
+                    const double *pos, double r_buffer, uint8_t *flags)
 {
     int n = L.n;
     if (n == 0)
         return;
     uint8_t *cand = at<uint8_t>(ws, L.cand);
-    k_lambda<<<(n + 255) / 256, 256, 0, s>>>(pos, n, b, species, ns, at<int>(ws, L.hdr), mode, reg,
-                                            nreg, r_buffer, lambda, flags, cand);
     if (mode == MLMIX_MODE_MIXED)
         k_buffer<<<(n + 3) / 4, 256, 0, s>>>(pos, n, b, L.cap, at<int>(ws, L.nbr),
                                                 at<int>(ws, L.cnt), r_buffer * r_buffer, flags,

@@ -118,13 +118,26 @@ __host__ __device__ inline int sp_clamp(int z, int ns) { return z < 0 ? 0 : (z >
 template <typename T>
 inline T *at(void *ws, size_t off) { return reinterpret_cast<T *>(static_cast<char *>(ws) + off); }
 
+// Inputs and outputs of the per-atom mixing weight pass (lambda, masks and
+// buffer candidates), which runs inside the binning kernel.
+struct RegionArgs {
+    int mode;
+    const int32_t *species;
+    int ns;
+    const mlmix_region *reg;
+    int nreg;
+    double r_buffer;
+    double *lam;
+    uint8_t *flags;
+    uint8_t *cand;
+};
+
 // ---- launchers (geom.hip) ----
 void launch_neighbors(hipStream_t s, void *ws, const WsLayout &L, const Box &b, double r_list,
-                      const double *pos, int force_rebuild, double skin);
+                      const double *pos, int force_rebuild, double skin, const RegionArgs &ra);
 void launch_reverse(hipStream_t s, void *ws, const WsLayout &L);
 void launch_regions(hipStream_t s, void *ws, const WsLayout &L, const Box &b, int mode,
-                    const double *pos, const int32_t *species, int ns, const mlmix_region *reg,
-                    int nreg, double r_buffer, double *lambda, uint8_t *flags);
+                    const double *pos, double r_buffer, uint8_t *flags);
 void launch_compact(hipStream_t s, void *ws, const WsLayout &L, uint8_t *flags, int32_t *n_expensive);
 
 // ---- ace.hip ----
@@ -146,9 +159,22 @@ void launch_uf3(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L, const 
                 const double *pos, const int32_t *species, double *e_cheap);
 
 // ---- tail.hip ----
+// Closing half kick of a velocity-Verlet step and per-block energy partials,
+// fused into the force gather for systems up to kGatherKickMax atoms (one
+// partial per four atoms, summed by one workgroup).
+struct KickArgs {
+    double *vel;
+    const double *mass;
+    double dt;
+    const double *e_cheap;
+    double *part;      // [blocks][3]: expensive, cheap, kinetic (set by the launcher)
+    double *energies;  // final sums
+};
+constexpr int kGatherKickMax = 65536;
 void launch_gather_blend(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L, int use_exp,
                          int use_cheap, const double *lambda, double *forces, double *e_exp,
-                         double *f_exp, double *f_cheap, double sign);
+                         double *f_exp, double *f_cheap, double sign,
+                         const KickArgs *kick = nullptr);
 void launch_fill_f64(hipStream_t s, double *p, double v, size_t n);
 void launch_vv_kick_sums(hipStream_t s, void *ws, const WsLayout &L, double *vel,
                          const double *mass, const double *forces, double dt, const double *e_exp,

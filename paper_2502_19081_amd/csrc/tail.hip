@@ -19,95 +19,141 @@ __device__ __forceinline__ double wave_sum_d(double v)
     return v;
 }
 
-template <typename T>
+constexpr double kKappa = 9.648533212e-3;
+
+template <typename T, bool KICK>
 __global__ void __launch_bounds__(256)
     k_gather_blend(int n, int cap, const int *__restrict__ nbr, const int *__restrict__ cnt,
                    const int *__restrict__ rev, const int *__restrict__ S_local,
                    const T *__restrict__ g, const T *__restrict__ h, int use_exp, int use_cheap,
                    const double *__restrict__ lambda, double *__restrict__ forces,
                    double *__restrict__ e_exp, double *__restrict__ f_exp,
-                   double *__restrict__ f_cheap, double sign)
+                   double *__restrict__ f_cheap, double sign, KickArgs ka)
 {
-    int i = blockIdx.x * 4 + (threadIdx.x >> 6);
-    int lane = threadIdx.x & 63;
-    if (i >= n)
-        return;
-    int c = cnt[i];
-    int si = S_local[i];
-    double fe0 = 0.0, fe1 = 0.0, fe2 = 0.0, fc0 = 0.0, fc1 = 0.0, fc2 = 0.0;
-    const size_t rowo = (size_t)i * cap;
-    for (int slot = lane; slot < c; slot += 64) {
-        int j = nbr[rowo + slot];
-        int r = rev[rowo + slot];
-        if (r < 0)
-            continue;
-        if (use_exp && si >= 0) {
-            int sj = S_local[j];
-            if (sj >= 0) {
-                const T *a = g + ((size_t)si * cap + slot) * 3;
-                const T *bb = g + ((size_t)sj * cap + r) * 3;
-                fe0 += (double)a[0] - (double)bb[0];
-                fe1 += (double)a[1] - (double)bb[1];
-                fe2 += (double)a[2] - (double)bb[2];
+    const int w = threadIdx.x >> 6;
+    const int i = blockIdx.x * 4 + w;
+    const int lane = threadIdx.x & 63;
+    double ee = 0.0, ec = 0.0, ke = 0.0;  // energy terms of atom i (lane 0, KICK)
+    if (i < n) {
+        int c = cnt[i];
+        int si = S_local[i];
+        double fe0 = 0.0, fe1 = 0.0, fe2 = 0.0, fc0 = 0.0, fc1 = 0.0, fc2 = 0.0;
+        const size_t rowo = (size_t)i * cap;
+        for (int slot = lane; slot < c; slot += 64) {
+            int j = nbr[rowo + slot];
+            int r = rev[rowo + slot];
+            if (r < 0)
+                continue;
+            if (use_exp && si >= 0) {
+                int sj = S_local[j];
+                if (sj >= 0) {
+                    const T *a = g + ((size_t)si * cap + slot) * 3;
+                    const T *bb = g + ((size_t)sj * cap + r) * 3;
+                    fe0 += (double)a[0] - (double)bb[0];
+                    fe1 += (double)a[1] - (double)bb[1];
+                    fe2 += (double)a[2] - (double)bb[2];
+                }
+            }
+            if (use_cheap) {
+                const T *a = h + (rowo + slot) * 3;
+                const T *bb = h + ((size_t)j * cap + r) * 3;
+                fc0 += (double)a[0] - (double)bb[0];
+                fc1 += (double)a[1] - (double)bb[1];
+                fc2 += (double)a[2] - (double)bb[2];
             }
         }
-        if (use_cheap) {
-            const T *a = h + (rowo + slot) * 3;
-            const T *bb = h + ((size_t)j * cap + r) * 3;
-            fc0 += (double)a[0] - (double)bb[0];
-            fc1 += (double)a[1] - (double)bb[1];
-            fc2 += (double)a[2] - (double)bb[2];
+        fe0 = wave_sum_d(fe0);
+        fe1 = wave_sum_d(fe1);
+        fe2 = wave_sum_d(fe2);
+        fc0 = wave_sum_d(fc0);
+        fc1 = wave_sum_d(fc1);
+        fc2 = wave_sum_d(fc2);
+        if (lane == 0) {
+            double lam = lambda ? lambda[i] : 1.0;
+            double om = 1.0 - lam;
+            const double F[3] = {sign * (lam * fe0 + om * fc0), sign * (lam * fe1 + om * fc1),
+                                 sign * (lam * fe2 + om * fc2)};
+            if (forces) {
+                forces[i] = F[0];
+                forces[n + i] = F[1];
+                forces[2 * n + i] = F[2];
+            }
+            if (f_exp) {
+                f_exp[i] = fe0;
+                f_exp[n + i] = fe1;
+                f_exp[2 * n + i] = fe2;
+            }
+            if (f_cheap) {
+                f_cheap[i] = fc0;
+                f_cheap[n + i] = fc1;
+                f_cheap[2 * n + i] = fc2;
+            }
+            if (e_exp && si < 0)
+                e_exp[i] = 0.0;
+            if (KICK) {
+                const double m = ka.mass[i];
+                const double cf = 0.5 * ka.dt * kKappa / m;
+                double v2 = 0.0;
+                for (int q = 0; q < 3; ++q) {
+                    const double v = ka.vel[q * n + i] + cf * F[q];
+                    ka.vel[q * n + i] = v;
+                    v2 += v * v;
+                }
+                ke = 0.5 * m * v2;
+                ee = si < 0 ? 0.0 : e_exp[i];
+                ec = ka.e_cheap[i];
+            }
         }
     }
-    fe0 = wave_sum_d(fe0);
-    fe1 = wave_sum_d(fe1);
-    fe2 = wave_sum_d(fe2);
-    fc0 = wave_sum_d(fc0);
-    fc1 = wave_sum_d(fc1);
-    fc2 = wave_sum_d(fc2);
-    if (lane == 0) {
-        double lam = lambda ? lambda[i] : 1.0;
-        double om = 1.0 - lam;
-        if (forces) {
-            forces[i] = sign * (lam * fe0 + om * fc0);
-            forces[n + i] = sign * (lam * fe1 + om * fc1);
-            forces[2 * n + i] = sign * (lam * fe2 + om * fc2);
+    if (KICK) {
+        __shared__ double sh[3][4];
+        if (lane == 0) {
+            sh[0][w] = ee;
+            sh[1][w] = ec;
+            sh[2][w] = ke;
         }
-        if (f_exp) {
-            f_exp[i] = fe0;
-            f_exp[n + i] = fe1;
-            f_exp[2 * n + i] = fe2;
-        }
-        if (f_cheap) {
-            f_cheap[i] = fc0;
-            f_cheap[n + i] = fc1;
-            f_cheap[2 * n + i] = fc2;
-        }
-        if (e_exp && si < 0)
-            e_exp[i] = 0.0;
+        __syncthreads();
+        if (threadIdx.x == 0)
+            for (int q = 0; q < 3; ++q)
+                ka.part[blockIdx.x * 3 + q] = (sh[q][0] + sh[q][1]) + (sh[q][2] + sh[q][3]);
     }
 }
 
+__global__ void __launch_bounds__(256) k_reduce_final(const double *__restrict__ part, int nb,
+                                                      double *__restrict__ out);
+
 void launch_gather_blend(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L, int use_exp,
                          int use_cheap, const double *lambda, double *forces, double *e_exp,
-                         double *f_exp, double *f_cheap, double sign)
+                         double *f_exp, double *f_cheap, double sign, const KickArgs *kick)
 {
     int n = L.n;
     if (n == 0)
         return;
     unsigned nb = (n + 3) / 4;
-    if (c.prec == MLMIX_FP64)
-        k_gather_blend<double><<<nb, 256, 0, s>>>(n, L.cap, at<int>(ws, L.nbr), at<int>(ws, L.cnt),
-                                                  at<int>(ws, L.rev), at<int>(ws, L.S_local),
-                                                  at<double>(ws, L.g), at<double>(ws, L.h), use_exp,
-                                                  use_cheap, lambda, forces, e_exp, f_exp, f_cheap,
-                                                  sign);
-    else
-        k_gather_blend<float><<<nb, 256, 0, s>>>(n, L.cap, at<int>(ws, L.nbr), at<int>(ws, L.cnt),
-                                                 at<int>(ws, L.rev), at<int>(ws, L.S_local),
-                                                 at<float>(ws, L.g), at<float>(ws, L.h), use_exp,
-                                                 use_cheap, lambda, forces, e_exp, f_exp, f_cheap,
-                                                 sign);
+    KickArgs ka{};
+    if (kick) {
+        ka = *kick;
+        ka.part = at<double>(ws, L.red);
+    }
+#define MLMIX_GATHER(T, K)                                                                        \
+    k_gather_blend<T, K><<<nb, 256, 0, s>>>(n, L.cap, at<int>(ws, L.nbr), at<int>(ws, L.cnt),      \
+                                           at<int>(ws, L.rev), at<int>(ws, L.S_local),             \
+                                           at<T>(ws, L.g), at<T>(ws, L.h), use_exp, use_cheap,     \
+                                           lambda, forces, e_exp, f_exp, f_cheap, sign, ka)
+    if (c.prec == MLMIX_FP64) {
+        if (kick)
+            MLMIX_GATHER(double, true);
+        else
+            MLMIX_GATHER(double, false);
+    } else {
+        if (kick)
+            MLMIX_GATHER(float, true);
+        else
+            MLMIX_GATHER(float, false);
+    }
+#undef MLMIX_GATHER
+    if (kick)
+        k_reduce_final<<<1, 256, 0, s>>>(ka.part, (int)nb, ka.energies);
 }
 
 __global__ void __launch_bounds__(256) k_fill_f64(double *p, double v, size_t n)
@@ -139,8 +185,6 @@ void launch_copy_i32(hipStream_t s, int32_t *dst, const int32_t *src, size_t n)
 }
 
 // ------------------------------------------------------------ reductions
-
-constexpr double kKappa = 9.648533212e-3;
 
 __global__ void __launch_bounds__(256)
     k_reduce_partial(int n, const double *__restrict__ e_exp, const double *__restrict__ e_cheap,
