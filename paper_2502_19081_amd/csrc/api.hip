@@ -504,6 +504,19 @@ static int build_tables(const mlmix_model_desc &d, HostTables &t)
                         if (t.u3[(((size_t)z * nb3 + p) * nb3 + q) * nb3 + s] !=
                             t.u3[(((size_t)z * nb3 + q) * nb3 + p) * nb3 + s])
                             return fail(MLMIX_E_ARG, "uf3_c3 is not symmetric in its first two indices");
+        // device layout: for every (z, a, b) and every first index c0 of a
+        // span of the third (r_jk) basis, the four coefficients c0..c0+3
+        // side by side, so that one span is one 4-wide load
+        const int nsp = nb3 - 3;
+        std::vector<double> x((size_t)ns * nb3 * nb3 * nsp * 4);
+        for (int z = 0; z < ns; ++z)
+            for (int a = 0; a < nb3; ++a)
+                for (int b = 0; b < nb3; ++b)
+                    for (int c0 = 0; c0 < nsp; ++c0)
+                        for (int u = 0; u < 4; ++u)
+                            x[((((size_t)z * nb3 + a) * nb3 + b) * nsp + c0) * 4 + u] =
+                                t.u3[(((size_t)z * nb3 + a) * nb3 + b) * nb3 + c0 + u];
+        t.u3.swap(x);
     }
     return MLMIX_OK;
 }
@@ -794,6 +807,8 @@ extern "C" int mlmix_create(const mlmix_model_desc *desc, mlmix_ctx **out)
     c.o3_nch2 = t.o3_nch2;
     if (const char *e = std::getenv("MLMIX_FORK_AT"))
         c.fork_at = std::atoi(e) ? 1 : 0;
+    if (const char *e = std::getenv("MLMIX_SIDE_BLOCKS"))
+        c.side_blocks = std::max(-1, std::atoi(e));
     if (const char *e = std::getenv("MLMIX_O3_MAX_SPLIT")) {
         int v = std::atoi(e);
         if (v == 1 || v == 2 || v == 4 || v == 8)
@@ -942,6 +957,12 @@ static int compute_impl(mlmix_ctx *ctx, hipStream_t s, void *ws, const WsLayout 
         fork = sd.s != nullptr;
     }
     hipStream_t s2 = fork ? sd.s : s;  // stream of the reverse slots and the cheap potential
+    // workgroup cap of those two kernels when they run beside the expensive
+    // chain (leave it room); on one stream or beside no expensive work they
+    // run uncapped
+    const int side_blocks = (!fork || m == MLMIX_MODE_ALL_CHEAP)
+                                ? 0
+                                : (c.side_blocks >= 0 ? c.side_blocks : (L.n < 262144 ? 256 : 1024));
     {
         StageTimer t(ctx, s, ST_NBR);
         RegionArgs ra{m, species, c.m.ns, regions, n_regions, r_buffer, lambda, flags, nullptr};
@@ -958,12 +979,12 @@ static int compute_impl(mlmix_ctx *ctx, hipStream_t s, void *ws, const WsLayout 
         }
         {
             StageTimer t(ctx, s2, ST_REV);
-            launch_reverse(s2, ws, L);
+            launch_reverse(s2, ws, L, side_blocks);
         }
         if (!energy_only) {
             if (m != MLMIX_MODE_ALL_EXPENSIVE) {
                 StageTimer t(ctx, s2, ST_UF3);
-                launch_uf3(s2, c, ws, L, b, pos, species, e_cheap);
+                launch_uf3(s2, c, ws, L, b, pos, species, e_cheap, side_blocks);
             } else {
                 launch_fill_f64(s2, e_cheap, 0.0, (size_t)L.n);
             }

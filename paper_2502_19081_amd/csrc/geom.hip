@@ -457,31 +457,32 @@ __global__ void __launch_bounds__(256) k_reverse(int n, int cap, const int *__re
 {
     if (hdr[H_REBUILD] == 0)
         return;
-    size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    for (size_t c = t; c < (size_t)ncell; c += (size_t)gridDim.x * blockDim.x)
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    const size_t t0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (size_t c = t0; c < (size_t)ncell; c += stride)
         count[c] = 0;
-    if (t >= (size_t)n * cap)
-        return;
-    int i = (int)(t / cap), s = (int)(t % cap);
-    int r = -1;
-    if (s < cnt[i]) {
-        int j = nbr[t];
-        const int *rowj = nbr + (size_t)j * cap;
-        int lo = 0, hi = cnt[j] - 1;
-        while (lo <= hi) {
-            int mid = (lo + hi) >> 1;
-            int v = rowj[mid];
-            if (v == i) {
-                r = mid;
-                break;
+    for (size_t t = t0; t < (size_t)n * cap; t += stride) {
+        int i = (int)(t / cap), s = (int)(t % cap);
+        int r = -1;
+        if (s < cnt[i]) {
+            int j = nbr[t];
+            const int *rowj = nbr + (size_t)j * cap;
+            int lo = 0, hi = cnt[j] - 1;
+            while (lo <= hi) {
+                int mid = (lo + hi) >> 1;
+                int v = rowj[mid];
+                if (v == i) {
+                    r = mid;
+                    break;
+                }
+                if (v < i)
+                    lo = mid + 1;
+                else
+                    hi = mid - 1;
             }
-            if (v < i)
-                lo = mid + 1;
-            else
-                hi = mid - 1;
-        }
     }
     rev[t] = r;
+    }
 }
 
 void launch_neighbors(hipStream_t s, void *ws, const WsLayout &L, const Box &b, double r_list,
@@ -515,13 +516,16 @@ void launch_neighbors(hipStream_t s, void *ws, const WsLayout &L, const Box &b, 
 
 // Reverse slots of a rebuilt list (skipped on the device when the list was
 // kept); needed by the force gather only, so it may run beside the potentials.
-void launch_reverse(hipStream_t s, void *ws, const WsLayout &L)
+void launch_reverse(hipStream_t s, void *ws, const WsLayout &L, int side_blocks)
 {
     const int n = L.n;
     if (n == 0)
         return;
     size_t tot = (size_t)n * L.cap;
-    k_reverse<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(
+    size_t nblk = (tot + 255) / 256;
+    if (side_blocks > 0 && nblk > (size_t)side_blocks)
+        nblk = side_blocks;
+    k_reverse<<<(unsigned)nblk, 256, 0, s>>>(
         n, L.cap, at<int>(ws, L.nbr), at<int>(ws, L.cnt), at<int>(ws, L.rev),
         at<int>(ws, L.cell_count), L.grid.ncell, at<int>(ws, L.hdr));
 }

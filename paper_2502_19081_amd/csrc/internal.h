@@ -99,6 +99,12 @@ struct Ctx {
     int o3 = 0;            // order-3 contraction on the per-wave matrix-core kernel
     int basis_mfma = 1;    // atomic basis and pair adjoint on the matrix cores (FP32)
     int fork_at = 0;       // second-stream fork after the rows (0) or the basis (1)
+    // workgroup cap of the second-stream kernels (reverse slots, cheap
+    // potential; grid-stride loops): -1 automatic, 0 uncapped. Measured
+    // (us or ms per mixed step, uncapped / 256 / 1024 workgroups): 8,193
+    // atoms 178 / 166 / 176 us, 1,023,800 atoms 11.3 / - / 10.6 ms; the
+    // automatic cap is 256 below 262,144 atoms and 1024 above.
+    int side_blocks = -1;
     int o3_nch2 = 0;       // row width of that kernel (channels rounded up to 4)
     // largest tile split of that kernel: 4 measured best on the 8,193-atom
     // cell (910 atoms in S: contraction 92 / 52 / 37 / 48 us at 1 / 2 / 4 / 8)
@@ -135,7 +141,7 @@ struct RegionArgs {
 // ---- launchers (geom.hip) ----
 void launch_neighbors(hipStream_t s, void *ws, const WsLayout &L, const Box &b, double r_list,
                       const double *pos, int force_rebuild, double skin, const RegionArgs &ra);
-void launch_reverse(hipStream_t s, void *ws, const WsLayout &L);
+void launch_reverse(hipStream_t s, void *ws, const WsLayout &L, int side_blocks);
 void launch_regions(hipStream_t s, void *ws, const WsLayout &L, const Box &b, int mode,
                     const double *pos, double r_buffer, uint8_t *flags);
 void launch_compact(hipStream_t s, void *ws, const WsLayout &L, uint8_t *flags, int32_t *n_expensive);
@@ -156,7 +162,7 @@ size_t o3_lds_bytes(const Ctx &c);
 
 // ---- uf3.hip ----
 void launch_uf3(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L, const Box &b,
-                const double *pos, const int32_t *species, double *e_cheap);
+                const double *pos, const int32_t *species, double *e_cheap, int side_blocks);
 
 // ---- tail.hip ----
 // Closing half kick of a velocity-Verlet step and per-block energy partials,

@@ -75,114 +75,161 @@ __device__ __forceinline__ T wave_sum_t(T v)
     return v;
 }
 
-// Per-wave LDS slice of the cheap kernel, in elements of T (ints stored in
-// T-sized slots are avoided: the integer arrays follow the T arrays).
-struct Uf3Slice {
-    int hs, d3, r3, B3, dB3, c3s, nT;  // offsets of the T arrays and their total
-};
-
-__host__ __device__ inline Uf3Slice uf3_slice(int cap, int nb3c)
+__device__ __forceinline__ void wave_sync_lds_u()
 {
-    Uf3Slice l;
-    l.hs = 0;
-    l.d3 = l.hs + 3 * cap;
-    l.r3 = l.d3 + 3 * kMaxTriplet;
-    l.B3 = l.r3 + kMaxTriplet;
-    l.dB3 = l.B3 + 4 * kMaxTriplet;
-    l.c3s = l.dB3 + 4 * kMaxTriplet;
-    l.nT = l.c3s + nb3c;
-    return l;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Four centre atoms per 256-thread block, one wavefront each. The loops run
-// to the block's maximum row length so that the four waves meet at every
-// barrier; each wave works in its own LDS slice.
-template <typename T>
+// Four consecutive coefficients (16-byte aligned for float, two 16-byte
+// loads for double).
+__device__ __forceinline__ void load4(const float *p, float v[4])
+{
+    const float4 q = *reinterpret_cast<const float4 *>(p);
+    v[0] = q.x;
+    v[1] = q.y;
+    v[2] = q.z;
+    v[3] = q.w;
+}
+
+__device__ __forceinline__ void load4(const double *p, double v[4])
+{
+    const double2 q0 = *reinterpret_cast<const double2 *>(p);
+    const double2 q1 = *reinterpret_cast<const double2 *>(p + 2);
+    v[0] = q0.x;
+    v[1] = q0.y;
+    v[2] = q1.x;
+    v[3] = q1.y;
+}
+
+// Per-wave LDS arrays of the cheap kernel, in elements of T: leg vectors d3
+// (3 x 64), inverse lengths (64), bases and derivatives (2 x 4 x 64) and the
+// per-round pair contributions (6 x 64; afterwards the leg sums, 3 x 64).
+constexpr int kUf3WaveT = 3 * kMaxTriplet + kMaxTriplet + 8 * kMaxTriplet + 6 * kMaxTriplet;
+
+__host__ __device__ inline int uf3_c3_elems(int ns, int nb3)
+{
+    return nb3 > 0 ? ns * nb3 * nb3 * (nb3 - 3) * 4 : 0;
+}
+
+// Four centre atoms per 256-thread block, one wavefront each; the spline
+// and coefficient tables are staged once per block (the only block
+// barrier), everything after it is wave-local.
+//
+// Pair terms: lane l owns row slots l + 64 u (u < U); all row entries and
+// partner positions are loaded before any arithmetic, E_i += V2(r)/2 and
+// h_ij = V2'(r) u / 2. Three-body terms: the legs inside the 3-body cutoff
+// are compacted by ballot into LDS in row order with their B-spline bases;
+// every unordered leg pair {j, k} is evaluated once (the coefficients are
+// symmetric in the two leg indices), E_i3 = sum_{j<k} V3(r_ij, r_ik, r_jk).
+// The pairs are enumerated cyclically, p = (o - 1) n3 + j with partner
+// k = (j + o) mod n3 for o = 1..n3/2 (for even n3 the last offset only for
+// j < n3/2), 64 pairs per round. Each pair leaves
+// dV3/dd_ij = V_1 u_ij - V_3 e / r_jk and dV3/dd_ik = V_2 u_ik + V_3 e / r_jk
+// (e = d_ik - d_ij) in LDS, and the lane of each leg adds the entries of its
+// pairs in a fixed order: no atomics, the same bits on every run.
+template <typename T, int U>
 __global__ void __launch_bounds__(256)
     k_uf3(const double *__restrict__ pos, int n, Box b, const int32_t *__restrict__ species,
           int cap, const int *__restrict__ nbr, const int *__restrict__ cnt, Uf3Args<T> a,
           T *__restrict__ hout, double *__restrict__ e_cheap, int *hdr)
 {
-    const int nb3c = a.nb3 > 0 ? a.nb3 * a.nb3 * a.nb3 : 0;
-    const Uf3Slice sl = uf3_slice(cap, nb3c);
+    const int nb = a.nb3;
+    const int c3n = uf3_c3_elems(a.ns, nb);
+    constexpr int nT = kUf3WaveT;
     const int w = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
-    const int i = blockIdx.x * 4 + w;
-    const bool valid = i < n;
     extern __shared__ __align__(16) char smem_raw[];
-    T *base = reinterpret_cast<T *>(smem_raw) + (size_t)w * sl.nT;
-    T *hs = base + sl.hs;
-    T *d3 = base + sl.d3;
-    T *r3 = base + sl.r3;
-    T *B3 = base + sl.B3;
-    T *dB3 = base + sl.dB3;
-    T *c3s = base + sl.c3s;
-    int *ibase = reinterpret_cast<int *>(reinterpret_cast<T *>(smem_raw) + 4 * (size_t)sl.nT);
-    int *f3 = ibase + w * 2 * kMaxTriplet;
-    int *sl3 = f3 + kMaxTriplet;
-    // per-span B-spline polynomials, shared by the block
-    T *pp2 = reinterpret_cast<T *>(ibase + 4 * 2 * kMaxTriplet);
+    T *c3x = reinterpret_cast<T *>(smem_raw);
+    T *d3 = c3x + c3n + (size_t)w * nT;
+    T *ir3 = d3 + 3 * kMaxTriplet;
+    T *B3 = ir3 + kMaxTriplet;
+    T *dB3 = B3 + 4 * kMaxTriplet;
+    T *rb = dB3 + 4 * kMaxTriplet;
+    int *f3 = reinterpret_cast<int *>(c3x + c3n + 4 * (size_t)nT) + w * kMaxTriplet;
+    T *pp2 = reinterpret_cast<T *>(reinterpret_cast<int *>(c3x + c3n + 4 * (size_t)nT) +
+                                   4 * kMaxTriplet);
     T *pp3 = pp2 + 16 * (a.nk2 - 1);
+    T *c2s = pp3 + (nb > 0 ? 16 * (a.nk3 - 1) : 0);
+    const int c2n = a.ns * a.ns * a.nb2;
     for (int e = threadIdx.x; e < 16 * (a.nk2 - 1); e += blockDim.x)
         pp2[e] = a.p2[e];
-    if (a.nb3 > 0)
+    for (int e = threadIdx.x; e < c2n; e += blockDim.x)
+        c2s[e] = a.c2[e];
+    if (nb > 0) {
         for (int e = threadIdx.x; e < 16 * (a.nk3 - 1); e += blockDim.x)
             pp3[e] = a.p3[e];
-    __shared__ int count3[4];
-    __shared__ int cmax_s[4];
-    const int zi = valid ? sp_clamp(species[i], a.ns) : 0;
-    const int c = valid ? cnt[i] : 0;
-    const int *row = nbr + (size_t)(valid ? i : 0) * cap;
-    if (lane == 0) {
-        count3[w] = 0;
-        cmax_s[w] = c;
+        for (int e = threadIdx.x; e < c3n; e += blockDim.x)
+            c3x[e] = a.c3[e];
     }
-    for (int e = lane; e < nb3c; e += 64)
-        c3s[e] = a.c3[(size_t)zi * nb3c + e];
-    for (int e = lane; e < 3 * c; e += 64)
-        hs[e] = T(0);
     __syncthreads();
-    const int cmax = max(max(cmax_s[0], cmax_s[1]), max(cmax_s[2], cmax_s[3]));
-    T Ep = T(0);
-    for (int base0 = 0; base0 < cmax; base0 += 64) {
-        int slot = base0 + lane;
-        bool in3 = false;
-        double d[3] = {0.0, 0.0, 0.0};
-        double r2 = 0.0;
-        if (slot < c) {
-            int j = row[slot];
-            r2 = pair_disp_u(pos, n, i, j, b, d);
-            if (r2 < a.rc2sq) {
-                double rd = sqrt(r2);
-                T r = T(rd);
-                int f;
-                T N[4], dN[4];
-                bspline4p<T>(r, a.ih2, a.nk2, pp2, f, N, dN);
-                const T *cc = a.c2 + ((size_t)zi * a.ns + sp_clamp(species[j], a.ns)) * a.nb2 + f;
-                T V = T(0), dV = T(0);
+    // groups of four atoms, grid-stride (no block barrier below)
+    for (int grp = blockIdx.x; grp < (n + 3) / 4; grp += gridDim.x) {
+        const int i = grp * 4 + w;
+        if (i >= n)
+            continue;
+        wave_sync_lds_u();
+        const int zi = sp_clamp(species[i], a.ns);
+        const int c = cnt[i];
+        const int *row = nbr + (size_t)i * cap;
+        int jj[U];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    V += cc[q] * N[q];
-                    dV += cc[q] * dN[q];
-                }
-                Ep += T(0.5) * V;
-                T sc = T(0.5) * dV / r;
-                hs[slot * 3 + 0] = sc * T(d[0]);
-                hs[slot * 3 + 1] = sc * T(d[1]);
-                hs[slot * 3 + 2] = sc * T(d[2]);
+        for (int u = 0; u < U; ++u) {
+            const int slot = lane + 64 * u;
+            jj[u] = slot < c ? row[slot] : -1;
+    }
+    double dd[U][3], rr2[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        rr2[u] = 1.0e300;
+        dd[u][0] = dd[u][1] = dd[u][2] = 0.0;
+        if (jj[u] >= 0)
+            rr2[u] = pair_disp_u(pos, n, i, jj[u], b, dd[u]);
+    }
+    int zj[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+        zj[u] = (a.ns > 1 && jj[u] >= 0) ? sp_clamp(species[jj[u]], a.ns) : 0;
+    T Ep = T(0);
+    int n3 = 0;
+    T hx[U], hy[U], hz[U];  // dE_i/dd_ij of the lane's slots
+    int leg[U];             // 3-body leg index of the slot, or -1
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int slot = lane + 64 * u;
+        const double r2 = rr2[u];
+        hx[u] = hy[u] = hz[u] = T(0);
+        leg[u] = -1;
+        if (r2 < a.rc2sq) {
+            const double rd = sqrt(r2);
+            const T r = T(rd);
+            int f;
+            T N[4], dN[4];
+            bspline4p<T>(r, a.ih2, a.nk2, pp2, f, N, dN);
+            const T *cc = c2s + (zi * a.ns + zj[u]) * a.nb2 + f;
+            T V = T(0), dV = T(0);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                V += cc[q] * N[q];
+                dV += cc[q] * dN[q];
             }
-            in3 = a.nb3 > 0 && r2 < a.rc3sq;
+            Ep += T(0.5) * V;
+            const T sc = T(0.5) * dV / r;
+            hx[u] = sc * T(dd[u][0]);
+            hy[u] = sc * T(dd[u][1]);
+            hz[u] = sc * T(dd[u][2]);
         }
-        unsigned long long mask = __ballot(in3);
-        int before = __popcll(mask & ((1ull << lane) - 1ull));
-        int p = count3[w] + before;
+        const bool in3 = nb > 0 && r2 < a.rc3sq;
+        const unsigned long long mask = __ballot(in3);
+        const int p = n3 + __popcll(mask & ((1ull << lane) - 1ull));
         if (in3 && p < kMaxTriplet) {
-            double rd = sqrt(r2);
-            d3[p * 3 + 0] = T(d[0]);
-            d3[p * 3 + 1] = T(d[1]);
-            d3[p * 3 + 2] = T(d[2]);
-            r3[p] = T(rd);
-            sl3[p] = slot;
+            const double rd = sqrt(r2);
+            d3[p * 3 + 0] = T(dd[u][0]);
+            d3[p * 3 + 1] = T(dd[u][1]);
+            d3[p * 3 + 2] = T(dd[u][2]);
+            ir3[p] = T(1.0 / rd);
+            leg[u] = p;
             int f;
             T N[4], dN[4];
             bspline4p<T>(T(rd), a.ih3, a.nk3, pp3, f, N, dN);
@@ -193,99 +240,143 @@ __global__ void __launch_bounds__(256)
                 dB3[p * 4 + q] = dN[q];
             }
         }
-        __syncthreads();
-        if (lane == 0)
-            count3[w] += __popcll(mask);
-        __syncthreads();
+        n3 += __popcll(mask);
     }
-    int n3 = count3[w];
+    wave_sync_lds_u();
     if (n3 > kMaxTriplet) {
         if (lane == 0)
             atomicOr(&hdr[H_STATUS], MLMIX_STATUS_TRIPLET_OVERFLOW);
         n3 = kMaxTriplet;
     }
-    if (a.nb3 > 0) {
-        // lane = leg j (low four bits) + k residue class kc (high two bits):
-        // lane (j, kc) sums the triplets (j, k) with k = kc (mod 4), then the
-        // four partial sums of leg j meet in a fixed shuffle order.
-        const int jl = lane & 15, kc = lane >> 4;
-        const int nb = a.nb3;
-        for (int jb = 0; jb < n3; jb += 16) {
-            const int t = jb + jl;
-            T hx = T(0), hy = T(0), hz = T(0);
-            if (t < n3) {
-                T dj0 = d3[t * 3], dj1 = d3[t * 3 + 1], dj2 = d3[t * 3 + 2];
-                T rj = r3[t];
-                int fj = f3[t];
-                T Bj[4], dBj[4];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    Bj[q] = B3[t * 4 + q];
-                    dBj[q] = dB3[t * 4 + q];
-                }
-                for (int k = kc; k < n3; k += 4) {
-                    if (k == t)
-                        continue;
-                    T e0 = d3[k * 3] - dj0, e1 = d3[k * 3 + 1] - dj1, e2 = d3[k * 3 + 2] - dj2;
-                    T rjk = sqrt(e0 * e0 + e1 * e1 + e2 * e2);
+    if (nb > 0) {
+        const T *cz = c3x + (size_t)zi * nb * nb * (nb - 3) * 4;
+        const int hh = n3 >> 1;
+        const int ngrid = n3 * hh;
+        const bool even = (n3 & 1) == 0;
+        T gx = T(0), gy = T(0), gz = T(0);  // lane x < n3: leg x
+        for (int t0 = 0; t0 < ngrid; t0 += 64) {
+            const int p = t0 + lane;
+            T cj0 = T(0), cj1 = T(0), cj2 = T(0), ck0 = T(0), ck1 = T(0), ck2 = T(0);
+            if (p < ngrid) {
+                const int o = p / n3 + 1;
+                const int j = p - (o - 1) * n3;
+                if (!(even && o == hh && j >= hh)) {
+                    int k = j + o;
+                    if (k >= n3)
+                        k -= n3;
+                    const T dj0 = d3[j * 3], dj1 = d3[j * 3 + 1], dj2 = d3[j * 3 + 2];
+                    const T dk0 = d3[k * 3], dk1 = d3[k * 3 + 1], dk2 = d3[k * 3 + 2];
+                    const T e0 = dk0 - dj0, e1 = dk1 - dj1, e2 = dk2 - dj2;
+                    const T rjk = sqrt(e0 * e0 + e1 * e1 + e2 * e2);
                     int fs;
                     T Ns[4], dNs[4];
                     bspline4p<T>(rjk, a.ih3c, a.nk3, pp3, fs, Ns, dNs);
-                    int fk = f3[k];
-                    T V = T(0), V1 = T(0), V3 = T(0);
+                    const int fj = f3[j], fk = f3[k];
+                    T Bj[4], dBj[4], Bk[4], dBk[4];
 #pragma unroll
-                    for (int pp = 0; pp < 4; ++pp) {
+                    for (int q = 0; q < 4; ++q) {
+                        Bj[q] = B3[j * 4 + q];
+                        dBj[q] = dB3[j * 4 + q];
+                        Bk[q] = B3[k * 4 + q];
+                        dBk[q] = dB3[k * 4 + q];
+                    }
+                    // contract the r_jk basis first, then leg k, then leg j
+                    T V = T(0), V1 = T(0), V2 = T(0), V3 = T(0);
+#pragma unroll
+                    for (int pa = 0; pa < 4; ++pa) {
+                        T u0 = T(0), uk = T(0), u1 = T(0);
 #pragma unroll
                         for (int q = 0; q < 4; ++q) {
-                            const T *cr = c3s + ((fj + pp) * nb + (fk + q)) * nb + fs;
-                            T bk = B3[k * 4 + q];
-                            T s0 = T(0), s1 = T(0);
-#pragma unroll
-                            for (int u = 0; u < 4; ++u) {
-                                s0 += cr[u] * Ns[u];
-                                s1 += cr[u] * dNs[u];
-                            }
-                            V += Bj[pp] * bk * s0;
-                            V1 += dBj[pp] * bk * s0;
-                            V3 += Bj[pp] * bk * s1;
+                            T cr[4];
+                            load4(cz + ((((fj + pa) * nb + (fk + q)) * (nb - 3) + fs) << 2), cr);
+                            const T s0 = ((cr[0] * Ns[0] + cr[1] * Ns[1]) + cr[2] * Ns[2]) + cr[3] * Ns[3];
+                            const T s1 =
+                                ((cr[0] * dNs[0] + cr[1] * dNs[1]) + cr[2] * dNs[2]) + cr[3] * dNs[3];
+                            u0 += s0 * Bk[q];
+                            uk += s0 * dBk[q];
+                            u1 += s1 * Bk[q];
                         }
+                        V += Bj[pa] * u0;
+                        V1 += dBj[pa] * u0;
+                        V2 += Bj[pa] * uk;
+                        V3 += Bj[pa] * u1;
                     }
-                    Ep += T(0.5) * V;
-                    T a1 = V1 / rj;
-                    T a3 = V3 / rjk;
-                    hx += a1 * dj0 - a3 * e0;
-                    hy += a1 * dj1 - a3 * e1;
-                    hz += a1 * dj2 - a3 * e2;
+                    Ep += V;
+                    const T irjk = T(1) / rjk;
+                    const T aj = V1 * ir3[j], ak = V2 * ir3[k], ajk = V3 * irjk;
+                    cj0 = aj * dj0 - ajk * e0;
+                    cj1 = aj * dj1 - ajk * e1;
+                    cj2 = aj * dj2 - ajk * e2;
+                    ck0 = ak * dk0 + ajk * e0;
+                    ck1 = ak * dk1 + ajk * e1;
+                    ck2 = ak * dk2 + ajk * e2;
                 }
             }
-            hx += __shfl_xor(hx, 16);
-            hy += __shfl_xor(hy, 16);
-            hz += __shfl_xor(hz, 16);
-            hx += __shfl_xor(hx, 32);
-            hy += __shfl_xor(hy, 32);
-            hz += __shfl_xor(hz, 32);
-            if (kc == 0 && t < n3) {
-                int slt = sl3[t];
-                hs[slt * 3 + 0] += hx;
-                hs[slt * 3 + 1] += hy;
-                hs[slt * 3 + 2] += hz;
+            rb[lane * 6 + 0] = cj0;
+            rb[lane * 6 + 1] = cj1;
+            rb[lane * 6 + 2] = cj2;
+            rb[lane * 6 + 3] = ck0;
+            rb[lane * 6 + 4] = ck1;
+            rb[lane * 6 + 5] = ck2;
+            wave_sync_lds_u();
+            if (lane < n3) {
+                const int x = lane;
+                for (int o = 1; o <= hh; ++o) {
+                    // pair (x, x + o): x is the first leg
+                    const int q1 = (o - 1) * n3 + x - t0;
+                    if (!(even && o == hh && x >= hh) && q1 >= 0 && q1 < 64) {
+                        gx += rb[q1 * 6 + 0];
+                        gy += rb[q1 * 6 + 1];
+                        gz += rb[q1 * 6 + 2];
+                    }
+                    // pair (x - o, x): x is the second leg
+                    int jp = x - o;
+                    if (jp < 0)
+                        jp += n3;
+                    const int q2 = (o - 1) * n3 + jp - t0;
+                    if (!(even && o == hh && jp >= hh) && q2 >= 0 && q2 < 64) {
+                        gx += rb[q2 * 6 + 3];
+                        gy += rb[q2 * 6 + 4];
+                        gz += rb[q2 * 6 + 5];
+                    }
+                }
             }
+            wave_sync_lds_u();
+        }
+        // leg sums back to the lanes that own the legs' slots
+        if (lane < n3) {
+            rb[lane * 3 + 0] = gx;
+            rb[lane * 3 + 1] = gy;
+            rb[lane * 3 + 2] = gz;
+        }
+        wave_sync_lds_u();
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (leg[u] >= 0) {
+                hx[u] += rb[leg[u] * 3 + 0];
+                hy[u] += rb[leg[u] * 3 + 1];
+                hz[u] += rb[leg[u] * 3 + 2];
+            }
+    }
+    T *ho = hout + (size_t)i * cap * 3;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int slot = lane + 64 * u;
+        if (slot < c) {
+            ho[slot * 3 + 0] = hx[u];
+            ho[slot * 3 + 1] = hy[u];
+            ho[slot * 3 + 2] = hz[u];
         }
     }
-    __syncthreads();
-    if (!valid)
-        return;
-    T *ho = hout + (size_t)i * cap * 3;
-    for (int e = lane; e < 3 * c; e += 64)
-        ho[e] = hs[e];
     T E = wave_sum_t(Ep);
     if (lane == 0)
         e_cheap[i] = (double)E;
+    }
 }
 
 template <typename T>
 static void uf3_t(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L, const Box &b,
-                  const double *pos, const int32_t *species, double *e_cheap)
+                  const double *pos, const int32_t *species, double *e_cheap, int side_blocks)
 {
     const DevModel &m = c.m;
     Uf3Args<T> a;
@@ -309,24 +400,36 @@ static void uf3_t(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L, cons
     a.c3 = reinterpret_cast<const T *>(base + m.u3);
     a.p2 = reinterpret_cast<const T *>(base + m.up2);
     a.p3 = reinterpret_cast<const T *>(base + m.up3);
-    int nb3c = m.nb3 > 0 ? m.nb3 * m.nb3 * m.nb3 : 0;
-    Uf3Slice sl = uf3_slice(L.cap, nb3c);
-    size_t sm = 4 * ((size_t)sl.nT * sizeof(T) + 2 * kMaxTriplet * sizeof(int)) +
-                16 * ((size_t)(m.nk2 - 1) + (m.nb3 > 0 ? m.nk3 - 1 : 0)) * sizeof(T) + 16;
-    k_uf3<T><<<(L.n + 3) / 4, 256, sm, s>>>(pos, L.n, b, species, L.cap, at<int>(ws, L.nbr),
-                                 at<int>(ws, L.cnt), a, at<T>(ws, L.h), e_cheap,
-                                 at<int>(ws, L.hdr));
+    const int c3n = uf3_c3_elems(m.ns, m.nb3);
+    const size_t nT = kUf3WaveT;
+    size_t sm = ((size_t)c3n + 4 * nT) * sizeof(T) + 4 * kMaxTriplet * sizeof(int) +
+                (16 * ((size_t)(m.nk2 - 1) + (m.nb3 > 0 ? m.nk3 - 1 : 0)) +
+                 (size_t)m.ns * m.ns * m.nb2) * sizeof(T) + 16;
+    unsigned nblk = (L.n + 3) / 4;
+    if (side_blocks > 0 && nblk > (unsigned)side_blocks)
+        nblk = side_blocks;
+#define MLMIX_UF3(U)                                                                             \
+    k_uf3<T, U><<<nblk, 256, sm, s>>>(pos, L.n, b, species, L.cap, at<int>(ws, L.nbr),            \
+                                      at<int>(ws, L.cnt), a, at<T>(ws, L.h), e_cheap,              \
+                                      at<int>(ws, L.hdr))
+    switch ((L.cap + 63) / 64) {
+    case 1: MLMIX_UF3(1); break;
+    case 2: MLMIX_UF3(2); break;
+    case 3: MLMIX_UF3(3); break;
+    default: MLMIX_UF3(4); break;
+    }
+#undef MLMIX_UF3
 }
 
 void launch_uf3(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L, const Box &b,
-                const double *pos, const int32_t *species, double *e_cheap)
+                const double *pos, const int32_t *species, double *e_cheap, int side_blocks)
 {
     if (L.n == 0)
         return;
     if (c.prec == MLMIX_FP64)
-        uf3_t<double>(s, c, ws, L, b, pos, species, e_cheap);
+        uf3_t<double>(s, c, ws, L, b, pos, species, e_cheap, side_blocks);
     else
-        uf3_t<float>(s, c, ws, L, b, pos, species, e_cheap);
+        uf3_t<float>(s, c, ws, L, b, pos, species, e_cheap, side_blocks);
 }
 
 }  // namespace mlmix
