@@ -224,6 +224,7 @@ static void build_o3(const mlmix_model_desc &d, HostTables &t)
         return;
     const int nch2 = nchp;  // row width of the kernel: channels rounded up to 4
     std::vector<int> cost(t.pb.size(), 0);
+    std::vector<std::vector<int>> rcost(t.pb.size());  // per (block, m3) row
     for (size_t p = 0; p < t.pb.size(); ++p) {
         const PBlock &b = t.pb[p];
         t.o3base.push_back((int)t.o3mt.size() / 2);
@@ -251,7 +252,9 @@ static void build_o3(const mlmix_model_desc &d, HostTables &t)
             }
             // MFMA steps per row tile: sparse 16 rows x groups, dense in
             // units of a 16x16x4 FP32 step (narrow operands are 8x cheaper)
-            cost[p] += 16 * ng + (narrow ? std::max(1, nch2 / 8) : 4 * nch2) + 4;
+            const int rc = 16 * ng + (narrow ? std::max(1, nch2 / 8) : 4 * nch2) + 4;
+            cost[p] += rc;
+            rcost[p].push_back(rc);
         }
     }
     (void)lmax;
@@ -283,33 +286,59 @@ static void build_o3(const mlmix_model_desc &d, HostTables &t)
                     }
                     t.o3w[(((p * nch2) + i) * 64 + l) * 4 + j] = v;
                 }
-    // blocks to waves, for a tile's block list split over G = 1, 2, 4, 8
-    // workgroups (4 G bins; longest first onto the least loaded bin)
-    std::vector<int> idx(P);
+    // work items to waves, for a tile's block list split over G = 1, 2, 4, 8
+    // workgroups (4 G bins). An item is a range of m3 rows of one block: for
+    // G > 1, a block costing more than half of a bin's even share is cut into
+    // row ranges of about that cost, so that no single block sets the time of
+    // its wave. Items go longest first onto the least loaded bin; each bin
+    // runs its items in (block, first row) order. Item code: block | first
+    // row << 16 | end row << 24.
+    long total = 0;
     for (size_t p = 0; p < P; ++p)
-        idx[p] = (int)p;
-    std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+        total += cost[p];
     t.o3order.clear();
     t.o3wbeg.clear();
     for (int G = 1; G <= kO3MaxSplit; G <<= 1) {
         const int nb = 4 * G;
+        // one workgroup per tile (large S): whole blocks (measured faster)
+        const long cap = G == 1 ? total : std::max<long>(1, total / nb / 2);
+        std::vector<std::pair<long, int>> items;  // (cost, code)
+        for (size_t p = 0; p < P; ++p) {
+            const int d3 = (int)rcost[p].size();
+            const int k = (int)std::min<long>(d3, (cost[p] + cap - 1) / cap);
+            int lo = 0;
+            for (int part = 0; part < k; ++part) {
+                const int hi = lo + (d3 - lo) / (k - part);  // near-even row counts
+                long cst = 0;
+                for (int r = lo; r < hi; ++r)
+                    cst += rcost[p][r];
+                items.push_back({cst, (int)p | (lo << 16) | (hi << 24)});
+                lo = hi;
+            }
+        }
+        std::stable_sort(items.begin(), items.end(),
+                         [](const std::pair<long, int> &x, const std::pair<long, int> &y) {
+                             return x.first > y.first;
+                         });
         std::vector<std::vector<int>> lists(nb);
         std::vector<long> load(nb, 0);
-        for (int p : idx) {
+        for (const auto &it : items) {
             int w = 0;
             for (int k = 1; k < nb; ++k)
                 if (load[k] < load[w])
                     w = k;
-            lists[w].push_back(p);
-            load[w] += cost[p];
+            lists[w].push_back(it.second);
+            load[w] += it.first;
         }
-        const int base = (int)t.o3order.size();
         for (int w = 0; w < nb; ++w) {
-            t.o3wbeg.push_back((int)t.o3order.size() - base);
-            std::sort(lists[w].begin(), lists[w].end());
+            t.o3wbeg.push_back((int)t.o3order.size());  // absolute offsets
+            std::sort(lists[w].begin(), lists[w].end(), [](int x, int y) {
+                const int px = x & 0xffff, py = y & 0xffff;
+                return px != py ? px < py : ((x >> 16) & 0xff) < ((y >> 16) & 0xff);
+            });
             t.o3order.insert(t.o3order.end(), lists[w].begin(), lists[w].end());
         }
-        t.o3wbeg.push_back((int)t.o3order.size() - base);
+        t.o3wbeg.push_back((int)t.o3order.size());
     }
     // FP8 row-scale bound: sum of |g| over the row's entries
     t.o3gs.clear();
@@ -878,7 +907,10 @@ extern "C" int mlmix_workspace_size(const mlmix_ctx *ctx, int32_t n_atoms, int32
     int rc = check_box(ctx, box, b);
     if (rc)
         return rc;
-    *bytes = make_layout(ctx->c, n_atoms, nbr_cap, b).total;
+    WsLayout L = make_layout(ctx->c, n_atoms, nbr_cap, b);
+    if ((double)L.grid.ncell * L.grid.bucket >= 2147483647.0)
+        return fail(MLMIX_E_ARG, "box too large for the cell grid (2^31 bucket records)");
+    *bytes = L.total;
     return MLMIX_OK;
 }
 
@@ -894,11 +926,14 @@ extern "C" int mlmix_workspace_init(mlmix_ctx *ctx, void *stream, void *ws, size
     if (rc)
         return rc;
     WsLayout L = make_layout(ctx->c, n_atoms, nbr_cap, b);
+    if ((double)L.grid.ncell * L.grid.bucket >= 2147483647.0)
+        return fail(MLMIX_E_ARG, "box too large for the cell grid (2^31 bucket records)");
     if (ws_bytes < L.total)
         return fail(MLMIX_E_WORKSPACE, "workspace smaller than mlmix_workspace_size()");
     hipStream_t s = static_cast<hipStream_t>(stream);
     k_zero_i32<<<1, H_COUNT, 0, s>>>(at<int>(ws, L.hdr), H_COUNT);
-    // cell counts start at zero; afterwards every force gather clears them
+    // cell counts start at zero; afterwards the reverse-slot pass of every
+    // rebuild clears them
     k_zero_i32<<<(L.grid.ncell + 255) / 256, 256, 0, s>>>(at<int>(ws, L.cell_count), L.grid.ncell);
     HIP_OK(hipGetLastError());
     std::lock_guard<std::mutex> g(ctx->mu);
@@ -962,7 +997,7 @@ static int compute_impl(mlmix_ctx *ctx, hipStream_t s, void *ws, const WsLayout 
     // run uncapped
     const int side_blocks = (!fork || m == MLMIX_MODE_ALL_CHEAP)
                                 ? 0
-                                : (c.side_blocks >= 0 ? c.side_blocks : (L.n < 262144 ? 256 : 1024));
+                                : (c.side_blocks >= 0 ? c.side_blocks : (L.n < 262144 ? 256 : 0));
     {
         StageTimer t(ctx, s, ST_NBR);
         RegionArgs ra{m, species, c.m.ns, regions, n_regions, r_buffer, lambda, flags, nullptr};

@@ -318,12 +318,18 @@ __device__ __forceinline__ void row_sort_store(const int *row, int lane, int kee
     }
 }
 
+// Candidate records listed per wave (at most this many; more fall back to
+// the per-cell walk).
+constexpr int kNbrList = 512;
+
 // One wavefront per atom, four atoms per 256-thread block, no block-level
 // barriers (each wave works in its own LDS slice). Each lane owns up to two
-// cells of the (up to) 5x5x5 stencil of half-radius cells and walks the
-// 32-byte records of their buckets two at a time (loads issued first); partners
-// closer than the list radius are kept by ballot compaction, and the row is
-// finally sorted ascending in registers (bitonic over 64, 128 or 256 keys).
+// cells of the (up to) 5x5x5 stencil of half-radius cells; a wave scan of
+// their bucket sizes places the candidates' record indices side by side in
+// LDS, and the lanes then test two 32-byte records per round (loads issued
+// first). Partners closer than the list radius are kept by ballot
+// compaction, and the row is finally sorted ascending in registers (bitonic
+// over 64, 128 or 256 keys).
 __global__ void __launch_bounds__(256) k_neighbors(const double *__restrict__ pos, int n, Box b,
                                                    Grid g, const int *__restrict__ count,
                                                    const CellAtom *__restrict__ atoms, double rl2,
@@ -335,6 +341,7 @@ __global__ void __launch_bounds__(256) k_neighbors(const double *__restrict__ po
     if (hdr[H_REBUILD] == 0)
         return;
     __shared__ int rows[4][kMaxCap];
+    __shared__ int lists[4][kNbrList];
     const int w = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     const int i = blockIdx.x * 4 + w;
@@ -383,47 +390,77 @@ __global__ void __launch_bounds__(256) k_neighbors(const double *__restrict__ po
             }
         }
     }
-    // every lane walks its own stencil cells (t and t + 64), kB records of
-    // each at a time with all their loads issued before the distance tests
-    int szmax = max(sz[0], sz[1]);
-#pragma unroll
-    for (int d = 32; d > 0; d >>= 1)
-        szmax = max(szmax, __shfl_xor(szmax, d));
+    // partner test of one record: inside the list radius (FP64, minimum
+    // image, no contraction) and not the atom itself; hits are compacted by
+    // ballot into the row (c counts every hit, also those past P)
     int c = 0;
-    constexpr int kB = 2;  // records per cell per round (register budget)
-    for (int k0 = 0; k0 < szmax; k0 += kB) {
-        CellAtom rec[2][kB];
-#pragma unroll
-        for (int h = 0; h < 2; ++h)
-#pragma unroll
-            for (int u = 0; u < kB; ++u)
-                if (k0 + u < sz[h])
-                    rec[h][u] = atoms[bg[h] + k0 + u];
-#pragma unroll
-        for (int h = 0; h < 2; ++h)
-#pragma unroll
-            for (int u = 0; u < kB; ++u) {
-                bool hit = false;
-                int j = 0;
-                if (k0 + u < sz[h]) {
-                    j = rec[h][u].j;
-                    double d[3] = {rec[h][u].x - xi[0], rec[h][u].y - xi[1], rec[h][u].z - xi[2]};
-                    for (int k = 0; k < 3; ++k) {
-                        if (b.per[k]) {
-                            double hh = 0.5 * b.L[k];
-                            double dx = d[k];
-                            dx = dx > hh ? dx - b.L[k] : (dx < -hh ? dx + b.L[k] : dx);
-                            d[k] = dx;
-                        }
-                    }
-                    hit = (j != i) && norm2(d) < rl2;
+    auto test = [&](bool valid, const CellAtom &r) {
+        bool hit = false;
+        if (valid) {
+            double d[3] = {r.x - xi[0], r.y - xi[1], r.z - xi[2]};
+            for (int k = 0; k < 3; ++k) {
+                if (b.per[k]) {
+                    double hh = 0.5 * b.L[k];
+                    double dx = d[k];
+                    dx = dx > hh ? dx - b.L[k] : (dx < -hh ? dx + b.L[k] : dx);
+                    d[k] = dx;
                 }
-                unsigned long long m = __ballot(hit);
-                int p = c + __popcll(m & ((1ull << lane) - 1ull));
-                if (hit && p < P)
-                    row[p] = j;
-                c += __popcll(m);
             }
+            hit = (r.j != i) && norm2(d) < rl2;
+        }
+        unsigned long long m = __ballot(hit);
+        int p = c + __popcll(m & ((1ull << lane) - 1ull));
+        if (hit && p < P)
+            row[p] = r.j;
+        c += __popcll(m);
+    };
+    // candidates in stencil-cell order: offsets by a wave scan of the sizes
+    const int inc0 = wave_incl_scan(sz[0]);
+    const int tot0 = __shfl(inc0, 63);
+    const int inc1 = wave_incl_scan(sz[1]);
+    const int ncand = tot0 + __shfl(inc1, 63);
+    if (ncand <= kNbrList) {
+        // dense list of the candidates' record indices; every lane then takes
+        // two records per round, loads first
+        int *lst = lists[w];
+        const int o0 = inc0 - sz[0], o1 = tot0 + inc1 - sz[1];
+        for (int k = 0; k < sz[0]; ++k)
+            lst[o0 + k] = (int)bg[0] + k;
+        for (int k = 0; k < sz[1]; ++k)
+            lst[o1 + k] = (int)bg[1] + k;
+        wave_sync_lds();
+        for (int f0 = 0; f0 < ncand; f0 += 128) {
+            const int fa = f0 + lane, fb = f0 + 64 + lane;
+            CellAtom ra{}, rb{};
+            if (fa < ncand)
+                ra = atoms[lst[fa]];
+            if (fb < ncand)
+                rb = atoms[lst[fb]];
+            test(fa < ncand, ra);
+            test(fb < ncand, rb);
+        }
+    } else {
+        // dense cells: every lane walks its own stencil cells (t and t + 64),
+        // kB records of each at a time with their loads issued first
+        int szmax = max(sz[0], sz[1]);
+#pragma unroll
+        for (int d = 32; d > 0; d >>= 1)
+            szmax = max(szmax, __shfl_xor(szmax, d));
+        constexpr int kB = 2;
+        for (int k0 = 0; k0 < szmax; k0 += kB) {
+            CellAtom rec[2][kB];
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int u = 0; u < kB; ++u)
+                    if (k0 + u < sz[h])
+                        rec[h][u] = atoms[bg[h] + k0 + u];
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int u = 0; u < kB; ++u)
+                    test(k0 + u < sz[h], rec[h][u]);
+        }
     }
     wave_sync_lds();
     const int keep = c < cap ? c : cap;
@@ -448,40 +485,65 @@ __global__ void __launch_bounds__(256) k_neighbors(const double *__restrict__ po
 }
 
 // rev[i][s] = slot of i in the row of j = nbr[i][s] (rows are ascending).
-// The bucket counts of the rebuild are no longer needed: they are cleared
-// here for the next one.
-__global__ void __launch_bounds__(256) k_reverse(int n, int cap, const int *__restrict__ nbr,
+// One wavefront per atom i (grid-stride), lane l owns slots l + 64 u; the U
+// searches of a lane advance together, each a branch-free binary search of
+// log2(P) steps (P = row capacity rounded up to a power of two). The bucket
+// counts of the rebuild are no longer needed: they are cleared here for the
+// next one.
+template <int U>
+__global__ void __launch_bounds__(256) k_reverse(int n, int cap, int P, const int *__restrict__ nbr,
                                                  const int *__restrict__ cnt,
                                                  int *__restrict__ rev, int *__restrict__ count,
                                                  int ncell, int *hdr)
 {
     if (hdr[H_REBUILD] == 0)
         return;
-    const size_t stride = (size_t)gridDim.x * blockDim.x;
-    const size_t t0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    for (size_t c = t0; c < (size_t)ncell; c += stride)
+    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+    for (int c = tid; c < ncell; c += gridDim.x * blockDim.x)
         count[c] = 0;
-    for (size_t t = t0; t < (size_t)n * cap; t += stride) {
-        int i = (int)(t / cap), s = (int)(t % cap);
-        int r = -1;
-        if (s < cnt[i]) {
-            int j = nbr[t];
-            const int *rowj = nbr + (size_t)j * cap;
-            int lo = 0, hi = cnt[j] - 1;
-            while (lo <= hi) {
-                int mid = (lo + hi) >> 1;
-                int v = rowj[mid];
-                if (v == i) {
-                    r = mid;
-                    break;
-                }
-                if (v < i)
-                    lo = mid + 1;
-                else
-                    hi = mid - 1;
+    const int lane = threadIdx.x & 63;
+    for (int i = blockIdx.x * 4 + (threadIdx.x >> 6); i < n; i += gridDim.x * 4) {
+        const int ci = cnt[i];
+        const int *rowi = nbr + (size_t)i * cap;
+        int j[U], cj[U], pos[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int sl = lane + 64 * u;
+            j[u] = sl < ci ? rowi[sl] : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            cj[u] = j[u] >= 0 ? cnt[j[u]] : 0;
+            pos[u] = 0;
+        }
+        // pos = number of entries of row j smaller than i
+        for (int step = P >> 1; step > 0; step >>= 1) {
+            int v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int k = pos[u] + step - 1;
+                v[u] = (j[u] >= 0 && k < cj[u]) ? nbr[(size_t)j[u] * cap + k] : 0x7fffffff;
             }
-    }
-    rev[t] = r;
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (v[u] < i)
+                    pos[u] += step;
+        }
+        if (P == 1) {
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                pos[u] = (j[u] >= 0 && cj[u] > 0 && nbr[(size_t)j[u] * cap] < i) ? 1 : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int sl = lane + 64 * u;
+            if (sl < cap) {
+                int r = -1;
+                if (j[u] >= 0 && pos[u] < cj[u] && nbr[(size_t)j[u] * cap + pos[u]] == i)
+                    r = pos[u];
+                rev[(size_t)i * cap + sl] = r;
+            }
+        }
     }
 }
 
@@ -516,18 +578,71 @@ void launch_neighbors(hipStream_t s, void *ws, const WsLayout &L, const Box &b, 
 
 // Reverse slots of a rebuilt list (skipped on the device when the list was
 // kept); needed by the force gather only, so it may run beside the potentials.
+// Uncapped form: one thread per (i, s), early-exit binary search in row j.
+__global__ void __launch_bounds__(256) k_reverse_flat(int n, int cap, const int *__restrict__ nbr,
+                                                      const int *__restrict__ cnt,
+                                                      int *__restrict__ rev,
+                                                      int *__restrict__ count, int ncell, int *hdr)
+{
+    if (hdr[H_REBUILD] == 0)
+        return;
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < (size_t)ncell)
+        count[t] = 0;
+    if (t >= (size_t)n * cap)
+        return;
+    // 32-bit division whenever the index fits (64-bit division is slow)
+    const int i = t < 0xffffffffull ? (int)((unsigned)t / (unsigned)cap) : (int)(t / cap);
+    const int sl = (int)(t - (size_t)i * cap);
+    int r = -1;
+    if (sl < cnt[i]) {
+        const int j = nbr[t];
+        const int *rowj = nbr + (size_t)j * cap;
+        int lo = 0, hi = cnt[j] - 1;
+        while (lo <= hi) {
+            const int mid = (lo + hi) >> 1;
+            const int v = rowj[mid];
+            if (v == i) {
+                r = mid;
+                break;
+            }
+            if (v < i)
+                lo = mid + 1;
+            else
+                hi = mid - 1;
+        }
+    }
+    rev[t] = r;
+}
+
 void launch_reverse(hipStream_t s, void *ws, const WsLayout &L, int side_blocks)
 {
     const int n = L.n;
     if (n == 0)
         return;
-    size_t tot = (size_t)n * L.cap;
-    size_t nblk = (tot + 255) / 256;
-    if (side_blocks > 0 && nblk > (size_t)side_blocks)
+    // uncapped: one thread per slot (measured faster on 1M atoms); capped
+    // beside the expensive chain: a wave per atom, grid-stride
+    const size_t tot = std::max((size_t)n * L.cap, (size_t)L.grid.ncell);
+    if (side_blocks <= 0 || (tot + 255) / 256 <= (size_t)side_blocks) {
+        k_reverse_flat<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(
+            n, L.cap, at<int>(ws, L.nbr), at<int>(ws, L.cnt), at<int>(ws, L.rev),
+            at<int>(ws, L.cell_count), L.grid.ncell, at<int>(ws, L.hdr));
+        return;
+    }
+    unsigned nblk = (unsigned)((n + 3) / 4);
+    if (nblk > (unsigned)side_blocks)
         nblk = side_blocks;
-    k_reverse<<<(unsigned)nblk, 256, 0, s>>>(
-        n, L.cap, at<int>(ws, L.nbr), at<int>(ws, L.cnt), at<int>(ws, L.rev),
-        at<int>(ws, L.cell_count), L.grid.ncell, at<int>(ws, L.hdr));
+#define MLMIX_REV(U)                                                                              \
+    k_reverse<U><<<nblk, 256, 0, s>>>(n, L.cap, L.P, at<int>(ws, L.nbr), at<int>(ws, L.cnt),       \
+                                      at<int>(ws, L.rev), at<int>(ws, L.cell_count), L.grid.ncell, \
+                                      at<int>(ws, L.hdr))
+    switch ((L.cap + 63) / 64) {
+    case 1: MLMIX_REV(1); break;
+    case 2: MLMIX_REV(2); break;
+    case 3: MLMIX_REV(3); break;
+    default: MLMIX_REV(4); break;
+    }
+#undef MLMIX_REV
 }
 
 // --------------------------------------------------------- lambda / masks

@@ -100,10 +100,11 @@ struct Ctx {
     int basis_mfma = 1;    // atomic basis and pair adjoint on the matrix cores (FP32)
     int fork_at = 0;       // second-stream fork after the rows (0) or the basis (1)
     // workgroup cap of the second-stream kernels (reverse slots, cheap
-    // potential; grid-stride loops): -1 automatic, 0 uncapped. Measured
-    // (us or ms per mixed step, uncapped / 256 / 1024 workgroups): 8,193
-    // atoms 178 / 166 / 176 us, 1,023,800 atoms 11.3 / - / 10.6 ms; the
-    // automatic cap is 256 below 262,144 atoms and 1024 above.
+    // potential; grid-stride loops): -1 automatic, 0 uncapped. Measured per
+    // mixed step, uncapped / 256 workgroups: 178 / 166 us on 8,193 atoms; on
+    // 1,023,800 atoms caps of 1024 and 2048 measured no better than none
+    // (11.6 / 11.2 / 11.3 ms, same box). Automatic: 256 below 262,144 atoms,
+    // uncapped above.
     int side_blocks = -1;
     int o3_nch2 = 0;       // row width of that kernel (channels rounded up to 4)
     // largest tile split of that kernel: 4 measured best on the 8,193-atom

@@ -5,8 +5,8 @@
 //
 // A workgroup owns a tile of 16 atoms of S and stages their A rows in LDS
 // ([atom][lm][16 channels], zero padded). Each of its four waves owns a fixed
-// list of blocks (balanced on the host) and, for every block and m3, one
-// 16-row tile whose rows are the 16 atoms:
+// list of work items (m3 row ranges of blocks, balanced on the host) and, for
+// every block and m3, one 16-row tile whose rows are the 16 atoms:
 //
 //  sparse stage  P_t[a][b] = sum_e g_e A_t[l1 m1_e][a] A_t[l2 m2_e][b] for
 //                each atom t, as a 16x16 MFMA product whose K runs over the
@@ -50,8 +50,9 @@ struct O3Args {
     const int *base;      // first (block, m3) row of each block
     const float *w;       // weight fragments [block][NC][64][4]
     const float *sw;      // FP8 weight scales [block][16]
-    const int *order;     // per split G = 1, 2, 4, 8: the blocks of bin 0, bin 1, ...
-    const int *wbeg;      // per split G: 4 G + 1 bin offsets into its order
+    const int *order;     // per split G = 1, 2, 4, 8: the items of bin 0, bin 1, ...
+                          // (block | first m3 << 16 | end m3 << 24)
+    const int *wbeg;      // per split G: 4 G + 1 bin offsets into order
     const float *gs;      // sum of |g| per (block, m3) (FP8 row-scale bound)
     const int *dp_off;    // per-block offset in the partial buffer
     const PBlock *pb;
@@ -195,7 +196,7 @@ __global__ void __launch_bounds__(256, 1)
                                              (size_t)4 * kO3Atoms * rowb);
     float *sP = sPall + wv * kO3Atoms;
     float *amax = sPall + 4 * kO3Atoms;  // [16][L1]: max |A| per atom and l (FP8)
-    const int *order = a.order + lg * a.n_pb;
+    const int *order = a.order;
     const int *wbeg = a.wbeg + 4 * (G - 1) + lg;
 
     for (int item = blockIdx.x; item < nitem; item += gridDim.x) {
@@ -229,9 +230,9 @@ __global__ void __launch_bounds__(256, 1)
         }
 
         for (int wi = w_lo; wi < w_hi; ++wi) {
-            const int p = order[wi];
+            const int code = order[wi];
+            const int p = code & 0xffff, m3lo = (code >> 16) & 0xff, m3hi = (code >> 24) & 0xff;
             const PBlock pbk = a.pb[p];
-            const int d3 = 2 * pbk.l3 + 1;
             const int rbase = a.base[p];
             // weight fragments of this lane: element 4 i + j <-> (a = i, b = 4 q + j, c = m)
             f4v wf[NC];
@@ -267,12 +268,12 @@ __global__ void __launch_bounds__(256, 1)
 
             // entries of the first row; each row prefetches the next one's
             int2 ent[kO3MaxGroups], ent_n[kO3MaxGroups];
-            int e0 = a.mt[2 * rbase], ng = a.mt[2 * rbase + 1];
+            int e0 = a.mt[2 * (rbase + m3lo)], ng = a.mt[2 * (rbase + m3lo) + 1];
             o3_load_row(a.e, e0, q, ent);
-            for (int m3 = 0; m3 < d3; ++m3) {
+            for (int m3 = m3lo; m3 < m3hi; ++m3) {
                 const int row = rbase + m3;
                 int ngn = 0;
-                if (m3 + 1 < d3) {
+                if (m3 + 1 < m3hi) {
                     ngn = a.mt[2 * row + 3];
                     o3_load_row(a.e, a.mt[2 * row + 2], q, ent_n);
                 }
