@@ -838,6 +838,8 @@ extern "C" int mlmix_create(const mlmix_model_desc *desc, mlmix_ctx **out)
         c.fork_at = std::atoi(e) ? 1 : 0;
     if (const char *e = std::getenv("MLMIX_SIDE_BLOCKS"))
         c.side_blocks = std::max(-1, std::atoi(e));
+    if (const char *e = std::getenv("MLMIX_REV_BLOCKS"))
+        c.rev_blocks = std::max(1, std::atoi(e));
     if (const char *e = std::getenv("MLMIX_O3_MAX_SPLIT")) {
         int v = std::atoi(e);
         if (v == 1 || v == 2 || v == 4 || v == 8)
@@ -995,6 +997,7 @@ static int compute_impl(mlmix_ctx *ctx, hipStream_t s, void *ws, const WsLayout 
     // workgroup cap of those two kernels when they run beside the expensive
     // chain (leave it room); on one stream or beside no expensive work they
     // run uncapped
+    const int rev_blocks = c.rev_blocks;
     const int side_blocks = (!fork || m == MLMIX_MODE_ALL_CHEAP)
                                 ? 0
                                 : (c.side_blocks >= 0 ? c.side_blocks : (L.n < 262144 ? 256 : 0));
@@ -1014,7 +1017,7 @@ static int compute_impl(mlmix_ctx *ctx, hipStream_t s, void *ws, const WsLayout 
         }
         {
             StageTimer t(ctx, s2, ST_REV);
-            launch_reverse(s2, ws, L, side_blocks);
+            launch_reverse(s2, ws, L, side_blocks > 0 ? rev_blocks : 0);
         }
         if (!energy_only) {
             if (m != MLMIX_MODE_ALL_EXPENSIVE) {
@@ -1036,7 +1039,7 @@ static int compute_impl(mlmix_ctx *ctx, hipStream_t s, void *ws, const WsLayout 
     }
     {
         StageTimer t(ctx, s, ST_REG);
-        launch_regions(s, ws, L, b, m, pos, r_buffer, flags);
+        launch_regions(s, ws, L, b, m, pos, r_buffer, flags, (mode & MLMIX_FORCE_REBUILD) ? 1 : 0);
     }
     {
         StageTimer t(ctx, s, ST_CMP);

@@ -335,7 +335,9 @@ __global__ void __launch_bounds__(256) k_neighbors(const double *__restrict__ po
                                                    const CellAtom *__restrict__ atoms, double rl2,
                                                    int cap, int P, int *__restrict__ nbr,
                                                    int *__restrict__ cnt,
-                                                   double *__restrict__ ref, int *hdr)
+                                                   double *__restrict__ ref, int *hdr,
+                                                   double rb2, uint8_t *__restrict__ flags,
+                                                   const uint8_t *__restrict__ cand)
 {
 #pragma clang fp contract(off)
     if (hdr[H_REBUILD] == 0)
@@ -392,8 +394,12 @@ __global__ void __launch_bounds__(256) k_neighbors(const double *__restrict__ po
     }
     // partner test of one record: inside the list radius (FP64, minimum
     // image, no contraction) and not the atom itself; hits are compacted by
-    // ballot into the row (c counts every hit, also those past P)
+    // ballot into the row (c counts every hit, also those past P). A buffer
+    // candidate (rb2 >= 0) also looks for a partner with lambda > 0 strictly
+    // inside the buffer radius (the same distance as the buffer pass).
     int c = 0;
+    const bool want_buf = rb2 >= 0.0 && cand[i];
+    bool in_buf = false;
     auto test = [&](bool valid, const CellAtom &r) {
         bool hit = false;
         if (valid) {
@@ -406,7 +412,10 @@ __global__ void __launch_bounds__(256) k_neighbors(const double *__restrict__ po
                     d[k] = dx;
                 }
             }
-            hit = (r.j != i) && norm2(d) < rl2;
+            const double d2 = norm2(d);
+            hit = (r.j != i) && d2 < rl2;
+            if (want_buf && hit && d2 < rb2 && (flags[r.j] & 1))
+                in_buf = true;
         }
         unsigned long long m = __ballot(hit);
         int p = c + __popcll(m & ((1ull << lane) - 1ull));
@@ -471,6 +480,8 @@ __global__ void __launch_bounds__(256) k_neighbors(const double *__restrict__ po
         row_sort_store<2>(row, lane, keep, cap, out);
     else
         row_sort_store<4>(row, lane, keep, cap, out);
+    if (__ballot(in_buf) != 0ull && lane == 0)
+        flags[i] = (uint8_t)(flags[i] | 4);
     if (lane == 0) {
         cnt[i] = keep;
         // same-address device atomics serialise across the whole grid: only
@@ -550,6 +561,7 @@ __global__ void __launch_bounds__(256) k_reverse(int n, int cap, int P, const in
 void launch_neighbors(hipStream_t s, void *ws, const WsLayout &L, const Box &b, double r_list,
                       const double *pos, int force_rebuild, double skin, const RegionArgs &ra)
 {
+    // the row kernel also finds the buffer atoms (mixed mode) whenever it runs
     int *hdr = at<int>(ws, L.hdr);
     const Grid &g = L.grid;
     const int n = L.n;
@@ -571,9 +583,11 @@ void launch_neighbors(hipStream_t s, void *ws, const WsLayout &L, const Box &b, 
     r.cand = at<uint8_t>(ws, L.cand);
     k_bin_bucket<<<(n + 255) / 256, 256, 0, s>>>(pos, n, b, g, force_rebuild, hdr, count,
                                                  at<CellAtom>(ws, L.cell_atoms), r);
+    const double rb2 = ra.mode == MLMIX_MODE_MIXED ? ra.r_buffer * ra.r_buffer : -1.0;
     k_neighbors<<<(n + 3) / 4, 256, 0, s>>>(pos, n, b, g, count, at<CellAtom>(ws, L.cell_atoms),
                                             r_list * r_list, L.cap, L.P, at<int>(ws, L.nbr),
-                                            at<int>(ws, L.cnt), at<double>(ws, L.ref_pos), hdr);
+                                            at<int>(ws, L.cnt), at<double>(ws, L.ref_pos), hdr,
+                                            rb2, ra.flags, r.cand);
 }
 
 // Reverse slots of a rebuilt list (skipped on the device when the list was
@@ -677,12 +691,15 @@ __global__ void __launch_bounds__(256) k_buffer(const double *__restrict__ pos, 
 }
 
 // Buffer pass of the region stage (lambda and the masks come from the
-// binning kernel of the neighbour stage).
+// binning kernel of the neighbour stage). On a forced rebuild the row kernel
+// has found the buffer atoms already; otherwise this pass runs and repeats
+// the same test (same distances, same result) for atoms whose rows were
+// rebuilt.
 void launch_regions(hipStream_t s, void *ws, const WsLayout &L, const Box &b, int mode,
-                    const double *pos, double r_buffer, uint8_t *flags)
+                    const double *pos, double r_buffer, uint8_t *flags, int force_rebuild)
 {
     int n = L.n;
-    if (n == 0)
+    if (n == 0 || force_rebuild)
         return;
     uint8_t *cand = at<uint8_t>(ws, L.cand);
     if (mode == MLMIX_MODE_MIXED)
@@ -692,6 +709,10 @@ void launch_regions(hipStream_t s, void *ws, const WsLayout &L, const Box &b, in
 }
 
 // ------------------------------------------------------------ compaction
+
+// Systems of at most this many scan tiles (2048 atoms each) compact in one
+// pass.
+constexpr int kCmpDirect = 32;
 
 __global__ void __launch_bounds__(256) k_cmp_blocksum(const uint8_t *__restrict__ flags, int n,
                                                       int *__restrict__ partS,
@@ -723,15 +744,55 @@ __global__ void __launch_bounds__(256) k_cmp_apply(const uint8_t *__restrict__ f
                                                    const int *__restrict__ partM, int *hdr,
                                                    int32_t *n_expensive, int *__restrict__ S_idx,
                                                    int *__restrict__ M_idx,
-                                                   int *__restrict__ S_local)
+                                                   int *__restrict__ S_local, int direct)
 {
     __shared__ int sh[4];
     __shared__ int offs[2];
-    // offsets of this block: sums of partS/partM over the blocks before it
+    // offsets of this block: sums of partS/partM over the blocks before it,
+    // or (small systems, no first pass) counts of their flags
     int os = 0, om = 0;
-    for (int b = threadIdx.x; b < (int)blockIdx.x; b += 256) {
-        os += partS[b];
-        om += partM[b];
+    if (direct) {
+        const int lim = (int)blockIdx.x * kScanTile;  // a multiple of 2048
+        if ((reinterpret_cast<uintptr_t>(flags) & 3) == 0) {
+            // four flags per load, eight loads in flight per thread
+            const uint32_t *fw = reinterpret_cast<const uint32_t *>(flags);
+            for (int w0 = 0; w0 < lim / 4; w0 += 8 * 256) {
+                uint32_t v[8];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const int e = w0 + k * 256 + (int)threadIdx.x;
+                    v[k] = e < lim / 4 ? fw[e] : 0u;
+                }
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const uint32_t f = (v[k] >> (8 * q)) & 0xffu;
+                        os += (f & 5u) ? 1 : 0;
+                        om += (f & 1u) ? 1 : 0;
+                    }
+                }
+            }
+        } else {
+            for (int e0 = 0; e0 < lim; e0 += 8 * 256) {
+                uint8_t v[8];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const int e = e0 + k * 256 + (int)threadIdx.x;
+                    v[k] = e < lim ? flags[e] : (uint8_t)0;
+                }
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    os += (v[k] & 5) ? 1 : 0;
+                    om += (v[k] & 1) ? 1 : 0;
+                }
+            }
+        }
+    } else {
+        for (int b = threadIdx.x; b < (int)blockIdx.x; b += 256) {
+            os += partS[b];
+            om += partM[b];
+        }
     }
     int ts, tm;
     block_excl_scan(os, sh, ts);
@@ -787,10 +848,13 @@ void launch_compact(hipStream_t s, void *ws, const WsLayout &L, uint8_t *flags,
         nb = 1;
     int *partS = at<int>(ws, L.scan_part);
     int *partM = partS + nb;
-    k_cmp_blocksum<<<nb, 256, 0, s>>>(flags, n, partS, partM);
+    // up to kCmpDirect tiles: one pass, each block counts the flags before it
+    const int direct = nb <= kCmpDirect ? 1 : 0;
+    if (!direct)
+        k_cmp_blocksum<<<nb, 256, 0, s>>>(flags, n, partS, partM);
     k_cmp_apply<<<nb, 256, 0, s>>>(flags, n, partS, partM, at<int>(ws, L.hdr), n_expensive,
                                    at<int>(ws, L.S_idx), at<int>(ws, L.M_idx),
-                                   at<int>(ws, L.S_local));
+                                   at<int>(ws, L.S_local), direct);
 }
 
 }  // namespace mlmix

@@ -99,13 +99,15 @@ struct Ctx {
     int o3 = 0;            // order-3 contraction on the per-wave matrix-core kernel
     int basis_mfma = 1;    // atomic basis and pair adjoint on the matrix cores (FP32)
     int fork_at = 0;       // second-stream fork after the rows (0) or the basis (1)
-    // workgroup cap of the second-stream kernels (reverse slots, cheap
-    // potential; grid-stride loops): -1 automatic, 0 uncapped. Measured per
-    // mixed step, uncapped / 256 workgroups: 178 / 166 us on 8,193 atoms; on
+    // workgroup cap of the cheap-potential kernel on the second stream
+    // (grid-stride loop): -1 automatic, 0 uncapped. Measured per mixed step
+    // on 8,193 atoms: uncapped 178 us, 256 workgroups (one per CU) 166 us,
+    // later 153 us against 168 / 183 / 175 us at 320 / 384 / 512; on
     // 1,023,800 atoms caps of 1024 and 2048 measured no better than none
     // (11.6 / 11.2 / 11.3 ms, same box). Automatic: 256 below 262,144 atoms,
     // uncapped above.
     int side_blocks = -1;
+    int rev_blocks = 1024;  // cap of the reverse-slot kernel when capped (256 / 1024 measured 153.0 / 152.4 us)
     int o3_nch2 = 0;       // row width of that kernel (channels rounded up to 4)
     // largest tile split of that kernel: 4 measured best on the 8,193-atom
     // cell (910 atoms in S: contraction 92 / 52 / 37 / 48 us at 1 / 2 / 4 / 8)
@@ -144,7 +146,7 @@ void launch_neighbors(hipStream_t s, void *ws, const WsLayout &L, const Box &b, 
                       const double *pos, int force_rebuild, double skin, const RegionArgs &ra);
 void launch_reverse(hipStream_t s, void *ws, const WsLayout &L, int side_blocks);
 void launch_regions(hipStream_t s, void *ws, const WsLayout &L, const Box &b, int mode,
-                    const double *pos, double r_buffer, uint8_t *flags);
+                    const double *pos, double r_buffer, uint8_t *flags, int force_rebuild);
 void launch_compact(hipStream_t s, void *ws, const WsLayout &L, uint8_t *flags, int32_t *n_expensive);
 
 // ---- ace.hip ----
