@@ -113,9 +113,10 @@ __host__ __device__ inline int uf3_c3_elems(int ns, int nb3)
     return nb3 > 0 ? ns * nb3 * nb3 * (nb3 - 3) * 4 : 0;
 }
 
-// Four centre atoms per 256-thread block, one wavefront each; the spline
-// and coefficient tables are staged once per block (the only block
-// barrier), everything after it is wave-local.
+// Four centre atoms per block, one wavefront each (grid-stride over groups
+// of atoms when the grid is capped); the spline and coefficient tables are
+// staged once per block (the only block barrier), everything after it is
+// wave-local.
 //
 // Pair terms: lane l owns row slots l + 64 u (u < U); all row entries and
 // partner positions are loaded before any arithmetic, E_i += V2(r)/2 and
@@ -129,7 +130,7 @@ __host__ __device__ inline int uf3_c3_elems(int ns, int nb3)
 // dV3/dd_ij = V_1 u_ij - V_3 e / r_jk and dV3/dd_ik = V_2 u_ik + V_3 e / r_jk
 // (e = d_ik - d_ij) in LDS, and the lane of each leg adds the entries of its
 // pairs in a fixed order: no atomics, the same bits on every run.
-template <typename T, int U>
+template <typename T, int U, bool LOOP>
 __global__ void __launch_bounds__(256)
     k_uf3(const double *__restrict__ pos, int n, Box b, const int32_t *__restrict__ species,
           int cap, const int *__restrict__ nbr, const int *__restrict__ cnt, Uf3Args<T> a,
@@ -147,9 +148,10 @@ __global__ void __launch_bounds__(256)
     T *B3 = ir3 + kMaxTriplet;
     T *dB3 = B3 + 4 * kMaxTriplet;
     T *rb = dB3 + 4 * kMaxTriplet;
-    int *f3 = reinterpret_cast<int *>(c3x + c3n + 4 * (size_t)nT) + w * kMaxTriplet;
-    T *pp2 = reinterpret_cast<T *>(reinterpret_cast<int *>(c3x + c3n + 4 * (size_t)nT) +
-                                   4 * kMaxTriplet);
+    constexpr int wpb = 4;  // waves (atoms in flight) per block
+    int *f3 = reinterpret_cast<int *>(c3x + c3n + wpb * (size_t)nT) + w * kMaxTriplet;
+    T *pp2 = reinterpret_cast<T *>(reinterpret_cast<int *>(c3x + c3n + wpb * (size_t)nT) +
+                                   wpb * kMaxTriplet);
     T *pp3 = pp2 + 16 * (a.nk2 - 1);
     T *c2s = pp3 + (nb > 0 ? 16 * (a.nk3 - 1) : 0);
     const int c2n = a.ns * a.ns * a.nb2;
@@ -164,11 +166,9 @@ __global__ void __launch_bounds__(256)
             c3x[e] = a.c3[e];
     }
     __syncthreads();
-    // groups of four atoms, grid-stride (no block barrier below)
-    for (int grp = blockIdx.x; grp < (n + 3) / 4; grp += gridDim.x) {
-        const int i = grp * 4 + w;
-        if (i >= n)
-            continue;
+    // one atom per wave: one group of atoms per block, or a grid-stride loop
+    // over groups (capped grids); no block barrier below
+    auto atom = [&](const int i) {
         wave_sync_lds_u();
         const int zi = sp_clamp(species[i], a.ns);
         const int c = cnt[i];
@@ -178,199 +178,210 @@ __global__ void __launch_bounds__(256)
         for (int u = 0; u < U; ++u) {
             const int slot = lane + 64 * u;
             jj[u] = slot < c ? row[slot] : -1;
-    }
-    double dd[U][3], rr2[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-        rr2[u] = 1.0e300;
-        dd[u][0] = dd[u][1] = dd[u][2] = 0.0;
-        if (jj[u] >= 0)
-            rr2[u] = pair_disp_u(pos, n, i, jj[u], b, dd[u]);
-    }
-    int zj[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-        zj[u] = (a.ns > 1 && jj[u] >= 0) ? sp_clamp(species[jj[u]], a.ns) : 0;
-    T Ep = T(0);
-    int n3 = 0;
-    T hx[U], hy[U], hz[U];  // dE_i/dd_ij of the lane's slots
-    int leg[U];             // 3-body leg index of the slot, or -1
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-        const int slot = lane + 64 * u;
-        const double r2 = rr2[u];
-        hx[u] = hy[u] = hz[u] = T(0);
-        leg[u] = -1;
-        if (r2 < a.rc2sq) {
-            const double rd = sqrt(r2);
-            const T r = T(rd);
-            int f;
-            T N[4], dN[4];
-            bspline4p<T>(r, a.ih2, a.nk2, pp2, f, N, dN);
-            const T *cc = c2s + (zi * a.ns + zj[u]) * a.nb2 + f;
-            T V = T(0), dV = T(0);
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                V += cc[q] * N[q];
-                dV += cc[q] * dN[q];
-            }
-            Ep += T(0.5) * V;
-            const T sc = T(0.5) * dV / r;
-            hx[u] = sc * T(dd[u][0]);
-            hy[u] = sc * T(dd[u][1]);
-            hz[u] = sc * T(dd[u][2]);
         }
-        const bool in3 = nb > 0 && r2 < a.rc3sq;
-        const unsigned long long mask = __ballot(in3);
-        const int p = n3 + __popcll(mask & ((1ull << lane) - 1ull));
-        if (in3 && p < kMaxTriplet) {
-            const double rd = sqrt(r2);
-            d3[p * 3 + 0] = T(dd[u][0]);
-            d3[p * 3 + 1] = T(dd[u][1]);
-            d3[p * 3 + 2] = T(dd[u][2]);
-            ir3[p] = T(1.0 / rd);
-            leg[u] = p;
-            int f;
-            T N[4], dN[4];
-            bspline4p<T>(T(rd), a.ih3, a.nk3, pp3, f, N, dN);
-            f3[p] = f;
+        double dd[U][3], rr2[U];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                B3[p * 4 + q] = N[q];
-                dB3[p * 4 + q] = dN[q];
-            }
+        for (int u = 0; u < U; ++u) {
+            rr2[u] = 1.0e300;
+            dd[u][0] = dd[u][1] = dd[u][2] = 0.0;
+            if (jj[u] >= 0)
+                rr2[u] = pair_disp_u(pos, n, i, jj[u], b, dd[u]);
         }
-        n3 += __popcll(mask);
-    }
-    wave_sync_lds_u();
-    if (n3 > kMaxTriplet) {
-        if (lane == 0)
-            atomicOr(&hdr[H_STATUS], MLMIX_STATUS_TRIPLET_OVERFLOW);
-        n3 = kMaxTriplet;
-    }
-    if (nb > 0) {
-        const T *cz = c3x + (size_t)zi * nb * nb * (nb - 3) * 4;
-        const int hh = n3 >> 1;
-        const int ngrid = n3 * hh;
-        const bool even = (n3 & 1) == 0;
-        T gx = T(0), gy = T(0), gz = T(0);  // lane x < n3: leg x
-        for (int t0 = 0; t0 < ngrid; t0 += 64) {
-            const int p = t0 + lane;
-            T cj0 = T(0), cj1 = T(0), cj2 = T(0), ck0 = T(0), ck1 = T(0), ck2 = T(0);
-            if (p < ngrid) {
-                const int o = p / n3 + 1;
-                const int j = p - (o - 1) * n3;
-                if (!(even && o == hh && j >= hh)) {
-                    int k = j + o;
-                    if (k >= n3)
-                        k -= n3;
-                    const T dj0 = d3[j * 3], dj1 = d3[j * 3 + 1], dj2 = d3[j * 3 + 2];
-                    const T dk0 = d3[k * 3], dk1 = d3[k * 3 + 1], dk2 = d3[k * 3 + 2];
-                    const T e0 = dk0 - dj0, e1 = dk1 - dj1, e2 = dk2 - dj2;
-                    const T rjk = sqrt(e0 * e0 + e1 * e1 + e2 * e2);
-                    int fs;
-                    T Ns[4], dNs[4];
-                    bspline4p<T>(rjk, a.ih3c, a.nk3, pp3, fs, Ns, dNs);
-                    const int fj = f3[j], fk = f3[k];
-                    T Bj[4], dBj[4], Bk[4], dBk[4];
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        Bj[q] = B3[j * 4 + q];
-                        dBj[q] = dB3[j * 4 + q];
-                        Bk[q] = B3[k * 4 + q];
-                        dBk[q] = dB3[k * 4 + q];
-                    }
-                    // contract the r_jk basis first, then leg k, then leg j
-                    T V = T(0), V1 = T(0), V2 = T(0), V3 = T(0);
-#pragma unroll
-                    for (int pa = 0; pa < 4; ++pa) {
-                        T u0 = T(0), uk = T(0), u1 = T(0);
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) {
-                            T cr[4];
-                            load4(cz + ((((fj + pa) * nb + (fk + q)) * (nb - 3) + fs) << 2), cr);
-                            const T s0 = ((cr[0] * Ns[0] + cr[1] * Ns[1]) + cr[2] * Ns[2]) + cr[3] * Ns[3];
-                            const T s1 =
-                                ((cr[0] * dNs[0] + cr[1] * dNs[1]) + cr[2] * dNs[2]) + cr[3] * dNs[3];
-                            u0 += s0 * Bk[q];
-                            uk += s0 * dBk[q];
-                            u1 += s1 * Bk[q];
-                        }
-                        V += Bj[pa] * u0;
-                        V1 += dBj[pa] * u0;
-                        V2 += Bj[pa] * uk;
-                        V3 += Bj[pa] * u1;
-                    }
-                    Ep += V;
-                    const T irjk = T(1) / rjk;
-                    const T aj = V1 * ir3[j], ak = V2 * ir3[k], ajk = V3 * irjk;
-                    cj0 = aj * dj0 - ajk * e0;
-                    cj1 = aj * dj1 - ajk * e1;
-                    cj2 = aj * dj2 - ajk * e2;
-                    ck0 = ak * dk0 + ajk * e0;
-                    ck1 = ak * dk1 + ajk * e1;
-                    ck2 = ak * dk2 + ajk * e2;
-                }
-            }
-            rb[lane * 6 + 0] = cj0;
-            rb[lane * 6 + 1] = cj1;
-            rb[lane * 6 + 2] = cj2;
-            rb[lane * 6 + 3] = ck0;
-            rb[lane * 6 + 4] = ck1;
-            rb[lane * 6 + 5] = ck2;
-            wave_sync_lds_u();
-            if (lane < n3) {
-                const int x = lane;
-                for (int o = 1; o <= hh; ++o) {
-                    // pair (x, x + o): x is the first leg
-                    const int q1 = (o - 1) * n3 + x - t0;
-                    if (!(even && o == hh && x >= hh) && q1 >= 0 && q1 < 64) {
-                        gx += rb[q1 * 6 + 0];
-                        gy += rb[q1 * 6 + 1];
-                        gz += rb[q1 * 6 + 2];
-                    }
-                    // pair (x - o, x): x is the second leg
-                    int jp = x - o;
-                    if (jp < 0)
-                        jp += n3;
-                    const int q2 = (o - 1) * n3 + jp - t0;
-                    if (!(even && o == hh && jp >= hh) && q2 >= 0 && q2 < 64) {
-                        gx += rb[q2 * 6 + 3];
-                        gy += rb[q2 * 6 + 4];
-                        gz += rb[q2 * 6 + 5];
-                    }
-                }
-            }
-            wave_sync_lds_u();
-        }
-        // leg sums back to the lanes that own the legs' slots
-        if (lane < n3) {
-            rb[lane * 3 + 0] = gx;
-            rb[lane * 3 + 1] = gy;
-            rb[lane * 3 + 2] = gz;
-        }
-        wave_sync_lds_u();
+        int zj[U];
 #pragma unroll
         for (int u = 0; u < U; ++u)
-            if (leg[u] >= 0) {
-                hx[u] += rb[leg[u] * 3 + 0];
-                hy[u] += rb[leg[u] * 3 + 1];
-                hz[u] += rb[leg[u] * 3 + 2];
-            }
-    }
-    T *ho = hout + (size_t)i * cap * 3;
+            zj[u] = (a.ns > 1 && jj[u] >= 0) ? sp_clamp(species[jj[u]], a.ns) : 0;
+        T Ep = T(0);
+        int n3 = 0;
+        T hx[U], hy[U], hz[U];  // dE_i/dd_ij of the lane's slots
+        int leg[U];             // 3-body leg index of the slot, or -1
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-        const int slot = lane + 64 * u;
-        if (slot < c) {
-            ho[slot * 3 + 0] = hx[u];
-            ho[slot * 3 + 1] = hy[u];
-            ho[slot * 3 + 2] = hz[u];
+        for (int u = 0; u < U; ++u) {
+            const int slot = lane + 64 * u;
+            const double r2 = rr2[u];
+            hx[u] = hy[u] = hz[u] = T(0);
+            leg[u] = -1;
+            if (r2 < a.rc2sq) {
+                const double rd = sqrt(r2);
+                const T r = T(rd);
+                int f;
+                T N[4], dN[4];
+                bspline4p<T>(r, a.ih2, a.nk2, pp2, f, N, dN);
+                const T *cc = c2s + (zi * a.ns + zj[u]) * a.nb2 + f;
+                T V = T(0), dV = T(0);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    V += cc[q] * N[q];
+                    dV += cc[q] * dN[q];
+                }
+                Ep += T(0.5) * V;
+                const T sc = T(0.5) * dV / r;
+                hx[u] = sc * T(dd[u][0]);
+                hy[u] = sc * T(dd[u][1]);
+                hz[u] = sc * T(dd[u][2]);
+            }
+            const bool in3 = nb > 0 && r2 < a.rc3sq;
+            const unsigned long long mask = __ballot(in3);
+            const int p = n3 + __popcll(mask & ((1ull << lane) - 1ull));
+            if (in3 && p < kMaxTriplet) {
+                const double rd = sqrt(r2);
+                d3[p * 3 + 0] = T(dd[u][0]);
+                d3[p * 3 + 1] = T(dd[u][1]);
+                d3[p * 3 + 2] = T(dd[u][2]);
+                ir3[p] = T(1.0 / rd);
+                leg[u] = p;
+                int f;
+                T N[4], dN[4];
+                bspline4p<T>(T(rd), a.ih3, a.nk3, pp3, f, N, dN);
+                f3[p] = f;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    B3[p * 4 + q] = N[q];
+                    dB3[p * 4 + q] = dN[q];
+                }
+            }
+            n3 += __popcll(mask);
         }
-    }
-    T E = wave_sum_t(Ep);
-    if (lane == 0)
-        e_cheap[i] = (double)E;
+        wave_sync_lds_u();
+        if (n3 > kMaxTriplet) {
+            if (lane == 0)
+                atomicOr(&hdr[H_STATUS], MLMIX_STATUS_TRIPLET_OVERFLOW);
+            n3 = kMaxTriplet;
+        }
+        if (nb > 0) {
+            const T *cz = c3x + (size_t)zi * nb * nb * (nb - 3) * 4;
+            const int hh = n3 >> 1;
+            const int ngrid = n3 * hh;
+            const bool even = (n3 & 1) == 0;
+            T gx = T(0), gy = T(0), gz = T(0);  // lane x < n3: leg x
+            for (int t0 = 0; t0 < ngrid; t0 += 64) {
+                const int p = t0 + lane;
+                T cj0 = T(0), cj1 = T(0), cj2 = T(0), ck0 = T(0), ck1 = T(0), ck2 = T(0);
+                if (p < ngrid) {
+                    const int o = p / n3 + 1;
+                    const int j = p - (o - 1) * n3;
+                    if (!(even && o == hh && j >= hh)) {
+                        int k = j + o;
+                        if (k >= n3)
+                            k -= n3;
+                        const T dj0 = d3[j * 3], dj1 = d3[j * 3 + 1], dj2 = d3[j * 3 + 2];
+                        const T dk0 = d3[k * 3], dk1 = d3[k * 3 + 1], dk2 = d3[k * 3 + 2];
+                        const T e0 = dk0 - dj0, e1 = dk1 - dj1, e2 = dk2 - dj2;
+                        const T rjk = sqrt(e0 * e0 + e1 * e1 + e2 * e2);
+                        int fs;
+                        T Ns[4], dNs[4];
+                        bspline4p<T>(rjk, a.ih3c, a.nk3, pp3, fs, Ns, dNs);
+                        const int fj = f3[j], fk = f3[k];
+                        T Bj[4], dBj[4], Bk[4], dBk[4];
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            Bj[q] = B3[j * 4 + q];
+                            dBj[q] = dB3[j * 4 + q];
+                            Bk[q] = B3[k * 4 + q];
+                            dBk[q] = dB3[k * 4 + q];
+                        }
+                        // contract the r_jk basis first, then leg k, then leg j
+                        T V = T(0), V1 = T(0), V2 = T(0), V3 = T(0);
+#pragma unroll
+                        for (int pa = 0; pa < 4; ++pa) {
+                            T u0 = T(0), uk = T(0), u1 = T(0);
+#pragma unroll
+                            for (int q = 0; q < 4; ++q) {
+                                T cr[4];
+                                load4(cz + ((((fj + pa) * nb + (fk + q)) * (nb - 3) + fs) << 2), cr);
+                                const T s0 = ((cr[0] * Ns[0] + cr[1] * Ns[1]) + cr[2] * Ns[2]) + cr[3] * Ns[3];
+                                const T s1 =
+                                    ((cr[0] * dNs[0] + cr[1] * dNs[1]) + cr[2] * dNs[2]) + cr[3] * dNs[3];
+                                u0 += s0 * Bk[q];
+                                uk += s0 * dBk[q];
+                                u1 += s1 * Bk[q];
+                            }
+                            V += Bj[pa] * u0;
+                            V1 += dBj[pa] * u0;
+                            V2 += Bj[pa] * uk;
+                            V3 += Bj[pa] * u1;
+                        }
+                        Ep += V;
+                        const T irjk = T(1) / rjk;
+                        const T aj = V1 * ir3[j], ak = V2 * ir3[k], ajk = V3 * irjk;
+                        cj0 = aj * dj0 - ajk * e0;
+                        cj1 = aj * dj1 - ajk * e1;
+                        cj2 = aj * dj2 - ajk * e2;
+                        ck0 = ak * dk0 + ajk * e0;
+                        ck1 = ak * dk1 + ajk * e1;
+                        ck2 = ak * dk2 + ajk * e2;
+                    }
+                }
+                rb[lane * 6 + 0] = cj0;
+                rb[lane * 6 + 1] = cj1;
+                rb[lane * 6 + 2] = cj2;
+                rb[lane * 6 + 3] = ck0;
+                rb[lane * 6 + 4] = ck1;
+                rb[lane * 6 + 5] = ck2;
+                wave_sync_lds_u();
+                if (lane < n3) {
+                    const int x = lane;
+                    for (int o = 1; o <= hh; ++o) {
+                        // pair (x, x + o): x is the first leg
+                        const int q1 = (o - 1) * n3 + x - t0;
+                        if (!(even && o == hh && x >= hh) && q1 >= 0 && q1 < 64) {
+                            gx += rb[q1 * 6 + 0];
+                            gy += rb[q1 * 6 + 1];
+                            gz += rb[q1 * 6 + 2];
+                        }
+                        // pair (x - o, x): x is the second leg
+                        int jp = x - o;
+                        if (jp < 0)
+                            jp += n3;
+                        const int q2 = (o - 1) * n3 + jp - t0;
+                        if (!(even && o == hh && jp >= hh) && q2 >= 0 && q2 < 64) {
+                            gx += rb[q2 * 6 + 3];
+                            gy += rb[q2 * 6 + 4];
+                            gz += rb[q2 * 6 + 5];
+                        }
+                    }
+                }
+                wave_sync_lds_u();
+            }
+            // leg sums back to the lanes that own the legs' slots
+            if (lane < n3) {
+                rb[lane * 3 + 0] = gx;
+                rb[lane * 3 + 1] = gy;
+                rb[lane * 3 + 2] = gz;
+            }
+            wave_sync_lds_u();
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (leg[u] >= 0) {
+                    hx[u] += rb[leg[u] * 3 + 0];
+                    hy[u] += rb[leg[u] * 3 + 1];
+                    hz[u] += rb[leg[u] * 3 + 2];
+                }
+        }
+        T *ho = hout + (size_t)i * cap * 3;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int slot = lane + 64 * u;
+            if (slot < c) {
+                ho[slot * 3 + 0] = hx[u];
+                ho[slot * 3 + 1] = hy[u];
+                ho[slot * 3 + 2] = hz[u];
+            }
+        }
+        T E = wave_sum_t(Ep);
+        if (lane == 0)
+            e_cheap[i] = (double)E;
+    };
+    if constexpr (!LOOP) {
+        const int i = blockIdx.x * wpb + w;
+        if (i < n)
+            atom(i);
+    } else {
+        for (int grp = blockIdx.x; grp < (n + wpb - 1) / wpb; grp += gridDim.x) {
+            const int i = grp * wpb + w;
+            if (i < n)
+                atom(i);
+        }
     }
 }
 
@@ -402,16 +413,24 @@ static void uf3_t(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L, cons
     a.p3 = reinterpret_cast<const T *>(base + m.up3);
     const int c3n = uf3_c3_elems(m.ns, m.nb3);
     const size_t nT = kUf3WaveT;
-    size_t sm = ((size_t)c3n + 4 * nT) * sizeof(T) + 4 * kMaxTriplet * sizeof(int) +
+    // eight waves per block on capped grids measured slower overall (the
+    // kernel then crowds the expensive chain: 159-166 us against 152 us)
+    const int wpb = 4;
+    size_t sm = ((size_t)c3n + wpb * nT) * sizeof(T) + wpb * kMaxTriplet * sizeof(int) +
                 (16 * ((size_t)(m.nk2 - 1) + (m.nb3 > 0 ? m.nk3 - 1 : 0)) +
                  (size_t)m.ns * m.ns * m.nb2) * sizeof(T) + 16;
-    unsigned nblk = (L.n + 3) / 4;
+    unsigned nblk = (L.n + wpb - 1) / wpb;
     if (side_blocks > 0 && nblk > (unsigned)side_blocks)
         nblk = side_blocks;
+#define MLMIX_UF3_W(U, LOOP)                                                                     \
+    k_uf3<T, U, LOOP><<<nblk, 256, sm, s>>>(pos, L.n, b, species, L.cap, at<int>(ws, L.nbr),    \
+                                                at<int>(ws, L.cnt), a, at<T>(ws, L.h), e_cheap,     \
+                                                at<int>(ws, L.hdr))
 #define MLMIX_UF3(U)                                                                             \
-    k_uf3<T, U><<<nblk, 256, sm, s>>>(pos, L.n, b, species, L.cap, at<int>(ws, L.nbr),            \
-                                      at<int>(ws, L.cnt), a, at<T>(ws, L.h), e_cheap,              \
-                                      at<int>(ws, L.hdr))
+    if (nblk < (unsigned)((L.n + wpb - 1) / wpb))                                                 \
+        MLMIX_UF3_W(U, true);                                                                     \
+    else                                                                                          \
+        MLMIX_UF3_W(U, false)
     switch ((L.cap + 63) / 64) {
     case 1: MLMIX_UF3(1); break;
     case 2: MLMIX_UF3(2); break;
@@ -419,6 +438,7 @@ static void uf3_t(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L, cons
     default: MLMIX_UF3(4); break;
     }
 #undef MLMIX_UF3
+#undef MLMIX_UF3_W
 }
 
 void launch_uf3(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L, const Box &b,

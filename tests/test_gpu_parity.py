@@ -94,3 +94,33 @@ def test_repeat_is_bitwise_and_rebuild_decision():
     g2 = run_gpu(w, 0, precision="fp32", system=(sy, pos, sp), force_rebuild=False)
     assert np.array_equal(g1["forces"], g2["forces"])
     assert np.array_equal(g1["e_exp"], g2["e_exp"])
+
+
+def test_buffer_paths_agree_with_oracle():
+    # the buffer atoms come from the row kernel on a forced rebuild, from the
+    # buffer pass when the list is kept, and from both when a displacement
+    # triggers the rebuild: every path must give the oracle's masks and sets
+    w = W.c2()
+    print("case c2 buffer paths: forced, kept, displacement rebuild", flush=True)
+    g1 = run_gpu(w, 0, precision="fp32")
+    sy, pos, sp = g1["system"]
+    g2 = run_gpu(w, 0, precision="fp32", system=(sy, pos, sp), force_rebuild=False)
+    ref = O.mixed(w, O.MODE_MIXED)
+    for g in (g1, g2):
+        assert np.array_equal(g["flags"], ref["flags"])
+        assert np.array_equal(g["S"], ref["S"])
+        assert np.array_equal(g["M"], ref["M"])
+    # move a few atoms by more than half the skin: the list is rebuilt
+    import torch
+    w3 = dict(w)
+    p3 = w["pos"].copy()
+    p3[::97] += 0.6
+    p3 = W.wrap(p3, w["L"], w["periodic"])
+    w3["pos"] = p3
+    pos.copy_(torch.from_numpy(np.ascontiguousarray(p3.T)).to(pos.device))
+    g3 = run_gpu(w3, 0, precision="fp32", system=(sy, pos, sp), force_rebuild=False)
+    ref3 = O.mixed(w3, O.MODE_MIXED)
+    assert_neighbors_equal(g3, ref3)
+    assert np.array_equal(g3["flags"], ref3["flags"])
+    assert np.array_equal(g3["S"], ref3["S"])
+    assert np.array_equal(g3["M"], ref3["M"])
