@@ -126,7 +126,7 @@ def pair_counts(w, nbr, cnt, S_mask):
     exp_pairs = int(np.sum(S_mask[rows] & S_mask[cols] & (r2 < rce ** 2)))
     cheap2 = int(np.sum(r2 < rc2 ** 2))
     k3 = np.bincount(rows[r2 < rc3 ** 2], minlength=n) if m["uf3"]["n_knots3"] > 0 else np.zeros(n, int)
-    cheap3 = int(np.sum(k3 * (k3 - 1)))
+    cheap3 = int(np.sum(k3 * (k3 - 1) // 2))  # unordered leg pairs
     return dict(exp_pairs=exp_pairs, cheap_pairs=cheap2, cheap_triplets=cheap3,
                 list_pairs=int(cnt.sum()), n=n)
 

@@ -266,7 +266,7 @@ const char *mlmix_profile_stage_name(int32_t stage);
 /* Operation counts of the kernels as written, for roofline reporting
  * (out[6]): [0] expensive order-3 contraction per S atom, [1] atomic basis
  * per expensive pair, [2] pair adjoint per expensive pair, [3] cheap 2-body
- * per pair, [4] cheap 3-body per ordered pair of legs, [5] the part of [0]
+ * per pair, [4] cheap 3-body per unordered pair of legs, [5] the part of [0]
  * spent in the dense order-3 stage (the stage whose operands the BF16/FP8
  * modes narrow). */
 int mlmix_model_flops(const mlmix_ctx *ctx, double *out);

@@ -815,7 +815,8 @@ extern "C" int mlmix_create(const mlmix_model_desc *desc, mlmix_ctx **out)
         ctx->flops[1] = 16.0 + 6.0 * nr + 8.0 * L2d + 2.0 * nr * L2d;   // atomic basis, per pair
         ctx->flops[2] = 31.0 + 10.0 * nr + L2d * (4.0 * nr + 24.0);     // pair adjoint, per pair
         ctx->flops[3] = 96.0;                                 // cheap 2-body, per pair
-        ctx->flops[4] = 495.0;                                // cheap 3-body, per ordered leg pair
+        ctx->flops[4] = 444.0;  // cheap 3-body, per unordered leg pair (r_jk spline, 4x4x4
+                                // contraction with the three derivatives, two leg forces)
         ctx->flops[5] = dense;                                // dense order-3 stage, per S atom
     }
     c.max_ent = 0;
