@@ -54,6 +54,9 @@ def parse():
     ap.add_argument("--only-mixed", action="store_true",
                     help="time the mixed step only (no all-expensive / all-cheap / latency runs); "
                          "used under a profiler so that every traced launch is a mixed-mode one")
+    ap.add_argument("--graph-steps", type=int, default=10,
+                    help="consecutive MD steps captured in one HIP graph for the timed "
+                         "region (1: one graph per step)")
     ap.add_argument("--single-stream", action="store_true",
                     help="keep every stage on the caller's stream (no fork of the cheap potential)")
     ap.add_argument("--probe", choices=["copy"], default=None,
@@ -172,20 +175,26 @@ def main():
                    single_stream=args.single_stream)
 
     def run(mode, steps, warmup, stage_mask=0, latency=False, graph=False):
-        """Times `steps` steps. graph=True captures one step in a HIP graph
-        and replays it; otherwise the step's kernels are launched eagerly."""
+        """Times `steps` steps. graph=True captures `chunk` consecutive steps
+        (args.graph_steps when it divides `steps`, one step when latency is
+        timed) in one HIP graph and replays it; otherwise the step's kernels
+        are launched eagerly."""
         sy, pos, vel, sp = fresh(mode)
         for _ in range(warmup):
             step(sy, pos, vel, sp, mode)
         sy.status()
         g = None
+        chunk = 1
         if graph:
+            if not latency and args.graph_steps > 1 and steps % args.graph_steps == 0:
+                chunk = args.graph_steps
             g = torch.cuda.CUDAGraph()
             cs = torch.cuda.Stream()
             cs.wait_stream(torch.cuda.current_stream())
             with torch.cuda.stream(cs):
                 with torch.cuda.graph(g, stream=cs):
-                    step(sy, pos, vel, sp, mode)
+                    for _ in range(chunk):
+                        step(sy, pos, vel, sp, mode)
             torch.cuda.current_stream().wait_stream(cs)
             for _ in range(3):
                 g.replay()
@@ -194,7 +203,7 @@ def main():
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         lat = []
-        for _ in range(steps):
+        for _ in range(steps // chunk):
             ts = time.perf_counter()
             if g is not None:
                 g.replay()
@@ -362,7 +371,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOADS[cfg], "n_atoms": n, "mode": "mixed",
                    "precision": prec, "neighbour_rebuild": "every step", "n_S": nS, "n_lambda_pos": nM,
-                   "launch": "one captured HIP graph per step, replayed"},
+                   "launch": (f"{args.graph_steps} consecutive steps per captured HIP graph, "
+                              "replayed" if args.steps % args.graph_steps == 0 and args.graph_steps > 1
+                              else "one captured HIP graph per step, replayed")},
         "eager_atom_steps_per_s": n * args.steps / el_eager,
         "all_expensive_atom_steps_per_s": rate_e,
         "all_cheap_atom_steps_per_s": rate_c,

@@ -836,7 +836,7 @@ extern "C" int mlmix_create(const mlmix_model_desc *desc, mlmix_ctx **out)
     c.o3 = t.o3 ? 1 : 0;
     c.o3_nch2 = t.o3_nch2;
     if (const char *e = std::getenv("MLMIX_FORK_AT"))
-        c.fork_at = std::atoi(e) ? 1 : 0;
+        c.fork_at = std::max(0, std::min(2, std::atoi(e)));
     if (const char *e = std::getenv("MLMIX_SIDE_BLOCKS"))
         c.side_blocks = std::max(-1, std::atoi(e));
     if (const char *e = std::getenv("MLMIX_REV_BLOCKS"))
@@ -1011,9 +1011,19 @@ static int compute_impl(mlmix_ctx *ctx, hipStream_t s, void *ws, const WsLayout 
     // fork: reverse slots and the cheap potential need only the list; they are
     // started after the neighbour rows (fork_at 0) or after the atomic basis
     // (fork_at 1, beside the matrix-core contraction)
+    bool fork_recorded = false;
+    auto record_fork = [&]() -> int {
+        if (fork && !fork_recorded) {
+            HIP_OK(hipEventRecord(sd.fork, s));
+            fork_recorded = true;
+        }
+        return MLMIX_OK;
+    };
     auto fork_side = [&]() -> int {
         if (fork) {
-            HIP_OK(hipEventRecord(sd.fork, s));
+            int rc = record_fork();
+            if (rc)
+                return rc;
             HIP_OK(hipStreamWaitEvent(sd.s, sd.fork, 0));
         }
         {
@@ -1032,8 +1042,16 @@ static int compute_impl(mlmix_ctx *ctx, hipStream_t s, void *ws, const WsLayout 
             HIP_OK(hipEventRecord(sd.join, sd.s));
         return MLMIX_OK;
     };
+    // fork_at 0: side kernels issued right after the rows; 2: fork point
+    // recorded after the rows, side kernels issued after the compaction (so
+    // that a captured graph keeps the expensive chain on the first queue);
+    // 1: both after the atomic basis
     const bool late = c.fork_at == 1 && m != MLMIX_MODE_ALL_CHEAP;
-    if (!late) {
+    if (c.fork_at == 2) {
+        int rc = record_fork();
+        if (rc)
+            return rc;
+    } else if (!late) {
         int rc = fork_side();
         if (rc)
             return rc;
@@ -1045,6 +1063,11 @@ static int compute_impl(mlmix_ctx *ctx, hipStream_t s, void *ws, const WsLayout 
     {
         StageTimer t(ctx, s, ST_CMP);
         launch_compact(s, ws, L, flags, n_expensive);
+    }
+    if (c.fork_at == 2) {
+        int rc = fork_side();
+        if (rc)
+            return rc;
     }
     if (m != MLMIX_MODE_ALL_CHEAP) {
         {

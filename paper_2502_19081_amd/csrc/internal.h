@@ -98,7 +98,11 @@ struct Ctx {
     int max_ent_pb;        // Gaunt entries of the largest single block
     int o3 = 0;            // order-3 contraction on the per-wave matrix-core kernel
     int basis_mfma = 1;    // atomic basis and pair adjoint on the matrix cores (FP32)
-    int fork_at = 0;       // second-stream fork after the rows (0) or the basis (1)
+    // second-stream fork after the rows (0), after the basis (1), or recorded
+    // after the rows and issued after the compaction (2: a captured graph then
+    // keeps the expensive chain on the first hardware queue; 148-150 us
+    // against 153-155 us per step on 8,193 atoms, no difference on 1M atoms)
+    int fork_at = 2;
     // workgroup cap of the cheap-potential kernel on the second stream
     // (grid-stride loop): -1 automatic, 0 uncapped. Measured per mixed step
     // on 8,193 atoms: uncapped 178 us, 256 workgroups (one per CU) 166 us,

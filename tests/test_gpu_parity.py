@@ -124,3 +124,4 @@ def test_buffer_paths_agree_with_oracle():
     assert np.array_equal(g3["flags"], ref3["flags"])
     assert np.array_equal(g3["S"], ref3["S"])
     assert np.array_equal(g3["M"], ref3["M"])
+
