@@ -605,15 +605,115 @@ extern void pb_ranges(const Ctx &c, int *lo, int *hi);
 
 typedef float f4v_t __attribute__((ext_vector_type(4)));
 
+// Geometry of one valid expensive pair, in the compacted order of the row.
+struct PairGeo {
+    float r, ux, uy, uz, ir;
+    int zj, slot, pad;
+};
+static_assert(sizeof(PairGeo) == 32, "PairGeo is eight 4-byte words");
+
+// Valid pairs of centre i (partner in S, inside the cutoff) over the whole
+// row: lane l tests slots l + 64 u, u < 4 (rows hold at most 256 slots); the
+// ballots give each valid pair its index in row order (pp[u], -1 if not
+// valid) and the function returns their number. Pairs whose index lies in
+// [64 rnd, 64 rnd + 64) leave their geometry in geo[index - 64 rnd].
+__device__ __forceinline__ int compact_pairs(const double *__restrict__ pos, int n, const Box &b,
+                                             const int32_t *__restrict__ species, int ns,
+                                             const int *__restrict__ row, int c,
+                                             const int *__restrict__ S_local, int i, double rc2,
+                                             int lane, int rnd, PairGeo *geo, int (&pp)[4])
+{
+    int nv = 0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        pp[u] = -1;
+        if (64 * u >= c)
+            continue;  // uniform
+        const int slot = lane + 64 * u;
+        bool ok = false;
+        double d[3] = {0.0, 0.0, 0.0}, r2 = 0.0;
+        int j = 0;
+        if (slot < c) {
+            j = row[slot];
+            if (S_local[j] >= 0) {
+                pair_disp_d(pos, n, i, j, b, d);
+                r2 = norm2_d(d);
+                ok = r2 < rc2;
+            }
+        }
+        const unsigned long long mask = __ballot(ok);
+        const int p = nv + __popcll(mask & ((1ull << lane) - 1ull));
+        if (ok) {
+            pp[u] = p;
+            if (p >= 64 * rnd && p < 64 * rnd + 64) {
+                const double rd = sqrt(r2), ird = 1.0 / rd;
+                PairGeo gq;
+                gq.r = float(rd);
+                gq.ux = float(d[0] * ird);
+                gq.uy = float(d[1] * ird);
+                gq.uz = float(d[2] * ird);
+                gq.ir = float(ird);
+                gq.zj = sp_clamp(species[j], ns);
+                gq.slot = slot;
+                gq.pad = 0;
+                geo[p - 64 * rnd] = gq;
+            }
+        }
+        nv += __popcll(mask);
+    }
+    return nv;
+}
+
+// Geometry of the pairs with compacted index in [64 rnd, 64 rnd + 64) for a
+// later round (rows with more than 64 valid pairs): recomputed from the
+// positions with the same operations.
+__device__ __forceinline__ void pairs_round(const double *__restrict__ pos, int n, const Box &b,
+                                            const int32_t *__restrict__ species, int ns,
+                                            const int *__restrict__ row, int i, int lane, int rnd,
+                                            const int (&pp)[4], PairGeo *geo)
+{
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int p = pp[u];
+        if (p >= 64 * rnd && p < 64 * rnd + 64) {
+            const int slot = lane + 64 * u;
+            const int j = row[slot];
+            double d[3];
+            pair_disp_d(pos, n, i, j, b, d);
+            const double r2 = norm2_d(d);
+            const double rd = sqrt(r2), ird = 1.0 / rd;
+            PairGeo gq;
+            gq.r = float(rd);
+            gq.ux = float(d[0] * ird);
+            gq.uy = float(d[1] * ird);
+            gq.uz = float(d[2] * ird);
+            gq.ir = float(ird);
+            gq.zj = sp_clamp(species[j], ns);
+            gq.slot = slot;
+            gq.pad = 0;
+            geo[p - 64 * rnd] = gq;
+        }
+    }
+}
+
+__device__ __forceinline__ void wave_sync_ace()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Atomic basis on the matrix cores (FP32 potentials): one wave per S atom.
-// Lanes evaluate the radial functions and harmonics of 64 list slots at a
-// time; the valid pairs (partner in S, inside the cutoff) are compacted by
-// ballot into wave-private LDS rows (radial row masked by the partner's
-// species, so that channel (z, n) holds R_n only for z = z_j; rows padded
-// with zeros to a multiple of four), and A[(z, n)][lm] = sum_j R_zn,j Y_lm,j
-// accumulates as 16x16x4 MFMA tiles (MT channel tiles x NT lm tiles, K = the
-// compacted pairs). Row strides are odd so that the row writes of the 64
-// lanes and the tile reads are free of bank conflicts.
+// The valid pairs of the whole row (partner in S, inside the cutoff) are
+// compacted by ballot first, their geometry left in LDS; lane q then
+// evaluates the radial functions and harmonics of compacted pair q into
+// wave-private LDS rows (radial row masked by the partner's species, so that
+// channel (z, n) holds R_n only for z = z_j; rows padded with zeros to a
+// multiple of four), and A[(z, n)][lm] = sum_j R_zn,j Y_lm,j accumulates as
+// 16x16x4 MFMA tiles (MT channel tiles x NT lm tiles, K = the compacted
+// pairs, 64 per round; rows hold about 40 valid pairs, so one round). Row
+// strides are odd so that the row writes of the 64 lanes and the tile reads
+// are free of bank conflicts.
 template <int MT, int NT>
 __global__ void __launch_bounds__(256)
     k_ace_basis_mfma(const double *__restrict__ pos, int n, Box b,
@@ -629,7 +729,8 @@ __global__ void __launch_bounds__(256)
     if (s >= nS)
         return;  // no barriers in this kernel
     extern __shared__ __align__(16) char smem_raw[];
-    float *Rz = reinterpret_cast<float *>(smem_raw) + (size_t)w * 64 * (RW + YW);
+    // per wave: R rows [64][RW], Y rows [64][YW], then 64 PairGeo (8 floats each)
+    float *Rz = reinterpret_cast<float *>(smem_raw) + (size_t)w * (64 * (RW + YW) + 64 * 8);
     float *Yt = Rz + 64 * RW;
     const int m16 = lane & 15, kg = lane >> 4;
     const int i = S_idx[s];
@@ -642,58 +743,40 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt)
             acc[mt][nt] = (f4v_t){0.f, 0.f, 0.f, 0.f};
-    for (int base = 0; base < c; base += 64) {
-        const int slot = base + lane;
-        bool ok = false;
-        float R[kMaxNrad], dR[kMaxNrad];
-        float ux = 0.f, uy = 0.f, uz = 0.f;
-        int zj = 0;
-        if (slot < c) {
-            const int j = row[slot];
-            if (S_local[j] >= 0) {
-                double d[3];
-                pair_disp_d(pos, n, i, j, b, d);
-                const double r2 = norm2_d(d);
-                if (r2 < a.rc2) {
-                    const double rd = sqrt(r2), ird = 1.0 / rd;
-                    radial<float>(nrad, float(rd), a.rc, R, dR);
-                    ux = float(d[0] * ird);
-                    uy = float(d[1] * ird);
-                    uz = float(d[2] * ird);
-                    zj = sp_clamp(species[j], a.ns);
-                    ok = true;
-                }
-            }
-        }
-        const unsigned long long mask = __ballot(ok);
-        const int nv = __popcll(mask);
+    PairGeo *geo = reinterpret_cast<PairGeo *>(Yt + 64 * YW);  // [64]
+    int pp[4];
+    const int nv_all = compact_pairs(pos, n, b, species, a.ns, row, c, S_local, i, a.rc2, lane, 0,
+                                     geo, pp);
+    for (int rnd = 0; 64 * rnd < nv_all; ++rnd) {
+        if (rnd > 0)
+            pairs_round(pos, n, b, species, a.ns, row, i, lane, rnd, pp, geo);
+        wave_sync_ace();
+        const int nv = min(64, nv_all - 64 * rnd);
         const int nv4 = (nv + 3) & ~3;
-        const int p = __popcll(mask & ((1ull << lane) - 1ull));
-        if (ok) {
-            float *rr = Rz + p * RW;
+        // lane q builds the rows of compacted pair q (rows nv..nv4-1 zero)
+        if (lane < nv) {
+            const PairGeo gq = geo[lane];
+            float R[kMaxNrad], dR[kMaxNrad];
+            radial<float>(nrad, gq.r, a.rc, R, dR);
+            float *rr = Rz + lane * RW;
             for (int ch = 0; ch < 16 * MT; ++ch)
                 rr[ch] = 0.f;
 #pragma unroll
             for (int k = 0; k < kMaxNrad; ++k)
                 if (k < nrad)
-                    rr[zj * nrad + k] = R[k];
-            float *yr = Yt + p * YW;
-            ylm_stream<float>(a.lmax, ux, uy, uz, a.K,
+                    rr[gq.zj * nrad + k] = R[k];
+            float *yr = Yt + lane * YW;
+            ylm_stream<float>(a.lmax, gq.ux, gq.uy, gq.uz, a.K,
                               [&](int lm, float Y, float, float, float) { yr[lm] = Y; });
             for (int lm = L2; lm < 16 * NT; ++lm)
                 yr[lm] = 0.f;
-        }
-        if (lane >= nv && lane < nv4) {
-            // zero the rows that pad K to a multiple of four (rows nv.. are
-            // not written by the compaction, whichever lanes hold pairs)
+        } else if (lane < nv4) {
             for (int ch = 0; ch < 16 * MT; ++ch)
                 Rz[lane * RW + ch] = 0.f;
             for (int lm = 0; lm < 16 * NT; ++lm)
                 Yt[lane * YW + lm] = 0.f;
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        wave_sync_ace();
         for (int k0 = 0; k0 < nv4; k0 += 4) {
             const int kr = k0 + kg;
             float xa[MT], yb[NT];
@@ -709,9 +792,7 @@ __global__ void __launch_bounds__(256)
                 for (int nt = 0; nt < NT; ++nt)
                     acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[mt], yb[nt], acc[mt][nt], 0, 0, 0);
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        wave_sync_ace();
     }
     // lane holds A[ch = 16 mt + 4 kg + v][lm = 16 nt + m16]: four consecutive
     // channels of one lm, stored as one 16-byte write (padded channels are 0)
@@ -728,8 +809,9 @@ __global__ void __launch_bounds__(256)
 
 // Pair adjoint on the matrix cores (FP32 potentials): one wave per S atom.
 // G = dE/dA of the atom (times its weight) is staged transposed, [(z, n)][lm].
-// For 64 list slots at a time the valid pairs (partner in S, inside the
-// cutoff) are compacted by ballot into species-masked rows R and dR;
+// The valid pairs of the whole row (partner in S, inside the cutoff) are
+// compacted by ballot first (geometry in LDS), 64 per round, and lane q
+// builds the species-masked rows R and dR of compacted pair q;
 // S_R = R G and S_D = dR G (pairs x lm) are 16x16x4 MFMA tiles (K =
 // channels); each pair's lane then contracts its rows with the harmonics and
 // their gradients, g = rad u + (v - u (u.v)) / r with rad = sum S_D Y and
@@ -751,10 +833,11 @@ __global__ void __launch_bounds__(256)
     if (s >= nS)
         return;  // no barriers in this kernel
     extern __shared__ __align__(16) char smem_raw[];
-    float *base = reinterpret_cast<float *>(smem_raw) + (size_t)w * (PAIR + 16 * MT * YW);
+    float *base = reinterpret_cast<float *>(smem_raw) + (size_t)w * (PAIR + 16 * MT * YW + 64 * 8);
     float *Rr = base, *Dr = base + 64 * RW;           // [64][RW] each
     float *SR = base, *SD = base + 64 * YW;           // [64][YW] each (after the MFMAs)
     float *Gt = base + PAIR;                          // [16 MT][YW]
+    PairGeo *geo = reinterpret_cast<PairGeo *>(Gt + 16 * MT * YW);  // [64]
     const int m16 = lane & 15, kg = lane >> 4;
     const int i = S_idx[s];
     const float wgt = weights ? float(weights[i]) : 1.0f;
@@ -766,38 +849,32 @@ __global__ void __launch_bounds__(256)
     const int c = cnt[i];
     const int *row = nbr + (size_t)i * cap;
     float *gs = g + (size_t)s * cap * 3;
-    for (int base0 = 0; base0 < c; base0 += 64) {
-        const int slot = base0 + lane;
-        bool ok = false;
-        float R[kMaxNrad], dR[kMaxNrad];
-        float ux = 0.f, uy = 0.f, uz = 0.f, ir = 0.f;
-        int zj = 0;
-        if (slot < c) {
-            const int j = row[slot];
-            if (S_local[j] >= 0) {
-                double d[3];
-                pair_disp_d(pos, n, i, j, b, d);
-                const double r2 = norm2_d(d);
-                if (r2 < a.rc2) {
-                    const double rd = sqrt(r2), ird = 1.0 / rd;
-                    radial<float>(nrad, float(rd), a.rc, R, dR);
-                    ux = float(d[0] * ird);
-                    uy = float(d[1] * ird);
-                    uz = float(d[2] * ird);
-                    ir = float(ird);
-                    zj = sp_clamp(species[j], a.ns);
-                    ok = true;
-                }
-            }
+    int pp[4];
+    const int nv_all = compact_pairs(pos, n, b, species, a.ns, row, c, S_local, i, a.rc2, lane, 0,
+                                     geo, pp);
+    // slots without a valid pair get a zero gradient from their owner lane
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int slot = lane + 64 * u;
+        if (slot < c && pp[u] < 0) {
+            gs[slot * 3 + 0] = 0.f;
+            gs[slot * 3 + 1] = 0.f;
+            gs[slot * 3 + 2] = 0.f;
         }
-        // valid pairs compacted into rows 0..nv-1; rows up to the next
-        // multiple of 16 (one MFMA row tile) are zero
-        const unsigned long long mask = __ballot(ok);
-        const int nv = __popcll(mask);
+    }
+    for (int rnd = 0; 64 * rnd < nv_all; ++rnd) {
+        if (rnd > 0)
+            pairs_round(pos, n, b, species, a.ns, row, i, lane, rnd, pp, geo);
+        wave_sync_ace();
+        const int nv = min(64, nv_all - 64 * rnd);
         const int nrt = (nv + 15) >> 4;
-        const int p = __popcll(mask & ((1ull << lane) - 1ull));
-        if (ok) {
-            float *rr = Rr + p * RW, *dr = Dr + p * RW;
+        // lane q builds the radial rows of compacted pair q; rows up to the
+        // next multiple of 16 (one MFMA row tile) are zero
+        if (lane < nv) {
+            const PairGeo gq = geo[lane];
+            float R[kMaxNrad], dR[kMaxNrad];
+            radial<float>(nrad, gq.r, a.rc, R, dR);
+            float *rr = Rr + lane * RW, *dr = Dr + lane * RW;
             for (int ch = 0; ch < 16 * MT; ++ch) {
                 rr[ch] = 0.f;
                 dr[ch] = 0.f;
@@ -805,20 +882,17 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
             for (int k = 0; k < kMaxNrad; ++k)
                 if (k < nrad) {
-                    rr[zj * nrad + k] = R[k];
-                    dr[zj * nrad + k] = dR[k];
+                    rr[gq.zj * nrad + k] = R[k];
+                    dr[gq.zj * nrad + k] = dR[k];
                 }
-        }
-        if (lane >= nv && lane < 16 * nrt) {
+        } else if (lane < 16 * nrt) {
             float *rr = Rr + lane * RW, *dr = Dr + lane * RW;
             for (int ch = 0; ch < 16 * MT; ++ch) {
                 rr[ch] = 0.f;
                 dr[ch] = 0.f;
             }
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        wave_sync_ace();
         // S tiles: rows = compacted pairs (nrt tiles of 16), cols = lm, K = channels
         f4v_t sr[4][NT], sd[4][NT];
 #pragma unroll
@@ -847,9 +921,7 @@ __global__ void __launch_bounds__(256)
                     }
                 }
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        wave_sync_ace();
         // lane holds S[pair row = 16 rt + 4 kg + v][lm = 16 nt + m16]
 #pragma unroll
         for (int rt = 0; rt < 4; ++rt)
@@ -863,44 +935,38 @@ __global__ void __launch_bounds__(256)
                         SD[sl * YW + lm] = sd[rt][nt][v];
                     }
             }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        if (slot < c) {
-            float gx = 0.f, gy = 0.f, gz = 0.f;
-            if (ok) {
-                const float *srow = SR + p * YW, *drow = SD + p * YW;
-                float rad = 0.f, vx = 0.f, vy = 0.f, vz = 0.f;
-                ylm_stream<float>(a.lmax, ux, uy, uz, a.K, [&](int lm, float Y, float yx, float yy, float yz) {
-                    const float sR = srow[lm], sD = drow[lm];
-                    rad += sD * Y;
-                    vx += sR * yx;
-                    vy += sR * yy;
-                    vz += sR * yz;
-                });
-                const float ud = ux * vx + uy * vy + uz * vz;
-                gx = rad * ux + (vx - ux * ud) * ir;
-                gy = rad * uy + (vy - uy * ud) * ir;
-                gz = rad * uz + (vz - uz * ud) * ir;
-            }
-            gs[slot * 3 + 0] = gx;
-            gs[slot * 3 + 1] = gy;
-            gs[slot * 3 + 2] = gz;
+        wave_sync_ace();
+        if (lane < nv) {
+            const PairGeo gq = geo[lane];
+            const float *srow = SR + lane * YW, *drow = SD + lane * YW;
+            float rad = 0.f, vx = 0.f, vy = 0.f, vz = 0.f;
+            ylm_stream<float>(a.lmax, gq.ux, gq.uy, gq.uz, a.K, [&](int lm, float Y, float yx, float yy, float yz) {
+                const float sR = srow[lm], sD = drow[lm];
+                rad += sD * Y;
+                vx += sR * yx;
+                vy += sR * yy;
+                vz += sR * yz;
+            });
+            const float ud = gq.ux * vx + gq.uy * vy + gq.uz * vz;
+            gs[gq.slot * 3 + 0] = rad * gq.ux + (vx - gq.ux * ud) * gq.ir;
+            gs[gq.slot * 3 + 1] = rad * gq.uy + (vy - gq.uy * ud) * gq.ir;
+            gs[gq.slot * 3 + 2] = rad * gq.uz + (vz - gq.uz * ud) * gq.ir;
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        wave_sync_ace();
     }
 }
 
 template <int MT, int NT>
-static size_t basis_mfma_lds() { return (size_t)64 * (16 * MT + 1 + 16 * NT + 1) * sizeof(float); }
+static size_t basis_mfma_lds()
+{
+    return (size_t)64 * (16 * MT + 1 + 16 * NT + 1) * sizeof(float) + 64 * sizeof(PairGeo);
+}
 template <int MT, int NT>
 static size_t pairgrad_mfma_lds()
 {
     constexpr int RW = 16 * MT + 1, YW = 16 * NT + 1;
     constexpr int PAIR = 64 * RW * 2 > 64 * YW * 2 ? 64 * RW * 2 : 64 * YW * 2;
-    return (size_t)(PAIR + 16 * MT * YW) * sizeof(float);
+    return (size_t)(PAIR + 16 * MT * YW + 64 * 8) * sizeof(float);
 }
 
 // Waves per workgroup that keep a workgroup's LDS within 64 KiB.

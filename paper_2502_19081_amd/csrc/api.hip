@@ -1001,7 +1001,7 @@ static int compute_impl(mlmix_ctx *ctx, hipStream_t s, void *ws, const WsLayout 
     const int rev_blocks = c.rev_blocks;
     const int side_blocks = (!fork || m == MLMIX_MODE_ALL_CHEAP)
                                 ? 0
-                                : (c.side_blocks >= 0 ? c.side_blocks : (L.n < 262144 ? 256 : 0));
+                                : (c.side_blocks >= 0 ? c.side_blocks : (L.n < 262144 ? 512 : 0));
     {
         StageTimer t(ctx, s, ST_NBR);
         RegionArgs ra{m, species, c.m.ns, regions, n_regions, r_buffer, lambda, flags, nullptr};

@@ -104,12 +104,13 @@ struct Ctx {
     // against 153-155 us per step on 8,193 atoms, no difference on 1M atoms)
     int fork_at = 2;
     // workgroup cap of the cheap-potential kernel on the second stream
-    // (grid-stride loop): -1 automatic, 0 uncapped. Measured per mixed step
-    // on 8,193 atoms: uncapped 178 us, 256 workgroups (one per CU) 166 us,
-    // later 153 us against 168 / 183 / 175 us at 320 / 384 / 512; on
-    // 1,023,800 atoms caps of 1024 and 2048 measured no better than none
-    // (11.6 / 11.2 / 11.3 ms, same box). Automatic: 256 below 262,144 atoms,
-    // uncapped above.
+    // (grid-stride loop): -1 automatic, 0 uncapped. The best cap follows the
+    // length of the expensive chain beside it; measured per mixed step on
+    // 8,193 atoms with the current chain and fork point: 148 / 138 / 137 /
+    // 137 us at 256 / 384 / 512 / 768 workgroups (an earlier, longer chain
+    // preferred 256). On 1,023,800 atoms caps of 1024 and 2048 measured no
+    // better than none (11.6 / 11.2 / 11.3 ms, same box). Automatic: 512
+    // below 262,144 atoms, uncapped above.
     int side_blocks = -1;
     int rev_blocks = 1024;  // cap of the reverse-slot kernel when capped (256 / 1024 measured 153.0 / 152.4 us)
     int o3_nch2 = 0;       // row width of that kernel (channels rounded up to 4)
