@@ -394,7 +394,8 @@ __global__ void __launch_bounds__(256)
     }
 }
 
-// One wavefront per S atom, lanes over the atomic-basis entries (lm, c):
+// One 256-thread workgroup per S atom, threads over the atomic-basis entries
+// (lm, c; at most three per thread for lmax 5 and 16 channels):
 // D3 = sum over the l-blocks' partial D (fixed order), D2 from the order-2
 // coefficients, dE/dA = c1 + 2 D2 + 3 D3 and E = c0 + sum A (c1 + D2 + D3).
 // The atom's A row, the block offsets, the per-l block ranges and (when
@@ -409,17 +410,18 @@ __global__ void __launch_bounds__(256)
                    const T *__restrict__ Dpart, T *__restrict__ dEdA, double *__restrict__ e_exp)
 {
     const int nS = hdr[H_NS];
-    if ((int)blockIdx.x * 4 >= nS)
+    const int s = blockIdx.x;  // one S atom per 256-thread block
+    if (s >= nS)
         return;  // uniform across the block
     const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
-    const int s = blockIdx.x * 4 + wv;
     const int nch = a.nchan, nchp = a.nchp, L1 = a.L1, KAt = a.KAt;
     extern __shared__ __align__(16) char smem_raw[];
-    T *As = reinterpret_cast<T *>(smem_raw) + (size_t)wv * KAt;            // [4][KAt]
-    T *Ct = reinterpret_cast<T *>(smem_raw) + (size_t)4 * KAt;             // [ns][L1][b][c]
+    T *As = reinterpret_cast<T *>(smem_raw);                               // [KAt]
+    T *Ct = As + KAt;                                                      // [ns][L1][b][c]
     const size_t nC = stage_c2 ? (size_t)a.ns * L1 * nch * nch : 0;
     int *dpo = reinterpret_cast<int *>(Ct + nC);                           // [n_pb]
     int *plo = dpo + n_pb, *phi = plo + L1;                                // [L1] each
+    __shared__ double esum[4];
     if (a.order >= 2)
         for (int e = tid; e < (int)nC; e += 256) {
             const int c = e % nch, r = e / nch;
@@ -432,18 +434,15 @@ __global__ void __launch_bounds__(256)
         plo[tid] = a.pb_lo[tid];
         phi[tid] = a.pb_hi[tid];
     }
-    if (s < nS)
-        for (int e = lane; e < KAt; e += 64)
-            As[e] = A[(size_t)s * KAt + e];
+    for (int e = tid; e < KAt; e += 256)
+        As[e] = A[(size_t)s * KAt + e];
     __syncthreads();
-    if (s >= nS)
-        return;
     const int i = S_idx[s];
     const int z = sp_clamp(species[i], a.ns);
     const T *Ds = Dpart + (size_t)s * dp_stride;
     const T *Cz = stage_c2 ? Ct + (size_t)z * L1 * nch * nch : nullptr;
     double es = 0.0;
-    for (int e = lane; e < KAt; e += 64) {
+    for (int e = tid; e < KAt; e += 256) {
         const int lm = e / nchp, c = e - lm * nchp;
         if (c >= nch) {
             dEdA[(size_t)s * KAt + e] = T(0);
@@ -490,7 +489,10 @@ __global__ void __launch_bounds__(256)
     for (int d = 32; d > 0; d >>= 1)
         es += __shfl_xor(es, d);
     if (lane == 0)
-        e_exp[i] = (double)a.c0[z] + es;
+        esum[wv] = es;
+    __syncthreads();
+    if (tid == 0)
+        e_exp[i] = (double)a.c0[z] + ((esum[0] + esum[1]) + (esum[2] + esum[3]));
 }
 
 template <typename T>
@@ -1106,13 +1108,13 @@ static void finalize_t(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L,
     const int *dp_off = reinterpret_cast<const int *>(static_cast<char *>(c.m.base) + c.m.dpoff);
     T *Dpart = at<T>(ws, L.dpart);
     const size_t nC = (size_t)c.m.ns * (c.m.lmax + 1) * c.m.nchan * c.m.nchan;
-    size_t sm = (size_t)4 * c.m.KAt * sizeof(T) + (c.m.n_pb + 2 * (c.m.lmax + 1)) * sizeof(int) + 16;
+    size_t sm = (size_t)c.m.KAt * sizeof(T) + (c.m.n_pb + 2 * (c.m.lmax + 1)) * sizeof(int) + 16;
     int stage_c2 = 0;
     if (sm + nC * sizeof(T) <= 48 * 1024) {
         stage_c2 = 1;
         sm += nC * sizeof(T);
     }
-    k_ace_finalize<T><<<(L.n + 3) / 4, 256, sm, s>>>(species, at<int>(ws, L.S_idx),
+    k_ace_finalize<T><<<L.n, 256, sm, s>>>(species, at<int>(ws, L.S_idx),
                                                      at<int>(ws, L.hdr), a, dp_off, c.m.n_pb, stage_c2,
                                                      c.m.dp_stride, at<T>(ws, L.A), Dpart,
                                                      at<T>(ws, L.dEdA), e_exp);
