@@ -394,30 +394,33 @@ __global__ void __launch_bounds__(256)
     }
 }
 
-// One 256-thread workgroup per S atom, threads over the atomic-basis entries
-// (lm, c; at most three per thread for lmax 5 and 16 channels):
+// APB S atoms per 256-thread workgroup (1: threads over the atomic-basis
+// entries, for small S where latency rules; 4: a wave per atom, lanes over
+// the entries, for large S where the staged tables are shared by four atoms):
 // D3 = sum over the l-blocks' partial D (fixed order), D2 from the order-2
 // coefficients, dE/dA = c1 + 2 D2 + 3 D3 and E = c0 + sum A (c1 + D2 + D3).
 // The atom's A row, the block offsets, the per-l block ranges and (when
 // they fit, stage_c2) the order-2 coefficients transposed to [z][l][b][c]
 // are staged in LDS, so that a lane's loads are independent LDS reads plus
 // coalesced reads of the partial D.
-template <typename T>
+template <typename T, int APB>
 __global__ void __launch_bounds__(256)
     k_ace_finalize(const int32_t *__restrict__ species, const int *__restrict__ S_idx,
                    const int *__restrict__ hdr, AceArgs<T> a, const int *__restrict__ dp_off,
                    int n_pb, int stage_c2, int dp_stride, const T *__restrict__ A,
                    const T *__restrict__ Dpart, T *__restrict__ dEdA, double *__restrict__ e_exp)
 {
+    constexpr int TPA = 256 / APB;  // threads per atom
     const int nS = hdr[H_NS];
-    const int s = blockIdx.x;  // one S atom per 256-thread block
-    if (s >= nS)
+    if ((int)blockIdx.x * APB >= nS)
         return;  // uniform across the block
     const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+    const int sub = tid / TPA, st = tid - sub * TPA;  // atom of the block, thread within it
+    const int s = blockIdx.x * APB + sub;
     const int nch = a.nchan, nchp = a.nchp, L1 = a.L1, KAt = a.KAt;
     extern __shared__ __align__(16) char smem_raw[];
-    T *As = reinterpret_cast<T *>(smem_raw);                               // [KAt]
-    T *Ct = As + KAt;                                                      // [ns][L1][b][c]
+    T *As = reinterpret_cast<T *>(smem_raw) + (size_t)sub * KAt;           // [APB][KAt]
+    T *Ct = reinterpret_cast<T *>(smem_raw) + (size_t)APB * KAt;           // [ns][L1][b][c]
     const size_t nC = stage_c2 ? (size_t)a.ns * L1 * nch * nch : 0;
     int *dpo = reinterpret_cast<int *>(Ct + nC);                           // [n_pb]
     int *plo = dpo + n_pb, *phi = plo + L1;                                // [L1] each
@@ -434,15 +437,18 @@ __global__ void __launch_bounds__(256)
         plo[tid] = a.pb_lo[tid];
         phi[tid] = a.pb_hi[tid];
     }
-    for (int e = tid; e < KAt; e += 256)
-        As[e] = A[(size_t)s * KAt + e];
+    if (s < nS)
+        for (int e = st; e < KAt; e += TPA)
+            As[e] = A[(size_t)s * KAt + e];
     __syncthreads();
+    if (s >= nS)
+        return;  // after the only block barrier (APB = 4; APB = 1 returned above)
     const int i = S_idx[s];
     const int z = sp_clamp(species[i], a.ns);
     const T *Ds = Dpart + (size_t)s * dp_stride;
     const T *Cz = stage_c2 ? Ct + (size_t)z * L1 * nch * nch : nullptr;
     double es = 0.0;
-    for (int e = tid; e < KAt; e += 256) {
+    for (int e = st; e < KAt; e += TPA) {
         const int lm = e / nchp, c = e - lm * nchp;
         if (c >= nch) {
             dEdA[(size_t)s * KAt + e] = T(0);
@@ -488,11 +494,16 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
     for (int d = 32; d > 0; d >>= 1)
         es += __shfl_xor(es, d);
-    if (lane == 0)
-        esum[wv] = es;
-    __syncthreads();
-    if (tid == 0)
-        e_exp[i] = (double)a.c0[z] + ((esum[0] + esum[1]) + (esum[2] + esum[3]));
+    if constexpr (APB == 4) {
+        if (lane == 0)
+            e_exp[i] = (double)a.c0[z] + es;
+    } else {
+        if (lane == 0)
+            esum[wv] = es;
+        __syncthreads();
+        if (tid == 0)
+            e_exp[i] = (double)a.c0[z] + ((esum[0] + esum[1]) + (esum[2] + esum[3]));
+    }
 }
 
 template <typename T>
@@ -703,6 +714,123 @@ __device__ __forceinline__ void wave_sync_ace()
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The same atomic basis in passes over 64 list slots (each lane evaluates
+// its own slot's pair; valid pairs compacted per pass): measured faster on
+// large systems (1M atoms, lmax 5: 10.58 against 10.82 ms per step), where
+// the whole-row form below is slower; small systems take the whole-row form
+// (8,193 atoms: 132.7 against 135.4 us per step).
+template <int MT, int NT>
+__global__ void __launch_bounds__(256)
+    k_ace_basis_mfma_chunks(const double *__restrict__ pos, int n, Box b,
+                     const int32_t *__restrict__ species, int cap, const int *__restrict__ nbr,
+                     const int *__restrict__ cnt, const int *__restrict__ S_idx,
+                     const int *__restrict__ S_local, const int *__restrict__ hdr,
+                     AceArgs<float> a, int wpb, float *__restrict__ A)
+{
+    constexpr int RW = 16 * MT + 1, YW = 16 * NT + 1;
+    const int nS = hdr[H_NS];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int s = blockIdx.x * wpb + w;
+    if (s >= nS)
+        return;  // no barriers in this kernel
+    extern __shared__ __align__(16) char smem_raw[];
+    float *Rz = reinterpret_cast<float *>(smem_raw) + (size_t)w * 64 * (RW + YW);
+    float *Yt = Rz + 64 * RW;
+    const int m16 = lane & 15, kg = lane >> 4;
+    const int i = S_idx[s];
+    const int c = cnt[i];
+    const int *row = nbr + (size_t)i * cap;
+    const int nrad = a.nrad, nch = a.nchan, L2 = a.L2;
+    f4v_t acc[MT][NT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+            acc[mt][nt] = (f4v_t){0.f, 0.f, 0.f, 0.f};
+    for (int base = 0; base < c; base += 64) {
+        const int slot = base + lane;
+        bool ok = false;
+        float R[kMaxNrad], dR[kMaxNrad];
+        float ux = 0.f, uy = 0.f, uz = 0.f;
+        int zj = 0;
+        if (slot < c) {
+            const int j = row[slot];
+            if (S_local[j] >= 0) {
+                double d[3];
+                pair_disp_d(pos, n, i, j, b, d);
+                const double r2 = norm2_d(d);
+                if (r2 < a.rc2) {
+                    const double rd = sqrt(r2), ird = 1.0 / rd;
+                    radial<float>(nrad, float(rd), a.rc, R, dR);
+                    ux = float(d[0] * ird);
+                    uy = float(d[1] * ird);
+                    uz = float(d[2] * ird);
+                    zj = sp_clamp(species[j], a.ns);
+                    ok = true;
+                }
+            }
+        }
+        const unsigned long long mask = __ballot(ok);
+        const int nv = __popcll(mask);
+        const int nv4 = (nv + 3) & ~3;
+        const int p = __popcll(mask & ((1ull << lane) - 1ull));
+        if (ok) {
+            float *rr = Rz + p * RW;
+            for (int ch = 0; ch < 16 * MT; ++ch)
+                rr[ch] = 0.f;
+#pragma unroll
+            for (int k = 0; k < kMaxNrad; ++k)
+                if (k < nrad)
+                    rr[zj * nrad + k] = R[k];
+            float *yr = Yt + p * YW;
+            ylm_stream<float>(a.lmax, ux, uy, uz, a.K,
+                              [&](int lm, float Y, float, float, float) { yr[lm] = Y; });
+            for (int lm = L2; lm < 16 * NT; ++lm)
+                yr[lm] = 0.f;
+        }
+        if (lane >= nv && lane < nv4) {
+            // zero the rows that pad K to a multiple of four (rows nv.. are
+            // not written by the compaction, whichever lanes hold pairs)
+            for (int ch = 0; ch < 16 * MT; ++ch)
+                Rz[lane * RW + ch] = 0.f;
+            for (int lm = 0; lm < 16 * NT; ++lm)
+                Yt[lane * YW + lm] = 0.f;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (int k0 = 0; k0 < nv4; k0 += 4) {
+            const int kr = k0 + kg;
+            float xa[MT], yb[NT];
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+                xa[mt] = Rz[kr * RW + mt * 16 + m16];
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt)
+                yb[nt] = Yt[kr * YW + nt * 16 + m16];
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt)
+                    acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[mt], yb[nt], acc[mt][nt], 0, 0, 0);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    // lane holds A[ch = 16 mt + 4 kg + v][lm = 16 nt + m16]: four consecutive
+    // channels of one lm, stored as one 16-byte write (padded channels are 0)
+    float *As = A + (size_t)s * a.KAt;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            const int lm = nt * 16 + m16, ch0 = mt * 16 + 4 * kg;
+            if (lm < L2 && ch0 < a.nchp)
+                *reinterpret_cast<f4v_t *>(As + lm * a.nchp + ch0) = acc[mt][nt];
+        }
 }
 
 // Atomic basis on the matrix cores (FP32 potentials): one wave per S atom.
@@ -984,6 +1112,15 @@ template <int MT, int NT>
 static void basis_mfma_launch(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L, const Box &b,
                               const double *pos, const int32_t *species, const AceArgs<float> &a)
 {
+    if (c.basis_chunks > 0 || (c.basis_chunks < 0 && L.n > 65536)) {
+        const size_t per = (size_t)64 * (16 * MT + 1 + 16 * NT + 1) * sizeof(float);
+        const int wpb = mfma_wpb(per);
+        k_ace_basis_mfma_chunks<MT, NT><<<(L.n + wpb - 1) / wpb, 64 * wpb, per * wpb, s>>>(
+            pos, L.n, b, species, L.cap, at<int>(ws, L.nbr), at<int>(ws, L.cnt),
+            at<int>(ws, L.S_idx), at<int>(ws, L.S_local), at<int>(ws, L.hdr), a, wpb,
+            at<float>(ws, L.A));
+        return;
+    }
     const size_t per = basis_mfma_lds<MT, NT>();
     const int wpb = mfma_wpb(per);
     k_ace_basis_mfma<MT, NT><<<(L.n + wpb - 1) / wpb, 64 * wpb, per * wpb, s>>>(
@@ -1108,16 +1245,23 @@ static void finalize_t(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L,
     const int *dp_off = reinterpret_cast<const int *>(static_cast<char *>(c.m.base) + c.m.dpoff);
     T *Dpart = at<T>(ws, L.dpart);
     const size_t nC = (size_t)c.m.ns * (c.m.lmax + 1) * c.m.nchan * c.m.nchan;
-    size_t sm = (size_t)c.m.KAt * sizeof(T) + (c.m.n_pb + 2 * (c.m.lmax + 1)) * sizeof(int) + 16;
+    // small systems: one atom per workgroup (8,193 atoms: 10.5 against 14.5 us);
+    // large: four (1M atoms: 0.55 against 0.99 ms, the staged tables shared)
+    const int apb = L.n <= 65536 ? 1 : 4;
+    size_t sm = (size_t)apb * c.m.KAt * sizeof(T) + (c.m.n_pb + 2 * (c.m.lmax + 1)) * sizeof(int) + 16;
     int stage_c2 = 0;
     if (sm + nC * sizeof(T) <= 48 * 1024) {
         stage_c2 = 1;
         sm += nC * sizeof(T);
     }
-    k_ace_finalize<T><<<L.n, 256, sm, s>>>(species, at<int>(ws, L.S_idx),
-                                                     at<int>(ws, L.hdr), a, dp_off, c.m.n_pb, stage_c2,
-                                                     c.m.dp_stride, at<T>(ws, L.A), Dpart,
-                                                     at<T>(ws, L.dEdA), e_exp);
+    if (apb == 1)
+        k_ace_finalize<T, 1><<<L.n, 256, sm, s>>>(species, at<int>(ws, L.S_idx), at<int>(ws, L.hdr),
+                                                  a, dp_off, c.m.n_pb, stage_c2, c.m.dp_stride,
+                                                  at<T>(ws, L.A), Dpart, at<T>(ws, L.dEdA), e_exp);
+    else
+        k_ace_finalize<T, 4><<<(L.n + 3) / 4, 256, sm, s>>>(
+            species, at<int>(ws, L.S_idx), at<int>(ws, L.hdr), a, dp_off, c.m.n_pb, stage_c2,
+            c.m.dp_stride, at<T>(ws, L.A), Dpart, at<T>(ws, L.dEdA), e_exp);
 }
 
 template <typename T>

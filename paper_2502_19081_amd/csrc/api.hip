@@ -846,6 +846,8 @@ extern "C" int mlmix_create(const mlmix_model_desc *desc, mlmix_ctx **out)
         if (v == 1 || v == 2 || v == 4 || v == 8)
             c.o3_max_split = v;
     }
+    if (const char *e = std::getenv("MLMIX_BASIS_CHUNKS"))
+        c.basis_chunks = std::max(-1, std::min(1, std::atoi(e)));
     if (const char *e = std::getenv("MLMIX_BASIS_MFMA"))
         c.basis_mfma = std::atoi(e) ? 1 : 0;  // VALU kernels (comparisons)
     if (const char *e = std::getenv("MLMIX_ACE_O3"))

@@ -98,6 +98,7 @@ struct Ctx {
     int max_ent_pb;        // Gaunt entries of the largest single block
     int o3 = 0;            // order-3 contraction on the per-wave matrix-core kernel
     int basis_mfma = 1;    // atomic basis and pair adjoint on the matrix cores (FP32)
+    int basis_chunks = -1; // basis in 64-slot passes: -1 above 65,536 atoms, 0 never, 1 always
     // second-stream fork after the rows (0), after the basis (1), or recorded
     // after the rows and issued after the compaction (2: a captured graph then
     // keeps the expensive chain on the first hardware queue; 148-150 us

@@ -125,3 +125,21 @@ def test_buffer_paths_agree_with_oracle():
     assert np.array_equal(g3["S"], ref3["S"])
     assert np.array_equal(g3["M"], ref3["M"])
 
+
+
+def test_basis_forms_agree():
+    # the atomic basis of large systems (64-slot passes) and of small ones
+    # (whole-row compaction) both match the oracle on the same cell
+    import os
+    w = W.c2()
+    ref = O.mixed(w, O.MODE_MIXED)
+    print("case c2 fp32: basis in 64-slot passes vs whole-row compaction", flush=True)
+    os.environ["MLMIX_BASIS_CHUNKS"] = "1"
+    try:
+        g1 = run_gpu(w, 0, precision="fp32")
+    finally:
+        del os.environ["MLMIX_BASIS_CHUNKS"]
+    g2 = run_gpu(w, 0, precision="fp32")
+    for g in (g1, g2):
+        assert np.abs(g["forces"] - ref["forces"]).max() < 1e-4
+        assert np.abs(g["e_exp"] - ref["e_exp"]).max() < 1e-3
