@@ -57,6 +57,9 @@ def parse():
     ap.add_argument("--graph-steps", type=int, default=10,
                     help="consecutive MD steps captured in one HIP graph for the timed "
                          "region (1: one graph per step)")
+    ap.add_argument("--dominant-only", action="store_true",
+                    help="stop after timing the dominant kernel (phases 1-2) and print its "
+                         "average; for a kernel trace of the same launches")
     ap.add_argument("--single-stream", action="store_true",
                     help="keep every stage on the caller's stream (no fork of the cheap potential)")
     ap.add_argument("--probe", choices=["copy"], default=None,
@@ -235,10 +238,16 @@ def main():
     print(f"bench: stage breakdown done, dominant {dominant}", file=sys.stderr, flush=True)
 
     # 2. the dominant kernel's duration: K eager steps with only that stage
-    # bracketed by HIP events on the launch stream
+    # timed by HIP events on its launch stream (for the matrix-core
+    # contraction the kernel's own start/end events)
     el_eager, prof, _, _ = run(B.MODE_MIXED, args.steps, args.warmup, stage_mask=1 << dom_bit)
     dom_ms, dom_cnt = prof[dominant]
     dom_avg_ms = dom_ms / max(dom_cnt, 1)
+    if args.dominant_only:
+        # the launches timed above, alone (for a kernel trace of exactly them)
+        print(json.dumps({"kernel": dominant, "avg_ms": dom_avg_ms, "launches": dom_cnt,
+                          "config": cfg, "precision": prec}), flush=True)
+        return
 
     # 3. timed region: K mixed steps replayed from one captured HIP graph
     el, _, _, _ = run(B.MODE_MIXED, args.steps, args.warmup, graph=True)

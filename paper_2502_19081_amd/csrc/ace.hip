@@ -1290,10 +1290,19 @@ void launch_ace_basis(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L, 
 }
 
 void launch_ace_contract(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L,
-                         const int32_t *species)
+                         const int32_t *species, hipEvent_t ev0, hipEvent_t ev1)
 {
-    if (L.n == 0)
+    if (L.n == 0) {
+        if (ev0) {  // keep the stage's event pair complete
+            (void)hipEventRecord(ev0, s);
+            (void)hipEventRecord(ev1, s);
+        }
         return;
+    }
+    if (c.prec != MLMIX_FP64 && c.o3) {
+        launch_ace_o3(s, c, ws, L, ev0, ev1);
+        return;
+    }
     if (c.prec == MLMIX_FP64)
         contract_t<double>(s, c, ws, L, species);
     else

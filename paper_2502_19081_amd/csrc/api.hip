@@ -62,22 +62,41 @@ static hipEvent_t take_event(mlmix_ctx *ctx)
 }
 
 // Brackets one stage with events when its bit is set in the profile mask.
+// Times a stage with two events on its stream. With kernel_events the stage
+// is one kernel whose launcher passes k0/k1 to hipExtLaunchKernel, so the
+// events carry the kernel's own start and end (no bracket overhead).
 struct StageTimer {
     mlmix_ctx *ctx;
     hipStream_t s;
     int stage;
     hipEvent_t a = nullptr;
-    StageTimer(mlmix_ctx *c, hipStream_t st, int stg) : ctx(c), s(st), stage(stg)
+    hipEvent_t k0 = nullptr, k1 = nullptr;
+    StageTimer(mlmix_ctx *c, hipStream_t st, int stg, bool kernel_events = false)
+        : ctx(c), s(st), stage(stg)
     {
         if (ctx->prof_mask & (1u << stage)) {
-            a = take_event(ctx);
-            if (a)
-                (void)hipEventRecord(a, s);
+            if (kernel_events) {
+                k0 = take_event(ctx);
+                k1 = take_event(ctx);
+                if (!k0 || !k1) {
+                    if (k0)
+                        ctx->pool.push_back(k0);
+                    if (k1)
+                        ctx->pool.push_back(k1);
+                    k0 = k1 = nullptr;
+                }
+            } else {
+                a = take_event(ctx);
+                if (a)
+                    (void)hipEventRecord(a, s);
+            }
         }
     }
     ~StageTimer()
     {
-        if (a) {
+        if (k0) {
+            ctx->pending.push_back({stage, k0, k1});
+        } else if (a) {
             hipEvent_t b = take_event(ctx);
             if (b) {
                 (void)hipEventRecord(b, s);
@@ -1082,8 +1101,9 @@ static int compute_impl(mlmix_ctx *ctx, hipStream_t s, void *ws, const WsLayout 
                 return rc;
         }
         {
-            StageTimer t(ctx, s, ST_CONTRACT);
-            launch_ace_contract(s, c, ws, L, species);
+            // the matrix-core contraction is one kernel: timed by its own events
+            StageTimer t(ctx, s, ST_CONTRACT, c.o3 && c.prec != MLMIX_FP64);
+            launch_ace_contract(s, c, ws, L, species, t.k0, t.k1);
         }
         {
             StageTimer t(ctx, s, ST_FIN);

@@ -158,15 +158,19 @@ void launch_compact(hipStream_t s, void *ws, const WsLayout &L, uint8_t *flags, 
 // ---- ace.hip ----
 void launch_ace_basis(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L, const Box &b,
                       const double *pos, const int32_t *species);
+// ev0/ev1 (may be null): start and end events of the matrix-core contraction
+// kernel (hipExtLaunchKernel), for stage timing
 void launch_ace_contract(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L,
-                         const int32_t *species);
+                         const int32_t *species, hipEvent_t ev0 = nullptr,
+                         hipEvent_t ev1 = nullptr);
 void launch_ace_finalize(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L,
                          const int32_t *species, double *e_exp);
 void launch_ace_pairgrad(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L, const Box &b,
                          const double *pos, const int32_t *species, const double *weights);
 
 // ---- o3.hip ----
-void launch_ace_o3(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L);
+void launch_ace_o3(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L,
+                   hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 size_t o3_lds_bytes(const Ctx &c);
 
 // ---- uf3.hip ----

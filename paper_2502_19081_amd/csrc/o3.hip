@@ -32,6 +32,8 @@
 // per-block partial buffer [atom][block offset + m3 * nch + c]; the
 // finalize kernel adds the blocks of one l3 in a fixed order, so results do
 // not depend on the launch shape.
+#include <hip/hip_ext.h>
+
 #include <type_traits>
 
 #include "internal.h"
@@ -378,7 +380,8 @@ size_t o3_lds_bytes(const Ctx &c)
            (size_t)(4 * kO3Atoms + kO3Atoms * (m.lmax + 1)) * sizeof(float);
 }
 
-void launch_ace_o3(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L)
+void launch_ace_o3(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L, hipEvent_t ev0,
+                   hipEvent_t ev1)
 {
     const DevModel &m = c.m;
     const char *base = static_cast<const char *>(m.base);
@@ -410,7 +413,12 @@ void launch_ace_o3(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L)
     const float *A = at<float>(ws, L.A);
     float *D = at<float>(ws, L.dpart);
     auto go = [&](auto qm, auto nc) {
-        k_ace_o3<decltype(qm)::value, decltype(nc)::value><<<grid, 256, lds, s>>>(hdr, a, A, D);
+        constexpr int QM = decltype(qm)::value, NC = decltype(nc)::value;
+        if (ev0)  // stage timing: events carry the kernel's own start and end
+            hipExtLaunchKernelGGL(k_ace_o3<QM, NC>, dim3(grid), dim3(256), (uint32_t)lds, s, ev0,
+                                  ev1, 0u, hdr, a, A, D);
+        else
+            k_ace_o3<QM, NC><<<grid, 256, lds, s>>>(hdr, a, A, D);
     };
     auto by_width = [&](auto qm) {
         switch (m.nchp) {
