@@ -103,16 +103,24 @@ def uf3_params(rng, n_species, n_knots2, rcut2, n_knots3=0, rcut3=3.5,
                 n_knots3=n_knots3, rcut3=float(rcut3), c3=c3)
 
 
-def sphere(center, r_core, r_blend, follow_atom=-1):
+def sphere(center, r_core, r_blend, follow_atom=-1, blend=0):
     return dict(type=0, axis=2, follow_atom=int(follow_atom),
                 center=np.asarray(center, dtype=np.float64), r_core=float(r_core),
-                r_blend=float(r_blend))
+                r_blend=float(r_blend), blend=int(blend))
 
 
-def cylinder(center, axis, r_core, r_blend):
+def cylinder(center, axis, r_core, r_blend, blend=0):
     return dict(type=1, axis=int(axis), follow_atom=-1,
                 center=np.asarray(center, dtype=np.float64), r_core=float(r_core),
-                r_blend=float(r_blend))
+                r_blend=float(r_blend), blend=int(blend))
+
+
+def seeded(r_core, r_blend, blend=0):
+    """Seeded region (the paper's fix): core = seed atoms and their neighbours
+    within r_core, blend measured to the nearest core atom; the seeds are the
+    workload's boolean array w["seeds"]."""
+    return dict(type=2, axis=2, follow_atom=-1, center=np.zeros(3), r_core=float(r_core),
+                r_blend=float(r_blend), blend=int(blend))
 
 
 def maxwell(rng, species, T):

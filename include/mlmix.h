@@ -81,6 +81,12 @@ extern "C" {
  * with the library's fork nested inside ended in a crash of the runtime's
  * capture end, so this path keeps such captures one level deep. */
 #define MLMIX_SINGLE_STREAM 0x400u
+/* The regions may include seeded regions (MLMIX_REGION_SEEDED); `flags` is
+ * then also an input: seed atoms carry MLMIX_FLAG_SEED, which every
+ * evaluation leaves set. The buffer then comes from its own pass after the
+ * seeded core and blend passes (two more neighbour-row kernels). */
+#define MLMIX_SEEDED 0x800u
+#define MLMIX_FLAG_SEED 0x80u
 
 /* Device status bits reported by mlmix_status(). */
 #define MLMIX_STATUS_NEIGH_OVERFLOW 1
@@ -88,6 +94,7 @@ extern "C" {
 #define MLMIX_STATUS_NONFINITE 4
 #define MLMIX_STATUS_TRIPLET_OVERFLOW 8
 #define MLMIX_STATUS_BAD_SPECIES 16
+#define MLMIX_STATUS_SEEDED_REGIONS 64 /* more than 8 seeded regions */
 #define MLMIX_STATUS_CELL_OVERFLOW 32 /* a cell held more atoms than its bucket
                                          (4 x the mean occupancy + 8) */
 
@@ -136,21 +143,37 @@ typedef struct {
     int32_t pad;
 } mlmix_box;
 
-/* Core region (device array of these, 56 bytes each). type 0: sphere about
- * `center`; type 1: infinite cylinder along coordinate axis `axis` through
- * `center`. follow_atom >= 0 replaces the centre by that atom's current
- * position. lambda = 1 for d < r_core, 1 - (d - r_core)/r_blend for
- * r_core <= d < r_core + r_blend (linear blend of Algorithm 2), else 0;
- * the atom's lambda is the maximum over regions. */
+/* Core region (device array of these, 56 bytes each).
+ * type 0 (MLMIX_REGION_SPHERE): sphere about `center`; type 1
+ * (MLMIX_REGION_CYLINDER): infinite cylinder along coordinate axis `axis`
+ * through `center`. follow_atom >= 0 replaces the centre by that atom's
+ * current position. lambda = 1 for d < r_core, b(t) with
+ * t = (d - r_core)/r_blend for r_core <= d < r_core + r_blend, else 0.
+ * type 2 (MLMIX_REGION_SEEDED, needs MLMIX_SEEDED): the paper's region fix
+ * (Algorithms 1-2) over the neighbour list: seed atoms (flag bit
+ * MLMIX_FLAG_SEED set on input) and their neighbours closer than r_core are
+ * core atoms (lambda 1); a neighbour j of a core atom i at distance
+ * r < r_blend gets lambda_j = max(lambda_j, b(r / r_blend)). center, axis and
+ * follow_atom are ignored; at most 8 seeded regions, all sharing the seeds;
+ * r_core and r_blend should not exceed the list radius.
+ * blend: MLMIX_BLEND_LINEAR b(t) = 1 - t (Algorithm 2) or MLMIX_BLEND_CUBIC
+ * b(t) = 1 - 3t^2 + 2t^3 (zero slope at both ends).
+ * The atom's lambda is the maximum over regions. */
 typedef struct {
     int32_t type;
     int32_t axis;
     int32_t follow_atom;
-    int32_t pad;
+    int32_t blend;
     double center[3];
     double r_core;
     double r_blend;
 } mlmix_region;
+
+#define MLMIX_REGION_SPHERE 0
+#define MLMIX_REGION_CYLINDER 1
+#define MLMIX_REGION_SEEDED 2
+#define MLMIX_BLEND_LINEAR 0
+#define MLMIX_BLEND_CUBIC 1
 
 typedef struct mlmix_ctx mlmix_ctx;
 

@@ -84,23 +84,41 @@ def neighbors(pos, L, periodic, r_list, method=1):
 def _regions_arrays(regions):
     k = len(regions)
     typ = np.array([r["type"] for r in regions], dtype=np.int32).reshape(k)
-    ax = np.array([r["axis"] for r in regions], dtype=np.int32).reshape(k)
-    fol = np.array([r["follow_atom"] for r in regions], dtype=np.int32).reshape(k)
-    cen = np.array([r["center"] for r in regions], dtype=np.float64).reshape(k, 3)
+    ax = np.array([r.get("axis", 2) for r in regions], dtype=np.int32).reshape(k)
+    fol = np.array([r.get("follow_atom", -1) for r in regions], dtype=np.int32).reshape(k)
+    cen = np.array([r.get("center", np.zeros(3)) for r in regions], dtype=np.float64).reshape(k, 3)
     rc = np.array([r["r_core"] for r in regions], dtype=np.float64).reshape(k)
     rb = np.array([r["r_blend"] for r in regions], dtype=np.float64).reshape(k)
-    return typ, ax, fol, cen, rc, rb
+    bl = np.array([r.get("blend", 0) for r in regions], dtype=np.int32).reshape(k)
+    return typ, ax, fol, cen, rc, rb, bl
 
 
 def lambda_flags(pos, L, periodic, regions):
+    """Geometric regions (types 0, 1); seeded regions (type 2) are skipped
+    here and applied by lambda_seeded over the neighbour list."""
     pos = _f64(pos)
     n = len(pos)
-    typ, ax, fol, cen, rc, rb = _regions_arrays(regions)
+    typ, ax, fol, cen, rc, rb, bl = _regions_arrays(regions)
     lam = np.zeros(n)
     flags = np.zeros(n, dtype=np.uint8)
     lib().or_lambda(ctypes.c_int(n), _p(pos), _p(_f64(L)), _p(_i32(periodic)),
                     ctypes.c_int(len(regions)), _p(typ), _p(ax), _p(fol), _p(cen),
-                    _p(rc), _p(rb), _p(lam), _p(flags))
+                    _p(rc), _p(rb), _p(bl), _p(lam), _p(flags))
+    return lam, flags
+
+
+def lambda_seeded(pos, L, periodic, offs, nbr, seeds, regions, lam):
+    """Seeded regions (Algorithms 1-2 over the neighbour list) on top of the
+    geometric lambda; returns (lambda, flags)."""
+    pos = _f64(pos)
+    n = len(pos)
+    typ, ax, fol, cen, rc, rb, bl = _regions_arrays(regions)
+    lam = _f64(lam).copy()
+    flags = np.zeros(n, dtype=np.uint8)
+    seed = np.ascontiguousarray(np.asarray(seeds).astype(np.uint8))
+    lib().or_lambda_seeded(ctypes.c_int(n), _p(pos), _p(_f64(L)), _p(_i32(periodic)),
+                           _p(offs), _p(_i32(nbr)), _p(seed), ctypes.c_int(len(regions)),
+                           _p(typ), _p(rc), _p(rb), _p(bl), _p(lam), _p(flags))
     return lam, flags
 
 
@@ -238,6 +256,9 @@ def mixed(w, mode=MODE_MIXED, pos=None, target=None, method=1):
     offs, nbr = neighbors(pos, w["L"], w["periodic"], r_list(model), method)
     if mode == MODE_MIXED:
         lam, flags = lambda_flags(pos, w["L"], w["periodic"], w["regions"])
+        if any(r["type"] == 2 for r in w["regions"]):
+            lam, flags = lambda_seeded(pos, w["L"], w["periodic"], offs, nbr, w["seeds"],
+                                       w["regions"], lam)
         flags = buffer_flags(pos, w["L"], w["periodic"], offs, nbr, w["r_buffer"], lam, flags)
     elif mode == MODE_ALL_EXPENSIVE:
         lam = np.ones(n)

@@ -251,16 +251,27 @@ int or_neighbors(int n, const double *pos, const double *L, const int32_t *per,
 /* flags bit0: lambda > 0, bit1: lambda == 1.                                 */
 /* ------------------------------------------------------------------------ */
 
+/* Blend value at t in [0, 1) (distance into the blend shell over its width):
+ * linear 1 - t (Algorithm 2), or the cubic 1 - 3 t^2 + 2 t^3, which has zero
+ * slope at both ends (the paper offers a cubic option without printing it;
+ * this is the reading adopted). */
+static double blend_value(double t, int cubic)
+{
+    return cubic ? 1.0 - t * t * (3.0 - 2.0 * t) : 1.0 - t;
+}
+
 void or_lambda(int n, const double *pos, const double *L, const int32_t *per,
                int nreg, const int32_t *type, const int32_t *axis,
                const int32_t *follow, const double *center,
-               const double *r_core, const double *r_blend, double *lam,
-               uint8_t *flags)
+               const double *r_core, const double *r_blend, const int32_t *blend,
+               double *lam, uint8_t *flags)
 {
 #pragma omp parallel for schedule(static)
     for (int i = 0; i < n; ++i) {
         double best = 0.0;
         for (int g = 0; g < nreg; ++g) {
+            if (type[g] == 2)
+                continue; /* seeded regions: or_lambda_seeded */
             const double *c = center + 3 * g;
             if (follow[g] >= 0)
                 c = pos + 3 * follow[g];
@@ -278,7 +289,7 @@ void or_lambda(int n, const double *pos, const double *L, const int32_t *per,
             } else if (d2 < outer * outer) {
                 double dist = sqrt(d2);
                 double t = (dist - rc) / rb;
-                b = 1.0 - t;
+                b = blend_value(t, blend[g]);
             } else {
                 b = 0.0;
             }
@@ -290,6 +301,73 @@ void or_lambda(int n, const double *pos, const double *L, const int32_t *per,
         if (best > 0.0)
             f |= 1;
         if (best == 1.0)
+            f |= 2;
+        flags[i] = f;
+    }
+}
+
+/* Seeded regions, as the paper's fix builds them (Algorithms 1 and 2), over
+ * the neighbour list, raising lam where a seeded region gives more:
+ *  Algorithm 1: every seed atom, and every neighbour j of a seed i with
+ *    |x_i - x_j| < r_core, is a core atom (lambda 1);
+ *  Algorithm 2: for every core atom i and neighbour j with
+ *    |x_i - x_j| = r < r_blend, lambda_j = max(lambda_j, b(r / r_blend)).
+ * Each seeded region g (type 2) has its own r_core, r_blend and blend
+ * function; all share the seed set. Distances: FP64 minimum image, strict
+ * comparisons on the squared distance, r = sqrt(d2). Flags are rewritten
+ * from the final lambda (bit0 lambda > 0, bit1 lambda == 1). */
+void or_lambda_seeded(int n, const double *pos, const double *L, const int32_t *per,
+                      const int64_t *offs, const int32_t *nbr, const uint8_t *seed,
+                      int nreg, const int32_t *type, const double *r_core,
+                      const double *r_blend, const int32_t *blend, double *lam,
+                      uint8_t *flags)
+{
+    uint8_t *core = (uint8_t *)malloc((size_t)(n > 0 ? n : 1));
+    for (int g = 0; g < nreg; ++g) {
+        if (type[g] != 2)
+            continue;
+        const double rc2 = r_core[g] * r_core[g], rb = r_blend[g], rb2 = rb * rb;
+        /* Algorithm 1: scatter from the seeds */
+        for (int i = 0; i < n; ++i)
+            core[i] = 0;
+        for (int i = 0; i < n; ++i) {
+            if (!seed[i])
+                continue;
+            core[i] = 1;
+            for (int64_t s = offs[i]; s < offs[i + 1]; ++s) {
+                const int j = nbr[s];
+                double d[3];
+                mi_disp(L, per, pos + 3 * i, pos + 3 * j, d);
+                if (norm2(d) < rc2)
+                    core[j] = 1;
+            }
+        }
+        for (int i = 0; i < n; ++i)
+            if (core[i])
+                lam[i] = 1.0;
+        /* Algorithm 2: scatter from the core atoms, keeping the maximum */
+        for (int i = 0; i < n; ++i) {
+            if (!core[i])
+                continue;
+            for (int64_t s = offs[i]; s < offs[i + 1]; ++s) {
+                const int j = nbr[s];
+                double d[3];
+                mi_disp(L, per, pos + 3 * i, pos + 3 * j, d);
+                const double d2 = norm2(d);
+                if (d2 < rb2) {
+                    const double v = blend_value(sqrt(d2) / rb, blend[g]);
+                    if (v > lam[j])
+                        lam[j] = v;
+                }
+            }
+        }
+    }
+    free(core);
+    for (int i = 0; i < n; ++i) {
+        uint8_t f = 0;
+        if (lam[i] > 0.0)
+            f |= 1;
+        if (lam[i] == 1.0)
             f |= 2;
         flags[i] = f;
     }

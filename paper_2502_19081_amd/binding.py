@@ -19,6 +19,8 @@ MODE_MIXED, MODE_ALL_EXPENSIVE, MODE_ALL_CHEAP = 0, 1, 2
 FORCE_REBUILD = 0x100
 ENERGY_ONLY = 0x200
 SINGLE_STREAM = 0x400
+SEEDED = 0x800
+FLAG_SEED = 0x80
 N_STAGES = 12
 STATUS_NEIGH_OVERFLOW, STATUS_OUT_OF_BOX, STATUS_NONFINITE, STATUS_TRIPLET_OVERFLOW, STATUS_BAD_SPECIES = 1, 2, 4, 8, 16
 
@@ -43,7 +45,7 @@ class Box(ctypes.Structure):
 
 class Region(ctypes.Structure):
     _fields_ = [("type", ctypes.c_int32), ("axis", ctypes.c_int32),
-                ("follow_atom", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("follow_atom", ctypes.c_int32), ("blend", ctypes.c_int32),
                 ("center", ctypes.c_double * 3), ("r_core", ctypes.c_double),
                 ("r_blend", ctypes.c_double)]
 

@@ -28,16 +28,20 @@ def make_box(L, periodic):
 
 
 def pack_regions(regions, device="cuda"):
-    """Region dictionaries (type, axis, follow_atom, center, r_core, r_blend)
-    -> a device byte tensor of mlmix_region structs."""
+    """Region dictionaries (type, axis, follow_atom, center, r_core, r_blend,
+    optional blend: 0 linear, 1 cubic) -> a device byte tensor of
+    mlmix_region structs. Seeded regions (type 2) need only r_core, r_blend
+    and blend."""
     n = max(len(regions), 1)
     arr = (B.Region * n)()
     for k, r in enumerate(regions):
         arr[k].type = int(r["type"])
-        arr[k].axis = int(r["axis"])
-        arr[k].follow_atom = int(r["follow_atom"])
+        arr[k].axis = int(r.get("axis", 2))
+        arr[k].follow_atom = int(r.get("follow_atom", -1))
+        arr[k].blend = int(r.get("blend", 0))
+        c = r.get("center", None)
         for q in range(3):
-            arr[k].center[q] = float(r["center"][q])
+            arr[k].center[q] = float(c[q]) if c is not None else 0.0
         arr[k].r_core = float(r["r_core"])
         arr[k].r_blend = float(r["r_blend"])
     raw = np.frombuffer(bytes(arr), dtype=np.uint8).copy()
@@ -129,6 +133,22 @@ class System:
         self.regions = pack_regions(regions, self.device)
         self.n_regions = len(regions)
 
+    def set_seeds(self, seeds):
+        """Seed atoms of the seeded regions (bool/uint8 (n,), any device), or
+        None. Each later evaluation passes them as MLMIX_FLAG_SEED bits of the
+        flags array with MLMIX_SEEDED set."""
+        if seeds is None:
+            self.seed_bits = None
+            return
+        s = torch.as_tensor(seeds).to(self.device).reshape(self.n)
+        self.seed_bits = (s != 0).to(torch.uint8) * B.FLAG_SEED
+
+    def _seed_mode(self):
+        if getattr(self, "seed_bits", None) is None:
+            return 0
+        self.flags.copy_(self.seed_bits)
+        return B.SEEDED
+
     def compute(self, pos, species, r_buffer=0.0, mode=B.MODE_MIXED, force_rebuild=False,
                 split=False, energy_only=False, single_stream=False):
         """pos: (3, n) float64 device tensor; species: (n,) int32 device tensor.
@@ -138,6 +158,7 @@ class System:
         assert species.shape == (self.n,) and species.dtype == torch.int32
         flags = (mode | (B.FORCE_REBUILD if force_rebuild else 0) |
                  (B.ENERGY_ONLY if energy_only else 0) | (B.SINGLE_STREAM if single_stream else 0))
+        flags |= self._seed_mode()
         self.generation += 1
         fe = fc = None
         if split:
@@ -165,6 +186,7 @@ class System:
                 force_rebuild=False, energies=True, single_stream=False):
         self.generation += 1
         flags = mode | (B.FORCE_REBUILD if force_rebuild else 0) | (B.SINGLE_STREAM if single_stream else 0)
+        flags |= self._seed_mode()
         B.check(B.lib().mlmix_vv_step(self.model.handle, _stream(), _p(self.ws), self.n, _p(pos),
                                       _p(vel), _p(mass), _p(species), float(dt),
                                       ctypes.byref(self.box), _p(self.regions), self.n_regions,

@@ -681,6 +681,7 @@ WsLayout make_layout(const Ctx &c, int n, int cap, const Box &b)
     take(L.hdr, H_COUNT * sizeof(int));
     take(L.cell_count, (size_t)L.grid.ncell * sizeof(int));
     take(L.cell_atoms, (size_t)L.grid.ncell * L.grid.bucket * sizeof(CellAtom));
+    take(L.seedcore, nn);
     take(L.scan_part, (size_t)nsp * sizeof(int));
     take(L.nbr, nn * cap * sizeof(int));
     take(L.rev, nn * cap * sizeof(int));
@@ -1025,7 +1026,8 @@ static int compute_impl(mlmix_ctx *ctx, hipStream_t s, void *ws, const WsLayout 
                                 : (c.side_blocks >= 0 ? c.side_blocks : (L.n < 262144 ? 512 : 0));
     {
         StageTimer t(ctx, s, ST_NBR);
-        RegionArgs ra{m, species, c.m.ns, regions, n_regions, r_buffer, lambda, flags, nullptr};
+        RegionArgs ra{m, species, c.m.ns, regions, n_regions, r_buffer, lambda, flags, nullptr,
+                      (mode & MLMIX_SEEDED) ? 1 : 0, nullptr};
         launch_neighbors(s, ws, L, b, c.r_list, pos, (mode & MLMIX_FORCE_REBUILD) ? 1 : 0,
                          c.d.skin, ra);
     }
@@ -1079,7 +1081,10 @@ static int compute_impl(mlmix_ctx *ctx, hipStream_t s, void *ws, const WsLayout 
     }
     {
         StageTimer t(ctx, s, ST_REG);
-        launch_regions(s, ws, L, b, m, pos, r_buffer, flags, (mode & MLMIX_FORCE_REBUILD) ? 1 : 0);
+        RegionArgs ra{m, species, c.m.ns, regions, n_regions, r_buffer, lambda, flags, nullptr,
+                      (mode & MLMIX_SEEDED) ? 1 : 0, nullptr};
+        launch_regions(s, ws, L, b, m, pos, r_buffer, flags, (mode & MLMIX_FORCE_REBUILD) ? 1 : 0,
+                       ra);
     }
     {
         StageTimer t(ctx, s, ST_CMP);
@@ -1139,7 +1144,8 @@ static int check_compute_args(mlmix_ctx *ctx, const double *pos, const int32_t *
     int m = (int)(mode & 0xff);
     if (m != MLMIX_MODE_MIXED && m != MLMIX_MODE_ALL_EXPENSIVE && m != MLMIX_MODE_ALL_CHEAP)
         return fail(MLMIX_E_ARG, "unknown mode");
-    if (mode & ~(0xffu | MLMIX_FORCE_REBUILD | MLMIX_ENERGY_ONLY | MLMIX_SINGLE_STREAM))
+    if (mode & ~(0xffu | MLMIX_FORCE_REBUILD | MLMIX_ENERGY_ONLY | MLMIX_SINGLE_STREAM |
+                 MLMIX_SEEDED))
         return fail(MLMIX_E_ARG, "unknown mode flag");
     if (!pos || !species || !e_exp || !lambda || !flags)
         return fail(MLMIX_E_ARG, "NULL array argument");
@@ -1286,6 +1292,8 @@ extern "C" int mlmix_status(mlmix_ctx *ctx, void *stream, void *ws, int32_t *sta
     int st = hdr[H_STATUS];
     if (st & (MLMIX_STATUS_NEIGH_OVERFLOW | MLMIX_STATUS_TRIPLET_OVERFLOW))
         return fail(MLMIX_E_NEIGH_OVERFLOW, "neighbour row capacity exceeded");
+    if (st & MLMIX_STATUS_SEEDED_REGIONS)
+        return fail(MLMIX_E_ARG, "more than 8 seeded regions");
     if (st & MLMIX_STATUS_CELL_OVERFLOW)
         return fail(MLMIX_E_NEIGH_OVERFLOW, "cell bucket capacity exceeded (local density far "
                                             "above the mean)");

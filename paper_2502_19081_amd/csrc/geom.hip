@@ -119,6 +119,20 @@ __global__ void __launch_bounds__(256) k_displacement(const double *__restrict__
 // Mixing weight of atom i: the largest linear blend over the regions
 // (Algorithms 1-2), its masks (bit 0: lambda > 0, bit 1: lambda == 1) and
 // whether it may join the buffer (lambda == 0 but near some region).
+// Blend value at t in [0, 1): linear 1 - t (Algorithm 2) or cubic
+// 1 - 3 t^2 + 2 t^3 (zero slope at both ends).
+__device__ __forceinline__ double blend_value(double t, int cubic)
+{
+#pragma clang fp contract(off)
+    return cubic ? 1.0 - t * t * (3.0 - 2.0 * t) : 1.0 - t;
+}
+
+// Mixing weight of atom i from the geometric regions (Algorithms 1-2 with
+// core shapes): the largest blend value over the regions, its masks (bit 0:
+// lambda > 0, bit 1: lambda == 1) and whether it may join the buffer
+// (lambda == 0 but near some region). Seeded regions are applied by later
+// passes over the neighbour rows; here seed atoms (with any seeded region
+// present) are core atoms of all of them, and the seed bit of flags is kept.
 __device__ __forceinline__ void atom_lambda(const double *__restrict__ pos, int n, const Box &b,
                                             int i, const RegionArgs &ra, int *hdr)
 {
@@ -126,23 +140,29 @@ __device__ __forceinline__ void atom_lambda(const double *__restrict__ pos, int 
     int z = ra.species[i];
     if (z < 0 || z >= ra.ns)
         atomicOr(&hdr[H_STATUS], MLMIX_STATUS_BAD_SPECIES);
+    const uint8_t keep = ra.seeded ? (uint8_t)(ra.flags[i] & MLMIX_FLAG_SEED) : (uint8_t)0;
     if (ra.mode == MLMIX_MODE_ALL_EXPENSIVE) {
         ra.lam[i] = 1.0;
-        ra.flags[i] = 3;
+        ra.flags[i] = (uint8_t)(3 | keep);
         ra.cand[i] = 0;
         return;
     }
     if (ra.mode == MLMIX_MODE_ALL_CHEAP) {
         ra.lam[i] = 0.0;
-        ra.flags[i] = 0;
+        ra.flags[i] = keep;
         ra.cand[i] = 0;
         return;
     }
     double best = 0.0;
     bool near = false;
+    int n_seeded = 0;
     double xi[3] = {pos[i], pos[n + i], pos[2 * n + i]};
     for (int g = 0; g < ra.nreg; ++g) {
         mlmix_region r = ra.reg[g];
+        if (r.type == MLMIX_REGION_SEEDED) {
+            ++n_seeded;
+            continue;
+        }
         double c[3] = {r.center[0], r.center[1], r.center[2]};
         if (r.follow_atom >= 0 && r.follow_atom < n) {
             c[0] = pos[r.follow_atom];
@@ -172,7 +192,7 @@ __device__ __forceinline__ void atom_lambda(const double *__restrict__ pos, int 
         } else if (d2 < outer * outer) {
             double dist = sqrt(d2);
             double t = (dist - rc) / rb;
-            v = 1.0 - t;
+            v = blend_value(t, r.blend);
         } else {
             v = 0.0;
         }
@@ -186,8 +206,16 @@ __device__ __forceinline__ void atom_lambda(const double *__restrict__ pos, int 
         if (d2 < far * far)
             near = true;
     }
+    if (ra.seeded) {
+        const bool is_seed = keep != 0 && n_seeded > 0;
+        if (is_seed)
+            best = 1.0;
+        ra.seedcore[i] = is_seed ? (uint8_t)0xff : (uint8_t)0;
+        if (n_seeded > kMaxSeeded && i == 0)
+            atomicOr(&hdr[H_STATUS], MLMIX_STATUS_SEEDED_REGIONS);
+    }
     ra.lam[i] = best;
-    uint8_t f = 0;
+    uint8_t f = keep;
     if (best > 0.0)
         f |= 1;
     if (best == 1.0)
@@ -581,9 +609,12 @@ void launch_neighbors(hipStream_t s, void *ws, const WsLayout &L, const Box &b, 
     int *count = at<int>(ws, L.cell_count);
     RegionArgs r = ra;
     r.cand = at<uint8_t>(ws, L.cand);
+    r.seedcore = at<uint8_t>(ws, L.seedcore);
     k_bin_bucket<<<(n + 255) / 256, 256, 0, s>>>(pos, n, b, g, force_rebuild, hdr, count,
                                                  at<CellAtom>(ws, L.cell_atoms), r);
-    const double rb2 = ra.mode == MLMIX_MODE_MIXED ? ra.r_buffer * ra.r_buffer : -1.0;
+    // (with seeded regions lambda is not final yet: the buffer pass follows them)
+    const double rb2 =
+        ra.mode == MLMIX_MODE_MIXED && !ra.seeded ? ra.r_buffer * ra.r_buffer : -1.0;
     k_neighbors<<<(n + 3) / 4, 256, 0, s>>>(pos, n, b, g, count, at<CellAtom>(ws, L.cell_atoms),
                                             r_list * r_list, L.cap, L.P, at<int>(ws, L.nbr),
                                             at<int>(ws, L.cnt), at<double>(ws, L.ref_pos), hdr,
@@ -690,16 +721,134 @@ __global__ void __launch_bounds__(256) k_buffer(const double *__restrict__ pos, 
         flags[i] = (uint8_t)(flags[i] | 4);
 }
 
-// Buffer pass of the region stage (lambda and the masks come from the
-// binning kernel of the neighbour stage). On a forced rebuild the row kernel
-// has found the buffer atoms already; otherwise this pass runs and repeats
-// the same test (same distances, same result) for atoms whose rows were
-// rebuilt.
+// Seeded regions, pass 1 (Algorithm 1 as a gather over the symmetric rows):
+// atom j (not a seed) is a core atom of seeded region k when a seed lies in
+// its row strictly closer than that region's r_core. One wavefront per atom.
+__global__ void __launch_bounds__(256) k_seed_core(const double *__restrict__ pos, int n, Box b,
+                                                   int cap, const int *__restrict__ nbr,
+                                                   const int *__restrict__ cnt,
+                                                   const mlmix_region *__restrict__ reg, int nreg,
+                                                   double *__restrict__ lam,
+                                                   uint8_t *__restrict__ flags,
+                                                   uint8_t *__restrict__ seedcore)
+{
+    const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (j >= n || (flags[j] & MLMIX_FLAG_SEED))
+        return;
+    const int c = cnt[j];
+    const int *row = nbr + (size_t)j * cap;
+    unsigned bits = 0;
+    for (int sl = lane; sl < c; sl += 64) {
+        const int i = row[sl];
+        if (!(flags[i] & MLMIX_FLAG_SEED))
+            continue;
+        double d[3];
+        pair_disp(pos, n, j, i, b, d);
+        const double d2 = norm2(d);
+        int k = 0;
+        for (int g = 0; g < nreg && k < kMaxSeeded; ++g) {
+            if (reg[g].type != MLMIX_REGION_SEEDED)
+                continue;
+            if (d2 < reg[g].r_core * reg[g].r_core)
+                bits |= 1u << k;
+            ++k;
+        }
+    }
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1)
+        bits |= __shfl_xor(bits, d);
+    if (lane == 0) {
+        seedcore[j] = (uint8_t)bits;
+        if (bits) {
+            lam[j] = 1.0;
+            flags[j] = (uint8_t)(flags[j] | 3);
+        }
+    }
+}
+
+// Seeded regions, pass 2 (Algorithm 2 as a gather): an atom j with
+// lambda < 1 takes the largest b(r / r_blend) over the core atoms i of each
+// seeded region in its row with r < r_blend (a maximum: the order of the
+// lanes does not matter). Atoms left at lambda == 0 become buffer candidates.
+__global__ void __launch_bounds__(256) k_seed_blend(const double *__restrict__ pos, int n, Box b,
+                                                    int cap, const int *__restrict__ nbr,
+                                                    const int *__restrict__ cnt,
+                                                    const mlmix_region *__restrict__ reg,
+                                                    int nreg, double *__restrict__ lam,
+                                                    uint8_t *__restrict__ flags,
+                                                    const uint8_t *__restrict__ seedcore,
+                                                    uint8_t *__restrict__ cand)
+{
+#pragma clang fp contract(off)
+    const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (j >= n)
+        return;
+    const double lj = lam[j];
+    double best = 0.0;
+    if (lj < 1.0) {
+        const int c = cnt[j];
+        const int *row = nbr + (size_t)j * cap;
+        for (int sl = lane; sl < c; sl += 64) {
+            const int i = row[sl];
+            const unsigned core = seedcore[i];
+            if (!core)
+                continue;
+            double d[3];
+            pair_disp(pos, n, j, i, b, d);
+            const double d2 = norm2(d);
+            int k = 0;
+            for (int g = 0; g < nreg && k < kMaxSeeded; ++g) {
+                if (reg[g].type != MLMIX_REGION_SEEDED)
+                    continue;
+                const double rb = reg[g].r_blend;
+                if ((core & (1u << k)) && d2 < rb * rb) {
+                    const double v = blend_value(sqrt(d2) / rb, reg[g].blend);
+                    best = v > best ? v : best;
+                }
+                ++k;
+            }
+        }
+#pragma unroll
+        for (int d = 32; d > 0; d >>= 1) {
+            const double o = __shfl_xor(best, d);
+            best = o > best ? o : best;
+        }
+    }
+    if (lane == 0) {
+        double l = lj;
+        if (best > l) {
+            l = best;
+            lam[j] = l;
+            flags[j] = (uint8_t)(flags[j] | 1);
+        }
+        cand[j] = l == 0.0 ? 1 : 0;
+    }
+}
+
+// Region stage after the rows: the seeded passes (MLMIX_SEEDED), then the
+// buffer pass. Lambda and the masks of the geometric regions come from the
+// binning kernel of the neighbour stage. On a forced rebuild without seeded
+// regions the row kernel has found the buffer atoms already; otherwise this
+// pass runs (for atoms whose rows were rebuilt it repeats the same test:
+// same distances, same result).
 void launch_regions(hipStream_t s, void *ws, const WsLayout &L, const Box &b, int mode,
-                    const double *pos, double r_buffer, uint8_t *flags, int force_rebuild)
+                    const double *pos, double r_buffer, uint8_t *flags, int force_rebuild,
+                    const RegionArgs &ra)
 {
     int n = L.n;
-    if (n == 0 || force_rebuild)
+    const bool seeded = ra.seeded && mode == MLMIX_MODE_MIXED;
+    if (n > 0 && seeded) {
+        uint8_t *core = at<uint8_t>(ws, L.seedcore);
+        k_seed_core<<<(n + 3) / 4, 256, 0, s>>>(pos, n, b, L.cap, at<int>(ws, L.nbr),
+                                                at<int>(ws, L.cnt), ra.reg, ra.nreg, ra.lam,
+                                                flags, core);
+        k_seed_blend<<<(n + 3) / 4, 256, 0, s>>>(pos, n, b, L.cap, at<int>(ws, L.nbr),
+                                                 at<int>(ws, L.cnt), ra.reg, ra.nreg, ra.lam,
+                                                 flags, core, at<uint8_t>(ws, L.cand));
+    }
+    if (n == 0 || (force_rebuild && !seeded))
         return;
     uint8_t *cand = at<uint8_t>(ws, L.cand);
     if (mode == MLMIX_MODE_MIXED)

@@ -55,7 +55,7 @@ struct WsLayout {
     int n, cap, P;  // atoms, row capacity, capacity rounded up to a power of two
     Grid grid;
     int n_scan_blk;  // blocks of the atom-sized scans
-    size_t hdr, cell_count, cell_atoms, scan_part;
+    size_t hdr, cell_count, cell_atoms, scan_part, seedcore;
     size_t nbr, cnt, rev, ref_pos, S_idx, M_idx, S_local, cand;
     size_t A, dEdA, g, h, red, dpart;
     size_t total;
@@ -145,14 +145,18 @@ struct RegionArgs {
     double *lam;
     uint8_t *flags;
     uint8_t *cand;
+    int seeded;         // MLMIX_SEEDED: seeded regions, seed bits in flags
+    uint8_t *seedcore;  // per atom: bit k = core atom of the k-th seeded region
 };
+constexpr int kMaxSeeded = 8;  // seeded regions per evaluation
 
 // ---- launchers (geom.hip) ----
 void launch_neighbors(hipStream_t s, void *ws, const WsLayout &L, const Box &b, double r_list,
                       const double *pos, int force_rebuild, double skin, const RegionArgs &ra);
 void launch_reverse(hipStream_t s, void *ws, const WsLayout &L, int side_blocks);
 void launch_regions(hipStream_t s, void *ws, const WsLayout &L, const Box &b, int mode,
-                    const double *pos, double r_buffer, uint8_t *flags, int force_rebuild);
+                    const double *pos, double r_buffer, uint8_t *flags, int force_rebuild,
+                    const RegionArgs &ra);
 void launch_compact(hipStream_t s, void *ws, const WsLayout &L, uint8_t *flags, int32_t *n_expensive);
 
 // ---- ace.hip ----

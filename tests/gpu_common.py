@@ -10,6 +10,8 @@ def run_gpu(w, mode=0, precision=None, cap=128, force_rebuild=True, split=True, 
     if system is None:
         model = core.Model(w["model"], precision=prec)
         _, sy, pos, sp = core.system_for(w, model=model, cap=cap)
+        if "seeds" in w:
+            sy.set_seeds(torch.from_numpy(np.asarray(w["seeds"]).astype(np.uint8)))
     else:
         sy, pos, sp = system
     out = sy.compute(pos, sp, r_buffer=w["r_buffer"], mode=mode, force_rebuild=force_rebuild,

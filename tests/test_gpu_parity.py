@@ -22,7 +22,8 @@ def _check(w, mode, precision, ref=None, f_tol=None):
     g = run_gpu(w, MODES[mode], precision=precision)
     assert_neighbors_equal(g, ref)
     assert np.array_equal(g["lam"], ref["lam"])
-    assert np.array_equal(g["flags"], ref["flags"])
+    # bit 7 is the seed marker the caller passes in (kept by the library)
+    assert np.array_equal(g["flags"] & 0x7F, ref["flags"])
     assert np.array_equal(g["S"], ref["S"])
     assert np.array_equal(g["M"], ref["M"])
     assert g["n_exp"].tolist() == [len(ref["S"]), len(ref["M"])]
@@ -143,3 +144,33 @@ def test_basis_forms_agree():
     for g in (g1, g2):
         assert np.abs(g["forces"] - ref["forces"]).max() < 1e-4
         assert np.abs(g["e_exp"] - ref["e_exp"]).max() < 1e-3
+
+
+def _seeded_tiny(seed, blend):
+    w = W.tiny(seed=seed, n_species=2)
+    rng = np.random.default_rng(seed)
+    seeds = np.zeros(len(w["pos"]), bool)
+    seeds[rng.choice(len(seeds), 2, replace=False)] = True
+    w["seeds"] = seeds
+    w["regions"] = [W.seeded(2.9, 3.2, blend=blend), W.sphere(w["L"] / 4.0, 1.0, 1.5, blend=1)]
+    return w
+
+
+@pytest.mark.parametrize("blend", [0, 1])
+def test_tiny_seeded_regions_fp64(blend):
+    # the paper's seeded region fix (core around seed atoms, blend to the
+    # nearest core atom; linear or cubic) beside a cubic geometric sphere
+    _check(_seeded_tiny(21 + blend, blend), "mixed", "fp64")
+
+
+def test_c2_seeded_region_fp32():
+    w = W.c2()
+    c = w["regions"][0]["center"]
+    d = w["pos"] - c
+    d -= w["L"] * np.round(d / w["L"])
+    r = np.linalg.norm(d, axis=1)
+    w["seeds"] = r < 2.0  # the atoms of the self-interstitial
+    w["regions"] = [W.seeded(3.0, 5.0, blend=1)]
+    g, ref = _check(w, "mixed", "fp32")
+    assert 0 < len(ref["M"]) < len(w["pos"]) and np.array_equal(g["lam"], ref["lam"])
+

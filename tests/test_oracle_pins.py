@@ -138,6 +138,95 @@ def test_buffer_brute_force_all_pairs():
         assert not np.any(((fb & 4) != 0) & inM)
 
 
+def _blend_ref(t, cubic):
+    return 1.0 - 3.0 * t ** 2 + 2.0 * t ** 3 if cubic else 1.0 - t
+
+
+def _seeded_brute(pos, L, per, seeds, regs, lam0):
+    """The paper's Algorithms 1-2 for seeded regions over all pairs (no
+    neighbour list), pure Python loops over the scatter loops as printed."""
+    n = len(pos)
+    d = pos[None, :, :] - pos[:, None, :]
+    for k in range(3):
+        if per[k]:
+            d[..., k] -= L[k] * np.round(d[..., k] / L[k])
+    r2 = (d ** 2).sum(-1)
+    lam = lam0.copy()
+    for r in regs:
+        if r["type"] != 2:
+            continue
+        core = np.asarray(seeds, bool).copy()
+        for i in range(n):
+            if seeds[i]:
+                for j in range(n):
+                    if j != i and r2[i, j] < r["r_core"] ** 2:
+                        core[j] = True
+        lam[core] = 1.0
+        for i in range(n):
+            if core[i]:
+                for j in range(n):
+                    if j != i and r2[i, j] < r["r_blend"] ** 2:
+                        lam[j] = max(lam[j], _blend_ref(math.sqrt(r2[i, j]) / r["r_blend"],
+                                                        r.get("blend", 0)))
+    return lam
+
+
+def test_seeded_chain_closed_form():
+    # atoms on a line 2 A apart, seed = atom 2; r_core 2.5 makes atoms 1-3
+    # core; blend radius 5 measured to the nearest core atom: atoms 0 and 4
+    # are 2 A from the core (t = 0.4), atom 5 is 4 A away (t = 0.8), atom 6
+    # (6 A) gets nothing; buffer 3 A then takes atom 6 (2 A from atom 5)
+    n = 9
+    pos = np.zeros((n, 3))
+    pos[:, 0] = 1.0 + 2.0 * np.arange(n)
+    pos[:, 1:] = 5.0
+    L, per = np.array([40.0, 10.0, 10.0]), [0, 0, 0]
+    seeds = np.zeros(n, bool)
+    seeds[2] = True
+    offs, nbr = O.neighbors(pos, L, per, 7.0)
+    for cubic in (0, 1):
+        regs = [W.seeded(2.5, 5.0, blend=cubic)]
+        lam, flags = O.lambda_flags(pos, L, per, regs)
+        assert not lam.any()
+        lam, flags = O.lambda_seeded(pos, L, per, offs, nbr, seeds, regs, lam)
+        b4, b8 = _blend_ref(0.4, cubic), _blend_ref(0.8, cubic)
+        np.testing.assert_allclose(lam, [b4, 1, 1, 1, b4, b8, 0, 0, 0], rtol=0, atol=1e-15)
+        flags = O.buffer_flags(pos, L, per, offs, nbr, 3.0, lam, flags)
+        assert flags.tolist() == [1, 3, 3, 3, 1, 1, 4, 0, 0]
+    # the cubic values themselves: 1 - 3 t^2 + 2 t^3 at t = 0.4 and 0.8
+    assert abs(_blend_ref(0.4, 1) - 0.648) < 1e-15 and abs(_blend_ref(0.8, 1) - 0.104) < 1e-15
+
+
+def test_seeded_brute_force_random_cluster():
+    rng = np.random.default_rng(11)
+    n = 70
+    L, per = np.array([11.0, 11.0, 11.0]), [1, 1, 0]
+    pos = rng.uniform(0.0, 11.0, size=(n, 3))
+    seeds = np.zeros(n, bool)
+    seeds[rng.choice(n, 3, replace=False)] = True
+    regs = [W.seeded(2.2, 3.0), W.seeded(1.5, 2.5, blend=1), W.sphere([2.0, 3.0, 4.0], 1.0, 1.5, blend=1)]
+    offs, nbr = O.neighbors(pos, L, per, 4.0)
+    lam0, _ = O.lambda_flags(pos, L, per, regs)
+    lam, flags = O.lambda_seeded(pos, L, per, offs, nbr, seeds, regs, lam0)
+    ref = _seeded_brute(pos, L, per, seeds, regs, lam0)
+    np.testing.assert_allclose(lam, ref, rtol=0, atol=1e-14)
+    assert np.array_equal((flags & 1) != 0, lam > 0)
+    assert np.array_equal((flags & 2) != 0, lam == 1.0)
+    assert (lam[seeds] == 1.0).all()
+
+
+def test_cubic_geometric_blend_closed_form():
+    # atoms on a ray from a sphere's centre at known distances
+    ds = np.array([0.5, 2.0, 2.6, 3.2, 3.8, 4.4, 5.0, 6.0])
+    pos = np.zeros((len(ds), 3)) + 10.0
+    pos[:, 0] += ds
+    c = np.array([10.0, 10.0, 10.0])
+    lam, _ = O.lambda_flags(pos, [30.0] * 3, [0, 0, 0], [W.sphere(c, 2.0, 3.0, blend=1)])
+    t = np.clip((ds - 2.0) / 3.0, 0.0, 1.0)
+    ref = np.where(ds < 2.0, 1.0, np.where(ds < 5.0, 1.0 - 3.0 * t ** 2 + 2.0 * t ** 3, 0.0))
+    np.testing.assert_allclose(lam, ref, rtol=0, atol=1e-14)
+
+
 # ------------------------------------------------------ special functions
 
 def test_radial_is_chebyshev_times_envelope():
