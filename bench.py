@@ -60,6 +60,9 @@ def parse():
     ap.add_argument("--seeded", action="store_true",
                     help="seeded region (the paper's fix: seeds at the defect, 6 A core, "
                          "2 A blend) instead of the workload's geometric regions")
+    ap.add_argument("--cheap-masked", action="store_true",
+                    help="the cheap potential on its own subsystem (lambda < 1 plus its "
+                         "buffer) as Algorithm 4 masks each potential")
     ap.add_argument("--dominant-only", action="store_true",
                     help="stop after timing the dominant kernel (phases 1-2) and print its "
                          "average; for a kernel trace of the same launches")
@@ -192,7 +195,7 @@ def main():
 
     def step(sy, pos, vel, sp, mode):
         sy.vv_step(pos, vel, mass, sp, dt, r_buffer=w["r_buffer"], mode=mode, force_rebuild=True,
-                   single_stream=args.single_stream)
+                   single_stream=args.single_stream, cheap_masked=args.cheap_masked)
 
     def run(mode, steps, warmup, stage_mask=0, latency=False, graph=False):
         """Times `steps` steps. graph=True captures `chunk` consecutive steps
@@ -290,7 +293,8 @@ def main():
 
     # work counts of the initial configuration (for the roofline)
     sy, pos, vel, sp = fresh(B.MODE_MIXED)
-    out = sy.compute(pos, sp, r_buffer=w["r_buffer"], mode=B.MODE_MIXED, force_rebuild=True)
+    out = sy.compute(pos, sp, r_buffer=w["r_buffer"], mode=B.MODE_MIXED, force_rebuild=True,
+                     cheap_masked=args.cheap_masked)
     torch.cuda.synchronize()
     nS, nM = [int(x) for x in out["n_exp"].cpu()]
     S_idx, _ = sy.index_sets()
@@ -362,7 +366,7 @@ def main():
         target = np.zeros(n, bool)
         target[sub] = True
         t0 = time.perf_counter()
-        ref = O.mixed(w, O.MODE_MIXED, target=target)
+        ref = O.mixed(w, O.MODE_MIXED, target=target, cheap_masked=args.cheap_masked)
         t_cpu = time.perf_counter() - t0
         ferr = float(np.abs(gpu_forces[sub] - ref["forces"][sub]).max())
         cpu = {"value": len(sub) / t_cpu, "unit": "atom-steps/s", "cores": O.num_threads(),
@@ -373,12 +377,13 @@ def main():
     elif not args.no_cpu_baseline:
         import oracle as O
         t0 = time.perf_counter()
-        ref = O.mixed(w, O.MODE_MIXED)
+        ref = O.mixed(w, O.MODE_MIXED, cheap_masked=args.cheap_masked)
         t_first = time.perf_counter() - t0
         ferr = float(np.abs(gpu_forces - ref["forces"]).max())
         n_cpu = max(1, int(args.cpu_seconds / max(t_first, 1e-3)))
         t0 = time.perf_counter()
-        O.velocity_verlet(w, w["pos"], vel0, float(w.get("dt", 1.0)), n_cpu, mode=O.MODE_MIXED)
+        O.velocity_verlet(w, w["pos"], vel0, float(w.get("dt", 1.0)), n_cpu, mode=O.MODE_MIXED,
+                          cheap_masked=args.cheap_masked)
         t_cpu = time.perf_counter() - t0
         cpu = {"value": n * n_cpu / t_cpu, "unit": "atom-steps/s", "cores": O.num_threads(),
                "kind": "oracle",
@@ -397,6 +402,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOADS[cfg], "n_atoms": n, "mode": "mixed",
                    "regions": "seeded (6 A core, 2 A blend)" if args.seeded else "geometric",
+                   "cheap": "masked to its subsystem" if args.cheap_masked else "every atom",
                    "precision": prec, "neighbour_rebuild": "every step", "n_S": nS, "n_lambda_pos": nM,
                    "launch": (f"{args.graph_steps} consecutive steps per captured HIP graph, "
                               "replayed" if args.steps % args.graph_steps == 0 and args.graph_steps > 1

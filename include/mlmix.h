@@ -87,6 +87,13 @@ extern "C" {
  * seeded core and blend passes (two more neighbour-row kernels). */
 #define MLMIX_SEEDED 0x800u
 #define MLMIX_FLAG_SEED 0x80u
+/* Mask the cheap potential as Algorithm 4 masks each potential in turn: it
+ * sees only its own subsystem S_c = {lambda < 1} plus its buffer (atoms with
+ * lambda == 1 strictly closer than r_buffer to an atom with lambda < 1;
+ * flags bit3). Atoms outside S_c are neither centres nor neighbours of the
+ * cheap potential (e_cheap and f_cheap are 0 there). Without this flag the
+ * cheap potential runs on every atom with the full lists. MIXED mode only. */
+#define MLMIX_CHEAP_MASKED 0x1000u
 
 /* Device status bits reported by mlmix_status(). */
 #define MLMIX_STATUS_NEIGH_OVERFLOW 1
@@ -211,7 +218,8 @@ int mlmix_workspace_init(mlmix_ctx *ctx, void *stream, void *ws, size_t ws_bytes
  * Outputs [dev]: forces 3 x n double (blended; may be NULL with
  *  MLMIX_ENERGY_ONLY), e_exp[n] (expensive site energies on S, 0 elsewhere),
  *  e_cheap[n] (cheap site energies, 0 in ALL_EXPENSIVE mode), lambda[n],
- *  flags[n] (bit0 lambda>0, bit1 lambda==1, bit2 buffer), n_expensive
+ *  flags[n] (bit0 lambda>0, bit1 lambda==1, bit2 buffer, bit3 cheap buffer
+ *  with MLMIX_CHEAP_MASKED, bit7 seed as passed in), n_expensive
  *  int32[2] (|S|, |{lambda>0}|). f_exp and f_cheap (3 x n double) are
  *  optional (NULL) copies of the two unblended force fields.
  * The neighbour list is rebuilt when MLMIX_FORCE_REBUILD is set, on the first

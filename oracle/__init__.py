@@ -122,6 +122,15 @@ def lambda_seeded(pos, L, periodic, offs, nbr, seeds, regions, lam):
     return lam, flags
 
 
+def cheap_buffer_flags(pos, L, periodic, offs, nbr, r_buffer, lam, flags):
+    pos = _f64(pos)
+    flags = flags.copy()
+    lib().or_cheap_buffer(ctypes.c_int(len(pos)), _p(pos), _p(_f64(L)), _p(_i32(periodic)),
+                          _p(offs), _p(_i32(nbr)), ctypes.c_double(r_buffer), _p(_f64(lam)),
+                          _p(flags))
+    return flags
+
+
 def buffer_flags(pos, L, periodic, offs, nbr, r_buffer, lam, flags):
     pos = _f64(pos)
     flags = flags.copy()
@@ -176,16 +185,18 @@ def ace_site(model, z, A):
     return E, dA
 
 
-def uf3(model, pos, species, L, periodic, offs, nbr, target=None):
+def uf3(model, pos, species, L, periodic, offs, nbr, target=None, in_S=None):
+    """Cheap potential; with in_S only on that induced subsystem."""
     pos = _f64(pos)
     n = len(pos)
     s, keep = _uf3_struct(model)
     e = np.zeros(n)
     f = np.zeros((n, 3))
     tg = None if target is None else np.ascontiguousarray(target, dtype=np.uint8)
+    inS = None if in_S is None else np.ascontiguousarray(in_S, dtype=np.uint8)
     rc = lib().or_uf3_eval(ctypes.byref(s), ctypes.c_int(n), _p(pos), _p(_i32(species)),
                            _p(_f64(L)), _p(_i32(periodic)), _p(offs), _p(_i32(nbr)),
-                           _p(tg), _p(e), _p(f))
+                           _p(tg), _p(inS), _p(e), _p(f))
     assert rc == 0
     return e, f
 
@@ -242,12 +253,15 @@ def r_list(model):
                model["uf3"]["rcut3"] if model["uf3"]["n_knots3"] > 0 else 0.0) + model["skin"]
 
 
-def mixed(w, mode=MODE_MIXED, pos=None, target=None, method=1):
+def mixed(w, mode=MODE_MIXED, pos=None, target=None, method=1, cheap_masked=False):
     """The whole mixed force evaluation for workload w.
 
     Returns dict(lam, flags, S, M, offs, nbr, e_exp, f_exp, e_cheap, f_cheap,
     forces). Modes: mixed; all-expensive (lambda = 1, S = every atom, cheap
-    not evaluated); all-cheap (lambda = 0, S empty).
+    not evaluated); all-cheap (lambda = 0, S empty). cheap_masked (mixed
+    mode): the cheap potential too sees only its induced subsystem
+    S_c = {lambda < 1} plus its buffer (flags bit3), as Algorithm 4 masks each
+    potential in turn.
     """
     pos = w["pos"] if pos is None else pos
     pos = _f64(pos)
@@ -260,6 +274,9 @@ def mixed(w, mode=MODE_MIXED, pos=None, target=None, method=1):
             lam, flags = lambda_seeded(pos, w["L"], w["periodic"], offs, nbr, w["seeds"],
                                        w["regions"], lam)
         flags = buffer_flags(pos, w["L"], w["periodic"], offs, nbr, w["r_buffer"], lam, flags)
+        if cheap_masked:
+            flags = cheap_buffer_flags(pos, w["L"], w["periodic"], offs, nbr, w["r_buffer"], lam,
+                                       flags)
     elif mode == MODE_ALL_EXPENSIVE:
         lam = np.ones(n)
         flags = np.full(n, 3, dtype=np.uint8)
@@ -275,8 +292,11 @@ def mixed(w, mode=MODE_MIXED, pos=None, target=None, method=1):
     else:
         e_exp, f_exp = np.zeros(n), np.zeros((n, 3))
     if mode != MODE_ALL_EXPENSIVE:
+        in_Sc = None
+        if cheap_masked and mode == MODE_MIXED:
+            in_Sc = (lam < 1.0) | ((flags & 8) != 0)
         e_ch, f_ch = uf3(model, pos, w["species"], w["L"], w["periodic"], offs, nbr,
-                         target=target)
+                         target=target, in_S=in_Sc)
     else:
         e_ch, f_ch = np.zeros(n), np.zeros((n, 3))
     forces = np.zeros((n, 3))
@@ -285,13 +305,13 @@ def mixed(w, mode=MODE_MIXED, pos=None, target=None, method=1):
                 f_exp=f_exp, e_cheap=e_ch, f_cheap=f_ch, forces=forces)
 
 
-def velocity_verlet(w, pos, vel, dt, nsteps, mode=MODE_MIXED, callback=None):
+def velocity_verlet(w, pos, vel, dt, nsteps, mode=MODE_MIXED, callback=None, cheap_masked=False):
     """Velocity Verlet: v += dt/2 kappa F/m; x += dt v; wrap; F(x); v += dt/2 kappa F/m."""
     from gen.workloads import KAPPA
     m = w["masses"][w["species"]][:, None]
     pos = _f64(pos).copy()
     vel = _f64(vel).copy()
-    out = mixed(w, mode, pos=pos)
+    out = mixed(w, mode, pos=pos, cheap_masked=cheap_masked)
     F = out["forces"]
     for step in range(nsteps):
         vel = vel + 0.5 * dt * KAPPA * F / m
@@ -300,7 +320,7 @@ def velocity_verlet(w, pos, vel, dt, nsteps, mode=MODE_MIXED, callback=None):
             if w["periodic"][k]:
                 Lk = w["L"][k]
                 pos[:, k] = pos[:, k] - Lk * np.floor(pos[:, k] / Lk)
-        out = mixed(w, mode, pos=pos)
+        out = mixed(w, mode, pos=pos, cheap_masked=cheap_masked)
         F = out["forces"]
         vel = vel + 0.5 * dt * KAPPA * F / m
         if callback:

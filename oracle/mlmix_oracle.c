@@ -399,6 +399,34 @@ void or_buffer(int n, const double *pos, const double *L, const int32_t *per,
     }
 }
 
+/* The cheap potential's own buffer when it is masked like the expensive one
+ * (Algorithm 4 for potential 1, whose weight is 1 - lambda): an atom with
+ * lambda == 1 joins it (flags bit3) when some neighbour j with lambda_j < 1
+ * lies strictly closer than r_buffer. The cheap subsystem is then
+ * {lambda < 1} plus these atoms. */
+void or_cheap_buffer(int n, const double *pos, const double *L, const int32_t *per,
+                     const int64_t *offs, const int32_t *nbr, double r_buffer,
+                     const double *lam, uint8_t *flags)
+{
+    double rb2 = r_buffer * r_buffer;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int i = 0; i < n; ++i) {
+        if (!(lam[i] == 1.0))
+            continue;
+        for (int64_t s = offs[i]; s < offs[i + 1]; ++s) {
+            int j = nbr[s];
+            if (lam[j] == 1.0)
+                continue;
+            double d[3];
+            mi_disp(L, per, pos + 3 * i, pos + 3 * j, d);
+            if (norm2(d) < rb2) {
+                flags[i] |= 8;
+                break;
+            }
+        }
+    }
+}
+
 /* ------------------------------------------------------------------------ */
 /* Special functions for the ACE-style model                                  */
 /* ------------------------------------------------------------------------ */
@@ -898,11 +926,14 @@ void or_clamped_knots(int n_pts, double top, double *t) { clamped_knots(n_pts, t
 /* E_i = 1/2 sum_{j, r_ij < rc2} V2^{z_i z_j}(r_ij)
  *     + sum_{j < k; r_ij, r_ik < rc3} V3^{z_i}(r_ij, r_ik, r_jk),
  * V2 = sum_n c2[z_i][z_j][n] B_n(r), V3 = sum_pqs c3[z_i][p][q][s] B_p(r_ij)
- * B_q(r_ik) B_s(r_jk), r_jk = |d_ik - d_ij|; forces = -grad of sum_i E_i. */
+ * B_q(r_ik) B_s(r_jk), r_jk = |d_ik - d_ij|; forces = -grad of sum_i E_i.
+ * With in_S (NULL = every atom) the potential sees the induced subsystem
+ * only, as Algorithm 4 removes the atoms of the other potential from the
+ * neighbour list: atoms outside S are neither centres nor neighbours. */
 int or_uf3_eval(const or_uf3_model *m, int n, const double *pos,
                 const int32_t *species, const double *L, const int32_t *per,
                 const int64_t *offs, const int32_t *nbr, const uint8_t *target,
-                double *e_out, double *f_out)
+                const uint8_t *in_S, double *e_out, double *f_out)
 {
     int ns = m->n_species;
     int nb2 = m->n_knots2 + 2;
@@ -917,13 +948,13 @@ int or_uf3_eval(const or_uf3_model *m, int n, const double *pos,
     uint8_t *need = (uint8_t *)calloc((size_t)(n > 0 ? n : 1), 1);
     double rmax = m->rcut2 > m->rcut3 ? m->rcut2 : m->rcut3;
     for (int i = 0; i < n; ++i) {
-        if (!target || target[i]) {
+        if ((!target || target[i]) && (!in_S || in_S[i])) {
             need[i] = 1;
             if (target)
                 for (int64_t s = offs[i]; s < offs[i + 1]; ++s) {
                     double d[3];
                     mi_disp(L, per, pos + 3 * i, pos + 3 * nbr[s], d);
-                    if (norm2(d) < rmax * rmax)
+                    if (norm2(d) < rmax * rmax && (!in_S || in_S[nbr[s]]))
                         need[nbr[s]] = 1;
                 }
         }
@@ -944,6 +975,8 @@ int or_uf3_eval(const or_uf3_model *m, int n, const double *pos,
             int64_t s0 = offs[i], s1 = offs[i + 1];
             for (int64_t s = s0; s < s1; ++s) {
                 int j = nbr[s];
+                if (in_S && !in_S[j])
+                    continue;
                 double d[3];
                 mi_disp(L, per, pos + 3 * i, pos + 3 * j, d);
                 double r2 = norm2(d);
@@ -964,12 +997,16 @@ int or_uf3_eval(const or_uf3_model *m, int n, const double *pos,
             if (nb3) {
                 const double *c3 = m->c3 + (size_t)zi * nb3 * nb3 * nb3;
                 for (int64_t sj = s0; sj < s1; ++sj) {
+                    if (in_S && !in_S[nbr[sj]])
+                        continue;
                     double dj[3];
                     mi_disp(L, per, pos + 3 * i, pos + 3 * nbr[sj], dj);
                     double rj2 = norm2(dj);
                     if (!(rj2 < rc3))
                         continue;
                     for (int64_t sk = sj + 1; sk < s1; ++sk) {
+                        if (in_S && !in_S[nbr[sk]])
+                            continue;
                         double dk[3];
                         mi_disp(L, per, pos + 3 * i, pos + 3 * nbr[sk], dk);
                         double rk2 = norm2(dk);

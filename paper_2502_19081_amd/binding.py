@@ -21,6 +21,7 @@ ENERGY_ONLY = 0x200
 SINGLE_STREAM = 0x400
 SEEDED = 0x800
 FLAG_SEED = 0x80
+CHEAP_MASKED = 0x1000
 N_STAGES = 12
 STATUS_NEIGH_OVERFLOW, STATUS_OUT_OF_BOX, STATUS_NONFINITE, STATUS_TRIPLET_OVERFLOW, STATUS_BAD_SPECIES = 1, 2, 4, 8, 16
 

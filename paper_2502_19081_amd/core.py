@@ -150,15 +150,16 @@ class System:
         return B.SEEDED
 
     def compute(self, pos, species, r_buffer=0.0, mode=B.MODE_MIXED, force_rebuild=False,
-                split=False, energy_only=False, single_stream=False):
+                split=False, energy_only=False, single_stream=False, cheap_masked=False):
         """pos: (3, n) float64 device tensor; species: (n,) int32 device tensor.
         single_stream: keep every stage on the current stream (no fork onto
-        the workspace's second stream)."""
+        the workspace's second stream). cheap_masked: the cheap potential on
+        its own subsystem only (MLMIX_CHEAP_MASKED)."""
         assert pos.shape == (3, self.n) and pos.dtype == torch.float64 and pos.is_contiguous()
         assert species.shape == (self.n,) and species.dtype == torch.int32
         flags = (mode | (B.FORCE_REBUILD if force_rebuild else 0) |
                  (B.ENERGY_ONLY if energy_only else 0) | (B.SINGLE_STREAM if single_stream else 0))
-        flags |= self._seed_mode()
+        flags |= self._seed_mode() | (B.CHEAP_MASKED if cheap_masked else 0)
         self.generation += 1
         fe = fc = None
         if split:
@@ -183,10 +184,10 @@ class System:
         return grad_pos
 
     def vv_step(self, pos, vel, mass, species, dt, r_buffer=0.0, mode=B.MODE_MIXED,
-                force_rebuild=False, energies=True, single_stream=False):
+                force_rebuild=False, energies=True, single_stream=False, cheap_masked=False):
         self.generation += 1
         flags = mode | (B.FORCE_REBUILD if force_rebuild else 0) | (B.SINGLE_STREAM if single_stream else 0)
-        flags |= self._seed_mode()
+        flags |= self._seed_mode() | (B.CHEAP_MASKED if cheap_masked else 0)
         B.check(B.lib().mlmix_vv_step(self.model.handle, _stream(), _p(self.ws), self.n, _p(pos),
                                       _p(vel), _p(mass), _p(species), float(dt),
                                       ctypes.byref(self.box), _p(self.regions), self.n_regions,

@@ -999,6 +999,7 @@ static int compute_impl(mlmix_ctx *ctx, hipStream_t s, void *ws, const WsLayout 
     int m = (int)(mode & 0xff);
     bool energy_only = (mode & MLMIX_ENERGY_ONLY) != 0;
     bool fork = (mode & MLMIX_SINGLE_STREAM) == 0;
+    const bool masked = (mode & MLMIX_CHEAP_MASKED) != 0 && m == MLMIX_MODE_MIXED;
     SideStream sd;
     if (fork) {
         // the workspace's second stream is created by its first forked
@@ -1056,7 +1057,8 @@ static int compute_impl(mlmix_ctx *ctx, hipStream_t s, void *ws, const WsLayout 
         if (!energy_only) {
             if (m != MLMIX_MODE_ALL_EXPENSIVE) {
                 StageTimer t(ctx, s2, ST_UF3);
-                launch_uf3(s2, c, ws, L, b, pos, species, e_cheap, side_blocks);
+                launch_uf3(s2, c, ws, L, b, pos, species, e_cheap, side_blocks,
+                           masked ? flags : nullptr);
             } else {
                 launch_fill_f64(s2, e_cheap, 0.0, (size_t)L.n);
             }
@@ -1069,12 +1071,14 @@ static int compute_impl(mlmix_ctx *ctx, hipStream_t s, void *ws, const WsLayout 
     // recorded after the rows, side kernels issued after the compaction (so
     // that a captured graph keeps the expensive chain on the first queue);
     // 1: both after the atomic basis
-    const bool late = c.fork_at == 1 && m != MLMIX_MODE_ALL_CHEAP;
-    if (c.fork_at == 2) {
+    // With the cheap potential masked its kernel needs the final masks: the
+    // fork point then follows the region stage.
+    const bool late = c.fork_at == 1 && m != MLMIX_MODE_ALL_CHEAP && !masked;
+    if (c.fork_at == 2 && !masked) {
         int rc = record_fork();
         if (rc)
             return rc;
-    } else if (!late) {
+    } else if (!late && !masked) {
         int rc = fork_side();
         if (rc)
             return rc;
@@ -1085,12 +1089,19 @@ static int compute_impl(mlmix_ctx *ctx, hipStream_t s, void *ws, const WsLayout 
                       (mode & MLMIX_SEEDED) ? 1 : 0, nullptr};
         launch_regions(s, ws, L, b, m, pos, r_buffer, flags, (mode & MLMIX_FORCE_REBUILD) ? 1 : 0,
                        ra);
+        if (masked)
+            launch_cheap_buffer(s, ws, L, b, pos, r_buffer, flags);
+    }
+    if (masked) {
+        int rc = record_fork();
+        if (rc)
+            return rc;
     }
     {
         StageTimer t(ctx, s, ST_CMP);
         launch_compact(s, ws, L, flags, n_expensive);
     }
-    if (c.fork_at == 2) {
+    if (c.fork_at == 2 || masked) {
         int rc = fork_side();
         if (rc)
             return rc;
@@ -1145,7 +1156,7 @@ static int check_compute_args(mlmix_ctx *ctx, const double *pos, const int32_t *
     if (m != MLMIX_MODE_MIXED && m != MLMIX_MODE_ALL_EXPENSIVE && m != MLMIX_MODE_ALL_CHEAP)
         return fail(MLMIX_E_ARG, "unknown mode");
     if (mode & ~(0xffu | MLMIX_FORCE_REBUILD | MLMIX_ENERGY_ONLY | MLMIX_SINGLE_STREAM |
-                 MLMIX_SEEDED))
+                 MLMIX_SEEDED | MLMIX_CHEAP_MASKED))
         return fail(MLMIX_E_ARG, "unknown mode flag");
     if (!pos || !species || !e_exp || !lambda || !flags)
         return fail(MLMIX_E_ARG, "NULL array argument");

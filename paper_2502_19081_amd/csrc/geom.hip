@@ -827,6 +827,43 @@ __global__ void __launch_bounds__(256) k_seed_blend(const double *__restrict__ p
     }
 }
 
+// The cheap potential's buffer (MLMIX_CHEAP_MASKED): an atom with
+// lambda == 1 joins it (flags bit3) when a row partner with lambda < 1 lies
+// strictly inside r_buffer. One wavefront per atom; others return at once.
+__global__ void __launch_bounds__(256) k_cheap_buffer(const double *__restrict__ pos, int n, Box b,
+                                                      int cap, const int *__restrict__ nbr,
+                                                      const int *__restrict__ cnt, double rb2,
+                                                      uint8_t *__restrict__ flags)
+{
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (i >= n || !(flags[i] & 2))
+        return;
+    const int c = cnt[i];
+    const int *row = nbr + (size_t)i * cap;
+    bool hit = false;
+    for (int sl = lane; sl < c; sl += 64) {
+        const int j = row[sl];
+        if (flags[j] & 2)
+            continue;
+        double d[3];
+        pair_disp(pos, n, i, j, b, d);
+        if (norm2(d) < rb2)
+            hit = true;
+    }
+    if (__ballot(hit) != 0ull && lane == 0)
+        flags[i] = (uint8_t)(flags[i] | 8);
+}
+
+void launch_cheap_buffer(hipStream_t s, void *ws, const WsLayout &L, const Box &b,
+                         const double *pos, double r_buffer, uint8_t *flags)
+{
+    if (L.n == 0)
+        return;
+    k_cheap_buffer<<<(L.n + 3) / 4, 256, 0, s>>>(pos, L.n, b, L.cap, at<int>(ws, L.nbr),
+                                                 at<int>(ws, L.cnt), r_buffer * r_buffer, flags);
+}
+
 // Region stage after the rows: the seeded passes (MLMIX_SEEDED), then the
 // buffer pass. Lambda and the masks of the geometric regions come from the
 // binning kernel of the neighbour stage. On a forced rebuild without seeded

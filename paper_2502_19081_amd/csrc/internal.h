@@ -158,6 +158,8 @@ void launch_regions(hipStream_t s, void *ws, const WsLayout &L, const Box &b, in
                     const double *pos, double r_buffer, uint8_t *flags, int force_rebuild,
                     const RegionArgs &ra);
 void launch_compact(hipStream_t s, void *ws, const WsLayout &L, uint8_t *flags, int32_t *n_expensive);
+void launch_cheap_buffer(hipStream_t s, void *ws, const WsLayout &L, const Box &b,
+                         const double *pos, double r_buffer, uint8_t *flags);
 
 // ---- ace.hip ----
 void launch_ace_basis(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L, const Box &b,
@@ -178,8 +180,11 @@ void launch_ace_o3(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L,
 size_t o3_lds_bytes(const Ctx &c);
 
 // ---- uf3.hip ----
+// mask_flags: NULL, or the flags array (MLMIX_CHEAP_MASKED): the cheap
+// potential then sees S_c = {lambda < 1} plus its buffer only
 void launch_uf3(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L, const Box &b,
-                const double *pos, const int32_t *species, double *e_cheap, int side_blocks);
+                const double *pos, const int32_t *species, double *e_cheap, int side_blocks,
+                const uint8_t *mask_flags = nullptr);
 
 // ---- tail.hip ----
 // Closing half kick of a velocity-Verlet step and per-block energy partials,

@@ -134,7 +134,8 @@ template <typename T, int U, bool LOOP>
 __global__ void __launch_bounds__(256)
     k_uf3(const double *__restrict__ pos, int n, Box b, const int32_t *__restrict__ species,
           int cap, const int *__restrict__ nbr, const int *__restrict__ cnt, Uf3Args<T> a,
-          T *__restrict__ hout, double *__restrict__ e_cheap, int *hdr)
+          T *__restrict__ hout, double *__restrict__ e_cheap, int *hdr,
+          const uint8_t *__restrict__ mflags)
 {
     const int nb = a.nb3;
     const int c3n = uf3_c3_elems(a.ns, nb);
@@ -173,11 +174,17 @@ __global__ void __launch_bounds__(256)
         const int zi = sp_clamp(species[i], a.ns);
         const int c = cnt[i];
         const int *row = nbr + (size_t)i * cap;
+        // masked (S_c = {lambda < 1} plus the cheap buffer): a centre outside
+        // S_c has no cheap energy or gradients, partners outside are absent
+        auto in_sc = [&](int k) { return !(mflags[k] & 2) || (mflags[k] & 8); };
+        const bool centre = !mflags || in_sc(i);
         int jj[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int slot = lane + 64 * u;
             jj[u] = slot < c ? row[slot] : -1;
+            if (jj[u] >= 0 && (!centre || (mflags && !in_sc(jj[u]))))
+                jj[u] = -1;  // the slot's gradient is written as zero
         }
         double dd[U][3], rr2[U];
 #pragma unroll
@@ -387,7 +394,8 @@ __global__ void __launch_bounds__(256)
 
 template <typename T>
 static void uf3_t(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L, const Box &b,
-                  const double *pos, const int32_t *species, double *e_cheap, int side_blocks)
+                  const double *pos, const int32_t *species, double *e_cheap, int side_blocks,
+                  const uint8_t *mask_flags)
 {
     const DevModel &m = c.m;
     Uf3Args<T> a;
@@ -425,7 +433,7 @@ static void uf3_t(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L, cons
 #define MLMIX_UF3_W(U, LOOP)                                                                     \
     k_uf3<T, U, LOOP><<<nblk, 256, sm, s>>>(pos, L.n, b, species, L.cap, at<int>(ws, L.nbr),    \
                                                 at<int>(ws, L.cnt), a, at<T>(ws, L.h), e_cheap,     \
-                                                at<int>(ws, L.hdr))
+                                                at<int>(ws, L.hdr), mask_flags)
 #define MLMIX_UF3(U)                                                                             \
     if (nblk < (unsigned)((L.n + wpb - 1) / wpb))                                                 \
         MLMIX_UF3_W(U, true);                                                                     \
@@ -442,14 +450,15 @@ static void uf3_t(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L, cons
 }
 
 void launch_uf3(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L, const Box &b,
-                const double *pos, const int32_t *species, double *e_cheap, int side_blocks)
+                const double *pos, const int32_t *species, double *e_cheap, int side_blocks,
+                const uint8_t *mask_flags)
 {
     if (L.n == 0)
         return;
     if (c.prec == MLMIX_FP64)
-        uf3_t<double>(s, c, ws, L, b, pos, species, e_cheap, side_blocks);
+        uf3_t<double>(s, c, ws, L, b, pos, species, e_cheap, side_blocks, mask_flags);
     else
-        uf3_t<float>(s, c, ws, L, b, pos, species, e_cheap, side_blocks);
+        uf3_t<float>(s, c, ws, L, b, pos, species, e_cheap, side_blocks, mask_flags);
 }
 
 }  // namespace mlmix

@@ -3,7 +3,8 @@ the results to numpy in the oracle's (N, 3) layout."""
 import numpy as np
 
 
-def run_gpu(w, mode=0, precision=None, cap=128, force_rebuild=True, split=True, system=None):
+def run_gpu(w, mode=0, precision=None, cap=128, force_rebuild=True, split=True, system=None,
+            cheap_masked=False):
     import torch
     from paper_2502_19081_amd import core
     prec = precision or w.get("precision", "fp64")
@@ -15,7 +16,7 @@ def run_gpu(w, mode=0, precision=None, cap=128, force_rebuild=True, split=True, 
     else:
         sy, pos, sp = system
     out = sy.compute(pos, sp, r_buffer=w["r_buffer"], mode=mode, force_rebuild=force_rebuild,
-                     split=split)
+                     split=split, cheap_masked=cheap_masked)
     bits, req, rc = sy.status(raise_on_error=False)
     torch.cuda.synchronize()
     assert rc == 0, f"device status {bits} (required cap {req})"

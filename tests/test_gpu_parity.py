@@ -16,10 +16,11 @@ pytestmark = pytest.mark.gpu
 MODES = {"mixed": O.MODE_MIXED, "all_expensive": O.MODE_ALL_EXPENSIVE, "all_cheap": O.MODE_ALL_CHEAP}
 
 
-def _check(w, mode, precision, ref=None, f_tol=None):
-    print(f"case {w['name']} seed={w['seed']} n={len(w['pos'])} mode={mode} prec={precision}", flush=True)
-    ref = ref or O.mixed(w, MODES[mode])
-    g = run_gpu(w, MODES[mode], precision=precision)
+def _check(w, mode, precision, ref=None, f_tol=None, cheap_masked=False):
+    print(f"case {w['name']} seed={w['seed']} n={len(w['pos'])} mode={mode} prec={precision}"
+          f"{' cheap masked' if cheap_masked else ''}", flush=True)
+    ref = ref or O.mixed(w, MODES[mode], cheap_masked=cheap_masked)
+    g = run_gpu(w, MODES[mode], precision=precision, cheap_masked=cheap_masked)
     assert_neighbors_equal(g, ref)
     assert np.array_equal(g["lam"], ref["lam"])
     # bit 7 is the seed marker the caller passes in (kept by the library)
@@ -173,4 +174,20 @@ def test_c2_seeded_region_fp32():
     w["regions"] = [W.seeded(3.0, 5.0, blend=1)]
     g, ref = _check(w, "mixed", "fp32")
     assert 0 < len(ref["M"]) < len(w["pos"]) and np.array_equal(g["lam"], ref["lam"])
+
+
+def test_tiny_cheap_masked_fp64():
+    # Algorithm 4 for the cheap potential too: S_c = {lambda < 1} plus its
+    # buffer (flags bit3); the core's central atom lies outside S_c
+    w = W.tiny(seed=17, cells=6)
+    w["regions"] = [W.sphere(w["L"] / 2.0, 3.5, 1.5)]
+    w["r_buffer"] = 3.0
+    g, ref = _check(w, "mixed", "fp64", cheap_masked=True)
+    assert ((ref["flags"] & 8) != 0).any()
+    in_Sc = (ref["lam"] < 1.0) | ((ref["flags"] & 8) != 0)
+    assert not in_Sc.all() and np.all(g["e_cheap"][~in_Sc] == 0.0)
+
+
+def test_c2_cheap_masked_fp32():
+    _check(W.c2(), "mixed", "fp32", cheap_masked=True)
 

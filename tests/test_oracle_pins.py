@@ -492,7 +492,9 @@ def _fd_forces(w, which, idx, h=1e-5, in_S=None):
                     if in_S is not None:
                         e = e[in_S]
                 else:
-                    e, _ = O.uf3(m, p, w["species"], w["L"], w["periodic"], offs, nbr)
+                    e, _ = O.uf3(m, p, w["species"], w["L"], w["periodic"], offs, nbr, in_S=in_S)
+                    if in_S is not None:
+                        e = e[in_S]
                 Es.append(e.sum())
             row.append(-(Es[0] - Es[1]) / (2 * h))
         res.append(row)
@@ -508,6 +510,69 @@ def test_forces_are_minus_gradient(which):
     fd = _fd_forces(w, which, idx)
     scale = np.abs(F).max()
     np.testing.assert_allclose(F[idx], fd, atol=2e-8 * max(scale, 1.0))
+
+
+def _masked_cheap_case():
+    # 6^3 cells, a 3.5 A core (15 atoms) and a 3 A buffer: the first and
+    # second shells of the core join the cheap buffer, the central atom lies
+    # deeper and leaves the cheap subsystem
+    w = W.tiny(seed=17, cells=6)
+    w["regions"] = [W.sphere(w["L"] / 2.0, 3.5, 1.5)]
+    w["r_buffer"] = 3.0
+    return w
+
+
+def test_cheap_buffer_brute_force_and_subset():
+    # the cheap potential's buffer: lambda == 1 atoms strictly within r_buffer
+    # of a lambda < 1 atom (all pairs); its subsystem is a proper subset here
+    w = _masked_cheap_case()
+    out = O.mixed(w, cheap_masked=True)
+    lam, fl = out["lam"], out["flags"]
+    pos = w["pos"]
+    d = pos[:, None, :] - pos[None, :, :]
+    for k in range(3):
+        if w["periodic"][k]:
+            d[..., k] -= w["L"][k] * np.round(d[..., k] / w["L"][k])
+    r2 = (d ** 2).sum(-1)
+    np.fill_diagonal(r2, np.inf)
+    core = lam == 1.0
+    ref = core & np.any((r2 < w["r_buffer"] ** 2) & ~core[None, :], axis=1)
+    assert np.array_equal((fl & 8) != 0, ref)
+    assert ref.any()
+    in_Sc = ~core | ref
+    assert 0 < in_Sc.sum() < len(pos)
+    assert np.all(out["e_cheap"][~in_Sc] == 0.0) and np.all(out["f_cheap"][~in_Sc] == 0.0)
+
+
+def test_masked_cheap_forces_gradient_and_locality():
+    # Algorithm 4 for the cheap potential: with S_c frozen, F_cheap on S_c is
+    # -grad of sum_{i in S_c} E_i^{S_c}; an atom whose 2 rc ball lies inside
+    # S_c gets exactly the unmasked cheap force; no core at all = unmasked
+    w = _masked_cheap_case()
+    out = O.mixed(w, cheap_masked=True)
+    in_Sc = (out["lam"] < 1.0) | ((out["flags"] & 8) != 0)
+    idx = list(np.nonzero(in_Sc)[0][[0, 7, -1]])
+    fd = _fd_forces(w, "cheap", idx, in_S=in_Sc)
+    np.testing.assert_allclose(out["f_cheap"][idx], fd,
+                               atol=2e-8 * max(np.abs(out["f_cheap"]).max(), 1.0))
+    full = O.mixed(w)
+    pos = w["pos"]
+    rc = w["model"]["uf3"]["rcut2"]
+    out_idx = np.nonzero(~in_Sc)[0]
+    far = []
+    for i in range(len(pos)):
+        d = pos[out_idx] - pos[i]
+        for k in range(3):
+            if w["periodic"][k]:
+                d[:, k] -= w["L"][k] * np.round(d[:, k] / w["L"][k])
+        if len(out_idx) == 0 or np.linalg.norm(d, axis=1).min() >= 2.0 * rc:
+            far.append(i)
+    assert len(far) > 0
+    assert np.array_equal(out["f_cheap"][far], full["f_cheap"][far])
+    w0 = W.tiny(seed=17)
+    w0["regions"] = [W.sphere(w0["L"] / 2.0, 0.0, 3.0)]  # blend only: lambda < 1 everywhere
+    a, b = O.mixed(w0, cheap_masked=True), O.mixed(w0)
+    assert np.array_equal(a["forces"], b["forces"]) and np.array_equal(a["e_cheap"], b["e_cheap"])
 
 
 def test_subsystem_forces_are_gradient_of_subsystem_energy():
