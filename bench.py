@@ -63,6 +63,9 @@ def parse():
     ap.add_argument("--cheap-masked", action="store_true",
                     help="the cheap potential on its own subsystem (lambda < 1 plus its "
                          "buffer) as Algorithm 4 masks each potential")
+    ap.add_argument("--langevin", action="store_true",
+                    help="Langevin thermostat (300 K, 2 ps) on the lambda == 0 atoms in every "
+                         "step; the step's normals are drawn on the device inside the timed region")
     ap.add_argument("--dominant-only", action="store_true",
                     help="stop after timing the dominant kernel (phases 1-2) and print its "
                          "average; for a kernel trace of the same launches")
@@ -188,6 +191,8 @@ def main():
         if "seeds" in w:
             sy.set_seeds(torch.from_numpy(w["seeds"].astype(np.uint8)))
         vel = torch.from_numpy(np.ascontiguousarray(vel0.T)).to(dev)
+        if args.langevin:
+            sy.set_langevin(300.0, 2000.0)
         sy.compute(pos, sp, r_buffer=w["r_buffer"], mode=mode, force_rebuild=True)
         return sy, pos, vel, sp
 
@@ -403,6 +408,8 @@ def main():
         "config": {"workload": WORKLOADS[cfg], "n_atoms": n, "mode": "mixed",
                    "regions": "seeded (6 A core, 2 A blend)" if args.seeded else "geometric",
                    "cheap": "masked to its subsystem" if args.cheap_masked else "every atom",
+                   "thermostat": ("Langevin 300 K, 2 ps, lambda == 0 atoms" if args.langevin
+                                  else "none (NVE)"),
                    "precision": prec, "neighbour_rebuild": "every step", "n_S": nS, "n_lambda_pos": nM,
                    "launch": (f"{args.graph_steps} consecutive steps per captured HIP graph, "
                               "replayed" if args.steps % args.graph_steps == 0 and args.graph_steps > 1

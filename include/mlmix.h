@@ -253,6 +253,27 @@ int mlmix_vv_step(mlmix_ctx *ctx, void *stream, void *ws, int32_t n_atoms, doubl
                   double *e_cheap, double *lambda, uint8_t *flags, int32_t *n_expensive,
                   double *energies);
 
+/* Langevin thermostat on the cheap region for mlmix_vv_step on workspace ws
+ * (Methods, "Si stretched bond" and "Diffusion coefficients": a weak
+ * thermostat, time constant 2 ps, acting only where the cheap potential
+ * alone gives the force, to hold the temperature against the drift that
+ * force mixing causes, Discussion). Every atom with lambda == 0 at the step's
+ * force call gets, added to its blended force,
+ *     F_L = -m v / (kappa tau) + sqrt(2 m kB T / (kappa tau dt)) xi,
+ * with v its half-step velocity (after the opening half kick), kB =
+ * 8.617333262e-5 eV/K, kappa as below, and xi the three standard normals of
+ * that atom in xi [dev] double[3][n] (caller-owned; the step reads it, so the
+ * caller refills it before each step, also under graph capture). F_L is part
+ * of `forces` on return, and the closing half kick and the next step's
+ * opening kick use it. temperature_K >= 0; damping_fs = tau in fs, <= 0
+ * turns the thermostat off (xi may then be NULL). The setting lives with the
+ * workspace until changed; mlmix_workspace_init with another n_atoms drops
+ * it. mlmix_compute ignores it. Errors: MLMIX_E_ARG (NULL ctx/ws, xi NULL
+ * with tau > 0, negative or non-finite T, n_atoms not the workspace's),
+ * MLMIX_E_STATE (workspace not initialised). */
+int mlmix_set_langevin(mlmix_ctx *ctx, void *ws, int32_t n_atoms, double temperature_K,
+                       double damping_fs, const double *xi);
+
 /* FP64 sums (sum e_exp, sum e_cheap, kinetic energy from vel and mass; vel
  * and mass may be NULL, kinetic is then 0) into energies [dev] double[3]. */
 int mlmix_energy_reduce(mlmix_ctx *ctx, void *stream, void *ws, int32_t n_atoms,

@@ -305,9 +305,20 @@ def mixed(w, mode=MODE_MIXED, pos=None, target=None, method=1, cheap_masked=Fals
                 f_exp=f_exp, e_cheap=e_ch, f_cheap=f_ch, forces=forces)
 
 
-def velocity_verlet(w, pos, vel, dt, nsteps, mode=MODE_MIXED, callback=None, cheap_masked=False):
-    """Velocity Verlet: v += dt/2 kappa F/m; x += dt v; wrap; F(x); v += dt/2 kappa F/m."""
-    from gen.workloads import KAPPA
+def velocity_verlet(w, pos, vel, dt, nsteps, mode=MODE_MIXED, callback=None, cheap_masked=False,
+                    langevin=None):
+    """Velocity Verlet: v += dt/2 kappa F/m; x += dt v; wrap; F(x); v += dt/2 kappa F/m.
+
+    langevin = (T in K, tau in fs, xi) adds a Langevin thermostat on the cheap
+    region only (Methods, Si stretched bond and diffusion coefficients: a weak
+    thermostat applied where the cheap potential alone acts). After each force
+    evaluation an atom with lambda == 0 feels, besides its blended force, the
+    friction -m v / tau and a random force whose variance over one step dt
+    fixes the temperature, 2 m kB T / (tau dt) (both in mass-velocity units,
+    divided by kappa for eV/A); v is the half-step velocity at that moment.
+    xi[step] is an (n, 3) array of standard normals for the step's force call.
+    """
+    from gen.workloads import KAPPA, KB
     m = w["masses"][w["species"]][:, None]
     pos = _f64(pos).copy()
     vel = _f64(vel).copy()
@@ -322,6 +333,13 @@ def velocity_verlet(w, pos, vel, dt, nsteps, mode=MODE_MIXED, callback=None, che
                 pos[:, k] = pos[:, k] - Lk * np.floor(pos[:, k] / Lk)
         out = mixed(w, mode, pos=pos, cheap_masked=cheap_masked)
         F = out["forces"]
+        if langevin is not None:
+            T, tau, xi = langevin
+            cheap = (out["lam"] == 0.0)[:, None]
+            friction = -m * vel / (KAPPA * tau)
+            noise = np.sqrt(2.0 * m * KB * T / (KAPPA * tau * dt)) * np.asarray(xi[step], np.float64)
+            F = np.where(cheap, F + (friction + noise), F)
+            out = dict(out, forces=F)
         vel = vel + 0.5 * dt * KAPPA * F / m
         if callback:
             callback(step, pos, vel, out)

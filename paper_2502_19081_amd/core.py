@@ -128,6 +128,9 @@ class System:
         self.regions = pack_regions([], device)
         self.n_regions = 0
         self.generation = 0  # bumped by every evaluation on this workspace
+        self.langevin = None
+        self.xi = None
+        self.xi_gen = None
 
     def set_regions(self, regions):
         self.regions = pack_regions(regions, self.device)
@@ -148,6 +151,20 @@ class System:
             return 0
         self.flags.copy_(self.seed_bits)
         return B.SEEDED
+
+    def set_langevin(self, temperature, damping_fs, generator=None):
+        """Langevin thermostat on the atoms with lambda == 0 inside vv_step
+        (temperature in K, damping time in fs; damping_fs <= 0 turns it off).
+        The standard normals live in self.xi (3, n): vv_step refills them from
+        `generator` before each step unless it is given xi itself."""
+        on = damping_fs > 0.0
+        if on and getattr(self, "xi", None) is None:
+            self.xi = torch.zeros(3, self.n, dtype=torch.float64, device=self.device)
+        self.langevin = (float(temperature), float(damping_fs)) if on else None
+        self.xi_gen = generator
+        B.check(B.lib().mlmix_set_langevin(self.model.handle, _p(self.ws), self.n,
+                                           float(temperature), float(damping_fs),
+                                           _p(self.xi) if on else None))
 
     def compute(self, pos, species, r_buffer=0.0, mode=B.MODE_MIXED, force_rebuild=False,
                 split=False, energy_only=False, single_stream=False, cheap_masked=False):
@@ -184,8 +201,16 @@ class System:
         return grad_pos
 
     def vv_step(self, pos, vel, mass, species, dt, r_buffer=0.0, mode=B.MODE_MIXED,
-                force_rebuild=False, energies=True, single_stream=False, cheap_masked=False):
+                force_rebuild=False, energies=True, single_stream=False, cheap_masked=False,
+                xi=None):
+        """One velocity-Verlet step. With a thermostat set, xi ((3, n) float64)
+        gives this step's normals; otherwise they are drawn here."""
         self.generation += 1
+        if getattr(self, "langevin", None) is not None:
+            if xi is not None:
+                self.xi.copy_(xi)
+            else:
+                self.xi.normal_(generator=self.xi_gen)
         flags = mode | (B.FORCE_REBUILD if force_rebuild else 0) | (B.SINGLE_STREAM if single_stream else 0)
         flags |= self._seed_mode() | (B.CHEAP_MASKED if cheap_masked else 0)
         B.check(B.lib().mlmix_vv_step(self.model.handle, _stream(), _p(self.ws), self.n, _p(pos),

@@ -28,10 +28,17 @@ struct SideStream {
     hipEvent_t fork = nullptr, join = nullptr;
 };
 
+// Langevin thermostat of one workspace (off when tau <= 0).
+struct LangevinSet {
+    double temperature = 0.0, tau = 0.0;
+    const double *xi = nullptr;
+};
+
 struct mlmix_ctx {
     Ctx c;
     std::mutex mu;
     std::unordered_map<void *, WsLayout> ws;
+    std::unordered_map<void *, LangevinSet> lang;
     std::unordered_map<void *, SideStream> side;
     uint32_t prof_mask = 0;
     double flops[6] = {0, 0, 0, 0, 0, 0};
@@ -962,6 +969,9 @@ extern "C" int mlmix_workspace_init(mlmix_ctx *ctx, void *stream, void *ws, size
     k_zero_i32<<<(L.grid.ncell + 255) / 256, 256, 0, s>>>(at<int>(ws, L.cell_count), L.grid.ncell);
     HIP_OK(hipGetLastError());
     std::lock_guard<std::mutex> g(ctx->mu);
+    auto prev = ctx->ws.find(ws);
+    if (prev == ctx->ws.end() || prev->second.n != L.n)
+        ctx->lang.erase(ws);  // the noise buffer was sized for another system
     ctx->ws[ws] = L;
     return MLMIX_OK;
 }
@@ -993,7 +1003,7 @@ static int compute_impl(mlmix_ctx *ctx, hipStream_t s, void *ws, const WsLayout 
                         int32_t n_regions, double r_buffer, uint32_t mode, double *forces,
                         double *e_exp, double *e_cheap, double *lambda, uint8_t *flags,
                         int32_t *n_expensive, double *f_exp, double *f_cheap,
-                        const KickArgs *kick = nullptr)
+                        const KickArgs *kick = nullptr, const LangevinArgs *lang = nullptr)
 {
     const Ctx &c = ctx->c;
     int m = (int)(mode & 0xff);
@@ -1141,7 +1151,7 @@ static int compute_impl(mlmix_ctx *ctx, hipStream_t s, void *ws, const WsLayout 
     {
         StageTimer t(ctx, s, ST_GATHER);
         launch_gather_blend(s, c, ws, L, m != MLMIX_MODE_ALL_CHEAP, m != MLMIX_MODE_ALL_EXPENSIVE,
-                            lambda, forces, e_exp, f_exp, f_cheap, 1.0, kick);
+                            lambda, forces, e_exp, f_exp, f_cheap, 1.0, kick, lang);
     }
     HIP_OK(hipGetLastError());
     return MLMIX_OK;
@@ -1233,6 +1243,28 @@ extern "C" int mlmix_energy_reduce(mlmix_ctx *ctx, void *stream, void *ws, int32
     return MLMIX_OK;
 }
 
+extern "C" int mlmix_set_langevin(mlmix_ctx *ctx, void *ws, int32_t n_atoms,
+                                  double temperature_K, double damping_fs, const double *xi)
+{
+    if (!ctx || !ws)
+        return fail(MLMIX_E_ARG, "NULL argument");
+    if (!(temperature_K >= 0.0) || !std::isfinite(temperature_K) || !std::isfinite(damping_fs))
+        return fail(MLMIX_E_ARG, "temperature must be finite and non-negative, damping finite");
+    if (damping_fs > 0.0 && !xi)
+        return fail(MLMIX_E_ARG, "a thermostat needs the noise buffer");
+    std::lock_guard<std::mutex> g(ctx->mu);
+    auto it = ctx->ws.find(ws);
+    if (it == ctx->ws.end())
+        return fail(MLMIX_E_STATE, "workspace was not initialised with mlmix_workspace_init");
+    if (it->second.n != n_atoms)
+        return fail(MLMIX_E_ARG, "n_atoms differs from the workspace's");
+    if (damping_fs > 0.0)
+        ctx->lang[ws] = LangevinSet{temperature_K, damping_fs, xi};
+    else
+        ctx->lang.erase(ws);
+    return MLMIX_OK;
+}
+
 extern "C" int mlmix_vv_step(mlmix_ctx *ctx, void *stream, void *ws, int32_t n_atoms, double *pos,
                              double *vel, const double *mass, const int32_t *species, double dt,
                              const mlmix_box *box, const mlmix_region *regions, int32_t n_regions,
@@ -1263,9 +1295,22 @@ extern "C" int mlmix_vv_step(mlmix_ctx *ctx, void *stream, void *ws, int32_t n_a
     // small systems: closing half kick and energy partials inside the gather
     const bool fused = energies && L.n > 0 && L.n <= kGatherKickMax;
     KickArgs ka{vel, mass, dt, e_cheap, nullptr, energies};
+    LangevinSet ls;
+    {
+        std::lock_guard<std::mutex> g(ctx->mu);
+        auto it = ctx->lang.find(ws);
+        if (it != ctx->lang.end())
+            ls = it->second;
+    }
+    // friction and noise use the half-step velocity the opening kick just made
+    LangevinArgs la{vel, mass, ls.xi, 0.0, 0.0};
+    if (ls.tau > 0.0) {
+        la.c_fric = 1.0 / (kKappa * ls.tau);
+        la.c_rand = 2.0 * kBoltzmann * ls.temperature / (kKappa * ls.tau * dt);
+    }
     rc = compute_impl(ctx, s, ws, L, b, pos, species, regions, n_regions, r_buffer, mode, forces,
                       e_exp, e_cheap, lambda, flags, n_expensive, nullptr, nullptr,
-                      fused ? &ka : nullptr);
+                      fused ? &ka : nullptr, ls.tau > 0.0 ? &la : nullptr);
     if (rc)
         return rc;
     if (!fused && energies) {

@@ -199,10 +199,23 @@ struct KickArgs {
     double *energies;  // final sums
 };
 constexpr int kGatherKickMax = 65536;
+
+constexpr double kKappa = 9.648533212e-3;     // eV/A/amu in A/fs^2
+constexpr double kBoltzmann = 8.617333262e-5;  // eV/K
+
+// Langevin terms added to the blended force of atoms with lambda == 0 inside
+// an MD step: F += -(m c_fric) v + sqrt(m c_rand) xi.
+struct LangevinArgs {
+    const double *vel;   // velocities at the force call (after the opening half kick)
+    const double *mass;
+    const double *xi;    // [3][n] standard normals, refilled by the caller per step
+    double c_fric;       // 1 / (kappa tau)
+    double c_rand;       // 2 kB T / (kappa tau dt)
+};
 void launch_gather_blend(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L, int use_exp,
                          int use_cheap, const double *lambda, double *forces, double *e_exp,
                          double *f_exp, double *f_cheap, double sign,
-                         const KickArgs *kick = nullptr);
+                         const KickArgs *kick = nullptr, const LangevinArgs *lang = nullptr);
 void launch_fill_f64(hipStream_t s, double *p, double v, size_t n);
 void launch_vv_kick_sums(hipStream_t s, void *ws, const WsLayout &L, double *vel,
                          const double *mass, const double *forces, double dt, const double *e_exp,

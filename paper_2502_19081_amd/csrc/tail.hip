@@ -19,8 +19,6 @@ __device__ __forceinline__ double wave_sum_d(double v)
     return v;
 }
 
-constexpr double kKappa = 9.648533212e-3;
-
 // Sum of nb [3]-partials by one 256-thread block in a fixed order (thread
 // stride, wave butterfly, then the four waves pairwise); out[2] (kinetic) is
 // converted to eV.
@@ -52,7 +50,7 @@ __global__ void __launch_bounds__(256)
                    const T *__restrict__ g, const T *__restrict__ h, int use_exp, int use_cheap,
                    const double *__restrict__ lambda, double *__restrict__ forces,
                    double *__restrict__ e_exp, double *__restrict__ f_exp,
-                   double *__restrict__ f_cheap, double sign, KickArgs ka)
+                   double *__restrict__ f_cheap, double sign, KickArgs ka, LangevinArgs la)
 {
     const int w = threadIdx.x >> 6;
     const int i = blockIdx.x * 4 + w;
@@ -95,8 +93,15 @@ __global__ void __launch_bounds__(256)
         if (lane == 0) {
             double lam = lambda ? lambda[i] : 1.0;
             double om = 1.0 - lam;
-            const double F[3] = {sign * (lam * fe0 + om * fc0), sign * (lam * fe1 + om * fc1),
-                                 sign * (lam * fe2 + om * fc2)};
+            double F[3] = {sign * (lam * fe0 + om * fc0), sign * (lam * fe1 + om * fc1),
+                           sign * (lam * fe2 + om * fc2)};
+            if (la.xi && lam == 0.0) {
+                // Langevin friction and noise on the cheap region
+                const double m = la.mass[i];
+                const double g = -m * la.c_fric, sg = sqrt(m * la.c_rand);
+                for (int q = 0; q < 3; ++q)
+                    F[q] = F[q] + (g * la.vel[q * n + i] + sg * la.xi[q * n + i]);
+            }
             if (forces) {
                 forces[i] = F[0];
                 forces[n + i] = F[1];
@@ -151,12 +156,16 @@ __global__ void __launch_bounds__(256) k_reduce_final(const double *__restrict__
 
 void launch_gather_blend(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L, int use_exp,
                          int use_cheap, const double *lambda, double *forces, double *e_exp,
-                         double *f_exp, double *f_cheap, double sign, const KickArgs *kick)
+                         double *f_exp, double *f_cheap, double sign, const KickArgs *kick,
+                         const LangevinArgs *lang)
 {
     int n = L.n;
     if (n == 0)
         return;
     unsigned nb = (n + 3) / 4;
+    LangevinArgs la{};
+    if (lang)
+        la = *lang;
     KickArgs ka{};
     if (kick) {
         ka = *kick;
@@ -166,7 +175,7 @@ void launch_gather_blend(hipStream_t s, const Ctx &c, void *ws, const WsLayout &
     k_gather_blend<T, K><<<nb, 256, 0, s>>>(n, L.cap, at<int>(ws, L.nbr), at<int>(ws, L.cnt),      \
                                            at<int>(ws, L.rev), at<int>(ws, L.S_local),             \
                                            at<T>(ws, L.g), at<T>(ws, L.h), use_exp, use_cheap,     \
-                                           lambda, forces, e_exp, f_exp, f_cheap, sign, ka)
+                                           lambda, forces, e_exp, f_exp, f_cheap, sign, ka, la)
     if (c.prec == MLMIX_FP64) {
         if (kick)
             MLMIX_GATHER(double, true);

@@ -125,3 +125,54 @@ def test_vv_trajectory_seeded_matches_oracle():
     assert np.abs(sy.lam.cpu().numpy() - out["lam"]).max() < 1e-9
     assert np.array_equal(sy.flags.cpu().numpy() & 0x7F, out["flags"])
 
+
+
+def test_vv_langevin_cheap_region_matches_oracle():
+    # thermostat on the lambda == 0 atoms, same normals on both sides
+    import torch
+    w = W.tiny(seed=35, n_species=2, sigma=0.05)
+    w["vel"] = w["vel"] * 3.0
+    n = len(w["pos"])
+    T, tau, steps = 600.0, 20.0, 10
+    xi = np.random.default_rng(11).normal(size=(steps, n, 3))
+    print("case tiny VV parity with the cheap-region Langevin thermostat, 10 steps FP64",
+          flush=True)
+    _, sy, pos, vel, mass, sp = _setup(w, "fp64")
+    sy.set_langevin(T, tau)
+    sy.compute(pos, sp, r_buffer=w["r_buffer"], force_rebuild=True)
+    for k in range(steps):
+        sy.vv_step(pos, vel, mass, sp, 1.0, r_buffer=w["r_buffer"],
+                   xi=torch.from_numpy(np.ascontiguousarray(xi[k].T)).cuda())
+    sy.status()
+    p_ref, v_ref, out = O.velocity_verlet(w, w["pos"], w["vel"], 1.0, steps,
+                                          langevin=(T, tau, xi))
+    assert 0 < int((out["lam"] == 0.0).sum()) < n
+    d = pos.cpu().numpy().T - p_ref
+    d -= w["L"] * np.round(d / w["L"])
+    assert np.abs(d).max() < 1e-10
+    assert np.abs(vel.cpu().numpy().T - v_ref).max() < 1e-10
+    assert np.abs(sy.forces.cpu().numpy().T - out["forces"]).max() < 1e-9
+
+
+@pytest.mark.parametrize("case", ["off", "all_expensive"])
+def test_langevin_without_cheap_atoms_is_nve(case):
+    # a thermostat turned off again, or one in all-expensive mode (lambda = 1
+    # everywhere), leaves the NVE trajectory bit for bit
+    import torch
+    w = W.tiny(seed=37, n_species=2, sigma=0.05)
+    mode = 1 if case == "all_expensive" else 0
+    print(f"case tiny VV with thermostat {case}, 5 steps FP64", flush=True)
+    res = []
+    for thermo in (False, True):
+        _, sy, pos, vel, mass, sp = _setup(w, "fp64")
+        if thermo:
+            sy.set_langevin(300.0, 10.0)
+            if case == "off":
+                sy.set_langevin(300.0, 0.0)
+        sy.compute(pos, sp, r_buffer=w["r_buffer"], mode=mode, force_rebuild=True)
+        for _ in range(5):
+            sy.vv_step(pos, vel, mass, sp, 1.0, r_buffer=w["r_buffer"], mode=mode)
+        sy.status()
+        res.append((pos.cpu().numpy(), vel.cpu().numpy()))
+    assert np.array_equal(res[0][0], res[1][0])
+    assert np.array_equal(res[0][1], res[1][1])

@@ -730,3 +730,79 @@ def test_vv_time_reversal_and_dt_squared_drift():
     d1 = drift(4.0, 10)
     d2 = drift(2.0, 20)
     assert 2.5 < d1 / d2 < 6.0   # energy error scales as dt^2 (ratio 4)
+
+
+# ---------------------------------------------------------- Langevin thermostat
+
+def _free_gas(seed=41, n_side=4, spacing=16.0):
+    """W and He atoms on a simple cubic lattice whose spacing is several
+    cutoffs: no potential acts, so only the thermostat changes velocities."""
+    w = W.tiny(seed=seed, n_species=2)
+    g = (np.arange(n_side) + 0.5) * spacing
+    pos = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+    n = len(pos)
+    species = (np.arange(n) % 2).astype(np.int32)
+    vel = W.maxwell(np.random.default_rng(seed), species, 300.0)
+    return dict(w, pos=pos, L=np.full(3, n_side * spacing), species=species, vel=vel)
+
+
+def test_langevin_friction_closed_form():
+    # T = 0: a free atom's velocity decays geometrically. The opening kick of
+    # step k carries the friction of step k-1, so the half-step velocity is
+    # v0 (1 - dt/tau)^(k-1) and the closing kick takes another dt/(2 tau).
+    w = _free_gas()
+    dt, tau, k = 0.5, 7.0, 12
+    xi = np.zeros((k, len(w["pos"]), 3))
+    p, v, out = O.velocity_verlet(w, w["pos"], w["vel"], dt, k, mode=O.MODE_ALL_CHEAP,
+                                  langevin=(0.0, tau, xi))
+    assert np.all(out["lam"] == 0.0) and np.abs(out["e_cheap"]).max() == 0.0
+    a = 1.0 - dt / tau
+    half = [w["vel"] * a ** j for j in range(k)]
+    assert np.allclose(v, half[-1] * (1.0 - 0.5 * dt / tau), rtol=1e-13, atol=0.0)
+    x = w["pos"] + dt * np.sum(half, axis=0)
+    d = p - x
+    d -= w["L"] * np.round(d / w["L"])
+    assert np.abs(d).max() < 1e-12
+
+
+def test_langevin_equipartition_and_mass_scaling():
+    # With no potential the scheme is a linear recurrence whose stationary
+    # full-step velocity variance is exactly kB T / m (times kappa): for
+    # h = dt/(2 tau) the half-step variance is s2/(1-h), s2 = kappa kB T/m, and
+    # the closing kick maps it to s2 (1-h) + s2 h. Both species (masses 184
+    # and 4) must sit at the bath temperature, started from 300 K.
+    w = _free_gas(seed=43)
+    dt, tau, T, k, burn = 1.0, 10.0, 900.0, 2400, 100
+    n = len(w["pos"])
+    xi = np.random.default_rng(7).normal(size=(k, n, 3))
+    m = w["masses"][w["species"]]
+    acc = np.zeros(n)
+    cnt = [0]
+
+    def cb(step, pos, vel, out):
+        if step >= burn:
+            acc[:] += (vel ** 2).sum(1)
+            cnt[0] += 1
+    O.velocity_verlet(w, w["pos"], w["vel"], dt, k, mode=O.MODE_ALL_CHEAP,
+                      langevin=(T, tau, xi), callback=cb)
+    t_est = acc / cnt[0] * m / (3.0 * W.KAPPA * W.KB)
+    for s in (0, 1):
+        ratio = t_est[w["species"] == s].mean() / T
+        assert abs(ratio - 1.0) < 0.05, (s, ratio)
+
+
+def test_langevin_acts_only_where_lambda_is_zero():
+    # one mixed step: the opening kick and the drift use the initial forces,
+    # so positions match NVE everywhere, velocities match bit for bit where
+    # lambda > 0 at the force call, and differ on every lambda == 0 atom
+    w = W.tiny(seed=47, n_species=2, sigma=0.05)
+    n = len(w["pos"])
+    xi = np.random.default_rng(3).normal(size=(1, n, 3))
+    p0, v0, out0 = O.velocity_verlet(w, w["pos"], w["vel"], 1.0, 1)
+    p1, v1, out1 = O.velocity_verlet(w, w["pos"], w["vel"], 1.0, 1,
+                                     langevin=(300.0, 50.0, xi))
+    assert np.array_equal(p0, p1)
+    cheap = out0["lam"] == 0.0
+    assert 0 < cheap.sum() < n
+    assert np.array_equal(v0[~cheap], v1[~cheap])
+    assert np.all(np.abs(v0[cheap] - v1[cheap]).max(1) > 0.0)
