@@ -63,3 +63,26 @@ def wrap(pos, L, periodic):
             # floor can leave exactly L after rounding; fold it back to 0
             out[:, d] = np.where(out[:, d] >= L[d], out[:, d] - L[d], out[:, d])
     return out
+
+
+def oriented_bcc(x_dir, y_dir, z_dir, periods, a=A_W):
+    """Orthorhombic periodic bcc cell whose edges run along the given cubic
+    directions (mutually orthogonal Miller vectors) with the given edge
+    lengths in units of a (each a lattice period along its direction).
+    Atoms sorted by (z, y, x)."""
+    R = np.stack([np.asarray(d, np.float64) / np.linalg.norm(d) for d in (x_dir, y_dir, z_dir)])
+    assert np.allclose(R @ R.T, np.eye(3))
+    edges = np.asarray(periods, np.float64) * a
+    m = int(np.ceil(np.linalg.norm(edges) / a)) + 1
+    rng = np.arange(-m, m + 1)
+    ii, jj, kk = np.meshgrid(rng, rng, rng, indexing="ij")
+    corners = np.stack([ii.ravel(), jj.ravel(), kk.ravel()], axis=1).astype(np.float64)
+    pts = np.concatenate([corners, corners + 0.5]) * a
+    rot = pts @ R.T
+    frac = rot / edges
+    keep = np.all((frac > -1e-9) & (frac < 1.0 - 1e-9), axis=1)
+    cell = np.where(np.abs(rot[keep]) < 1e-9, 0.0, rot[keep])
+    key = np.lexsort((np.round(cell[:, 0], 6), np.round(cell[:, 1], 6), np.round(cell[:, 2], 6)))
+    cell = cell[key]
+    assert len(cell) == int(round(2.0 * np.prod(edges) / a ** 3)), len(cell)
+    return cell, edges
