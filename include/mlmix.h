@@ -297,6 +297,70 @@ int mlmix_get_neighbors(mlmix_ctx *ctx, void *stream, void *ws, int32_t n_atoms,
 int mlmix_get_index_sets(mlmix_ctx *ctx, void *stream, void *ws, int32_t n_atoms,
                          int32_t *S_out, int32_t *M_out);
 
+/* ---------------------------------------------------------------------
+ * Constrained linear fitting of the cheap potential (Methods, "Constrained
+ * potential fitting"). The cheap potential is linear in its free spline
+ * coefficients u, so the energies and forces of a configuration are A u.
+ * Free parameters, in column order: for each species pair za <= zb the
+ * 2-body coefficients n < n_knots2 - 1 (the last three of n_knots2 + 2
+ * vanish at the cutoff); then for each centre species z, legs p <= q <
+ * n_knots3 - 1 and third side s < n_knots3 + 2 the 3-body coefficient
+ * c3[z][p][q][s] = c3[z][q][p][s]. The fit is FP64 in every precision mode.
+ * Soft data is matched in the least-squares sense while the hard data must
+ * satisfy ||A_H u - y_H||^2 <= alpha; at a fixed multiplier lam the augmented
+ * Lagrangian's minimiser solves (G_S + lam G_H + ridge I) u = b_S + lam b_H
+ * with G = A^T W A, b = A^T W y (W = diag(w); G_H, b_H with unit weights). */
+
+/* Number of free parameters of the context's cheap potential. */
+int mlmix_fit_n_params(mlmix_ctx *ctx, int32_t *n_params);
+
+/* Design rows of one configuration: rows [dev] double[(1 + 3 n) x ld],
+ * row-major; row 0 = d(total energy)/du, row 1 + q n + i = d(F_i,q)/du.
+ * Reads the neighbour rows of the last mlmix_compute / mlmix_vv_step on ws,
+ * which must have been given these positions (the call builds no list), and
+ * uses the workspace's pair-gradient scratch for per-atom energy rows (so
+ * call mlmix_compute again before mlmix_backward). Errors: MLMIX_E_ARG (NULL,
+ * ld < n_params, more than 120 parameters, n_atoms not the workspace's),
+ * MLMIX_E_WORKSPACE (nbr_cap too small to hold n x n_params doubles in that
+ * scratch), MLMIX_E_BOX. More than 64 neighbours inside the 3-body cutoff of
+ * one atom sets MLMIX_STATUS_TRIPLET_OVERFLOW (read with mlmix_status). */
+int mlmix_fit_design(mlmix_ctx *ctx, void *stream, void *ws, int32_t n_atoms, const double *pos,
+                     const int32_t *species, const mlmix_box *box, double *rows, int32_t ld);
+
+/* Bytes of device scratch that mlmix_fit_gram (for n_rows rows) and
+ * mlmix_fit_constrained need. */
+int mlmix_fit_work_size(int64_t n_rows, int32_t n_params, size_t *bytes);
+
+/* G += A^T diag(w) A and b += A^T diag(w) y for rows [dev] double[n_rows x
+ * ld] (row-major), y, w [dev] double[n_rows] (w NULL = unit weights, y NULL
+ * = zero). G [dev] double[n_params x n_params] (both triangles written) and
+ * b [dev] double[n_params] are accumulated, so the caller zeroes them first
+ * and may stream the rows in several calls. work [dev] holds at least
+ * mlmix_fit_work_size(n_rows, n_params) bytes. Fixed summation order. */
+int mlmix_fit_gram(mlmix_ctx *ctx, void *stream, const double *rows, int64_t n_rows,
+                   int32_t n_params, int32_t ld, const double *y, const double *w, double *G,
+                   double *b, void *work, size_t work_bytes);
+
+/* The lambda search, all on the device: solve at lambda0, 10 lambda0, ...
+ * (at most max_decades increases) until ||A_H u - y_H||^2 <= alpha, then
+ * bisect between the last failing and the first passing lambda (at most
+ * max_bisect solves) until the passing end's residual lies within tol of
+ * alpha (the paper's default tol is alpha / 10). GS, bS from
+ * mlmix_fit_gram of the soft rows; AH [dev] double[n_hard x ld_h] and yH
+ * [dev] double[n_hard] are the hard rows. Outputs u [dev] double[n_params]
+ * (the passing end's solution) and info [dev] double[6] = {lambda, hard
+ * residual, number of solves, status, last failing lambda, decades}; status
+ * 0 = converged (also when lambda0 already passes), 1 = alpha not reached
+ * (the solution with the smallest residual seen is returned), 2 = bisection
+ * limit, 3 = non-positive pivot in the factorisation. work as for
+ * mlmix_fit_gram. Errors: MLMIX_E_ARG (NULL, sizes, alpha/tol/lambda0 not
+ * positive, ridge negative, limits beyond 64 decades / 1000 solves). */
+int mlmix_fit_constrained(mlmix_ctx *ctx, void *stream, int32_t n_params, const double *GS,
+                          const double *bS, const double *AH, int32_t ld_h, int32_t n_hard,
+                          const double *yH, double alpha, double tol, double lambda0,
+                          double ridge, int32_t max_decades, int32_t max_bisect, double *u,
+                          double *info, void *work, size_t work_bytes);
+
 /* Stage timing for benchmarks. Stages (bit i of the mask, name from
  * mlmix_profile_stage_name(i)): 0 neighbours (lambda and masks, cells,
  * rows), 1 regions (buffer), 2 compaction, 3 expensive atomic basis,

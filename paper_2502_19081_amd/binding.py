@@ -76,6 +76,15 @@ SIGNATURES = {
     "mlmix_get_neighbors": (ctypes.c_int, [_vp, _vp, _vp, _i32, _vp, _vp]),
     "mlmix_get_index_sets": (ctypes.c_int, [_vp, _vp, _vp, _i32, _vp, _vp]),
     "mlmix_model_flops": (ctypes.c_int, [_vp, _vp]),
+    "mlmix_fit_n_params": (ctypes.c_int, [_vp, ctypes.POINTER(_i32)]),
+    "mlmix_fit_design": (ctypes.c_int, [_vp, _vp, _vp, _i32, _vp, _vp, ctypes.POINTER(Box), _vp,
+                                        _i32]),
+    "mlmix_fit_work_size": (ctypes.c_int, [ctypes.c_int64, _i32, ctypes.POINTER(ctypes.c_size_t)]),
+    "mlmix_fit_gram": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int64, _i32, _i32, _vp, _vp, _vp,
+                                      _vp, _vp, ctypes.c_size_t]),
+    "mlmix_fit_constrained": (ctypes.c_int, [_vp, _vp, _i32, _vp, _vp, _vp, _i32, _i32, _vp, _d,
+                                             _d, _d, _d, _i32, _i32, _vp, _vp, _vp,
+                                             ctypes.c_size_t]),
     "mlmix_profile_enable": (ctypes.c_int, [_vp, _u32]),
     "mlmix_profile_read": (ctypes.c_int, [_vp, _vp, _vp]),
     "mlmix_profile_stage_name": (ctypes.c_char_p, [_i32]),

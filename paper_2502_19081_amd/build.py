@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmlmix.so")
-SOURCES = ["geom.hip", "ace.hip", "o3.hip", "uf3.hip", "tail.hip", "api.hip"]
+SOURCES = ["geom.hip", "ace.hip", "o3.hip", "uf3.hip", "tail.hip", "fit.hip", "api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC",

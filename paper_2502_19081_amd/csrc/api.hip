@@ -1406,6 +1406,109 @@ extern "C" int mlmix_get_index_sets(mlmix_ctx *ctx, void *stream, void *ws, int3
     return MLMIX_OK;
 }
 
+// ------------------------------------------- constrained fit of the cheap potential
+
+static int fit_params(const Ctx &c)
+{
+    const int ns = c.d.n_species, nk2 = c.d.uf3_n_knots2, nk3 = c.d.uf3_n_knots3;
+    int nd = ns * (ns + 1) / 2 * (nk2 - 1);
+    if (nk3 > 0)
+        nd += ns * ((nk3 - 1) * nk3 / 2) * (nk3 + 2);
+    return nd;
+}
+
+extern "C" int mlmix_fit_n_params(mlmix_ctx *ctx, int32_t *n_params)
+{
+    if (!ctx || !n_params)
+        return fail(MLMIX_E_ARG, "NULL argument");
+    *n_params = fit_params(ctx->c);
+    return MLMIX_OK;
+}
+
+extern "C" int mlmix_fit_design(mlmix_ctx *ctx, void *stream, void *ws, int32_t n_atoms,
+                                const double *pos, const int32_t *species, const mlmix_box *box,
+                                double *rows, int32_t ld)
+{
+    if (!ctx || !ws || !pos || !species || !rows)
+        return fail(MLMIX_E_ARG, "NULL argument");
+    const int nd = fit_params(ctx->c);
+    if (nd < 1 || nd > kFitMaxParams)
+        return fail(MLMIX_E_ARG, "the cheap potential has more free parameters than the fit supports");
+    if (ld < nd)
+        return fail(MLMIX_E_ARG, "ld is smaller than the number of parameters");
+    WsLayout L;
+    Box b;
+    int rc = lookup(ctx, ws, n_atoms, box, L, b);
+    if (rc)
+        return rc;
+    // per-atom energy rows live in the pair-gradient scratch of the workspace
+    const size_t avail = 2 * (L.h - L.g);
+    if ((size_t)L.n * nd * sizeof(double) > avail)
+        return fail(MLMIX_E_WORKSPACE, "workspace too small for the design rows (raise nbr_cap)");
+    launch_fit_design(static_cast<hipStream_t>(stream), ctx->c, ws, L, b, pos, species, rows, ld,
+                      at<double>(ws, L.g), nd);
+    HIP_OK(hipGetLastError());
+    return MLMIX_OK;
+}
+
+extern "C" int mlmix_fit_work_size(int64_t n_rows, int32_t n_params, size_t *bytes)
+{
+    if (!bytes || n_rows < 0 || n_params < 1 || n_params > kFitMaxParams)
+        return fail(MLMIX_E_ARG, "bad sizes");
+    long long chunk = 0;
+    const size_t parts = fit_gram_parts(n_rows > 0 ? n_rows : 1, chunk);
+    const size_t gram = fit_gram_part_bytes(n_params, parts);
+    const size_t search = ((size_t)n_params * n_params + n_params) * sizeof(double);
+    *bytes = gram > search ? gram : search;
+    return MLMIX_OK;
+}
+
+extern "C" int mlmix_fit_gram(mlmix_ctx *ctx, void *stream, const double *rows, int64_t n_rows,
+                              int32_t n_params, int32_t ld, const double *y, const double *w,
+                              double *G, double *b, void *work, size_t work_bytes)
+{
+    if (!ctx || !G || !b || (n_rows > 0 && (!rows || !work)))
+        return fail(MLMIX_E_ARG, "NULL argument");
+    if (n_rows < 0 || n_params < 1 || n_params > kFitMaxParams || ld < n_params)
+        return fail(MLMIX_E_ARG, "bad sizes");
+    size_t need = 0;
+    int rc = mlmix_fit_work_size(n_rows, n_params, &need);
+    if (rc)
+        return rc;
+    if (work_bytes < need)
+        return fail(MLMIX_E_WORKSPACE, "work buffer smaller than mlmix_fit_work_size");
+    launch_fit_gram(static_cast<hipStream_t>(stream), n_rows, n_params, ld, rows, y, w, G, b,
+                    static_cast<double *>(work));
+    HIP_OK(hipGetLastError());
+    return MLMIX_OK;
+}
+
+extern "C" int mlmix_fit_constrained(mlmix_ctx *ctx, void *stream, int32_t n_params,
+                                     const double *GS, const double *bS, const double *AH,
+                                     int32_t ld_h, int32_t n_hard, const double *yH, double alpha,
+                                     double tol, double lambda0, double ridge,
+                                     int32_t max_decades, int32_t max_bisect, double *c,
+                                     double *info, void *work, size_t work_bytes)
+{
+    if (!ctx || !GS || !bS || !c || !info || !work || (n_hard > 0 && (!AH || !yH)))
+        return fail(MLMIX_E_ARG, "NULL argument");
+    if (n_params < 1 || n_params > kFitMaxParams || n_hard < 0 || (n_hard > 0 && ld_h < n_params))
+        return fail(MLMIX_E_ARG, "bad sizes");
+    if (!(alpha > 0.0) || !(tol > 0.0) || !(lambda0 > 0.0) || !(ridge >= 0.0) ||
+        !std::isfinite(alpha) || !std::isfinite(tol) || !std::isfinite(lambda0) ||
+        !std::isfinite(ridge))
+        return fail(MLMIX_E_ARG, "alpha, tol and lambda0 must be positive, ridge non-negative");
+    if (max_decades < 0 || max_decades > 64 || max_bisect < 0 || max_bisect > 1000)
+        return fail(MLMIX_E_ARG, "iteration limits out of range");
+    if (work_bytes < ((size_t)n_params * n_params + n_params) * sizeof(double))
+        return fail(MLMIX_E_WORKSPACE, "work buffer smaller than mlmix_fit_work_size");
+    launch_fit_search(static_cast<hipStream_t>(stream), n_params, n_hard, ld_h, GS, bS, AH, yH,
+                      alpha, tol, lambda0, ridge, max_decades, max_bisect, c, info,
+                      static_cast<double *>(work));
+    HIP_OK(hipGetLastError());
+    return MLMIX_OK;
+}
+
 extern "C" int mlmix_profile_enable(mlmix_ctx *ctx, uint32_t stage_mask)
 {
     if (!ctx)

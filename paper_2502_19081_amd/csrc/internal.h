@@ -227,4 +227,19 @@ void launch_vv_kick_drift(hipStream_t s, void *ws, const WsLayout &L, const Box 
                           int drift);
 void launch_copy_i32(hipStream_t s, int32_t *dst, const int32_t *src, size_t n);
 
+// ---- fit.hip (constrained linear fitting of the cheap potential) ----
+constexpr int kFitMaxParams = 120;  // packed Cholesky factor of the search in LDS
+// erow: scratch of nd * n doubles (per-atom energy rows, column-major)
+void launch_fit_design(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L, const Box &b,
+                       const double *pos, const int32_t *species, double *rows, int ld,
+                       double *erow, int nd);
+size_t fit_gram_parts(long long nrows, long long &chunk);
+size_t fit_gram_part_bytes(int nd, size_t parts);
+void launch_fit_gram(hipStream_t s, long long nrows, int nd, int ld, const double *A,
+                     const double *y, const double *w, double *G, double *b, double *part);
+void launch_fit_search(hipStream_t s, int nd, int nh, int ldh, const double *GS, const double *bS,
+                       const double *AH, const double *yH, double alpha, double tol, double lam0,
+                       double ridge, int max_decades, int max_bisect, double *c, double *info,
+                       double *scratch);
+
 }  // namespace mlmix
