@@ -71,6 +71,14 @@ def parse():
                          "average; for a kernel trace of the same launches")
     ap.add_argument("--single-stream", action="store_true",
                     help="keep every stage on the caller's stream (no fork of the cheap potential)")
+    ap.add_argument("--fit", action="store_true",
+                    help="the second workload instead: constrained linear fit of the cheap "
+                         "potential to expensive-potential labels (thermal snapshots + strained "
+                         "cells); prints its own JSON line")
+    ap.add_argument("--fit-streams", type=int, default=4,
+                    help="streams over which --fit spreads the design rows of its configurations")
+    ap.add_argument("--fit-snapshots", type=int, default=20,
+                    help="soft-constraint snapshots of the 2,000-atom cube for --fit")
     ap.add_argument("--probe", choices=["copy"], default=None,
                     help="copy: a plain 256 MiB device-to-device copy, 20 times (calibration of "
                          "the HBM byte counters)")
@@ -146,10 +154,182 @@ def pair_counts(w, nbr, cnt, S_mask):
                 list_pairs=int(cnt.sum()), n=n)
 
 
+def fit_main(args):
+    """Constrained linear fit of the cheap potential (Methods, "Constrained
+    potential fitting" and "Generation of synthetic data"): soft data =
+    energies and forces of thermal snapshots of a 2,000-atom bcc W cube, hard
+    data = energies of 102 strained cells (six strain states x 17 strains in
+    +-0.5 %), labelled by the expensive potential before the timed region.
+    Timed: the design rows of every configuration, the weighted normal
+    equations of the soft rows and the lambda search, on one stream; the
+    search's result is read back at the end of each fit."""
+    import torch
+    from gen import fitdata as FD
+    from paper_2502_19081_amd import binding as B
+    from paper_2502_19081_amd import core
+    from paper_2502_19081_amd.fit import CheapFit
+    torch.cuda.set_device(0)
+    dev = "cuda"
+    m = FD.fit_model()
+    model = core.Model(m, precision="fp64")
+    fit = CheapFit(model, device=dev)
+    nd = fit.nd
+    soft = FD.thermal_snapshots(args.fit_snapshots)
+    hard = FD.strained_cells()
+    print(f"bench: fit, {len(soft)} soft snapshots, {len(hard)} strained cells, {nd} parameters",
+          file=sys.stderr, flush=True)
+
+    def prep(cfgs):
+        out = []
+        for c in cfgs:
+            n = len(c["pos"])
+            sy = core.System(model, n, c["L"], c["periodic"], cap=128, device=dev)
+            pos = torch.from_numpy(np.ascontiguousarray(c["pos"].T)).to(dev)
+            sp = torch.zeros(n, dtype=torch.int32, device=dev)
+            r = sy.compute(pos, sp, mode=B.MODE_ALL_EXPENSIVE, force_rebuild=True)
+            out.append((sy, pos, sp, n, r["e_exp"].sum().reshape(1), r["forces"].clone()))
+            sy.status()
+        return out
+    S, H = prep(soft), prep(hard)
+    offs = np.cumsum([0] + [1 + 3 * n for (_, _, _, n, _, _) in S])
+    n_rows = int(offs[-1])
+    rows = torch.empty(n_rows, nd, dtype=torch.float64, device=dev)
+    y = torch.cat([torch.cat([e, f.reshape(-1)]) for (_, _, _, _, e, f) in S])
+    w = torch.cat([torch.cat([torch.full((1,), 1.0 / n ** 2, dtype=torch.float64),
+                              torch.ones(3 * n, dtype=torch.float64)])
+                   for (_, _, _, n, _, _) in S]).to(dev)
+    hoffs = np.cumsum([0] + [1 + 3 * n for (_, _, _, n, _, _) in H])
+    hrows = torch.empty(int(hoffs[-1]), nd, dtype=torch.float64, device=dev)
+    h_energy_rows = torch.from_numpy(hoffs[:-1].astype(np.int64)).to(dev)
+    items = ([(sy, pos, sp, rows[o:o + 1 + 3 * n]) for (sy, pos, sp, n, _, _), o in zip(S, offs)] +
+             [(sy, pos, sp, hrows[o:o + 1 + 3 * n]) for (sy, pos, sp, n, _, _), o in zip(H, hoffs)])
+    yH = torch.cat([e for (_, _, _, _, e, _) in H])
+    wH = torch.tensor([1.0 / n ** 2 for (_, _, _, n, _, _) in H], dtype=torch.float64, device=dev)
+    G = torch.zeros(nd, nd, dtype=torch.float64, device=dev)
+    bvec = torch.zeros(nd, dtype=torch.float64, device=dev)
+    n_atoms = sum(n for (_, _, _, n, _, _) in S) + sum(n for (_, _, _, n, _, _) in H)
+
+    AH = None
+
+    def design_all():
+        nonlocal AH
+        fit.design_many(items, n_streams=args.fit_streams)
+        AH = hrows.index_select(0, h_energy_rows)
+
+    def normal():
+        G.zero_()
+        bvec.zero_()
+        fit.gram(rows, y, w, G, bvec)
+
+    # alpha: three decades below the hard residual of the unconstrained fit
+    design_all()
+    normal()
+    ridge = 1e-8 * float(torch.diagonal(G).mean())
+    _, free = fit.constrained(G, bvec, AH, yH, 1e300, lam0=1e-12, ridge=ridge, wH=wH)
+    alpha = 1e-3 * free["residual"]
+    lam0 = 1e-6
+
+    def once(ev=None):
+        if ev:
+            ev[0].record()
+        design_all()
+        if ev:
+            ev[1].record()
+        normal()
+        if ev:
+            ev[2].record()
+        return fit.constrained(G, bvec, AH, yH, alpha, lam0=lam0, ridge=ridge, wH=wH)
+
+    for _ in range(args.warmup):
+        once()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        u, info = once()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ms_fit = 1e3 * el / args.steps
+    # stage split (events on the one stream)
+    stage = np.zeros(3)
+    for _ in range(max(3, args.steps // 4)):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        once(ev)
+        ev[3].record()
+        torch.cuda.synchronize()
+        stage += [ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2]), ev[2].elapsed_time(ev[3])]
+    stage /= max(3, args.steps // 4)
+    # soft-data errors of the fitted cheap potential (per atom and per force component)
+    pred = rows @ u
+    err = (pred - y).cpu().numpy()
+    e_rows = offs[:-1]
+    e_err = np.array([err[o] / n for o, (_, _, _, n, _, _) in zip(e_rows, S)])
+    f_mask = np.ones(n_rows, bool)
+    f_mask[e_rows] = False
+    print(f"bench: fit {ms_fit:.3f} ms (design {stage[0]:.3f}, normal equations {stage[1]:.3f}, "
+          f"search {stage[2]:.3f}); lambda {info['lam']:.4e}, {info['n_solves']} solves",
+          file=sys.stderr, flush=True)
+
+    # Gram kernel roofline: it streams the soft rows once (HBM bound)
+    gram_bytes = n_rows * (nd + 2) * 8
+    cpu = None
+    if not args.no_cpu_baseline:
+        # the oracle's fit on a bounded sample: design rows of one soft
+        # snapshot and of the 17 strains of one state, scaled to the whole
+        # job by atom count; its Gram and search on the full matrices
+        import oracle as O
+        from oracle import fit as OF
+        t0 = time.perf_counter()
+        c = soft[0]
+        OF.design(m, c["pos"], np.zeros(len(c["pos"]), np.int32), c["L"], c["periodic"])
+        for c in hard[:17]:
+            OF.design(m, c["pos"], np.zeros(len(c["pos"]), np.int32), c["L"], c["periodic"])
+        t_design = time.perf_counter() - t0
+        n_sample = len(soft[0]["pos"]) + sum(len(c["pos"]) for c in hard[:17])
+        A_np, y_np, w_np = rows.cpu().numpy(), y.cpu().numpy(), w.cpu().numpy()
+        t0 = time.perf_counter()
+        GSr, bSr = OF.gram(A_np, y_np, w_np)
+        OF.constrained_fit(GSr, bSr, AH.cpu().numpy(), yH.cpu().numpy(), alpha, lam0=lam0,
+                           ridge=ridge, wH=wH.cpu().numpy())
+        t_solve = time.perf_counter() - t0
+        t_cpu = t_design * n_atoms / n_sample + t_solve
+        cpu = {"value": t_cpu * 1e3, "unit": "ms per fit", "cores": O.num_threads(),
+               "kind": "oracle",
+               "sample": f"design rows of one {len(soft[0]['pos'])}-atom snapshot and 17 strained "
+                         f"cells ({n_sample} atoms, {t_design:.1f} s) scaled by atom count to the "
+                         f"{n_atoms} atoms of the job, plus the oracle's Gram and lambda search on "
+                         f"the full matrices ({t_solve:.2f} s)"}
+    res = {
+        "metric": "constrained fit of the cheap potential: wall time per fit (design rows, "
+                  "normal equations, lambda search)",
+        "value": ms_fit, "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_fit, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"constrained fit: {len(soft)} thermal snapshots of a 2,000-atom "
+                               f"bcc W cube + {len(hard)} strained cells, {nd} parameters",
+                   "soft_rows": n_rows, "hard_rows": len(H), "labelled_atoms": n_atoms,
+                   "alpha": alpha, "ridge": ridge},
+        "stage_ms": {"design": stage[0], "normal_equations": stage[1], "search": stage[2]},
+        "design_streams": args.fit_streams,
+        "lambda": info["lam"], "hard_residual": info["residual"], "status": info["status"],
+        "n_solves": info["n_solves"], "unconstrained_hard_residual": free["residual"],
+        "soft_energy_rmse_eV_per_atom": float(np.sqrt(np.mean(e_err ** 2))),
+        "soft_force_rmse_eV_per_A": float(np.sqrt(np.mean(err[f_mask] ** 2))),
+        "roofline": {"bound": "hbm", "kernel": "normal_equations",
+                     "achieved": gram_bytes / (stage[1] * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": gram_bytes / (stage[1] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "traffic": None, "algorithmic_per_launch": gram_bytes},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(res))
+
+
 def main():
     args = parse()
     if args.probe == "copy":
         copy_probe()
+        return
+    if args.fit:
+        fit_main(args)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "

@@ -318,17 +318,17 @@ int mlmix_fit_n_params(mlmix_ctx *ctx, int32_t *n_params);
  * row-major; row 0 = d(total energy)/du, row 1 + q n + i = d(F_i,q)/du.
  * Reads the neighbour rows of the last mlmix_compute / mlmix_vv_step on ws,
  * which must have been given these positions (the call builds no list), and
- * uses the workspace's pair-gradient scratch for per-atom energy rows (so
- * call mlmix_compute again before mlmix_backward). Errors: MLMIX_E_ARG (NULL,
- * ld < n_params, more than 120 parameters, n_atoms not the workspace's),
- * MLMIX_E_WORKSPACE (nbr_cap too small to hold n x n_params doubles in that
- * scratch), MLMIX_E_BOX. More than 64 neighbours inside the 3-body cutoff of
+ * uses the workspace's pair-gradient scratch for per-atom energy rows and
+ * 3-body neighbour lists (so call mlmix_compute again before
+ * mlmix_backward). Errors: MLMIX_E_ARG (NULL, ld < n_params, more than 120
+ * parameters, n_atoms not the workspace's), MLMIX_E_WORKSPACE (nbr_cap too
+ * small for n x (8 n_params + 260) bytes in that scratch), MLMIX_E_BOX. More than 64 neighbours inside the 3-body cutoff of
  * one atom sets MLMIX_STATUS_TRIPLET_OVERFLOW (read with mlmix_status). */
 int mlmix_fit_design(mlmix_ctx *ctx, void *stream, void *ws, int32_t n_atoms, const double *pos,
                      const int32_t *species, const mlmix_box *box, double *rows, int32_t ld);
 
-/* Bytes of device scratch that mlmix_fit_gram (for n_rows rows) and
- * mlmix_fit_constrained need. */
+/* Bytes of device scratch that mlmix_fit_gram needs for n_rows rows, and
+ * that mlmix_fit_constrained needs with n_rows = n_hard. */
 int mlmix_fit_work_size(int64_t n_rows, int32_t n_params, size_t *bytes);
 
 /* G += A^T diag(w) A and b += A^T diag(w) y for rows [dev] double[n_rows x
@@ -342,22 +342,25 @@ int mlmix_fit_gram(mlmix_ctx *ctx, void *stream, const double *rows, int64_t n_r
                    double *b, void *work, size_t work_bytes);
 
 /* The lambda search, all on the device: solve at lambda0, 10 lambda0, ...
- * (at most max_decades increases) until ||A_H u - y_H||^2 <= alpha, then
+ * (at most max_decades increases) until the hard residual
+ * sum_h wH_h (A_H u - y_H)_h^2 <= alpha, then
  * bisect between the last failing and the first passing lambda (at most
  * max_bisect solves) until the passing end's residual lies within tol of
  * alpha (the paper's default tol is alpha / 10). GS, bS from
- * mlmix_fit_gram of the soft rows; AH [dev] double[n_hard x ld_h] and yH
- * [dev] double[n_hard] are the hard rows. Outputs u [dev] double[n_params]
+ * mlmix_fit_gram of the soft rows; AH [dev] double[n_hard x ld_h], yH and
+ * wH [dev] double[n_hard] are the hard rows and their weights (wH NULL =
+ * unit weights; 1/n^2 on total-energy rows gives per-atom errors). Outputs u [dev] double[n_params]
  * (the passing end's solution) and info [dev] double[6] = {lambda, hard
  * residual, number of solves, status, last failing lambda, decades}; status
  * 0 = converged (also when lambda0 already passes), 1 = alpha not reached
  * (the solution with the smallest residual seen is returned), 2 = bisection
- * limit, 3 = non-positive pivot in the factorisation. work as for
- * mlmix_fit_gram. Errors: MLMIX_E_ARG (NULL, sizes, alpha/tol/lambda0 not
+ * limit, 3 = non-positive pivot in the factorisation. work holds at least
+ * mlmix_fit_work_size(n_hard, n_params) bytes. Errors: MLMIX_E_ARG (NULL, sizes, alpha/tol/lambda0 not
  * positive, ridge negative, limits beyond 64 decades / 1000 solves). */
 int mlmix_fit_constrained(mlmix_ctx *ctx, void *stream, int32_t n_params, const double *GS,
                           const double *bS, const double *AH, int32_t ld_h, int32_t n_hard,
-                          const double *yH, double alpha, double tol, double lambda0,
+                          const double *yH, const double *wH, double alpha, double tol,
+                          double lambda0,
                           double ridge, int32_t max_decades, int32_t max_bisect, double *u,
                           double *info, void *work, size_t work_bytes);
 

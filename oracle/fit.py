@@ -108,29 +108,34 @@ def solve_fixed(GS, bS, GH, bH, lam, ridge):
     return np.linalg.solve(GS + lam * GH + ridge * np.eye(nd), bS + lam * bH)
 
 
-def hard_residual(AH, yH, c):
+def hard_residual(AH, yH, c, wH=None):
     r = AH @ c - yH
-    return float(r @ r)
+    if wH is None:
+        return float(r @ r)
+    return float(r @ (wH * r))
 
 
 def constrained_fit(GS, bS, AH, yH, alpha, lam0=1.0, ridge=0.0, tol=None, max_decades=24,
-                    max_bisect=200):
+                    max_bisect=200, wH=None):
     """The lambda search: solve at lam0, 10 lam0, 100 lam0, ... until the hard
     residual is at most alpha, then bisect between the last failing and the
     first passing lambda until the passing end's residual is within tol of
     alpha (tol = alpha/10 by default). Returns (c, info) with info = dict(lam,
     residual, n_solves, status, trace) and status 0 = converged, 1 = alpha not
     reached within max_decades (the solution with the smallest residual seen
-    is returned), 2 = bisection limit reached (the passing end is returned)."""
+    is returned), 2 = bisection limit reached (the passing end is returned).
+    wH (optional) weights the hard rows: the residual is sum wH (A_H c - y_H)^2
+    (per-atom energies from total-energy rows with wH = 1/n^2)."""
     if tol is None:
         tol = alpha / 10.0
-    GH = AH.T @ AH
-    bH = AH.T @ yH
+    if wH is None:
+        wH = np.ones(len(yH))
+    GH, bH = gram(AH, yH, wH)
     trace = []
 
     def run(lam):
         c = solve_fixed(GS, bS, GH, bH, lam, ridge)
-        r = hard_residual(AH, yH, c)
+        r = hard_residual(AH, yH, c, wH)
         trace.append((lam, r))
         return c, r
 

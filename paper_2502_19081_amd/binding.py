@@ -82,7 +82,7 @@ SIGNATURES = {
     "mlmix_fit_work_size": (ctypes.c_int, [ctypes.c_int64, _i32, ctypes.POINTER(ctypes.c_size_t)]),
     "mlmix_fit_gram": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int64, _i32, _i32, _vp, _vp, _vp,
                                       _vp, _vp, ctypes.c_size_t]),
-    "mlmix_fit_constrained": (ctypes.c_int, [_vp, _vp, _i32, _vp, _vp, _vp, _i32, _i32, _vp, _d,
+    "mlmix_fit_constrained": (ctypes.c_int, [_vp, _vp, _i32, _vp, _vp, _vp, _i32, _i32, _vp, _vp, _d,
                                              _d, _d, _d, _i32, _i32, _vp, _vp, _vp,
                                              ctypes.c_size_t]),
     "mlmix_profile_enable": (ctypes.c_int, [_vp, _u32]),

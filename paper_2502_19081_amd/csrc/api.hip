@@ -1441,9 +1441,10 @@ extern "C" int mlmix_fit_design(mlmix_ctx *ctx, void *stream, void *ws, int32_t 
     int rc = lookup(ctx, ws, n_atoms, box, L, b);
     if (rc)
         return rc;
-    // per-atom energy rows live in the pair-gradient scratch of the workspace
+    // per-atom energy rows and 3-body lists live in the pair-gradient
+    // scratch of the workspace
     const size_t avail = 2 * (L.h - L.g);
-    if ((size_t)L.n * nd * sizeof(double) > avail)
+    if ((size_t)L.n * (nd * sizeof(double) + (kMaxTriplet + 1) * sizeof(int)) > avail)
         return fail(MLMIX_E_WORKSPACE, "workspace too small for the design rows (raise nbr_cap)");
     launch_fit_design(static_cast<hipStream_t>(stream), ctx->c, ws, L, b, pos, species, rows, ld,
                       at<double>(ws, L.g), nd);
@@ -1457,9 +1458,9 @@ extern "C" int mlmix_fit_work_size(int64_t n_rows, int32_t n_params, size_t *byt
         return fail(MLMIX_E_ARG, "bad sizes");
     long long chunk = 0;
     const size_t parts = fit_gram_parts(n_rows > 0 ? n_rows : 1, chunk);
-    const size_t gram = fit_gram_part_bytes(n_params, parts);
-    const size_t search = ((size_t)n_params * n_params + n_params) * sizeof(double);
-    *bytes = gram > search ? gram : search;
+    // Gram partials of n_rows rows, after G_H and b_H of the search
+    *bytes = ((size_t)n_params * n_params + n_params) * sizeof(double) +
+             fit_gram_part_bytes(n_params, parts);
     return MLMIX_OK;
 }
 
@@ -1478,14 +1479,15 @@ extern "C" int mlmix_fit_gram(mlmix_ctx *ctx, void *stream, const double *rows, 
     if (work_bytes < need)
         return fail(MLMIX_E_WORKSPACE, "work buffer smaller than mlmix_fit_work_size");
     launch_fit_gram(static_cast<hipStream_t>(stream), n_rows, n_params, ld, rows, y, w, G, b,
-                    static_cast<double *>(work));
+                    static_cast<double *>(work) + (size_t)n_params * n_params + n_params);
     HIP_OK(hipGetLastError());
     return MLMIX_OK;
 }
 
 extern "C" int mlmix_fit_constrained(mlmix_ctx *ctx, void *stream, int32_t n_params,
                                      const double *GS, const double *bS, const double *AH,
-                                     int32_t ld_h, int32_t n_hard, const double *yH, double alpha,
+                                     int32_t ld_h, int32_t n_hard, const double *yH,
+                                     const double *wH, double alpha,
                                      double tol, double lambda0, double ridge,
                                      int32_t max_decades, int32_t max_bisect, double *c,
                                      double *info, void *work, size_t work_bytes)
@@ -1500,9 +1502,13 @@ extern "C" int mlmix_fit_constrained(mlmix_ctx *ctx, void *stream, int32_t n_par
         return fail(MLMIX_E_ARG, "alpha, tol and lambda0 must be positive, ridge non-negative");
     if (max_decades < 0 || max_decades > 64 || max_bisect < 0 || max_bisect > 1000)
         return fail(MLMIX_E_ARG, "iteration limits out of range");
-    if (work_bytes < ((size_t)n_params * n_params + n_params) * sizeof(double))
-        return fail(MLMIX_E_WORKSPACE, "work buffer smaller than mlmix_fit_work_size");
-    launch_fit_search(static_cast<hipStream_t>(stream), n_params, n_hard, ld_h, GS, bS, AH, yH,
+    size_t need = 0;
+    int rc = mlmix_fit_work_size(n_hard, n_params, &need);
+    if (rc)
+        return rc;
+    if (work_bytes < need)
+        return fail(MLMIX_E_WORKSPACE, "work buffer smaller than mlmix_fit_work_size(n_hard)");
+    launch_fit_search(static_cast<hipStream_t>(stream), n_params, n_hard, ld_h, GS, bS, AH, yH, wH,
                       alpha, tol, lambda0, ridge, max_decades, max_bisect, c, info,
                       static_cast<double *>(work));
     HIP_OK(hipGetLastError());

@@ -10,15 +10,17 @@
 //    (one per lane) as records in LDS and then consumed by every lane for its
 //    own columns, so each output element is a sum in a fixed order (no
 //    atomics). F_i collects the pairs of i, the triplets centred on i, and the
-//    triplets centred on a neighbour j in which i is a leg.
+//    triplets centred on a neighbour j in which i is a leg (the other leg
+//    from j's 3-body list, built beforehand by k_fit_list3).
 //  - k_fit_gram_partial / k_fit_gram_reduce: G = A^T diag(w) A and
 //    b = A^T diag(w) y. Each workgroup stages 32 rows at a time in LDS and
 //    every thread accumulates 4 x 4 blocks of the upper triangle; partials of
 //    fixed row chunks are summed in chunk order.
-//  - k_fit_search: one workgroup runs the whole lambda search: the normal
+//  - k_fit_search: one workgroup runs the whole lambda search (G_H and b_H
+//    come from the Gram kernels just before): the normal
 //    equations (G_S + lam G_H + ridge I) c = b_S + lam b_H solved by a
 //    Cholesky factorisation held packed in LDS, the hard residual
-//    ||A_H c - y_H||^2 from the hard rows, decades of lam until the residual
+//    sum_h w_h (A_H c - y_H)_h^2 from the hard rows, decades of lam until the residual
 //    is at most alpha, then interval bisection until it is within tol of
 //    alpha. Every loop has a fixed bound.
 // Everything is FP64 whatever the context's force precision.
@@ -31,30 +33,41 @@ constexpr int kFitColsPerLane = 2;  // columns per lane: kFitMaxParams <= 128
 
 // ---------------------------------------------------------------- B-splines
 
-__device__ __forceinline__ double fit_knot(int i, int npts, double top)
+// The four non-zero clamped uniform cubic B-splines at x (0 <= x < top) and
+// their derivatives, by the Cox-de Boor triangle on the span holding x. The
+// recursion runs in knot units u = x / h (B-splines do not change when x and
+// the knots are scaled together), where every knot difference is a small
+// integer, so no division is left; ih = 1/h = (npts - 1)/top. The functions
+// are B_first .. B_first+3.
+__device__ __forceinline__ int fit_k(int i, int npts)
 {
-    int k = i - 3;
-    k = k < 0 ? 0 : (k > npts - 1 ? npts - 1 : k);
-    return top * (double)k / (double)(npts - 1);
+    const int k = i - 3;
+    return k < 0 ? 0 : (k > npts - 1 ? npts - 1 : k);
 }
 
-// The four non-zero clamped uniform cubic B-splines at x (0 <= x < top) and
-// their derivatives, by the Cox-de Boor triangle on the span holding x; the
-// functions are B_first .. B_first+3.
-__device__ void fit_bspline(double x, int npts, double top, int &first, double N[4], double dN[4])
+__device__ __forceinline__ double fit_inv_small(int m)
 {
-    const double h = top / (double)(npts - 1);
-    int sp = (int)floor(x / h);
+    // 1/m for the knot-difference counts 1..3 that occur (0 never divides)
+    return m == 1 ? 1.0 : (m == 2 ? 0.5 : 1.0 / 3.0);
+}
+
+__device__ void fit_bspline(double x, int npts, double ih, int &first, double N[4], double dN[4])
+{
+    const double u = x * ih;
+    int sp = (int)floor(u);
     sp = sp < 0 ? 0 : (sp > npts - 2 ? npts - 2 : sp);
     const int mu = sp + 3;
     double B[4] = {1.0, 0.0, 0.0, 0.0}, B2[3] = {0.0, 0.0, 0.0};
     double left[4], right[4];
+#pragma unroll
     for (int j = 1; j <= 3; ++j) {
-        left[j] = x - fit_knot(mu + 1 - j, npts, top);
-        right[j] = fit_knot(mu + j, npts, top) - x;
+        left[j] = u - (double)fit_k(mu + 1 - j, npts);
+        right[j] = (double)fit_k(mu + j, npts) - u;
         double saved = 0.0;
+#pragma unroll
         for (int r = 0; r < j; ++r) {
-            const double tmp = B[r] / (right[r + 1] + left[j - r]);
+            const int m = fit_k(mu + r + 1, npts) - fit_k(mu + 1 - j + r, npts);
+            const double tmp = B[r] * fit_inv_small(m);
             B[r] = saved + right[r + 1] * tmp;
             saved = left[j - r] * tmp;
         }
@@ -65,14 +78,15 @@ __device__ void fit_bspline(double x, int npts, double top, int &first, double N
             B2[2] = B[2];
         }
     }
-    // derivative of B_k = 3 (B2_k / (t_k+3 - t_k) - B2_k+1 / (t_k+4 - t_k+1)),
-    // with the degree-2 functions B2_{mu-2..mu} non-zero
+    // dB_k/du = 3 (B2_k / (K_k+3 - K_k) - B2_k+1 / (K_k+4 - K_k+1)), with the
+    // degree-2 functions B2_{mu-2..mu} non-zero; d/dx = ih d/du
+#pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int k = mu - 3 + r;
-        const double a = r >= 1 ? B2[r - 1] / (fit_knot(k + 3, npts, top) - fit_knot(k, npts, top)) : 0.0;
-        const double b = r <= 2 ? B2[r] / (fit_knot(k + 4, npts, top) - fit_knot(k + 1, npts, top)) : 0.0;
+        const double a = r >= 1 ? B2[r - 1] * fit_inv_small(fit_k(k + 3, npts) - fit_k(k, npts)) : 0.0;
+        const double b = r <= 2 ? B2[r] * fit_inv_small(fit_k(k + 4, npts) - fit_k(k + 1, npts)) : 0.0;
         N[r] = B[r];
-        dN[r] = 3.0 * (a - b);
+        dN[r] = 3.0 * ih * (a - b);
     }
     first = sp;
 }
@@ -106,17 +120,18 @@ __device__ __forceinline__ double fit_disp(const double *__restrict__ pos, int n
 struct FitShape {
     int ns, nk2, nk3, nd, n2cols;  // n2cols: 2-body columns (all species pairs)
     double rc2, rc3;
+    double ih2, ih3, ih3c;         // knots per A: 2-body, 3-body legs, third side
 };
 
-// Column k decoded: kind 2 (species pair za <= zb, spline n) or 3 (centre
-// species z, legs p <= q, third side s); kind 0 = no column.
+// Column k decoded: kind 2 (species pair a <= b, spline p) or 3 (centre
+// species a, leg pair index p of (p1 <= p2), third side s); kind 0 = none.
 struct FitCol {
-    int kind, a, b, p, q, s;
+    int kind, a, b, p, s;
 };
 
 __device__ FitCol fit_decode(const FitShape &sh, int k)
 {
-    FitCol c{0, 0, 0, 0, 0, 0};
+    FitCol c{0, 0, 0, 0, 0};
     if (k >= sh.nd)
         return c;
     const int nf2 = sh.nk2 - 1;  // nb2 - 3
@@ -141,42 +156,45 @@ __device__ FitCol fit_decode(const FitShape &sh, int k)
     c.kind = 3;
     c.a = r / per_z;
     r -= c.a * per_z;
-    int pq = r / nb3;
-    c.s = r - pq * nb3;
-    for (int p = 0; p < nf3; ++p) {
-        const int row = nf3 - p;
-        if (pq < row) {
-            c.p = p;
-            c.q = p + pq;
-            break;
-        }
-        pq -= row;
-    }
+    c.p = r / nb3;
+    c.s = r - c.p * nb3;
     return c;
 }
-
-// One record: a pair (kind 2) or a triplet (kind 3) as seen by atom i.
-struct FitRec {
-    int z;       // species of the centre (triplet) or of j (pair); -1 = empty
-    int centre;  // triplet centred on i (its energy is part of E_i)
-    int fa, fb, fs;
-    double A[4], dA[4], Bv[4], dBv[4], C[4], dC[4];
-    double v1[3], v2[3];
-};
 
 // Entry of the list of i's neighbours inside the 3-body cutoff.
 struct FitLeg {
     int j, z, f;
-    double u[3], r, B[4], dB[4], d[3];
+    double u[3], B[4], dB[4], d[3];
 };
+
+constexpr int kFitRec = 32;  // records per batch
+
+// Dense records in dynamic LDS, record index fastest:
+//   pairs:    B[nf2][R], dB[nf2][R] (the 2-body basis and its derivative)
+//   triplets: P, Pa, Pb [npq][R] (leg products symmetrised over p1 <= p2 and
+//             their derivatives by leg a and leg b), C, dC [nb3][R] (third side)
+//   then v1, v2 [3][R] (force directions), z [R], centre [R] (ints).
+__host__ __device__ inline int fit_dense(int nk2, int nk3)
+{
+    const int nf2 = nk2 - 1;
+    const int nf3 = nk3 > 0 ? nk3 - 1 : 0;
+    const int npq = nf3 * (nf3 + 1) / 2;
+    const int t3 = nk3 > 0 ? 3 * npq + 2 * (nk3 + 2) : 0;
+    return 2 * nf2 > t3 ? 2 * nf2 : t3;
+}
+
+size_t fit_design_lds(int nk2, int nk3)
+{
+    return (size_t)(fit_dense(nk2, nk3) + 6) * kFitRec * sizeof(double) + 2 * kFitRec * sizeof(int);
+}
 
 __global__ void __launch_bounds__(kFitWave)
     k_fit_design(int n, int cap, const int *__restrict__ nbr, const int *__restrict__ cnt,
                  const double *__restrict__ pos, const int32_t *__restrict__ species, Box box,
                  FitShape sh, double *__restrict__ rows, int ld, double *__restrict__ erow,
-                 int *__restrict__ hdr)
+                 const int *__restrict__ l3, const int *__restrict__ l3cnt, int *__restrict__ hdr)
 {
-    __shared__ FitRec rec[kFitWave];
+    extern __shared__ double smem[];
     __shared__ FitLeg leg[kMaxTriplet];
     __shared__ int legpre[kMaxTriplet + 1];
     __shared__ int nleg;
@@ -184,6 +202,19 @@ __global__ void __launch_bounds__(kFitWave)
     const int lane = threadIdx.x;
     if (i >= n)
         return;
+    constexpr int R = kFitRec;
+    const int nf2 = sh.nk2 - 1;
+    const bool three = sh.nk3 > 1;
+    const int nb3 = sh.nk3 + 2, nf3 = three ? sh.nk3 - 1 : 0;
+    const int npq = nf3 * (nf3 + 1) / 2;
+    const int dense = fit_dense(sh.nk2, sh.nk3);
+    double *D = smem;
+    double *V = smem + (size_t)dense * R;
+    int *RZ = reinterpret_cast<int *>(V + 6 * R);
+    int *RC = RZ + R;
+    double *P = D, *Pa = D + npq * R, *Pb = D + 2 * npq * R;
+    double *C = D + 3 * npq * R, *dC = C + nb3 * R;
+
     const int zi = sp_clamp(species[i], sh.ns);
     FitCol col[kFitColsPerLane];
     double e[kFitColsPerLane], f[kFitColsPerLane][3];
@@ -193,95 +224,75 @@ __global__ void __launch_bounds__(kFitWave)
         f[m][0] = f[m][1] = f[m][2] = 0.0;
     }
     const double rc2sq = sh.rc2 * sh.rc2, rc3sq = sh.rc3 * sh.rc3;
-    const bool three = sh.nk3 > 0;
     const int ci = cnt[i] < cap ? cnt[i] : cap;
     if (lane == 0)
         nleg = 0;
     __syncthreads();
 
-    // consume one batch: every lane adds the records to its own columns
-    auto consume = [&](int nrec) {
-        for (int t = 0; t < nrec; ++t) {
-            const FitRec &R = rec[t];
-            if (R.z < 0)
-                continue;
-            for (int m = 0; m < kFitColsPerLane; ++m) {
-                const FitCol &c = col[m];
-                if (c.kind == 2 && R.fs < 0) {
-                    // pair: columns of the sorted species pair
-                    const int lo = R.z < zi ? R.z : zi, hi = R.z < zi ? zi : R.z;
-                    if (c.a != lo || c.b != hi)
-                        continue;
-                    const double bv = fit_win(R.A, R.fa, c.p), dv = fit_win(R.dA, R.fa, c.p);
-                    e[m] += 0.5 * bv;
-                    for (int k = 0; k < 3; ++k)
-                        f[m][k] += dv * R.v1[k];
-                } else if (c.kind == 3 && R.fs >= 0 && c.a == R.z) {
-                    const double ap = fit_win(R.A, R.fa, c.p), aq = fit_win(R.A, R.fa, c.q);
-                    const double bp = fit_win(R.Bv, R.fb, c.p), bq = fit_win(R.Bv, R.fb, c.q);
-                    const double dap = fit_win(R.dA, R.fa, c.p), daq = fit_win(R.dA, R.fa, c.q);
-                    const double dbp = fit_win(R.dBv, R.fb, c.p), dbq = fit_win(R.dBv, R.fb, c.q);
-                    const double cs = fit_win(R.C, R.fs, c.s), dcs = fit_win(R.dC, R.fs, c.s);
-                    const bool sym = c.p != c.q;
-                    const double P = ap * bq + (sym ? aq * bp : 0.0);
-                    const double Pa = dap * bq + (sym ? daq * bp : 0.0);
-                    const double Pb = ap * dbq + (sym ? aq * dbp : 0.0);
-                    const double X = Pa * cs;
-                    const double Y = R.centre ? Pb * cs : P * dcs;
-                    if (R.centre)
-                        e[m] += P * cs;
-                    for (int k = 0; k < 3; ++k)
-                        f[m][k] += X * R.v1[k] + Y * R.v2[k];
-                }
-            }
-        }
-    };
-
-    // 1. pairs of i, and the list of neighbours inside the 3-body cutoff
-    for (int base = 0; base < ci; base += kFitWave) {
+    // 1. pairs of i (2-body columns), and the list of its 3-body legs
+    for (int base = 0; base < ci; base += R) {
         const int slot = base + lane;
-        FitRec &R = rec[lane];
-        R.z = -1;
-        R.fs = -1;
         bool in3 = false;
         double d[3] = {0.0, 0.0, 0.0}, r2 = 0.0;
         int j = -1;
-        if (slot < ci) {
-            j = nbr[(size_t)i * cap + slot];
-            if (j >= 0 && j < n) {
-                r2 = fit_disp(pos, n, i, j, box, d);
-                const double r = sqrt(r2);
-                if (r2 < rc2sq) {
-                    R.z = sp_clamp(species[j], sh.ns);
-                    fit_bspline(r, sh.nk2, sh.rc2, R.fa, R.A, R.dA);
-                    for (int k = 0; k < 3; ++k)
-                        R.v1[k] = d[k] / r;
+        if (lane < R) {
+            RZ[lane] = -1;
+            if (slot < ci) {
+                j = nbr[(size_t)i * cap + slot];
+                if (j >= 0 && j < n) {
+                    r2 = fit_disp(pos, n, i, j, box, d);
+                    const double r = sqrt(r2);
+                    if (r2 < rc2sq) {
+                        int fb;
+                        double Bw[4], dBw[4];
+                        fit_bspline(r, sh.nk2, sh.ih2, fb, Bw, dBw);
+                        RZ[lane] = sp_clamp(species[j], sh.ns);
+                        for (int q = 0; q < nf2; ++q) {
+                            const unsigned o = (unsigned)(q - fb);
+                            D[q * R + lane] = o < 4u ? Bw[o] : 0.0;
+                            D[(nf2 + q) * R + lane] = o < 4u ? dBw[o] : 0.0;
+                        }
+                        for (int k = 0; k < 3; ++k)
+                            V[k * R + lane] = d[k] / r;
+                    }
+                    in3 = three && r2 < rc3sq;
                 }
-                in3 = three && r2 < rc3sq;
             }
         }
-        // append the 3-body legs in row order
         const unsigned long long m3 = __ballot(in3);
-        const int before = __popcll(m3 & ((1ull << lane) - 1ull));
-        const int pos3 = nleg + before;
+        const int pos3 = nleg + __popcll(m3 & ((1ull << lane) - 1ull));
         if (in3) {
             if (pos3 < kMaxTriplet) {
                 FitLeg &G = leg[pos3];
                 const double r = sqrt(r2);
                 G.j = j;
                 G.z = sp_clamp(species[j], sh.ns);
-                G.r = r;
                 for (int k = 0; k < 3; ++k) {
                     G.d[k] = d[k];
                     G.u[k] = d[k] / r;
                 }
-                fit_bspline(r, sh.nk3, sh.rc3, G.f, G.B, G.dB);
+                fit_bspline(r, sh.nk3, sh.ih3, G.f, G.B, G.dB);
             } else {
                 atomicOr(&hdr[H_STATUS], MLMIX_STATUS_TRIPLET_OVERFLOW);
             }
         }
         __syncthreads();
-        consume(ci - base < kFitWave ? ci - base : kFitWave);
+        const int nrec = ci - base < R ? ci - base : R;
+        for (int t = 0; t < nrec; ++t) {
+            const int zj = RZ[t];
+            if (zj < 0)
+                continue;
+            const int lo = zj < zi ? zj : zi, hi = zj < zi ? zi : zj;
+            for (int m = 0; m < kFitColsPerLane; ++m) {
+                const FitCol &c = col[m];
+                if (c.kind != 2 || c.a != lo || c.b != hi)
+                    continue;
+                const double bv = D[c.p * R + t], dv = D[(nf2 + c.p) * R + t];
+                e[m] += 0.5 * bv;
+                for (int k = 0; k < 3; ++k)
+                    f[m][k] += dv * V[k * R + t];
+            }
+        }
         if (lane == 0) {
             const int tot = nleg + __popcll(m3);
             nleg = tot < kMaxTriplet ? tot : kMaxTriplet;
@@ -290,96 +301,146 @@ __global__ void __launch_bounds__(kFitWave)
     }
     const int m = nleg;
 
+    // dense leg products of one triplet record (lane t < R): legs a and b
+    // (windows fa/A/dA and fb/Bv/dBv), third side (fs/Cw/dCw)
+    auto put = [&](int t, int fa, const double *A, const double *dA, int fb, const double *Bv,
+                   const double *dBv, int fs, const double *Cw, const double *dCw, bool centre) {
+        int idx = 0;
+        for (int p1 = 0; p1 < nf3; ++p1) {
+            const unsigned o1a = (unsigned)(p1 - fa), o1b = (unsigned)(p1 - fb);
+            const double a1 = o1a < 4u ? A[o1a] : 0.0, da1 = o1a < 4u ? dA[o1a] : 0.0;
+            const double b1 = o1b < 4u ? Bv[o1b] : 0.0, db1 = o1b < 4u ? dBv[o1b] : 0.0;
+            for (int p2 = p1; p2 < nf3; ++p2, ++idx) {
+                const unsigned o2a = (unsigned)(p2 - fa), o2b = (unsigned)(p2 - fb);
+                const double a2 = o2a < 4u ? A[o2a] : 0.0, da2 = o2a < 4u ? dA[o2a] : 0.0;
+                const double b2 = o2b < 4u ? Bv[o2b] : 0.0, db2 = o2b < 4u ? dBv[o2b] : 0.0;
+                const bool sym = p1 != p2;
+                P[idx * R + t] = a1 * b2 + (sym ? a2 * b1 : 0.0);
+                Pa[idx * R + t] = da1 * b2 + (sym ? da2 * b1 : 0.0);
+                if (centre)
+                    Pb[idx * R + t] = a1 * db2 + (sym ? a2 * db1 : 0.0);
+            }
+        }
+        for (int q = 0; q < nb3; ++q) {
+            const unsigned o = (unsigned)(q - fs);
+            C[q * R + t] = o < 4u ? Cw[o] : 0.0;
+            dC[q * R + t] = o < 4u ? dCw[o] : 0.0;
+        }
+    };
+    // every lane adds a batch of triplet records to its own columns
+    auto consume3 = [&](int nrec) {
+        for (int t = 0; t < nrec; ++t) {
+            const int z = RZ[t];
+            if (z < 0)
+                continue;
+            const bool centre = RC[t] != 0;
+            const double v1[3] = {V[t], V[R + t], V[2 * R + t]};
+            const double v2[3] = {V[3 * R + t], V[4 * R + t], V[5 * R + t]};
+            for (int mm = 0; mm < kFitColsPerLane; ++mm) {
+                const FitCol &c = col[mm];
+                if (c.kind != 3 || c.a != z)
+                    continue;
+                const double u = P[c.p * R + t], ua = Pa[c.p * R + t];
+                const double cs = C[c.s * R + t];
+                const double X = ua * cs;
+                double Y;
+                if (centre) {
+                    Y = Pb[c.p * R + t] * cs;
+                    e[mm] += u * cs;
+                } else {
+                    Y = u * dC[c.s * R + t];
+                }
+                for (int k = 0; k < 3; ++k)
+                    f[mm][k] += X * v1[k] + Y * v2[k];
+            }
+        }
+    };
+
     if (three && m > 0) {
         // 2. triplets centred on i: unordered leg pairs (a < b)
         const int npairs = m * (m - 1) / 2;
-        for (int base = 0; base < npairs; base += kFitWave) {
+        for (int base = 0; base < npairs; base += R) {
             const int t = base + lane;
-            FitRec &R = rec[lane];
-            R.z = -1;
-            if (t < npairs) {
-                int a = 0, rem = t;
-                while (rem >= m - 1 - a) {
-                    rem -= m - 1 - a;
-                    ++a;
-                }
-                const int b = a + 1 + rem;
-                const FitLeg &Ga = leg[a], &Gb = leg[b];
-                double dd[3];
-                for (int k = 0; k < 3; ++k)
-                    dd[k] = Gb.d[k] - Ga.d[k];
-                const double rjk = sqrt(dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2]);
-                R.z = zi;
-                R.centre = 1;
-                R.fa = Ga.f;
-                R.fb = Gb.f;
-                for (int q = 0; q < 4; ++q) {
-                    R.A[q] = Ga.B[q];
-                    R.dA[q] = Ga.dB[q];
-                    R.Bv[q] = Gb.B[q];
-                    R.dBv[q] = Gb.dB[q];
-                }
-                fit_bspline(rjk, sh.nk3, 2.0 * sh.rc3, R.fs, R.C, R.dC);
-                for (int k = 0; k < 3; ++k) {
-                    R.v1[k] = Ga.u[k];
-                    R.v2[k] = Gb.u[k];
+            if (lane < R) {
+                RZ[lane] = -1;
+                if (t < npairs) {
+                    int a = 0, rem = t;
+                    while (rem >= m - 1 - a) {
+                        rem -= m - 1 - a;
+                        ++a;
+                    }
+                    const int b = a + 1 + rem;
+                    const FitLeg &Ga = leg[a], &Gb = leg[b];
+                    double dd[3];
+                    for (int k = 0; k < 3; ++k)
+                        dd[k] = Gb.d[k] - Ga.d[k];
+                    const double rjk = sqrt(dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2]);
+                    int fs;
+                    double Cw[4], dCw[4];
+                    fit_bspline(rjk, sh.nk3, sh.ih3c, fs, Cw, dCw);
+                    put(lane, Ga.f, Ga.B, Ga.dB, Gb.f, Gb.B, Gb.dB, fs, Cw, dCw, true);
+                    for (int k = 0; k < 3; ++k) {
+                        V[k * R + lane] = Ga.u[k];
+                        V[(3 + k) * R + lane] = Gb.u[k];
+                    }
+                    RZ[lane] = zi;
+                    RC[lane] = 1;
                 }
             }
             __syncthreads();
-            consume(npairs - base < kFitWave ? npairs - base : kFitWave);
+            consume3(npairs - base < R ? npairs - base : R);
             __syncthreads();
         }
 
-        // 3. triplets centred on a 3-body neighbour j with i as one leg
+        // 3. triplets centred on a 3-body neighbour j with i as one leg: the
+        // other leg k runs over j's own 3-body list (k != i)
         if (lane == 0) {
             int acc = 0;
             for (int a = 0; a < m; ++a) {
                 legpre[a] = acc;
-                const int cj = cnt[leg[a].j];
-                acc += cj < cap ? cj : cap;
+                acc += l3cnt[leg[a].j];
             }
             legpre[m] = acc;
         }
         __syncthreads();
         const int total = legpre[m];
-        for (int base = 0; base < total; base += kFitWave) {
+        for (int base = 0; base < total; base += R) {
             const int t = base + lane;
-            FitRec &R = rec[lane];
-            R.z = -1;
-            if (t < total) {
-                int a = 0;
-                while (legpre[a + 1] <= t)
-                    ++a;
-                const FitLeg &Ga = leg[a];
-                const int j = Ga.j;
-                const int k = nbr[(size_t)j * cap + (t - legpre[a])];
-                if (k >= 0 && k < n && k != i) {
-                    double djk[3];
-                    const double r2jk = fit_disp(pos, n, j, k, box, djk);
-                    if (r2jk < rc3sq) {
-                        const double rjk = sqrt(r2jk);
-                        double d3[3];
-                        for (int q = 0; q < 3; ++q)
-                            d3[q] = Ga.d[q] + djk[q];
-                        const double r3 = sqrt(d3[0] * d3[0] + d3[1] * d3[1] + d3[2] * d3[2]);
-                        R.z = Ga.z;
-                        R.centre = 0;
-                        R.fa = Ga.f;
-                        for (int q = 0; q < 4; ++q) {
-                            R.A[q] = Ga.B[q];
-                            R.dA[q] = Ga.dB[q];
-                        }
-                        fit_bspline(rjk, sh.nk3, sh.rc3, R.fb, R.Bv, R.dBv);
-                        fit_bspline(r3, sh.nk3, 2.0 * sh.rc3, R.fs, R.C, R.dC);
-                        for (int q = 0; q < 3; ++q) {
-                            R.v1[q] = Ga.u[q];
-                            R.v2[q] = d3[q] / r3;
+            if (lane < R) {
+                RZ[lane] = -1;
+                if (t < total) {
+                    int a = 0;
+                    while (legpre[a + 1] <= t)
+                        ++a;
+                    const FitLeg &Ga = leg[a];
+                    const int j = Ga.j;
+                    const int k = l3[(size_t)j * kMaxTriplet + (t - legpre[a])];
+                    if (k >= 0 && k < n && k != i) {
+                        double djk[3];
+                        const double r2jk = fit_disp(pos, n, j, k, box, djk);
+                        if (r2jk < rc3sq) {
+                            const double rjk = sqrt(r2jk);
+                            double d3[3];
+                            for (int q = 0; q < 3; ++q)
+                                d3[q] = Ga.d[q] + djk[q];
+                            const double r3 = sqrt(d3[0] * d3[0] + d3[1] * d3[1] + d3[2] * d3[2]);
+                            int fb, fs;
+                            double Bw[4], dBw[4], Cw[4], dCw[4];
+                            fit_bspline(rjk, sh.nk3, sh.ih3, fb, Bw, dBw);
+                            fit_bspline(r3, sh.nk3, sh.ih3c, fs, Cw, dCw);
+                            put(lane, Ga.f, Ga.B, Ga.dB, fb, Bw, dBw, fs, Cw, dCw, false);
+                            for (int q = 0; q < 3; ++q) {
+                                V[q * R + lane] = Ga.u[q];
+                                V[(3 + q) * R + lane] = d3[q] / r3;
+                            }
+                            RZ[lane] = Ga.z;
+                            RC[lane] = 0;
                         }
                     }
                 }
             }
             __syncthreads();
-            consume(total - base < kFitWave ? total - base : kFitWave);
+            consume3(total - base < R ? total - base : R);
             __syncthreads();
         }
     }
@@ -392,6 +453,44 @@ __global__ void __launch_bounds__(kFitWave)
         for (int q = 0; q < 3; ++q)
             rows[(size_t)(1 + (size_t)q * n + i) * ld + k] = f[mm][q];
     }
+}
+
+// Every atom's neighbours inside the 3-body cutoff, in row order (at most
+// kMaxTriplet; more sets MLMIX_STATUS_TRIPLET_OVERFLOW).
+__global__ void __launch_bounds__(kFitWave)
+    k_fit_list3(int n, int cap, const int *__restrict__ nbr, const int *__restrict__ cnt,
+                const double *__restrict__ pos, Box box, double rc3sq, int *__restrict__ l3,
+                int *__restrict__ l3cnt, int *__restrict__ hdr)
+{
+    const int i = blockIdx.x;
+    const int lane = threadIdx.x;
+    if (i >= n)
+        return;
+    const int ci = cnt[i] < cap ? cnt[i] : cap;
+    int m = 0;
+    for (int base = 0; base < ci; base += kFitWave) {
+        const int slot = base + lane;
+        bool in3 = false;
+        int j = -1;
+        if (slot < ci) {
+            j = nbr[(size_t)i * cap + slot];
+            if (j >= 0 && j < n) {
+                double d[3];
+                in3 = fit_disp(pos, n, i, j, box, d) < rc3sq;
+            }
+        }
+        const unsigned long long b = __ballot(in3);
+        const int at3 = m + __popcll(b & ((1ull << lane) - 1ull));
+        if (in3) {
+            if (at3 < kMaxTriplet)
+                l3[(size_t)i * kMaxTriplet + at3] = j;
+            else
+                atomicOr(&hdr[H_STATUS], MLMIX_STATUS_TRIPLET_OVERFLOW);
+        }
+        m += __popcll(b);
+    }
+    if (lane == 0)
+        l3cnt[i] = m < kMaxTriplet ? m : kMaxTriplet;
 }
 
 // rows[0][k] = sum_i erow[k][i], one workgroup per column, fixed order
@@ -428,8 +527,18 @@ void launch_fit_design(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L,
     sh.n2cols = sh.ns * (sh.ns + 1) / 2 * (sh.nk2 - 1);
     sh.rc2 = c.d.uf3_rcut2;
     sh.rc3 = c.d.uf3_rcut3;
-    k_fit_design<<<L.n, kFitWave, 0, s>>>(L.n, L.cap, at<int>(ws, L.nbr), at<int>(ws, L.cnt), pos,
-                                          species, b, sh, rows, ld, erow, at<int>(ws, L.hdr));
+    sh.ih2 = (double)(sh.nk2 - 1) / sh.rc2;
+    sh.ih3 = sh.nk3 > 1 ? (double)(sh.nk3 - 1) / sh.rc3 : 0.0;
+    sh.ih3c = sh.nk3 > 1 ? (double)(sh.nk3 - 1) / (2.0 * sh.rc3) : 0.0;
+    int *l3 = reinterpret_cast<int *>(erow + (size_t)nd * L.n);
+    int *l3cnt = l3 + (size_t)kMaxTriplet * L.n;
+    if (sh.nk3 > 1)
+        k_fit_list3<<<L.n, kFitWave, 0, s>>>(L.n, L.cap, at<int>(ws, L.nbr), at<int>(ws, L.cnt),
+                                             pos, b, sh.rc3 * sh.rc3, l3, l3cnt,
+                                             at<int>(ws, L.hdr));
+    k_fit_design<<<L.n, kFitWave, fit_design_lds(sh.nk2, sh.nk3), s>>>(L.n, L.cap, at<int>(ws, L.nbr), at<int>(ws, L.cnt), pos,
+                                          species, b, sh, rows, ld, erow, l3, l3cnt,
+                                          at<int>(ws, L.hdr));
     k_fit_erow_sum<<<nd, 256, 0, s>>>(L.n, erow, rows);
 }
 
@@ -589,12 +698,27 @@ void launch_fit_gram(hipStream_t s, long long nrows, int nd, int ld, const doubl
 
 struct FitSearchArgs {
     int nd, nh, ldh;
-    const double *GS, *bS, *AH, *yH;
+    const double *GS, *bS, *AH, *yH, *wH;
     double alpha, tol, lam0, ridge;
     int max_decades, max_bisect;
-    double *GH, *bH;  // scratch nd*nd + nd
+    const double *GH, *bH;  // A_H^T W A_H and A_H^T W y_H (built before the search)
     double *c, *info;
 };
+
+__device__ __forceinline__ double fit_wave_sum(double v)
+{
+    for (int o = 32; o > 0; o >>= 1)
+        v += __shfl_xor(v, o);
+    return v;
+}
+
+// Orders one wavefront's LDS writes before its later LDS reads.
+__device__ __forceinline__ void fit_wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 // Block sum over 256 threads in a fixed order.
 __device__ double fit_block_sum(double v, double *red)
@@ -613,31 +737,16 @@ __device__ double fit_block_sum(double v, double *red)
 
 __global__ void __launch_bounds__(256) k_fit_search(FitSearchArgs a)
 {
-    constexpr int kPacked = kFitMaxParams * (kFitMaxParams + 1) / 2;
+    // packed lower triangle of M plus the right-hand side as an extra row nd
+    // (factorising that row performs the forward substitution)
+    constexpr int kPacked = (kFitMaxParams + 1) * (kFitMaxParams + 2) / 2;
     __shared__ double Lp[kPacked];
-    __shared__ double z[kFitMaxParams], cur[kFitMaxParams], keep[kFitMaxParams];
+    __shared__ double cur[kFitMaxParams], keep[kFitMaxParams], rdg[kFitMaxParams];
     __shared__ double red[256];
     __shared__ int fail;
     const int nd = a.nd, tid = threadIdx.x;
     auto P = [](int r, int c2) { return r * (r + 1) / 2 + c2; };  // r >= c2
 
-    // G_H = A_H^T A_H and b_H = A_H^T y_H
-    for (int e = tid; e < nd * nd + nd; e += 256) {
-        double s = 0.0;
-        if (e < nd * nd) {
-            const int k = e / nd, l = e - k * nd;
-            for (int h = 0; h < a.nh; ++h)
-                s += a.AH[(size_t)h * a.ldh + k] * a.AH[(size_t)h * a.ldh + l];
-            a.GH[e] = s;
-        } else {
-            const int k = e - nd * nd;
-            for (int h = 0; h < a.nh; ++h)
-                s += a.AH[(size_t)h * a.ldh + k] * a.yH[h];
-            a.bH[k] = s;
-        }
-    }
-    __threadfence();
-    __syncthreads();
 
     // one solve at lam: cur = c(lam); returns the hard residual (or -1 when
     // the factorisation meets a non-positive pivot)
@@ -655,57 +764,82 @@ __global__ void __launch_bounds__(256) k_fit_search(FitSearchArgs a)
             Lp[e] = v;
         }
         if (tid < nd)
-            z[tid] = a.bS[tid] + lam * a.bH[tid];
+            Lp[P(nd, tid)] = a.bS[tid] + lam * a.bH[tid];
         if (tid == 0)
             fail = 0;
         __syncthreads();
-        // left-looking Cholesky, column by column
+        // left-looking Cholesky, column by column. The unnormalised column
+        // is written first; every thread then scales its own entry by
+        // 1/sqrt(t_jj) (kept in rdg), so a column needs two barriers. The
+        // diagonal of Lp keeps t_jj; the substitutions use rdg.
         for (int j = 0; j < nd; ++j) {
+            const int i = j + tid;  // rows j .. nd (nd = right-hand side); nd < 256
             double t = 0.0;
-            const int i = j + tid;  // rows j .. nd-1; nd <= 256 threads
-            if (i < nd) {
-                t = Lp[P(i, j)];
-                for (int k = 0; k < j; ++k)
-                    t -= Lp[P(i, k)] * Lp[P(j, k)];
+            if (i <= nd) {
+                // four partial sums so that the LDS loads of later terms are
+                // in flight while earlier ones accumulate
+                const double *li = Lp + P(i, 0), *lj = Lp + P(j, 0);
+                double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;
+                int k = 0;
+                for (; k + 4 <= j; k += 4) {
+                    t0 += li[k] * lj[k];
+                    t1 += li[k + 1] * lj[k + 1];
+                    t2 += li[k + 2] * lj[k + 2];
+                    t3 += li[k + 3] * lj[k + 3];
+                }
+                for (; k < j; ++k)
+                    t0 += li[k] * lj[k];
+                t = Lp[P(i, j)] - ((t0 + t1) + (t2 + t3));
+                Lp[P(i, j)] = t;
             }
             __syncthreads();
-            if (i == j) {
-                if (!(t > 0.0))
+            const double tj = Lp[P(j, j)];
+            const double r = tj > 0.0 ? 1.0 / sqrt(tj) : 1.0;
+            if (i > j && i <= nd)
+                Lp[P(i, j)] = t * r;
+            if (tid == 0) {
+                if (!(tj > 0.0))
                     fail = 1;
-                Lp[P(j, j)] = t > 0.0 ? sqrt(t) : 1.0;
+                rdg[j] = r;
             }
             __syncthreads();
-            if (i > j && i < nd)
-                Lp[P(i, j)] = t / Lp[P(j, j)];
-            __syncthreads();
         }
-        // L x = z, then L^T c = x (in place in z)
-        for (int j = 0; j < nd; ++j) {
-            if (tid == 0)
-                z[j] = z[j] / Lp[P(j, j)];
-            __syncthreads();
-            const int i = j + 1 + tid;
-            if (i < nd)
-                z[i] -= Lp[P(i, j)] * z[j];
-            __syncthreads();
+        // row nd now holds x with L x = b; L^T c = x by wavefront 0, column
+        // by column (c_j = x_j / L_jj, then x_k -= L_jk c_j for k < j)
+        if (tid < 64) {
+            for (int k = tid; k < nd; k += 64)
+                cur[k] = Lp[P(nd, k)];
+            fit_wave_sync();
+            for (int j = nd - 1; j >= 0; --j) {
+                if (tid == 0)
+                    cur[j] = cur[j] * rdg[j];
+                fit_wave_sync();
+                const double cj = cur[j];
+                for (int k = tid; k < j; k += 64)
+                    cur[k] -= Lp[P(j, k)] * cj;
+                fit_wave_sync();
+            }
         }
-        for (int j = nd - 1; j >= 0; --j) {
-            if (tid == 0)
-                z[j] = z[j] / Lp[P(j, j)];
-            __syncthreads();
-            if (tid < j)
-                z[tid] -= Lp[P(j, tid)] * z[j];
-            __syncthreads();
-        }
-        if (tid < nd)
-            cur[tid] = z[tid];
         __syncthreads();
+        // hard residual: each wavefront takes four rows at a time, lanes
+        // over the parameters
         double part = 0.0;
-        for (int h = tid; h < a.nh; h += 256) {
-            double r = -a.yH[h];
-            for (int k = 0; k < nd; ++k)
-                r += a.AH[(size_t)h * a.ldh + k] * cur[k];
-            part += r * r;
+        const int wv = tid >> 6, ln = tid & 63;
+        for (int h0 = 4 * wv; h0 < a.nh; h0 += 16) {
+            double r[4] = {0.0, 0.0, 0.0, 0.0};
+            for (int k = ln; k < nd; k += 64) {
+                const double ck = cur[k];
+                for (int q = 0; q < 4; ++q)
+                    if (h0 + q < a.nh)
+                        r[q] += a.AH[(size_t)(h0 + q) * a.ldh + k] * ck;
+            }
+            for (int q = 0; q < 4; ++q) {
+                const double rq = fit_wave_sum(r[q]);
+                if (ln == 0 && h0 + q < a.nh) {
+                    const double d = rq - a.yH[h0 + q];
+                    part += (a.wH ? a.wH[h0 + q] : 1.0) * d * d;
+                }
+            }
         }
         const double res = fit_block_sum(part, red);
         return fail ? -1.0 : res;
@@ -789,12 +923,17 @@ __global__ void __launch_bounds__(256) k_fit_search(FitSearchArgs a)
 }
 
 void launch_fit_search(hipStream_t s, int nd, int nh, int ldh, const double *GS, const double *bS,
-                       const double *AH, const double *yH, double alpha, double tol, double lam0,
-                       double ridge, int max_decades, int max_bisect, double *c, double *info,
-                       double *scratch)
+                       const double *AH, const double *yH, const double *wH, double alpha,
+                       double tol, double lam0, double ridge, int max_decades, int max_bisect,
+                       double *c, double *info, double *scratch)
 {
-    FitSearchArgs a{nd, nh, ldh, GS, bS, AH, yH, alpha, tol, lam0, ridge, max_decades, max_bisect,
-                    scratch, scratch + (size_t)nd * nd, c, info};
+    // G_H, b_H by the Gram kernels (zeroed by a fill kernel first), then the
+    // search in one workgroup
+    double *GH = scratch, *bH = scratch + (size_t)nd * nd, *part = bH + nd;
+    launch_fill_f64(s, GH, 0.0, (size_t)nd * nd + nd);
+    launch_fit_gram(s, nh, nd, ldh, AH, yH, wH, GH, bH, part);
+    FitSearchArgs a{nd, nh, ldh, GS, bS, AH, yH, wH, alpha, tol, lam0, ridge, max_decades, max_bisect,
+                    GH, bH, c, info};
     k_fit_search<<<1, 256, 0, s>>>(a);
 }
 

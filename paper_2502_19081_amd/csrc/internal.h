@@ -238,8 +238,8 @@ size_t fit_gram_part_bytes(int nd, size_t parts);
 void launch_fit_gram(hipStream_t s, long long nrows, int nd, int ld, const double *A,
                      const double *y, const double *w, double *G, double *b, double *part);
 void launch_fit_search(hipStream_t s, int nd, int nh, int ldh, const double *GS, const double *bS,
-                       const double *AH, const double *yH, double alpha, double tol, double lam0,
-                       double ridge, int max_decades, int max_bisect, double *c, double *info,
-                       double *scratch);
+                       const double *AH, const double *yH, const double *wH, double alpha,
+                       double tol, double lam0, double ridge, int max_decades, int max_bisect,
+                       double *c, double *info, double *scratch);
 
 }  // namespace mlmix

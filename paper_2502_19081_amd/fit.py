@@ -36,6 +36,26 @@ class CheapFit:
                                          _p(species), ctypes.byref(system.box), _p(out), self.nd))
         return out
 
+    def design_many(self, items, n_streams=4):
+        """Design rows of several configurations, items = [(system, pos,
+        species, out)], spread round-robin over n_streams streams so that the
+        kernels of small configurations overlap on the device; the current
+        stream waits for all of them."""
+        main = torch.cuda.current_stream()
+        if not hasattr(self, "_streams") or len(self._streams) != n_streams:
+            self._streams = [torch.cuda.Stream() for _ in range(n_streams)]
+        start = torch.cuda.Event()
+        start.record(main)
+        for st in self._streams:
+            st.wait_event(start)
+        for k, (sy, pos, sp, out) in enumerate(items):
+            with torch.cuda.stream(self._streams[k % n_streams]):
+                self.design(sy, pos, sp, out)
+        for st in self._streams:
+            done = torch.cuda.Event()
+            done.record(st)
+            main.wait_event(done)
+
     def work(self, n_rows):
         sz = ctypes.c_size_t()
         B.check(B.lib().mlmix_fit_work_size(int(n_rows), self.nd, ctypes.byref(sz)))
@@ -56,16 +76,17 @@ class CheapFit:
         return G, b
 
     def constrained(self, GS, bS, AH, yH, alpha, tol=None, lam0=1.0, ridge=0.0, max_decades=24,
-                    max_bisect=200):
-        """The lambda search; returns (u, info dict)."""
+                    max_bisect=200, wH=None):
+        """The lambda search; returns (u, info dict). wH weights the hard rows."""
         if tol is None:
             tol = alpha / 10.0
         AH = AH.contiguous()
         u = torch.zeros(self.nd, dtype=torch.float64, device=self.device)
         info = torch.zeros(6, dtype=torch.float64, device=self.device)
-        wk = self.work(1)
+        wk = self.work(AH.shape[0])
         B.check(B.lib().mlmix_fit_constrained(self.model.handle, _stream(), self.nd, _p(GS), _p(bS),
-                                              _p(AH), self.nd, AH.shape[0], _p(yH), float(alpha),
+                                              _p(AH), self.nd, AH.shape[0], _p(yH), _p(wH),
+                                              float(alpha),
                                               float(tol), float(lam0), float(ridge),
                                               int(max_decades), int(max_bisect), _p(u), _p(info),
                                               _p(wk), wk.numel()))

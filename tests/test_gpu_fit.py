@@ -156,14 +156,15 @@ def test_fit_pipeline_matches_oracle():
     y = torch.cat([torch.cat([e.reshape(1), f.reshape(-1)]) for (_, e, f, _) in S])
     w = torch.cat([torch.cat([torch.full((1,), 1.0 / n ** 2), torch.ones(3 * n)]) for (n, _, _, _) in S]).cuda().double()
     GS, bS = fit.gram(rows, y, w)
-    AH = torch.stack([r[0] / n for (n, _, _, r) in H])
-    yH = torch.stack([e / n for (n, e, _, _) in H])
-    r_free = None
+    # hard rows: total-energy rows weighted 1/n^2 (per-atom energy errors)
+    AH = torch.stack([r[0] for (_, _, _, r) in H]).contiguous()
+    yH = torch.stack([e for (_, e, _, _) in H])
+    wH = torch.tensor([1.0 / n ** 2 for (n, _, _, _) in H], dtype=torch.float64).cuda()
     ridge = 1e-8 * float(torch.diagonal(GS).mean())
-    u0, i0 = fit.constrained(GS, bS, AH, yH, 1e30, lam0=1e-12, ridge=ridge)
+    u0, i0 = fit.constrained(GS, bS, AH, yH, 1e30, lam0=1e-12, ridge=ridge, wH=wH)
     r_free = i0["residual"]
     alpha = 1e-3 * r_free
-    u, info = fit.constrained(GS, bS, AH, yH, alpha, lam0=1e-6, ridge=ridge)
+    u, info = fit.constrained(GS, bS, AH, yH, alpha, lam0=1e-6, ridge=ridge, wH=wH)
 
     # the oracle: its own labels and design rows
     def lab(cfgs):
@@ -181,11 +182,12 @@ def test_fit_pipeline_matches_oracle():
     yr = np.concatenate([np.concatenate([[e], f.T.reshape(-1)]) for (_, e, f, _) in So])
     wr = np.concatenate([np.concatenate([[1.0 / n ** 2], np.ones(3 * n)]) for (n, _, _, _) in So])
     GSr, bSr = OF.gram(Ar, yr, wr)
-    AHr = np.stack([A[0] / n for (n, _, _, A) in Ho])
-    yHr = np.array([e / n for (n, e, _, _) in Ho])
+    AHr = np.stack([A[0] for (_, _, _, A) in Ho])
+    yHr = np.array([e for (_, e, _, _) in Ho])
+    wHr = np.array([1.0 / n ** 2 for (n, _, _, _) in Ho])
     assert np.abs(rows.cpu().numpy() - Ar).max() <= 1e-12 * np.abs(Ar).max()
     assert np.abs(y.cpu().numpy() - yr).max() <= 1e-9 * np.abs(yr).max()
-    ur, ref = OF.constrained_fit(GSr, bSr, AHr, yHr, alpha, lam0=1e-6, ridge=ridge)
+    ur, ref = OF.constrained_fit(GSr, bSr, AHr, yHr, alpha, lam0=1e-6, ridge=ridge, wH=wHr)
     print(f"  device {info}; oracle lam {ref['lam']:.6e} res {ref['residual']:.6e} "
           f"solves {ref['n_solves']} status {ref['status']}; unconstrained residual {r_free:.3e}",
           flush=True)

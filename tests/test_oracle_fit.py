@@ -194,3 +194,21 @@ def test_strain_cells_are_perfect_bcc(frame):
     assert np.all(counts == 14)   # 8 first + 6 second neighbours of bcc
     offs, _ = O.neighbors(pos, L, np.ones(3, np.int32), 0.9 * A_W)
     assert np.all(np.diff(offs) == 8)
+
+
+def test_weighted_hard_rows_equal_scaled_rows():
+    # weights w on the hard rows are the same problem as rows scaled by sqrt(w)
+    AS, yS, AH, yH, w = _lsq_problem(6, nh=12)
+    GS, bS = OF.gram(AS, yS, w)
+    wH = np.random.default_rng(1).uniform(0.01, 3.0, size=len(yH))
+    s = np.sqrt(wH)
+    c_free = OF.solve_fixed(GS, bS, 0.0 * GS, 0.0 * bS, 0.0, 0.0)
+    r_free = OF.hard_residual(AH, yH, c_free, wH)
+    r_min = OF.hard_residual(AH * s[:, None], yH * s,
+                             np.linalg.lstsq(AH * s[:, None], yH * s, rcond=None)[0])
+    alpha = r_min + 0.3 * (r_free - r_min)
+    c1, i1 = OF.constrained_fit(GS, bS, AH, yH, alpha, lam0=1e-2, wH=wH)
+    c2, i2 = OF.constrained_fit(GS, bS, AH * s[:, None], yH * s, alpha, lam0=1e-2)
+    assert i1["n_solves"] == i2["n_solves"] and i1["status"] == i2["status"] == 0
+    assert abs(i1["lam"] - i2["lam"]) <= 1e-12 * i2["lam"]
+    assert np.abs(c1 - c2).max() <= 1e-10 * np.abs(c2).max()
