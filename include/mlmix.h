@@ -322,8 +322,9 @@ int mlmix_fit_n_params(mlmix_ctx *ctx, int32_t *n_params);
  * 3-body neighbour lists (so call mlmix_compute again before
  * mlmix_backward). Errors: MLMIX_E_ARG (NULL, ld < n_params, more than 120
  * parameters, n_atoms not the workspace's), MLMIX_E_WORKSPACE (nbr_cap too
- * small for n x (8 n_params + 260) bytes in that scratch), MLMIX_E_BOX. More than 64 neighbours inside the 3-body cutoff of
- * one atom sets MLMIX_STATUS_TRIPLET_OVERFLOW (read with mlmix_status). */
+ * small for n x (8 n_params + 260) bytes in that scratch), MLMIX_E_BOX.
+ * More than 32 neighbours inside the 3-body cutoff of one atom sets
+ * MLMIX_STATUS_TRIPLET_OVERFLOW (read with mlmix_status). */
 int mlmix_fit_design(mlmix_ctx *ctx, void *stream, void *ws, int32_t n_atoms, const double *pos,
                      const int32_t *species, const mlmix_box *box, double *rows, int32_t ld);
 

@@ -164,10 +164,11 @@ __device__ FitCol fit_decode(const FitShape &sh, int k)
 // Entry of the list of i's neighbours inside the 3-body cutoff.
 struct FitLeg {
     int j, z, f;
-    double u[3], B[4], dB[4], d[3];
+    double d[3], ir, B[4], dB[4];  // d = x_j - x_i, ir = 1/|d|
 };
 
-constexpr int kFitRec = 32;  // records per batch
+constexpr int kFitRec = 16;   // records per batch
+constexpr int kFitLegs = 32;  // 3-body neighbours per atom in the design kernel
 
 // Dense records in dynamic LDS, record index fastest:
 //   pairs:    B[nf2][R], dB[nf2][R] (the 2-body basis and its derivative)
@@ -195,8 +196,8 @@ __global__ void __launch_bounds__(kFitWave)
                  const int *__restrict__ l3, const int *__restrict__ l3cnt, int *__restrict__ hdr)
 {
     extern __shared__ double smem[];
-    __shared__ FitLeg leg[kMaxTriplet];
-    __shared__ int legpre[kMaxTriplet + 1];
+    __shared__ FitLeg leg[kFitLegs];
+    __shared__ int legpre[kFitLegs + 1];
     __shared__ int nleg;
     const int i = blockIdx.x;
     const int lane = threadIdx.x;
@@ -262,15 +263,14 @@ __global__ void __launch_bounds__(kFitWave)
         const unsigned long long m3 = __ballot(in3);
         const int pos3 = nleg + __popcll(m3 & ((1ull << lane) - 1ull));
         if (in3) {
-            if (pos3 < kMaxTriplet) {
+            if (pos3 < kFitLegs) {
                 FitLeg &G = leg[pos3];
                 const double r = sqrt(r2);
                 G.j = j;
                 G.z = sp_clamp(species[j], sh.ns);
-                for (int k = 0; k < 3; ++k) {
+                G.ir = 1.0 / r;
+                for (int k = 0; k < 3; ++k)
                     G.d[k] = d[k];
-                    G.u[k] = d[k] / r;
-                }
                 fit_bspline(r, sh.nk3, sh.ih3, G.f, G.B, G.dB);
             } else {
                 atomicOr(&hdr[H_STATUS], MLMIX_STATUS_TRIPLET_OVERFLOW);
@@ -295,7 +295,7 @@ __global__ void __launch_bounds__(kFitWave)
         }
         if (lane == 0) {
             const int tot = nleg + __popcll(m3);
-            nleg = tot < kMaxTriplet ? tot : kMaxTriplet;
+            nleg = tot < kFitLegs ? tot : kFitLegs;
         }
         __syncthreads();
     }
@@ -380,8 +380,8 @@ __global__ void __launch_bounds__(kFitWave)
                     fit_bspline(rjk, sh.nk3, sh.ih3c, fs, Cw, dCw);
                     put(lane, Ga.f, Ga.B, Ga.dB, Gb.f, Gb.B, Gb.dB, fs, Cw, dCw, true);
                     for (int k = 0; k < 3; ++k) {
-                        V[k * R + lane] = Ga.u[k];
-                        V[(3 + k) * R + lane] = Gb.u[k];
+                        V[k * R + lane] = Ga.d[k] * Ga.ir;
+                        V[(3 + k) * R + lane] = Gb.d[k] * Gb.ir;
                     }
                     RZ[lane] = zi;
                     RC[lane] = 1;
@@ -430,7 +430,7 @@ __global__ void __launch_bounds__(kFitWave)
                             fit_bspline(r3, sh.nk3, sh.ih3c, fs, Cw, dCw);
                             put(lane, Ga.f, Ga.B, Ga.dB, fb, Bw, dBw, fs, Cw, dCw, false);
                             for (int q = 0; q < 3; ++q) {
-                                V[q * R + lane] = Ga.u[q];
+                                V[q * R + lane] = Ga.d[q] * Ga.ir;
                                 V[(3 + q) * R + lane] = d3[q] / r3;
                             }
                             RZ[lane] = Ga.z;
@@ -642,9 +642,16 @@ __global__ void __launch_bounds__(256) k_fit_gram_reduce(int nd, int nparts,
     const int e = blockIdx.x * 256 + threadIdx.x;
     if (e >= nblk * 16 + nd4)
         return;
-    double s = 0.0;
-    for (int p = 0; p < nparts; ++p)
-        s += part[(size_t)p * stride + e];
+    // eight running sums (partial p goes to sum p mod 8) keep eight loads in
+    // flight; they are combined in a fixed order
+    double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int p = 0;
+    for (; p + 8 <= nparts; p += 8)
+        for (int q = 0; q < 8; ++q)
+            acc[q] += part[(size_t)(p + q) * stride + e];
+    for (int q = 0; p < nparts; ++p, ++q)
+        acc[q] += part[(size_t)p * stride + e];
+    const double s = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
     if (e < nblk * 16) {
         int bi, bj;
         fit_blk(e / 16, nb, bi, bj);
