@@ -75,8 +75,6 @@ def parse():
                     help="the second workload instead: constrained linear fit of the cheap "
                          "potential to expensive-potential labels (thermal snapshots + strained "
                          "cells); prints its own JSON line")
-    ap.add_argument("--fit-streams", type=int, default=4,
-                    help="streams over which --fit spreads the design rows of its configurations")
     ap.add_argument("--fit-snapshots", type=int, default=20,
                     help="soft-constraint snapshots of the 2,000-atom cube for --fit")
     ap.add_argument("--probe", choices=["copy"], default=None,
@@ -213,7 +211,7 @@ def fit_main(args):
 
     def design_all():
         nonlocal AH
-        fit.design_many(items, n_streams=args.fit_streams)
+        fit.design_many(items)
         AH = hrows.index_select(0, h_energy_rows)
 
     def normal():
@@ -332,7 +330,6 @@ def fit_main(args):
                    "soft_rows": n_rows, "hard_rows": len(H), "labelled_atoms": n_atoms,
                    "alpha": alpha, "ridge": ridge},
         "stage_ms": {"design": stage[0], "normal_equations": stage[1], "search": stage[2]},
-        "design_streams": args.fit_streams,
         "lambda": info["lam"], "hard_residual": info["residual"], "status": info["status"],
         "n_solves": info["n_solves"], "unconstrained_hard_residual": free["residual"],
         "soft_energy_rmse_eV_per_atom": float(np.sqrt(np.mean(e_err ** 2))),
@@ -343,7 +340,7 @@ def fit_main(args):
                      "frac": design_flops / (stage[0] * 1e-3) / 1e12 / FP64_VALU_TFLOPS,
                      "traffic": None, "algorithmic_per_stage": design_flops,
                      "pairs": pairs, "centred_triplets": trip,
-                     "note": "stage time over the configurations spread on the design streams"},
+                     "note": "stage time: one batched design call over all configurations"},
         "normal_equations_hbm": {"achieved": gram_bytes / (stage[1] * 1e-3) / 1e9,
                                  "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                  "frac": gram_bytes / (stage[1] * 1e-3) / 1e9 / HBM_PEAK_GBS,

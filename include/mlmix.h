@@ -328,6 +328,23 @@ int mlmix_fit_n_params(mlmix_ctx *ctx, int32_t *n_params);
 int mlmix_fit_design(mlmix_ctx *ctx, void *stream, void *ws, int32_t n_atoms, const double *pos,
                      const int32_t *species, const mlmix_box *box, double *rows, int32_t ld);
 
+/* Several configurations in one call (one set of launches over all their
+ * atoms, 24 configurations per launch), each as for mlmix_fit_design; the
+ * array is read on the host during the call. Each workspace may appear once.
+ * Errors as for mlmix_fit_design, for the first configuration that fails
+ * (nothing is launched then). */
+typedef struct {
+    void *ws;
+    int32_t n_atoms;
+    int32_t pad;
+    const double *pos;      /* [dev] 3 x n_atoms */
+    const int32_t *species; /* [dev] n_atoms */
+    mlmix_box box;
+    double *rows;           /* [dev] (1 + 3 n_atoms) x ld */
+} mlmix_fit_config;
+int mlmix_fit_design_batch(mlmix_ctx *ctx, void *stream, int32_t n_configs,
+                           const mlmix_fit_config *configs, int32_t ld);
+
 /* Bytes of device scratch that mlmix_fit_gram needs for n_rows rows, and
  * that mlmix_fit_constrained needs with n_rows = n_hard. */
 int mlmix_fit_work_size(int64_t n_rows, int32_t n_params, size_t *bytes);

@@ -44,6 +44,12 @@ class Box(ctypes.Structure):
                 ("pad", ctypes.c_int32)]
 
 
+class FitConfig(ctypes.Structure):
+    _fields_ = [("ws", ctypes.c_void_p), ("n_atoms", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("pos", ctypes.c_void_p), ("species", ctypes.c_void_p), ("box", Box),
+                ("rows", ctypes.c_void_p)]
+
+
 class Region(ctypes.Structure):
     _fields_ = [("type", ctypes.c_int32), ("axis", ctypes.c_int32),
                 ("follow_atom", ctypes.c_int32), ("blend", ctypes.c_int32),
@@ -79,6 +85,7 @@ SIGNATURES = {
     "mlmix_fit_n_params": (ctypes.c_int, [_vp, ctypes.POINTER(_i32)]),
     "mlmix_fit_design": (ctypes.c_int, [_vp, _vp, _vp, _i32, _vp, _vp, ctypes.POINTER(Box), _vp,
                                         _i32]),
+    "mlmix_fit_design_batch": (ctypes.c_int, [_vp, _vp, _i32, _vp, _i32]),
     "mlmix_fit_work_size": (ctypes.c_int, [ctypes.c_int64, _i32, ctypes.POINTER(ctypes.c_size_t)]),
     "mlmix_fit_gram": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int64, _i32, _i32, _vp, _vp, _vp,
                                       _vp, _vp, ctypes.c_size_t]),

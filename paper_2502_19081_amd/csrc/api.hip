@@ -1425,29 +1425,72 @@ extern "C" int mlmix_fit_n_params(mlmix_ctx *ctx, int32_t *n_params)
     return MLMIX_OK;
 }
 
-extern "C" int mlmix_fit_design(mlmix_ctx *ctx, void *stream, void *ws, int32_t n_atoms,
-                                const double *pos, const int32_t *species, const mlmix_box *box,
-                                double *rows, int32_t ld)
+static int fit_config(mlmix_ctx *ctx, int nd, void *ws, int32_t n_atoms, const double *pos,
+                      const int32_t *species, const mlmix_box *box, double *rows, FitCfgHost &h)
 {
-    if (!ctx || !ws || !pos || !species || !rows)
+    if (!ws || !pos || !species || !rows)
         return fail(MLMIX_E_ARG, "NULL argument");
-    const int nd = fit_params(ctx->c);
-    if (nd < 1 || nd > kFitMaxParams)
-        return fail(MLMIX_E_ARG, "the cheap potential has more free parameters than the fit supports");
-    if (ld < nd)
-        return fail(MLMIX_E_ARG, "ld is smaller than the number of parameters");
-    WsLayout L;
-    Box b;
-    int rc = lookup(ctx, ws, n_atoms, box, L, b);
+    int rc = lookup(ctx, ws, n_atoms, box, h.L, h.box);
     if (rc)
         return rc;
     // per-atom energy rows and 3-body lists live in the pair-gradient
     // scratch of the workspace
-    const size_t avail = 2 * (L.h - L.g);
-    if ((size_t)L.n * (nd * sizeof(double) + (kMaxTriplet + 1) * sizeof(int)) > avail)
+    const size_t avail = 2 * (h.L.h - h.L.g);
+    if ((size_t)h.L.n * (nd * sizeof(double) + (kMaxTriplet + 1) * sizeof(int)) > avail)
         return fail(MLMIX_E_WORKSPACE, "workspace too small for the design rows (raise nbr_cap)");
-    launch_fit_design(static_cast<hipStream_t>(stream), ctx->c, ws, L, b, pos, species, rows, ld,
-                      at<double>(ws, L.g), nd);
+    h.ws = ws;
+    h.pos = pos;
+    h.species = species;
+    h.rows = rows;
+    return MLMIX_OK;
+}
+
+static int fit_nd_check(mlmix_ctx *ctx, int32_t ld, int &nd)
+{
+    nd = fit_params(ctx->c);
+    if (nd < 1 || nd > kFitMaxParams)
+        return fail(MLMIX_E_ARG, "the cheap potential has more free parameters than the fit supports");
+    if (ld < nd)
+        return fail(MLMIX_E_ARG, "ld is smaller than the number of parameters");
+    return MLMIX_OK;
+}
+
+extern "C" int mlmix_fit_design(mlmix_ctx *ctx, void *stream, void *ws, int32_t n_atoms,
+                                const double *pos, const int32_t *species, const mlmix_box *box,
+                                double *rows, int32_t ld)
+{
+    if (!ctx)
+        return fail(MLMIX_E_ARG, "NULL argument");
+    int nd = 0;
+    int rc = fit_nd_check(ctx, ld, nd);
+    if (rc)
+        return rc;
+    FitCfgHost h;
+    rc = fit_config(ctx, nd, ws, n_atoms, pos, species, box, rows, h);
+    if (rc)
+        return rc;
+    launch_fit_design(static_cast<hipStream_t>(stream), ctx->c, &h, 1, ld, nd);
+    HIP_OK(hipGetLastError());
+    return MLMIX_OK;
+}
+
+extern "C" int mlmix_fit_design_batch(mlmix_ctx *ctx, void *stream, int32_t n_configs,
+                                      const mlmix_fit_config *configs, int32_t ld)
+{
+    if (!ctx || (n_configs > 0 && !configs) || n_configs < 0)
+        return fail(MLMIX_E_ARG, "NULL argument or negative count");
+    int nd = 0;
+    int rc = fit_nd_check(ctx, ld, nd);
+    if (rc)
+        return rc;
+    std::vector<FitCfgHost> h((size_t)n_configs);
+    for (int q = 0; q < n_configs; ++q) {
+        const mlmix_fit_config &c = configs[q];
+        rc = fit_config(ctx, nd, c.ws, c.n_atoms, c.pos, c.species, &c.box, c.rows, h[q]);
+        if (rc)
+            return rc;
+    }
+    launch_fit_design(static_cast<hipStream_t>(stream), ctx->c, h.data(), n_configs, ld, nd);
     HIP_OK(hipGetLastError());
     return MLMIX_OK;
 }

@@ -167,6 +167,35 @@ struct FitLeg {
     double d[3], ir, B[4], dB[4];  // d = x_j - x_i, ir = 1/|d|
 };
 
+// One configuration of a batched design launch (everything per workspace).
+struct FitCfgDev {
+    int n, cap;
+    const int *nbr, *cnt;
+    const double *pos;
+    const int32_t *species;
+    double *rows, *erow;
+    int *l3, *l3cnt, *hdr;
+    Box box;
+};
+// Configurations of one launch, passed by value as kernel arguments; the
+// workgroup of global atom b belongs to the configuration whose atom range
+// [atom0[c], atom0[c+1]) holds b.
+struct FitBatch {
+    int ncfg, ld;
+    int atom0[kFitBatch + 1];
+    FitCfgDev c[kFitBatch];
+};
+
+static_assert(sizeof(FitBatch) + 64 <= 4096, "design launch arguments exceed 4 KB");
+
+__device__ __forceinline__ int fit_cfg_of(const FitBatch &B, int b)
+{
+    int c = 0;
+    while (c + 1 < B.ncfg && B.atom0[c + 1] <= b)
+        ++c;
+    return c;
+}
+
 constexpr int kFitRec = 16;   // records per batch
 constexpr int kFitLegs = 32;  // 3-body neighbours per atom in the design kernel
 
@@ -189,17 +218,26 @@ size_t fit_design_lds(int nk2, int nk3)
     return (size_t)(fit_dense(nk2, nk3) + 6) * kFitRec * sizeof(double) + 2 * kFitRec * sizeof(int);
 }
 
-__global__ void __launch_bounds__(kFitWave)
-    k_fit_design(int n, int cap, const int *__restrict__ nbr, const int *__restrict__ cnt,
-                 const double *__restrict__ pos, const int32_t *__restrict__ species, Box box,
-                 FitShape sh, double *__restrict__ rows, int ld, double *__restrict__ erow,
-                 const int *__restrict__ l3, const int *__restrict__ l3cnt, int *__restrict__ hdr)
+__global__ void __launch_bounds__(kFitWave) k_fit_design(FitBatch Bt, FitShape sh)
 {
     extern __shared__ double smem[];
     __shared__ FitLeg leg[kFitLegs];
     __shared__ int legpre[kFitLegs + 1];
     __shared__ int nleg;
-    const int i = blockIdx.x;
+    const int cfg = fit_cfg_of(Bt, blockIdx.x);
+    const FitCfgDev &Cf = Bt.c[cfg];
+    const int n = Cf.n, cap = Cf.cap, ld = Bt.ld;
+    const int *__restrict__ nbr = Cf.nbr;
+    const int *__restrict__ cnt = Cf.cnt;
+    const double *__restrict__ pos = Cf.pos;
+    const int32_t *__restrict__ species = Cf.species;
+    double *__restrict__ rows = Cf.rows;
+    double *__restrict__ erow = Cf.erow;
+    const int *__restrict__ l3 = Cf.l3;
+    const int *__restrict__ l3cnt = Cf.l3cnt;
+    int *__restrict__ hdr = Cf.hdr;
+    const Box box = Cf.box;
+    const int i = blockIdx.x - Bt.atom0[cfg];
     const int lane = threadIdx.x;
     if (i >= n)
         return;
@@ -457,12 +495,19 @@ __global__ void __launch_bounds__(kFitWave)
 
 // Every atom's neighbours inside the 3-body cutoff, in row order (at most
 // kMaxTriplet; more sets MLMIX_STATUS_TRIPLET_OVERFLOW).
-__global__ void __launch_bounds__(kFitWave)
-    k_fit_list3(int n, int cap, const int *__restrict__ nbr, const int *__restrict__ cnt,
-                const double *__restrict__ pos, Box box, double rc3sq, int *__restrict__ l3,
-                int *__restrict__ l3cnt, int *__restrict__ hdr)
+__global__ void __launch_bounds__(kFitWave) k_fit_list3(FitBatch Bt, double rc3sq)
 {
-    const int i = blockIdx.x;
+    const int cfg = fit_cfg_of(Bt, blockIdx.x);
+    const FitCfgDev &Cf = Bt.c[cfg];
+    const int n = Cf.n, cap = Cf.cap;
+    const int *__restrict__ nbr = Cf.nbr;
+    const int *__restrict__ cnt = Cf.cnt;
+    const double *__restrict__ pos = Cf.pos;
+    int *__restrict__ l3 = Cf.l3;
+    int *__restrict__ l3cnt = Cf.l3cnt;
+    int *__restrict__ hdr = Cf.hdr;
+    const Box box = Cf.box;
+    const int i = blockIdx.x - Bt.atom0[cfg];
     const int lane = threadIdx.x;
     if (i >= n)
         return;
@@ -493,12 +538,16 @@ __global__ void __launch_bounds__(kFitWave)
         l3cnt[i] = m < kMaxTriplet ? m : kMaxTriplet;
 }
 
-// rows[0][k] = sum_i erow[k][i], one workgroup per column, fixed order
-__global__ void __launch_bounds__(256) k_fit_erow_sum(int n, const double *__restrict__ erow,
-                                                      double *__restrict__ rows)
+// rows[0][k] = sum_i erow[k][i], one workgroup per (column, configuration),
+// fixed order
+__global__ void __launch_bounds__(256) k_fit_erow_sum(FitBatch Bt)
 {
     __shared__ double sh[256];
     const int k = blockIdx.x;
+    const FitCfgDev &Cf = Bt.c[blockIdx.y];
+    const int n = Cf.n;
+    const double *__restrict__ erow = Cf.erow;
+    double *__restrict__ rows = Cf.rows;
     double s = 0.0;
     for (int i = threadIdx.x; i < n; i += 256)
         s += erow[(size_t)k * n + i];
@@ -513,12 +562,8 @@ __global__ void __launch_bounds__(256) k_fit_erow_sum(int n, const double *__res
         rows[k] = sh[0];
 }
 
-void launch_fit_design(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L, const Box &b,
-                       const double *pos, const int32_t *species, double *rows, int ld,
-                       double *erow, int nd)
+void launch_fit_design(hipStream_t s, const Ctx &c, const FitCfgHost *cfg, int ncfg, int ld, int nd)
 {
-    if (L.n == 0)
-        return;
     FitShape sh;
     sh.ns = c.m.ns;
     sh.nk2 = c.d.uf3_n_knots2;
@@ -530,16 +575,40 @@ void launch_fit_design(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L,
     sh.ih2 = (double)(sh.nk2 - 1) / sh.rc2;
     sh.ih3 = sh.nk3 > 1 ? (double)(sh.nk3 - 1) / sh.rc3 : 0.0;
     sh.ih3c = sh.nk3 > 1 ? (double)(sh.nk3 - 1) / (2.0 * sh.rc3) : 0.0;
-    int *l3 = reinterpret_cast<int *>(erow + (size_t)nd * L.n);
-    int *l3cnt = l3 + (size_t)kMaxTriplet * L.n;
-    if (sh.nk3 > 1)
-        k_fit_list3<<<L.n, kFitWave, 0, s>>>(L.n, L.cap, at<int>(ws, L.nbr), at<int>(ws, L.cnt),
-                                             pos, b, sh.rc3 * sh.rc3, l3, l3cnt,
-                                             at<int>(ws, L.hdr));
-    k_fit_design<<<L.n, kFitWave, fit_design_lds(sh.nk2, sh.nk3), s>>>(L.n, L.cap, at<int>(ws, L.nbr), at<int>(ws, L.cnt), pos,
-                                          species, b, sh, rows, ld, erow, l3, l3cnt,
-                                          at<int>(ws, L.hdr));
-    k_fit_erow_sum<<<nd, 256, 0, s>>>(L.n, erow, rows);
+    for (int c0 = 0; c0 < ncfg; c0 += kFitBatch) {
+        FitBatch Bt{};
+        Bt.ld = ld;
+        int atoms = 0;
+        for (int q = 0; q < kFitBatch && c0 + q < ncfg; ++q) {
+            const FitCfgHost &h = cfg[c0 + q];
+            const WsLayout &L = h.L;
+            if (L.n == 0)
+                continue;
+            FitCfgDev &d = Bt.c[Bt.ncfg];
+            d.n = L.n;
+            d.cap = L.cap;
+            d.nbr = at<int>(h.ws, L.nbr);
+            d.cnt = at<int>(h.ws, L.cnt);
+            d.pos = h.pos;
+            d.species = h.species;
+            d.rows = h.rows;
+            d.erow = at<double>(h.ws, L.g);
+            d.l3 = reinterpret_cast<int *>(d.erow + (size_t)nd * L.n);
+            d.l3cnt = d.l3 + (size_t)kMaxTriplet * L.n;
+            d.hdr = at<int>(h.ws, L.hdr);
+            d.box = h.box;
+            Bt.atom0[Bt.ncfg] = atoms;
+            atoms += L.n;
+            ++Bt.ncfg;
+        }
+        if (Bt.ncfg == 0)
+            continue;
+        Bt.atom0[Bt.ncfg] = atoms;
+        if (sh.nk3 > 1)
+            k_fit_list3<<<atoms, kFitWave, 0, s>>>(Bt, sh.rc3 * sh.rc3);
+        k_fit_design<<<atoms, kFitWave, fit_design_lds(sh.nk2, sh.nk3), s>>>(Bt, sh);
+        k_fit_erow_sum<<<dim3(nd, Bt.ncfg), 256, 0, s>>>(Bt);
+    }
 }
 
 // ------------------------------------------------------------------ Gram

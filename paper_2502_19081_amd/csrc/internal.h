@@ -229,10 +229,19 @@ void launch_copy_i32(hipStream_t s, int32_t *dst, const int32_t *src, size_t n);
 
 // ---- fit.hip (constrained linear fitting of the cheap potential) ----
 constexpr int kFitMaxParams = 120;  // packed Cholesky factor of the search in LDS
-// erow: scratch of nd * n doubles (per-atom energy rows, column-major)
-void launch_fit_design(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L, const Box &b,
-                       const double *pos, const int32_t *species, double *rows, int ld,
-                       double *erow, int nd);
+constexpr int kFitBatch = 24;       // configurations per design launch (kernel-argument size)
+// One configuration of a design call: its workspace (whose pair-gradient
+// scratch holds the per-atom energy rows and 3-body lists), positions,
+// species, box and output rows.
+struct FitCfgHost {
+    void *ws;
+    WsLayout L;
+    Box box;
+    const double *pos;
+    const int32_t *species;
+    double *rows;
+};
+void launch_fit_design(hipStream_t s, const Ctx &c, const FitCfgHost *cfg, int ncfg, int ld, int nd);
 size_t fit_gram_parts(long long nrows, long long &chunk);
 size_t fit_gram_part_bytes(int nd, size_t parts);
 void launch_fit_gram(hipStream_t s, long long nrows, int nd, int ld, const double *A,

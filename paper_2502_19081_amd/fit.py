@@ -36,25 +36,20 @@ class CheapFit:
                                          _p(species), ctypes.byref(system.box), _p(out), self.nd))
         return out
 
-    def design_many(self, items, n_streams=4):
-        """Design rows of several configurations, items = [(system, pos,
-        species, out)], spread round-robin over n_streams streams so that the
-        kernels of small configurations overlap on the device; the current
-        stream waits for all of them."""
-        main = torch.cuda.current_stream()
-        if not hasattr(self, "_streams") or len(self._streams) != n_streams:
-            self._streams = [torch.cuda.Stream() for _ in range(n_streams)]
-        start = torch.cuda.Event()
-        start.record(main)
-        for st in self._streams:
-            st.wait_event(start)
+    def design_many(self, items):
+        """Design rows of several configurations in one call, items =
+        [(system, pos, species, out)] (one set of launches over all atoms)."""
+        arr = (B.FitConfig * len(items))()
         for k, (sy, pos, sp, out) in enumerate(items):
-            with torch.cuda.stream(self._streams[k % n_streams]):
-                self.design(sy, pos, sp, out)
-        for st in self._streams:
-            done = torch.cuda.Event()
-            done.record(st)
-            main.wait_event(done)
+            assert out.shape == (1 + 3 * sy.n, self.nd) and out.is_contiguous()
+            arr[k].ws = sy.ws.data_ptr()
+            arr[k].n_atoms = sy.n
+            arr[k].pos = pos.data_ptr()
+            arr[k].species = sp.data_ptr()
+            arr[k].box = sy.box
+            arr[k].rows = out.data_ptr()
+        B.check(B.lib().mlmix_fit_design_batch(self.model.handle, _stream(), len(items), arr,
+                                               self.nd))
 
     def work(self, n_rows):
         sz = ctypes.c_size_t()

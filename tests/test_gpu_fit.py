@@ -198,3 +198,30 @@ def test_fit_pipeline_matches_oracle():
     pu = Ar @ u.cpu().numpy()
     pr = Ar @ ur
     assert np.abs(pu - pr).max() <= 1e-6 * np.abs(pr).max()
+
+
+def test_batched_design_equals_single_calls():
+    # 30 strained cells of three sizes (two launches of the batched call)
+    import torch
+    from paper_2502_19081_amd import binding as B
+    from paper_2502_19081_amd import core
+    from paper_2502_19081_amd.fit import CheapFit
+    print("case fit design, 30 configurations in one batched call vs one call each", flush=True)
+    model = core.Model(FD.fit_model(), precision="fp64")
+    fit = CheapFit(model)
+    cfgs = FD.strained_cells(n_strain=5)
+    cfgs = cfgs[::1][:30]
+    items = []
+    for c in cfgs:
+        n = len(c["pos"])
+        sy = core.System(model, n, c["L"], c["periodic"], cap=128)
+        pos = _dev(c["pos"].T)
+        sp = torch.zeros(n, dtype=torch.int32, device="cuda")
+        sy.compute(pos, sp, mode=B.MODE_ALL_CHEAP, force_rebuild=True)
+        items.append((sy, pos, sp, torch.full((1 + 3 * n, fit.nd), float("nan"),
+                                              dtype=torch.float64, device="cuda")))
+    fit.design_many(items)
+    for sy, pos, sp, out in items:
+        ref = fit.design(sy, pos, sp)
+        sy.status()
+        assert torch.equal(out, ref)
