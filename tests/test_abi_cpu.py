@@ -30,6 +30,22 @@ def test_struct_layouts():
     from paper_2502_19081_amd import binding as B
     assert ctypes.sizeof(B.Region) == 56
     assert ctypes.sizeof(B.Box) == 40
+    assert ctypes.sizeof(B.FitConfig) == 80
+    assert B.FitConfig.box.offset == 32 and B.FitConfig.rows.offset == 72
+
+
+def test_fit_work_size_is_host_only_and_checks_sizes():
+    from paper_2502_19081_amd import binding as B
+    sz = ctypes.c_size_t()
+    assert B.lib().mlmix_fit_work_size(120020, 81, ctypes.byref(sz)) == 0
+    # G_H and b_H of the search, then the Gram partials (at most 512 chunks of
+    # the upper-triangle 4x4 blocks plus the padded right-hand side)
+    nb = (81 + 3) // 4
+    per_part = (nb * (nb + 1) // 2 * 16 + nb * 4) * 8
+    assert sz.value >= (81 * 81 + 81) * 8 + per_part
+    assert sz.value <= (81 * 81 + 81) * 8 + 512 * per_part
+    assert B.lib().mlmix_fit_work_size(10, 121, ctypes.byref(sz)) == -1
+    assert B.lib().mlmix_fit_work_size(-1, 81, ctypes.byref(sz)) == -1
     assert B.ModelDesc.uf3_c3.offset == ctypes.sizeof(B.ModelDesc) - 8
 
 

@@ -225,3 +225,51 @@ def test_batched_design_equals_single_calls():
         ref = fit.design(sy, pos, sp)
         sy.status()
         assert torch.equal(out, ref)
+
+
+def test_design_row_stride_and_empty_edge_cases():
+    # ld wider than the parameter count leaves the padding columns untouched;
+    # an empty row set leaves G and b as they were; no hard rows leaves the
+    # unconstrained (ridge) solution at lambda0 with status 0
+    import ctypes
+    import torch
+    from paper_2502_19081_amd import binding as B
+    from paper_2502_19081_amd import core
+    from paper_2502_19081_amd.core import _p, _stream
+    from paper_2502_19081_amd.fit import CheapFit
+    print("case fit edge cases: row stride, empty Gram, no hard rows", flush=True)
+    model = core.Model(FD.fit_model(), precision="fp64")
+    fit = CheapFit(model)
+    c = FD.strained_cells(n_strain=3)[1]
+    n = len(c["pos"])
+    sy = core.System(model, n, c["L"], c["periodic"], cap=128)
+    pos = _dev(c["pos"].T)
+    sp = torch.zeros(n, dtype=torch.int32, device="cuda")
+    sy.compute(pos, sp, mode=B.MODE_ALL_CHEAP, force_rebuild=True)
+    ld = fit.nd + 7
+    wide = torch.full((1 + 3 * n, ld), float("nan"), dtype=torch.float64, device="cuda")
+    B.check(B.lib().mlmix_fit_design(model.handle, _stream(), _p(sy.ws), n, _p(pos), _p(sp),
+                                     ctypes.byref(sy.box), _p(wide), ld))
+    ref = fit.design(sy, pos, sp)
+    sy.status()
+    assert torch.equal(wide[:, :fit.nd], ref)
+    assert torch.isnan(wide[:, fit.nd:]).all()
+
+    G = torch.full((fit.nd, fit.nd), 2.0, dtype=torch.float64, device="cuda")
+    b = torch.full((fit.nd,), 3.0, dtype=torch.float64, device="cuda")
+    empty = torch.zeros(0, fit.nd, dtype=torch.float64, device="cuda")
+    fit.gram(empty, None, None, G, b)
+    assert bool((G == 2.0).all()) and bool((b == 3.0).all())
+
+    r = np.random.default_rng(3)
+    A = r.normal(size=(300, fit.nd))
+    y = r.normal(size=300)
+    GS, bS = OF.gram(A, y, np.ones(300))
+    ridge = 1e-3
+    u, info = fit.constrained(_dev(GS), _dev(bS), torch.zeros(0, fit.nd, dtype=torch.float64,
+                                                               device="cuda"),
+                              torch.zeros(0, dtype=torch.float64, device="cuda"), 1e-6,
+                              lam0=1e-3, ridge=ridge)
+    assert info["status"] == 0 and info["n_solves"] == 1 and info["residual"] == 0.0
+    want = OF.solve_fixed(GS, bS, np.zeros_like(GS), np.zeros_like(bS), 0.0, ridge)
+    assert np.abs(u.cpu().numpy() - want).max() <= 1e-10 * np.abs(want).max()
