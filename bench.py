@@ -405,18 +405,19 @@ def main():
 
     dt = float(w.get("dt", 1.0))
 
-    def step(sy, pos, vel, sp, mode):
-        sy.vv_step(pos, vel, mass, sp, dt, r_buffer=w["r_buffer"], mode=mode, force_rebuild=True,
-                   single_stream=args.single_stream, cheap_masked=args.cheap_masked)
+    def step(sy, pos, vel, sp, mode, rebuild=True):
+        sy.vv_step(pos, vel, mass, sp, dt, r_buffer=w["r_buffer"], mode=mode,
+                   force_rebuild=rebuild, single_stream=args.single_stream,
+                   cheap_masked=args.cheap_masked)
 
-    def run(mode, steps, warmup, stage_mask=0, latency=False, graph=False):
+    def run(mode, steps, warmup, stage_mask=0, latency=False, graph=False, rebuild=True):
         """Times `steps` steps. graph=True captures `chunk` consecutive steps
         (args.graph_steps when it divides `steps`, one step when latency is
         timed) in one HIP graph and replays it; otherwise the step's kernels
         are launched eagerly."""
         sy, pos, vel, sp = fresh(mode)
         for _ in range(warmup):
-            step(sy, pos, vel, sp, mode)
+            step(sy, pos, vel, sp, mode, rebuild)
         sy.status()
         g = None
         chunk = 1
@@ -429,7 +430,7 @@ def main():
             with torch.cuda.stream(cs):
                 with torch.cuda.graph(g, stream=cs):
                     for _ in range(chunk):
-                        step(sy, pos, vel, sp, mode)
+                        step(sy, pos, vel, sp, mode, rebuild)
             torch.cuda.current_stream().wait_stream(cs)
             for _ in range(3):
                 g.replay()
@@ -443,7 +444,7 @@ def main():
             if g is not None:
                 g.replay()
             else:
-                step(sy, pos, vel, sp, mode)
+                step(sy, pos, vel, sp, mode, rebuild)
             if latency:
                 torch.cuda.synchronize()
                 lat.append(time.perf_counter() - ts)
@@ -491,6 +492,7 @@ def main():
     # 4. all-expensive and all-cheap rates on the same GPU, same method
     rate_e = rate_c = None
     lat_ms = None
+    rate_skin = None
     if not args.only_mixed:
         el_e, _, _, _ = run(B.MODE_ALL_EXPENSIVE, args.steps, args.warmup, graph=True)
         el_c, _, _, _ = run(B.MODE_ALL_CHEAP, args.steps, args.warmup, graph=True)
@@ -502,6 +504,13 @@ def main():
         # 5. step latency (each replay waited for)
         _, _, lat, _ = run(B.MODE_MIXED, args.steps, 5, latency=True, graph=True)
         lat_ms = np.array(lat) * 1e3
+        # 6. the same mixed steps with the neighbour list kept while no atom
+        # has moved half the skin (the MD engine's usual check; lambda, the
+        # buffer and both potentials are still evaluated every step)
+        el_s, _, _, sy_s = run(B.MODE_MIXED, args.steps, args.warmup, graph=True, rebuild=False)
+        rate_skin = n * args.steps / el_s
+        print(f"bench: mixed with skin reuse {1e3 * el_s / args.steps:.4f} ms/step",
+              file=sys.stderr, flush=True)
 
     # work counts of the initial configuration (for the roofline)
     sy, pos, vel, sp = fresh(B.MODE_MIXED)
@@ -625,6 +634,7 @@ def main():
         "all_expensive_atom_steps_per_s": rate_e,
         "all_cheap_atom_steps_per_s": rate_c,
         "mixed_over_all_expensive": value / rate_e if rate_e else None,
+        "skin_reuse_atom_steps_per_s": rate_skin,
         "S_UL": s_ul,
         "force_err_max_eV_per_A": ferr,
         "p50_step_ms": float(np.percentile(lat_ms, 50)) if lat_ms is not None else None,
