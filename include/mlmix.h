@@ -400,6 +400,17 @@ int mlmix_profile_enable(mlmix_ctx *ctx, uint32_t stage_mask);
 int mlmix_profile_read(mlmix_ctx *ctx, double *ms, int64_t *count);
 const char *mlmix_profile_stage_name(int32_t stage);
 
+/* Benchmark hook: launches the kernels of one stage reps times, back to back
+ * on `stream`, on the data the last evaluation left in ws (the stage reads
+ * and writes workspace arrays only, so every replay does the same work).
+ * Only stage 4 (the expensive order-3 contraction) is supported; species as
+ * in mlmix_compute. Timing these launches with two events gives the kernel's
+ * own duration without the dispatch gap in front of it. Errors: MLMIX_E_ARG
+ * (NULL, negative reps, another stage, n_atoms not the workspace's),
+ * MLMIX_E_STATE (workspace not initialised). */
+int mlmix_profile_replay(mlmix_ctx *ctx, void *stream, void *ws, int32_t n_atoms,
+                         const int32_t *species, int32_t stage, int32_t reps);
+
 /* Operation counts of the kernels as written, for roofline reporting
  * (out[6]): [0] expensive order-3 contraction per S atom, [1] atomic basis
  * per expensive pair, [2] pair adjoint per expensive pair, [3] cheap 2-body

@@ -1566,6 +1566,30 @@ extern "C" int mlmix_profile_enable(mlmix_ctx *ctx, uint32_t stage_mask)
     return MLMIX_OK;
 }
 
+extern "C" int mlmix_profile_replay(mlmix_ctx *ctx, void *stream, void *ws, int32_t n_atoms,
+                                    const int32_t *species, int32_t stage, int32_t reps)
+{
+    if (!ctx || !ws || !species || reps < 0)
+        return fail(MLMIX_E_ARG, "NULL argument or negative count");
+    if (stage != ST_CONTRACT)
+        return fail(MLMIX_E_ARG, "only the order-3 contraction (stage 4) can be replayed");
+    WsLayout L;
+    {
+        std::lock_guard<std::mutex> g(ctx->mu);
+        auto it = ctx->ws.find(ws);
+        if (it == ctx->ws.end())
+            return fail(MLMIX_E_STATE, "workspace was not initialised");
+        L = it->second;
+    }
+    if (L.n != n_atoms)
+        return fail(MLMIX_E_ARG, "n_atoms differs from the workspace's");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    for (int r = 0; r < reps; ++r)
+        launch_ace_contract(s, ctx->c, ws, L, species);
+    HIP_OK(hipGetLastError());
+    return MLMIX_OK;
+}
+
 extern "C" int mlmix_profile_read(mlmix_ctx *ctx, double *ms, int64_t *count)
 {
     if (!ctx || !ms || !count)
