@@ -99,6 +99,50 @@ def copy_probe():
                       "bytes_written_per_launch": 4 * n, "launches": 20}))
 
 
+def measured_peaks():
+    """Achievable peaks on this GPU: a 256 MiB device copy (bytes read plus
+    written per second) and the FP32 matrix-core probe of the library."""
+    import ctypes
+    import torch
+    from paper_2502_19081_amd import binding as B
+    n = 64 << 20
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(20):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    hbm = 20 * 2 * 4 * n / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    sink = torch.zeros(2048, dtype=torch.float32, device="cuda")
+    fl = ctypes.c_double()
+    cur = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    B.check(B.lib().mlmix_probe_mfma_f32(cur, 2048, 256, ctypes.c_void_p(sink.data_ptr()),
+                                         ctypes.byref(fl)))
+    e0.record()
+    B.check(B.lib().mlmix_probe_mfma_f32(cur, 2048, 4096, ctypes.c_void_p(sink.data_ptr()),
+                                         ctypes.byref(fl)))
+    e1.record()
+    torch.cuda.synchronize()
+    mfma = fl.value / (e0.elapsed_time(e1) * 1e-3) / 1e12
+    return {"hbm_copy_GBps": hbm, "mfma_fp32_TFLOPs": mfma}
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 KERNEL_SOURCES = {"ace_contract": ["paper_2502_19081_amd/csrc/o3.hip", "paper_2502_19081_amd/csrc/internal.h"]}
 
 
@@ -605,6 +649,13 @@ def main():
                 "avg_ms": dom_avg_ms, "launches": dom_cnt, "algorithmic_per_launch": units,
                 "timing": dom_method, "in_step_bracket_ms": dom_in_step_ms}
 
+    peaks = measured_peaks()
+    roof["peak_measured"] = peaks
+    if roof["unit"] == "GB/s":
+        roof["frac_of_measured"] = roof["achieved"] / peaks["hbm_copy_GBps"]
+    elif roof["bound"] == "mfma" and prec == "fp32":
+        roof["frac_of_measured"] = roof["achieved"] / peaks["mfma_fp32_TFLOPs"]
+
     # 6. CPU baseline: the FP64 reference on this host, bounded sample of the
     # same workload (its first force call also gives the force error)
     cpu = None
@@ -623,7 +674,7 @@ def main():
         t_cpu = time.perf_counter() - t0
         ferr = float(np.abs(gpu_forces[sub] - ref["forces"][sub]).max())
         cpu = {"value": len(sub) / t_cpu, "unit": "atom-steps/s", "cores": O.num_threads(),
-               "kind": "oracle",
+               "kind": "oracle", "cpu_model": cpu_model(),
                "sample": f"one mixed FP64 force call of the same {cfg} cell with forces on the "
                          f"{len(sub)} atoms of a 40 A cube around a vacancy (neighbour list, "
                          f"lambda and buffer over the whole cell), rate = cube atoms / time"}
@@ -638,10 +689,21 @@ def main():
         O.velocity_verlet(w, w["pos"], vel0, float(w.get("dt", 1.0)), n_cpu, mode=O.MODE_MIXED,
                           cheap_masked=args.cheap_masked)
         t_cpu = time.perf_counter() - t0
-        cpu = {"value": n * n_cpu / t_cpu, "unit": "atom-steps/s", "cores": O.num_threads(),
-               "kind": "oracle",
+        # one thread, a shorter sample of the same steps
+        cores = O.num_threads()
+        O.set_threads(1)
+        n1 = max(1, n_cpu // max(cores, 1))
+        t0 = time.perf_counter()
+        O.velocity_verlet(w, w["pos"], vel0, float(w.get("dt", 1.0)), n1, mode=O.MODE_MIXED,
+                          cheap_masked=args.cheap_masked)
+        t1 = time.perf_counter() - t0
+        O.set_threads(cores)
+        cpu = {"value": n * n_cpu / t_cpu, "unit": "atom-steps/s", "cores": cores,
+               "kind": "oracle", "cpu_model": cpu_model(),
+               "value_1_thread": n * n1 / t1,
                "sample": f"{n_cpu} velocity-Verlet steps of the same {cfg} workload in mixed mode "
-                         f"(plus one initial force call), FP64, neighbour list rebuilt every step"}
+                         f"(plus one initial force call), FP64, neighbour list rebuilt every step; "
+                         f"{n1} steps on one thread for value_1_thread"}
 
     s_ul = None
     if rate_e:

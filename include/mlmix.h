@@ -411,6 +411,13 @@ const char *mlmix_profile_stage_name(int32_t stage);
 int mlmix_profile_replay(mlmix_ctx *ctx, void *stream, void *ws, int32_t n_atoms,
                          const int32_t *species, int32_t stage, int32_t reps);
 
+/* Achievable-peak probe: launches `blocks` workgroups of four waves, each
+ * running `iters` rounds of eight independent FP32 16x16x4 matrix-core
+ * chains on register operands; *flops receives the launch's flop count (the
+ * caller times the launch with events on `stream`). sink [dev] float[blocks]
+ * is never written in practice (it keeps the work). */
+int mlmix_probe_mfma_f32(void *stream, int32_t blocks, int32_t iters, float *sink, double *flops);
+
 /* Operation counts of the kernels as written, for roofline reporting
  * (out[6]): [0] expensive order-3 contraction per S atom, [1] atomic basis
  * per expensive pair, [2] pair adjoint per expensive pair, [3] cheap 2-body

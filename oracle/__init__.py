@@ -62,6 +62,10 @@ def num_threads():
     return int(lib().or_num_threads())
 
 
+def set_threads(n):
+    lib().or_set_threads(ctypes.c_int(int(n)))
+
+
 # ---------------------------------------------------------------- geometry
 
 def neighbors(pos, L, periodic, r_list, method=1):

@@ -79,6 +79,17 @@ int or_num_threads(void)
 #endif
 }
 
+/* Threads of the later parallel regions (timing of the baseline only). */
+void or_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0)
+        omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------------ */
 /* Neighbour set: N(i) = { j != i : |d_ij|^2 < r_list^2 }, rows ascending.   */
 /* method 0 = all pairs, method 1 = cell bins of edge >= r_list.             */

@@ -1590,6 +1590,18 @@ extern "C" int mlmix_profile_replay(mlmix_ctx *ctx, void *stream, void *ws, int3
     return MLMIX_OK;
 }
 
+extern "C" int mlmix_probe_mfma_f32(void *stream, int32_t blocks, int32_t iters, float *sink,
+                                    double *flops)
+{
+    if (!sink || !flops || blocks < 1 || iters < 1)
+        return fail(MLMIX_E_ARG, "NULL argument or non-positive size");
+    launch_probe_mfma_f32(static_cast<hipStream_t>(stream), blocks, iters, sink);
+    HIP_OK(hipGetLastError());
+    // 4 waves per block, 8 chains per round, 2 * 16 * 16 * 4 flops per MFMA
+    *flops = (double)blocks * 4.0 * (double)iters * 8.0 * 2048.0;
+    return MLMIX_OK;
+}
+
 extern "C" int mlmix_profile_read(mlmix_ctx *ctx, double *ms, int64_t *count)
 {
     if (!ctx || !ms || !count)

@@ -226,6 +226,7 @@ void launch_vv_kick_drift(hipStream_t s, void *ws, const WsLayout &L, const Box 
                           double *vel, const double *mass, const double *forces, double dt,
                           int drift);
 void launch_copy_i32(hipStream_t s, int32_t *dst, const int32_t *src, size_t n);
+void launch_probe_mfma_f32(hipStream_t s, int blocks, int iters, float *sink);
 
 // ---- fit.hip (constrained linear fitting of the cheap potential) ----
 constexpr int kFitMaxParams = 120;  // packed Cholesky factor of the search in LDS

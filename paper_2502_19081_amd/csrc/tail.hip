@@ -366,4 +366,34 @@ void launch_vv_kick_drift(hipStream_t s, void *ws, const WsLayout &L, const Box 
     k_vv<<<(L.n + 255) / 256, 256, 0, s>>>(L.n, b, pos, vel, mass, forces, dt, drift);
 }
 
+// ------------------------------------------------------------ peak probe
+
+// Matrix-core FP32 throughput: every wave runs `iters` rounds of eight
+// independent 16x16x4 MFMA chains on register operands (no memory traffic)
+// and stores one value so that the work is kept.
+__global__ void __launch_bounds__(256) k_probe_mfma_f32(int iters, float *sink)
+{
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    const int lane = threadIdx.x & 63;
+    const float a = 1.0f + 1e-7f * (float)lane, b = 1.0f - 1e-7f * (float)threadIdx.x;
+    f4 c[8];
+    for (int k = 0; k < 8; ++k)
+        c[k] = (f4){0.f, 0.f, 0.f, 0.f};
+    for (int it = 0; it < iters; ++it) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            c[k] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c[k], 0, 0, 0);
+    }
+    float s = 0.f;
+    for (int k = 0; k < 8; ++k)
+        s += c[k][0] + c[k][1] + c[k][2] + c[k][3];
+    if (s == -1.0f)  // never true; keeps the chains
+        sink[blockIdx.x] = s;
+}
+
+void launch_probe_mfma_f32(hipStream_t s, int blocks, int iters, float *sink)
+{
+    k_probe_mfma_f32<<<blocks, 256, 0, s>>>(iters, sink);
+}
+
 }  // namespace mlmix

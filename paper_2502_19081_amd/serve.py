@@ -266,7 +266,9 @@ def main(argv=None):
     rep.update({"workload": "c4: W(001)+He impact replicas, log-uniform 2,000-20,000 atoms, "
                             "dt 0.2 fs, 8 A sphere following He, FP32 potentials",
                 "steps_per_replica": args.steps, "arrival_rate_hz": args.rate,
-                "slots": args.slots, "graph": args.graph})
+                "slots": args.slots, "graph": args.graph,
+                "hbm_budget_bytes": srv.budget,
+                "hbm_peak_allocated_bytes": int(torch.cuda.max_memory_allocated())})
     print(json.dumps(rep))
     return rep
 
