@@ -625,6 +625,24 @@ def main():
         "integrator": ("bytes", 2 * 88 * n),
         "energy_sums": ("bytes", 48 * n),
     }
+    # every stage against its bound from the bracketed per-step times of the
+    # breakdown (a bracket also holds the dispatch gap, so these achieved
+    # figures are lower bounds; stages on the second stream overlap)
+    stage_roof = {}
+    for k, (kd, u) in work.items():
+        t = stage_ms.get(k)
+        if not t:
+            continue
+        if kd == "flops":
+            pk = FP64_VALU_TFLOPS if prec == "fp64" else FP32_VALU_TFLOPS
+            if k == "ace_contract" and prec != "fp64" and w["model"]["n_species"] == 1:
+                pk = MFMA_TFLOPS["fp32"]
+            a_ = u / (t * 1e-3) / 1e12
+            stage_roof[k] = {"unit": "TFLOP/s", "achieved": a_, "peak": pk, "frac": a_ / pk}
+        else:
+            a_ = u / (t * 1e-3) / 1e9
+            stage_roof[k] = {"unit": "GB/s", "achieved": a_, "peak": HBM_PEAK_GBS,
+                             "frac": a_ / HBM_PEAK_GBS}
     traffic = measured_traffic(dominant, cfg, prec)
     kind, units = work[dominant]
     if kind == "flops":
@@ -734,6 +752,7 @@ def main():
         "p50_step_ms": float(np.percentile(lat_ms, 50)) if lat_ms is not None else None,
         "p99_step_ms": float(np.percentile(lat_ms, 99)) if lat_ms is not None else None,
         "stage_ms_per_step": {k: round(v, 5) for k, v in stage_ms.items()},
+        "stage_roofline": stage_roof,
         "roofline": roof,
         "cpu_baseline": cpu,
     }
