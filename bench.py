@@ -457,6 +457,19 @@ def main():
                    force_rebuild=rebuild, single_stream=args.single_stream,
                    cheap_masked=args.cheap_masked)
 
+    en_buf = torch.zeros(max(args.graph_steps, 1), 3, dtype=torch.float64, device=dev)
+
+    def steps_fused(sy, pos, vel, sp, mode, k, rebuild=True):
+        # k steps in one call (the library fuses them up to 65,536 atoms);
+        # with the thermostat every step needs its own normals
+        if args.langevin or k == 1:
+            for _ in range(k):
+                step(sy, pos, vel, sp, mode, rebuild)
+            return
+        sy.vv_steps(pos, vel, mass, sp, dt, k, r_buffer=w["r_buffer"], mode=mode,
+                    force_rebuild=rebuild, single_stream=args.single_stream,
+                    cheap_masked=args.cheap_masked, energies=en_buf[:k])
+
     def run(mode, steps, warmup, stage_mask=0, latency=False, graph=False, rebuild=True):
         """Times `steps` steps. graph=True captures `chunk` consecutive steps
         (args.graph_steps when it divides `steps`, one step when latency is
@@ -476,8 +489,7 @@ def main():
             cs.wait_stream(torch.cuda.current_stream())
             with torch.cuda.stream(cs):
                 with torch.cuda.graph(g, stream=cs):
-                    for _ in range(chunk):
-                        step(sy, pos, vel, sp, mode, rebuild)
+                    steps_fused(sy, pos, vel, sp, mode, chunk, rebuild)
             torch.cuda.current_stream().wait_stream(cs)
             for _ in range(3):
                 g.replay()
@@ -739,7 +751,8 @@ def main():
                    "thermostat": ("Langevin 300 K, 2 ps, lambda == 0 atoms" if args.langevin
                                   else "none (NVE)"),
                    "precision": prec, "neighbour_rebuild": "every step", "n_S": nS, "n_lambda_pos": nM,
-                   "launch": (f"{args.graph_steps} consecutive steps per captured HIP graph, "
+                   "launch": (f"{args.graph_steps} consecutive steps per captured HIP graph "
+                              f"({'one step per call' if args.langevin else 'one fused multi-step call'}), "
                               "replayed" if args.steps % args.graph_steps == 0 and args.graph_steps > 1
                               else "one captured HIP graph per step, replayed")},
         "eager_atom_steps_per_s": n * args.steps / el_eager,

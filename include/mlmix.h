@@ -253,6 +253,21 @@ int mlmix_vv_step(mlmix_ctx *ctx, void *stream, void *ws, int32_t n_atoms, doubl
                   double *e_cheap, double *lambda, uint8_t *flags, int32_t *n_expensive,
                   double *energies);
 
+/* n_steps velocity-Verlet steps in one call, each exactly as mlmix_vv_step
+ * (same results bit for bit); energies [dev] double[n_steps][3] receives the
+ * sums of every step (required). Up to 65,536 atoms the steps are fused: the
+ * force gather of a step also applies the next step's opening half kick and
+ * drift, and the next step's binning kernel sums the previous step's
+ * energies, so a step launches two kernels fewer. With a thermostat set
+ * (mlmix_set_langevin) only n_steps = 1 is accepted (each step needs fresh
+ * normals): MLMIX_E_STATE otherwise. Other errors as for mlmix_vv_step. */
+int mlmix_vv_steps(mlmix_ctx *ctx, void *stream, void *ws, int32_t n_atoms, double *pos,
+                   double *vel, const double *mass, const int32_t *species, double dt,
+                   int32_t n_steps, const mlmix_box *box, const mlmix_region *regions,
+                   int32_t n_regions, double r_buffer, uint32_t mode, double *forces,
+                   double *e_exp, double *e_cheap, double *lambda, uint8_t *flags,
+                   int32_t *n_expensive, double *energies);
+
 /* Langevin thermostat on the cheap region for mlmix_vv_step on workspace ws
  * (Methods, "Si stretched bond" and "Diffusion coefficients": a weak
  * thermostat, time constant 2 ps, acting only where the cheap potential

@@ -77,6 +77,9 @@ SIGNATURES = {
     "mlmix_vv_step": (ctypes.c_int, [_vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp, _d, ctypes.POINTER(Box),
                                      _vp, _i32, _d, _u32, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "mlmix_set_langevin": (ctypes.c_int, [_vp, _vp, _i32, _d, _d, _vp]),
+    "mlmix_vv_steps": (ctypes.c_int, [_vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp, _d, _i32,
+                                      ctypes.POINTER(Box), _vp, _i32, _d, _u32, _vp, _vp, _vp,
+                                      _vp, _vp, _vp, _vp]),
     "mlmix_energy_reduce": (ctypes.c_int, [_vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp, _vp]),
     "mlmix_status": (ctypes.c_int, [_vp, _vp, _vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
     "mlmix_get_neighbors": (ctypes.c_int, [_vp, _vp, _vp, _i32, _vp, _vp]),

@@ -220,6 +220,25 @@ class System:
                                       _p(self.e_cheap), _p(self.lam), _p(self.flags),
                                       _p(self.n_exp), _p(self.energies) if energies else None))
 
+    def vv_steps(self, pos, vel, mass, species, dt, n_steps, r_buffer=0.0, mode=B.MODE_MIXED,
+                 force_rebuild=False, single_stream=False, cheap_masked=False, energies=None):
+        """n_steps velocity-Verlet steps in one call (fused up to 65,536
+        atoms); returns the (n_steps, 3) energy sums of every step. Not with
+        the thermostat."""
+        self.generation += n_steps
+        flags = mode | (B.FORCE_REBUILD if force_rebuild else 0) | (B.SINGLE_STREAM if single_stream else 0)
+        flags |= self._seed_mode() | (B.CHEAP_MASKED if cheap_masked else 0)
+        if energies is None:
+            energies = torch.zeros(n_steps, 3, dtype=torch.float64, device=self.device)
+        B.check(B.lib().mlmix_vv_steps(self.model.handle, _stream(), _p(self.ws), self.n, _p(pos),
+                                       _p(vel), _p(mass), _p(species), float(dt), int(n_steps),
+                                       ctypes.byref(self.box), _p(self.regions), self.n_regions,
+                                       float(r_buffer), flags, _p(self.forces), _p(self.e_exp),
+                                       _p(self.e_cheap), _p(self.lam), _p(self.flags),
+                                       _p(self.n_exp), _p(energies)))
+        self.energies.copy_(energies[-1])
+        return energies
+
     def energy_reduce(self, vel=None, mass=None):
         B.check(B.lib().mlmix_energy_reduce(self.model.handle, _stream(), _p(self.ws), self.n,
                                             _p(self.e_exp), _p(self.e_cheap), _p(vel), _p(mass),

@@ -1003,7 +1003,8 @@ static int compute_impl(mlmix_ctx *ctx, hipStream_t s, void *ws, const WsLayout 
                         int32_t n_regions, double r_buffer, uint32_t mode, double *forces,
                         double *e_exp, double *e_cheap, double *lambda, uint8_t *flags,
                         int32_t *n_expensive, double *f_exp, double *f_cheap,
-                        const KickArgs *kick = nullptr, const LangevinArgs *lang = nullptr)
+                        const KickArgs *kick = nullptr, const LangevinArgs *lang = nullptr,
+                        double *red_out = nullptr)
 {
     const Ctx &c = ctx->c;
     int m = (int)(mode & 0xff);
@@ -1039,6 +1040,11 @@ static int compute_impl(mlmix_ctx *ctx, hipStream_t s, void *ws, const WsLayout 
         StageTimer t(ctx, s, ST_NBR);
         RegionArgs ra{m, species, c.m.ns, regions, n_regions, r_buffer, lambda, flags, nullptr,
                       (mode & MLMIX_SEEDED) ? 1 : 0, nullptr};
+        if (red_out) {  // the previous step's energy partials (multi-step call)
+            ra.red_part = at<double>(ws, L.red);
+            ra.red_nb = (L.n + 3) / 4;
+            ra.red_out = red_out;
+        }
         launch_neighbors(s, ws, L, b, c.r_list, pos, (mode & MLMIX_FORCE_REBUILD) ? 1 : 0,
                          c.d.skin, ra);
     }
@@ -1320,6 +1326,69 @@ extern "C" int mlmix_vv_step(mlmix_ctx *ctx, void *stream, void *ws, int32_t n_a
     } else if (!fused) {
         StageTimer t(ctx, s, ST_VV);
         launch_vv_kick_drift(s, ws, L, b, pos, vel, mass, forces, dt, 0);
+    }
+    HIP_OK(hipGetLastError());
+    return MLMIX_OK;
+}
+
+extern "C" int mlmix_vv_steps(mlmix_ctx *ctx, void *stream, void *ws, int32_t n_atoms,
+                              double *pos, double *vel, const double *mass,
+                              const int32_t *species, double dt, int32_t n_steps,
+                              const mlmix_box *box, const mlmix_region *regions,
+                              int32_t n_regions, double r_buffer, uint32_t mode, double *forces,
+                              double *e_exp, double *e_cheap, double *lambda, uint8_t *flags,
+                              int32_t *n_expensive, double *energies)
+{
+    if (!ctx || !ws || !vel || !mass || !energies)
+        return fail(MLMIX_E_ARG, "NULL argument");
+    if (n_steps < 1)
+        return fail(MLMIX_E_ARG, "n_steps must be at least 1");
+    if (mode & MLMIX_ENERGY_ONLY)
+        return fail(MLMIX_E_ARG, "MLMIX_ENERGY_ONLY is not valid for an MD step");
+    if (!(dt > 0.0))
+        return fail(MLMIX_E_ARG, "dt must be positive");
+    bool thermo = false;
+    {
+        std::lock_guard<std::mutex> g(ctx->mu);
+        thermo = ctx->lang.find(ws) != ctx->lang.end();
+    }
+    if (thermo && n_steps > 1)
+        return fail(MLMIX_E_STATE, "with a thermostat each step needs fresh normals: one step per call");
+    WsLayout L;
+    Box b;
+    int rc = lookup(ctx, ws, n_atoms, box, L, b);
+    if (rc)
+        return rc;
+    rc = check_compute_args(ctx, pos, species, regions, n_regions, r_buffer, mode, forces, e_exp,
+                            e_cheap, lambda, flags);
+    if (rc)
+        return rc;
+    if (n_steps == 1 || L.n == 0 || L.n > kGatherKickMax) {
+        for (int k = 0; k < n_steps; ++k) {
+            rc = mlmix_vv_step(ctx, stream, ws, n_atoms, pos, vel, mass, species, dt, box, regions,
+                               n_regions, r_buffer, mode, forces, e_exp, e_cheap, lambda, flags,
+                               n_expensive, energies + 3 * (size_t)k);
+            if (rc)
+                return rc;
+        }
+        return MLMIX_OK;
+    }
+    // fused steps: the gather of step k also applies step k+1's opening half
+    // kick and drift, and step k+1's binning kernel sums step k's energies
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    {
+        StageTimer t(ctx, s, ST_VV);
+        launch_vv_kick_drift(s, ws, L, b, pos, vel, mass, forces, dt, 1);
+    }
+    for (int k = 0; k < n_steps; ++k) {
+        const bool last = k + 1 == n_steps;
+        KickArgs ka{vel, mass, dt, e_cheap, nullptr, energies + 3 * (size_t)k,
+                    last ? 0 : 1, last ? 0 : 1, pos, b};
+        rc = compute_impl(ctx, s, ws, L, b, pos, species, regions, n_regions, r_buffer, mode,
+                          forces, e_exp, e_cheap, lambda, flags, n_expensive, nullptr, nullptr,
+                          &ka, nullptr, k > 0 ? energies + 3 * (size_t)(k - 1) : nullptr);
+        if (rc)
+            return rc;
     }
     HIP_OK(hipGetLastError());
     return MLMIX_OK;

@@ -8,6 +8,7 @@
 // in FP64 without FMA contraction so that it reproduces the CPU reference
 // bit for bit.
 #include "internal.h"
+#include "reduce.h"
 
 namespace mlmix {
 
@@ -240,6 +241,10 @@ __global__ void __launch_bounds__(256) k_bin_bucket(const double *__restrict__ p
                                                     int *__restrict__ count,
                                                     CellAtom *__restrict__ atoms, RegionArgs ra)
 {
+    // the previous step's energy sums (multi-step calls), by the whole of
+    // workgroup 0 before anything else
+    if (ra.red_part && blockIdx.x == 0)
+        reduce_parts(ra.red_part, ra.red_nb, ra.red_out);
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n)
         atom_lambda(pos, n, b, i, ra, hdr);

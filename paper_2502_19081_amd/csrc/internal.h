@@ -147,6 +147,11 @@ struct RegionArgs {
     uint8_t *cand;
     int seeded;         // MLMIX_SEEDED: seeded regions, seed bits in flags
     uint8_t *seedcore;  // per atom: bit k = core atom of the k-th seeded region
+    // energy partials of the previous step of a multi-step call, summed by
+    // the first workgroup of the binning kernel into red_out (none if NULL)
+    const double *red_part;
+    int red_nb;
+    double *red_out;
 };
 constexpr int kMaxSeeded = 8;  // seeded regions per evaluation
 
@@ -197,6 +202,10 @@ struct KickArgs {
     const double *e_cheap;
     double *part;      // [blocks][3]: expensive, cheap, kinetic (set by the launcher)
     double *energies;  // final sums
+    int next;          // also apply the next step's opening half kick and drift
+    int defer;         // leave the final sum to the next step's binning kernel
+    double *pos;       // positions (drift of the next step)
+    Box box;
 };
 constexpr int kGatherKickMax = 65536;
 

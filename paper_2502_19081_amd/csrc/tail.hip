@@ -8,40 +8,9 @@
 // give the same bits. The blend F = lambda F_exp + (1 - lambda) F_cheap is
 // fused into the same pass.
 #include "internal.h"
+#include "reduce.h"
 
 namespace mlmix {
-
-__device__ __forceinline__ double wave_sum_d(double v)
-{
-#pragma unroll
-    for (int d = 32; d > 0; d >>= 1)
-        v += __shfl_xor(v, d);
-    return v;
-}
-
-// Sum of nb [3]-partials by one 256-thread block in a fixed order (thread
-// stride, wave butterfly, then the four waves pairwise); out[2] (kinetic) is
-// converted to eV.
-__device__ void reduce_parts(const double *part, int nb, double *out)
-{
-    __shared__ double sh[3][4];
-    double v[3] = {0.0, 0.0, 0.0};
-    for (int b = threadIdx.x; b < nb; b += blockDim.x)
-        for (int q = 0; q < 3; ++q)
-            v[q] += part[b * 3 + q];
-    for (int q = 0; q < 3; ++q)
-        v[q] = wave_sum_d(v[q]);
-    int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0)
-        for (int q = 0; q < 3; ++q)
-            sh[q][w] = v[q];
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int q = 0; q < 3; ++q)
-            out[q] = (sh[q][0] + sh[q][1]) + (sh[q][2] + sh[q][3]);
-        out[2] /= kKappa;
-    }
-}
 
 template <typename T, bool KICK>
 __global__ void __launch_bounds__(256)
@@ -124,9 +93,26 @@ __global__ void __launch_bounds__(256)
                 const double cf = 0.5 * ka.dt * kKappa / m;
                 double v2 = 0.0;
                 for (int q = 0; q < 3; ++q) {
-                    const double v = ka.vel[q * n + i] + cf * F[q];
-                    ka.vel[q * n + i] = v;
+                    // kicks and drifts as explicit fused multiply-adds, the same
+                    // in every kernel that applies them (so fused and separate
+                    // steps give the same bits)
+                    const double v = fma(cf, F[q], ka.vel[q * n + i]);
                     v2 += v * v;
+                    if (ka.next) {
+                        // the next step's opening half kick and drift, as
+                        // k_vv computes them
+                        const double vn = fma(cf, F[q], v);
+                        ka.vel[q * n + i] = vn;
+                        double x = fma(ka.dt, vn, ka.pos[q * n + i]);
+                        if (ka.box.per[q]) {
+                            x = x - ka.box.L[q] * floor(x / ka.box.L[q]);
+                            if (x >= ka.box.L[q])
+                                x -= ka.box.L[q];
+                        }
+                        ka.pos[q * n + i] = x;
+                    } else {
+                        ka.vel[q * n + i] = v;
+                    }
                 }
                 ke = 0.5 * m * v2;
                 ee = si < 0 ? 0.0 : e_exp[i];
@@ -188,7 +174,7 @@ void launch_gather_blend(hipStream_t s, const Ctx &c, void *ws, const WsLayout &
             MLMIX_GATHER(float, false);
     }
 #undef MLMIX_GATHER
-    if (kick)
+    if (kick && !ka.defer)
         k_reduce_final<<<1, 256, 0, s>>>(ka.part, (int)nb, ka.energies);
 }
 
@@ -286,10 +272,10 @@ __global__ void __launch_bounds__(256) k_vv(int n, Box b, double *__restrict__ p
         return;
     double c = 0.5 * dt * kKappa / mass[i];
     for (int k = 0; k < 3; ++k) {
-        double v = vel[k * n + i] + c * f[k * n + i];
+        double v = fma(c, f[k * n + i], vel[k * n + i]);
         vel[k * n + i] = v;
         if (drift) {
-            double x = pos[k * n + i] + dt * v;
+            double x = fma(dt, v, pos[k * n + i]);
             if (b.per[k]) {
                 x = x - b.L[k] * floor(x / b.L[k]);
                 if (x >= b.L[k])
@@ -316,7 +302,7 @@ __global__ void __launch_bounds__(256) k_vv_kick_sums(int n, double *__restrict_
         const double c = 0.5 * dt * kKappa / mass[i];
         double v2 = 0.0;
         for (int q = 0; q < 3; ++q) {
-            const double v = vel[q * n + i] + c * f[q * n + i];
+            const double v = fma(c, f[q * n + i], vel[q * n + i]);
             vel[q * n + i] = v;
             v2 += v * v;
         }

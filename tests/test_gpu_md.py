@@ -176,3 +176,77 @@ def test_langevin_without_cheap_atoms_is_nve(case):
         res.append((pos.cpu().numpy(), vel.cpu().numpy()))
     assert np.array_equal(res[0][0], res[1][0])
     assert np.array_equal(res[0][1], res[1][1])
+
+
+@pytest.mark.parametrize("case", ["c2_fp32_rebuild", "tiny_fp64_skin"])
+def test_fused_steps_equal_single_steps(case):
+    # n steps in one call (gather fused with the next opening kick and drift,
+    # energy sums in the next binning kernel) = n single steps, bit for bit
+    import torch
+    if case == "c2_fp32_rebuild":
+        w = W.c2()
+        vel0 = W.maxwell(np.random.default_rng(5), w["species"], 300.0)
+        prec, rebuild, dt, steps = "fp32", True, 1.0, 6
+    else:
+        w = W.tiny(seed=41, n_species=2, sigma=0.05)
+        vel0 = w["vel"] * 4.0
+        prec, rebuild, dt, steps = "fp64", False, 1.0, 7
+    w = dict(w, vel=vel0)
+    print(f"case fused multi-step VV {case}, {steps} steps", flush=True)
+    res = []
+    for fused in (False, True):
+        _, sy, pos, vel, mass, sp = _setup(w, prec)
+        sy.compute(pos, sp, r_buffer=w["r_buffer"], force_rebuild=True)
+        if fused:
+            en = sy.vv_steps(pos, vel, mass, sp, dt, steps, r_buffer=w["r_buffer"],
+                             force_rebuild=rebuild).cpu().numpy()
+        else:
+            en = []
+            for _ in range(steps):
+                sy.vv_step(pos, vel, mass, sp, dt, r_buffer=w["r_buffer"], force_rebuild=rebuild)
+                en.append(sy.energies.cpu().numpy().copy())
+            en = np.array(en)
+        sy.status()
+        res.append((pos.cpu().numpy(), vel.cpu().numpy(), sy.forces.cpu().numpy(), en,
+                    sy.lam.cpu().numpy()))
+    for a, b in zip(res[0], res[1]):
+        assert np.array_equal(a, b)
+
+
+def test_fused_steps_in_a_graph():
+    # the fused call captured once and replayed = the same call launched eagerly
+    import torch
+    w = W.c4_replica(1, n_target=2000)
+    print("case fused multi-step VV captured in a graph, c4 replica, 3 steps x 4 replays",
+          flush=True)
+    dt, steps = 0.2, 3
+    _, sy, pos, vel, mass, sp = _setup(w, "fp32")
+    sy.compute(pos, sp, r_buffer=w["r_buffer"], force_rebuild=True)
+    eager = []
+    for _ in range(4):
+        en = sy.vv_steps(pos, vel, mass, sp, dt, steps, r_buffer=w["r_buffer"], force_rebuild=True)
+        torch.cuda.synchronize()
+        eager.append((pos.cpu().numpy().copy(), en.cpu().numpy().copy()))
+    _, sy2, pos2, vel2, mass2, sp2 = _setup(w, "fp32")
+    sy2.compute(pos2, sp2, r_buffer=w["r_buffer"], force_rebuild=True)
+    en2 = torch.zeros(steps, 3, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    p0, v0, f0 = pos2.clone(), vel2.clone(), sy2.forces.clone()
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            sy2.vv_steps(pos2, vel2, mass2, sp2, dt, steps, r_buffer=w["r_buffer"],
+                         force_rebuild=True, energies=en2)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    pos2.copy_(p0)
+    vel2.copy_(v0)
+    sy2.forces.copy_(f0)
+    for k in range(4):
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(pos2.cpu().numpy(), eager[k][0]), k
+        assert np.array_equal(en2.cpu().numpy(), eager[k][1]), k
+    sy2.status()
