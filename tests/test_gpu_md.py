@@ -178,32 +178,45 @@ def test_langevin_without_cheap_atoms_is_nve(case):
     assert np.array_equal(res[0][1], res[1][1])
 
 
-@pytest.mark.parametrize("case", ["c2_fp32_rebuild", "tiny_fp64_skin"])
+@pytest.mark.parametrize("case", ["c2_fp32_rebuild", "tiny_fp64_skin", "tiny_seeded_cubic",
+                                  "tiny_cheap_masked"])
 def test_fused_steps_equal_single_steps(case):
     # n steps in one call (gather fused with the next opening kick and drift,
     # energy sums in the next binning kernel) = n single steps, bit for bit
     import torch
+    masked = False
+    seeds = None
     if case == "c2_fp32_rebuild":
         w = W.c2()
         vel0 = W.maxwell(np.random.default_rng(5), w["species"], 300.0)
         prec, rebuild, dt, steps = "fp32", True, 1.0, 6
     else:
-        w = W.tiny(seed=41, n_species=2, sigma=0.05)
+        w = W.tiny(seed=41, n_species=2, sigma=0.05, cells=6 if case == "tiny_cheap_masked" else 3)
         vel0 = w["vel"] * 4.0
         prec, rebuild, dt, steps = "fp64", False, 1.0, 7
+        if case == "tiny_seeded_cubic":
+            seeds = np.zeros(len(w["pos"]), bool)
+            seeds[[3, 30]] = True
+            w = dict(w, regions=[W.seeded(2.9, 3.2, blend=1)])
+        if case == "tiny_cheap_masked":
+            masked = True
+            w = dict(w, regions=[W.sphere(w["L"] / 2.0, 3.5, 1.5)], r_buffer=3.0)
     w = dict(w, vel=vel0)
     print(f"case fused multi-step VV {case}, {steps} steps", flush=True)
     res = []
     for fused in (False, True):
         _, sy, pos, vel, mass, sp = _setup(w, prec)
-        sy.compute(pos, sp, r_buffer=w["r_buffer"], force_rebuild=True)
+        if seeds is not None:
+            sy.set_seeds(torch.from_numpy(seeds.astype(np.uint8)))
+        sy.compute(pos, sp, r_buffer=w["r_buffer"], force_rebuild=True, cheap_masked=masked)
         if fused:
             en = sy.vv_steps(pos, vel, mass, sp, dt, steps, r_buffer=w["r_buffer"],
-                             force_rebuild=rebuild).cpu().numpy()
+                             force_rebuild=rebuild, cheap_masked=masked).cpu().numpy()
         else:
             en = []
             for _ in range(steps):
-                sy.vv_step(pos, vel, mass, sp, dt, r_buffer=w["r_buffer"], force_rebuild=rebuild)
+                sy.vv_step(pos, vel, mass, sp, dt, r_buffer=w["r_buffer"], force_rebuild=rebuild,
+                           cheap_masked=masked)
                 en.append(sy.energies.cpu().numpy().copy())
             en = np.array(en)
         sy.status()
