@@ -7,6 +7,9 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+# where tests that measure something (drift, precision) leave their figures
+RESULTS_DIR = os.environ.get("MLMIX_RESULTS_DIR", os.path.join(ROOT, "test_results"))
+
 
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (HIP device) and the built HIP library")

@@ -93,8 +93,9 @@ def test_c3_nve_1000_steps():
               flush=True)
         if name != "mixed":
             assert np.abs(drift).max() < 2e-4
-    os.makedirs("gpurun_out", exist_ok=True)
-    with open("gpurun_out/c3_nve_drift.json", "w") as f:
+    from conftest import RESULTS_DIR
+    os.makedirs(RESULTS_DIR, exist_ok=True)
+    with open(os.path.join(RESULTS_DIR, "c3_nve_drift.json"), "w") as f:
         json.dump(res, f)
 
 

@@ -7,7 +7,8 @@ of the order-3 force contribution (the only term they change), print it, and
 gate it loosely: an operand-layout or scaling mistake in the matrix-core
 stage makes the order-3 term wrong as a whole (relative error of order one),
 which these gates catch, while the rounding of correct operands stays well
-inside them. The measured figures go to gpurun_out/precision_errors.json.
+inside them. The measured figures go to precision_errors.json in the results
+directory (MLMIX_RESULTS_DIR, default test_results/).
 """
 import json
 import os
@@ -64,8 +65,9 @@ def _case(name, w, sample):
               flush=True)
         del g
     RESULTS[name] = out
-    os.makedirs("gpurun_out", exist_ok=True)
-    with open("gpurun_out/precision_errors.json", "w") as fh:
+    from conftest import RESULTS_DIR
+    os.makedirs(RESULTS_DIR, exist_ok=True)
+    with open(os.path.join(RESULTS_DIR, "precision_errors.json"), "w") as fh:
         json.dump(RESULTS, fh, indent=1)
     for prec, gate in GATE.items():
         assert out[prec]["rms_rel_order3"] < gate, (prec, out[prec])
