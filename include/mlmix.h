@@ -224,7 +224,9 @@ int mlmix_workspace_init(mlmix_ctx *ctx, void *stream, void *ws, size_t ws_bytes
  *  optional (NULL) copies of the two unblended force fields.
  * The neighbour list is rebuilt when MLMIX_FORCE_REBUILD is set, on the first
  * call after mlmix_workspace_init, or when an atom moved more than skin/2
- * since the last rebuild (decided on the device). */
+ * since the last rebuild (decided on the device). An empty system (n_atoms
+ * = 0) may pass NULL per-atom arrays; only n_expensive is written (zeros),
+ * and mlmix_vv_step / mlmix_vv_steps write zero energy sums. */
 int mlmix_compute(mlmix_ctx *ctx, void *stream, void *ws, int32_t n_atoms,
                   const double *pos, const int32_t *species, const mlmix_box *box,
                   const mlmix_region *regions, int32_t n_regions, double r_buffer,

@@ -1166,7 +1166,7 @@ static int compute_impl(mlmix_ctx *ctx, hipStream_t s, void *ws, const WsLayout 
 static int check_compute_args(mlmix_ctx *ctx, const double *pos, const int32_t *species,
                               const mlmix_region *regions, int32_t n_regions, double r_buffer,
                               uint32_t mode, double *forces, double *e_exp, double *e_cheap,
-                              double *lambda, uint8_t *flags)
+                              double *lambda, uint8_t *flags, int32_t n_atoms)
 {
     int m = (int)(mode & 0xff);
     if (m != MLMIX_MODE_MIXED && m != MLMIX_MODE_ALL_EXPENSIVE && m != MLMIX_MODE_ALL_CHEAP)
@@ -1174,9 +1174,10 @@ static int check_compute_args(mlmix_ctx *ctx, const double *pos, const int32_t *
     if (mode & ~(0xffu | MLMIX_FORCE_REBUILD | MLMIX_ENERGY_ONLY | MLMIX_SINGLE_STREAM |
                  MLMIX_SEEDED | MLMIX_CHEAP_MASKED))
         return fail(MLMIX_E_ARG, "unknown mode flag");
-    if (!pos || !species || !e_exp || !lambda || !flags)
+    // per-atom arrays may be NULL for an empty system (nothing is read or written)
+    if (n_atoms > 0 && (!pos || !species || !e_exp || !lambda || !flags))
         return fail(MLMIX_E_ARG, "NULL array argument");
-    if (!(mode & MLMIX_ENERGY_ONLY) && (!forces || !e_cheap))
+    if (n_atoms > 0 && !(mode & MLMIX_ENERGY_ONLY) && (!forces || !e_cheap))
         return fail(MLMIX_E_ARG, "forces and e_cheap are required unless MLMIX_ENERGY_ONLY");
     if (m == MLMIX_MODE_MIXED) {
         if (n_regions < 0 || (n_regions > 0 && !regions))
@@ -1184,6 +1185,17 @@ static int check_compute_args(mlmix_ctx *ctx, const double *pos, const int32_t *
         if (!(r_buffer >= 0.0) || r_buffer > ctx->c.r_list)
             return fail(MLMIX_E_ARG, "r_buffer must lie in [0, list radius]");
     }
+    return MLMIX_OK;
+}
+
+// An empty system: the counts and energy sums are zero, nothing else is touched.
+static int empty_outputs(hipStream_t s, int32_t *n_expensive, double *energies, int n_energies)
+{
+    if (n_expensive)
+        k_zero_i32<<<1, 64, 0, s>>>(n_expensive, 2);
+    if (energies)
+        launch_fill_f64(s, energies, 0.0, (size_t)3 * n_energies);
+    HIP_OK(hipGetLastError());
     return MLMIX_OK;
 }
 
@@ -1202,9 +1214,11 @@ extern "C" int mlmix_compute(mlmix_ctx *ctx, void *stream, void *ws, int32_t n_a
     if (rc)
         return rc;
     rc = check_compute_args(ctx, pos, species, regions, n_regions, r_buffer, mode, forces, e_exp,
-                            e_cheap, lambda, flags);
+                            e_cheap, lambda, flags, n_atoms);
     if (rc)
         return rc;
+    if (L.n == 0)
+        return empty_outputs(static_cast<hipStream_t>(stream), n_expensive, nullptr, 0);
     return compute_impl(ctx, static_cast<hipStream_t>(stream), ws, L, b, pos, species, regions,
                         n_regions, r_buffer, mode, forces, e_exp, e_cheap, lambda, flags,
                         n_expensive, f_exp, f_cheap);
@@ -1278,7 +1292,7 @@ extern "C" int mlmix_vv_step(mlmix_ctx *ctx, void *stream, void *ws, int32_t n_a
                              double *e_cheap, double *lambda, uint8_t *flags,
                              int32_t *n_expensive, double *energies)
 {
-    if (!ctx || !ws || !vel || !mass)
+    if (!ctx || !ws || (n_atoms > 0 && (!vel || !mass)))
         return fail(MLMIX_E_ARG, "NULL argument");
     if (mode & MLMIX_ENERGY_ONLY)
         return fail(MLMIX_E_ARG, "MLMIX_ENERGY_ONLY is not valid for an MD step");
@@ -1290,10 +1304,12 @@ extern "C" int mlmix_vv_step(mlmix_ctx *ctx, void *stream, void *ws, int32_t n_a
     if (rc)
         return rc;
     rc = check_compute_args(ctx, pos, species, regions, n_regions, r_buffer, mode, forces, e_exp,
-                            e_cheap, lambda, flags);
+                            e_cheap, lambda, flags, n_atoms);
     if (rc)
         return rc;
     hipStream_t s = static_cast<hipStream_t>(stream);
+    if (L.n == 0)
+        return empty_outputs(s, n_expensive, energies, 1);
     {
         StageTimer t(ctx, s, ST_VV);
         launch_vv_kick_drift(s, ws, L, b, pos, vel, mass, forces, dt, 1);
@@ -1339,7 +1355,7 @@ extern "C" int mlmix_vv_steps(mlmix_ctx *ctx, void *stream, void *ws, int32_t n_
                               double *e_exp, double *e_cheap, double *lambda, uint8_t *flags,
                               int32_t *n_expensive, double *energies)
 {
-    if (!ctx || !ws || !vel || !mass || !energies)
+    if (!ctx || !ws || !energies || (n_atoms > 0 && (!vel || !mass)))
         return fail(MLMIX_E_ARG, "NULL argument");
     if (n_steps < 1)
         return fail(MLMIX_E_ARG, "n_steps must be at least 1");
@@ -1360,7 +1376,7 @@ extern "C" int mlmix_vv_steps(mlmix_ctx *ctx, void *stream, void *ws, int32_t n_
     if (rc)
         return rc;
     rc = check_compute_args(ctx, pos, species, regions, n_regions, r_buffer, mode, forces, e_exp,
-                            e_cheap, lambda, flags);
+                            e_cheap, lambda, flags, n_atoms);
     if (rc)
         return rc;
     if (n_steps == 1 || L.n == 0 || L.n > kGatherKickMax) {

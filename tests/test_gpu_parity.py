@@ -191,3 +191,76 @@ def test_tiny_cheap_masked_fp64():
 def test_c2_cheap_masked_fp32():
     _check(W.c2(), "mixed", "fp32", cheap_masked=True)
 
+
+
+# ------------------------------------------------------- degenerate cases
+
+def test_no_region_is_the_cheap_potential():
+    # mixed mode without regions: lambda = 0, S empty (every expensive launch
+    # sees |S| = 0), forces = the cheap forces exactly
+    w = dict(W.tiny(seed=51, n_species=2, sigma=0.05), regions=[])
+    g, ref = _check(w, "mixed", "fp64")
+    assert len(ref["S"]) == 0 and np.all(g["lam"] == 0.0)
+    cheap = O.mixed(w, O.MODE_ALL_CHEAP)
+    assert rel_force_err(g["forces"], cheap["forces"]) < 1e-10
+
+
+def test_region_covering_everything_is_the_expensive_potential():
+    # a core sphere larger than the cell: lambda = 1 everywhere, forces = the
+    # all-expensive forces
+    w = W.tiny(seed=53, n_species=1, sigma=0.05)
+    w = dict(w, regions=[W.sphere(w["L"] / 2.0, 100.0, 0.0)])
+    g, ref = _check(w, "mixed", "fp64")
+    assert np.all(g["lam"] == 1.0)
+    full = O.mixed(w, O.MODE_ALL_EXPENSIVE)
+    assert rel_force_err(g["forces"], full["forces"]) < 1e-10
+
+
+def test_neighbour_overflow_is_reported_and_regrowth_recovers():
+    import torch
+    from paper_2502_19081_amd import binding as B
+    from paper_2502_19081_amd import core
+    w = W.c1()
+    print("case c1 with nbr_cap 32 (rows hold 58): overflow, then the required capacity",
+          flush=True)
+    model = core.Model(w["model"], precision="fp64")
+    _, sy, pos, sp = core.system_for(w, model=model, cap=32)
+    sy.compute(pos, sp, r_buffer=w["r_buffer"], force_rebuild=True)
+    bits, req, rc = sy.status(raise_on_error=False)
+    assert rc == -4 and bits & B.STATUS_NEIGH_OVERFLOW and req >= 58
+    ref = O.mixed(w)
+    assert req == int(np.diff(ref["offs"]).max())
+    g = run_gpu(w, O.MODE_MIXED, precision="fp64", cap=req)
+    assert rel_force_err(g["forces"], ref["forces"]) < 1e-10
+
+
+def test_atom_outside_a_nonperiodic_box_is_reported():
+    from paper_2502_19081_amd import binding as B
+    from paper_2502_19081_amd import core
+    w = W.tiny(seed=55, periodic=(0, 0, 0), vacuum=4.0, sigma=0.05)
+    pos = w["pos"].copy()
+    pos[3, 2] = w["L"][2] + 0.5   # beyond the box's upper z face
+    w = dict(w, pos=pos)
+    print("case non-periodic cell with one atom outside the box", flush=True)
+    model = core.Model(w["model"], precision="fp64")
+    _, sy, p, sp = core.system_for(w, model=model)
+    sy.compute(p, sp, r_buffer=w["r_buffer"], force_rebuild=True)
+    bits, _, rc = sy.status(raise_on_error=False)
+    assert rc == -5 and bits & B.STATUS_OUT_OF_BOX
+
+
+def test_empty_system():
+    import torch
+    from paper_2502_19081_amd import core
+    w = W.tiny(seed=57)
+    print("case zero atoms: compute and an MD step are no-ops", flush=True)
+    model = core.Model(w["model"], precision="fp64")
+    sy = core.System(model, 0, w["L"], w["periodic"])
+    pos = torch.zeros(3, 0, dtype=torch.float64, device="cuda")
+    sp = torch.zeros(0, dtype=torch.int32, device="cuda")
+    out = sy.compute(pos, sp, r_buffer=w["r_buffer"], force_rebuild=True)
+    vel = torch.zeros(3, 0, dtype=torch.float64, device="cuda")
+    mass = torch.zeros(0, dtype=torch.float64, device="cuda")
+    sy.vv_step(pos, vel, mass, sp, 1.0, r_buffer=w["r_buffer"])
+    sy.status()
+    assert out["forces"].numel() == 0 and out["n_exp"].cpu().tolist() == [0, 0]
