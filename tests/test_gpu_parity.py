@@ -264,3 +264,63 @@ def test_empty_system():
     sy.vv_step(pos, vel, mass, sp, 1.0, r_buffer=w["r_buffer"])
     sy.status()
     assert out["forces"].numel() == 0 and out["n_exp"].cpu().tolist() == [0, 0]
+
+
+_C5 = {}
+
+
+def _c5_reference():
+    """c5 at its full size (1,023,800 atoms) with the oracle's forces on a
+    seeded sample: atoms in the blend shells, inside the spheres and far from
+    them (lambda, masks and lists are computed for every atom)."""
+    if not _C5:
+        w = W.c5()
+        lam, _ = O.lambda_flags(O._f64(w["pos"]), w["L"], w["periodic"], w["regions"])
+        r = np.random.default_rng(2025)
+        shell = np.nonzero((lam > 0) & (lam < 1))[0]
+        core_ = np.nonzero(lam == 1)[0]
+        far = np.nonzero(lam == 0)[0]
+        sample = np.unique(np.concatenate([r.choice(shell, 24, replace=False),
+                                           r.choice(core_, 8, replace=False),
+                                           r.choice(far, 32, replace=False)]))
+        target = np.zeros(len(w["pos"]), bool)
+        target[sample] = True
+        _C5.update(w=w, sample=sample, ref=O.mixed(w, O.MODE_MIXED, target=target))
+    return _C5["w"], _C5["sample"], _C5["ref"]
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_c5_full_size_sampled(precision):
+    """The largest workload in the launch shapes of its benchmark (uncapped
+    side passes, chunked basis, 16-channel contraction, slot-parallel reverse
+    slots): lists, lambda, masks and S/M bit-exact for all atoms;
+    forces against the oracle on the sample; and, for every atom, the
+    property that holds at any size: each pair gradient enters the gather of
+    both of its atoms with opposite signs, so the cheap forces of all atoms
+    and the expensive forces of S sum to zero up to the FP64 rounding of the
+    sums."""
+    w, sample, ref = _c5_reference()
+    print(f"case c5 full n={len(w['pos'])} sample={len(sample)} prec={precision}", flush=True)
+    g = run_gpu(w, O.MODE_MIXED, precision=precision)
+    cap = g["nbr"].shape[1]
+    valid = np.arange(cap)[None, :] < g["cnt"][:, None]
+    assert np.array_equal(g["cnt"], np.diff(ref["offs"]).astype(np.int32))
+    assert np.array_equal(g["nbr"][valid], ref["nbr"])
+    assert np.array_equal(g["lam"], ref["lam"])
+    assert np.array_equal(g["flags"] & 0x7F, ref["flags"])
+    assert np.array_equal(g["S"], ref["S"]) and np.array_equal(g["M"], ref["M"])
+    for key in ("forces", "f_exp", "f_cheap"):
+        d = np.abs(g[key][sample] - ref[key][sample]).max()
+        scale = np.abs(ref[key][sample]).max()
+        print(f"  {key}: max |dF| on the sample = {d:.3e} eV/A (max |F| {scale:.3f})", flush=True)
+        if precision == "fp64":
+            assert d < 1e-10 * max(scale, 1e-300), key
+        else:
+            assert d < 1e-4, key
+    for key in ("f_cheap", "f_exp"):
+        net = np.abs(g[key].sum(axis=0)).max()
+        print(f"  {key}: |sum over atoms| = {net:.3e} eV/A", flush=True)
+        assert net < 1e-6, key
+    outside = np.ones(len(w["pos"]), bool)
+    outside[ref["S"]] = False
+    assert np.all(g["f_exp"][outside] == 0) and np.all(g["e_exp"][outside] == 0)
