@@ -82,8 +82,10 @@ def test_c2_fp32_all_expensive():
     _check(W.c2(), "all_expensive", "fp32")
 
 
-def test_c4_replica_two_species_fp32():
-    w = W.c4_replica(3, n_target=2500)
+@pytest.mark.parametrize("index,n_target", [(3, 2500), (5, 20000)])
+def test_c4_replica_two_species_fp32(index, n_target):
+    # the smallest and the largest replica size of the serving workload
+    w = W.c4_replica(index, n_target=n_target)
     _check(w, "mixed", "fp32")
 
 
@@ -266,15 +268,15 @@ def test_empty_system():
     assert out["forces"].numel() == 0 and out["n_exp"].cpu().tolist() == [0, 0]
 
 
-_C5 = {}
+_BIG = {}
 
 
-def _c5_reference():
-    """c5 at its full size (1,023,800 atoms) with the oracle's forces on a
-    seeded sample: atoms in the blend shells, inside the spheres and far from
-    them (lambda, masks and lists are computed for every atom)."""
-    if not _C5:
-        w = W.c5()
+def _sampled_reference(name):
+    """A workload at its full size with the oracle's forces on a seeded
+    sample: atoms in the blend shells, inside the regions and far from them
+    (lambda, masks and lists are computed for every atom)."""
+    if name not in _BIG:
+        w = {"c3": W.c3, "c5": W.c5}[name]()
         lam, _ = O.lambda_flags(O._f64(w["pos"]), w["L"], w["periodic"], w["regions"])
         r = np.random.default_rng(2025)
         shell = np.nonzero((lam > 0) & (lam < 1))[0]
@@ -285,22 +287,24 @@ def _c5_reference():
                                            r.choice(far, 32, replace=False)]))
         target = np.zeros(len(w["pos"]), bool)
         target[sample] = True
-        _C5.update(w=w, sample=sample, ref=O.mixed(w, O.MODE_MIXED, target=target))
-    return _C5["w"], _C5["sample"], _C5["ref"]
+        _BIG[name] = (w, sample, O.mixed(w, O.MODE_MIXED, target=target))
+    return _BIG[name]
 
 
-@pytest.mark.parametrize("precision", ["fp32", "fp64"])
-def test_c5_full_size_sampled(precision):
-    """The largest workload in the launch shapes of its benchmark (uncapped
-    side passes, chunked basis, 16-channel contraction, slot-parallel reverse
-    slots): lists, lambda, masks and S/M bit-exact for all atoms;
-    forces against the oracle on the sample; and, for every atom, the
-    property that holds at any size: each pair gradient enters the gather of
-    both of its atoms with opposite signs, so the cheap forces of all atoms
-    and the expensive forces of S sum to zero up to the FP64 rounding of the
-    sums."""
-    w, sample, ref = _c5_reference()
-    print(f"case c5 full n={len(w['pos'])} sample={len(sample)} prec={precision}", flush=True)
+@pytest.mark.parametrize("name,precision", [("c3", "fp32"), ("c3", "fp64"), ("c5", "fp32"),
+                                            ("c5", "fp64")])
+def test_full_size_sampled(name, precision):
+    """The dislocation slab (54,000 atoms) and the largest workload
+    (1,023,800 atoms) at their full sizes, in the launch shapes of their
+    benchmarks (on c5: uncapped side passes, chunked basis, 16-channel
+    contraction, slot-parallel reverse slots): lists, lambda, masks and S/M
+    bit-exact for all atoms; forces against the oracle on the sample; and,
+    for every atom, the property that holds at any size: each pair gradient
+    enters the gather of both of its atoms with opposite signs, so the cheap
+    forces of all atoms and the expensive forces of S sum to zero up to the
+    FP64 rounding of the sums."""
+    w, sample, ref = _sampled_reference(name)
+    print(f"case {name} full n={len(w['pos'])} sample={len(sample)} prec={precision}", flush=True)
     g = run_gpu(w, O.MODE_MIXED, precision=precision)
     cap = g["nbr"].shape[1]
     valid = np.arange(cap)[None, :] < g["cnt"][:, None]
