@@ -9,9 +9,12 @@ each on its own stream, so the replicas' kernels overlap on the device:
 either as eager launches (default) or, with use_graph, as one HIP graph
 captured whenever the set of active replicas changes (each replica in its own
 stream branch, forked from the capture stream and joined back), so that a
-tick costs one graph launch. The graph mode is off by default: its capture
-and replay crashed in the host runtime in a recent run, with the cause not
-yet shown.
+tick costs one graph launch. That mode is off by default: its capture and
+replay crashed in the host runtime in a recent run, with the cause not yet
+shown. With use_graph="replica" each replica's step is captured once, alone
+on one stream, when the replica is admitted (the one-level capture whose
+replays are bitwise equal to eager steps), and a tick launches every active
+replica's graph on its own stream.
 Finished replicas are retired (state copied to the host, memory released)
 and their slots refilled at the next tick.
 
@@ -46,6 +49,7 @@ class Replica:
         self.done = 0
         self.admitted_at = None
         self.finished_at = None
+        self.graph = None  # this replica's captured step (use_graph="replica")
         self.latencies = []
         self.result = None
         self.error = None
@@ -79,6 +83,7 @@ class Replica:
         self.result = dict(pos=self.pos.cpu().numpy().T.copy(), vel=self.vel.cpu().numpy().T.copy(),
                            energies=self.sy.energies.cpu().numpy().copy(),
                            n_exp=self.sy.n_exp.cpu().numpy().copy())
+        self.graph = None  # before the buffers it launches on are released
         del self.sy, self.pos, self.vel, self.mass, self.sp
 
 
@@ -100,7 +105,7 @@ class Server:
         self.finished = []
         self.in_use = 0
         self.graph = None
-        self.recaptures = 0
+        self.recaptures = 0  # graph captures (per batch, or per replica)
         self.ticks = []
         self.check_every = check_every
         self.failed = []
@@ -120,12 +125,28 @@ class Server:
                 break
             self.waiting.pop(0)
             r.load(self.model, self.cap, self.device)
+            if self.use_graph == "replica":
+                self._capture_replica(r)
             r.admitted_at = now
             r.fp = fp
             self.in_use += fp
             self.active.append(r)
             changed = True
         return changed
+
+    def _capture_replica(self, r):
+        # the step is recorded, not run: the replica does not advance here
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        cs = self.capture_stream
+        cs.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(cs):
+            with torch.cuda.graph(g, stream=cs):
+                r.step()
+        torch.cuda.current_stream().wait_stream(cs)
+        torch.cuda.synchronize()
+        r.graph = g
+        self.recaptures += 1
 
     def _capture(self):
         torch.cuda.synchronize()
@@ -149,7 +170,14 @@ class Server:
 
     def _tick(self):
         t0 = time.perf_counter()
-        if self.use_graph:
+        if self.use_graph == "replica":
+            cur = torch.cuda.current_stream()
+            for st in self.streams[:min(len(self.active), len(self.streams))]:
+                st.wait_stream(cur)
+            for k, r in enumerate(self.active):
+                with torch.cuda.stream(self.streams[k % len(self.streams)]):
+                    r.graph.replay()
+        elif self.use_graph:
             self.graph.replay()
         else:
             # admission evaluates new replicas on the current stream: order the
@@ -181,6 +209,7 @@ class Server:
         for r in bad:
             r.finished_at = now
             self.in_use -= r.fp
+            r.graph = None
             del r.sy, r.pos, r.vel, r.mass, r.sp
             self.failed.append(r)
         if bad:
@@ -200,7 +229,7 @@ class Server:
                 time.sleep(max(0.0, min(0.01, self.waiting[0].arrival - now)))
                 continue
             if changed or self.graph is None:
-                if self.use_graph:
+                if self.use_graph is True:
                     self._capture()
             self._tick()
             if len(self.ticks) % self.check_every == 0:
@@ -251,11 +280,15 @@ def main(argv=None):
     ap.add_argument("--graph", action="store_true",
                     help="one multi-stream HIP graph per batch composition (default: eager "
                          "launches of every replica's step on its own stream)")
+    ap.add_argument("--graph-per-replica", action="store_true",
+                    help="one HIP graph per replica, captured at admission; a tick launches "
+                         "the active replicas' graphs, each on its own stream")
     args = ap.parse_args(argv)
+    mode = "replica" if args.graph_per_replica else args.graph
     from gen import workloads as W
     model = core.Model(W.c4_model(), precision="fp32")
     srv = Server(model, hbm_budget=args.hbm_gb * (1 << 30), max_slots=args.slots,
-                 use_graph=args.graph)
+                 use_graph=mode)
     reps = replicas_c4(args.replicas, args.steps, rate_hz=args.rate or None)
     for r in reps:
         srv.submit(r)
@@ -266,7 +299,7 @@ def main(argv=None):
     rep.update({"workload": "c4: W(001)+He impact replicas, log-uniform 2,000-20,000 atoms, "
                             "dt 0.2 fs, 8 A sphere following He, FP32 potentials",
                 "steps_per_replica": args.steps, "arrival_rate_hz": args.rate,
-                "slots": args.slots, "graph": args.graph,
+                "slots": args.slots, "graph": mode,
                 "hbm_budget_bytes": srv.budget,
                 "hbm_peak_allocated_bytes": int(torch.cuda.max_memory_allocated())})
     print(json.dumps(rep))

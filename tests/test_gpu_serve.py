@@ -2,9 +2,11 @@
 alone and in a changing mix; admission respects the HBM budget; a replica
 with a non-finite position is evicted alone.
 
-Each test runs in both tick modes of the server: one multi-stream HIP graph
-per batch composition ("graph"), and eager launches of every replica's step
-on its own stream ("eager"). The graph mode is skipped: its capture end and
+Each test runs in the tick modes of the server: one multi-stream HIP graph
+per batch composition ("graph"), eager launches of every replica's step on
+its own stream ("eager"), and one graph per replica captured at admission,
+the active replicas' graphs launched each on its own stream
+("replica_graphs"). The batch-graph mode is skipped: its capture end and
 a later replay crashed in the host runtime (segmentation fault, no GPU fault
 reported) after the library began to fork work onto a second stream; the
 cause has not been shown, so the mode stays off until it is.
@@ -17,7 +19,8 @@ pytestmark = pytest.mark.gpu
 GRAPH_SKIP = pytest.mark.skip(
     reason="multi-replica graph capture/replay crashed in the host runtime (SIGSEGV in capture "
            "end, then in replay); cause not shown yet, so this mode stays off the GPU")
-MODES = [pytest.param(True, id="graph", marks=GRAPH_SKIP), pytest.param(False, id="eager")]
+MODES = [pytest.param(True, id="graph", marks=GRAPH_SKIP), pytest.param(False, id="eager"),
+         pytest.param("replica", id="replica_graphs")]
 
 
 def _model():
@@ -92,3 +95,25 @@ def test_nonfinite_replica_is_evicted_alone(use_graph):
     assert [r.rid for r in srv.failed] == [9]
     assert sorted(r.rid for r in srv.finished) == [7, 8]
     assert all(r.error is None for r in srv.finished)
+
+
+def test_replica_graphs_equal_eager_steps():
+    # a replica served through its captured step gives the bits of the same
+    # replica served with eager launches, beside another replica in both runs
+    from paper_2502_19081_amd.serve import Server
+    model = _model()
+    print("case serving per-replica graphs vs eager (c4 replicas, 30 steps)", flush=True)
+    out = {}
+    for mode in (False, "replica"):
+        srv = Server(model, max_slots=2, use_graph=mode)
+        reps = [_rep(6, 30, 0.0, 3500), _rep(2, 20, 0.0, 2200)]
+        for r in reps:
+            srv.submit(r)
+        srv.run(clock=lambda: 0.0)
+        assert all(r.error is None for r in srv.finished)
+        out[mode] = {r.rid: r.result for r in srv.finished}
+        if mode == "replica":
+            assert srv.recaptures == 2
+    for rid in (6, 2):
+        for key in ("pos", "vel", "energies"):
+            assert np.array_equal(out[False][rid][key], out["replica"][rid][key]), (rid, key)
