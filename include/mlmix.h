@@ -55,14 +55,19 @@ extern "C" {
 #define MLMIX_E_BOX (-5)
 #define MLMIX_E_NONFINITE (-6)
 #define MLMIX_E_STATE (-7)
+#define MLMIX_E_HOST (-8) /* host-side failure inside the library (host memory exhausted) */
 
 /* Arithmetic of the two potentials. Positions, lambda, the blend, energy
  * sums and the integrator are FP64 in every mode. The two reduced-precision
  * modes compute in FP32 except the dense stage of the order-3 product-basis
- * contraction, whose operands are rounded to BF16 or scaled to FP8 (E4M3:
- * one scale per atom shared by the m components, from a per-call maximum,
- * and one per output channel of the weights), with FP32 accumulation on the
- * matrix cores; they require a single-species model. */
+ * contraction (the coupled products P of two atomic-basis blocks against the
+ * weights), whose operands are rounded to BF16 or scaled to FP8 with FP32
+ * accumulation on the matrix cores. FP8 is OCP E4M3 with two kinds of
+ * scale, neither data-dependent across atoms: each row of P (one atom, one
+ * (l1, l2, l3) block, one m3) is divided by the bound
+ * sum|Gaunt| x max_m1|A_l1| x max_m2|A_l2| / 240 of its entries, and each
+ * output channel c of a block's weights by max|W(., c)| / 240; the product
+ * is rescaled in FP32 after the accumulation. */
 #define MLMIX_FP64 0
 #define MLMIX_FP32 1
 #define MLMIX_BF16_CONTRACT 2
@@ -313,6 +318,14 @@ int mlmix_get_neighbors(mlmix_ctx *ctx, void *stream, void *ws, int32_t n_atoms,
                         int32_t *nbr_out, int32_t *cnt_out);
 int mlmix_get_index_sets(mlmix_ctx *ctx, void *stream, void *ws, int32_t n_atoms,
                          int32_t *S_out, int32_t *M_out);
+
+/* Test hook, host only (no device call): the real Gaunt coefficients the
+ * order-3 contraction uses, G[lm1][lm2][lm3] = integral over the unit sphere
+ * of Y_lm1 Y_lm2 Y_lm3 (real orthonormal harmonics without the
+ * Condon-Shortley phase, index l^2 + l + m, cosine type for m > 0), from
+ * the Wigner-3j closed form. out [host] double[L2^3], L2 = (lmax + 1)^2,
+ * 0 <= lmax <= 6. Errors: MLMIX_E_ARG. */
+int mlmix_gaunt_table(int32_t lmax, double *out);
 
 /* ---------------------------------------------------------------------
  * Constrained linear fitting of the cheap potential (Methods, "Constrained

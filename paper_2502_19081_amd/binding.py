@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(_HERE, "libmlmix.so")
 MLMIX_OK = 0
 ERRORS = {-1: "MLMIX_E_ARG", -2: "MLMIX_E_HIP", -3: "MLMIX_E_WORKSPACE",
           -4: "MLMIX_E_NEIGH_OVERFLOW", -5: "MLMIX_E_BOX", -6: "MLMIX_E_NONFINITE",
-          -7: "MLMIX_E_STATE"}
+          -7: "MLMIX_E_STATE", -8: "MLMIX_E_HOST"}
 FP64, FP32, BF16_CONTRACT, FP8_CONTRACT = 0, 1, 2, 3
 MODE_MIXED, MODE_ALL_EXPENSIVE, MODE_ALL_CHEAP = 0, 1, 2
 FORCE_REBUILD = 0x100
@@ -85,6 +85,7 @@ SIGNATURES = {
     "mlmix_get_neighbors": (ctypes.c_int, [_vp, _vp, _vp, _i32, _vp, _vp]),
     "mlmix_get_index_sets": (ctypes.c_int, [_vp, _vp, _vp, _i32, _vp, _vp]),
     "mlmix_model_flops": (ctypes.c_int, [_vp, _vp]),
+    "mlmix_gaunt_table": (ctypes.c_int, [_i32, _vp]),
     "mlmix_fit_n_params": (ctypes.c_int, [_vp, ctypes.POINTER(_i32)]),
     "mlmix_fit_design": (ctypes.c_int, [_vp, _vp, _vp, _i32, _vp, _vp, ctypes.POINTER(Box), _vp,
                                         _i32]),

@@ -176,14 +176,6 @@ struct Mfma<float> {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(x, y, c, 0, 0, 0);
     }
 };
-template <>
-struct Mfma<double> {
-    typedef double v4 __attribute__((ext_vector_type(4)));
-    static __device__ __forceinline__ v4 op(double x, double y, v4 c)
-    {
-        return __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, c, 0, 0, 0);
-    }
-};
 
 // Rows of the P tile (atoms x m3, padded to 16) and its row stride (odd, so
 // that 16 consecutive rows fall into distinct LDS banks).
@@ -263,7 +255,11 @@ __global__ void __launch_bounds__(256)
         }
         __syncthreads();
         const int ncb = nchp >> 2;
+        // the matrix-core stages exist for FP32 only (FP64 keeps the VALU)
+        bool done = false;
+        if constexpr (sizeof(T) == 4) {
         if (use_mfma) {
+            done = true;
             // sparse Gaunt stage on MFMA: for each row (atom t, m3),
             // P[a][b] = sum_e (g_e A[o1_e][a]) A[o2_e][b], i.e. a 16x16 product
             // with K = the m3 group's Gaunt entries, four per instruction.
@@ -303,7 +299,9 @@ __global__ void __launch_bounds__(256)
                         }
                     }
             }
-        } else {
+        }
+        }
+        if (!done) {
         // sparse Gaunt stage on VALU. Thread -> (a, four b) once; rows advance
         // by a fixed stride, so no per-item integer division is needed.
         const int Q = nch * ncb;
@@ -340,7 +338,10 @@ __global__ void __launch_bounds__(256)
         }
         __syncthreads();
         T *Dbase = Dpart + dp_off[p];
+        done = false;
+        if constexpr (sizeof(T) == 4) {
         if (use_mfma) {
+            done = true;
             // D[row][c] = sum_k P[row][k] Ws[k][c]: 16x16 tiles over 4 waves
             const int nrt = (nrows + 15) >> 4, nct = (nch + 15) >> 4;
             for (int tt = wv; tt < nrt * nct; tt += 4) {
@@ -366,7 +367,9 @@ __global__ void __launch_bounds__(256)
                     }
                 }
             }
-        } else {
+        }
+        }
+        if (!done) {
             // VALU: groups (row, four channels); weights per atom species
             for (int g = tid; g < nrows * ncb; g += 256) {
                 int r = g / ncb, cb = g - r * ncb;

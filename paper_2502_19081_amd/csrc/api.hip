@@ -2,10 +2,14 @@
 // the launch sequence of one mixed force evaluation (see include/mlmix.h).
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
+#include <memory>
+#include <new>
+#include <stdexcept>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -101,73 +105,72 @@ struct StageTimer {
     }
     ~StageTimer()
     {
-        if (k0) {
-            ctx->pending.push_back({stage, k0, k1});
-        } else if (a) {
-            hipEvent_t b = take_event(ctx);
-            if (b) {
-                (void)hipEventRecord(b, s);
-                ctx->pending.push_back({stage, a, b});
-            } else {
-                ctx->pool.push_back(a);
+        // a destructor must not throw: a bracket that cannot be queued is
+        // dropped (its events are released)
+        try {
+            if (k0) {
+                ctx->pending.push_back({stage, k0, k1});
+            } else if (a) {
+                hipEvent_t b = take_event(ctx);
+                if (b) {
+                    (void)hipEventRecord(b, s);
+                    ctx->pending.push_back({stage, a, b});
+                } else {
+                    ctx->pool.push_back(a);
+                }
             }
+        } catch (...) {
+            (void)hipEventDestroy(k0 ? k0 : a);
+            if (k1)
+                (void)hipEventDestroy(k1);
         }
     }
 };
 
-static thread_local std::string g_err;
+// Message of the last failing call on this thread (a fixed buffer: reporting
+// an error allocates nothing).
+static thread_local char g_err[512];
 
-static int fail(int code, const std::string &msg)
+static int fail(int code, const char *msg)
 {
-    g_err = msg;
+    std::snprintf(g_err, sizeof g_err, "%s", msg);
     return code;
 }
 
-extern "C" const char *mlmix_last_error(void) { return g_err.c_str(); }
+static int fail_hip(const char *what, hipError_t e)
+{
+    std::snprintf(g_err, sizeof g_err, "%s: %s", what, hipGetErrorString(e));
+    return MLMIX_E_HIP;
+}
 
-#define HIP_OK(expr)                                                                     \
-    do {                                                                                 \
-        hipError_t e_ = (expr);                                                          \
-        if (e_ != hipSuccess)                                                            \
-            return fail(MLMIX_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+// Handler of every entry point's function-try-block: no C++ exception
+// crosses the C ABI (the host tables and bookkeeping use the standard
+// containers, which report exhausted host memory by throwing).
+static int host_exception() noexcept
+{
+    try {
+        throw;
+    } catch (const std::bad_alloc &) {
+        return fail(MLMIX_E_HOST, "host memory exhausted");
+    } catch (const std::exception &ex) {
+        return fail(MLMIX_E_HOST, ex.what());
+    } catch (...) {
+        return fail(MLMIX_E_HOST, "unexpected host exception");
+    }
+}
+
+extern "C" const char *mlmix_last_error(void) { return g_err; }
+
+#define HIP_OK(expr)                        \
+    do {                                    \
+        hipError_t e_ = (expr);             \
+        if (e_ != hipSuccess)               \
+            return fail_hip(#expr, e_);     \
     } while (0)
 
 namespace mlmix {
 
 // ------------------------------------------------------------ tabulation
-
-// Gauss-Legendre nodes and weights on [-1, 1] (Newton on P_N).
-static void gauss_legendre(int N, std::vector<double> &x, std::vector<double> &w)
-{
-    x.resize(N);
-    w.resize(N);
-    for (int i = 0; i < N; ++i) {
-        double z = std::cos(M_PI * (i + 0.75) / (N + 0.5));
-        double dp = 1.0;
-        for (int it = 0; it < 100; ++it) {
-            double p0 = 1.0, p1 = z;
-            for (int k = 2; k <= N; ++k) {
-                double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
-                p0 = p1;
-                p1 = p2;
-            }
-            dp = N * (z * p1 - p0) / (z * z - 1.0);
-            double dz = p1 / dp;
-            z -= dz;
-            if (std::fabs(dz) < 1e-16)
-                break;
-        }
-        double p0 = 1.0, p1 = z;
-        for (int k = 2; k <= N; ++k) {
-            double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
-            p0 = p1;
-            p1 = p2;
-        }
-        dp = N * (z * p1 - p0) / (z * z - 1.0);
-        x[i] = z;
-        w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
-    }
-}
 
 static std::vector<double> ylm_norm(int lmax)
 {
@@ -185,30 +188,102 @@ static std::vector<double> ylm_norm(int lmax)
     return K;
 }
 
-// Real Gaunt coefficients G[lm1][lm2][lm3] by product quadrature (Gauss-
-// Legendre in cos(theta), uniform in phi), with the same harmonics the
-// kernels evaluate.
-static std::vector<double> gaunt(int lmax, const std::vector<double> &K)
+// Wigner 3j symbol by Racah's single-sum formula (factorials up to
+// (3 kMaxLmax + 1)! are exact enough in double for the cancellations of the
+// alternating sum at l <= 6).
+static double wigner3j(int j1, int j2, int j3, int m1, int m2, int m3)
 {
-    int L2 = (lmax + 1) * (lmax + 1);
-    int Nz = 2 * lmax + 3, Np = 4 * lmax + 5;
-    std::vector<double> zx, zw;
-    gauss_legendre(Nz, zx, zw);
-    std::vector<double> G((size_t)L2 * L2 * L2, 0.0), Y(L2);
-    for (int a = 0; a < Nz; ++a)
-        for (int b = 0; b < Np; ++b) {
-            double ph = 2.0 * M_PI * b / Np;
-            double st = std::sqrt(1.0 - zx[a] * zx[a]);
-            double w = zw[a] * 2.0 * M_PI / Np;
-            ylm_stream<double>(lmax, st * std::cos(ph), st * std::sin(ph), zx[a], K.data(),
-                               [&](int lm, double v, double, double, double) { Y[lm] = v; });
-            for (int i = 0; i < L2; ++i)
-                for (int j = 0; j < L2; ++j) {
-                    double wij = w * Y[i] * Y[j];
-                    for (int k = 0; k < L2; ++k)
-                        G[((size_t)i * L2 + j) * L2 + k] += wij * Y[k];
-                }
+    if (m1 + m2 + m3 != 0 || j3 > j1 + j2 || j3 < std::abs(j1 - j2))
+        return 0.0;
+    if (std::abs(m1) > j1 || std::abs(m2) > j2 || std::abs(m3) > j3)
+        return 0.0;
+    double f[3 * kMaxLmax + 2];
+    f[0] = 1.0;
+    for (int k = 1; k < 3 * kMaxLmax + 2; ++k)
+        f[k] = f[k - 1] * k;
+    const double tri = f[j1 + j2 - j3] * f[j1 - j2 + j3] * f[-j1 + j2 + j3] / f[j1 + j2 + j3 + 1];
+    const double pre = std::sqrt(tri * f[j1 + m1] * f[j1 - m1] * f[j2 + m2] * f[j2 - m2] *
+                                 f[j3 + m3] * f[j3 - m3]);
+    double sum = 0.0;
+    for (int k = 0; k <= j1 + j2 + j3; ++k) {
+        const int a[6] = {k, j3 - j2 + k + m1, j3 - j1 + k - m2, j1 + j2 - j3 - k, j1 - k - m1,
+                          j2 - k + m2};
+        if (*std::min_element(a, a + 6) < 0)
+            continue;
+        const double den = f[a[0]] * f[a[1]] * f[a[2]] * f[a[3]] * f[a[4]] * f[a[5]];
+        sum += ((k & 1) ? -1.0 : 1.0) / den;
+    }
+    return (((j1 - j2 - m3) & 1) ? -1.0 : 1.0) * pre * sum;
+}
+
+// Real Gaunt coefficients G[lm1][lm2][lm3] = integral of the product of three
+// real harmonics over the sphere, from the closed form of the complex ones,
+//   int Y_l1^m1 Y_l2^m2 Y_l3^m3 = sqrt((2l1+1)(2l2+1)(2l3+1)/(4 pi))
+//                                 (l1 l2 l3; 0 0 0) (l1 l2 l3; m1 m2 m3),
+// and the change of basis to the real harmonics that ylm_stream evaluates
+// (no Condon-Shortley phase; index l^2 + l + m, cosine type for m > 0, sine
+// type for m < 0): with Y_l^m the complex harmonics (Condon-Shortley phase),
+//   Y_{l,m>0}  = ((-1)^m Y_l^m + Y_l^-m) / sqrt(2),
+//   Y_{l,-m<0} = ((-1)^m Y_l^m - Y_l^-m) / (i sqrt(2)),   Y_{l,0} = Y_l^0.
+// Each real harmonic has at most two complex components, so each real
+// coefficient is a sum of at most eight complex ones (its imaginary part is
+// zero).
+static std::vector<double> gaunt(int lmax)
+{
+    typedef std::complex<double> cd;
+    const int L2 = (lmax + 1) * (lmax + 1);
+    // complex components (m, coefficient) of every real harmonic
+    std::vector<int> nc(L2), cm((size_t)2 * L2);
+    std::vector<cd> cc((size_t)2 * L2);
+    const double r2 = 1.0 / std::sqrt(2.0);
+    for (int l = 0; l <= lmax; ++l)
+        for (int m = -l; m <= l; ++m) {
+            const int q = l * l + l + m, mu = std::abs(m);
+            const double sg = (mu & 1) ? -1.0 : 1.0;
+            if (m == 0) {
+                nc[q] = 1;
+                cm[2 * q] = 0;
+                cc[2 * q] = cd(1.0, 0.0);
+            } else if (m > 0) {
+                nc[q] = 2;
+                cm[2 * q] = mu;
+                cc[2 * q] = cd(sg * r2, 0.0);
+                cm[2 * q + 1] = -mu;
+                cc[2 * q + 1] = cd(r2, 0.0);
+            } else {  // 1 / i = -i
+                nc[q] = 2;
+                cm[2 * q] = mu;
+                cc[2 * q] = cd(0.0, -sg * r2);
+                cm[2 * q + 1] = -mu;
+                cc[2 * q + 1] = cd(0.0, r2);
+            }
         }
+    std::vector<double> G((size_t)L2 * L2 * L2, 0.0);
+    for (int l1 = 0; l1 <= lmax; ++l1)
+        for (int l2 = 0; l2 <= lmax; ++l2)
+            for (int l3 = 0; l3 <= lmax; ++l3) {
+                if ((l1 + l2 + l3) & 1 || l3 > l1 + l2 || l3 < std::abs(l1 - l2))
+                    continue;
+                const double pre =
+                    std::sqrt((2.0 * l1 + 1.0) * (2.0 * l2 + 1.0) * (2.0 * l3 + 1.0) / (4.0 * M_PI)) *
+                    wigner3j(l1, l2, l3, 0, 0, 0);
+                for (int q1 = l1 * l1; q1 < (l1 + 1) * (l1 + 1); ++q1)
+                    for (int q2 = l2 * l2; q2 < (l2 + 1) * (l2 + 1); ++q2)
+                        for (int q3 = l3 * l3; q3 < (l3 + 1) * (l3 + 1); ++q3) {
+                            cd v(0.0, 0.0);
+                            for (int a = 0; a < nc[q1]; ++a)
+                                for (int b = 0; b < nc[q2]; ++b)
+                                    for (int c = 0; c < nc[q3]; ++c) {
+                                        const int m1 = cm[2 * q1 + a], m2 = cm[2 * q2 + b],
+                                                  m3 = cm[2 * q3 + c];
+                                        if (m1 + m2 + m3 != 0)
+                                            continue;
+                                        v += cc[2 * q1 + a] * cc[2 * q2 + b] * cc[2 * q3 + c] *
+                                             (pre * wigner3j(l1, l2, l3, m1, m2, m3));
+                                    }
+                            G[((size_t)q1 * L2 + q2) * L2 + q3] = v.real();
+                        }
+            }
     return G;
 }
 
@@ -473,7 +548,7 @@ static int build_tables(const mlmix_model_desc &d, HostTables &t)
                     }
     }
     if (d.ace_order >= 3) {
-        std::vector<double> G = gaunt(lmax, t.K);
+        std::vector<double> G = gaunt(lmax);
         for (int l3 = 0; l3 <= lmax; ++l3)
             for (int l1 = 0; l1 <= lmax; ++l1)
                 for (int l2 = l1; l2 <= lmax; ++l2) {
@@ -736,7 +811,7 @@ static int check_box(const mlmix_ctx *ctx, const mlmix_box *box, Box &b)
 }
 
 extern "C" int mlmix_create(const mlmix_model_desc *desc, mlmix_ctx **out)
-{
+try {
     if (!desc || !out)
         return fail(MLMIX_E_ARG, "NULL argument");
     *out = nullptr;
@@ -769,7 +844,9 @@ extern "C" int mlmix_create(const mlmix_model_desc *desc, mlmix_ctx **out)
     if (nch * (2 * d.ace_lmax + 1) > 8 * 64)
         return fail(MLMIX_E_ARG, "order-3 output block larger than 512 entries");
 
-    mlmix_ctx *ctx = new mlmix_ctx();
+    // owned here until every step succeeded (early returns release it)
+    std::unique_ptr<mlmix_ctx> holder(new mlmix_ctx());
+    mlmix_ctx *ctx = holder.get();
     Ctx &c = ctx->c;
     c.d = d;
     c.prec = d.precision == MLMIX_FP64 ? MLMIX_FP64 : MLMIX_FP32;
@@ -789,10 +866,8 @@ extern "C" int mlmix_create(const mlmix_model_desc *desc, mlmix_ctx **out)
     HIP_OK(hipGetDevice(&c.device));
     HostTables t;
     int rc = build_tables(d, t);
-    if (rc != MLMIX_OK) {
-        delete ctx;
+    if (rc != MLMIX_OK)
         return rc;
-    }
     DevModel &m = c.m;
     m.ns = d.n_species;
     m.nrad = d.ace_n_rad;
@@ -881,29 +956,27 @@ extern "C" int mlmix_create(const mlmix_model_desc *desc, mlmix_ctx **out)
         if (!std::atoi(e))
             c.o3 = 0;  // general block kernel (comparisons)
     if (c.qmode != 0 && !c.o3) {
-        delete ctx;
         return fail(MLMIX_E_ARG, "the BF16/FP8 contraction modes need a single-species model "
                                  "with at most 16 radial channels and correlation order 3");
     }
     std::vector<char> blob = c.prec == MLMIX_FP64 ? pack<double>(t, m) : pack<float>(t, m);
     m.bytes = blob.size();
     hipError_t e = hipMalloc(&m.base, m.bytes);
-    if (e != hipSuccess) {
-        delete ctx;
-        return fail(MLMIX_E_HIP, std::string("hipMalloc(model): ") + hipGetErrorString(e));
-    }
+    if (e != hipSuccess)
+        return fail_hip("hipMalloc(model)", e);
     e = hipMemcpy(m.base, blob.data(), m.bytes, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         (void)hipFree(m.base);
-        delete ctx;
-        return fail(MLMIX_E_HIP, std::string("hipMemcpy(model): ") + hipGetErrorString(e));
+        return fail_hip("hipMemcpy(model)", e);
     }
-    *out = ctx;
+    *out = holder.release();
     return MLMIX_OK;
+} catch (...) {
+    return host_exception();
 }
 
 extern "C" int mlmix_destroy(mlmix_ctx *ctx)
-{
+try {
     if (!ctx)
         return MLMIX_OK;
     for (PendingEvent &p : ctx->pending) {
@@ -924,13 +997,15 @@ extern "C" int mlmix_destroy(mlmix_ctx *ctx)
         (void)hipFree(ctx->c.m.base);
     delete ctx;
     return MLMIX_OK;
+} catch (...) {
+    return host_exception();
 }
 
 extern "C" double mlmix_list_radius(const mlmix_ctx *ctx) { return ctx ? ctx->c.r_list : 0.0; }
 
 extern "C" int mlmix_workspace_size(const mlmix_ctx *ctx, int32_t n_atoms, int32_t nbr_cap,
                                     const mlmix_box *box, size_t *bytes)
-{
+try {
     if (!ctx || !bytes)
         return fail(MLMIX_E_ARG, "NULL argument");
     if (n_atoms < 0 || nbr_cap < 1 || nbr_cap > kMaxCap)
@@ -944,11 +1019,13 @@ extern "C" int mlmix_workspace_size(const mlmix_ctx *ctx, int32_t n_atoms, int32
         return fail(MLMIX_E_ARG, "box too large for the cell grid (2^31 bucket records)");
     *bytes = L.total;
     return MLMIX_OK;
+} catch (...) {
+    return host_exception();
 }
 
 extern "C" int mlmix_workspace_init(mlmix_ctx *ctx, void *stream, void *ws, size_t ws_bytes,
                                     int32_t n_atoms, int32_t nbr_cap, const mlmix_box *box)
-{
+try {
     if (!ctx || !ws)
         return fail(MLMIX_E_ARG, "NULL argument");
     if (n_atoms < 0 || nbr_cap < 1 || nbr_cap > kMaxCap)
@@ -974,6 +1051,8 @@ extern "C" int mlmix_workspace_init(mlmix_ctx *ctx, void *stream, void *ws, size
         ctx->lang.erase(ws);  // the noise buffer was sized for another system
     ctx->ws[ws] = L;
     return MLMIX_OK;
+} catch (...) {
+    return host_exception();
 }
 
 static int lookup(mlmix_ctx *ctx, void *ws, int n, const mlmix_box *box, WsLayout &L, Box &b)
@@ -1205,7 +1284,7 @@ extern "C" int mlmix_compute(mlmix_ctx *ctx, void *stream, void *ws, int32_t n_a
                              uint32_t mode, double *forces, double *e_exp, double *e_cheap,
                              double *lambda, uint8_t *flags, int32_t *n_expensive,
                              double *f_exp, double *f_cheap)
-{
+try {
     if (!ctx || !ws)
         return fail(MLMIX_E_ARG, "NULL context or workspace");
     WsLayout L;
@@ -1222,12 +1301,14 @@ extern "C" int mlmix_compute(mlmix_ctx *ctx, void *stream, void *ws, int32_t n_a
     return compute_impl(ctx, static_cast<hipStream_t>(stream), ws, L, b, pos, species, regions,
                         n_regions, r_buffer, mode, forces, e_exp, e_cheap, lambda, flags,
                         n_expensive, f_exp, f_cheap);
+} catch (...) {
+    return host_exception();
 }
 
 extern "C" int mlmix_backward(mlmix_ctx *ctx, void *stream, void *ws, int32_t n_atoms,
                               const double *pos, const int32_t *species, const mlmix_box *box,
                               const double *grad_e, double *grad_pos)
-{
+try {
     if (!ctx || !ws || !pos || !species || !grad_e || !grad_pos)
         return fail(MLMIX_E_ARG, "NULL argument");
     WsLayout L;
@@ -1240,12 +1321,14 @@ extern "C" int mlmix_backward(mlmix_ctx *ctx, void *stream, void *ws, int32_t n_
     launch_gather_blend(s, ctx->c, ws, L, 1, 0, nullptr, grad_pos, nullptr, nullptr, nullptr, -1.0);
     HIP_OK(hipGetLastError());
     return MLMIX_OK;
+} catch (...) {
+    return host_exception();
 }
 
 extern "C" int mlmix_energy_reduce(mlmix_ctx *ctx, void *stream, void *ws, int32_t n_atoms,
                                    const double *e_exp, const double *e_cheap, const double *vel,
                                    const double *mass, double *energies)
-{
+try {
     if (!ctx || !ws || !energies)
         return fail(MLMIX_E_ARG, "NULL argument");
     WsLayout L;
@@ -1261,11 +1344,13 @@ extern "C" int mlmix_energy_reduce(mlmix_ctx *ctx, void *stream, void *ws, int32
     launch_reduce(static_cast<hipStream_t>(stream), ws, L, e_exp, e_cheap, vel, mass, energies);
     HIP_OK(hipGetLastError());
     return MLMIX_OK;
+} catch (...) {
+    return host_exception();
 }
 
 extern "C" int mlmix_set_langevin(mlmix_ctx *ctx, void *ws, int32_t n_atoms,
                                   double temperature_K, double damping_fs, const double *xi)
-{
+try {
     if (!ctx || !ws)
         return fail(MLMIX_E_ARG, "NULL argument");
     if (!(temperature_K >= 0.0) || !std::isfinite(temperature_K) || !std::isfinite(damping_fs))
@@ -1283,6 +1368,8 @@ extern "C" int mlmix_set_langevin(mlmix_ctx *ctx, void *ws, int32_t n_atoms,
     else
         ctx->lang.erase(ws);
     return MLMIX_OK;
+} catch (...) {
+    return host_exception();
 }
 
 extern "C" int mlmix_vv_step(mlmix_ctx *ctx, void *stream, void *ws, int32_t n_atoms, double *pos,
@@ -1291,7 +1378,7 @@ extern "C" int mlmix_vv_step(mlmix_ctx *ctx, void *stream, void *ws, int32_t n_a
                              double r_buffer, uint32_t mode, double *forces, double *e_exp,
                              double *e_cheap, double *lambda, uint8_t *flags,
                              int32_t *n_expensive, double *energies)
-{
+try {
     if (!ctx || !ws || (n_atoms > 0 && (!vel || !mass)))
         return fail(MLMIX_E_ARG, "NULL argument");
     if (mode & MLMIX_ENERGY_ONLY)
@@ -1345,6 +1432,8 @@ extern "C" int mlmix_vv_step(mlmix_ctx *ctx, void *stream, void *ws, int32_t n_a
     }
     HIP_OK(hipGetLastError());
     return MLMIX_OK;
+} catch (...) {
+    return host_exception();
 }
 
 extern "C" int mlmix_vv_steps(mlmix_ctx *ctx, void *stream, void *ws, int32_t n_atoms,
@@ -1354,7 +1443,7 @@ extern "C" int mlmix_vv_steps(mlmix_ctx *ctx, void *stream, void *ws, int32_t n_
                               int32_t n_regions, double r_buffer, uint32_t mode, double *forces,
                               double *e_exp, double *e_cheap, double *lambda, uint8_t *flags,
                               int32_t *n_expensive, double *energies)
-{
+try {
     if (!ctx || !ws || !energies || (n_atoms > 0 && (!vel || !mass)))
         return fail(MLMIX_E_ARG, "NULL argument");
     if (n_steps < 1)
@@ -1408,11 +1497,13 @@ extern "C" int mlmix_vv_steps(mlmix_ctx *ctx, void *stream, void *ws, int32_t n_
     }
     HIP_OK(hipGetLastError());
     return MLMIX_OK;
+} catch (...) {
+    return host_exception();
 }
 
 extern "C" int mlmix_status(mlmix_ctx *ctx, void *stream, void *ws, int32_t *status_bits,
                             int32_t *required_cap)
-{
+try {
     if (!ctx || !ws)
         return fail(MLMIX_E_ARG, "NULL argument");
     WsLayout L;
@@ -1445,11 +1536,13 @@ extern "C" int mlmix_status(mlmix_ctx *ctx, void *stream, void *ws, int32_t *sta
     if (st & MLMIX_STATUS_OUT_OF_BOX)
         return fail(MLMIX_E_BOX, "atom outside a non-periodic box dimension");
     return MLMIX_OK;
+} catch (...) {
+    return host_exception();
 }
 
 extern "C" int mlmix_get_neighbors(mlmix_ctx *ctx, void *stream, void *ws, int32_t n_atoms,
                                    int32_t *nbr_out, int32_t *cnt_out)
-{
+try {
     if (!ctx || !ws || !nbr_out || !cnt_out)
         return fail(MLMIX_E_ARG, "NULL argument");
     WsLayout L;
@@ -1467,11 +1560,13 @@ extern "C" int mlmix_get_neighbors(mlmix_ctx *ctx, void *stream, void *ws, int32
     launch_copy_i32(s, cnt_out, at<int>(ws, L.cnt), (size_t)L.n);
     HIP_OK(hipGetLastError());
     return MLMIX_OK;
+} catch (...) {
+    return host_exception();
 }
 
 extern "C" int mlmix_get_index_sets(mlmix_ctx *ctx, void *stream, void *ws, int32_t n_atoms,
                                     int32_t *S_out, int32_t *M_out)
-{
+try {
     if (!ctx || !ws || !S_out || !M_out)
         return fail(MLMIX_E_ARG, "NULL argument");
     WsLayout L;
@@ -1489,6 +1584,8 @@ extern "C" int mlmix_get_index_sets(mlmix_ctx *ctx, void *stream, void *ws, int3
     launch_copy_i32(s, M_out, at<int>(ws, L.M_idx), (size_t)L.n);
     HIP_OK(hipGetLastError());
     return MLMIX_OK;
+} catch (...) {
+    return host_exception();
 }
 
 // ------------------------------------------- constrained fit of the cheap potential
@@ -1503,11 +1600,13 @@ static int fit_params(const Ctx &c)
 }
 
 extern "C" int mlmix_fit_n_params(mlmix_ctx *ctx, int32_t *n_params)
-{
+try {
     if (!ctx || !n_params)
         return fail(MLMIX_E_ARG, "NULL argument");
     *n_params = fit_params(ctx->c);
     return MLMIX_OK;
+} catch (...) {
+    return host_exception();
 }
 
 static int fit_config(mlmix_ctx *ctx, int nd, void *ws, int32_t n_atoms, const double *pos,
@@ -1543,7 +1642,7 @@ static int fit_nd_check(mlmix_ctx *ctx, int32_t ld, int &nd)
 extern "C" int mlmix_fit_design(mlmix_ctx *ctx, void *stream, void *ws, int32_t n_atoms,
                                 const double *pos, const int32_t *species, const mlmix_box *box,
                                 double *rows, int32_t ld)
-{
+try {
     if (!ctx)
         return fail(MLMIX_E_ARG, "NULL argument");
     int nd = 0;
@@ -1557,11 +1656,13 @@ extern "C" int mlmix_fit_design(mlmix_ctx *ctx, void *stream, void *ws, int32_t 
     launch_fit_design(static_cast<hipStream_t>(stream), ctx->c, &h, 1, ld, nd);
     HIP_OK(hipGetLastError());
     return MLMIX_OK;
+} catch (...) {
+    return host_exception();
 }
 
 extern "C" int mlmix_fit_design_batch(mlmix_ctx *ctx, void *stream, int32_t n_configs,
                                       const mlmix_fit_config *configs, int32_t ld)
-{
+try {
     if (!ctx || (n_configs > 0 && !configs) || n_configs < 0)
         return fail(MLMIX_E_ARG, "NULL argument or negative count");
     int nd = 0;
@@ -1578,10 +1679,12 @@ extern "C" int mlmix_fit_design_batch(mlmix_ctx *ctx, void *stream, int32_t n_co
     launch_fit_design(static_cast<hipStream_t>(stream), ctx->c, h.data(), n_configs, ld, nd);
     HIP_OK(hipGetLastError());
     return MLMIX_OK;
+} catch (...) {
+    return host_exception();
 }
 
 extern "C" int mlmix_fit_work_size(int64_t n_rows, int32_t n_params, size_t *bytes)
-{
+try {
     if (!bytes || n_rows < 0 || n_params < 1 || n_params > kFitMaxParams)
         return fail(MLMIX_E_ARG, "bad sizes");
     long long chunk = 0;
@@ -1590,12 +1693,14 @@ extern "C" int mlmix_fit_work_size(int64_t n_rows, int32_t n_params, size_t *byt
     *bytes = ((size_t)n_params * n_params + n_params) * sizeof(double) +
              fit_gram_part_bytes(n_params, parts);
     return MLMIX_OK;
+} catch (...) {
+    return host_exception();
 }
 
 extern "C" int mlmix_fit_gram(mlmix_ctx *ctx, void *stream, const double *rows, int64_t n_rows,
                               int32_t n_params, int32_t ld, const double *y, const double *w,
                               double *G, double *b, void *work, size_t work_bytes)
-{
+try {
     if (!ctx || !G || !b || (n_rows > 0 && (!rows || !work)))
         return fail(MLMIX_E_ARG, "NULL argument");
     if (n_rows < 0 || n_params < 1 || n_params > kFitMaxParams || ld < n_params)
@@ -1610,6 +1715,8 @@ extern "C" int mlmix_fit_gram(mlmix_ctx *ctx, void *stream, const double *rows, 
                     static_cast<double *>(work) + (size_t)n_params * n_params + n_params);
     HIP_OK(hipGetLastError());
     return MLMIX_OK;
+} catch (...) {
+    return host_exception();
 }
 
 extern "C" int mlmix_fit_constrained(mlmix_ctx *ctx, void *stream, int32_t n_params,
@@ -1619,7 +1726,7 @@ extern "C" int mlmix_fit_constrained(mlmix_ctx *ctx, void *stream, int32_t n_par
                                      double tol, double lambda0, double ridge,
                                      int32_t max_decades, int32_t max_bisect, double *c,
                                      double *info, void *work, size_t work_bytes)
-{
+try {
     if (!ctx || !GS || !bS || !c || !info || !work || (n_hard > 0 && (!AH || !yH)))
         return fail(MLMIX_E_ARG, "NULL argument");
     if (n_params < 1 || n_params > kFitMaxParams || n_hard < 0 || (n_hard > 0 && ld_h < n_params))
@@ -1641,19 +1748,23 @@ extern "C" int mlmix_fit_constrained(mlmix_ctx *ctx, void *stream, int32_t n_par
                       static_cast<double *>(work));
     HIP_OK(hipGetLastError());
     return MLMIX_OK;
+} catch (...) {
+    return host_exception();
 }
 
 extern "C" int mlmix_profile_enable(mlmix_ctx *ctx, uint32_t stage_mask)
-{
+try {
     if (!ctx)
         return fail(MLMIX_E_ARG, "NULL context");
     ctx->prof_mask = stage_mask & ((1u << MLMIX_N_STAGES) - 1u);
     return MLMIX_OK;
+} catch (...) {
+    return host_exception();
 }
 
 extern "C" int mlmix_profile_replay(mlmix_ctx *ctx, void *stream, void *ws, int32_t n_atoms,
                                     const int32_t *species, int32_t stage, int32_t reps)
-{
+try {
     if (!ctx || !ws || !species || reps < 0)
         return fail(MLMIX_E_ARG, "NULL argument or negative count");
     if (stage != ST_CONTRACT)
@@ -1673,11 +1784,13 @@ extern "C" int mlmix_profile_replay(mlmix_ctx *ctx, void *stream, void *ws, int3
         launch_ace_contract(s, ctx->c, ws, L, species);
     HIP_OK(hipGetLastError());
     return MLMIX_OK;
+} catch (...) {
+    return host_exception();
 }
 
 extern "C" int mlmix_probe_mfma_f32(void *stream, int32_t blocks, int32_t iters, float *sink,
                                     double *flops)
-{
+try {
     if (!sink || !flops || blocks < 1 || iters < 1)
         return fail(MLMIX_E_ARG, "NULL argument or non-positive size");
     launch_probe_mfma_f32(static_cast<hipStream_t>(stream), blocks, iters, sink);
@@ -1685,10 +1798,12 @@ extern "C" int mlmix_probe_mfma_f32(void *stream, int32_t blocks, int32_t iters,
     // 4 waves per block, 8 chains per round, 2 * 16 * 16 * 4 flops per MFMA
     *flops = (double)blocks * 4.0 * (double)iters * 8.0 * 2048.0;
     return MLMIX_OK;
+} catch (...) {
+    return host_exception();
 }
 
 extern "C" int mlmix_profile_read(mlmix_ctx *ctx, double *ms, int64_t *count)
-{
+try {
     if (!ctx || !ms || !count)
         return fail(MLMIX_E_ARG, "NULL argument");
     for (int i = 0; i < MLMIX_N_STAGES; ++i) {
@@ -1702,7 +1817,7 @@ extern "C" int mlmix_profile_read(mlmix_ctx *ctx, double *ms, int64_t *count)
         if (e == hipSuccess)
             e = hipEventElapsedTime(&t, p.a, p.b);
         if (e != hipSuccess)
-            rc = fail(MLMIX_E_HIP, std::string("profile events: ") + hipGetErrorString(e));
+            rc = fail_hip("profile events", e);
         ms[p.stage] += t;
         count[p.stage] += 1;
         ctx->pool.push_back(p.a);
@@ -1710,6 +1825,8 @@ extern "C" int mlmix_profile_read(mlmix_ctx *ctx, double *ms, int64_t *count)
     }
     ctx->pending.clear();
     return rc;
+} catch (...) {
+    return host_exception();
 }
 
 extern "C" const char *mlmix_profile_stage_name(int32_t stage)
@@ -1720,10 +1837,23 @@ extern "C" const char *mlmix_profile_stage_name(int32_t stage)
 }
 
 extern "C" int mlmix_model_flops(const mlmix_ctx *ctx, double *out)
-{
+try {
     if (!ctx || !out)
         return fail(MLMIX_E_ARG, "NULL argument");
     for (int i = 0; i < 6; ++i)
         out[i] = ctx->flops[i];
     return MLMIX_OK;
+} catch (...) {
+    return host_exception();
+}
+
+extern "C" int mlmix_gaunt_table(int32_t lmax, double *out)
+try {
+    if (!out || lmax < 0 || lmax > kMaxLmax)
+        return fail(MLMIX_E_ARG, "0 <= lmax <= 6 and an output array required");
+    const std::vector<double> G = gaunt(lmax);
+    std::memcpy(out, G.data(), G.size() * sizeof(double));
+    return MLMIX_OK;
+} catch (...) {
+    return host_exception();
 }

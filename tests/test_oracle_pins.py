@@ -337,23 +337,33 @@ def _U(l):
     return U
 
 
+def _racah_real_gaunt(l1, l2, l3):
+    """Real Gaunt block (l1, l2, l3) from Wigner 3j symbols and the complex ->
+    real change of basis."""
+    Gc = np.zeros((2 * l1 + 1, 2 * l2 + 1, 2 * l3 + 1))
+    pre = math.sqrt((2 * l1 + 1) * (2 * l2 + 1) * (2 * l3 + 1) / (4 * math.pi)) \
+        * _w3j(l1, l2, l3, 0, 0, 0)
+    for m1 in range(-l1, l1 + 1):
+        for m2 in range(-l2, l2 + 1):
+            for m3 in range(-l3, l3 + 1):
+                Gc[m1 + l1, m2 + l2, m3 + l3] = pre * _w3j(l1, l2, l3, m1, m2, m3)
+    Gr = np.einsum("ai,bj,ck,ijk->abc", _U(l1), _U(l2), _U(l3), Gc)
+    assert np.abs(Gr.imag).max() < 1e-13
+    return Gr.real
+
+
+# every l-triple up to lmax 6, the largest degree the library accepts (the
+# 1,023,800-atom workload runs lmax 5): a quadrature one order too short
+# fails here at the top degrees first
 def test_gaunt_matches_racah_closed_form():
-    lmax = 4
+    lmax = 6
     G = O.gaunt_table(lmax)
     for l1 in range(lmax + 1):
         for l2 in range(lmax + 1):
             for l3 in range(lmax + 1):
-                Gc = np.zeros((2 * l1 + 1, 2 * l2 + 1, 2 * l3 + 1))
-                pre = math.sqrt((2 * l1 + 1) * (2 * l2 + 1) * (2 * l3 + 1) / (4 * math.pi)) \
-                    * _w3j(l1, l2, l3, 0, 0, 0)
-                for m1 in range(-l1, l1 + 1):
-                    for m2 in range(-l2, l2 + 1):
-                        for m3 in range(-l3, l3 + 1):
-                            Gc[m1 + l1, m2 + l2, m3 + l3] = pre * _w3j(l1, l2, l3, m1, m2, m3)
-                Gr = np.einsum("ai,bj,ck,ijk->abc", _U(l1), _U(l2), _U(l3), Gc)
-                assert np.abs(Gr.imag).max() < 1e-13
+                Gr = _racah_real_gaunt(l1, l2, l3)
                 sub = G[l1 * l1:(l1 + 1) ** 2, l2 * l2:(l2 + 1) ** 2, l3 * l3:(l3 + 1) ** 2]
-                np.testing.assert_allclose(sub, Gr.real, atol=1e-13)
+                np.testing.assert_allclose(sub, Gr, atol=1e-13)
 
 
 # ----------------------------------------------------- ACE-style potential
@@ -434,16 +444,17 @@ def test_order2_legendre_closed_form():
         assert abs(E - out["e_exp"][i]) < 1e-11 * max(1.0, abs(E))
 
 
-def test_order3_sphere_integral_form():
+def _order3_sphere_integral(w, stride):
     # sum_m G Y Y Y over three atomic bases equals the sphere integral of the
     # product of three Legendre-weighted densities:
-    # B = int dO prod_k [ (2l_k+1)/(4pi) sum_j R_{a_k}(r_j) P_{l_k}(u_j . O) ].
-    w = _model_with_orders(W.tiny(seed=8, lmax=2, n_rad=3), {3})
+    # B = int dO prod_k [ (2l_k+1)/(4pi) sum_j R_{a_k}(r_j) P_{l_k}(u_j . O) ],
+    # with a = (species of j, n): no harmonics and no Gaunt table involved.
     out = O.mixed(w, O.MODE_ALL_EXPENSIVE)
     a = w["model"]["ace"]
+    ns = w["model"]["n_species"]
     nr, lmax = a["n_rad"], a["lmax"]
     L1 = lmax + 1
-    K = nr * L1
+    K = ns * nr * L1
     x, wx = np.polynomial.legendre.leggauss(2 * lmax + 4)
     nph = 4 * lmax + 6
     dirs, wts = [], []
@@ -455,24 +466,45 @@ def test_order3_sphere_integral_form():
             wts.append(wi * 2 * math.pi / nph)
     dirs = np.array(dirs)
     wts = np.array(wts)
-    for i in range(0, len(w["pos"]), 9):
+    checked = 0
+    for i in range(0, len(w["pos"]), stride):
         d, r, z = _env(w, i)
         u = d / r[:, None]
         R = _np_radial(nr, a["rcut"], r)
         cos = u @ dirs.T
+        P = [(2 * l + 1) / (4 * math.pi) * sps.eval_legendre(l, cos) for l in range(L1)]
         rho = np.zeros((K, len(dirs)))
-        for aa in range(nr):
-            for l in range(L1):
-                rho[aa * L1 + l] = (2 * l + 1) / (4 * math.pi) * (R[:, aa][:, None] * sps.eval_legendre(l, cos)).sum(0)
-        E = a["c0"][0]
+        for zz in range(ns):
+            sel = z == zz
+            for n in range(nr):
+                ch = zz * nr + n
+                for l in range(L1):
+                    rho[ch * L1 + l] = (R[sel, n][:, None] * P[l][sel]).sum(0)
+        zi = w["species"][i]
+        E = a["c0"][zi]
         for p in range(K):
             for q in range(p, K):
+                rpq = wts * rho[p] * rho[q]
                 for s in range(q, K):
                     l1, l2, l3 = p % L1, q % L1, s % L1
                     if (l1 + l2 + l3) % 2 or l3 > l1 + l2 or l3 < abs(l1 - l2):
                         continue
-                    E += a["c3"][0, p, q, s] * (wts * rho[p] * rho[q] * rho[s]).sum()
-        assert abs(E - out["e_exp"][i]) < 1e-11 * max(1.0, abs(E))
+                    E += a["c3"][zi, p, q, s] * (rpq * rho[s]).sum()
+        assert abs(E - out["e_exp"][i]) < 1e-11 * max(1.0, abs(E)), (i, E, out["e_exp"][i])
+        checked += 1
+    assert checked > 0
+
+
+def test_order3_sphere_integral_form():
+    _order3_sphere_integral(_model_with_orders(W.tiny(seed=8, lmax=2, n_rad=3), {3}), 9)
+
+
+# the degree of the 1,023,800-atom workload (lmax 5) with two species, so that
+# channel offsets by neighbour species and the top l-triples are both covered
+def test_order3_sphere_integral_form_lmax5_two_species():
+    w = _model_with_orders(W.tiny(seed=18, n_species=2, lmax=5, n_rad=2), {3})
+    assert len(set(w["species"].tolist())) == 2
+    _order3_sphere_integral(w, 13)
 
 
 def _fd_forces(w, which, idx, h=1e-5, in_S=None):
