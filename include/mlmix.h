@@ -109,6 +109,7 @@ extern "C" {
 #define MLMIX_STATUS_SEEDED_REGIONS 64 /* more than 8 seeded regions */
 #define MLMIX_STATUS_CELL_OVERFLOW 32 /* a cell held more atoms than its bucket
                                          (4 x the mean occupancy + 8) */
+#define MLMIX_STATUS_S_OVERFLOW 128   /* |S| exceeded the workspace's S capacity */
 
 /* Model description (host memory; copied by mlmix_create).
  *
@@ -199,13 +200,23 @@ int mlmix_destroy(mlmix_ctx *ctx);
 double mlmix_list_radius(const mlmix_ctx *ctx);
 
 /* Bytes of workspace for n_atoms atoms, a neighbour-row capacity of nbr_cap
- * (1..256) and the given box (the cell grid depends on it). */
-int mlmix_workspace_size(const mlmix_ctx *ctx, int32_t n_atoms, int32_t nbr_cap,
+ * (1..256), an S capacity s_cap and the given box (the cell grid depends on
+ * it). s_cap bounds |S| (the expensive atoms plus their buffer): the
+ * buffers of the expensive potential (atomic basis, dE/dA, pair gradients,
+ * the order-3 partial sums: about 4 nbr_cap x 3 + 20 K bytes per S row in
+ * FP32 for the workloads here) are sized for s_cap rows instead of n_atoms.
+ * s_cap <= 0 or > n_atoms means n_atoms (required for MLMIX_MODE_ALL_EXPENSIVE,
+ * where S is every atom). An evaluation whose S exceeds s_cap leaves the
+ * atoms past the capacity out of S and raises MLMIX_STATUS_S_OVERFLOW
+ * (mlmix_status returns MLMIX_E_WORKSPACE; n_expensive[0] holds the |S| that
+ * was needed). */
+int mlmix_workspace_size(const mlmix_ctx *ctx, int32_t n_atoms, int32_t nbr_cap, int32_t s_cap,
                          const mlmix_box *box, size_t *bytes);
 
 /* Clears the workspace header (status, neighbour-list state) on `stream`.
  * Must be called once before the first mlmix_compute on a workspace and
- * again whenever n_atoms, nbr_cap or the box size changes.
+ * again whenever n_atoms, nbr_cap, s_cap or the box size changes (the same
+ * n_atoms, nbr_cap, s_cap and box as mlmix_workspace_size).
  * Second stream: an evaluation without MLMIX_SINGLE_STREAM forks the reverse
  * slots and the cheap potential onto the workspace's second stream and joins
  * back on the caller's stream before returning, so calls stay ordered on
@@ -214,7 +225,7 @@ int mlmix_workspace_size(const mlmix_ctx *ctx, int32_t n_atoms, int32_t nbr_cap,
  * context, destroyed by mlmix_destroy); until then evaluations run on the
  * caller's stream alone. Calls on one workspace must not overlap. */
 int mlmix_workspace_init(mlmix_ctx *ctx, void *stream, void *ws, size_t ws_bytes,
-                         int32_t n_atoms, int32_t nbr_cap, const mlmix_box *box);
+                         int32_t n_atoms, int32_t nbr_cap, int32_t s_cap, const mlmix_box *box);
 
 /* The mixed force evaluation.
  *  pos [dev] 3 x n double (SoA), species [dev] int32[n] in [0, n_species),

@@ -24,6 +24,7 @@ FLAG_SEED = 0x80
 CHEAP_MASKED = 0x1000
 N_STAGES = 12
 STATUS_NEIGH_OVERFLOW, STATUS_OUT_OF_BOX, STATUS_NONFINITE, STATUS_TRIPLET_OVERFLOW, STATUS_BAD_SPECIES = 1, 2, 4, 8, 16
+STATUS_CELL_OVERFLOW, STATUS_SEEDED_REGIONS, STATUS_S_OVERFLOW = 32, 64, 128
 
 
 class ModelDesc(ctypes.Structure):
@@ -69,8 +70,10 @@ SIGNATURES = {
     "mlmix_create": (ctypes.c_int, [ctypes.POINTER(ModelDesc), ctypes.POINTER(_vp)]),
     "mlmix_destroy": (ctypes.c_int, [_vp]),
     "mlmix_list_radius": (ctypes.c_double, [_vp]),
-    "mlmix_workspace_size": (ctypes.c_int, [_vp, _i32, _i32, ctypes.POINTER(Box), ctypes.POINTER(_sz)]),
-    "mlmix_workspace_init": (ctypes.c_int, [_vp, _vp, _vp, _sz, _i32, _i32, ctypes.POINTER(Box)]),
+    "mlmix_workspace_size": (ctypes.c_int, [_vp, _i32, _i32, _i32, ctypes.POINTER(Box),
+                                            ctypes.POINTER(_sz)]),
+    "mlmix_workspace_init": (ctypes.c_int, [_vp, _vp, _vp, _sz, _i32, _i32, _i32,
+                                            ctypes.POINTER(Box)]),
     "mlmix_compute": (ctypes.c_int, [_vp, _vp, _vp, _i32, _vp, _vp, ctypes.POINTER(Box), _vp, _i32, _d,
                                      _u32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "mlmix_backward": (ctypes.c_int, [_vp, _vp, _vp, _i32, _vp, _vp, ctypes.POINTER(Box), _vp, _vp]),

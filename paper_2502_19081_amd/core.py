@@ -104,19 +104,20 @@ class System:
     """One workspace: n atoms in an orthorhombic box with a neighbour-row
     capacity `cap`. Outputs are allocated once and reused between calls."""
 
-    def __init__(self, model, n, L, periodic, cap=128, device="cuda"):
+    def __init__(self, model, n, L, periodic, cap=128, device="cuda", s_cap=0):
         self.model = model
         self.n = int(n)
         self.cap = int(cap)
+        self.s_cap = int(s_cap)  # rows of the expensive potential's buffers (0: n)
         self.box = make_box(L, periodic)
         self.device = device
         sz = ctypes.c_size_t()
-        B.check(B.lib().mlmix_workspace_size(model.handle, self.n, self.cap,
+        B.check(B.lib().mlmix_workspace_size(model.handle, self.n, self.cap, self.s_cap,
                                              ctypes.byref(self.box), ctypes.byref(sz)))
         self.ws_bytes = int(sz.value)
         self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
         B.check(B.lib().mlmix_workspace_init(model.handle, _stream(), _p(self.ws), self.ws_bytes,
-                                             self.n, self.cap, ctypes.byref(self.box)))
+                                             self.n, self.cap, self.s_cap, ctypes.byref(self.box)))
         z = dict(dtype=torch.float64, device=device)
         self.forces = torch.zeros(3, self.n, **z)
         self.e_exp = torch.zeros(self.n, **z)
@@ -270,13 +271,13 @@ class System:
         return S[:ns], M[:nm]
 
 
-def system_for(w, model=None, cap=128, device="cuda"):
+def system_for(w, model=None, cap=128, device="cuda", s_cap=0):
     """Model + System + device inputs for a workload dictionary of
     gen.workloads."""
     if model is None:
         model = Model(w["model"], precision=w.get("precision", "fp64"))
     n = len(w["pos"])
-    sys_ = System(model, n, w["L"], w["periodic"], cap=cap, device=device)
+    sys_ = System(model, n, w["L"], w["periodic"], cap=cap, device=device, s_cap=s_cap)
     sys_.set_regions(w["regions"])
     pos = torch.from_numpy(np.ascontiguousarray(w["pos"].T)).to(device)
     species = torch.from_numpy(w["species"].astype(np.int32)).to(device)

@@ -734,11 +734,12 @@ Grid make_grid(const Ctx &c, const Box &b)
 
 static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
-WsLayout make_layout(const Ctx &c, int n, int cap, const Box &b)
+WsLayout make_layout(const Ctx &c, int n, int cap, const Box &b, int scap)
 {
     WsLayout L{};
     L.n = n;
     L.cap = cap;
+    L.scap = (scap <= 0 || scap > n) ? n : scap;
     int P = 1;
     while (P < cap)
         P <<= 1;
@@ -773,13 +774,14 @@ WsLayout make_layout(const Ctx &c, int n, int cap, const Box &b)
     take(L.M_idx, nn * sizeof(int));
     take(L.S_local, nn * sizeof(int));
     take(L.cand, nn);
-    take(L.A, nn * c.m.KAt * tsz);
-    take(L.dEdA, nn * c.m.KAt * tsz);
-    take(L.g, nn * cap * 3 * tsz);
+    const size_t ns = (size_t)(L.scap > 0 ? L.scap : 1);
+    take(L.A, ns * c.m.KAt * tsz);
+    take(L.dEdA, ns * c.m.KAt * tsz);
+    take(L.g, ns * cap * 3 * tsz);
     take(L.h, nn * cap * 3 * tsz);
     take(L.red, (size_t)std::max(kReduceBlocks, n <= kGatherKickMax ? (n + 3) / 4 : 0) * 3 *
                     sizeof(double));
-    take(L.dpart, nn * (size_t)(c.m.dp_stride > 0 ? c.m.dp_stride : 1) * tsz);
+    take(L.dpart, ns * (size_t)(c.m.dp_stride > 0 ? c.m.dp_stride : 1) * tsz);
     L.total = off;
     return L;
 }
@@ -1004,7 +1006,7 @@ try {
 extern "C" double mlmix_list_radius(const mlmix_ctx *ctx) { return ctx ? ctx->c.r_list : 0.0; }
 
 extern "C" int mlmix_workspace_size(const mlmix_ctx *ctx, int32_t n_atoms, int32_t nbr_cap,
-                                    const mlmix_box *box, size_t *bytes)
+                                    int32_t s_cap, const mlmix_box *box, size_t *bytes)
 try {
     if (!ctx || !bytes)
         return fail(MLMIX_E_ARG, "NULL argument");
@@ -1014,7 +1016,7 @@ try {
     int rc = check_box(ctx, box, b);
     if (rc)
         return rc;
-    WsLayout L = make_layout(ctx->c, n_atoms, nbr_cap, b);
+    WsLayout L = make_layout(ctx->c, n_atoms, nbr_cap, b, s_cap);
     if ((double)L.grid.ncell * L.grid.bucket >= 2147483647.0)
         return fail(MLMIX_E_ARG, "box too large for the cell grid (2^31 bucket records)");
     *bytes = L.total;
@@ -1024,7 +1026,8 @@ try {
 }
 
 extern "C" int mlmix_workspace_init(mlmix_ctx *ctx, void *stream, void *ws, size_t ws_bytes,
-                                    int32_t n_atoms, int32_t nbr_cap, const mlmix_box *box)
+                                    int32_t n_atoms, int32_t nbr_cap, int32_t s_cap,
+                                    const mlmix_box *box)
 try {
     if (!ctx || !ws)
         return fail(MLMIX_E_ARG, "NULL argument");
@@ -1034,7 +1037,7 @@ try {
     int rc = check_box(ctx, box, b);
     if (rc)
         return rc;
-    WsLayout L = make_layout(ctx->c, n_atoms, nbr_cap, b);
+    WsLayout L = make_layout(ctx->c, n_atoms, nbr_cap, b, s_cap);
     if ((double)L.grid.ncell * L.grid.bucket >= 2147483647.0)
         return fail(MLMIX_E_ARG, "box too large for the cell grid (2^31 bucket records)");
     if (ws_bytes < L.total)
@@ -1526,6 +1529,9 @@ try {
         return fail(MLMIX_E_NEIGH_OVERFLOW, "neighbour row capacity exceeded");
     if (st & MLMIX_STATUS_SEEDED_REGIONS)
         return fail(MLMIX_E_ARG, "more than 8 seeded regions");
+    if (st & MLMIX_STATUS_S_OVERFLOW)
+        return fail(MLMIX_E_WORKSPACE, "|S| exceeded the workspace's S capacity (n_expensive[0] "
+                                       "holds the required value)");
     if (st & MLMIX_STATUS_CELL_OVERFLOW)
         return fail(MLMIX_E_NEIGH_OVERFLOW, "cell bucket capacity exceeded (local density far "
                                             "above the mean)");
@@ -1619,7 +1625,7 @@ static int fit_config(mlmix_ctx *ctx, int nd, void *ws, int32_t n_atoms, const d
         return rc;
     // per-atom energy rows and 3-body lists live in the pair-gradient
     // scratch of the workspace
-    const size_t avail = 2 * (h.L.h - h.L.g);
+    const size_t avail = h.L.red - h.L.g;  // the expensive and cheap gradient buffers
     if ((size_t)h.L.n * (nd * sizeof(double) + (kMaxTriplet + 1) * sizeof(int)) > avail)
         return fail(MLMIX_E_WORKSPACE, "workspace too small for the design rows (raise nbr_cap)");
     h.ws = ws;

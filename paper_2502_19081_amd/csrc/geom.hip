@@ -935,7 +935,8 @@ __global__ void __launch_bounds__(256) k_cmp_apply(const uint8_t *__restrict__ f
                                                    const int *__restrict__ partM, int *hdr,
                                                    int32_t *n_expensive, int *__restrict__ S_idx,
                                                    int *__restrict__ M_idx,
-                                                   int *__restrict__ S_local, int direct)
+                                                   int *__restrict__ S_local, int direct,
+                                                   int scap)
 {
     __shared__ int sh[4];
     __shared__ int offs[2];
@@ -1009,8 +1010,10 @@ __global__ void __launch_bounds__(256) k_cmp_apply(const uint8_t *__restrict__ f
         if (i >= n)
             break;
         if (f[k] & 5) {
+            // atoms past the S capacity get no rows of the per-S buffers: the
+            // evaluation is then incomplete, which the status bit reports
             S_idx[es] = i;
-            S_local[i] = es;
+            S_local[i] = es < scap ? es : -1;
             es++;
         } else {
             S_local[i] = -1;
@@ -1021,7 +1024,10 @@ __global__ void __launch_bounds__(256) k_cmp_apply(const uint8_t *__restrict__ f
         }
     }
     if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
-        hdr[H_NS] = offs[0] + bs;
+        const int nS = offs[0] + bs;
+        hdr[H_NS] = nS < scap ? nS : scap;
+        if (nS > scap)
+            atomicOr(&hdr[H_STATUS], MLMIX_STATUS_S_OVERFLOW);
         hdr[H_NM] = offs[1] + bm;
         if (n_expensive) {
             n_expensive[0] = offs[0] + bs;
@@ -1045,7 +1051,7 @@ void launch_compact(hipStream_t s, void *ws, const WsLayout &L, uint8_t *flags,
         k_cmp_blocksum<<<nb, 256, 0, s>>>(flags, n, partS, partM);
     k_cmp_apply<<<nb, 256, 0, s>>>(flags, n, partS, partM, at<int>(ws, L.hdr), n_expensive,
                                    at<int>(ws, L.S_idx), at<int>(ws, L.M_idx),
-                                   at<int>(ws, L.S_local), direct);
+                                   at<int>(ws, L.S_local), direct, L.scap);
 }
 
 }  // namespace mlmix

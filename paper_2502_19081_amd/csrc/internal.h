@@ -53,6 +53,7 @@ struct Grid {
 
 struct WsLayout {
     int n, cap, P;  // atoms, row capacity, capacity rounded up to a power of two
+    int scap;       // capacity of S (rows of the per-S buffers A, dE/dA, g, partial D)
     Grid grid;
     int n_scan_blk;  // blocks of the atom-sized scans
     size_t hdr, cell_count, cell_atoms, scan_part, seedcore;
@@ -123,7 +124,7 @@ struct Ctx {
     int device;
 };
 
-WsLayout make_layout(const Ctx &c, int n, int cap, const Box &b);
+WsLayout make_layout(const Ctx &c, int n, int cap, const Box &b, int scap);
 Grid make_grid(const Ctx &c, const Box &b);
 
 // Species index clamped into the model's range (invalid input is reported by

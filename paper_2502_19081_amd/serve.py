@@ -58,7 +58,7 @@ class Replica:
         """Device bytes of this replica: workspace plus resident state."""
         sz = ctypes.c_size_t()
         box = core.make_box(self.w["L"], self.w["periodic"])
-        B.check(B.lib().mlmix_workspace_size(model.handle, self.n, cap, ctypes.byref(box),
+        B.check(B.lib().mlmix_workspace_size(model.handle, self.n, cap, 0, ctypes.byref(box),
                                              ctypes.byref(sz)))
         state = self.n * (3 * 8 * 4 + 8 * 4 + 4 + 1) + 4096
         return int(sz.value) + state
