@@ -250,6 +250,36 @@ int mlmix_compute(mlmix_ctx *ctx, void *stream, void *ws, int32_t n_atoms,
                   double *lambda, uint8_t *flags, int32_t *n_expensive,
                   double *f_exp, double *f_cheap);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the mixed
+ * force evaluation of mlmix_compute without a caller workspace. Its
+ * workspace is a static device array of the library,
+ * MLMIX_NOALLOC_SCRATCH_BYTES per GPU (each GPU the library runs on holds
+ * its copy until the process ends; the device address is looked up by
+ * mlmix_create on that device). The call allocates nothing (no hipMalloc,
+ * no stream or event creation): every stage runs on `stream`, the neighbour
+ * list is rebuilt on each call (the scratch keeps the last call's contents,
+ * so the header and cell counts are cleared first by fill kernels), and no
+ * stage timing is recorded. nbr_cap and s_cap as for mlmix_workspace_size;
+ * status [dev] int32[2] (may be NULL) receives this call's MLMIX_STATUS_*
+ * bits and largest neighbour count (as mlmix_status reports them for a
+ * workspace; read it after the stream reaches the call); *bytes_used [host]
+ * (may be NULL) receives the scratch bytes this system needs. Arguments and
+ * outputs otherwise as mlmix_compute (without f_exp / f_cheap;
+ * MLMIX_ENERGY_ONLY is refused). The results equal mlmix_compute's with
+ * MLMIX_FORCE_REBUILD on a workspace of the same nbr_cap and s_cap bit for
+ * bit. Calls that overlap on one GPU (other streams, other threads, other
+ * contexts) share the scratch and race: the caller serialises them.
+ * Errors: those of mlmix_compute, and MLMIX_E_WORKSPACE when the system
+ * needs more than MLMIX_NOALLOC_SCRATCH_BYTES (lower s_cap or nbr_cap). */
+#define MLMIX_NOALLOC_SCRATCH_BYTES (64u << 20)
+int mlmix_compute_noalloc(mlmix_ctx *ctx, void *stream, int32_t n_atoms, int32_t nbr_cap,
+                          int32_t s_cap, const double *pos, const int32_t *species,
+                          const mlmix_box *box, const mlmix_region *regions, int32_t n_regions,
+                          double r_buffer, uint32_t mode, double *forces, double *e_exp,
+                          double *e_cheap, double *lambda, uint8_t *flags,
+                          int32_t *n_expensive, int32_t *status, size_t *bytes_used);
+
 /* Adjoint of the expensive site energies: grad_pos = d(sum_i w_i E_i)/dx
  * (3 x n double [dev]) for weights w = grad_e [dev] double[n], using S, the
  * neighbour list and dE/dA from the last mlmix_compute on this workspace

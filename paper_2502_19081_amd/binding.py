@@ -23,6 +23,7 @@ SEEDED = 0x800
 FLAG_SEED = 0x80
 CHEAP_MASKED = 0x1000
 N_STAGES = 12
+NOALLOC_SCRATCH_BYTES = 64 << 20
 STATUS_NEIGH_OVERFLOW, STATUS_OUT_OF_BOX, STATUS_NONFINITE, STATUS_TRIPLET_OVERFLOW, STATUS_BAD_SPECIES = 1, 2, 4, 8, 16
 STATUS_CELL_OVERFLOW, STATUS_SEEDED_REGIONS, STATUS_S_OVERFLOW = 32, 64, 128
 
@@ -76,6 +77,9 @@ SIGNATURES = {
                                             ctypes.POINTER(Box)]),
     "mlmix_compute": (ctypes.c_int, [_vp, _vp, _vp, _i32, _vp, _vp, ctypes.POINTER(Box), _vp, _i32, _d,
                                      _u32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "mlmix_compute_noalloc": (ctypes.c_int, [_vp, _vp, _i32, _i32, _i32, _vp, _vp,
+                                             ctypes.POINTER(Box), _vp, _i32, _d, _u32, _vp, _vp,
+                                             _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(_sz)]),
     "mlmix_backward": (ctypes.c_int, [_vp, _vp, _vp, _i32, _vp, _vp, ctypes.POINTER(Box), _vp, _vp]),
     "mlmix_vv_step": (ctypes.c_int, [_vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp, _d, ctypes.POINTER(Box),
                                      _vp, _i32, _d, _u32, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),

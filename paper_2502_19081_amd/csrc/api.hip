@@ -72,6 +72,10 @@ static hipEvent_t take_event(mlmix_ctx *ctx)
     return e;
 }
 
+// Set for the duration of an allocation-free call: stage brackets take
+// events, which such a call must not create.
+static thread_local bool tl_no_timers = false;
+
 // Brackets one stage with events when its bit is set in the profile mask.
 // Times a stage with two events on its stream. With kernel_events the stage
 // is one kernel whose launcher passes k0/k1 to hipExtLaunchKernel, so the
@@ -85,7 +89,7 @@ struct StageTimer {
     StageTimer(mlmix_ctx *c, hipStream_t st, int stg, bool kernel_events = false)
         : ctx(c), s(st), stage(stg)
     {
-        if (ctx->prof_mask & (1u << stage)) {
+        if (!tl_no_timers && (ctx->prof_mask & (1u << stage))) {
             if (kernel_events) {
                 k0 = take_event(ctx);
                 k1 = take_event(ctx);
@@ -167,6 +171,42 @@ extern "C" const char *mlmix_last_error(void) { return g_err; }
         if (e_ != hipSuccess)               \
             return fail_hip(#expr, e_);     \
     } while (0)
+
+// ------------------------------------------- workspace of the allocation-free call
+// mlmix_compute_noalloc keeps its workspace in this file-scope device array
+// (one copy per GPU the library runs on, held until the process ends). Host
+// code never passes the array's name to a kernel or a copy: the device
+// address of each GPU's copy is looked up once per device, at mlmix_create
+// with that device current, and kept in g_scratch_dev.
+static __device__ __align__(256) unsigned char scratch[MLMIX_NOALLOC_SCRATCH_BYTES];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_dev[kMaxDevices] = {};
+
+static int scratch_setup(int device)
+{
+    if (device < 0 || device >= kMaxDevices)
+        return fail(MLMIX_E_ARG, "device index beyond the library's table of 64 devices");
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (g_scratch_dev[device])
+        return MLMIX_OK;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess)
+        return fail_hip("hipGetSymbolAddress(scratch)", e);
+    if (!p)
+        return fail(MLMIX_E_HIP, "hipGetSymbolAddress(scratch) returned no address");
+    g_scratch_dev[device] = p;
+    return MLMIX_OK;
+}
+
+static void *scratch_ptr(int device)
+{
+    if (device < 0 || device >= kMaxDevices)
+        return nullptr;
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    return g_scratch_dev[device];
+}
 
 namespace mlmix {
 
@@ -866,6 +906,13 @@ try {
         rmax = std::max(rmax, d.uf3_rcut3);
     c.r_list = rmax + d.skin;
     HIP_OK(hipGetDevice(&c.device));
+    {
+        // device address of this GPU's copy of the allocation-free call's
+        // workspace (once per device)
+        const int rc_s = scratch_setup(c.device);
+        if (rc_s != MLMIX_OK)
+            return rc_s;
+    }
     HostTables t;
     int rc = build_tables(d, t);
     if (rc != MLMIX_OK)
@@ -1304,6 +1351,77 @@ try {
     return compute_impl(ctx, static_cast<hipStream_t>(stream), ws, L, b, pos, species, regions,
                         n_regions, r_buffer, mode, forces, e_exp, e_cheap, lambda, flags,
                         n_expensive, f_exp, f_cheap);
+} catch (...) {
+    return host_exception();
+}
+
+extern "C" int mlmix_compute_noalloc(mlmix_ctx *ctx, void *stream, int32_t n_atoms,
+                                     int32_t nbr_cap, int32_t s_cap, const double *pos,
+                                     const int32_t *species, const mlmix_box *box,
+                                     const mlmix_region *regions, int32_t n_regions,
+                                     double r_buffer, uint32_t mode, double *forces,
+                                     double *e_exp, double *e_cheap, double *lambda,
+                                     uint8_t *flags, int32_t *n_expensive, int32_t *status,
+                                     size_t *bytes_used)
+try {
+    if (!ctx)
+        return fail(MLMIX_E_ARG, "NULL context");
+    if (n_atoms < 0 || nbr_cap < 1 || nbr_cap > kMaxCap)
+        return fail(MLMIX_E_ARG, "n_atoms >= 0 and 1 <= nbr_cap <= 256 required");
+    if (mode & ~(0xffu | MLMIX_FORCE_REBUILD | MLMIX_SINGLE_STREAM | MLMIX_SEEDED |
+                 MLMIX_CHEAP_MASKED))
+        return fail(MLMIX_E_ARG, "unknown or unsupported mode flag (MLMIX_ENERGY_ONLY is not "
+                                 "available here)");
+    Box b;
+    int rc = check_box(ctx, box, b);
+    if (rc)
+        return rc;
+    rc = check_compute_args(ctx, pos, species, regions, n_regions, r_buffer, mode, forces, e_exp,
+                            e_cheap, lambda, flags, n_atoms);
+    if (rc)
+        return rc;
+    const WsLayout L = make_layout(ctx->c, n_atoms, nbr_cap, b, s_cap);
+    if (bytes_used)
+        *bytes_used = L.total;
+    if ((double)L.grid.ncell * L.grid.bucket >= 2147483647.0)
+        return fail(MLMIX_E_ARG, "box too large for the cell grid (2^31 bucket records)");
+    if (L.total > (size_t)MLMIX_NOALLOC_SCRATCH_BYTES)
+        return fail(MLMIX_E_WORKSPACE, "this system needs more workspace than the library's "
+                                       "static scratch (MLMIX_NOALLOC_SCRATCH_BYTES; *bytes_used "
+                                       "holds the need): lower s_cap or nbr_cap, or use "
+                                       "mlmix_compute with a workspace");
+    void *ws = scratch_ptr(ctx->c.device);
+    if (!ws)
+        return fail(MLMIX_E_STATE, "the static scratch of this device was not set up "
+                                   "(mlmix_create on this device failed or was not called)");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (L.n == 0) {
+        if (status)
+            k_zero_i32<<<1, 64, 0, s>>>(status, 2);
+        return empty_outputs(s, n_expensive, nullptr, 0);
+    }
+    // the scratch keeps whatever the last call on this GPU left: clear the
+    // header and the cell counts with fill kernels (no memset nodes, so the
+    // call may be captured), then build the list afresh
+    k_zero_i32<<<1, H_COUNT, 0, s>>>(at<int>(ws, L.hdr), H_COUNT);
+    k_zero_i32<<<(L.grid.ncell + 255) / 256, 256, 0, s>>>(at<int>(ws, L.cell_count),
+                                                           L.grid.ncell);
+    HIP_OK(hipGetLastError());
+    struct NoTimers {
+        NoTimers() { tl_no_timers = true; }
+        ~NoTimers() { tl_no_timers = false; }
+    } no_timers;
+    rc = compute_impl(ctx, s, ws, L, b, pos, species, regions, n_regions, r_buffer,
+                      mode | MLMIX_FORCE_REBUILD | MLMIX_SINGLE_STREAM, forces, e_exp, e_cheap,
+                      lambda, flags, n_expensive, nullptr, nullptr);
+    if (rc)
+        return rc;
+    if (status) {  // the status word and the largest row count of this call
+        static_assert(H_REQCAP == H_STATUS + 1, "status words are adjacent");
+        launch_copy_i32(s, status, at<int>(ws, L.hdr) + H_STATUS, 2);
+        HIP_OK(hipGetLastError());
+    }
+    return MLMIX_OK;
 } catch (...) {
     return host_exception();
 }
