@@ -343,6 +343,79 @@ int mlmix_energy_reduce(mlmix_ctx *ctx, void *stream, void *ws, int32_t n_atoms,
                         const double *e_exp, const double *e_cheap, const double *vel,
                         const double *mass, double *energies);
 
+/* ---------------------------------------------------------------------
+ * Batched systems: several independent systems (MD replicas) sharing one
+ * model, evaluated and integrated together, one launch per kernel for the
+ * whole batch (the serving workload). The systems' atoms sit side by side
+ * in the batch arrays (SoA over all n_atoms of the batch: x of every atom,
+ * then y, then z); a segment table gives each system its range, box and
+ * regions. Every kernel takes its atom's box, cell grid and regions from the
+ * table, neighbour rows never cross systems, and each system's results are
+ * the same bits alone and in any batch (launch shapes that change the
+ * rounding do not depend on the batch's size or composition). Systems share
+ * the neighbour-list rebuild decision (an atom of any system moving more
+ * than skin/2 rebuilds every list), dt, r_buffer and the mode; seeded
+ * regions and MLMIX_ENERGY_ONLY are not available. */
+typedef struct {
+    int32_t offset;        /* first atom of the system in the batch arrays (the
+                              segments tile [0, n_atoms) in order) */
+    int32_t n_atoms;       /* >= 1 */
+    mlmix_box box;         /* the system's box, as for a single system */
+    int32_t region_offset; /* its regions are regions[region_offset ..
+                              region_offset + n_regions) of the call's array;
+                              follow_atom counts from the system's first atom */
+    int32_t n_regions;
+} mlmix_segment;
+
+/* Bytes of a batch workspace for the segment table segs [host] (n_segments
+ * entries), a neighbour-row capacity nbr_cap and an S capacity s_cap for
+ * the whole batch (as for mlmix_workspace_size; 0 = every atom). */
+int mlmix_batch_workspace_size(const mlmix_ctx *ctx, int32_t n_segments,
+                               const mlmix_segment *segs, int32_t nbr_cap, int32_t s_cap,
+                               size_t *bytes);
+
+/* Prepares a batch workspace for the segment table segs [host]: clears its
+ * header, copies the table to the device (waits for `stream` once: call it
+ * outside graph capture) and tags every atom with its segment. Call it again
+ * whenever the set of systems changes; the next call rebuilds every list.
+ * Errors: MLMIX_E_ARG (segments not tiling [0, n) in order, an empty
+ * segment, sizes), MLMIX_E_BOX, MLMIX_E_WORKSPACE. */
+int mlmix_batch_init(mlmix_ctx *ctx, void *stream, void *ws, size_t ws_bytes, int32_t n_segments,
+                     const mlmix_segment *segs, int32_t nbr_cap, int32_t s_cap);
+
+/* The mixed force evaluation of every system of the batch, as mlmix_compute
+ * per system: n_atoms = the batch's total, per-atom arrays over the batch,
+ * regions [dev] mlmix_region[n_regions] holding every segment's range.
+ * n_expensive [dev] int32[n_segments][2] (may be NULL) receives each
+ * system's |S| and |{lambda > 0}|; energies [dev] double[n_segments][3] (may
+ * be NULL) each system's (sum e_exp, sum e_cheap, 0). */
+int mlmix_batch_compute(mlmix_ctx *ctx, void *stream, void *ws, int32_t n_atoms,
+                        const double *pos, const int32_t *species, const mlmix_region *regions,
+                        int32_t n_regions, double r_buffer, uint32_t mode, double *forces,
+                        double *e_exp, double *e_cheap, double *lambda, uint8_t *flags,
+                        int32_t *n_expensive, double *energies);
+
+/* n_steps velocity-Verlet steps of every system of the batch, each step as
+ * mlmix_vv_step per system (the same bits as that system's own
+ * mlmix_vv_steps up to the energy sums' summation order, which here is per
+ * system and fixed): one launch per kernel per step for the whole batch.
+ * energies [dev] double[n_steps][n_segments][3] receives each system's
+ * (sum e_exp, sum e_cheap, kinetic) after every step; n_expensive [dev]
+ * int32[n_segments][2] (may be NULL) the set sizes of the last step. A
+ * thermostat set with mlmix_set_langevin does not apply here. */
+int mlmix_batch_vv_steps(mlmix_ctx *ctx, void *stream, void *ws, int32_t n_atoms, double *pos,
+                         double *vel, const double *mass, const int32_t *species, double dt,
+                         int32_t n_steps, const mlmix_region *regions, int32_t n_regions,
+                         double r_buffer, uint32_t mode, double *forces, double *e_exp,
+                         double *e_cheap, double *lambda, uint8_t *flags, int32_t *n_expensive,
+                         double *energies);
+
+/* As mlmix_status for a batch workspace, and segment_bits [host]
+ * int32[n_segments] (may be NULL) receives each system's own MLMIX_STATUS_*
+ * bits (so that a failing replica can be evicted alone). */
+int mlmix_batch_status(mlmix_ctx *ctx, void *stream, void *ws, int32_t *segment_bits,
+                       int32_t *required_cap);
+
 /* Waits for `stream`, then reads the device status word of the workspace:
  * *status_bits receives MLMIX_STATUS_* bits, *required_cap the largest
  * neighbour count of an overflowing row (0 without overflow; for regrowing

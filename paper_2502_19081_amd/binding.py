@@ -52,6 +52,11 @@ class FitConfig(ctypes.Structure):
                 ("rows", ctypes.c_void_p)]
 
 
+class Segment(ctypes.Structure):
+    _fields_ = [("offset", ctypes.c_int32), ("n_atoms", ctypes.c_int32), ("box", Box),
+                ("region_offset", ctypes.c_int32), ("n_regions", ctypes.c_int32)]
+
+
 class Region(ctypes.Structure):
     _fields_ = [("type", ctypes.c_int32), ("axis", ctypes.c_int32),
                 ("follow_atom", ctypes.c_int32), ("blend", ctypes.c_int32),
@@ -60,6 +65,7 @@ class Region(ctypes.Structure):
 
 
 assert ctypes.sizeof(Region) == 56
+assert ctypes.sizeof(Segment) == 56
 
 _vp = ctypes.c_void_p
 _i32 = ctypes.c_int32
@@ -88,6 +94,15 @@ SIGNATURES = {
                                       ctypes.POINTER(Box), _vp, _i32, _d, _u32, _vp, _vp, _vp,
                                       _vp, _vp, _vp, _vp]),
     "mlmix_energy_reduce": (ctypes.c_int, [_vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp, _vp]),
+    "mlmix_batch_workspace_size": (ctypes.c_int, [_vp, _i32, _vp, _i32, _i32,
+                                                  ctypes.POINTER(_sz)]),
+    "mlmix_batch_init": (ctypes.c_int, [_vp, _vp, _vp, _sz, _i32, _vp, _i32, _i32]),
+    "mlmix_batch_compute": (ctypes.c_int, [_vp, _vp, _vp, _i32, _vp, _vp, _vp, _i32, _d, _u32,
+                                           _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "mlmix_batch_vv_steps": (ctypes.c_int, [_vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp, _d, _i32,
+                                            _vp, _i32, _d, _u32, _vp, _vp, _vp, _vp, _vp, _vp,
+                                            _vp]),
+    "mlmix_batch_status": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.POINTER(_i32)]),
     "mlmix_status": (ctypes.c_int, [_vp, _vp, _vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
     "mlmix_get_neighbors": (ctypes.c_int, [_vp, _vp, _vp, _i32, _vp, _vp]),
     "mlmix_get_index_sets": (ctypes.c_int, [_vp, _vp, _vp, _i32, _vp, _vp]),

@@ -282,3 +282,102 @@ def system_for(w, model=None, cap=128, device="cuda", s_cap=0):
     pos = torch.from_numpy(np.ascontiguousarray(w["pos"].T)).to(device)
     species = torch.from_numpy(w["species"].astype(np.int32)).to(device)
     return model, sys_, pos, species
+
+
+class Batch:
+    """Several independent systems sharing one model, evaluated and integrated
+    together: one launch per kernel for the whole batch (mlmix_batch_*).
+
+    systems: list of dicts with n (atoms), L, periodic and regions (region
+    dictionaries as for System.set_regions; follow_atom counts from the
+    system's first atom). The batch arrays hold the systems side by side:
+    positions (3, n_total) SoA, per-atom arrays (n_total,); `offsets[k]` is
+    the first atom of system k."""
+
+    def __init__(self, model, systems, cap=128, s_cap=0, device="cuda"):
+        self.model = model
+        self.device = device
+        self.cap = int(cap)
+        self.s_cap = int(s_cap)
+        self.nseg = len(systems)
+        segs = (B.Segment * max(self.nseg, 1))()
+        regions = []
+        off = 0
+        self.offsets = []
+        self.sizes = []
+        for k, sy in enumerate(systems):
+            n = int(sy["n"])
+            segs[k].offset = off
+            segs[k].n_atoms = n
+            segs[k].box = make_box(sy["L"], sy["periodic"])
+            segs[k].region_offset = len(regions)
+            segs[k].n_regions = len(sy.get("regions", []))
+            regions.extend(sy.get("regions", []))
+            self.offsets.append(off)
+            self.sizes.append(n)
+            off += n
+        self.n = off
+        self.segs = segs
+        self.n_regions = len(regions)
+        self.regions = pack_regions(regions, device)
+        sz = ctypes.c_size_t()
+        B.check(B.lib().mlmix_batch_workspace_size(model.handle, self.nseg, segs, self.cap,
+                                                   self.s_cap, ctypes.byref(sz)))
+        self.ws_bytes = int(sz.value)
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
+        B.check(B.lib().mlmix_batch_init(model.handle, _stream(), _p(self.ws), self.ws_bytes,
+                                         self.nseg, segs, self.cap, self.s_cap))
+        z = dict(dtype=torch.float64, device=device)
+        self.forces = torch.zeros(3, self.n, **z)
+        self.e_exp = torch.zeros(self.n, **z)
+        self.e_cheap = torch.zeros(self.n, **z)
+        self.lam = torch.zeros(self.n, **z)
+        self.flags = torch.zeros(self.n, dtype=torch.uint8, device=device)
+        self.n_exp = torch.zeros(self.nseg, 2, dtype=torch.int32, device=device)
+        self.energies = torch.zeros(self.nseg, 3, **z)
+
+    def _flags(self, mode, force_rebuild, single_stream, cheap_masked):
+        return (mode | (B.FORCE_REBUILD if force_rebuild else 0) |
+                (B.SINGLE_STREAM if single_stream else 0) | (B.CHEAP_MASKED if cheap_masked else 0))
+
+    def compute(self, pos, species, r_buffer=0.0, mode=B.MODE_MIXED, force_rebuild=False,
+                single_stream=False, cheap_masked=False):
+        assert pos.shape == (3, self.n) and pos.dtype == torch.float64 and pos.is_contiguous()
+        assert species.shape == (self.n,) and species.dtype == torch.int32
+        B.check(B.lib().mlmix_batch_compute(
+            self.model.handle, _stream(), _p(self.ws), self.n, _p(pos), _p(species),
+            _p(self.regions), self.n_regions, float(r_buffer),
+            self._flags(mode, force_rebuild, single_stream, cheap_masked), _p(self.forces),
+            _p(self.e_exp), _p(self.e_cheap), _p(self.lam), _p(self.flags), _p(self.n_exp),
+            _p(self.energies)))
+        return dict(forces=self.forces, e_exp=self.e_exp, e_cheap=self.e_cheap, lam=self.lam,
+                    flags=self.flags, n_exp=self.n_exp, energies=self.energies)
+
+    def vv_steps(self, pos, vel, mass, species, dt, n_steps, r_buffer=0.0, mode=B.MODE_MIXED,
+                 force_rebuild=True, single_stream=False, cheap_masked=False, energies=None):
+        """n_steps velocity-Verlet steps of every system; returns the
+        (n_steps, n_systems, 3) energy sums (expensive, cheap, kinetic)."""
+        if energies is None:
+            energies = torch.zeros(n_steps, self.nseg, 3, dtype=torch.float64,
+                                   device=self.device)
+        B.check(B.lib().mlmix_batch_vv_steps(
+            self.model.handle, _stream(), _p(self.ws), self.n, _p(pos), _p(vel), _p(mass),
+            _p(species), float(dt), int(n_steps), _p(self.regions), self.n_regions,
+            float(r_buffer), self._flags(mode, force_rebuild, single_stream, cheap_masked),
+            _p(self.forces), _p(self.e_exp), _p(self.e_cheap), _p(self.lam), _p(self.flags),
+            _p(self.n_exp), _p(energies)))
+        return energies
+
+    def status(self, raise_on_error=True):
+        """(per-system status bits, required row capacity, return code)."""
+        bits = (ctypes.c_int32 * max(self.nseg, 1))()
+        req = ctypes.c_int32()
+        rc = B.lib().mlmix_batch_status(self.model.handle, _stream(), _p(self.ws), bits,
+                                        ctypes.byref(req))
+        if raise_on_error:
+            B.check(rc)
+        return [int(bits[k]) for k in range(self.nseg)], int(req.value), rc
+
+    def slice(self, k):
+        """Atom range of system k in the batch arrays."""
+        return slice(self.offsets[k], self.offsets[k] + self.sizes[k])

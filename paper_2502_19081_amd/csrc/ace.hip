@@ -68,10 +68,10 @@ constexpr int kMaxOwn = 16;  // (lm, channel) entries per lane: L2 * nchp <= 102
 // the block's longest row so that the waves meet at every barrier.
 template <typename T>
 __global__ void __launch_bounds__(256)
-    k_ace_basis(const double *__restrict__ pos, int n, Box b, const int32_t *__restrict__ species,
+    k_ace_basis(const double *__restrict__ pos, int n, Box b0, const int32_t *__restrict__ species,
                 int cap, const int *__restrict__ nbr, const int *__restrict__ cnt,
                 const int *__restrict__ S_idx, const int *__restrict__ S_local,
-                const int *__restrict__ hdr, AceArgs<T> a, int wpb, T *__restrict__ A)
+                const int *__restrict__ hdr, AceArgs<T> a, int wpb, T *__restrict__ A, Seg sg)
 {
     const int nS = hdr[H_NS];
     if (blockIdx.x * wpb >= nS)
@@ -87,6 +87,7 @@ __global__ void __launch_bounds__(256)
     int *zt = reinterpret_cast<int *>(reinterpret_cast<T *>(smem_raw) + (size_t)wpb * slice) + w * 64;
     __shared__ int cm[4];
     const int i = valid ? S_idx[s] : 0;
+    const Box b = seg_box(b0, sg, i);
     const int c = valid ? cnt[i] : 0;
     if (lane == 0)
         cm[w] = c;
@@ -511,11 +512,11 @@ __global__ void __launch_bounds__(256)
 
 template <typename T>
 __global__ void __launch_bounds__(256)
-    k_ace_pairgrad(const double *__restrict__ pos, int n, Box b, const int32_t *__restrict__ species,
+    k_ace_pairgrad(const double *__restrict__ pos, int n, Box b0, const int32_t *__restrict__ species,
                    int cap, const int *__restrict__ nbr, const int *__restrict__ cnt,
                    const int *__restrict__ S_idx, const int *__restrict__ S_local,
                    const int *__restrict__ hdr, AceArgs<T> a, int wpb, const T *__restrict__ dEdA,
-                   const double *__restrict__ weights, T *__restrict__ g)
+                   const double *__restrict__ weights, T *__restrict__ g, Seg sg)
 {
     const int nS = hdr[H_NS];
     const int w = threadIdx.x >> 6;
@@ -526,6 +527,7 @@ __global__ void __launch_bounds__(256)
     extern __shared__ __align__(16) char smem_raw[];
     T *dAs = reinterpret_cast<T *>(smem_raw) + (size_t)w * a.KAt;
     const int i = S_idx[s];
+    const Box b = seg_box(b0, sg, i);
     T wgt = weights ? T(weights[i]) : T(1);
     for (int e = lane; e < a.KAt; e += 64)
         dAs[e] = dEdA[(size_t)s * a.KAt + e] * wgt;
@@ -726,11 +728,11 @@ __device__ __forceinline__ void wave_sync_ace()
 // (8,193 atoms: 132.7 against 135.4 us per step).
 template <int MT, int NT>
 __global__ void __launch_bounds__(256)
-    k_ace_basis_mfma_chunks(const double *__restrict__ pos, int n, Box b,
+    k_ace_basis_mfma_chunks(const double *__restrict__ pos, int n, Box b0,
                      const int32_t *__restrict__ species, int cap, const int *__restrict__ nbr,
                      const int *__restrict__ cnt, const int *__restrict__ S_idx,
                      const int *__restrict__ S_local, const int *__restrict__ hdr,
-                     AceArgs<float> a, int wpb, float *__restrict__ A)
+                     AceArgs<float> a, int wpb, float *__restrict__ A, Seg sg)
 {
     constexpr int RW = 16 * MT + 1, YW = 16 * NT + 1;
     const int nS = hdr[H_NS];
@@ -743,6 +745,7 @@ __global__ void __launch_bounds__(256)
     float *Yt = Rz + 64 * RW;
     const int m16 = lane & 15, kg = lane >> 4;
     const int i = S_idx[s];
+    const Box b = seg_box(b0, sg, i);
     const int c = cnt[i];
     const int *row = nbr + (size_t)i * cap;
     const int nrad = a.nrad, nch = a.nchan, L2 = a.L2;
@@ -849,11 +852,11 @@ __global__ void __launch_bounds__(256)
 // are free of bank conflicts.
 template <int MT, int NT>
 __global__ void __launch_bounds__(256)
-    k_ace_basis_mfma(const double *__restrict__ pos, int n, Box b,
+    k_ace_basis_mfma(const double *__restrict__ pos, int n, Box b0,
                      const int32_t *__restrict__ species, int cap, const int *__restrict__ nbr,
                      const int *__restrict__ cnt, const int *__restrict__ S_idx,
                      const int *__restrict__ S_local, const int *__restrict__ hdr,
-                     AceArgs<float> a, int wpb, float *__restrict__ A)
+                     AceArgs<float> a, int wpb, float *__restrict__ A, Seg sg)
 {
     constexpr int RW = 16 * MT + 1, YW = 16 * NT + 1;
     const int nS = hdr[H_NS];
@@ -867,6 +870,7 @@ __global__ void __launch_bounds__(256)
     float *Yt = Rz + 64 * RW;
     const int m16 = lane & 15, kg = lane >> 4;
     const int i = S_idx[s];
+    const Box b = seg_box(b0, sg, i);
     const int c = cnt[i];
     const int *row = nbr + (size_t)i * cap;
     const int nrad = a.nrad, nch = a.nchan, L2 = a.L2;
@@ -951,12 +955,12 @@ __global__ void __launch_bounds__(256)
 // v = sum S_R grad_u Y, and writes g to its list slot (0 for other slots).
 template <int MT, int NT>
 __global__ void __launch_bounds__(256)
-    k_ace_pairgrad_mfma(const double *__restrict__ pos, int n, Box b,
+    k_ace_pairgrad_mfma(const double *__restrict__ pos, int n, Box b0,
                         const int32_t *__restrict__ species, int cap, const int *__restrict__ nbr,
                         const int *__restrict__ cnt, const int *__restrict__ S_idx,
                         const int *__restrict__ S_local, const int *__restrict__ hdr,
                         AceArgs<float> a, int wpb, const float *__restrict__ dEdA,
-                        const double *__restrict__ weights, float *__restrict__ g)
+                        const double *__restrict__ weights, float *__restrict__ g, Seg sg)
 {
     constexpr int RW = 16 * MT + 1, YW = 16 * NT + 1;
     constexpr int PAIR = 64 * RW * 2 > 64 * YW * 2 ? 64 * RW * 2 : 64 * YW * 2;
@@ -973,6 +977,7 @@ __global__ void __launch_bounds__(256)
     PairGeo *geo = reinterpret_cast<PairGeo *>(Gt + 16 * MT * YW);  // [64]
     const int m16 = lane & 15, kg = lane >> 4;
     const int i = S_idx[s];
+    const Box b = seg_box(b0, sg, i);
     const float wgt = weights ? float(weights[i]) : 1.0f;
     const int nrad = a.nrad, nch = a.nchan, L2 = a.L2, nchp = a.nchp;
     for (int e = lane; e < 16 * MT * 16 * NT; e += 64) {
@@ -1115,20 +1120,23 @@ template <int MT, int NT>
 static void basis_mfma_launch(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L, const Box &b,
                               const double *pos, const int32_t *species, const AceArgs<float> &a)
 {
-    if (c.basis_chunks > 0 || (c.basis_chunks < 0 && L.n > 65536)) {
+    // a batched call keeps the whole-row form whatever its total size: the
+    // two forms group the pairs differently (different rounding), and a
+    // system must give the same bits alone and in any batch
+    if (c.basis_chunks > 0 || (c.basis_chunks < 0 && L.n > 65536 && L.nseg == 0)) {
         const size_t per = (size_t)64 * (16 * MT + 1 + 16 * NT + 1) * sizeof(float);
         const int wpb = mfma_wpb(per);
         k_ace_basis_mfma_chunks<MT, NT><<<(L.n + wpb - 1) / wpb, 64 * wpb, per * wpb, s>>>(
             pos, L.n, b, species, L.cap, at<int>(ws, L.nbr), at<int>(ws, L.cnt),
             at<int>(ws, L.S_idx), at<int>(ws, L.S_local), at<int>(ws, L.hdr), a, wpb,
-            at<float>(ws, L.A));
+            at<float>(ws, L.A), seg_args(ws, L));
         return;
     }
     const size_t per = basis_mfma_lds<MT, NT>();
     const int wpb = mfma_wpb(per);
     k_ace_basis_mfma<MT, NT><<<(L.n + wpb - 1) / wpb, 64 * wpb, per * wpb, s>>>(
         pos, L.n, b, species, L.cap, at<int>(ws, L.nbr), at<int>(ws, L.cnt), at<int>(ws, L.S_idx),
-        at<int>(ws, L.S_local), at<int>(ws, L.hdr), a, wpb, at<float>(ws, L.A));
+        at<int>(ws, L.S_local), at<int>(ws, L.hdr), a, wpb, at<float>(ws, L.A), seg_args(ws, L));
 }
 
 template <int MT, int NT>
@@ -1141,7 +1149,7 @@ static void pairgrad_mfma_launch(hipStream_t s, const Ctx &c, void *ws, const Ws
     k_ace_pairgrad_mfma<MT, NT><<<(L.n + wpb - 1) / wpb, 64 * wpb, per * wpb, s>>>(
         pos, L.n, b, species, L.cap, at<int>(ws, L.nbr), at<int>(ws, L.cnt), at<int>(ws, L.S_idx),
         at<int>(ws, L.S_local), at<int>(ws, L.hdr), a, wpb, at<float>(ws, L.dEdA), weights,
-        at<float>(ws, L.g));
+        at<float>(ws, L.g), seg_args(ws, L));
 }
 
 // Dispatch over (channel tiles, lm tiles); false if the model is outside the
@@ -1184,7 +1192,7 @@ static void basis_t(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L, co
     size_t sm = (size_t)wpb * 64 * ((a.nrad + a.L2) * sizeof(T) + sizeof(int)) + 16;
     k_ace_basis<T><<<(n + wpb - 1) / wpb, 64 * wpb, sm, s>>>(
         pos, n, b, species, L.cap, at<int>(ws, L.nbr), at<int>(ws, L.cnt), at<int>(ws, L.S_idx),
-        at<int>(ws, L.S_local), at<int>(ws, L.hdr), a, wpb, at<T>(ws, L.A));
+        at<int>(ws, L.S_local), at<int>(ws, L.hdr), a, wpb, at<T>(ws, L.A), seg_args(ws, L));
 }
 
 // LDS bytes of one order-3 block workgroup of ta atoms.
@@ -1250,7 +1258,9 @@ static void finalize_t(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L,
     const size_t nC = (size_t)c.m.ns * (c.m.lmax + 1) * c.m.nchan * c.m.nchan;
     // small systems: one atom per workgroup (8,193 atoms: 10.5 against 14.5 us);
     // large: four (1M atoms: 0.55 against 0.99 ms, the staged tables shared)
-    const int apb = L.n <= 65536 ? 1 : 4;
+    // (a batched call keeps one atom per wave whatever its size, so that a
+    // system's site energies do not depend on the batch it runs in)
+    const int apb = (L.n <= 65536 && L.nseg == 0) ? 1 : 4;
     size_t sm = (size_t)apb * c.m.KAt * sizeof(T) + (c.m.n_pb + 2 * (c.m.lmax + 1)) * sizeof(int) + 16;
     int stage_c2 = 0;
     if (sm + nC * sizeof(T) <= 48 * 1024) {
@@ -1278,7 +1288,7 @@ static void pairgrad_t(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L,
     k_ace_pairgrad<T><<<(n + wpb - 1) / wpb, 64 * wpb, sm, s>>>(
         pos, n, b, species, L.cap, at<int>(ws, L.nbr), at<int>(ws, L.cnt), at<int>(ws, L.S_idx),
         at<int>(ws, L.S_local), at<int>(ws, L.hdr), a, wpb, at<T>(ws, L.dEdA), weights,
-        at<T>(ws, L.g));
+        at<T>(ws, L.g), seg_args(ws, L));
 }
 
 void launch_ace_basis(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L, const Box &b,

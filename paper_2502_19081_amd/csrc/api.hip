@@ -44,6 +44,7 @@ struct mlmix_ctx {
     std::unordered_map<void *, WsLayout> ws;
     std::unordered_map<void *, LangevinSet> lang;
     std::unordered_map<void *, SideStream> side;
+    std::unordered_map<void *, std::vector<mlmix_segment>> batch;  // segments of batch workspaces
     uint32_t prof_mask = 0;
     double flops[6] = {0, 0, 0, 0, 0, 0};
     std::vector<PendingEvent> pending;
@@ -774,24 +775,26 @@ Grid make_grid(const Ctx &c, const Box &b)
 
 static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
-WsLayout make_layout(const Ctx &c, int n, int cap, const Box &b, int scap)
+// Records per cell bucket: four times the mean occupancy plus 8, at least 16.
+static int bucket_size(int n, int ncell)
 {
-    WsLayout L{};
-    L.n = n;
-    L.cap = cap;
-    L.scap = (scap <= 0 || scap > n) ? n : scap;
+    const double mean = (double)n / (double)ncell;
+    int bk = (int)std::ceil(4.0 * mean + 8.0);
+    bk = (bk + 3) & ~3;
+    return bk < 16 ? 16 : bk;
+}
+
+// Offsets of every workspace array for n atoms (all systems of a batch),
+// ncell cell counts and nrec bucket records; nseg > 0 adds the segment
+// tables of a batch.
+static void layout_arrays(const Ctx &c, WsLayout &L, size_t ncell, size_t nrec, int nseg)
+{
+    const int n = L.n, cap = L.cap;
     int P = 1;
     while (P < cap)
         P <<= 1;
     L.P = P;
-    L.grid = make_grid(c, b);
-    // cell buckets: four times the mean occupancy plus 8, at least 16
-    {
-        const double mean = (double)n / (double)L.grid.ncell;
-        int bk = (int)std::ceil(4.0 * mean + 8.0);
-        bk = (bk + 3) & ~3;
-        L.grid.bucket = bk < 16 ? 16 : bk;
-    }
+    L.nseg = nseg;
     size_t tsz = c.prec == MLMIX_FP64 ? 8 : 4;
     size_t off = 0;
     auto take = [&](size_t &field, size_t bytes) {
@@ -802,8 +805,8 @@ WsLayout make_layout(const Ctx &c, int n, int cap, const Box &b, int scap)
     int nba = (n + kScanTile - 1) / kScanTile;
     int nsp = 2 * nba + 2;  // compaction block totals
     take(L.hdr, H_COUNT * sizeof(int));
-    take(L.cell_count, (size_t)L.grid.ncell * sizeof(int));
-    take(L.cell_atoms, (size_t)L.grid.ncell * L.grid.bucket * sizeof(CellAtom));
+    take(L.cell_count, ncell * sizeof(int));
+    take(L.cell_atoms, nrec * sizeof(CellAtom));
     take(L.seedcore, nn);
     take(L.scan_part, (size_t)nsp * sizeof(int));
     take(L.nbr, nn * cap * sizeof(int));
@@ -822,7 +825,51 @@ WsLayout make_layout(const Ctx &c, int n, int cap, const Box &b, int scap)
     take(L.red, (size_t)std::max(kReduceBlocks, n <= kGatherKickMax ? (n + 3) / 4 : 0) * 3 *
                     sizeof(double));
     take(L.dpart, ns * (size_t)(c.m.dp_stride > 0 ? c.m.dp_stride : 1) * tsz);
+    if (nseg > 0) {
+        take(L.seg_of, nn * sizeof(int));
+        take(L.segs, (size_t)nseg * sizeof(SegGeo));
+        take(L.seg_status, (size_t)nseg * sizeof(int));
+        take(L.seg_red, nn * sizeof(double));  // per-atom kinetic energy of the step
+    }
     L.total = off;
+}
+
+WsLayout make_layout(const Ctx &c, int n, int cap, const Box &b, int scap)
+{
+    WsLayout L{};
+    L.n = n;
+    L.cap = cap;
+    L.scap = (scap <= 0 || scap > n) ? n : scap;
+    L.grid = make_grid(c, b);
+    L.grid.bucket = bucket_size(n, L.grid.ncell);
+    layout_arrays(c, L, (size_t)L.grid.ncell, (size_t)L.grid.ncell * L.grid.bucket, 0);
+    return L;
+}
+
+// Layout of a batch workspace: every system's own grid and buckets, their
+// cells and records side by side (geo receives the device segment table).
+static WsLayout make_batch_layout(const Ctx &c, const std::vector<SegGeo> &in, int cap, int scap,
+                                  std::vector<SegGeo> &geo)
+{
+    WsLayout L{};
+    long long n = 0, ncell = 0, nrec = 0;
+    geo = in;
+    for (SegGeo &G : geo) {
+        G.grid = make_grid(c, G.box);
+        G.grid.bucket = bucket_size(G.n, G.grid.ncell);
+        G.cell0 = (int)ncell;
+        G.rec0 = nrec;
+        ncell += G.grid.ncell;
+        nrec += (long long)G.grid.ncell * G.grid.bucket;
+        n += G.n;
+    }
+    L.n = (int)n;
+    L.cap = cap;
+    L.scap = (scap <= 0 || scap > L.n) ? L.n : scap;
+    L.grid = Grid{};
+    L.grid.ncell = (int)ncell;
+    L.grid.bucket = 0;  // per segment
+    layout_arrays(c, L, (size_t)ncell, (size_t)nrec, (int)geo.size());
     return L;
 }
 
@@ -1096,6 +1143,7 @@ try {
     k_zero_i32<<<(L.grid.ncell + 255) / 256, 256, 0, s>>>(at<int>(ws, L.cell_count), L.grid.ncell);
     HIP_OK(hipGetLastError());
     std::lock_guard<std::mutex> g(ctx->mu);
+    ctx->batch.erase(ws);  // a single system now
     auto prev = ctx->ws.find(ws);
     if (prev == ctx->ws.end() || prev->second.n != L.n)
         ctx->lang.erase(ws);  // the noise buffer was sized for another system
@@ -1117,6 +1165,8 @@ static int lookup(mlmix_ctx *ctx, void *ws, int n, const mlmix_box *box, WsLayou
             return fail(MLMIX_E_STATE, "workspace was not initialised with mlmix_workspace_init");
         L = it->second;
     }
+    if (L.nseg > 0)
+        return fail(MLMIX_E_ARG, "a batch workspace (mlmix_batch_init) needs the mlmix_batch_* calls");
     if (L.n != n)
         return fail(MLMIX_E_ARG, "n_atoms differs from the workspace's");
     Grid g = make_grid(ctx->c, b);
@@ -1618,6 +1668,244 @@ try {
     }
     HIP_OK(hipGetLastError());
     return MLMIX_OK;
+} catch (...) {
+    return host_exception();
+}
+
+// ------------------------------------------------------ batched systems
+
+static int check_segments(const mlmix_ctx *ctx, int32_t n_segments, const mlmix_segment *segs,
+                          std::vector<SegGeo> &out)
+{
+    if (n_segments < 1 || n_segments > (1 << 20) || !segs)
+        return fail(MLMIX_E_ARG, "1 <= n_segments <= 2^20 and a segment table required");
+    out.clear();
+    out.reserve((size_t)n_segments);
+    long long next = 0;
+    for (int k = 0; k < n_segments; ++k) {
+        const mlmix_segment &q = segs[k];
+        if (q.offset != next)
+            return fail(MLMIX_E_ARG, "segments must tile the batch arrays in order (offset of "
+                                     "each = sum of the n_atoms before it)");
+        if (q.n_atoms < 1)
+            return fail(MLMIX_E_ARG, "every segment needs at least one atom");
+        if (q.region_offset < 0 || q.n_regions < 0)
+            return fail(MLMIX_E_ARG, "negative region range in a segment");
+        Box b;
+        int rc = check_box(ctx, &q.box, b);
+        if (rc)
+            return rc;
+        SegGeo G{};
+        G.box = b;
+        G.off = q.offset;
+        G.n = q.n_atoms;
+        G.reg0 = q.region_offset;
+        G.nreg = q.n_regions;
+        out.push_back(G);
+        next += q.n_atoms;
+        if (next > 2147483647LL)
+            return fail(MLMIX_E_ARG, "more than 2^31 - 1 atoms in a batch");
+    }
+    return MLMIX_OK;
+}
+
+static int batch_layout(const mlmix_ctx *ctx, int32_t n_segments, const mlmix_segment *segs,
+                        int32_t nbr_cap, int32_t s_cap, WsLayout &L, std::vector<SegGeo> &geo)
+{
+    if (nbr_cap < 1 || nbr_cap > kMaxCap)
+        return fail(MLMIX_E_ARG, "1 <= nbr_cap <= 256 required");
+    std::vector<SegGeo> in;
+    int rc = check_segments(ctx, n_segments, segs, in);
+    if (rc)
+        return rc;
+    L = make_batch_layout(ctx->c, in, nbr_cap, s_cap, geo);
+    for (const SegGeo &G : geo)
+        if ((double)G.grid.ncell * G.grid.bucket >= 2147483647.0)
+            return fail(MLMIX_E_ARG, "box too large for the cell grid (2^31 bucket records)");
+    return MLMIX_OK;
+}
+
+extern "C" int mlmix_batch_workspace_size(const mlmix_ctx *ctx, int32_t n_segments,
+                                          const mlmix_segment *segs, int32_t nbr_cap,
+                                          int32_t s_cap, size_t *bytes)
+try {
+    if (!ctx || !bytes)
+        return fail(MLMIX_E_ARG, "NULL argument");
+    WsLayout L;
+    std::vector<SegGeo> geo;
+    int rc = batch_layout(ctx, n_segments, segs, nbr_cap, s_cap, L, geo);
+    if (rc)
+        return rc;
+    *bytes = L.total;
+    return MLMIX_OK;
+} catch (...) {
+    return host_exception();
+}
+
+extern "C" int mlmix_batch_init(mlmix_ctx *ctx, void *stream, void *ws, size_t ws_bytes,
+                                int32_t n_segments, const mlmix_segment *segs, int32_t nbr_cap,
+                                int32_t s_cap)
+try {
+    if (!ctx || !ws)
+        return fail(MLMIX_E_ARG, "NULL argument");
+    WsLayout L;
+    std::vector<SegGeo> geo;
+    int rc = batch_layout(ctx, n_segments, segs, nbr_cap, s_cap, L, geo);
+    if (rc)
+        return rc;
+    if (ws_bytes < L.total)
+        return fail(MLMIX_E_WORKSPACE, "workspace smaller than mlmix_batch_workspace_size()");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    k_zero_i32<<<1, H_COUNT, 0, s>>>(at<int>(ws, L.hdr), H_COUNT);
+    k_zero_i32<<<(L.grid.ncell + 255) / 256, 256, 0, s>>>(at<int>(ws, L.cell_count), L.grid.ncell);
+    k_zero_i32<<<(L.nseg + 255) / 256, 256, 0, s>>>(at<int>(ws, L.seg_status), L.nseg);
+    HIP_OK(hipGetLastError());
+    // the segment table (the host copy is released when this call returns)
+    HIP_OK(hipMemcpyAsync(at<SegGeo>(ws, L.segs), geo.data(), geo.size() * sizeof(SegGeo),
+                          hipMemcpyHostToDevice, s));
+    HIP_OK(hipStreamSynchronize(s));
+    launch_seg_fill(s, ws, L);
+    HIP_OK(hipGetLastError());
+    std::vector<mlmix_segment> keep(segs, segs + n_segments);
+    std::lock_guard<std::mutex> g(ctx->mu);
+    ctx->lang.erase(ws);
+    ctx->ws[ws] = L;
+    ctx->batch[ws].swap(keep);
+    return MLMIX_OK;
+} catch (...) {
+    return host_exception();
+}
+
+static int batch_lookup(mlmix_ctx *ctx, void *ws, int32_t n_atoms, int32_t n_regions,
+                        WsLayout &L)
+{
+    if (!ctx || !ws)
+        return fail(MLMIX_E_ARG, "NULL context or workspace");
+    std::lock_guard<std::mutex> g(ctx->mu);
+    auto it = ctx->ws.find(ws);
+    auto bt = ctx->batch.find(ws);
+    if (it == ctx->ws.end() || bt == ctx->batch.end() || it->second.nseg == 0)
+        return fail(MLMIX_E_STATE, "workspace was not initialised with mlmix_batch_init");
+    L = it->second;
+    if (L.n != n_atoms)
+        return fail(MLMIX_E_ARG, "n_atoms differs from the batch's (sum over its segments)");
+    for (const mlmix_segment &q : bt->second)
+        if ((long long)q.region_offset + q.n_regions > (long long)n_regions)
+            return fail(MLMIX_E_ARG, "a segment's regions reach past n_regions");
+    return MLMIX_OK;
+}
+
+static int check_batch_mode(uint32_t mode)
+{
+    if (mode & (MLMIX_SEEDED | MLMIX_ENERGY_ONLY))
+        return fail(MLMIX_E_ARG, "batched calls take neither seeded regions nor "
+                                 "MLMIX_ENERGY_ONLY");
+    return MLMIX_OK;
+}
+
+extern "C" int mlmix_batch_compute(mlmix_ctx *ctx, void *stream, void *ws, int32_t n_atoms,
+                                   const double *pos, const int32_t *species,
+                                   const mlmix_region *regions, int32_t n_regions,
+                                   double r_buffer, uint32_t mode, double *forces, double *e_exp,
+                                   double *e_cheap, double *lambda, uint8_t *flags,
+                                   int32_t *n_expensive, double *energies)
+try {
+    WsLayout L;
+    int rc = batch_lookup(ctx, ws, n_atoms, n_regions, L);
+    if (rc)
+        return rc;
+    rc = check_batch_mode(mode);
+    if (rc)
+        return rc;
+    rc = check_compute_args(ctx, pos, species, regions, n_regions, r_buffer, mode, forces, e_exp,
+                            e_cheap, lambda, flags, n_atoms);
+    if (rc)
+        return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const Box unused{};  // every kernel takes its atom's box from the segment table
+    rc = compute_impl(ctx, s, ws, L, unused, pos, species, regions, n_regions, r_buffer, mode,
+                      forces, e_exp, e_cheap, lambda, flags, nullptr, nullptr, nullptr);
+    if (rc)
+        return rc;
+    if (n_expensive || energies) {
+        launch_seg_sums(s, ws, L, e_exp, e_cheap, nullptr, flags, energies, n_expensive);
+        HIP_OK(hipGetLastError());
+    }
+    return MLMIX_OK;
+} catch (...) {
+    return host_exception();
+}
+
+extern "C" int mlmix_batch_vv_steps(mlmix_ctx *ctx, void *stream, void *ws, int32_t n_atoms,
+                                    double *pos, double *vel, const double *mass,
+                                    const int32_t *species, double dt, int32_t n_steps,
+                                    const mlmix_region *regions, int32_t n_regions,
+                                    double r_buffer, uint32_t mode, double *forces,
+                                    double *e_exp, double *e_cheap, double *lambda,
+                                    uint8_t *flags, int32_t *n_expensive, double *energies)
+try {
+    WsLayout L;
+    int rc = batch_lookup(ctx, ws, n_atoms, n_regions, L);
+    if (rc)
+        return rc;
+    rc = check_batch_mode(mode);
+    if (rc)
+        return rc;
+    if (!vel || !mass || !energies)
+        return fail(MLMIX_E_ARG, "NULL argument");
+    if (n_steps < 1)
+        return fail(MLMIX_E_ARG, "n_steps must be at least 1");
+    if (!(dt > 0.0))
+        return fail(MLMIX_E_ARG, "dt must be positive");
+    rc = check_compute_args(ctx, pos, species, regions, n_regions, r_buffer, mode, forces, e_exp,
+                            e_cheap, lambda, flags, n_atoms);
+    if (rc)
+        return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const Box unused{};
+    double *ke = at<double>(ws, L.seg_red);
+    {
+        StageTimer t(ctx, s, ST_VV);
+        launch_vv_kick_drift(s, ws, L, unused, pos, vel, mass, forces, dt, 1);
+    }
+    for (int k = 0; k < n_steps; ++k) {
+        const bool last = k + 1 == n_steps;
+        // the gather closes the step (half kick, per-atom kinetic energy) and,
+        // before the next step, applies its opening half kick and drift
+        KickArgs ka{vel, mass, dt, e_cheap, nullptr, nullptr, last ? 0 : 1, 0, pos, unused, ke};
+        rc = compute_impl(ctx, s, ws, L, unused, pos, species, regions, n_regions, r_buffer, mode,
+                          forces, e_exp, e_cheap, lambda, flags, nullptr, nullptr, nullptr, &ka);
+        if (rc)
+            return rc;
+        StageTimer t(ctx, s, ST_RED);
+        launch_seg_sums(s, ws, L, e_exp, e_cheap, ke, flags,
+                        energies + (size_t)k * L.nseg * 3, last ? n_expensive : nullptr);
+    }
+    HIP_OK(hipGetLastError());
+    return MLMIX_OK;
+} catch (...) {
+    return host_exception();
+}
+
+extern "C" int mlmix_batch_status(mlmix_ctx *ctx, void *stream, void *ws, int32_t *segment_bits,
+                                  int32_t *required_cap)
+try {
+    if (!ctx || !ws)
+        return fail(MLMIX_E_ARG, "NULL argument");
+    WsLayout L;
+    {
+        std::lock_guard<std::mutex> g(ctx->mu);
+        auto it = ctx->ws.find(ws);
+        if (it == ctx->ws.end() || it->second.nseg == 0)
+            return fail(MLMIX_E_STATE, "workspace was not initialised with mlmix_batch_init");
+        L = it->second;
+    }
+    if (segment_bits) {
+        HIP_OK(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
+        HIP_OK(hipMemcpy(segment_bits, at<int>(ws, L.seg_status), (size_t)L.nseg * sizeof(int),
+                         hipMemcpyDeviceToHost));
+    }
+    return mlmix_status(ctx, stream, ws, nullptr, required_cap);
 } catch (...) {
     return host_exception();
 }

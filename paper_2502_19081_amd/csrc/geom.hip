@@ -135,12 +135,12 @@ __device__ __forceinline__ double blend_value(double t, int cubic)
 // passes over the neighbour rows; here seed atoms (with any seeded region
 // present) are core atoms of all of them, and the seed bit of flags is kept.
 __device__ __forceinline__ void atom_lambda(const double *__restrict__ pos, int n, const Box &b,
-                                            int i, const RegionArgs &ra, int *hdr)
+                                            int i, const RegionArgs &ra, int *hdr, const Seg &sg)
 {
 #pragma clang fp contract(off)
     int z = ra.species[i];
     if (z < 0 || z >= ra.ns)
-        atomicOr(&hdr[H_STATUS], MLMIX_STATUS_BAD_SPECIES);
+        seg_status_or(&hdr[H_STATUS], sg, i, MLMIX_STATUS_BAD_SPECIES);
     const uint8_t keep = ra.seeded ? (uint8_t)(ra.flags[i] & MLMIX_FLAG_SEED) : (uint8_t)0;
     if (ra.mode == MLMIX_MODE_ALL_EXPENSIVE) {
         ra.lam[i] = 1.0;
@@ -158,17 +158,27 @@ __device__ __forceinline__ void atom_lambda(const double *__restrict__ pos, int 
     bool near = false;
     int n_seeded = 0;
     double xi[3] = {pos[i], pos[n + i], pos[2 * n + i]};
-    for (int g = 0; g < ra.nreg; ++g) {
+    // a batched call: the atom's own system's regions, atom indices local to it
+    int g0 = 0, g1 = ra.nreg, a0 = 0, na = n;
+    if (sg.of) {
+        const SegGeo &G = sg.geo[sg.of[i]];
+        g0 = G.reg0;
+        g1 = G.reg0 + G.nreg;
+        a0 = G.off;
+        na = G.n;
+    }
+    for (int g = g0; g < g1; ++g) {
         mlmix_region r = ra.reg[g];
         if (r.type == MLMIX_REGION_SEEDED) {
             ++n_seeded;
             continue;
         }
         double c[3] = {r.center[0], r.center[1], r.center[2]};
-        if (r.follow_atom >= 0 && r.follow_atom < n) {
-            c[0] = pos[r.follow_atom];
-            c[1] = pos[n + r.follow_atom];
-            c[2] = pos[2 * n + r.follow_atom];
+        if (r.follow_atom >= 0 && r.follow_atom < na) {
+            const int fa = a0 + r.follow_atom;
+            c[0] = pos[fa];
+            c[1] = pos[n + fa];
+            c[2] = pos[2 * n + fa];
         }
         double d[3];
         for (int k = 0; k < 3; ++k) {
@@ -236,18 +246,31 @@ __device__ __forceinline__ void atom_lambda(const double *__restrict__ pos, int 
 // flag (otherwise the flag comes from the displacement check before it) and,
 // whenever the list is rebuilt, marks the workspace as built. Order inside a
 // bucket follows the atomics; the rows are sorted afterwards.
-__global__ void __launch_bounds__(256) k_bin_bucket(const double *__restrict__ pos, int n, Box b,
-                                                    Grid g, int force, int *hdr,
+__global__ void __launch_bounds__(256) k_bin_bucket(const double *__restrict__ pos, int n, Box b0,
+                                                    Grid g0, int force, int *hdr,
                                                     int *__restrict__ count,
-                                                    CellAtom *__restrict__ atoms, RegionArgs ra)
+                                                    CellAtom *__restrict__ atoms, RegionArgs ra,
+                                                    Seg sg)
 {
     // the previous step's energy sums (multi-step calls), by the whole of
     // workgroup 0 before anything else
     if (ra.red_part && blockIdx.x == 0)
         reduce_parts(ra.red_part, ra.red_nb, ra.red_out);
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    // the atom's system: its box, grid and first cell / bucket record
+    Box b = b0;
+    Grid g = g0;
+    int cell0 = 0;
+    size_t rec0 = 0;
+    if (sg.of && i < n) {
+        const SegGeo &G = sg.geo[sg.of[i]];
+        b = G.box;
+        g = G.grid;
+        cell0 = G.cell0;
+        rec0 = (size_t)G.rec0;
+    }
     if (i < n)
-        atom_lambda(pos, n, b, i, ra, hdr);
+        atom_lambda(pos, n, b, i, ra, hdr, sg);
     const int rebuild = force ? 1 : hdr[H_REBUILD];
     if (!rebuild)
         return;  // uniform
@@ -270,11 +293,11 @@ __global__ void __launch_bounds__(256) k_bin_bucket(const double *__restrict__ p
         c[k] = cell_coord(x[k], g, k);
     }
     if (bad)
-        atomicOr(&hdr[H_STATUS], MLMIX_STATUS_NONFINITE);
+        seg_status_or(&hdr[H_STATUS], sg, i, MLMIX_STATUS_NONFINITE);
     if (out)
-        atomicOr(&hdr[H_STATUS], MLMIX_STATUS_OUT_OF_BOX);
+        seg_status_or(&hdr[H_STATUS], sg, i, MLMIX_STATUS_OUT_OF_BOX);
     const int cell = (c[2] * g.nc[1] + c[1]) * g.nc[0] + c[0];
-    const int slot = atomicAdd(&count[cell], 1);
+    const int slot = atomicAdd(&count[cell0 + cell], 1);
     if (slot < g.bucket) {
         CellAtom r;
         r.x = x[0];
@@ -282,9 +305,9 @@ __global__ void __launch_bounds__(256) k_bin_bucket(const double *__restrict__ p
         r.z = x[2];
         r.j = i;
         r.pad = 0;
-        atoms[(size_t)cell * g.bucket + slot] = r;
+        atoms[rec0 + (size_t)cell * g.bucket + slot] = r;
     } else {
-        atomicOr(&hdr[H_STATUS], MLMIX_STATUS_CELL_OVERFLOW);
+        seg_status_or(&hdr[H_STATUS], sg, i, MLMIX_STATUS_CELL_OVERFLOW);
     }
 }
 
@@ -363,14 +386,14 @@ constexpr int kNbrList = 512;
 // first). Partners closer than the list radius are kept by ballot
 // compaction, and the row is finally sorted ascending in registers (bitonic
 // over 64, 128 or 256 keys).
-__global__ void __launch_bounds__(256) k_neighbors(const double *__restrict__ pos, int n, Box b,
-                                                   Grid g, const int *__restrict__ count,
-                                                   const CellAtom *__restrict__ atoms, double rl2,
+__global__ void __launch_bounds__(256) k_neighbors(const double *__restrict__ pos, int n, Box b0,
+                                                   Grid g0, const int *__restrict__ count0,
+                                                   const CellAtom *__restrict__ atoms0, double rl2,
                                                    int cap, int P, int *__restrict__ nbr,
                                                    int *__restrict__ cnt,
                                                    double *__restrict__ ref, int *hdr,
                                                    double rb2, uint8_t *__restrict__ flags,
-                                                   const uint8_t *__restrict__ cand)
+                                                   const uint8_t *__restrict__ cand, Seg sg)
 {
 #pragma clang fp contract(off)
     if (hdr[H_REBUILD] == 0)
@@ -382,6 +405,18 @@ __global__ void __launch_bounds__(256) k_neighbors(const double *__restrict__ po
     const int i = blockIdx.x * 4 + w;
     if (i >= n)
         return;
+    // the atom's system: its box, grid, cell counts and bucket records
+    Box b = b0;
+    Grid g = g0;
+    const int *count = count0;
+    const CellAtom *atoms = atoms0;
+    if (sg.of) {
+        const SegGeo &G = sg.geo[sg.of[i]];
+        b = G.box;
+        g = G.grid;
+        count = count0 + G.cell0;
+        atoms = atoms0 + G.rec0;
+    }
     const int Pe = P < 64 ? 64 : P;  // keys sorted (64 V)
     int *row = rows[w];
     for (int t = lane; t < Pe; t += 64)
@@ -520,7 +555,7 @@ __global__ void __launch_bounds__(256) k_neighbors(const double *__restrict__ po
         // same-address device atomics serialise across the whole grid: only
         // an overflowing row records its length
         if (c > cap) {
-            atomicOr(&hdr[H_STATUS], MLMIX_STATUS_NEIGH_OVERFLOW);
+            seg_status_or(&hdr[H_STATUS], sg, i, MLMIX_STATUS_NEIGH_OVERFLOW);
             atomicMax(&hdr[H_REQCAP], c);
         }
     }
@@ -615,15 +650,16 @@ void launch_neighbors(hipStream_t s, void *ws, const WsLayout &L, const Box &b, 
     RegionArgs r = ra;
     r.cand = at<uint8_t>(ws, L.cand);
     r.seedcore = at<uint8_t>(ws, L.seedcore);
+    const Seg sg = seg_args(ws, L);
     k_bin_bucket<<<(n + 255) / 256, 256, 0, s>>>(pos, n, b, g, force_rebuild, hdr, count,
-                                                 at<CellAtom>(ws, L.cell_atoms), r);
+                                                 at<CellAtom>(ws, L.cell_atoms), r, sg);
     // (with seeded regions lambda is not final yet: the buffer pass follows them)
     const double rb2 =
         ra.mode == MLMIX_MODE_MIXED && !ra.seeded ? ra.r_buffer * ra.r_buffer : -1.0;
     k_neighbors<<<(n + 3) / 4, 256, 0, s>>>(pos, n, b, g, count, at<CellAtom>(ws, L.cell_atoms),
                                             r_list * r_list, L.cap, L.P, at<int>(ws, L.nbr),
                                             at<int>(ws, L.cnt), at<double>(ws, L.ref_pos), hdr,
-                                            rb2, ra.flags, r.cand);
+                                            rb2, ra.flags, r.cand, sg);
 }
 
 // Reverse slots of a rebuilt list (skipped on the device when the list was
@@ -700,16 +736,17 @@ void launch_reverse(hipStream_t s, void *ws, const WsLayout &L, int side_blocks)
 // One wavefront per atom (lanes over row slots): an atom with lambda == 0
 // near a region joins the buffer when any neighbour with lambda > 0 lies
 // strictly inside r_buffer.
-__global__ void __launch_bounds__(256) k_buffer(const double *__restrict__ pos, int n, Box b,
+__global__ void __launch_bounds__(256) k_buffer(const double *__restrict__ pos, int n, Box b0,
                                                 int cap, const int *__restrict__ nbr,
                                                 const int *__restrict__ cnt, double rb2,
                                                 uint8_t *__restrict__ flags,
-                                                const uint8_t *__restrict__ cand)
+                                                const uint8_t *__restrict__ cand, Seg sg)
 {
     const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (i >= n || !cand[i])
         return;
+    const Box b = seg_box(b0, sg, i);
     const int c = cnt[i];
     const int *row = nbr + (size_t)i * cap;
     bool hit = false;
@@ -835,15 +872,16 @@ __global__ void __launch_bounds__(256) k_seed_blend(const double *__restrict__ p
 // The cheap potential's buffer (MLMIX_CHEAP_MASKED): an atom with
 // lambda == 1 joins it (flags bit3) when a row partner with lambda < 1 lies
 // strictly inside r_buffer. One wavefront per atom; others return at once.
-__global__ void __launch_bounds__(256) k_cheap_buffer(const double *__restrict__ pos, int n, Box b,
+__global__ void __launch_bounds__(256) k_cheap_buffer(const double *__restrict__ pos, int n, Box b0,
                                                       int cap, const int *__restrict__ nbr,
                                                       const int *__restrict__ cnt, double rb2,
-                                                      uint8_t *__restrict__ flags)
+                                                      uint8_t *__restrict__ flags, Seg sg)
 {
     const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (i >= n || !(flags[i] & 2))
         return;
+    const Box b = seg_box(b0, sg, i);
     const int c = cnt[i];
     const int *row = nbr + (size_t)i * cap;
     bool hit = false;
@@ -866,7 +904,8 @@ void launch_cheap_buffer(hipStream_t s, void *ws, const WsLayout &L, const Box &
     if (L.n == 0)
         return;
     k_cheap_buffer<<<(L.n + 3) / 4, 256, 0, s>>>(pos, L.n, b, L.cap, at<int>(ws, L.nbr),
-                                                 at<int>(ws, L.cnt), r_buffer * r_buffer, flags);
+                                                 at<int>(ws, L.cnt), r_buffer * r_buffer, flags,
+                                                 seg_args(ws, L));
 }
 
 // Region stage after the rows: the seeded passes (MLMIX_SEEDED), then the
@@ -896,7 +935,7 @@ void launch_regions(hipStream_t s, void *ws, const WsLayout &L, const Box &b, in
     if (mode == MLMIX_MODE_MIXED)
         k_buffer<<<(n + 3) / 4, 256, 0, s>>>(pos, n, b, L.cap, at<int>(ws, L.nbr),
                                                 at<int>(ws, L.cnt), r_buffer * r_buffer, flags,
-                                                cand);
+                                                cand, seg_args(ws, L));
 }
 
 // ------------------------------------------------------------ compaction

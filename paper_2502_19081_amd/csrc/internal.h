@@ -51,16 +51,63 @@ struct Grid {
     int bucket;  // records per cell bucket
 };
 
+// One system of a batched call: atoms [off, off + n) of the batch arrays, its
+// box and cell grid (cells [cell0, cell0 + grid.ncell) of the batch's cell
+// counts, bucket records from rec0) and its regions [reg0, reg0 + nreg).
+struct SegGeo {
+    Box box;
+    Grid grid;
+    int off, n;
+    int cell0, reg0, nreg, pad;
+    long long rec0;
+};
+
+// Segment lookup of a batched call; all null for a single system. of[i] is
+// the segment of atom i, geo the segment table, status per-segment
+// MLMIX_STATUS_* words (the workspace header keeps their union).
+struct Seg {
+    const int *of;
+    const SegGeo *geo;
+    int *status;
+};
+
+// Box of atom i (and of every partner in its rows).
+__device__ __forceinline__ Box seg_box(const Box &b, const Seg &sg, int i)
+{
+    return sg.of ? sg.geo[sg.of[i]].box : b;
+}
+
+// Status bits of atom i's system: the workspace header, and in a batched
+// call also the atom's segment word.
+__device__ __forceinline__ void seg_status_or(int *hdr_status, const Seg &sg, int i, int bits)
+{
+    atomicOr(hdr_status, bits);
+    if (sg.of)
+        atomicOr(&sg.status[sg.of[i]], bits);
+}
+
 struct WsLayout {
     int n, cap, P;  // atoms, row capacity, capacity rounded up to a power of two
     int scap;       // capacity of S (rows of the per-S buffers A, dE/dA, g, partial D)
-    Grid grid;
+    Grid grid;      // single system: its grid; batch: ncell = cells of all segments
     int n_scan_blk;  // blocks of the atom-sized scans
+    int nseg;        // segments of a batch workspace (0: one system)
     size_t hdr, cell_count, cell_atoms, scan_part, seedcore;
     size_t nbr, cnt, rev, ref_pos, S_idx, M_idx, S_local, cand;
     size_t A, dEdA, g, h, red, dpart;
+    size_t seg_of, segs, seg_status, seg_red;  // batch workspaces only
     size_t total;
 };
+
+template <typename T>
+inline T *at(void *ws, size_t off) { return reinterpret_cast<T *>(static_cast<char *>(ws) + off); }
+
+inline Seg seg_args(void *ws, const WsLayout &L)
+{
+    if (L.nseg == 0)
+        return Seg{nullptr, nullptr, nullptr};
+    return Seg{at<int>(ws, L.seg_of), at<SegGeo>(ws, L.segs), at<int>(ws, L.seg_status)};
+}
 
 // Model tables on the device, in the arithmetic type of the context.
 struct DevModel {
@@ -130,9 +177,6 @@ Grid make_grid(const Ctx &c, const Box &b);
 // Species index clamped into the model's range (invalid input is reported by
 // a status bit; clamping keeps every table read in bounds).
 __host__ __device__ inline int sp_clamp(int z, int ns) { return z < 0 ? 0 : (z >= ns ? ns - 1 : z); }
-
-template <typename T>
-inline T *at(void *ws, size_t off) { return reinterpret_cast<T *>(static_cast<char *>(ws) + off); }
 
 // Inputs and outputs of the per-atom mixing weight pass (lambda, masks and
 // buffer candidates), which runs inside the binning kernel.
@@ -207,6 +251,7 @@ struct KickArgs {
     int defer;         // leave the final sum to the next step's binning kernel
     double *pos;       // positions (drift of the next step)
     Box box;
+    double *ke_atom;   // per-atom kinetic energy 0.5 m v^2 of the full step (batches)
 };
 constexpr int kGatherKickMax = 65536;
 
@@ -236,6 +281,10 @@ void launch_vv_kick_drift(hipStream_t s, void *ws, const WsLayout &L, const Box 
                           double *vel, const double *mass, const double *forces, double dt,
                           int drift);
 void launch_copy_i32(hipStream_t s, int32_t *dst, const int32_t *src, size_t n);
+void launch_seg_fill(hipStream_t s, void *ws, const WsLayout &L);
+void launch_seg_sums(hipStream_t s, void *ws, const WsLayout &L, const double *e_exp,
+                     const double *e_cheap, const double *ke, const uint8_t *flags, double *out,
+                     int32_t *counts);
 void launch_probe_mfma_f32(hipStream_t s, int blocks, int iters, float *sink);
 
 // ---- fit.hip (constrained linear fitting of the cheap potential) ----

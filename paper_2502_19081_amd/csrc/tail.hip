@@ -19,7 +19,8 @@ __global__ void __launch_bounds__(256)
                    const T *__restrict__ g, const T *__restrict__ h, int use_exp, int use_cheap,
                    const double *__restrict__ lambda, double *__restrict__ forces,
                    double *__restrict__ e_exp, double *__restrict__ f_exp,
-                   double *__restrict__ f_cheap, double sign, KickArgs ka, LangevinArgs la)
+                   double *__restrict__ f_cheap, double sign, KickArgs ka, LangevinArgs la,
+                   Seg sg)
 {
     const int w = threadIdx.x >> 6;
     const int i = blockIdx.x * 4 + w;
@@ -104,10 +105,11 @@ __global__ void __launch_bounds__(256)
                         const double vn = fma(cf, F[q], v);
                         ka.vel[q * n + i] = vn;
                         double x = fma(ka.dt, vn, ka.pos[q * n + i]);
-                        if (ka.box.per[q]) {
-                            x = x - ka.box.L[q] * floor(x / ka.box.L[q]);
-                            if (x >= ka.box.L[q])
-                                x -= ka.box.L[q];
+                        const Box bx = seg_box(ka.box, sg, i);
+                        if (bx.per[q]) {
+                            x = x - bx.L[q] * floor(x / bx.L[q]);
+                            if (x >= bx.L[q])
+                                x -= bx.L[q];
                         }
                         ka.pos[q * n + i] = x;
                     } else {
@@ -117,10 +119,12 @@ __global__ void __launch_bounds__(256)
                 ke = 0.5 * m * v2;
                 ee = si < 0 ? 0.0 : e_exp[i];
                 ec = ka.e_cheap[i];
+                if (ka.ke_atom)
+                    ka.ke_atom[i] = ke;
             }
         }
     }
-    if (KICK) {
+    if (KICK && ka.part) {
         // block partial; k_reduce_final sums the partials in a fixed order
         // (a last-block-done reduction in this kernel measured 61 us against
         // 12 + 4 us on 8,193 atoms: the per-block device-scope fences)
@@ -155,13 +159,15 @@ void launch_gather_blend(hipStream_t s, const Ctx &c, void *ws, const WsLayout &
     KickArgs ka{};
     if (kick) {
         ka = *kick;
-        ka.part = at<double>(ws, L.red);
+        // a batch sums its energies per system in k_seg_sums instead
+        ka.part = L.nseg == 0 ? at<double>(ws, L.red) : nullptr;
     }
 #define MLMIX_GATHER(T, K)                                                                        \
     k_gather_blend<T, K><<<nb, 256, 0, s>>>(n, L.cap, at<int>(ws, L.nbr), at<int>(ws, L.cnt),      \
                                            at<int>(ws, L.rev), at<int>(ws, L.S_local),             \
                                            at<T>(ws, L.g), at<T>(ws, L.h), use_exp, use_cheap,     \
-                                           lambda, forces, e_exp, f_exp, f_cheap, sign, ka, la)
+                                           lambda, forces, e_exp, f_exp, f_cheap, sign, ka, la, \
+                                           seg_args(ws, L))
     if (c.prec == MLMIX_FP64) {
         if (kick)
             MLMIX_GATHER(double, true);
@@ -174,7 +180,7 @@ void launch_gather_blend(hipStream_t s, const Ctx &c, void *ws, const WsLayout &
             MLMIX_GATHER(float, false);
     }
 #undef MLMIX_GATHER
-    if (kick && !ka.defer)
+    if (kick && !ka.defer && ka.part)
         k_reduce_final<<<1, 256, 0, s>>>(ka.part, (int)nb, ka.energies);
 }
 
@@ -262,14 +268,16 @@ void launch_reduce(hipStream_t s, void *ws, const WsLayout &L, const double *e_e
 
 // -------------------------------------------------------- velocity Verlet
 
-__global__ void __launch_bounds__(256) k_vv(int n, Box b, double *__restrict__ pos,
+__global__ void __launch_bounds__(256) k_vv(int n, Box b0, double *__restrict__ pos,
                                             double *__restrict__ vel,
                                             const double *__restrict__ mass,
-                                            const double *__restrict__ f, double dt, int drift)
+                                            const double *__restrict__ f, double dt, int drift,
+                                            Seg sg)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n)
         return;
+    const Box b = seg_box(b0, sg, i);
     double c = 0.5 * dt * kKappa / mass[i];
     for (int k = 0; k < 3; ++k) {
         double v = fma(c, f[k * n + i], vel[k * n + i]);
@@ -346,10 +354,96 @@ void launch_vv_kick_drift(hipStream_t s, void *ws, const WsLayout &L, const Box 
                           double *vel, const double *mass, const double *forces, double dt,
                           int drift)
 {
-    (void)ws;
     if (L.n == 0)
         return;
-    k_vv<<<(L.n + 255) / 256, 256, 0, s>>>(L.n, b, pos, vel, mass, forces, dt, drift);
+    k_vv<<<(L.n + 255) / 256, 256, 0, s>>>(L.n, b, pos, vel, mass, forces, dt, drift,
+                                           seg_args(ws, L));
+}
+
+// ------------------------------------------------------ batched systems
+
+// Segment index of every atom of a batch: one workgroup per segment.
+__global__ void __launch_bounds__(256) k_seg_fill(const SegGeo *__restrict__ geo,
+                                                  int *__restrict__ seg_of)
+{
+    const SegGeo G = geo[blockIdx.x];
+    for (int t = threadIdx.x; t < G.n; t += blockDim.x)
+        seg_of[G.off + t] = (int)blockIdx.x;
+}
+
+void launch_seg_fill(hipStream_t s, void *ws, const WsLayout &L)
+{
+    if (L.nseg > 0)
+        k_seg_fill<<<L.nseg, 256, 0, s>>>(at<SegGeo>(ws, L.segs), at<int>(ws, L.seg_of));
+}
+
+// Energy sums and set sizes of every system of a batch: one workgroup per
+// segment; thread t sums the segment's atoms t, t + 256, ... (counted from
+// the segment's first atom), then the wave butterfly and the four waves in
+// a fixed order, so a system's sums have the same bits wherever it sits in
+// whichever batch. out[3 k + q] = (sum e_exp, sum e_cheap, kinetic in eV) of
+// segment k (kinetic from the per-atom 0.5 m v^2 the force gather left in
+// ke, or 0 without it); counts[2 k] = (|S|, |{lambda > 0}|) from the flags.
+__global__ void __launch_bounds__(256) k_seg_sums(const SegGeo *__restrict__ geo,
+                                                  const double *__restrict__ e_exp,
+                                                  const double *__restrict__ e_cheap,
+                                                  const double *__restrict__ ke,
+                                                  const uint8_t *__restrict__ flags,
+                                                  double *__restrict__ out,
+                                                  int32_t *__restrict__ counts)
+{
+    __shared__ double sh[3][4];
+    __shared__ int shc[2][4];
+    const SegGeo G = geo[blockIdx.x];
+    double a = 0.0, b = 0.0, k = 0.0;
+    int cs = 0, cm = 0;
+    for (int t = threadIdx.x; t < G.n; t += blockDim.x) {
+        const int i = G.off + t;
+        a += e_exp[i];
+        b += e_cheap[i];
+        if (ke)
+            k += ke[i];
+        const uint8_t f = flags[i];
+        cs += (f & 5) ? 1 : 0;
+        cm += (f & 1) ? 1 : 0;
+    }
+    a = wave_sum_d(a);
+    b = wave_sum_d(b);
+    k = wave_sum_d(k);
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) {
+        cs += __shfl_xor(cs, d);
+        cm += __shfl_xor(cm, d);
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        sh[0][w] = a;
+        sh[1][w] = b;
+        sh[2][w] = k;
+        shc[0][w] = cs;
+        shc[1][w] = cm;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (out) {
+            for (int q = 0; q < 3; ++q)
+                out[3 * blockIdx.x + q] = (sh[q][0] + sh[q][1]) + (sh[q][2] + sh[q][3]);
+            out[3 * blockIdx.x + 2] /= kKappa;
+        }
+        if (counts) {
+            counts[2 * blockIdx.x] = (shc[0][0] + shc[0][1]) + (shc[0][2] + shc[0][3]);
+            counts[2 * blockIdx.x + 1] = (shc[1][0] + shc[1][1]) + (shc[1][2] + shc[1][3]);
+        }
+    }
+}
+
+void launch_seg_sums(hipStream_t s, void *ws, const WsLayout &L, const double *e_exp,
+                     const double *e_cheap, const double *ke, const uint8_t *flags, double *out,
+                     int32_t *counts)
+{
+    if (L.nseg > 0)
+        k_seg_sums<<<L.nseg, 256, 0, s>>>(at<SegGeo>(ws, L.segs), e_exp, e_cheap, ke, flags, out,
+                                          counts);
 }
 
 // ------------------------------------------------------------ peak probe

@@ -135,7 +135,7 @@ __global__ void __launch_bounds__(256)
     k_uf3(const double *__restrict__ pos, int n, Box b, const int32_t *__restrict__ species,
           int cap, const int *__restrict__ nbr, const int *__restrict__ cnt, Uf3Args<T> a,
           T *__restrict__ hout, double *__restrict__ e_cheap, int *hdr,
-          const uint8_t *__restrict__ mflags)
+          const uint8_t *__restrict__ mflags, Seg sg)
 {
     const int nb = a.nb3;
     const int c3n = uf3_c3_elems(a.ns, nb);
@@ -171,6 +171,7 @@ __global__ void __launch_bounds__(256)
     // over groups (capped grids); no block barrier below
     auto atom = [&](const int i) {
         wave_sync_lds_u();
+        const Box bi = seg_box(b, sg, i);  // box of the atom's system
         const int zi = sp_clamp(species[i], a.ns);
         const int c = cnt[i];
         const int *row = nbr + (size_t)i * cap;
@@ -192,7 +193,7 @@ __global__ void __launch_bounds__(256)
             rr2[u] = 1.0e300;
             dd[u][0] = dd[u][1] = dd[u][2] = 0.0;
             if (jj[u] >= 0)
-                rr2[u] = pair_disp_u(pos, n, i, jj[u], b, dd[u]);
+                rr2[u] = pair_disp_u(pos, n, i, jj[u], bi, dd[u]);
         }
         int zj[U];
 #pragma unroll
@@ -252,7 +253,7 @@ __global__ void __launch_bounds__(256)
         wave_sync_lds_u();
         if (n3 > kMaxTriplet) {
             if (lane == 0)
-                atomicOr(&hdr[H_STATUS], MLMIX_STATUS_TRIPLET_OVERFLOW);
+                seg_status_or(&hdr[H_STATUS], sg, i, MLMIX_STATUS_TRIPLET_OVERFLOW);
             n3 = kMaxTriplet;
         }
         if (nb > 0) {
@@ -433,7 +434,7 @@ static void uf3_t(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L, cons
 #define MLMIX_UF3_W(U, LOOP)                                                                     \
     k_uf3<T, U, LOOP><<<nblk, 256, sm, s>>>(pos, L.n, b, species, L.cap, at<int>(ws, L.nbr),    \
                                                 at<int>(ws, L.cnt), a, at<T>(ws, L.h), e_cheap,     \
-                                                at<int>(ws, L.hdr), mask_flags)
+                                                at<int>(ws, L.hdr), mask_flags, seg_args(ws, L))
 #define MLMIX_UF3(U)                                                                             \
     if (nblk < (unsigned)((L.n + wpb - 1) / wpb))                                                 \
         MLMIX_UF3_W(U, true);                                                                     \
