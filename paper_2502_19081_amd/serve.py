@@ -1,28 +1,31 @@
 """Continuous batching of independent MD replicas (the He-impact serving
 workload) on one GPU.
 
-Each replica keeps its positions, velocities, forces, neighbour list and
-every intermediate resident in its own workspace. Requests arrive over time
-(Poisson arrivals); whenever a slot and enough HBM are free, waiting requests
-are admitted. A tick runs one velocity-Verlet step of every active replica,
-each on its own stream, so the replicas' kernels overlap on the device:
-either as eager launches (default) or, with use_graph, as one HIP graph
-captured whenever the set of active replicas changes (each replica in its own
-stream branch, forked from the capture stream and joined back), so that a
-tick costs one graph launch. That mode is off by default: its capture and
-replay crashed in the host runtime in a recent run, with the cause not yet
-shown. With use_graph="replica" each replica's step is captured once, alone
-on one stream, when the replica is admitted (the one-level capture whose
-replays are bitwise equal to eager steps), and a tick launches every active
-replica's graph on its own stream.
-Finished replicas are retired (state copied to the host, memory released)
-and their slots refilled at the next tick.
+Requests arrive over time (Poisson arrivals); whenever the HBM budget
+allows, waiting requests are admitted. Two servers:
 
-Latency of a replica step = wall time of the tick it ran in, including the
-wait for the other replicas of the batch (host timestamps around the replay
-and its completion).
+BatchServer (the default): every active replica's atoms sit side by side in
+one set of batch arrays, and the batched C ABI calls (mlmix_batch_*) advance
+all of them by one velocity-Verlet step with one launch per kernel, captured
+once per batch composition in a HIP graph (a one-level capture: the
+library's own fork onto its second stream inside it). A replica's results
+are the same bits alone and in any batch. The host enqueues steps without
+waiting, and latencies come from HIP events between consecutive steps.
 
-CLI: python -m paper_2502_19081_amd.serve --replicas 64 --steps 500
+Server: each replica keeps its own workspace, and a tick runs one step of
+every active replica, each on its own stream (eager launches, or one graph
+per replica captured at admission with use_graph="replica"), with the
+device synchronised after every tick; a replica's step latency is the
+tick's wall time. It is kept as the per-replica baseline. Its third mode,
+one multi-stream graph per batch composition (use_graph=True: each
+replica's step in its own stream branch forked off the capture stream),
+crashed in the runtime's capture end and later in replay, with the cause
+not shown, and is refused.
+
+Finished replicas are retired (state copied to the host) and the batch (or
+the slot) is reused.
+
+CLI: python -m paper_2502_19081_amd.serve --replicas 256 --steps 2000 --load 0.8
 """
 import argparse
 import ctypes
@@ -267,6 +270,270 @@ class Server:
                 "max_batch": max(a for a, _ in self.ticks), "graph_captures": self.recaptures}
 
 
+class BatchServer:
+    """Continuous batching of replicas through the batched C ABI calls
+    (mlmix_batch_*): every active replica's atoms sit in one set of batch
+    arrays and one launch per kernel advances all of them by one
+    velocity-Verlet step (captured once per batch composition in a HIP graph
+    with use_graph; each replica's bits do not depend on the batch it runs
+    in). The host enqueues steps without waiting for them, at most
+    `max_inflight` ahead of the device.
+
+    The batch is rebuilt when a replica finishes (its state is copied out at
+    exactly its last step), when a replica fails its status check, and when
+    replicas wait and at least `admit_every` steps have run since the last
+    rebuild (or nothing is active). Admission is by HBM footprint: the
+    batch workspace (additive over replicas) plus resident state must fit
+    the budget.
+
+    Latency of a replica step = the device time between the completion of
+    the batch step before it and its own (HIP events on the serving stream),
+    i.e. the step's duration on a busy device; the first step after a
+    rebuild is timed from an event recorded just before it."""
+
+    def __init__(self, model, hbm_budget=64 << 30, max_active=512, cap=128, s_cap_per_replica=1024,
+                 device="cuda", use_graph=True, admit_every=20, max_inflight=8, check_every=200,
+                 r_buffer=5.0):
+        self.model = model
+        self.budget = int(hbm_budget)
+        self.max_active = int(max_active)
+        self.cap = int(cap)
+        self.s_cap_per_replica = int(s_cap_per_replica)
+        self.device = device
+        self.use_graph = bool(use_graph)
+        self.admit_every = int(admit_every)
+        self.max_inflight = int(max_inflight)
+        self.check_every = int(check_every)
+        self.r_buffer = float(r_buffer)
+        self.stream = torch.cuda.Stream(device=device)
+        self.waiting = []
+        self.active = []
+        self.finished = []
+        self.failed = []
+        self.in_use = 0
+        self.batch = None
+        self.graph = None
+        self.rebuilds = 0
+        self.ticks = []        # (n_active, atoms, start event or None, end event)
+        self.tick_batch = []   # replica ids of each tick's batch (index into self.ticks)
+        self._since_rebuild = 0
+        self._ticks_total = 0
+        self._need_start = True  # time the next step from an event of its own
+        self.peak_in_use = 0
+
+    def submit(self, replica):
+        self.waiting.append(replica)
+        self.waiting.sort(key=lambda r: r.arrival)
+
+    def footprint(self, r):
+        """Device bytes one replica adds: its share of a batch workspace and
+        its resident state (positions, velocities, forces, masses, species,
+        site energies, lambda, flags)."""
+        segs = (B.Segment * 1)()
+        segs[0].offset = 0
+        segs[0].n_atoms = r.n
+        segs[0].box = core.make_box(r.w["L"], r.w["periodic"])
+        segs[0].region_offset = 0
+        segs[0].n_regions = len(r.w["regions"])
+        sz = ctypes.c_size_t()
+        B.check(B.lib().mlmix_batch_workspace_size(self.model.handle, 1, segs, self.cap,
+                                                   min(self.s_cap_per_replica, r.n),
+                                                   ctypes.byref(sz)))
+        return int(sz.value) + r.n * (3 * 8 * 3 + 8 * 4 + 4 + 1) + 4096
+
+    # ------------------------------------------------------------ batch state
+
+    def _rebuild(self, leaving, joining, now):
+        """New batch arrays and workspace for (active - leaving + joining)."""
+        self.rebuilds += 1
+        dev = self.device
+        keep = [r for r in self.active if r not in leaving]
+        old = self.batch
+        parts = {"pos": [], "vel": [], "mass": [], "species": []}
+        with torch.cuda.stream(self.stream):
+            for r in keep:
+                sl = old.slice(self.active.index(r))
+                parts["pos"].append(self.pos[:, sl])
+                parts["vel"].append(self.vel[:, sl])
+                parts["mass"].append(self.mass[sl])
+                parts["species"].append(self.species[sl])
+            for r in joining:
+                w = r.w
+                parts["pos"].append(torch.from_numpy(np.ascontiguousarray(w["pos"].T)).to(dev))
+                parts["vel"].append(torch.from_numpy(np.ascontiguousarray(w["vel"].T)).to(dev))
+                parts["mass"].append(torch.from_numpy(
+                    w["masses"][w["species"]].astype(np.float64)).to(dev))
+                parts["species"].append(torch.from_numpy(w["species"].astype(np.int32)).to(dev))
+            self.graph = None
+            self.active = keep + list(joining)
+            if not self.active:
+                self.batch = None
+                return
+            self.pos = torch.cat(parts["pos"], dim=1).contiguous()
+            self.vel = torch.cat(parts["vel"], dim=1).contiguous()
+            self.mass = torch.cat(parts["mass"]).contiguous()
+            self.species = torch.cat(parts["species"]).contiguous()
+            systems = [dict(n=r.n, L=r.w["L"], periodic=r.w["periodic"], regions=r.w["regions"])
+                       for r in self.active]
+            s_cap = sum(min(self.s_cap_per_replica, r.n) for r in self.active)
+            self.batch = core.Batch(self.model, systems, cap=self.cap, s_cap=s_cap, device=dev)
+            # forces of the current state (the step needs F(x) on entry; a
+            # replica's forces are the same bits in any batch)
+            self.batch.compute(self.pos, self.species, r_buffer=self.r_buffer,
+                               mode=B.MODE_MIXED, force_rebuild=True)
+            self.energies = torch.zeros(1, len(self.active), 3, dtype=torch.float64, device=dev)
+            if self.use_graph:
+                g = torch.cuda.CUDAGraph()
+                with torch.cuda.graph(g, stream=self.stream):
+                    self._step()
+                self.graph = g
+        for r in joining:
+            r.admitted_at = now
+        self._since_rebuild = 0
+        self._need_start = True
+
+    def _step(self):
+        self.batch.vv_steps(self.pos, self.vel, self.mass, self.species, self.active[0].dt, 1,
+                            r_buffer=self.r_buffer, mode=self.active[0].mode, force_rebuild=True,
+                            energies=self.energies)
+
+    def _retire(self, r, k, now):
+        sl = self.batch.slice(k)
+        r.result = dict(pos=self.pos[:, sl].cpu().numpy().T.copy(),
+                        vel=self.vel[:, sl].cpu().numpy().T.copy(),
+                        energies=self.energies[0, k].cpu().numpy().copy(),
+                        n_exp=self.batch.n_exp[k].cpu().numpy().copy())
+        r.finished_at = now
+        self.in_use -= r.fp
+
+    # ------------------------------------------------------------------ loop
+
+    def _admit_candidates(self, now):
+        out = []
+        budget = self.in_use
+        while self.waiting and self.waiting[0].arrival <= now and \
+                len(self.active) + len(out) < self.max_active:
+            r = self.waiting[0]
+            fp = self.footprint(r)
+            if budget + fp > self.budget:
+                if not self.active and not out:
+                    raise RuntimeError(f"replica {r.rid} needs {fp} bytes, over the HBM budget")
+                break
+            self.waiting.pop(0)
+            r.fp = fp
+            budget += fp
+            out.append(r)
+        return out
+
+    def _check(self, now):
+        bits, _, _ = self.batch.status(raise_on_error=False)
+        return [r for k, r in enumerate(self.active) if bits[k] != 0]
+
+    def run(self, clock=None):
+        """Serve until every submitted replica has finished or failed.
+        `clock()` gives the time used for arrivals (wall time by default)."""
+        start = time.perf_counter()
+        clock = clock or (lambda: time.perf_counter() - start)
+        self.t_start = start
+        inflight = []
+        while self.waiting or self.active:
+            now = clock()
+            leaving = [r for r in self.active if r.done >= r.steps]
+            joining = []
+            if self.waiting and self.waiting[0].arrival <= now and \
+                    (not self.active or leaving or self._since_rebuild >= self.admit_every):
+                joining = self._admit_candidates(now)
+            if leaving or joining:
+                self.stream.synchronize()
+                inflight.clear()
+                for r in leaving:
+                    self._retire(r, self.active.index(r), clock())
+                    self.finished.append(r)
+                for r in joining:
+                    self.in_use += r.fp
+                self.peak_in_use = max(self.peak_in_use, self.in_use)
+                self._rebuild(leaving, joining, clock())
+            if not self.active:
+                if self.waiting:
+                    time.sleep(max(0.0, min(0.005, self.waiting[0].arrival - clock())))
+                continue
+            # steps until the next replica finishes, and at most admit_every
+            # when replicas are waiting for a slot in the batch
+            left = min(r.steps - r.done for r in self.active)
+            if self.waiting:
+                left = max(1, min(left, self.admit_every - self._since_rebuild))
+            for _ in range(left):
+                if len(inflight) >= self.max_inflight:
+                    inflight.pop(0).synchronize()
+                ev0 = None
+                with torch.cuda.stream(self.stream):
+                    if self._need_start:
+                        ev0 = torch.cuda.Event(enable_timing=True)
+                        ev0.record(self.stream)
+                        self._need_start = False
+                    if self.graph is not None:
+                        self.graph.replay()
+                    else:
+                        self._step()
+                    ev1 = torch.cuda.Event(enable_timing=True)
+                    ev1.record(self.stream)
+                inflight.append(ev1)
+                self.ticks.append((len(self.active), self.batch.n, ev0, ev1))
+                self._since_rebuild += 1
+                self._ticks_total += 1
+                for r in self.active:
+                    r.done += 1
+                if self.check_every and self._ticks_total % self.check_every == 0:
+                    self.stream.synchronize()
+                    inflight.clear()
+                    self._need_start = True
+                    bad = self._check(clock())
+                    if bad:
+                        for r in bad:
+                            bits, _, _ = self.batch.status(raise_on_error=False)
+                            r.error = bits[self.active.index(r)]
+                            r.finished_at = clock()
+                            self.in_use -= r.fp
+                            self.failed.append(r)
+                        self._rebuild(bad, [], clock())
+                        break
+        self.stream.synchronize()
+        self.t_end = time.perf_counter()
+        return self.finished
+
+    def step_latencies_ms(self):
+        """Per-tick device durations (ms) and the number of replicas in each."""
+        durs, counts = [], []
+        prev = None
+        for n_act, atoms, ev0, ev1 in self.ticks:
+            ref = ev0 if ev0 is not None else prev
+            durs.append(ref.elapsed_time(ev1))
+            counts.append(n_act)
+            prev = ev1
+        return np.array(durs), np.array(counts)
+
+    def report(self, wall=None):
+        wall = wall if wall is not None else self.t_end - self.t_start
+        durs, counts = self.step_latencies_ms()
+        # every replica-step carries its tick's duration
+        per_rep = np.repeat(durs, counts)
+        atom_steps = sum(r.n * r.steps for r in self.finished)
+        waits = np.array([r.admitted_at - r.arrival for r in self.finished])
+        turnaround = np.array([r.finished_at - r.arrival for r in self.finished])
+        return {"replicas": len(self.finished), "failed": len(self.failed),
+                "atom_steps": atom_steps, "wall_s": wall,
+                "replica_atom_steps_per_s": atom_steps / wall,
+                "p50_step_ms": float(np.percentile(per_rep, 50)),
+                "p99_step_ms": float(np.percentile(per_rep, 99)),
+                "mean_batch": float(np.mean(counts)), "max_batch": int(counts.max()),
+                "mean_queue_wait_s": float(waits.mean()),
+                "p99_queue_wait_s": float(np.percentile(waits, 99)),
+                "mean_turnaround_s": float(turnaround.mean()),
+                "rebuilds": self.rebuilds, "ticks": len(durs),
+                "device_busy_s": float(durs.sum() / 1e3),
+                "peak_admitted_bytes": int(self.peak_in_use)}
+
+
 def replicas_c4(count, steps, seed_rate=None, rate_hz=None, dt=0.2, n_range=(2000, 20000), seed=0):
     """Replica requests of the He-impact workload with Poisson arrivals."""
     from gen import workloads as W
@@ -280,39 +547,75 @@ def replicas_c4(count, steps, seed_rate=None, rate_hz=None, dt=0.2, n_range=(200
     return out
 
 
+def c4_rate_for_load(load, atom_steps_per_s, n_range=(2000, 20000), steps=2000):
+    """Poisson arrival rate (1/s) at `load` x the capacity a measured
+    throughput gives: capacity in replicas/s = throughput / (mean atoms of
+    the log-uniform size distribution x steps)."""
+    lo, hi = n_range
+    mean_atoms = (hi - lo) / np.log(hi / lo)
+    return load * atom_steps_per_s / (mean_atoms * steps)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("--replicas", type=int, default=64)
-    ap.add_argument("--steps", type=int, default=500)
-    ap.add_argument("--rate", type=float, default=0.0, help="Poisson arrival rate (1/s); 0 = all at t=0")
-    ap.add_argument("--slots", type=int, default=16)
-    ap.add_argument("--hbm-gb", type=float, default=16.0)
-    ap.add_argument("--graph", action="store_true",
-                    help="one multi-stream HIP graph per batch composition (default: eager "
-                         "launches of every replica's step on its own stream)")
-    ap.add_argument("--graph-per-replica", action="store_true",
-                    help="one HIP graph per replica, captured at admission; a tick launches "
-                         "the active replicas' graphs, each on its own stream")
+    ap.add_argument("--replicas", type=int, default=256)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--rate", type=float, default=0.0,
+                    help="Poisson arrival rate (1/s); 0 = all at t=0")
+    ap.add_argument("--load", type=float, default=0.0,
+                    help="arrival rate as this fraction of the capacity measured by a short "
+                         "calibration run first (overrides --rate)")
+    ap.add_argument("--hbm-gb", type=float, default=128.0)
+    ap.add_argument("--max-active", type=int, default=512)
+    ap.add_argument("--admit-every", type=int, default=20)
+    ap.add_argument("--eager", action="store_true", help="no HIP graph per batch composition")
+    ap.add_argument("--per-replica-streams", action="store_true",
+                    help="the per-replica server (each replica's step on its own stream, "
+                         "ticks in lockstep) instead of the batched one")
+    ap.add_argument("--slots", type=int, default=16, help="slots of the per-replica server")
+    ap.add_argument("--out", default="")
     args = ap.parse_args(argv)
-    mode = "replica" if args.graph_per_replica else args.graph
     from gen import workloads as W
     model = core.Model(W.c4_model(), precision="fp32")
-    srv = Server(model, hbm_budget=args.hbm_gb * (1 << 30), max_slots=args.slots,
-                 use_graph=mode)
-    reps = replicas_c4(args.replicas, args.steps, rate_hz=args.rate or None)
+    rate = args.rate
+    calib = None
+    if args.load > 0:
+        # capacity: 32 replicas, all at t = 0, 100 steps each
+        srv = BatchServer(model, hbm_budget=args.hbm_gb * (1 << 30), use_graph=not args.eager)
+        for r in replicas_c4(32, 100, seed=1):
+            srv.submit(r)
+        srv.run(clock=lambda: 1e9)
+        calib = srv.report()
+        rate = c4_rate_for_load(args.load, calib["replica_atom_steps_per_s"], steps=args.steps)
+        print(json.dumps({"calibration": calib, "rate_hz": rate}), flush=True)
+    reps = replicas_c4(args.replicas, args.steps, rate_hz=rate or None)
+    if args.per_replica_streams:
+        srv = Server(model, hbm_budget=args.hbm_gb * (1 << 30), max_slots=args.slots,
+                     use_graph="replica" if not args.eager else False)
+    else:
+        srv = BatchServer(model, hbm_budget=args.hbm_gb * (1 << 30), max_active=args.max_active,
+                          admit_every=args.admit_every, use_graph=not args.eager)
     for r in reps:
         srv.submit(r)
     t0 = time.perf_counter()
     srv.run()
     wall = time.perf_counter() - t0
     rep = srv.report(wall)
-    rep.update({"workload": "c4: W(001)+He impact replicas, log-uniform 2,000-20,000 atoms, "
-                            "dt 0.2 fs, 8 A sphere following He, FP32 potentials",
-                "steps_per_replica": args.steps, "arrival_rate_hz": args.rate,
-                "slots": args.slots, "graph": mode,
-                "hbm_budget_bytes": srv.budget,
+    sizes = np.array([r.n for r in reps])
+    rep.update({"workload": "W(001)+He impact replicas, log-uniform 2,000-20,000 atoms, "
+                            "dt 0.2 fs, 8 A sphere following He, two-species FP32 potentials",
+                "server": "per-replica streams" if args.per_replica_streams else "batched",
+                "graph": not args.eager,
+                "steps_per_replica": args.steps, "arrival_rate_hz": rate, "load": args.load,
+                "mean_replica_atoms": float(sizes.mean()),
+                "hbm_budget_bytes": int(args.hbm_gb * (1 << 30)),
                 "hbm_peak_allocated_bytes": int(torch.cuda.max_memory_allocated())})
-    print(json.dumps(rep))
+    if calib:
+        rep["calibration_atom_steps_per_s"] = calib["replica_atom_steps_per_s"]
+    print(json.dumps(rep), flush=True)
+    if args.out:
+        with open(args.out, "w") as f:
+            json.dump(rep, f, indent=1)
     return rep
 
 

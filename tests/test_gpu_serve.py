@@ -117,3 +117,76 @@ def test_replica_graphs_equal_eager_steps():
     for rid in (6, 2):
         for key in ("pos", "vel", "energies"):
             assert np.array_equal(out[False][rid][key], out["replica"][rid][key]), (rid, key)
+
+
+# ------------------------------------------------------------ batched server
+
+def _tick_clock(srv):
+    # arrivals in units of batch steps: the mix changes at known steps
+    return lambda: float(srv._ticks_total)
+
+
+def test_batch_server_alone_equals_in_changing_mix():
+    from paper_2502_19081_amd.serve import BatchServer
+    model = _model()
+    print("case batched serving: a replica alone vs in a changing mix (bitwise)", flush=True)
+    res = {}
+    for name in ("alone", "mix"):
+        srv = BatchServer(model, admit_every=4, check_every=7)
+        reps = [_rep(5, 40, 0.0, 2500)]
+        if name == "mix":
+            reps += [_rep(1, 10, 0.0, 2000), _rep(2, 20, 5.0, 3000), _rep(3, 15, 12.0, 2200),
+                     _rep(4, 6, 30.0, 2100)]
+        for r in reps:
+            srv.submit(r)
+        srv.run(clock=_tick_clock(srv))
+        assert not srv.failed and all(r.done == r.steps for r in srv.finished)
+        a = [r for r in srv.finished if r.rid == 5][0]
+        res[name] = a.result
+        if name == "mix":
+            assert srv.rebuilds >= 5
+            rep = srv.report()
+            assert rep["max_batch"] >= 3 and rep["replicas"] == 5
+    for key in ("pos", "vel", "energies", "n_exp"):
+        assert np.array_equal(res["alone"][key], res["mix"][key]), key
+
+
+def test_batch_server_graph_equals_eager_and_admission_by_budget():
+    from paper_2502_19081_amd.serve import BatchServer
+    model = _model()
+    print("case batched serving: graph = eager, HBM budget of 2.5 replicas", flush=True)
+    out = {}
+    for use_graph in (False, True):
+        probe = BatchServer(model)
+        fp = max(probe.footprint(_rep(k, 1, 0.0, 2000)) for k in range(4))
+        srv = BatchServer(model, hbm_budget=int(2.5 * fp), use_graph=use_graph, admit_every=3)
+        for k in range(4):
+            srv.submit(_rep(k, 12 + 3 * k, 0.0, 2000))
+        srv.run(clock=_tick_clock(srv))
+        rep = srv.report()
+        assert rep["replicas"] == 4 and rep["max_batch"] <= 2
+        assert srv.peak_in_use <= srv.budget
+        out[use_graph] = {r.rid: r.result for r in srv.finished}
+    for rid in range(4):
+        for key in ("pos", "vel", "energies"):
+            assert np.array_equal(out[False][rid][key], out[True][rid][key]), (rid, key)
+
+
+def test_batch_server_evicts_nonfinite_replica_alone():
+    from paper_2502_19081_amd.serve import BatchServer
+    model = _model()
+    print("case batched serving: eviction of a non-finite replica", flush=True)
+    srv = BatchServer(model, check_every=3)
+    good = [_rep(k, 8, 0.0, 2000) for k in (7, 8)]
+    bad = _rep(9, 8, 0.0, 2000)
+    bad.w = dict(bad.w)
+    p = bad.w["pos"].copy()
+    p[10, 0] = np.nan
+    bad.w["pos"] = p
+    for r in good + [bad]:
+        srv.submit(r)
+    srv.run(clock=lambda: 0.0)
+    assert [r.rid for r in srv.failed] == [9]
+    assert sorted(r.rid for r in srv.finished) == [7, 8]
+    for r in srv.finished:
+        assert np.isfinite(r.result["pos"]).all()
