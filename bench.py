@@ -25,6 +25,9 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FP32_VALU_TFLOPS = 157.3
+# the library is built without packed FP32 instructions: its FP32 vector code
+# issues one FP32 FMA per lane per cycle, half the packed rate
+FP32_VALU_UNPACKED_TFLOPS = 78.6
 FP64_VALU_TFLOPS = 78.6
 # dense matrix-core peaks (FP32 MFMA matches the FP32 vector peak)
 MFMA_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp8": 5000.0}
@@ -143,7 +146,8 @@ def cpu_model():
     return None
 
 
-KERNEL_SOURCES = {"ace_contract": ["paper_2502_19081_amd/csrc/o3.hip", "paper_2502_19081_amd/csrc/internal.h"]}
+KERNEL_SOURCES = {"ace_contract": ["paper_2502_19081_amd/csrc/o3.hip", "paper_2502_19081_amd/csrc/internal.h"],
+                  "uf3": ["paper_2502_19081_amd/csrc/uf3.hip", "paper_2502_19081_amd/csrc/internal.h"]}
 
 
 def measured_traffic(stage, cfg, prec):
@@ -397,6 +401,27 @@ def fit_main(args):
     print(json.dumps(res))
 
 
+def replay_ms(model, sy, pos, sp, stage, reps):
+    """Average duration (ms) of one stage's kernel: `reps` back-to-back
+    launches on the state the last evaluation left in the workspace, two HIP
+    events around them on the launch stream (the current stream)."""
+    import ctypes
+    import torch
+    from paper_2502_19081_amd import binding as B
+    cur = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    args = (model.handle, cur, ctypes.c_void_p(sy.ws.data_ptr()), sy.n,
+            ctypes.c_void_p(pos.data_ptr()), ctypes.c_void_p(sp.data_ptr()),
+            ctypes.byref(sy.box), ctypes.c_void_p(sy.e_cheap.data_ptr()), stage)
+    B.check(B.lib().mlmix_profile_replay(*args, 10))
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    B.check(B.lib().mlmix_profile_replay(*args, reps))
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
 def main():
     args = parse()
     if args.probe == "copy":
@@ -539,25 +564,14 @@ def main():
     dom_avg_ms = dom_ms / max(dom_cnt, 1)
     dom_in_step_ms = dom_avg_ms
     dom_method = "stage bracketed by HIP events inside each of the K eager steps"
+    # the state of one mixed step for the kernel replays below
+    sy_r, pos_r, vel_r, sp_r = fresh(B.MODE_MIXED)
+    step(sy_r, pos_r, vel_r, sp_r, B.MODE_MIXED)
     if dominant == "ace_contract":
         # the contraction's own duration: K back-to-back launches on the
         # state of a mixed step, two events around them on its stream (the
         # in-step bracket also holds the dispatch gap before the kernel)
-        import ctypes
-        sy_r, pos_r, vel_r, sp_r = fresh(B.MODE_MIXED)
-        step(sy_r, pos_r, vel_r, sp_r, B.MODE_MIXED)
-        cur = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
-        B.check(B.lib().mlmix_profile_replay(model.handle, cur, ctypes.c_void_p(sy_r.ws.data_ptr()),
-                                             n, ctypes.c_void_p(sp_r.data_ptr()), dom_bit, 10))
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record()
-        B.check(B.lib().mlmix_profile_replay(model.handle, cur, ctypes.c_void_p(sy_r.ws.data_ptr()),
-                                             n, ctypes.c_void_p(sp_r.data_ptr()), dom_bit,
-                                             args.steps))
-        e1.record()
-        torch.cuda.synchronize()
-        dom_avg_ms = e0.elapsed_time(e1) / args.steps
+        dom_avg_ms = replay_ms(model, sy_r, pos_r, sp_r, dom_bit, args.steps)
         dom_cnt = args.steps
         dom_method = ("K back-to-back launches on the state of a mixed step, HIP events on "
                       "the launch stream")
@@ -567,6 +581,11 @@ def main():
                           "in_step_bracket_ms": dom_in_step_ms, "method": dom_method,
                           "config": cfg, "precision": prec}), flush=True)
         return
+
+    # the cheap potential's own duration (second stream: it runs beside the
+    # expensive chain in a step), K back-to-back uncapped launches
+    uf3_bit = [B.lib().mlmix_profile_stage_name(i).decode() for i in range(B.N_STAGES)].index("uf3")
+    uf3_ms = replay_ms(model, sy_r, pos_r, sp_r, uf3_bit, args.steps)
 
     # 3. timed region: K mixed steps replayed from one captured HIP graph
     el, _, _, _ = run(B.MODE_MIXED, args.steps, args.warmup, graph=True)
@@ -646,7 +665,7 @@ def main():
         if not t:
             continue
         if kd == "flops":
-            pk = FP64_VALU_TFLOPS if prec == "fp64" else FP32_VALU_TFLOPS
+            pk = FP64_VALU_TFLOPS if prec == "fp64" else FP32_VALU_UNPACKED_TFLOPS
             if k == "ace_contract" and prec != "fp64" and w["model"]["n_species"] == 1:
                 pk = MFMA_TFLOPS["fp32"]
             a_ = u / (t * 1e-3) / 1e12
@@ -655,6 +674,17 @@ def main():
             a_ = u / (t * 1e-3) / 1e9
             stage_roof[k] = {"unit": "GB/s", "achieved": a_, "peak": HBM_PEAK_GBS,
                              "frac": a_ / HBM_PEAK_GBS}
+    uf3_units = work["uf3"][1]
+    uf3_peak = FP64_VALU_TFLOPS if prec == "fp64" else FP32_VALU_UNPACKED_TFLOPS
+    uf3_roof = {"kernel": "uf3", "bound": "alu", "unit": "TFLOP/s",
+                "achieved": uf3_units / (uf3_ms * 1e-3) / 1e12, "peak": uf3_peak,
+                "frac": uf3_units / (uf3_ms * 1e-3) / 1e12 / uf3_peak, "avg_ms": uf3_ms,
+                "launches": args.steps, "algorithmic_per_launch": uf3_units,
+                "traffic": measured_traffic("uf3", cfg, prec),
+                "timing": "K back-to-back uncapped launches on the state of a mixed step, HIP "
+                          "events on the launch stream",
+                "note": "second stream: in a step it runs beside the expensive chain; peak = "
+                        "FP32 vector rate without packed instructions (the build disables them)"}
     traffic = measured_traffic(dominant, cfg, prec)
     kind, units = work[dominant]
     if kind == "flops":
@@ -767,6 +797,7 @@ def main():
         "stage_ms_per_step": {k: round(v, 5) for k, v in stage_ms.items()},
         "stage_roofline": stage_roof,
         "roofline": roof,
+        "second_stream_roofline": uf3_roof,
         "cpu_baseline": cpu,
     }
     print(json.dumps(res))

@@ -545,15 +545,18 @@ int mlmix_profile_read(mlmix_ctx *ctx, double *ms, int64_t *count);
 const char *mlmix_profile_stage_name(int32_t stage);
 
 /* Benchmark hook: launches the kernels of one stage reps times, back to back
- * on `stream`, on the data the last evaluation left in ws (the stage reads
- * and writes workspace arrays only, so every replay does the same work).
- * Only stage 4 (the expensive order-3 contraction) is supported; species as
- * in mlmix_compute. Timing these launches with two events gives the kernel's
- * own duration without the dispatch gap in front of it. Errors: MLMIX_E_ARG
- * (NULL, negative reps, another stage, n_atoms not the workspace's),
- * MLMIX_E_STATE (workspace not initialised). */
+ * on `stream`, on the data the last evaluation left in ws (every replay does
+ * the same work). Stage 4 (the expensive order-3 contraction) reads and
+ * writes workspace arrays only (pos, box and e_cheap may be NULL); stage 7
+ * (the cheap potential, uncapped as on one stream) also reads pos [dev] and
+ * box and writes e_cheap [dev] double[n]. Species as in mlmix_compute.
+ * Timing these launches with two events gives the kernel's own duration
+ * without the dispatch gap in front of it. Errors: MLMIX_E_ARG (NULL,
+ * negative reps, another stage, n_atoms not the workspace's, a batch
+ * workspace), MLMIX_E_STATE (workspace not initialised). */
 int mlmix_profile_replay(mlmix_ctx *ctx, void *stream, void *ws, int32_t n_atoms,
-                         const int32_t *species, int32_t stage, int32_t reps);
+                         const double *pos, const int32_t *species, const mlmix_box *box,
+                         double *e_cheap, int32_t stage, int32_t reps);
 
 /* Achievable-peak probe: launches `blocks` workgroups of four waves, each
  * running `iters` rounds of eight independent FP32 16x16x4 matrix-core

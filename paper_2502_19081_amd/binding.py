@@ -119,7 +119,8 @@ SIGNATURES = {
                                              _d, _d, _d, _i32, _i32, _vp, _vp, _vp,
                                              ctypes.c_size_t]),
     "mlmix_profile_enable": (ctypes.c_int, [_vp, _u32]),
-    "mlmix_profile_replay": (ctypes.c_int, [_vp, _vp, _vp, _i32, _vp, _i32, _i32]),
+    "mlmix_profile_replay": (ctypes.c_int, [_vp, _vp, _vp, _i32, _vp, _vp, ctypes.POINTER(Box),
+                                            _vp, _i32, _i32]),
     "mlmix_probe_mfma_f32": (ctypes.c_int, [_vp, _i32, _i32, _vp, ctypes.POINTER(_d)]),
     "mlmix_profile_read": (ctypes.c_int, [_vp, _vp, _vp]),
     "mlmix_profile_stage_name": (ctypes.c_char_p, [_i32]),

@@ -1234,7 +1234,10 @@ static void contract_t(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L,
     const int *dp_off = reinterpret_cast<const int *>(static_cast<char *>(c.m.base) + c.m.dpoff);
     T *Dpart = at<T>(ws, L.dpart);
     if (a.order >= 3 && c.m.n_pb > 0 && c.o3 && sizeof(T) == 4) {
-        launch_ace_o3(s, c, ws, L);
+        if (c.o3 == 2)
+            launch_ace_o3w(s, c, ws, L, species);
+        else
+            launch_ace_o3(s, c, ws, L);
     } else if (a.order >= 3 && c.m.n_pb > 0) {
         int TA, mf, stage;
         blocks_shape(c, sizeof(T), TA, mf, stage);
@@ -1313,7 +1316,10 @@ void launch_ace_contract(hipStream_t s, const Ctx &c, void *ws, const WsLayout &
         return;
     }
     if (c.prec != MLMIX_FP64 && c.o3) {
-        launch_ace_o3(s, c, ws, L, ev0, ev1);
+        if (c.o3 == 2)
+            launch_ace_o3w(s, c, ws, L, species, ev0, ev1);
+        else
+            launch_ace_o3(s, c, ws, L, ev0, ev1);
         return;
     }
     if (c.prec == MLMIX_FP64)

@@ -336,6 +336,7 @@ struct HostTables {
     int dp_stride = 0;
     // matrix-core order-3 kernel
     bool o3 = false;
+    int o3_kind = 0;  // 1 single-species narrow form, 2 wide form
     int o3_nch2 = 0;
     std::vector<double> o3g, o3w, o3sw, o3gs;
     std::vector<int> o3o, o3mt, o3base, o3order, o3wbeg;
@@ -355,15 +356,30 @@ struct HostTables {
 //  - longest-processing-time assignments of the blocks to 4 G bins (four
 //    waves of each of G workgroups sharing a tile), G = 1, 2, 4, 8;
 //  - per (block, m3) the sum of |g|, for the FP8 row-scale bound.
+//
+// The wide form (FP32, more than one species or 17-32 channels) uses the same
+// entry lists with A rows 16 NT channels apart in LDS (NT = channel tiles of
+// 16), its own cost model, and weight fragments for its dense stage, per
+// species: for lane (c = l % 16, q = l / 16), channel tile ct and a, the
+// NJ = nchp / 4 values W[a][b = NJ q + j][c = 16 ct + c], j < NJ, padded to a
+// multiple of four, stored [species][block][a][ct][lane][NJ padded].
 static void build_o3(const mlmix_model_desc &d, HostTables &t)
 {
     const int nch = d.n_species * d.ace_n_rad, lmax = d.ace_lmax;
     const int nchp = (nch + 3) & ~3;
-    const bool narrow = d.precision == MLMIX_BF16_CONTRACT || d.precision == MLMIX_FP8_CONTRACT;
+    const bool reduced = d.precision == MLMIX_BF16_CONTRACT || d.precision == MLMIX_FP8_CONTRACT;
     t.o3 = false;
-    if (d.ace_order < 3 || d.n_species != 1 || nch > 16 || t.pb.empty() ||
-        d.precision == MLMIX_FP64)
+    t.o3_kind = 0;
+    if (d.ace_order < 3 || t.pb.empty() || d.precision == MLMIX_FP64)
         return;
+    const bool narrow_ok = d.n_species == 1 && nch <= 16;
+    const bool wide_ok = !narrow_ok && nch <= 32 && d.precision == MLMIX_FP32;
+    if (!narrow_ok && !wide_ok)
+        return;
+    const int kind = narrow_ok ? 1 : 2;
+    const int NT = kind == 1 ? 1 : (nchp + 15) / 16;  // channel tiles of the wide form
+    const int NCP = 16 * NT;                          // LDS channel stride of the A rows
+    const int NJ = nchp / 4, NJP = (NJ + 3) & ~3;
     const int nch2 = nchp;  // row width of the kernel: channels rounded up to 4
     std::vector<int> cost(t.pb.size(), 0);
     std::vector<std::vector<int>> rcost(t.pb.size());  // per (block, m3) row
@@ -382,7 +398,7 @@ static void build_o3(const mlmix_model_desc &d, HostTables &t)
                 float g = 0.0f;
                 if (e < e1) {
                     int m1 = t.gidx[e] & 0xff, m2 = t.gidx[e] >> 8;
-                    int o1 = (b.l1 * b.l1 + m1) * 16, o2 = (b.l2 * b.l2 + m2) * 16;
+                    int o1 = (b.l1 * b.l1 + m1) * NCP, o2 = (b.l2 * b.l2 + m2) * NCP;
                     o = o1 | (o2 << 16);
                     g = (float)t.gval[e];
                 }
@@ -392,9 +408,11 @@ static void build_o3(const mlmix_model_desc &d, HostTables &t)
                 t.o3o.push_back(gbits);
                 t.o3g.push_back(g);
             }
-            // MFMA steps per row tile: sparse 16 rows x groups, dense in
-            // units of a 16x16x4 FP32 step (narrow operands are 8x cheaper)
-            const int rc = 16 * ng + (narrow ? std::max(1, nch2 / 8) : 4 * nch2) + 4;
+            // MFMA steps per row tile: sparse 16 rows x groups (x NT^2 tiles
+            // in the wide form), dense in units of a 16x16x4 FP32 step
+            // (reduced operands are 8x cheaper)
+            const int rc = kind == 2 ? 16 * NT * NT * ng + nch2 * NT * NJ + 4
+                                     : 16 * ng + (reduced ? std::max(1, nch2 / 8) : 4 * nch2) + 4;
             cost[p] += rc;
             rcost[p].push_back(rc);
         }
@@ -405,8 +423,27 @@ static void build_o3(const mlmix_model_desc &d, HostTables &t)
         t.o3o.push_back(0);
         t.o3o.push_back(0);
     }
-    // weight fragments (and FP8 column scales)
     const size_t P = t.pb.size();
+    if (kind == 2) {
+        const int ns = d.n_species;
+        t.o3w.assign((size_t)ns * P * nch2 * NT * 64 * NJP, 0.0);
+        for (int z = 0; z < ns; ++z)
+            for (size_t p = 0; p < P; ++p)
+                for (int a = 0; a < nch; ++a)
+                    for (int ct = 0; ct < NT; ++ct)
+                        for (int l = 0; l < 64; ++l)
+                            for (int j = 0; j < NJ; ++j) {
+                                const int c = 16 * ct + (l & 15), b = NJ * (l >> 4) + j;
+                                double v = 0.0;
+                                if (b < nch && c < nch)
+                                    v = t.W[(size_t)z * t.w_per_species + t.pb[p].w_off +
+                                            ((size_t)a * nchp + b) * nchp + c];
+                                t.o3w[((((((size_t)z * P + p) * nch2 + a) * NT + ct) * 64 + l) *
+                                       NJP) + j] = v;
+                            }
+        t.o3sw.assign(P * 16, 1.0);
+    } else {
+    // weight fragments (and FP8 column scales)
     t.o3sw.assign(P * 16, 1.0);
     if (d.precision == MLMIX_FP8_CONTRACT)
         for (size_t p = 0; p < P; ++p)
@@ -428,6 +465,7 @@ static void build_o3(const mlmix_model_desc &d, HostTables &t)
                     }
                     t.o3w[(((p * nch2) + i) * 64 + l) * 4 + j] = v;
                 }
+    }
     // work items to waves, for a tile's block list split over G = 1, 2, 4, 8
     // workgroups (4 G bins). An item is a range of m3 rows of one block: for
     // G > 1, a block costing more than half of a bin's even share is cut into
@@ -492,6 +530,7 @@ static void build_o3(const mlmix_model_desc &d, HostTables &t)
     }
     t.o3_nch2 = nch2;
     t.o3 = true;
+    t.o3_kind = kind;
 }
 
 // Clamped uniform cubic B-splines on knots t(i) = clamp(i - 3, 0, npts - 1)
@@ -1031,7 +1070,7 @@ try {
         c.max_gm3 = std::max(c.max_gm3, g_hi - g_lo);
         c.max_ent = std::max(c.max_ent, t.gm3[g_hi - 1] - t.gm3[g_lo]);
     }
-    c.o3 = t.o3 ? 1 : 0;
+    c.o3 = t.o3 ? t.o3_kind : 0;
     c.o3_nch2 = t.o3_nch2;
     if (const char *e = std::getenv("MLMIX_FORK_AT"))
         c.fork_at = std::max(0, std::min(2, std::atoi(e)));
@@ -1051,7 +1090,18 @@ try {
     if (const char *e = std::getenv("MLMIX_ACE_O3"))
         if (!std::atoi(e))
             c.o3 = 0;  // general block kernel (comparisons)
-    if (c.qmode != 0 && !c.o3) {
+    {
+        int lim = 0;
+        if (hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, c.device) ==
+                hipSuccess &&
+            lim > 0)
+            c.max_lds = lim;
+    }
+    if (c.o3 == 2 && (o3w_lds_bytes(c) > (size_t)c.max_lds || o3w_prepare(c) != hipSuccess)) {
+        (void)hipGetLastError();
+        c.o3 = 0;  // the wide form does not fit this device: VALU blocks
+    }
+    if (c.qmode != 0 && c.o3 != 1) {
         return fail(MLMIX_E_ARG, "the BF16/FP8 contraction modes need a single-species model "
                                  "with at most 16 radial channels and correlation order 3");
     }
@@ -2175,12 +2225,17 @@ try {
 }
 
 extern "C" int mlmix_profile_replay(mlmix_ctx *ctx, void *stream, void *ws, int32_t n_atoms,
-                                    const int32_t *species, int32_t stage, int32_t reps)
+                                    const double *pos, const int32_t *species,
+                                    const mlmix_box *box, double *e_cheap, int32_t stage,
+                                    int32_t reps)
 try {
     if (!ctx || !ws || !species || reps < 0)
         return fail(MLMIX_E_ARG, "NULL argument or negative count");
-    if (stage != ST_CONTRACT)
-        return fail(MLMIX_E_ARG, "only the order-3 contraction (stage 4) can be replayed");
+    if (stage != ST_CONTRACT && stage != ST_UF3)
+        return fail(MLMIX_E_ARG, "only the order-3 contraction (stage 4) and the cheap "
+                                 "potential (stage 7) can be replayed");
+    if (stage == ST_UF3 && (!pos || !box || !e_cheap))
+        return fail(MLMIX_E_ARG, "the cheap potential needs pos, box and e_cheap");
     WsLayout L;
     {
         std::lock_guard<std::mutex> g(ctx->mu);
@@ -2191,9 +2246,21 @@ try {
     }
     if (L.n != n_atoms)
         return fail(MLMIX_E_ARG, "n_atoms differs from the workspace's");
+    if (L.nseg > 0)
+        return fail(MLMIX_E_ARG, "replays take a single-system workspace");
+    Box b{};
+    if (stage == ST_UF3) {
+        int rc = check_box(ctx, box, b);
+        if (rc)
+            return rc;
+    }
     hipStream_t s = static_cast<hipStream_t>(stream);
-    for (int r = 0; r < reps; ++r)
-        launch_ace_contract(s, ctx->c, ws, L, species);
+    for (int r = 0; r < reps; ++r) {
+        if (stage == ST_CONTRACT)
+            launch_ace_contract(s, ctx->c, ws, L, species);
+        else  // uncapped, as on one stream
+            launch_uf3(s, ctx->c, ws, L, b, pos, species, e_cheap, 0);
+    }
     HIP_OK(hipGetLastError());
     return MLMIX_OK;
 } catch (...) {

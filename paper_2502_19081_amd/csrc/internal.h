@@ -144,7 +144,11 @@ struct Ctx {
     int m_pb_lo[kMaxLmax + 1], m_pb_hi[kMaxLmax + 1];  // order-3 blocks per l3
     int max_ent, max_gm3;  // Gaunt entries / m3 offsets of the largest l3 group
     int max_ent_pb;        // Gaunt entries of the largest single block
-    int o3 = 0;            // order-3 contraction on the per-wave matrix-core kernel
+    // order-3 contraction on the matrix cores: 0 no (VALU blocks), 1 the
+    // single-species form (<= 16 channels, FP32/BF16/FP8 operands), 2 the wide
+    // form (FP32, any species count, <= 32 channels)
+    int o3 = 0;
+    int max_lds = 65536;   // dynamic LDS a workgroup may use on this device
     int basis_mfma = 1;    // atomic basis and pair adjoint on the matrix cores (FP32)
     int basis_chunks = -1; // basis in 64-slot passes: -1 above 65,536 atoms, 0 never, 1 always
     // second-stream fork after the rows (0), after the basis (1), or recorded
@@ -228,6 +232,10 @@ void launch_ace_pairgrad(hipStream_t s, const Ctx &c, void *ws, const WsLayout &
 void launch_ace_o3(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L,
                    hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 size_t o3_lds_bytes(const Ctx &c);
+void launch_ace_o3w(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L,
+                    const int32_t *species, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+size_t o3w_lds_bytes(const Ctx &c);
+hipError_t o3w_prepare(const Ctx &c);
 
 // ---- uf3.hip ----
 // mask_flags: NULL, or the flags array (MLMIX_CHEAP_MASKED): the cheap

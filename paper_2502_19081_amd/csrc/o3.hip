@@ -372,6 +372,307 @@ __global__ void __launch_bounds__(256, 1)
     }
 }
 
+// ------------------------------------------------------------- wide form
+//
+// The same contraction for FP32 models of any number of species and at most
+// 32 channels (channels a = species of the neighbour x radial function):
+// the same tiles of 16 atoms, work items, bins and per-block partial D; the
+// channel dimensions take NT = ceil(channels / 16) tiles of 16.
+//
+//  sparse stage  for each channel tile ta of a, every tile tb of b:
+//                P_t[a][b] as 16x16 MFMA products over the row's Gaunt
+//                entries (the atoms' A rows in LDS 16 NT channels apart,
+//                zero padded), all 16 atoms' tiles in registers;
+//  dense stage   eight channels a at a time through LDS: lane (atom m, q)
+//                reads P_m[a][NJ q + j], j < NJ = nchp / 4, so the MFMA K
+//                runs over exactly nchp^2 values (a, b), against weight
+//                fragments W_z[a][NJ q + j][16 ct + m] read through the cache
+//                (one set per centre species z and channel tile ct of c).
+//                A tile whose atoms are of several species runs the dense
+//                stage once per species present with the other species' rows
+//                zeroed: an atom's accumulator then receives the same
+//                nonzero terms in the same order as in a one-species tile
+//                (adding exact zeros changes no bits).
+struct O3WArgs {
+    const int *e;       // entries (A-row offsets 16 NT channels apart, coefficient bits)
+    const int *mt;      // (first entry, groups of four) per (block, m3)
+    const int *base;    // first (block, m3) row of each block
+    const float *w;     // [species][block][a][ct][64 lanes][NJ padded to 4]
+    const int *order;   // work items per split, as the single-species form
+    const int *wbeg;
+    const int *dp_off;  // per-block offset in the partial buffer
+    int n_pb, nch, L2, KAt, dp_stride, max_split, ns;
+};
+
+constexpr int kO3wAH = 8;  // channels a per dense pass of the wide form
+
+__host__ __device__ constexpr int o3w_rowb(int nc) { return kO3wAH * nc * 4 + 16; }
+
+// Sparse stage of the wide form for channel tile ta of a: cc[tb][t] holds
+// P_t[a = 16 ta + m][b = 16 tb + 4 q + v] after the NG entry groups.
+template <int NT, int NCP, int NG>
+__device__ __forceinline__ void o3w_sparse(const float *__restrict__ At, int L2, int m, int ta,
+                                           const int2 (&ent)[kO3MaxGroups],
+                                           f4v (&cc)[NT][kO3Atoms])
+{
+#pragma unroll
+    for (int t = 0; t < kO3Atoms; ++t) {
+#pragma unroll
+        for (int tb = 0; tb < NT; ++tb)
+            cc[tb][t] = (f4v){0.f, 0.f, 0.f, 0.f};
+        const float *At_t = At + (size_t)t * L2 * NCP + m;
+#pragma unroll
+        for (int k = 0; k < NG; ++k) {
+            const int o1 = ent[k].x & 0xffff, o2 = ent[k].x >> 16;
+            const float bv = __int_as_float(ent[k].y) * At_t[o1 + 16 * ta];
+#pragma unroll
+            for (int tb = 0; tb < NT; ++tb)
+                cc[tb][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(At_t[o2 + 16 * tb], bv, cc[tb][t],
+                                                                 0, 0, 0);
+        }
+    }
+}
+
+template <int NC>  // channels rounded up to a multiple of four (<= 32)
+__global__ void __launch_bounds__(256, 1)
+    k_ace_o3w(const int *__restrict__ hdr, const int32_t *__restrict__ species,
+              const int *__restrict__ S_idx, O3WArgs a, const float *__restrict__ A,
+              float *__restrict__ Dpart)
+{
+    constexpr int NT = (NC + 15) / 16;
+    constexpr int NCP = 16 * NT;
+    constexpr int NJ = NC / 4;
+    constexpr int NJP = (NJ + 3) & ~3;
+    constexpr int ROWB = o3w_rowb(NC);
+    const int nS = hdr[H_NS];
+    const int ntile = (nS + kO3Atoms - 1) / kO3Atoms;
+    int G = 1, lg = 0;
+    while (G < a.max_split && ntile * G < (int)gridDim.x) {
+        G <<= 1;
+        ++lg;
+    }
+    const int nitem = ntile * G;
+    if ((int)blockIdx.x >= nitem)
+        return;  // uniform across the workgroup
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int m = lane & 15, q = lane >> 4;
+    const int nch = a.nch, L2 = a.L2;
+    extern __shared__ __align__(16) char smem_raw[];
+    float *At = reinterpret_cast<float *>(smem_raw);  // [16][L2][NCP]
+    const size_t at_bytes = (size_t)kO3Atoms * L2 * NCP * sizeof(float);
+    char *Pw = smem_raw + at_bytes + (size_t)wv * kO3Atoms * ROWB;
+    int *zt = reinterpret_cast<int *>(smem_raw + at_bytes + (size_t)4 * kO3Atoms * ROWB);
+    const int *wbeg = a.wbeg + 4 * (G - 1) + lg;
+    const size_t wz = (size_t)a.n_pb * NC * NT * 64 * NJP;  // weight floats per species
+
+    for (int item = blockIdx.x; item < nitem; item += gridDim.x) {
+        const int tile = item >> lg, bin = ((item & (G - 1)) << 2) + wv;
+        const int w_lo = wbeg[bin], w_hi = wbeg[bin + 1];
+        const int s0 = tile * kO3Atoms;
+        const int na = min(kO3Atoms, nS - s0);
+        __syncthreads();  // every wave is done with the previous tile
+        for (int r = tid; r < kO3Atoms * L2; r += 256) {
+            const int t = r / L2, lm = r - t * L2;
+            f4v *dst = reinterpret_cast<f4v *>(At + (size_t)r * NCP);
+            const f4v *src = reinterpret_cast<const f4v *>(A + (size_t)(s0 + t) * a.KAt + lm * NC);
+#pragma unroll
+            for (int c4 = 0; c4 < NCP / 4; ++c4)
+                dst[c4] = (c4 < NC / 4 && t < na) ? src[c4] : (f4v){0.f, 0.f, 0.f, 0.f};
+        }
+        if (tid < kO3Atoms)
+            zt[tid] = tid < na ? sp_clamp(species[S_idx[s0 + tid]], a.ns) : -1;
+        __syncthreads();
+        unsigned zmask = 0;
+        for (int t = 0; t < kO3Atoms; ++t)
+            if (zt[t] >= 0)
+                zmask |= 1u << zt[t];
+        const int zrow = zt[m];  // species of this lane's atom row in the dense stage
+
+        for (int wi = w_lo; wi < w_hi; ++wi) {
+            const int code = a.order[wi];
+            const int p = code & 0xffff, m3lo = (code >> 16) & 0xff, m3hi = (code >> 24) & 0xff;
+            const int rbase = a.base[p];
+            float *Dblk = Dpart + a.dp_off[p];
+            int2 ent[kO3MaxGroups], ent_n[kO3MaxGroups];
+            int ng = a.mt[2 * (rbase + m3lo) + 1];
+            o3_load_row(a.e, a.mt[2 * (rbase + m3lo)], q, ent);
+            for (int m3 = m3lo; m3 < m3hi; ++m3) {
+                const int row = rbase + m3;
+                int ngn = 0;
+                if (m3 + 1 < m3hi) {
+                    ngn = a.mt[2 * row + 3];
+                    o3_load_row(a.e, a.mt[2 * row + 2], q, ent_n);
+                }
+                f4v acc[NT];
+#pragma unroll
+                for (int ct = 0; ct < NT; ++ct)
+                    acc[ct] = (f4v){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int ta = 0; ta < NT; ++ta) {
+                    f4v cc[NT][kO3Atoms];
+#define O3W_SPARSE(NGV) o3w_sparse<NT, NCP, NGV>(At, L2, m, ta, ent, cc)
+                    switch (ng) {
+                    case 0: O3W_SPARSE(0); break;
+                    case 1: O3W_SPARSE(1); break;
+                    case 2: O3W_SPARSE(2); break;
+                    case 3: O3W_SPARSE(3); break;
+                    case 4: O3W_SPARSE(4); break;
+                    case 5: O3W_SPARSE(5); break;
+                    case 6: O3W_SPARSE(6); break;
+                    case 7: O3W_SPARSE(7); break;
+                    default: O3W_SPARSE(8); break;
+                    }
+#undef O3W_SPARSE
+#pragma unroll
+                    for (int h = 0; h < 16; h += kO3wAH) {
+                        const int a0 = 16 * ta + h;
+                        if (a0 >= NC)
+                            break;  // uniform
+                        // P rows of the pass: [atom][a - a0][b], b contiguous
+                        if (m >= h && m < h + kO3wAH && a0 + m - h < NC) {
+#pragma unroll
+                            for (int tb = 0; tb < NT; ++tb) {
+                                const int b0 = 16 * tb + 4 * q;
+                                if (b0 < NC)
+#pragma unroll
+                                    for (int t = 0; t < kO3Atoms; ++t)
+                                        *reinterpret_cast<f4v *>(Pw + (size_t)t * ROWB +
+                                                                 ((m - h) * NC + b0) * 4) = cc[tb][t];
+                            }
+                        }
+                        wave_sync_lds();
+                        for (int z = 0; z < a.ns; ++z) {
+                            if (!((zmask >> z) & 1u))
+                                continue;  // uniform
+                            const bool mine = zrow == z;
+                            const float *wsrc = a.w + (size_t)z * wz + (size_t)p * NC * NT * 64 * NJP;
+#pragma unroll
+                            for (int al = 0; al < kO3wAH; ++al) {
+                                const int aa = a0 + al;
+                                if (aa >= NC)
+                                    break;  // uniform
+                                const float *prow =
+                                    reinterpret_cast<const float *>(Pw + (size_t)m * ROWB) +
+                                    al * NC + NJ * q;
+                                float pv[NJ];
+#pragma unroll
+                                for (int j = 0; j < NJ; ++j)
+                                    pv[j] = mine ? prow[j] : 0.0f;
+#pragma unroll
+                                for (int ct = 0; ct < NT; ++ct) {
+                                    const f4v *wf = reinterpret_cast<const f4v *>(
+                                        wsrc + (((size_t)aa * NT + ct) * 64 + lane) * NJP);
+                                    f4v w4[NJP / 4];
+#pragma unroll
+                                    for (int u = 0; u < NJP / 4; ++u)
+                                        w4[u] = wf[u];
+#pragma unroll
+                                    for (int j = 0; j < NJ; ++j)
+                                        acc[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                                            pv[j], w4[j >> 2][j & 3], acc[ct], 0, 0, 0);
+                                }
+                            }
+                        }
+                        wave_sync_lds();  // the next pass rewrites the P rows
+                    }
+                }
+                // lane holds D[atom = 4 q + v][c = 16 ct + m]
+#pragma unroll
+                for (int ct = 0; ct < NT; ++ct)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int t = 4 * q + v, c = 16 * ct + m;
+                        if (t < na && c < nch)
+                            Dblk[(size_t)(s0 + t) * a.dp_stride + m3 * nch + c] = acc[ct][v];
+                    }
+#pragma unroll
+                for (int k = 0; k < kO3MaxGroups; ++k)
+                    ent[k] = ent_n[k];
+                ng = ngn;
+            }
+        }
+    }
+}
+
+size_t o3w_lds_bytes(const Ctx &c)
+{
+    const DevModel &m = c.m;
+    const int nt = (m.nchp + 15) / 16;
+    return (size_t)kO3Atoms * m.L2 * 16 * nt * sizeof(float) +
+           (size_t)4 * kO3Atoms * o3w_rowb(m.nchp) + kO3Atoms * sizeof(int);
+}
+
+// Lets the wide kernel of this model use its dynamic LDS (beyond 64 KiB on
+// gfx950, whose workgroups may take up to 160 KiB).
+hipError_t o3w_prepare(const Ctx &c)
+{
+    const int lds = (int)o3w_lds_bytes(c);
+    auto set = [&](auto nc) {
+        constexpr int NC = decltype(nc)::value;
+        return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_ace_o3w<NC>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    };
+    switch (c.m.nchp) {
+    case 4: return set(std::integral_constant<int, 4>());
+    case 8: return set(std::integral_constant<int, 8>());
+    case 12: return set(std::integral_constant<int, 12>());
+    case 16: return set(std::integral_constant<int, 16>());
+    case 20: return set(std::integral_constant<int, 20>());
+    case 24: return set(std::integral_constant<int, 24>());
+    case 28: return set(std::integral_constant<int, 28>());
+    default: return set(std::integral_constant<int, 32>());
+    }
+}
+
+void launch_ace_o3w(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L,
+                    const int32_t *species, hipEvent_t ev0, hipEvent_t ev1)
+{
+    const DevModel &m = c.m;
+    const char *base = static_cast<const char *>(m.base);
+    O3WArgs a;
+    a.e = reinterpret_cast<const int *>(base + m.o3o);
+    a.mt = reinterpret_cast<const int *>(base + m.o3mt);
+    a.base = reinterpret_cast<const int *>(base + m.o3base);
+    a.w = reinterpret_cast<const float *>(base + m.o3w);
+    a.order = reinterpret_cast<const int *>(base + m.o3order);
+    a.wbeg = reinterpret_cast<const int *>(base + m.o3wbeg);
+    a.dp_off = reinterpret_cast<const int *>(base + m.dpoff);
+    a.n_pb = m.n_pb;
+    a.nch = m.nchan;
+    a.L2 = m.L2;
+    a.KAt = m.KAt;
+    a.dp_stride = m.dp_stride;
+    a.max_split = c.o3_max_split;
+    a.ns = m.ns;
+    const size_t lds = o3w_lds_bytes(c);
+    const int per_cu = lds <= 80 * 1024 ? 2 : 1;
+    const long items = (((long)L.n + kO3Atoms - 1) / kO3Atoms) * kO3MaxSplit;
+    const int grid = (int)std::min<long>(std::max<long>(items, 1), 256L * per_cu);
+    const int *hdr = at<int>(ws, L.hdr);
+    const int *S_idx = at<int>(ws, L.S_idx);
+    const float *A = at<float>(ws, L.A);
+    float *D = at<float>(ws, L.dpart);
+    auto go = [&](auto nc) {
+        constexpr int NC = decltype(nc)::value;
+        if (ev0)
+            hipExtLaunchKernelGGL(k_ace_o3w<NC>, dim3(grid), dim3(256), (uint32_t)lds, s, ev0, ev1,
+                                  0u, hdr, species, S_idx, a, A, D);
+        else
+            k_ace_o3w<NC><<<grid, 256, lds, s>>>(hdr, species, S_idx, a, A, D);
+    };
+    switch (m.nchp) {
+    case 4: go(std::integral_constant<int, 4>()); break;
+    case 8: go(std::integral_constant<int, 8>()); break;
+    case 12: go(std::integral_constant<int, 12>()); break;
+    case 16: go(std::integral_constant<int, 16>()); break;
+    case 20: go(std::integral_constant<int, 20>()); break;
+    case 24: go(std::integral_constant<int, 24>()); break;
+    case 28: go(std::integral_constant<int, 28>()); break;
+    default: go(std::integral_constant<int, 32>()); break;
+    }
+}
+
 size_t o3_lds_bytes(const Ctx &c)
 {
     const DevModel &m = c.m;

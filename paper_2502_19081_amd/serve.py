@@ -293,7 +293,7 @@ class BatchServer:
 
     def __init__(self, model, hbm_budget=64 << 30, max_active=512, cap=128, s_cap_per_replica=1024,
                  device="cuda", use_graph=True, admit_every=20, max_inflight=8, check_every=200,
-                 r_buffer=5.0):
+                 r_buffer=5.0, progress_s=0.0):
         self.model = model
         self.budget = int(hbm_budget)
         self.max_active = int(max_active)
@@ -305,6 +305,7 @@ class BatchServer:
         self.max_inflight = int(max_inflight)
         self.check_every = int(check_every)
         self.r_buffer = float(r_buffer)
+        self.progress_s = float(progress_s)  # seconds between progress lines (0: none)
         self.stream = torch.cuda.Stream(device=device)
         self.waiting = []
         self.active = []
@@ -436,8 +437,14 @@ class BatchServer:
         clock = clock or (lambda: time.perf_counter() - start)
         self.t_start = start
         inflight = []
+        next_progress = self.progress_s
         while self.waiting or self.active:
             now = clock()
+            if self.progress_s > 0 and time.perf_counter() - start >= next_progress:
+                next_progress += self.progress_s
+                print(f"serve: {time.perf_counter() - start:.0f} s, {len(self.finished)} done, "
+                      f"{len(self.active)} active, {len(self.waiting)} waiting, "
+                      f"{self._ticks_total} steps", flush=True)
             leaving = [r for r in self.active if r.done >= r.steps]
             joining = []
             if self.waiting and self.waiting[0].arrival <= now and \
@@ -580,9 +587,10 @@ def main(argv=None):
     rate = args.rate
     calib = None
     if args.load > 0:
-        # capacity: 32 replicas, all at t = 0, 100 steps each
+        # capacity at saturation: 64 replicas of the same size distribution,
+        # all at t = 0, 200 steps each (one full batch)
         srv = BatchServer(model, hbm_budget=args.hbm_gb * (1 << 30), use_graph=not args.eager)
-        for r in replicas_c4(32, 100, seed=1):
+        for r in replicas_c4(64, 200, seed=1):
             srv.submit(r)
         srv.run(clock=lambda: 1e9)
         calib = srv.report()
@@ -594,7 +602,7 @@ def main(argv=None):
                      use_graph="replica" if not args.eager else False)
     else:
         srv = BatchServer(model, hbm_budget=args.hbm_gb * (1 << 30), max_active=args.max_active,
-                          admit_every=args.admit_every, use_graph=not args.eager)
+                          admit_every=args.admit_every, use_graph=not args.eager, progress_s=20.0)
     for r in reps:
         srv.submit(r)
     t0 = time.perf_counter()
