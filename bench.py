@@ -75,6 +75,9 @@ def parse():
     ap.add_argument("--dominant", default=None,
                     help="take this stage as the dominant one instead of the largest in the "
                          "breakdown (for profiler runs)")
+    ap.add_argument("--keep-list", action="store_true",
+                    help="time the mixed step with the neighbour list kept while no atom has "
+                         "moved half the skin (as phase 6 does) in phases 1-3 (for profiler runs)")
     ap.add_argument("--single-stream", action="store_true",
                     help="keep every stage on the caller's stream (no fork of the cheap potential)")
     ap.add_argument("--fit", action="store_true",
@@ -540,8 +543,9 @@ def main():
         return (t1 - t0), prof, lat, sy
 
     # 1. per-stage breakdown (every stage bracketed) to find the dominant kernel
+    main_rebuild = not args.keep_list
     _, prof_all, _, _ = run(B.MODE_MIXED, max(10, args.steps // 4), args.warmup,
-                               stage_mask=(1 << B.N_STAGES) - 1)
+                               stage_mask=(1 << B.N_STAGES) - 1, rebuild=main_rebuild)
     stage_ms = {k: v[0] / max(v[1], 1) for k, v in prof_all.items() if v[1]}
     # with the second stream, the reverse slots and the cheap potential run
     # beside the expensive chain under a workgroup cap (their event times
@@ -559,7 +563,8 @@ def main():
     # 2. the dominant kernel's duration: K eager steps with only that stage
     # timed by HIP events on its launch stream (for the matrix-core
     # contraction the kernel's own start/end events)
-    el_eager, prof, _, _ = run(B.MODE_MIXED, args.steps, args.warmup, stage_mask=1 << dom_bit)
+    el_eager, prof, _, _ = run(B.MODE_MIXED, args.steps, args.warmup, stage_mask=1 << dom_bit,
+                               rebuild=main_rebuild)
     dom_ms, dom_cnt = prof[dominant]
     dom_avg_ms = dom_ms / max(dom_cnt, 1)
     dom_in_step_ms = dom_avg_ms
@@ -588,7 +593,7 @@ def main():
     uf3_ms = replay_ms(model, sy_r, pos_r, sp_r, uf3_bit, args.steps)
 
     # 3. timed region: K mixed steps replayed from one captured HIP graph
-    el, _, _, _ = run(B.MODE_MIXED, args.steps, args.warmup, graph=True)
+    el, _, _, _ = run(B.MODE_MIXED, args.steps, args.warmup, graph=True, rebuild=main_rebuild)
     ms_step = 1e3 * el / args.steps
     value = n * args.steps / el
 
@@ -780,7 +785,9 @@ def main():
                    "cheap": "masked to its subsystem" if args.cheap_masked else "every atom",
                    "thermostat": ("Langevin 300 K, 2 ps, lambda == 0 atoms" if args.langevin
                                   else "none (NVE)"),
-                   "precision": prec, "neighbour_rebuild": "every step", "n_S": nS, "n_lambda_pos": nM,
+                   "precision": prec,
+                   "neighbour_rebuild": ("kept while no atom moved half the skin"
+                                         if args.keep_list else "every step"), "n_S": nS, "n_lambda_pos": nM,
                    "launch": (f"{args.graph_steps} consecutive steps per captured HIP graph "
                               f"({'one step per call' if args.langevin else 'one fused multi-step call'}), "
                               "replayed" if args.steps % args.graph_steps == 0 and args.graph_steps > 1

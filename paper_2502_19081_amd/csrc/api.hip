@@ -337,6 +337,8 @@ struct HostTables {
     // matrix-core order-3 kernel
     bool o3 = false;
     int o3_kind = 0;  // 1 single-species narrow form, 2 wide form
+    bool o3_wide_ready = false;  // wide-form weight fragments built
+    std::vector<double> o3ww;
     int o3_nch2 = 0;
     std::vector<double> o3g, o3w, o3sw, o3gs;
     std::vector<int> o3o, o3mt, o3base, o3order, o3wbeg;
@@ -424,9 +426,11 @@ static void build_o3(const mlmix_model_desc &d, HostTables &t)
         t.o3o.push_back(0);
     }
     const size_t P = t.pb.size();
-    if (kind == 2) {
+    // wide-form fragments: for the wide form, and for a single-species FP32
+    // model too (the wide form can then be selected for comparisons)
+    if (kind == 2 || d.precision == MLMIX_FP32) {
         const int ns = d.n_species;
-        t.o3w.assign((size_t)ns * P * nch2 * NT * 64 * NJP, 0.0);
+        t.o3ww.assign((size_t)ns * P * nch2 * NT * 64 * NJP, 0.0);
         for (int z = 0; z < ns; ++z)
             for (size_t p = 0; p < P; ++p)
                 for (int a = 0; a < nch; ++a)
@@ -438,9 +442,12 @@ static void build_o3(const mlmix_model_desc &d, HostTables &t)
                                 if (b < nch && c < nch)
                                     v = t.W[(size_t)z * t.w_per_species + t.pb[p].w_off +
                                             ((size_t)a * nchp + b) * nchp + c];
-                                t.o3w[((((((size_t)z * P + p) * nch2 + a) * NT + ct) * 64 + l) *
-                                       NJP) + j] = v;
+                                t.o3ww[((((((size_t)z * P + p) * nch2 + a) * NT + ct) * 64 + l) *
+                                        NJP) + j] = v;
                             }
+        t.o3_wide_ready = true;
+    }
+    if (kind == 2) {
         t.o3sw.assign(P * 16, 1.0);
     } else {
     // weight fragments (and FP8 column scales)
@@ -775,6 +782,7 @@ static std::vector<char> pack(const HostTables &t, DevModel &m)
     append_raw(blob, m.o3mt, t.o3mt);
     append_raw(blob, m.o3base, t.o3base);
     append<float>(blob, m.o3w, t.o3w);
+    append<float>(blob, m.o3ww, t.o3ww);
     append<float>(blob, m.o3sw, t.o3sw);
     append_raw(blob, m.o3order, t.o3order);
     append_raw(blob, m.o3wbeg, t.o3wbeg);
@@ -1087,9 +1095,13 @@ try {
         c.basis_chunks = std::max(-1, std::min(1, std::atoi(e)));
     if (const char *e = std::getenv("MLMIX_BASIS_MFMA"))
         c.basis_mfma = std::atoi(e) ? 1 : 0;  // VALU kernels (comparisons)
-    if (const char *e = std::getenv("MLMIX_ACE_O3"))
-        if (!std::atoi(e))
+    if (const char *e = std::getenv("MLMIX_ACE_O3")) {
+        const int v = std::atoi(e);
+        if (!v)
             c.o3 = 0;  // general block kernel (comparisons)
+        else if (v == 2 && c.o3 == 1 && c.qmode == 0 && t.o3_wide_ready)
+            c.o3 = 2;  // the wide form for a single-species model (comparisons)
+    }
     {
         int lim = 0;
         if (hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, c.device) ==

@@ -88,31 +88,37 @@ __device__ __forceinline__ int block_excl_scan(int v, int *sh, int &total)
 constexpr int kPer = kScanTile / 256;
 
 // ------------------------------------------------------ rebuild decision
-
-__global__ void k_prepare(int *hdr, int force)
-{
-    if (threadIdx.x == 0 && blockIdx.x == 0)
-        hdr[H_REBUILD] = (force || hdr[H_BUILT] == 0) ? 1 : 0;
-}
+//
+// Without a forced rebuild, k_displacement raises H_MOVED when an atom moved
+// more than half the skin since the last build; the binning kernel (every
+// workgroup, from words no kernel writes meanwhile) decides rebuild = forced
+// or never built or moved, and its first workgroup publishes the decision in
+// H_REBUILD for the later kernels; the row kernel's first workgroup clears
+// H_MOVED for the next call and marks the list built.
 
 __global__ void __launch_bounds__(256) k_displacement(const double *__restrict__ pos,
                                                       const double *__restrict__ ref, int n,
-                                                      double thr2, int *hdr)
+                                                      Box b0, double thr2, int *hdr, Seg sg)
 {
 #pragma clang fp contract(off)
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n)
         return;
-    // positions in periodic dimensions may have wrapped: fold the difference
+    // positions in periodic dimensions wrap when an atom crosses a face: the
+    // difference is folded to the minimum image (a crossing is no motion;
+    // the rows hold atom indices, and every pair distance is folded anyway)
+    const Box b = seg_box(b0, sg, i);
     double d2 = 0.0;
     for (int k = 0; k < 3; ++k) {
         double d = pos[k * n + i] - ref[k * n + i];
+        if (b.per[k]) {
+            const double h = 0.5 * b.L[k];
+            d = d > h ? d - b.L[k] : (d < -h ? d + b.L[k] : d);
+        }
         d2 = d2 + d * d;
     }
-    // a wrapped atom shows a displacement of about L, which also (and
-    // harmlessly) triggers a rebuild
     if (!(d2 <= thr2))
-        hdr[H_REBUILD] = 1;
+        hdr[H_MOVED] = 1;
 }
 
 // ------------------------------------------------ lambda, cell lists
@@ -271,14 +277,11 @@ __global__ void __launch_bounds__(256) k_bin_bucket(const double *__restrict__ p
     }
     if (i < n)
         atom_lambda(pos, n, b, i, ra, hdr, sg);
-    const int rebuild = force ? 1 : hdr[H_REBUILD];
+    const int rebuild = (force || hdr[H_BUILT] == 0 || hdr[H_MOVED] != 0) ? 1 : 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        hdr[H_REBUILD] = rebuild;
     if (!rebuild)
         return;  // uniform
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        if (force)
-            hdr[H_REBUILD] = 1;
-        hdr[H_BUILT] = 1;
-    }
     if (i >= n)
         return;
     double x[3];
@@ -396,7 +399,13 @@ __global__ void __launch_bounds__(256) k_neighbors(const double *__restrict__ po
                                                    const uint8_t *__restrict__ cand, Seg sg)
 {
 #pragma clang fp contract(off)
-    if (hdr[H_REBUILD] == 0)
+    const int rebuild = hdr[H_REBUILD];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        hdr[H_MOVED] = 0;  // for the next call's displacement check
+        if (rebuild)
+            hdr[H_BUILT] = 1;
+    }
+    if (rebuild == 0)
         return;
     __shared__ int rows[4][kMaxCap];
     __shared__ int lists[4][kNbrList];
@@ -633,18 +642,12 @@ void launch_neighbors(hipStream_t s, void *ws, const WsLayout &L, const Box &b, 
     int *hdr = at<int>(ws, L.hdr);
     const Grid &g = L.grid;
     const int n = L.n;
-    if (!force_rebuild) {
-        k_prepare<<<1, 64, 0, s>>>(hdr, 0);
-        if (n > 0) {
-            double thr = 0.5 * skin;
-            k_displacement<<<(n + 255) / 256, 256, 0, s>>>(pos, at<double>(ws, L.ref_pos), n,
-                                                           thr * thr, hdr);
-        }
-    }
-    if (n == 0) {
-        if (force_rebuild)
-            k_prepare<<<1, 64, 0, s>>>(hdr, 1);
+    if (n == 0)
         return;
+    if (!force_rebuild) {
+        double thr = 0.5 * skin;
+        k_displacement<<<(n + 255) / 256, 256, 0, s>>>(pos, at<double>(ws, L.ref_pos), n, b,
+                                                       thr * thr, hdr, seg_args(ws, L));
     }
     int *count = at<int>(ws, L.cell_count);
     RegionArgs r = ra;

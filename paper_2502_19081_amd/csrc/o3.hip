@@ -634,7 +634,7 @@ void launch_ace_o3w(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L,
     a.e = reinterpret_cast<const int *>(base + m.o3o);
     a.mt = reinterpret_cast<const int *>(base + m.o3mt);
     a.base = reinterpret_cast<const int *>(base + m.o3base);
-    a.w = reinterpret_cast<const float *>(base + m.o3w);
+    a.w = reinterpret_cast<const float *>(base + m.o3ww);
     a.order = reinterpret_cast<const int *>(base + m.o3order);
     a.wbeg = reinterpret_cast<const int *>(base + m.o3wbeg);
     a.dp_off = reinterpret_cast<const int *>(base + m.dpoff);
