@@ -75,9 +75,10 @@ def parse():
     ap.add_argument("--dominant", default=None,
                     help="take this stage as the dominant one instead of the largest in the "
                          "breakdown (for profiler runs)")
-    ap.add_argument("--keep-list", action="store_true",
-                    help="time the mixed step with the neighbour list kept while no atom has "
-                         "moved half the skin (as phase 6 does) in phases 1-3 (for profiler runs)")
+    ap.add_argument("--rebuild-every-step", action="store_true",
+                    help="rebuild the neighbour list in every step of the timed runs instead of "
+                         "keeping it while no atom has moved half the skin (the list policy of "
+                         "the method; the other policy is timed too and reported beside it)")
     ap.add_argument("--single-stream", action="store_true",
                     help="keep every stage on the caller's stream (no fork of the cheap potential)")
     ap.add_argument("--fit", action="store_true",
@@ -523,6 +524,7 @@ def main():
                 g.replay()
         model.profile_read()
         model.profile_enable(stage_mask)
+        builds0 = sy.list_builds()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         lat = []
@@ -540,12 +542,15 @@ def main():
         model.profile_enable(0)
         prof = model.profile_read()
         sy.status()
+        run.builds = sy.list_builds() - builds0  # list builds inside the timed region
         return (t1 - t0), prof, lat, sy
 
     # 1. per-stage breakdown (every stage bracketed) to find the dominant kernel
-    main_rebuild = not args.keep_list
-    _, prof_all, _, _ = run(B.MODE_MIXED, max(10, args.steps // 4), args.warmup,
+    main_rebuild = args.rebuild_every_step
+    n_break = max(10, args.steps // 4)
+    _, prof_all, _, _ = run(B.MODE_MIXED, n_break, args.warmup,
                                stage_mask=(1 << B.N_STAGES) - 1, rebuild=main_rebuild)
+    build_frac = run.builds / n_break  # list builds per step in the breakdown
     stage_ms = {k: v[0] / max(v[1], 1) for k, v in prof_all.items() if v[1]}
     # with the second stream, the reverse slots and the cheap potential run
     # beside the expensive chain under a workgroup cap (their event times
@@ -594,6 +599,7 @@ def main():
 
     # 3. timed region: K mixed steps replayed from one captured HIP graph
     el, _, _, _ = run(B.MODE_MIXED, args.steps, args.warmup, graph=True, rebuild=main_rebuild)
+    timed_builds = run.builds
     ms_step = 1e3 * el / args.steps
     value = n * args.steps / el
 
@@ -602,24 +608,30 @@ def main():
     # 4. all-expensive and all-cheap rates on the same GPU, same method
     rate_e = rate_c = None
     lat_ms = None
-    rate_skin = None
+    rate_other = None
+    other_builds = None
     if not args.only_mixed:
-        el_e, _, _, _ = run(B.MODE_ALL_EXPENSIVE, args.steps, args.warmup, graph=True)
-        el_c, _, _, _ = run(B.MODE_ALL_CHEAP, args.steps, args.warmup, graph=True)
+        el_e, _, _, _ = run(B.MODE_ALL_EXPENSIVE, args.steps, args.warmup, graph=True,
+                            rebuild=main_rebuild)
+        el_c, _, _, _ = run(B.MODE_ALL_CHEAP, args.steps, args.warmup, graph=True,
+                            rebuild=main_rebuild)
         rate_e = n * args.steps / el_e
         rate_c = n * args.steps / el_c
         print(f"bench: all-expensive {1e3 * el_e / args.steps:.4f} ms/step, all-cheap "
               f"{1e3 * el_c / args.steps:.4f} ms/step", file=sys.stderr, flush=True)
 
         # 5. step latency (each replay waited for)
-        _, _, lat, _ = run(B.MODE_MIXED, args.steps, 5, latency=True, graph=True)
+        _, _, lat, _ = run(B.MODE_MIXED, args.steps, 5, latency=True, graph=True,
+                           rebuild=main_rebuild)
         lat_ms = np.array(lat) * 1e3
-        # 6. the same mixed steps with the neighbour list kept while no atom
-        # has moved half the skin (the MD engine's usual check; lambda, the
-        # buffer and both potentials are still evaluated every step)
-        el_s, _, _, sy_s = run(B.MODE_MIXED, args.steps, args.warmup, graph=True, rebuild=False)
-        rate_skin = n * args.steps / el_s
-        print(f"bench: mixed with skin reuse {1e3 * el_s / args.steps:.4f} ms/step",
+        # 6. the same mixed steps under the other list policy (rebuilt every
+        # step, or kept while no atom has moved half the skin; lambda, the
+        # buffer and both potentials are evaluated every step either way)
+        el_s, _, _, sy_s = run(B.MODE_MIXED, args.steps, args.warmup, graph=True,
+                               rebuild=not main_rebuild)
+        rate_other = n * args.steps / el_s
+        other_builds = run.builds
+        print(f"bench: mixed with the other list policy {1e3 * el_s / args.steps:.4f} ms/step",
               file=sys.stderr, flush=True)
 
     # work counts of the initial configuration (for the roofline)
@@ -653,7 +665,11 @@ def main():
         "ace_pairgrad": ("flops", fl[2] * pc["exp_pairs"]),
         "uf3": ("flops", fl[3] * pc["cheap_pairs"] + fl[4] * pc["cheap_triplets"]),
         # HBM bytes per launch
-        "neighbours": ("bytes", 24 * n + 8 * pc["list_pairs"] + 8 * n),
+        # per step: the displacement check (48 B per atom) unless every step
+        # rebuilds, and a build's 24 B per atom + 8 B per list entry + 8 B per
+        # atom in the fraction of steps that rebuilt
+        "neighbours": ("bytes", build_frac * (24 * n + 8 * pc["list_pairs"] + 8 * n)
+                       + (0 if main_rebuild else 48 * n)),
         "regions": ("bytes", 33 * n),
         "compaction": ("bytes", 9 * n + 4 * nS),
         "gather_blend": ("bytes", 44 * n + 8 * pc["list_pairs"] + 2 * 3 * tsz * pc["list_pairs"]
@@ -786,8 +802,11 @@ def main():
                    "thermostat": ("Langevin 300 K, 2 ps, lambda == 0 atoms" if args.langevin
                                   else "none (NVE)"),
                    "precision": prec,
-                   "neighbour_rebuild": ("kept while no atom moved half the skin"
-                                         if args.keep_list else "every step"), "n_S": nS, "n_lambda_pos": nM,
+                   "neighbour_rebuild": ("every step" if main_rebuild else
+                                         "when an atom has moved more than half the 1 A skin "
+                                         "since the last build (checked on the device every "
+                                         "step)"),
+                   "list_builds_in_timed_steps": timed_builds, "n_S": nS, "n_lambda_pos": nM,
                    "launch": (f"{args.graph_steps} consecutive steps per captured HIP graph "
                               f"({'one step per call' if args.langevin else 'one fused multi-step call'}), "
                               "replayed" if args.steps % args.graph_steps == 0 and args.graph_steps > 1
@@ -796,7 +815,9 @@ def main():
         "all_expensive_atom_steps_per_s": rate_e,
         "all_cheap_atom_steps_per_s": rate_c,
         "mixed_over_all_expensive": value / rate_e if rate_e else None,
-        "skin_reuse_atom_steps_per_s": rate_skin,
+        ("rebuild_every_step_atom_steps_per_s" if not main_rebuild
+         else "skin_list_atom_steps_per_s"): rate_other,
+        "other_policy_list_builds": other_builds,
         "S_UL": s_ul,
         "force_err_max_eV_per_A": ferr,
         "p50_step_ms": float(np.percentile(lat_ms, 50)) if lat_ms is not None else None,

@@ -424,6 +424,11 @@ int mlmix_batch_status(mlmix_ctx *ctx, void *stream, void *ws, int32_t *segment_
 int mlmix_status(mlmix_ctx *ctx, void *stream, void *ws, int32_t *status_bits,
                  int32_t *required_cap);
 
+/* Waits for `stream`, then *builds [host] receives the number of neighbour-
+ * list builds on the workspace since mlmix_workspace_init / mlmix_batch_init
+ * (forced or triggered by the skin check). */
+int mlmix_list_builds(mlmix_ctx *ctx, void *stream, void *ws, int32_t *builds);
+
 /* Test hooks (device -> device copies, enqueued on stream): the neighbour
  * rows (int32[n][nbr_cap], ascending j, unused slots -1) and counts, and
  * the compacted index sets S and M (ascending, int32[n] each, valid up to

@@ -104,6 +104,7 @@ SIGNATURES = {
                                             _vp]),
     "mlmix_batch_status": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.POINTER(_i32)]),
     "mlmix_status": (ctypes.c_int, [_vp, _vp, _vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
+    "mlmix_list_builds": (ctypes.c_int, [_vp, _vp, _vp, ctypes.POINTER(_i32)]),
     "mlmix_get_neighbors": (ctypes.c_int, [_vp, _vp, _vp, _i32, _vp, _vp]),
     "mlmix_get_index_sets": (ctypes.c_int, [_vp, _vp, _vp, _i32, _vp, _vp]),
     "mlmix_model_flops": (ctypes.c_int, [_vp, _vp]),

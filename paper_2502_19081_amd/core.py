@@ -255,6 +255,13 @@ class System:
             B.check(rc)
         return int(bits.value), int(req.value), rc
 
+    def list_builds(self):
+        """Neighbour-list builds since the workspace was set up."""
+        b = ctypes.c_int32()
+        B.check(B.lib().mlmix_list_builds(self.model.handle, _stream(), _p(self.ws),
+                                          ctypes.byref(b)))
+        return int(b.value)
+
     def neighbors(self):
         nbr = torch.empty(self.n, self.cap, dtype=torch.int32, device=self.device)
         cnt = torch.empty(self.n, dtype=torch.int32, device=self.device)

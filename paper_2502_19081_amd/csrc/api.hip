@@ -365,7 +365,7 @@ struct HostTables {
 // species: for lane (c = l % 16, q = l / 16), channel tile ct and a, the
 // NJ = nchp / 4 values W[a][b = NJ q + j][c = 16 ct + c], j < NJ, padded to a
 // multiple of four, stored [species][block][a][ct][lane][NJ padded].
-static void build_o3(const mlmix_model_desc &d, HostTables &t)
+static void build_o3(const mlmix_model_desc &d, HostTables &t, int waves)
 {
     const int nch = d.n_species * d.ace_n_rad, lmax = d.ace_lmax;
     const int nchp = (nch + 3) & ~3;
@@ -461,7 +461,12 @@ static void build_o3(const mlmix_model_desc &d, HostTables &t)
         for (int i = 0; i < nch2; ++i)
             for (int l = 0; l < 64; ++l)
                 for (int j = 0; j < 4; ++j) {
-                    int c = l & 15, q = l >> 4, a = i, b = 4 * q + j;
+                    // FP32: lane q holds b = (nch2 / 4) q + j, j < nch2 / 4
+                    // (K over exactly the nch2^2 pairs); BF16 / FP8 (32-deep
+                    // K steps): b = 4 q + j
+                    const int c = l & 15, q = l >> 4, a = i;
+                    const int njk = reduced ? 4 : nch2 / 4;
+                    const int b = j < njk ? njk * q + j : nch2;  // j >= njk: zero
                     double v = 0.0;
                     if (a < nch && b < nch && c < nch) {
                         v = t.W[t.pb[p].w_off + ((size_t)a * nchp + b) * nchp + c];
@@ -486,7 +491,9 @@ static void build_o3(const mlmix_model_desc &d, HostTables &t)
     t.o3order.clear();
     t.o3wbeg.clear();
     for (int G = 1; G <= kO3MaxSplit; G <<= 1) {
-        const int nb = 4 * G;
+        // bins: the waves of the G workgroups sharing a tile (the wide form
+        // always has four waves per workgroup)
+        const int nb = (kind == 1 ? waves : 4) * G;
         // one workgroup per tile (large S): whole blocks (measured faster)
         const long cap = G == 1 ? total : std::max<long>(1, total / nb / 2);
         std::vector<std::pair<long, int>> items;  // (cost, code)
@@ -615,7 +622,7 @@ static std::vector<double> bspline_span_poly(int npts)
     return out;
 }
 
-static int build_tables(const mlmix_model_desc &d, HostTables &t)
+static int build_tables(const mlmix_model_desc &d, HostTables &t, int o3_waves)
 {
     const int ns = d.n_species, nr = d.ace_n_rad, lmax = d.ace_lmax;
     const int L1 = lmax + 1, L2 = L1 * L1, nch = ns * nr, K3 = nch * L1;
@@ -700,7 +707,7 @@ static int build_tables(const mlmix_model_desc &d, HostTables &t)
                 mx = std::max(mx, std::fabs(t.W[t.pb[p].w_off + (size_t)k * nchp + c]));
             t.wsc[p * nchp + c] = mx > 0.0 ? mx / 240.0 : 0.0;
         }
-    build_o3(d, t);
+    build_o3(d, t, o3_waves);
     // cheap model
     int nb2 = d.uf3_n_knots2 + 2;
     t.up2 = bspline_span_poly(d.uf3_n_knots2);
@@ -1008,7 +1015,10 @@ try {
             return rc_s;
     }
     HostTables t;
-    int rc = build_tables(d, t);
+    // waves per workgroup of the single-species order-3 kernel (tuning)
+    if (const char *e = std::getenv("MLMIX_O3_WAVES"))
+        c.o3_waves = std::atoi(e) == 8 ? 8 : 4;
+    int rc = build_tables(d, t, c.o3_waves);
     if (rc != MLMIX_OK)
         return rc;
     DevModel &m = c.m;
@@ -2009,6 +2019,26 @@ try {
         return fail(MLMIX_E_ARG, "species index outside [0, n_species)");
     if (st & MLMIX_STATUS_OUT_OF_BOX)
         return fail(MLMIX_E_BOX, "atom outside a non-periodic box dimension");
+    return MLMIX_OK;
+} catch (...) {
+    return host_exception();
+}
+
+extern "C" int mlmix_list_builds(mlmix_ctx *ctx, void *stream, void *ws, int32_t *builds)
+try {
+    if (!ctx || !ws || !builds)
+        return fail(MLMIX_E_ARG, "NULL argument");
+    WsLayout L;
+    {
+        std::lock_guard<std::mutex> g(ctx->mu);
+        auto it = ctx->ws.find(ws);
+        if (it == ctx->ws.end())
+            return fail(MLMIX_E_STATE, "workspace was not initialised");
+        L = it->second;
+    }
+    HIP_OK(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
+    HIP_OK(hipMemcpy(builds, at<int>(ws, L.hdr) + H_NBUILD, sizeof(int32_t),
+                     hipMemcpyDeviceToHost));
     return MLMIX_OK;
 } catch (...) {
     return host_exception();

@@ -402,8 +402,10 @@ __global__ void __launch_bounds__(256) k_neighbors(const double *__restrict__ po
     const int rebuild = hdr[H_REBUILD];
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         hdr[H_MOVED] = 0;  // for the next call's displacement check
-        if (rebuild)
+        if (rebuild) {
             hdr[H_BUILT] = 1;
+            hdr[H_NBUILD] += 1;
+        }
     }
     if (rebuild == 0)
         return;

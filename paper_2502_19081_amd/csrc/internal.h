@@ -29,6 +29,7 @@ enum HeaderWord {
     H_NM = 5,         // |{lambda > 0}|
     H_FWD = 6,        // a forward pass with dE/dA exists
     H_MOVED = 7,      // an atom moved more than half the skin since the last build
+    H_NBUILD = 8,     // neighbour-list builds since the workspace was initialised
     H_COUNT = 64
 };
 
@@ -172,6 +173,7 @@ struct Ctx {
     // largest tile split of that kernel: 4 measured best on the 8,193-atom
     // cell (910 atoms in S: contraction 92 / 52 / 37 / 48 us at 1 / 2 / 4 / 8)
     int o3_max_split = 4;
+    int o3_waves = 4;      // waves per workgroup of the single-species form (4 or 8)
     int ace_tile = 4;      // atoms per order-3 block workgroup (tuning)
     int ace_stage_w = 1;   // stage the block's weights in LDS (tuning)
     int device;

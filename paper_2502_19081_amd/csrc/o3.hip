@@ -11,14 +11,17 @@
 //  sparse stage  P_t[a][b] = sum_e g_e A_t[l1 m1_e][a] A_t[l2 m2_e][b] for
 //                each atom t, as a 16x16 MFMA product whose K runs over the
 //                (m1, m2) entries of the row (four per step; padded entries
-//                have g = 0). The wave writes P_t into its own LDS rows in
-//                the layout [b / 4][a][b % 4] (a stride: the channels rounded up to a
-//                multiple of four), which makes
-//                the lanes' 16-byte writes and the dense stage's reads free
-//                of bank conflicts.
+//                have g = 0). The wave writes P_t into its own LDS rows:
+//                with BF16 / FP8 operands in the layout [b / 4][a][b % 4]
+//                (a stride: the channels rounded up to a multiple of four),
+//                which makes the lanes' writes and the dense stage's reads
+//                free of bank conflicts; with FP32 operands (kept in
+//                registers first) eight channels a at a time as [a][b].
 //  dense stage   D[t][c] = sum_{a,b} P_t[a][b] W[a][b][c] as 16x16 MFMA
 //                steps with the block's weights held in registers (one
-//                fragment per lane, loaded once per block).
+//                fragment per lane, loaded once per block); with FP32
+//                operands the K steps run over exactly the nch^2 pairs
+//                (a, b) (lane q holds b = (nch / 4) q + j).
 //
 // When S holds few tiles, the block lists of one tile are split over G = 2,
 // 4 or 8 workgroups (chosen on the device from the size of S, so that the
@@ -66,10 +69,10 @@ constexpr int kO3Atoms = 16;
 constexpr int kO3MaxGroups = 8;  // entries of one (block, m3) row: at most 4 x 8
 
 // bytes of one P row per format (16-byte pad keeps rows 4 banks apart); the
-// FP32 rows hold half of the channels a at a time (at most 8)
+// FP32 rows hold eight channels a at a time, each with its nc values of b
 __host__ __device__ constexpr int o3_row_bytes(int qm, int nc)
 {
-    return qm == 0 ? 4 * (nc < 8 ? nc : 8) * 16 + 16 : 4 * nc * 4 * (qm == 1 ? 2 : 1) + 16;
+    return qm == 0 ? 4 * (nc < 8 ? nc : 8) * nc + 16 : 4 * nc * 4 * (qm == 1 ? 2 : 1) + 16;
 }
 
 __device__ __forceinline__ void wave_sync_lds()
@@ -171,11 +174,12 @@ __device__ __forceinline__ void o3_sparse(const float *__restrict__ At, int L2, 
     }
 }
 
-template <int QM, int NC>
-__global__ void __launch_bounds__(256, 1)
+template <int QM, int NC, int NW>  // NW waves per workgroup (4 or 8)
+__global__ void __launch_bounds__(64 * NW, 1)
     k_ace_o3(const int *__restrict__ hdr, O3Args a, const float *__restrict__ A,
              float *__restrict__ Dpart)
 {
+    constexpr int NTH = 64 * NW;
     const int nS = hdr[H_NS];
     const int ntile = (nS + kO3Atoms - 1) / kO3Atoms;
     int G = 1, lg = 0;
@@ -195,20 +199,21 @@ __global__ void __launch_bounds__(256, 1)
     float *At = reinterpret_cast<float *>(smem_raw);  // [16][L2][16]
     char *Pw = smem_raw + (size_t)kO3Atoms * L2 * 16 * sizeof(float) + (size_t)wv * kO3Atoms * rowb;
     float *sPall = reinterpret_cast<float *>(smem_raw + (size_t)kO3Atoms * L2 * 16 * sizeof(float) +
-                                             (size_t)4 * kO3Atoms * rowb);
+                                             (size_t)NW * kO3Atoms * rowb);
     float *sP = sPall + wv * kO3Atoms;
-    float *amax = sPall + 4 * kO3Atoms;  // [16][L1]: max |A| per atom and l (FP8)
+    float *amax = sPall + NW * kO3Atoms;  // [16][L1]: max |A| per atom and l (FP8)
     const int *order = a.order;
-    const int *wbeg = a.wbeg + 4 * (G - 1) + lg;
+    // bin offsets of the split G: the tables of G' = 1, 2, .. G / 2 come first
+    const int *wbeg = a.wbeg + NW * (G - 1) + lg;
 
     for (int item = blockIdx.x; item < nitem; item += gridDim.x) {
-        const int tile = item >> lg, bin = ((item & (G - 1)) << 2) + wv;
+        const int tile = item >> lg, bin = (item & (G - 1)) * NW + wv;
         const int w_lo = wbeg[bin], w_hi = wbeg[bin + 1];
         const int s0 = tile * kO3Atoms;
         const int na = min(kO3Atoms, nS - s0);
         __syncthreads();  // every wave is done with the previous tile's A
         // stage the tile's A rows (NC channels in HBM, 16 in LDS, zero padded)
-        for (int r = tid; r < kO3Atoms * L2; r += 256) {
+        for (int r = tid; r < kO3Atoms * L2; r += NTH) {
             const int t = r / L2, lm = r - t * L2;
             f4v *dst = reinterpret_cast<f4v *>(At + (size_t)r * 16);
             const f4v *src = reinterpret_cast<const f4v *>(A + (size_t)(s0 + t) * a.KAt + lm * NC);
@@ -282,9 +287,8 @@ __global__ void __launch_bounds__(256, 1)
                 f4v acc = {0.f, 0.f, 0.f, 0.f};
                 const char *Prow = Pw + (size_t)m * rowb;
                 if constexpr (QM == 0) {
-                    // ---- sparse stage into registers, then dense stage in
-                    // halves of the channel range a (P rows [b / 4][a % HW][b % 4],
-                    // HW = min(NC, 8) channels per half)
+                    // ---- sparse stage into registers, then the dense stage
+                    // in passes of HW = min(NC, 8) channels a
                     f4v cc[kO3Atoms];
 #define O3_SPARSE(NGV) o3_sparse_regs<NGV>(At, L2, m, ent, cc)
                     switch (ng) {
@@ -299,25 +303,36 @@ __global__ void __launch_bounds__(256, 1)
                     default: O3_SPARSE(8); break;
                     }
 #undef O3_SPARSE
+                    // dense stage, eight channels a at a time: P rows
+                    // [a - a0][b] (b contiguous); lane (atom m, q) takes the
+                    // NJ = NC / 4 values b = NJ q + j, so K runs over exactly
+                    // NC^2 values (a, b), against weights W[a][NJ q + j][c = m]
+                    constexpr int NJ = NC / 4;
 #pragma unroll
                     for (int a0 = 0; a0 < NC; a0 += 8) {
                         constexpr int HW = NC < 8 ? NC : 8;
                         const int hw = NC - a0 < HW ? NC - a0 : HW;
-                        if (m >= a0 && m < a0 + hw)
+                        if (m >= a0 && m < a0 + hw && 4 * q < NC)
 #pragma unroll
                             for (int t = 0; t < kO3Atoms; ++t)
-                                *reinterpret_cast<f4v *>(Pw + (size_t)t * rowb + (q * HW + m - a0) * 16) = cc[t];
+                                *reinterpret_cast<f4v *>(Pw + (size_t)t * rowb +
+                                                         ((m - a0) * NC + 4 * q) * 4) = cc[t];
                         wave_sync_lds();
 #pragma unroll
                         for (int i = 0; i < HW; ++i)
                             if (i < hw) {
-                                const f4v pv = *reinterpret_cast<const f4v *>(Prow + (q * HW + i) * 16);
-                                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(pv[0], wf[a0 + i][0], acc, 0, 0, 0);
-                                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(pv[1], wf[a0 + i][1], acc, 0, 0, 0);
-                                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(pv[2], wf[a0 + i][2], acc, 0, 0, 0);
-                                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(pv[3], wf[a0 + i][3], acc, 0, 0, 0);
+                                const float *pr =
+                                    reinterpret_cast<const float *>(Prow) + i * NC + NJ * q;
+                                float pv[NJ];
+#pragma unroll
+                                for (int j = 0; j < NJ; ++j)
+                                    pv[j] = pr[j];
+#pragma unroll
+                                for (int j = 0; j < NJ; ++j)
+                                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(pv[j], wf[a0 + i][j],
+                                                                               acc, 0, 0, 0);
                             }
-                        wave_sync_lds();  // the next half overwrites the rows
+                        wave_sync_lds();  // the next pass overwrites the rows
                     }
                 } else {
                     const float gsum = QM == 2 ? a.gs[row] * (1.0f / 240.0f) : 0.0f;
@@ -676,9 +691,10 @@ void launch_ace_o3w(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L,
 size_t o3_lds_bytes(const Ctx &c)
 {
     const DevModel &m = c.m;
+    const int nw = c.o3_waves;
     return (size_t)kO3Atoms * m.L2 * 16 * sizeof(float) +
-           (size_t)4 * kO3Atoms * o3_row_bytes(c.qmode, m.nchp) +
-           (size_t)(4 * kO3Atoms + kO3Atoms * (m.lmax + 1)) * sizeof(float);
+           (size_t)nw * kO3Atoms * o3_row_bytes(c.qmode, m.nchp) +
+           (size_t)(nw * kO3Atoms + kO3Atoms * (m.lmax + 1)) * sizeof(float);
 }
 
 void launch_ace_o3(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L, hipEvent_t ev0,
@@ -715,11 +731,18 @@ void launch_ace_o3(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L, hip
     float *D = at<float>(ws, L.dpart);
     auto go = [&](auto qm, auto nc) {
         constexpr int QM = decltype(qm)::value, NC = decltype(nc)::value;
-        if (ev0)  // stage timing: events carry the kernel's own start and end
-            hipExtLaunchKernelGGL(k_ace_o3<QM, NC>, dim3(grid), dim3(256), (uint32_t)lds, s, ev0,
-                                  ev1, 0u, hdr, a, A, D);
+        auto launch = [&](auto nw) {
+            constexpr int NW = decltype(nw)::value;
+            if (ev0)  // stage timing: events carry the kernel's own start and end
+                hipExtLaunchKernelGGL(k_ace_o3<QM, NC, NW>, dim3(grid), dim3(64 * NW),
+                                      (uint32_t)lds, s, ev0, ev1, 0u, hdr, a, A, D);
+            else
+                k_ace_o3<QM, NC, NW><<<grid, 64 * NW, lds, s>>>(hdr, a, A, D);
+        };
+        if (c.o3_waves == 8)
+            launch(std::integral_constant<int, 8>());
         else
-            k_ace_o3<QM, NC><<<grid, 256, lds, s>>>(hdr, a, A, D);
+            launch(std::integral_constant<int, 4>());
     };
     auto by_width = [&](auto qm) {
         switch (m.nchp) {
