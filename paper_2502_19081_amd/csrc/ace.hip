@@ -66,7 +66,7 @@ constexpr int kMaxOwn = 16;  // (lm, channel) entries per lane: L2 * nchp <= 102
 
 // wpb atoms per block (one wavefront each). The neighbour-chunk loop runs to
 // the block's longest row so that the waves meet at every barrier.
-template <typename T>
+template <typename T, bool SEG>
 __global__ void __launch_bounds__(256)
     k_ace_basis(const double *__restrict__ pos, int n, Box b0, const int32_t *__restrict__ species,
                 int cap, const int *__restrict__ nbr, const int *__restrict__ cnt,
@@ -87,7 +87,7 @@ __global__ void __launch_bounds__(256)
     int *zt = reinterpret_cast<int *>(reinterpret_cast<T *>(smem_raw) + (size_t)wpb * slice) + w * 64;
     __shared__ int cm[4];
     const int i = valid ? S_idx[s] : 0;
-    const Box b = seg_box(b0, sg, i);
+    const Box b = seg_box<SEG, true>(b0, sg, i);
     const int c = valid ? cnt[i] : 0;
     if (lane == 0)
         cm[w] = c;
@@ -510,7 +510,7 @@ __global__ void __launch_bounds__(256)
     }
 }
 
-template <typename T>
+template <typename T, bool SEG>
 __global__ void __launch_bounds__(256)
     k_ace_pairgrad(const double *__restrict__ pos, int n, Box b0, const int32_t *__restrict__ species,
                    int cap, const int *__restrict__ nbr, const int *__restrict__ cnt,
@@ -527,7 +527,7 @@ __global__ void __launch_bounds__(256)
     extern __shared__ __align__(16) char smem_raw[];
     T *dAs = reinterpret_cast<T *>(smem_raw) + (size_t)w * a.KAt;
     const int i = S_idx[s];
-    const Box b = seg_box(b0, sg, i);
+    const Box b = seg_box<SEG, true>(b0, sg, i);
     T wgt = weights ? T(weights[i]) : T(1);
     for (int e = lane; e < a.KAt; e += 64)
         dAs[e] = dEdA[(size_t)s * a.KAt + e] * wgt;
@@ -726,7 +726,7 @@ __device__ __forceinline__ void wave_sync_ace()
 // large systems (1M atoms, lmax 5: 10.58 against 10.82 ms per step), where
 // the whole-row form below is slower; small systems take the whole-row form
 // (8,193 atoms: 132.7 against 135.4 us per step).
-template <int MT, int NT>
+template <int MT, int NT, bool SEG>
 __global__ void __launch_bounds__(256)
     k_ace_basis_mfma_chunks(const double *__restrict__ pos, int n, Box b0,
                      const int32_t *__restrict__ species, int cap, const int *__restrict__ nbr,
@@ -745,7 +745,7 @@ __global__ void __launch_bounds__(256)
     float *Yt = Rz + 64 * RW;
     const int m16 = lane & 15, kg = lane >> 4;
     const int i = S_idx[s];
-    const Box b = seg_box(b0, sg, i);
+    const Box b = seg_box<SEG, true>(b0, sg, i);
     const int c = cnt[i];
     const int *row = nbr + (size_t)i * cap;
     const int nrad = a.nrad, nch = a.nchan, L2 = a.L2;
@@ -850,7 +850,7 @@ __global__ void __launch_bounds__(256)
 // pairs, 64 per round; rows hold about 40 valid pairs, so one round). Row
 // strides are odd so that the row writes of the 64 lanes and the tile reads
 // are free of bank conflicts.
-template <int MT, int NT>
+template <int MT, int NT, bool SEG>
 __global__ void __launch_bounds__(256)
     k_ace_basis_mfma(const double *__restrict__ pos, int n, Box b0,
                      const int32_t *__restrict__ species, int cap, const int *__restrict__ nbr,
@@ -870,7 +870,7 @@ __global__ void __launch_bounds__(256)
     float *Yt = Rz + 64 * RW;
     const int m16 = lane & 15, kg = lane >> 4;
     const int i = S_idx[s];
-    const Box b = seg_box(b0, sg, i);
+    const Box b = seg_box<SEG, true>(b0, sg, i);
     const int c = cnt[i];
     const int *row = nbr + (size_t)i * cap;
     const int nrad = a.nrad, nch = a.nchan, L2 = a.L2;
@@ -953,7 +953,7 @@ __global__ void __launch_bounds__(256)
 // channels); each pair's lane then contracts its rows with the harmonics and
 // their gradients, g = rad u + (v - u (u.v)) / r with rad = sum S_D Y and
 // v = sum S_R grad_u Y, and writes g to its list slot (0 for other slots).
-template <int MT, int NT>
+template <int MT, int NT, bool SEG>
 __global__ void __launch_bounds__(256)
     k_ace_pairgrad_mfma(const double *__restrict__ pos, int n, Box b0,
                         const int32_t *__restrict__ species, int cap, const int *__restrict__ nbr,
@@ -977,7 +977,7 @@ __global__ void __launch_bounds__(256)
     PairGeo *geo = reinterpret_cast<PairGeo *>(Gt + 16 * MT * YW);  // [64]
     const int m16 = lane & 15, kg = lane >> 4;
     const int i = S_idx[s];
-    const Box b = seg_box(b0, sg, i);
+    const Box b = seg_box<SEG, true>(b0, sg, i);
     const float wgt = weights ? float(weights[i]) : 1.0f;
     const int nrad = a.nrad, nch = a.nchan, L2 = a.L2, nchp = a.nchp;
     for (int e = lane; e < 16 * MT * 16 * NT; e += 64) {
@@ -1126,7 +1126,9 @@ static void basis_mfma_launch(hipStream_t s, const Ctx &c, void *ws, const WsLay
     if (c.basis_chunks > 0 || (c.basis_chunks < 0 && L.n > 65536 && L.nseg == 0)) {
         const size_t per = (size_t)64 * (16 * MT + 1 + 16 * NT + 1) * sizeof(float);
         const int wpb = mfma_wpb(per);
-        k_ace_basis_mfma_chunks<MT, NT><<<(L.n + wpb - 1) / wpb, 64 * wpb, per * wpb, s>>>(
+        auto kern = L.nseg > 0 ? k_ace_basis_mfma_chunks<MT, NT, true>
+                               : k_ace_basis_mfma_chunks<MT, NT, false>;
+        kern<<<(L.n + wpb - 1) / wpb, 64 * wpb, per * wpb, s>>>(
             pos, L.n, b, species, L.cap, at<int>(ws, L.nbr), at<int>(ws, L.cnt),
             at<int>(ws, L.S_idx), at<int>(ws, L.S_local), at<int>(ws, L.hdr), a, wpb,
             at<float>(ws, L.A), seg_args(ws, L));
@@ -1134,7 +1136,8 @@ static void basis_mfma_launch(hipStream_t s, const Ctx &c, void *ws, const WsLay
     }
     const size_t per = basis_mfma_lds<MT, NT>();
     const int wpb = mfma_wpb(per);
-    k_ace_basis_mfma<MT, NT><<<(L.n + wpb - 1) / wpb, 64 * wpb, per * wpb, s>>>(
+    auto kern = L.nseg > 0 ? k_ace_basis_mfma<MT, NT, true> : k_ace_basis_mfma<MT, NT, false>;
+    kern<<<(L.n + wpb - 1) / wpb, 64 * wpb, per * wpb, s>>>(
         pos, L.n, b, species, L.cap, at<int>(ws, L.nbr), at<int>(ws, L.cnt), at<int>(ws, L.S_idx),
         at<int>(ws, L.S_local), at<int>(ws, L.hdr), a, wpb, at<float>(ws, L.A), seg_args(ws, L));
 }
@@ -1146,7 +1149,8 @@ static void pairgrad_mfma_launch(hipStream_t s, const Ctx &c, void *ws, const Ws
 {
     const size_t per = pairgrad_mfma_lds<MT, NT>();
     const int wpb = mfma_wpb(per);
-    k_ace_pairgrad_mfma<MT, NT><<<(L.n + wpb - 1) / wpb, 64 * wpb, per * wpb, s>>>(
+    auto kern = L.nseg > 0 ? k_ace_pairgrad_mfma<MT, NT, true> : k_ace_pairgrad_mfma<MT, NT, false>;
+    kern<<<(L.n + wpb - 1) / wpb, 64 * wpb, per * wpb, s>>>(
         pos, L.n, b, species, L.cap, at<int>(ws, L.nbr), at<int>(ws, L.cnt), at<int>(ws, L.S_idx),
         at<int>(ws, L.S_local), at<int>(ws, L.hdr), a, wpb, at<float>(ws, L.dEdA), weights,
         at<float>(ws, L.g), seg_args(ws, L));
@@ -1190,7 +1194,8 @@ static void basis_t(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L, co
     while (wpb > 1 && (size_t)wpb * 64 * ((a.nrad + a.L2) * sizeof(T) + sizeof(int)) > 48 * 1024)
         wpb >>= 1;
     size_t sm = (size_t)wpb * 64 * ((a.nrad + a.L2) * sizeof(T) + sizeof(int)) + 16;
-    k_ace_basis<T><<<(n + wpb - 1) / wpb, 64 * wpb, sm, s>>>(
+    auto kern = L.nseg > 0 ? k_ace_basis<T, true> : k_ace_basis<T, false>;
+    kern<<<(n + wpb - 1) / wpb, 64 * wpb, sm, s>>>(
         pos, n, b, species, L.cap, at<int>(ws, L.nbr), at<int>(ws, L.cnt), at<int>(ws, L.S_idx),
         at<int>(ws, L.S_local), at<int>(ws, L.hdr), a, wpb, at<T>(ws, L.A), seg_args(ws, L));
 }
@@ -1288,7 +1293,8 @@ static void pairgrad_t(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L,
     int n = L.n;
     const int wpb = 4;
     size_t sm = (size_t)wpb * a.KAt * sizeof(T) + 16;
-    k_ace_pairgrad<T><<<(n + wpb - 1) / wpb, 64 * wpb, sm, s>>>(
+    auto kern = L.nseg > 0 ? k_ace_pairgrad<T, true> : k_ace_pairgrad<T, false>;
+    kern<<<(n + wpb - 1) / wpb, 64 * wpb, sm, s>>>(
         pos, n, b, species, L.cap, at<int>(ws, L.nbr), at<int>(ws, L.cnt), at<int>(ws, L.S_idx),
         at<int>(ws, L.S_local), at<int>(ws, L.hdr), a, wpb, at<T>(ws, L.dEdA), weights,
         at<T>(ws, L.g), seg_args(ws, L));

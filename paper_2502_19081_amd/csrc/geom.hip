@@ -96,6 +96,7 @@ constexpr int kPer = kScanTile / 256;
 // H_REBUILD for the later kernels; the row kernel's first workgroup clears
 // H_MOVED for the next call and marks the list built.
 
+template <bool SEG>
 __global__ void __launch_bounds__(256) k_displacement(const double *__restrict__ pos,
                                                       const double *__restrict__ ref, int n,
                                                       Box b0, double thr2, int *hdr, Seg sg)
@@ -107,7 +108,7 @@ __global__ void __launch_bounds__(256) k_displacement(const double *__restrict__
     // positions in periodic dimensions wrap when an atom crosses a face: the
     // difference is folded to the minimum image (a crossing is no motion;
     // the rows hold atom indices, and every pair distance is folded anyway)
-    const Box b = seg_box(b0, sg, i);
+    const Box b = seg_box<SEG>(b0, sg, i);
     double d2 = 0.0;
     for (int k = 0; k < 3; ++k) {
         double d = pos[k * n + i] - ref[k * n + i];
@@ -140,13 +141,14 @@ __device__ __forceinline__ double blend_value(double t, int cubic)
 // (lambda == 0 but near some region). Seeded regions are applied by later
 // passes over the neighbour rows; here seed atoms (with any seeded region
 // present) are core atoms of all of them, and the seed bit of flags is kept.
+template <bool SEG>
 __device__ __forceinline__ void atom_lambda(const double *__restrict__ pos, int n, const Box &b,
                                             int i, const RegionArgs &ra, int *hdr, const Seg &sg)
 {
 #pragma clang fp contract(off)
     int z = ra.species[i];
     if (z < 0 || z >= ra.ns)
-        seg_status_or(&hdr[H_STATUS], sg, i, MLMIX_STATUS_BAD_SPECIES);
+        seg_status_or<SEG>(&hdr[H_STATUS], sg, i, MLMIX_STATUS_BAD_SPECIES);
     const uint8_t keep = ra.seeded ? (uint8_t)(ra.flags[i] & MLMIX_FLAG_SEED) : (uint8_t)0;
     if (ra.mode == MLMIX_MODE_ALL_EXPENSIVE) {
         ra.lam[i] = 1.0;
@@ -166,7 +168,7 @@ __device__ __forceinline__ void atom_lambda(const double *__restrict__ pos, int 
     double xi[3] = {pos[i], pos[n + i], pos[2 * n + i]};
     // a batched call: the atom's own system's regions, atom indices local to it
     int g0 = 0, g1 = ra.nreg, a0 = 0, na = n;
-    if (sg.of) {
+    if constexpr (SEG) {
         const SegGeo &G = sg.geo[sg.of[i]];
         g0 = G.reg0;
         g1 = G.reg0 + G.nreg;
@@ -252,6 +254,7 @@ __device__ __forceinline__ void atom_lambda(const double *__restrict__ pos, int 
 // flag (otherwise the flag comes from the displacement check before it) and,
 // whenever the list is rebuilt, marks the workspace as built. Order inside a
 // bucket follows the atomics; the rows are sorted afterwards.
+template <bool SEG>
 __global__ void __launch_bounds__(256) k_bin_bucket(const double *__restrict__ pos, int n, Box b0,
                                                     Grid g0, int force, int *hdr,
                                                     int *__restrict__ count,
@@ -268,15 +271,17 @@ __global__ void __launch_bounds__(256) k_bin_bucket(const double *__restrict__ p
     Grid g = g0;
     int cell0 = 0;
     size_t rec0 = 0;
-    if (sg.of && i < n) {
-        const SegGeo &G = sg.geo[sg.of[i]];
-        b = G.box;
-        g = G.grid;
-        cell0 = G.cell0;
-        rec0 = (size_t)G.rec0;
+    if constexpr (SEG) {
+        if (i < n) {
+            const SegGeo &G = sg.geo[sg.of[i]];
+            b = G.box;
+            g = G.grid;
+            cell0 = G.cell0;
+            rec0 = (size_t)G.rec0;
+        }
     }
     if (i < n)
-        atom_lambda(pos, n, b, i, ra, hdr, sg);
+        atom_lambda<SEG>(pos, n, b, i, ra, hdr, sg);
     const int rebuild = (force || hdr[H_BUILT] == 0 || hdr[H_MOVED] != 0) ? 1 : 0;
     if (blockIdx.x == 0 && threadIdx.x == 0)
         hdr[H_REBUILD] = rebuild;
@@ -296,9 +301,9 @@ __global__ void __launch_bounds__(256) k_bin_bucket(const double *__restrict__ p
         c[k] = cell_coord(x[k], g, k);
     }
     if (bad)
-        seg_status_or(&hdr[H_STATUS], sg, i, MLMIX_STATUS_NONFINITE);
+        seg_status_or<SEG>(&hdr[H_STATUS], sg, i, MLMIX_STATUS_NONFINITE);
     if (out)
-        seg_status_or(&hdr[H_STATUS], sg, i, MLMIX_STATUS_OUT_OF_BOX);
+        seg_status_or<SEG>(&hdr[H_STATUS], sg, i, MLMIX_STATUS_OUT_OF_BOX);
     const int cell = (c[2] * g.nc[1] + c[1]) * g.nc[0] + c[0];
     const int slot = atomicAdd(&count[cell0 + cell], 1);
     if (slot < g.bucket) {
@@ -310,7 +315,7 @@ __global__ void __launch_bounds__(256) k_bin_bucket(const double *__restrict__ p
         r.pad = 0;
         atoms[rec0 + (size_t)cell * g.bucket + slot] = r;
     } else {
-        seg_status_or(&hdr[H_STATUS], sg, i, MLMIX_STATUS_CELL_OVERFLOW);
+        seg_status_or<SEG>(&hdr[H_STATUS], sg, i, MLMIX_STATUS_CELL_OVERFLOW);
     }
 }
 
@@ -389,6 +394,7 @@ constexpr int kNbrList = 512;
 // first). Partners closer than the list radius are kept by ballot
 // compaction, and the row is finally sorted ascending in registers (bitonic
 // over 64, 128 or 256 keys).
+template <bool SEG>
 __global__ void __launch_bounds__(256) k_neighbors(const double *__restrict__ pos, int n, Box b0,
                                                    Grid g0, const int *__restrict__ count0,
                                                    const CellAtom *__restrict__ atoms0, double rl2,
@@ -421,8 +427,8 @@ __global__ void __launch_bounds__(256) k_neighbors(const double *__restrict__ po
     Grid g = g0;
     const int *count = count0;
     const CellAtom *atoms = atoms0;
-    if (sg.of) {
-        const SegGeo &G = sg.geo[sg.of[i]];
+    if constexpr (SEG) {
+        const SegGeo &G = sg.geo[__builtin_amdgcn_readfirstlane(sg.of[i])];
         b = G.box;
         g = G.grid;
         count = count0 + G.cell0;
@@ -566,7 +572,7 @@ __global__ void __launch_bounds__(256) k_neighbors(const double *__restrict__ po
         // same-address device atomics serialise across the whole grid: only
         // an overflowing row records its length
         if (c > cap) {
-            seg_status_or(&hdr[H_STATUS], sg, i, MLMIX_STATUS_NEIGH_OVERFLOW);
+            seg_status_or<SEG>(&hdr[H_STATUS], sg, i, MLMIX_STATUS_NEIGH_OVERFLOW);
             atomicMax(&hdr[H_REQCAP], c);
         }
     }
@@ -648,23 +654,37 @@ void launch_neighbors(hipStream_t s, void *ws, const WsLayout &L, const Box &b, 
         return;
     if (!force_rebuild) {
         double thr = 0.5 * skin;
-        k_displacement<<<(n + 255) / 256, 256, 0, s>>>(pos, at<double>(ws, L.ref_pos), n, b,
-                                                       thr * thr, hdr, seg_args(ws, L));
+        if (L.nseg > 0)
+            k_displacement<true><<<(n + 255) / 256, 256, 0, s>>>(
+                pos, at<double>(ws, L.ref_pos), n, b, thr * thr, hdr, seg_args(ws, L));
+        else
+            k_displacement<false><<<(n + 255) / 256, 256, 0, s>>>(
+                pos, at<double>(ws, L.ref_pos), n, b, thr * thr, hdr, seg_args(ws, L));
     }
     int *count = at<int>(ws, L.cell_count);
     RegionArgs r = ra;
     r.cand = at<uint8_t>(ws, L.cand);
     r.seedcore = at<uint8_t>(ws, L.seedcore);
     const Seg sg = seg_args(ws, L);
-    k_bin_bucket<<<(n + 255) / 256, 256, 0, s>>>(pos, n, b, g, force_rebuild, hdr, count,
-                                                 at<CellAtom>(ws, L.cell_atoms), r, sg);
+    if (L.nseg > 0)
+        k_bin_bucket<true><<<(n + 255) / 256, 256, 0, s>>>(pos, n, b, g, force_rebuild, hdr, count,
+                                                           at<CellAtom>(ws, L.cell_atoms), r, sg);
+    else
+        k_bin_bucket<false><<<(n + 255) / 256, 256, 0, s>>>(pos, n, b, g, force_rebuild, hdr, count,
+                                                            at<CellAtom>(ws, L.cell_atoms), r, sg);
     // (with seeded regions lambda is not final yet: the buffer pass follows them)
     const double rb2 =
         ra.mode == MLMIX_MODE_MIXED && !ra.seeded ? ra.r_buffer * ra.r_buffer : -1.0;
-    k_neighbors<<<(n + 3) / 4, 256, 0, s>>>(pos, n, b, g, count, at<CellAtom>(ws, L.cell_atoms),
-                                            r_list * r_list, L.cap, L.P, at<int>(ws, L.nbr),
-                                            at<int>(ws, L.cnt), at<double>(ws, L.ref_pos), hdr,
-                                            rb2, ra.flags, r.cand, sg);
+    if (L.nseg > 0)
+        k_neighbors<true><<<(n + 3) / 4, 256, 0, s>>>(pos, n, b, g, count, at<CellAtom>(ws, L.cell_atoms),
+                                                r_list * r_list, L.cap, L.P, at<int>(ws, L.nbr),
+                                                at<int>(ws, L.cnt), at<double>(ws, L.ref_pos), hdr,
+                                                rb2, ra.flags, r.cand, sg);
+    else
+        k_neighbors<false><<<(n + 3) / 4, 256, 0, s>>>(pos, n, b, g, count, at<CellAtom>(ws, L.cell_atoms),
+                                                r_list * r_list, L.cap, L.P, at<int>(ws, L.nbr),
+                                                at<int>(ws, L.cnt), at<double>(ws, L.ref_pos), hdr,
+                                                rb2, ra.flags, r.cand, sg);
 }
 
 // Reverse slots of a rebuilt list (skipped on the device when the list was
@@ -741,6 +761,7 @@ void launch_reverse(hipStream_t s, void *ws, const WsLayout &L, int side_blocks)
 // One wavefront per atom (lanes over row slots): an atom with lambda == 0
 // near a region joins the buffer when any neighbour with lambda > 0 lies
 // strictly inside r_buffer.
+template <bool SEG>
 __global__ void __launch_bounds__(256) k_buffer(const double *__restrict__ pos, int n, Box b0,
                                                 int cap, const int *__restrict__ nbr,
                                                 const int *__restrict__ cnt, double rb2,
@@ -751,7 +772,7 @@ __global__ void __launch_bounds__(256) k_buffer(const double *__restrict__ pos, 
     const int lane = threadIdx.x & 63;
     if (i >= n || !cand[i])
         return;
-    const Box b = seg_box(b0, sg, i);
+    const Box b = seg_box<SEG, true>(b0, sg, i);
     const int c = cnt[i];
     const int *row = nbr + (size_t)i * cap;
     bool hit = false;
@@ -877,6 +898,7 @@ __global__ void __launch_bounds__(256) k_seed_blend(const double *__restrict__ p
 // The cheap potential's buffer (MLMIX_CHEAP_MASKED): an atom with
 // lambda == 1 joins it (flags bit3) when a row partner with lambda < 1 lies
 // strictly inside r_buffer. One wavefront per atom; others return at once.
+template <bool SEG>
 __global__ void __launch_bounds__(256) k_cheap_buffer(const double *__restrict__ pos, int n, Box b0,
                                                       int cap, const int *__restrict__ nbr,
                                                       const int *__restrict__ cnt, double rb2,
@@ -886,7 +908,7 @@ __global__ void __launch_bounds__(256) k_cheap_buffer(const double *__restrict__
     const int lane = threadIdx.x & 63;
     if (i >= n || !(flags[i] & 2))
         return;
-    const Box b = seg_box(b0, sg, i);
+    const Box b = seg_box<SEG, true>(b0, sg, i);
     const int c = cnt[i];
     const int *row = nbr + (size_t)i * cap;
     bool hit = false;
@@ -908,9 +930,14 @@ void launch_cheap_buffer(hipStream_t s, void *ws, const WsLayout &L, const Box &
 {
     if (L.n == 0)
         return;
-    k_cheap_buffer<<<(L.n + 3) / 4, 256, 0, s>>>(pos, L.n, b, L.cap, at<int>(ws, L.nbr),
-                                                 at<int>(ws, L.cnt), r_buffer * r_buffer, flags,
-                                                 seg_args(ws, L));
+    if (L.nseg > 0)
+        k_cheap_buffer<true><<<(L.n + 3) / 4, 256, 0, s>>>(pos, L.n, b, L.cap, at<int>(ws, L.nbr),
+                                                           at<int>(ws, L.cnt), r_buffer * r_buffer,
+                                                           flags, seg_args(ws, L));
+    else
+        k_cheap_buffer<false><<<(L.n + 3) / 4, 256, 0, s>>>(pos, L.n, b, L.cap, at<int>(ws, L.nbr),
+                                                            at<int>(ws, L.cnt), r_buffer * r_buffer,
+                                                            flags, seg_args(ws, L));
 }
 
 // Region stage after the rows: the seeded passes (MLMIX_SEEDED), then the
@@ -937,10 +964,16 @@ void launch_regions(hipStream_t s, void *ws, const WsLayout &L, const Box &b, in
     if (n == 0 || (force_rebuild && !seeded))
         return;
     uint8_t *cand = at<uint8_t>(ws, L.cand);
-    if (mode == MLMIX_MODE_MIXED)
-        k_buffer<<<(n + 3) / 4, 256, 0, s>>>(pos, n, b, L.cap, at<int>(ws, L.nbr),
-                                                at<int>(ws, L.cnt), r_buffer * r_buffer, flags,
-                                                cand, seg_args(ws, L));
+    if (mode == MLMIX_MODE_MIXED) {
+        if (L.nseg > 0)
+            k_buffer<true><<<(n + 3) / 4, 256, 0, s>>>(pos, n, b, L.cap, at<int>(ws, L.nbr),
+                                                       at<int>(ws, L.cnt), r_buffer * r_buffer,
+                                                       flags, cand, seg_args(ws, L));
+        else
+            k_buffer<false><<<(n + 3) / 4, 256, 0, s>>>(pos, n, b, L.cap, at<int>(ws, L.nbr),
+                                                        at<int>(ws, L.cnt), r_buffer * r_buffer,
+                                                        flags, cand, seg_args(ws, L));
+    }
 }
 
 // ------------------------------------------------------------ compaction

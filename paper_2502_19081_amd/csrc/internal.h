@@ -73,18 +73,32 @@ struct Seg {
     int *status;
 };
 
-// Box of atom i (and of every partner in its rows).
+// Kernels that need an atom's box or grid take a template flag SEG: false
+// for a single system (no segment code at all, the box stays a kernel
+// argument), true for a batch.
+
+// Box of atom i (and of every partner in its rows). WAVE: i is the same on
+// every lane of the wave, so the segment index is read once (scalar).
+template <bool SEG, bool WAVE = false>
 __device__ __forceinline__ Box seg_box(const Box &b, const Seg &sg, int i)
 {
-    return sg.of ? sg.geo[sg.of[i]].box : b;
+    if constexpr (SEG) {
+        int k = sg.of[i];
+        if constexpr (WAVE)
+            k = __builtin_amdgcn_readfirstlane(k);
+        return sg.geo[k].box;
+    } else {
+        return b;
+    }
 }
 
 // Status bits of atom i's system: the workspace header, and in a batched
 // call also the atom's segment word.
+template <bool SEG>
 __device__ __forceinline__ void seg_status_or(int *hdr_status, const Seg &sg, int i, int bits)
 {
     atomicOr(hdr_status, bits);
-    if (sg.of)
+    if constexpr (SEG)
         atomicOr(&sg.status[sg.of[i]], bits);
 }
 

@@ -12,7 +12,7 @@
 
 namespace mlmix {
 
-template <typename T, bool KICK>
+template <typename T, bool KICK, bool SEG>
 __global__ void __launch_bounds__(256)
     k_gather_blend(int n, int cap, const int *__restrict__ nbr, const int *__restrict__ cnt,
                    const int *__restrict__ rev, const int *__restrict__ S_local,
@@ -105,7 +105,7 @@ __global__ void __launch_bounds__(256)
                         const double vn = fma(cf, F[q], v);
                         ka.vel[q * n + i] = vn;
                         double x = fma(ka.dt, vn, ka.pos[q * n + i]);
-                        const Box bx = seg_box(ka.box, sg, i);
+                        const Box bx = seg_box<SEG, true>(ka.box, sg, i);
                         if (bx.per[q]) {
                             x = x - bx.L[q] * floor(x / bx.L[q]);
                             if (x >= bx.L[q])
@@ -163,7 +163,7 @@ void launch_gather_blend(hipStream_t s, const Ctx &c, void *ws, const WsLayout &
         ka.part = L.nseg == 0 ? at<double>(ws, L.red) : nullptr;
     }
 #define MLMIX_GATHER(T, K)                                                                        \
-    k_gather_blend<T, K><<<nb, 256, 0, s>>>(n, L.cap, at<int>(ws, L.nbr), at<int>(ws, L.cnt),      \
+    (L.nseg > 0 ? k_gather_blend<T, K, true> : k_gather_blend<T, K, false>)<<<nb, 256, 0, s>>>(n, L.cap, at<int>(ws, L.nbr), at<int>(ws, L.cnt),      \
                                            at<int>(ws, L.rev), at<int>(ws, L.S_local),             \
                                            at<T>(ws, L.g), at<T>(ws, L.h), use_exp, use_cheap,     \
                                            lambda, forces, e_exp, f_exp, f_cheap, sign, ka, la, \
@@ -268,6 +268,7 @@ void launch_reduce(hipStream_t s, void *ws, const WsLayout &L, const double *e_e
 
 // -------------------------------------------------------- velocity Verlet
 
+template <bool SEG>
 __global__ void __launch_bounds__(256) k_vv(int n, Box b0, double *__restrict__ pos,
                                             double *__restrict__ vel,
                                             const double *__restrict__ mass,
@@ -277,7 +278,7 @@ __global__ void __launch_bounds__(256) k_vv(int n, Box b0, double *__restrict__ 
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n)
         return;
-    const Box b = seg_box(b0, sg, i);
+    const Box b = seg_box<SEG>(b0, sg, i);
     double c = 0.5 * dt * kKappa / mass[i];
     for (int k = 0; k < 3; ++k) {
         double v = fma(c, f[k * n + i], vel[k * n + i]);
@@ -356,8 +357,8 @@ void launch_vv_kick_drift(hipStream_t s, void *ws, const WsLayout &L, const Box 
 {
     if (L.n == 0)
         return;
-    k_vv<<<(L.n + 255) / 256, 256, 0, s>>>(L.n, b, pos, vel, mass, forces, dt, drift,
-                                           seg_args(ws, L));
+    (L.nseg > 0 ? k_vv<true> : k_vv<false>)<<<(L.n + 255) / 256, 256, 0, s>>>(
+        L.n, b, pos, vel, mass, forces, dt, drift, seg_args(ws, L));
 }
 
 // ------------------------------------------------------ batched systems

@@ -130,7 +130,7 @@ __host__ __device__ inline int uf3_c3_elems(int ns, int nb3)
 // dV3/dd_ij = V_1 u_ij - V_3 e / r_jk and dV3/dd_ik = V_2 u_ik + V_3 e / r_jk
 // (e = d_ik - d_ij) in LDS, and the lane of each leg adds the entries of its
 // pairs in a fixed order: no atomics, the same bits on every run.
-template <typename T, int U, bool LOOP>
+template <typename T, int U, bool LOOP, bool SEG>
 __global__ void __launch_bounds__(256)
     k_uf3(const double *__restrict__ pos, int n, Box b, const int32_t *__restrict__ species,
           int cap, const int *__restrict__ nbr, const int *__restrict__ cnt, Uf3Args<T> a,
@@ -171,7 +171,7 @@ __global__ void __launch_bounds__(256)
     // over groups (capped grids); no block barrier below
     auto atom = [&](const int i) {
         wave_sync_lds_u();
-        const Box bi = seg_box(b, sg, i);  // box of the atom's system
+        const Box bi = seg_box<SEG, true>(b, sg, i);  // box of the atom's system
         const int zi = sp_clamp(species[i], a.ns);
         const int c = cnt[i];
         const int *row = nbr + (size_t)i * cap;
@@ -253,7 +253,7 @@ __global__ void __launch_bounds__(256)
         wave_sync_lds_u();
         if (n3 > kMaxTriplet) {
             if (lane == 0)
-                seg_status_or(&hdr[H_STATUS], sg, i, MLMIX_STATUS_TRIPLET_OVERFLOW);
+                seg_status_or<SEG>(&hdr[H_STATUS], sg, i, MLMIX_STATUS_TRIPLET_OVERFLOW);
             n3 = kMaxTriplet;
         }
         if (nb > 0) {
@@ -432,9 +432,9 @@ static void uf3_t(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L, cons
     if (side_blocks > 0 && nblk > (unsigned)side_blocks)
         nblk = side_blocks;
 #define MLMIX_UF3_W(U, LOOP)                                                                     \
-    k_uf3<T, U, LOOP><<<nblk, 256, sm, s>>>(pos, L.n, b, species, L.cap, at<int>(ws, L.nbr),    \
-                                                at<int>(ws, L.cnt), a, at<T>(ws, L.h), e_cheap,     \
-                                                at<int>(ws, L.hdr), mask_flags, seg_args(ws, L))
+    (L.nseg > 0 ? k_uf3<T, U, LOOP, true> : k_uf3<T, U, LOOP, false>)<<<nblk, 256, sm, s>>>(     \
+        pos, L.n, b, species, L.cap, at<int>(ws, L.nbr), at<int>(ws, L.cnt), a, at<T>(ws, L.h),    \
+        e_cheap, at<int>(ws, L.hdr), mask_flags, seg_args(ws, L))
 #define MLMIX_UF3(U)                                                                             \
     if (nblk < (unsigned)((L.n + wpb - 1) / wpb))                                                 \
         MLMIX_UF3_W(U, true);                                                                     \
