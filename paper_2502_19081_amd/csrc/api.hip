@@ -1255,7 +1255,7 @@ static int compute_impl(mlmix_ctx *ctx, hipStream_t s, void *ws, const WsLayout 
                         double *e_exp, double *e_cheap, double *lambda, uint8_t *flags,
                         int32_t *n_expensive, double *f_exp, double *f_cheap,
                         const KickArgs *kick = nullptr, const LangevinArgs *lang = nullptr,
-                        double *red_out = nullptr)
+                        double *red_out = nullptr, bool disp_checked = false)
 {
     const Ctx &c = ctx->c;
     int m = (int)(mode & 0xff);
@@ -1281,12 +1281,13 @@ static int compute_impl(mlmix_ctx *ctx, hipStream_t s, void *ws, const WsLayout 
     }
     hipStream_t s2 = fork ? sd.s : s;  // stream of the reverse slots and the cheap potential
     // workgroup cap of those two kernels when they run beside the expensive
-    // chain (leave it room); on one stream or beside no expensive work they
-    // run uncapped
+    // chain (leave it room: one workgroup per compute unit measured best for
+    // systems of some thousand atoms); on one stream or beside no expensive
+    // work they run uncapped
     const int rev_blocks = c.rev_blocks;
     const int side_blocks = (!fork || m == MLMIX_MODE_ALL_CHEAP)
                                 ? 0
-                                : (c.side_blocks >= 0 ? c.side_blocks : (L.n < 262144 ? 512 : 0));
+                                : (c.side_blocks >= 0 ? c.side_blocks : (L.n < 262144 ? 256 : 0));
     {
         StageTimer t(ctx, s, ST_NBR);
         RegionArgs ra{m, species, c.m.ns, regions, n_regions, r_buffer, lambda, flags, nullptr,
@@ -1297,7 +1298,7 @@ static int compute_impl(mlmix_ctx *ctx, hipStream_t s, void *ws, const WsLayout 
             ra.red_out = red_out;
         }
         launch_neighbors(s, ws, L, b, c.r_list, pos, (mode & MLMIX_FORCE_REBUILD) ? 1 : 0,
-                         c.d.skin, ra);
+                         c.d.skin, ra, disp_checked);
     }
     // fork: reverse slots and the cheap potential need only the list; they are
     // started after the neighbour rows (fork_at 0) or after the atomic basis
@@ -1640,9 +1641,11 @@ try {
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (L.n == 0)
         return empty_outputs(s, n_expensive, energies, 1);
+    // the drift also does the skin check of the new positions
+    const DispCheck dc = disp_check_args(ws, L, ctx->c.d.skin);
     {
         StageTimer t(ctx, s, ST_VV);
-        launch_vv_kick_drift(s, ws, L, b, pos, vel, mass, forces, dt, 1);
+        launch_vv_kick_drift(s, ws, L, b, pos, vel, mass, forces, dt, 1, &dc);
     }
     // small systems: closing half kick and energy partials inside the gather
     const bool fused = energies && L.n > 0 && L.n <= kGatherKickMax;
@@ -1662,7 +1665,7 @@ try {
     }
     rc = compute_impl(ctx, s, ws, L, b, pos, species, regions, n_regions, r_buffer, mode, forces,
                       e_exp, e_cheap, lambda, flags, n_expensive, nullptr, nullptr,
-                      fused ? &ka : nullptr, ls.tau > 0.0 ? &la : nullptr);
+                      fused ? &ka : nullptr, ls.tau > 0.0 ? &la : nullptr, nullptr, true);
     if (rc)
         return rc;
     if (!fused && energies) {
@@ -1724,17 +1727,19 @@ try {
     // fused steps: the gather of step k also applies step k+1's opening half
     // kick and drift, and step k+1's binning kernel sums step k's energies
     hipStream_t s = static_cast<hipStream_t>(stream);
+    // every drift (the opening kernel's, then the gathers') does the skin check
+    const DispCheck dc = disp_check_args(ws, L, ctx->c.d.skin);
     {
         StageTimer t(ctx, s, ST_VV);
-        launch_vv_kick_drift(s, ws, L, b, pos, vel, mass, forces, dt, 1);
+        launch_vv_kick_drift(s, ws, L, b, pos, vel, mass, forces, dt, 1, &dc);
     }
     for (int k = 0; k < n_steps; ++k) {
         const bool last = k + 1 == n_steps;
         KickArgs ka{vel, mass, dt, e_cheap, nullptr, energies + 3 * (size_t)k,
-                    last ? 0 : 1, last ? 0 : 1, pos, b};
+                    last ? 0 : 1, last ? 0 : 1, pos, b, nullptr, dc};
         rc = compute_impl(ctx, s, ws, L, b, pos, species, regions, n_regions, r_buffer, mode,
                           forces, e_exp, e_cheap, lambda, flags, n_expensive, nullptr, nullptr,
-                          &ka, nullptr, k > 0 ? energies + 3 * (size_t)(k - 1) : nullptr);
+                          &ka, nullptr, k > 0 ? energies + 3 * (size_t)(k - 1) : nullptr, true);
         if (rc)
             return rc;
     }
@@ -1936,17 +1941,19 @@ try {
     hipStream_t s = static_cast<hipStream_t>(stream);
     const Box unused{};
     double *ke = at<double>(ws, L.seg_red);
+    const DispCheck dc = disp_check_args(ws, L, ctx->c.d.skin);
     {
         StageTimer t(ctx, s, ST_VV);
-        launch_vv_kick_drift(s, ws, L, unused, pos, vel, mass, forces, dt, 1);
+        launch_vv_kick_drift(s, ws, L, unused, pos, vel, mass, forces, dt, 1, &dc);
     }
     for (int k = 0; k < n_steps; ++k) {
         const bool last = k + 1 == n_steps;
         // the gather closes the step (half kick, per-atom kinetic energy) and,
         // before the next step, applies its opening half kick and drift
-        KickArgs ka{vel, mass, dt, e_cheap, nullptr, nullptr, last ? 0 : 1, 0, pos, unused, ke};
+        KickArgs ka{vel, mass, dt, e_cheap, nullptr, nullptr, last ? 0 : 1, 0, pos, unused, ke, dc};
         rc = compute_impl(ctx, s, ws, L, unused, pos, species, regions, n_regions, r_buffer, mode,
-                          forces, e_exp, e_cheap, lambda, flags, nullptr, nullptr, nullptr, &ka);
+                          forces, e_exp, e_cheap, lambda, flags, nullptr, nullptr, nullptr, &ka,
+                          nullptr, nullptr, true);
         if (rc)
             return rc;
         StageTimer t(ctx, s, ST_RED);

@@ -413,13 +413,34 @@ __global__ void __launch_bounds__(256) k_neighbors(const double *__restrict__ po
             hdr[H_NBUILD] += 1;
         }
     }
-    if (rebuild == 0)
-        return;
-    __shared__ int rows[4][kMaxCap];
-    __shared__ int lists[4][kNbrList];
     const int w = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     const int i = blockIdx.x * 4 + w;
+    if (rebuild == 0) {
+        // kept list: this call's buffer test over the kept row (the same
+        // test as the rebuild path below): a candidate joins the buffer when
+        // a partner with lambda > 0 lies strictly inside r_buffer
+        if (rb2 >= 0.0 && i < n && cand[i]) {
+            const Box bb = seg_box<SEG, true>(b0, sg, i);
+            const int c = cnt[i];
+            const int *row = nbr + (size_t)i * cap;
+            bool hit = false;
+            for (int sl = lane; sl < c; sl += 64) {
+                const int j = row[sl];
+                if (flags[j] & 1) {
+                    double d[3];
+                    pair_disp(pos, n, i, j, bb, d);
+                    if (norm2(d) < rb2)
+                        hit = true;
+                }
+            }
+            if (__ballot(hit) != 0ull && lane == 0)
+                flags[i] = (uint8_t)(flags[i] | 4);
+        }
+        return;
+    }
+    __shared__ int rows[4][kMaxCap];
+    __shared__ int lists[4][kNbrList];
     if (i >= n)
         return;
     // the atom's system: its box, grid, cell counts and bucket records
@@ -643,8 +664,15 @@ __global__ void __launch_bounds__(256) k_reverse(int n, int cap, int P, const in
     }
 }
 
+DispCheck disp_check_args(void *ws, const WsLayout &L, double skin)
+{
+    const double thr = 0.5 * skin;
+    return DispCheck{at<double>(ws, L.ref_pos), thr * thr, at<int>(ws, L.hdr)};
+}
+
 void launch_neighbors(hipStream_t s, void *ws, const WsLayout &L, const Box &b, double r_list,
-                      const double *pos, int force_rebuild, double skin, const RegionArgs &ra)
+                      const double *pos, int force_rebuild, double skin, const RegionArgs &ra,
+                      bool checked)
 {
     // the row kernel also finds the buffer atoms (mixed mode) whenever it runs
     int *hdr = at<int>(ws, L.hdr);
@@ -652,7 +680,7 @@ void launch_neighbors(hipStream_t s, void *ws, const WsLayout &L, const Box &b, 
     const int n = L.n;
     if (n == 0)
         return;
-    if (!force_rebuild) {
+    if (!force_rebuild && !checked) {
         double thr = 0.5 * skin;
         if (L.nseg > 0)
             k_displacement<true><<<(n + 255) / 256, 256, 0, s>>>(
@@ -940,12 +968,11 @@ void launch_cheap_buffer(hipStream_t s, void *ws, const WsLayout &L, const Box &
                                                             flags, seg_args(ws, L));
 }
 
-// Region stage after the rows: the seeded passes (MLMIX_SEEDED), then the
-// buffer pass. Lambda and the masks of the geometric regions come from the
-// binning kernel of the neighbour stage. On a forced rebuild without seeded
-// regions the row kernel has found the buffer atoms already; otherwise this
-// pass runs (for atoms whose rows were rebuilt it repeats the same test:
-// same distances, same result).
+// Region stage after the rows, for seeded regions only: the seeded passes
+// (MLMIX_SEEDED), then the buffer pass (lambda is final only now). Lambda and
+// the masks of the geometric regions come from the binning kernel of the
+// neighbour stage, and without seeded regions the row kernel does the buffer
+// test on every call (on the rows it builds, or on the kept rows).
 void launch_regions(hipStream_t s, void *ws, const WsLayout &L, const Box &b, int mode,
                     const double *pos, double r_buffer, uint8_t *flags, int force_rebuild,
                     const RegionArgs &ra)
@@ -961,7 +988,9 @@ void launch_regions(hipStream_t s, void *ws, const WsLayout &L, const Box &b, in
                                                  at<int>(ws, L.cnt), ra.reg, ra.nreg, ra.lam,
                                                  flags, core, at<uint8_t>(ws, L.cand));
     }
-    if (n == 0 || (force_rebuild && !seeded))
+    // without seeded regions the row kernel has done the buffer test on
+    // every call (rebuilt rows or kept ones)
+    if (n == 0 || !seeded)
         return;
     uint8_t *cand = at<uint8_t>(ws, L.cand);
     if (mode == MLMIX_MODE_MIXED) {

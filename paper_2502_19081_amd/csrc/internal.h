@@ -223,8 +223,10 @@ struct RegionArgs {
 constexpr int kMaxSeeded = 8;  // seeded regions per evaluation
 
 // ---- launchers (geom.hip) ----
+// checked: the integrator kernel that last moved the atoms did the skin check
 void launch_neighbors(hipStream_t s, void *ws, const WsLayout &L, const Box &b, double r_list,
-                      const double *pos, int force_rebuild, double skin, const RegionArgs &ra);
+                      const double *pos, int force_rebuild, double skin, const RegionArgs &ra,
+                      bool checked = false);
 void launch_reverse(hipStream_t s, void *ws, const WsLayout &L, int side_blocks);
 void launch_regions(hipStream_t s, void *ws, const WsLayout &L, const Box &b, int mode,
                     const double *pos, double r_buffer, uint8_t *flags, int force_rebuild,
@@ -266,6 +268,36 @@ void launch_uf3(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L, const 
 // Closing half kick of a velocity-Verlet step and per-block energy partials,
 // fused into the force gather for systems up to kGatherKickMax atoms (one
 // partial per four atoms, summed by one workgroup).
+// The skin check of the positions an integrator kernel has just drifted:
+// an atom that moved more than half the skin since the last list build
+// (minimum image, so a face crossing is no motion) raises H_MOVED, and the
+// next evaluation needs no check of its own. hdr == nullptr: no check.
+struct DispCheck {
+    const double *ref;  // positions at the last build (SoA)
+    double thr2;        // (skin / 2)^2
+    int *hdr;
+};
+
+template <bool SEG>
+__device__ __forceinline__ void disp_check(const DispCheck &dc, const double x[3], int n, int i,
+                                           const Box &b)
+{
+#pragma clang fp contract(off)
+    double d2 = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        double d = x[k] - dc.ref[k * n + i];
+        if (b.per[k]) {
+            const double h = 0.5 * b.L[k];
+            d = d > h ? d - b.L[k] : (d < -h ? d + b.L[k] : d);
+        }
+        d2 = d2 + d * d;
+    }
+    if (!(d2 <= dc.thr2))
+        dc.hdr[H_MOVED] = 1;
+}
+
+DispCheck disp_check_args(void *ws, const WsLayout &L, double skin);
+
 struct KickArgs {
     double *vel;
     const double *mass;
@@ -278,6 +310,7 @@ struct KickArgs {
     double *pos;       // positions (drift of the next step)
     Box box;
     double *ke_atom;   // per-atom kinetic energy 0.5 m v^2 of the full step (batches)
+    DispCheck chk;     // skin check of the next step's drifted positions (next != 0)
 };
 constexpr int kGatherKickMax = 65536;
 
@@ -305,7 +338,7 @@ void launch_reduce(hipStream_t s, void *ws, const WsLayout &L, const double *e_e
                    const double *e_cheap, const double *vel, const double *mass, double *out);
 void launch_vv_kick_drift(hipStream_t s, void *ws, const WsLayout &L, const Box &b, double *pos,
                           double *vel, const double *mass, const double *forces, double dt,
-                          int drift);
+                          int drift, const DispCheck *chk = nullptr);
 void launch_copy_i32(hipStream_t s, int32_t *dst, const int32_t *src, size_t n);
 void launch_seg_fill(hipStream_t s, void *ws, const WsLayout &L);
 void launch_seg_sums(hipStream_t s, void *ws, const WsLayout &L, const double *e_exp,

@@ -93,6 +93,8 @@ __global__ void __launch_bounds__(256)
                 const double m = ka.mass[i];
                 const double cf = 0.5 * ka.dt * kKappa / m;
                 double v2 = 0.0;
+                double xn[3];
+                const Box bx = seg_box<SEG, true>(ka.box, sg, i);
                 for (int q = 0; q < 3; ++q) {
                     // kicks and drifts as explicit fused multiply-adds, the same
                     // in every kernel that applies them (so fused and separate
@@ -105,17 +107,19 @@ __global__ void __launch_bounds__(256)
                         const double vn = fma(cf, F[q], v);
                         ka.vel[q * n + i] = vn;
                         double x = fma(ka.dt, vn, ka.pos[q * n + i]);
-                        const Box bx = seg_box<SEG, true>(ka.box, sg, i);
                         if (bx.per[q]) {
                             x = x - bx.L[q] * floor(x / bx.L[q]);
                             if (x >= bx.L[q])
                                 x -= bx.L[q];
                         }
                         ka.pos[q * n + i] = x;
+                        xn[q] = x;
                     } else {
                         ka.vel[q * n + i] = v;
                     }
                 }
+                if (ka.next && ka.chk.hdr)
+                    disp_check<SEG>(ka.chk, xn, n, i, bx);
                 ke = 0.5 * m * v2;
                 ee = si < 0 ? 0.0 : e_exp[i];
                 ec = ka.e_cheap[i];
@@ -273,13 +277,14 @@ __global__ void __launch_bounds__(256) k_vv(int n, Box b0, double *__restrict__ 
                                             double *__restrict__ vel,
                                             const double *__restrict__ mass,
                                             const double *__restrict__ f, double dt, int drift,
-                                            Seg sg)
+                                            Seg sg, DispCheck chk)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n)
         return;
     const Box b = seg_box<SEG>(b0, sg, i);
     double c = 0.5 * dt * kKappa / mass[i];
+    double xn[3];
     for (int k = 0; k < 3; ++k) {
         double v = fma(c, f[k * n + i], vel[k * n + i]);
         vel[k * n + i] = v;
@@ -291,8 +296,11 @@ __global__ void __launch_bounds__(256) k_vv(int n, Box b0, double *__restrict__ 
                     x -= b.L[k];
             }
             pos[k * n + i] = x;
+            xn[k] = x;
         }
     }
+    if (drift && chk.hdr)
+        disp_check<SEG>(chk, xn, n, i, b);
 }
 
 // Closing half kick of a step fused with the per-block energy partials
@@ -353,12 +361,13 @@ void launch_vv_kick_sums(hipStream_t s, void *ws, const WsLayout &L, double *vel
 
 void launch_vv_kick_drift(hipStream_t s, void *ws, const WsLayout &L, const Box &b, double *pos,
                           double *vel, const double *mass, const double *forces, double dt,
-                          int drift)
+                          int drift, const DispCheck *chk)
 {
     if (L.n == 0)
         return;
+    const DispCheck dc = chk ? *chk : DispCheck{nullptr, 0.0, nullptr};
     (L.nseg > 0 ? k_vv<true> : k_vv<false>)<<<(L.n + 255) / 256, 256, 0, s>>>(
-        L.n, b, pos, vel, mass, forces, dt, drift, seg_args(ws, L));
+        L.n, b, pos, vel, mass, forces, dt, drift, seg_args(ws, L), dc);
 }
 
 // ------------------------------------------------------ batched systems
