@@ -341,7 +341,10 @@ struct HostTables {
     std::vector<double> o3ww;
     int o3_nch2 = 0;
     std::vector<double> o3g, o3w, o3sw, o3gs;
-    std::vector<int> o3o, o3mt, o3base, o3order, o3wbeg;
+    std::vector<int> o3o, o3mt, o3mtv, o3base, o3order, o3wbeg;
+    std::vector<int> o3rowv, o3rbeg;  // bins as flat row lists (vector-sparse FP32 form)
+    int o3rows_max = 0;               // longest such list
+    bool o3rows_empty = false;        // some (block, m3) has no Gaunt entry
 };
 
 // Tables of the per-wave matrix-core order-3 kernel (single-species models
@@ -350,7 +353,8 @@ struct HostTables {
 //    multiple of four (one MFMA K step), as pairs (packed offsets
 //    (l1 m1)*16 | (l2 m2)*16 << 16 of the two A rows in the kernel's
 //    16-channel LDS layout, FP32 bits of the coefficient); (first entry,
-//    groups) per (block, m3);
+//    groups) per (block, m3), and (first entry, exact count) for the FP32
+//    form whose sparse stage runs on the vector ALUs;
 //  - the block weights as per-lane MFMA fragments: for lane (c = l % 16,
 //    q = l / 16) element f = 4 i + j holds W[a = i][b = 4 q + j][c], stored
 //    [block][i][lane][4] so that a wave loads them as 16-byte rows; in the
@@ -395,6 +399,10 @@ static void build_o3(const mlmix_model_desc &d, HostTables &t, int waves)
                 return;  // more than 32 entries in one row: keep the general kernel
             t.o3mt.push_back((int)t.o3g.size());  // entry index (pairs in o3o)
             t.o3mt.push_back(ng);
+            t.o3mtv.push_back((int)t.o3g.size());
+            t.o3mtv.push_back(n_e);
+            if (n_e == 0)
+                t.o3rows_empty = true;
             for (int e = e0; e < e0 + 4 * ng; ++e) {
                 int o = 0;
                 float g = 0.0f;
@@ -490,6 +498,9 @@ static void build_o3(const mlmix_model_desc &d, HostTables &t, int waves)
         total += cost[p];
     t.o3order.clear();
     t.o3wbeg.clear();
+    t.o3rowv.clear();
+    t.o3rbeg.clear();
+    t.o3rows_max = 0;
     for (int G = 1; G <= kO3MaxSplit; G <<= 1) {
         // bins: the waves of the G workgroups sharing a tile (the wide form
         // always has four waves per workgroup)
@@ -526,13 +537,29 @@ static void build_o3(const mlmix_model_desc &d, HostTables &t, int waves)
         }
         for (int w = 0; w < nb; ++w) {
             t.o3wbeg.push_back((int)t.o3order.size());  // absolute offsets
+            t.o3rbeg.push_back((int)t.o3rowv.size() / 4);
             std::sort(lists[w].begin(), lists[w].end(), [](int x, int y) {
                 const int px = x & 0xffff, py = y & 0xffff;
                 return px != py ? px < py : ((x >> 16) & 0xff) < ((y >> 16) & 0xff);
             });
             t.o3order.insert(t.o3order.end(), lists[w].begin(), lists[w].end());
+            // the same bin as a flat list of rows (first entry, exact count,
+            // block | m3 << 16, partial-D column of the row)
+            int nrow = 0;
+            for (int code : lists[w]) {
+                const int p = code & 0xffff, lo = (code >> 16) & 0xff, hi = (code >> 24) & 0xff;
+                for (int m3 = lo; m3 < hi; ++m3, ++nrow) {
+                    const int row = t.o3base[p] + m3;
+                    t.o3rowv.push_back(t.o3mtv[2 * row]);
+                    t.o3rowv.push_back(t.o3mtv[2 * row + 1]);
+                    t.o3rowv.push_back(p | (m3 << 16));
+                    t.o3rowv.push_back(t.dpoff[p] + m3 * nch);
+                }
+            }
+            t.o3rows_max = std::max(t.o3rows_max, nrow);
         }
         t.o3wbeg.push_back((int)t.o3order.size());
+        t.o3rbeg.push_back((int)t.o3rowv.size() / 4);
     }
     // FP8 row-scale bound: sum of |g| over the row's entries
     t.o3gs.clear();
@@ -787,6 +814,9 @@ static std::vector<char> pack(const HostTables &t, DevModel &m)
     append<float>(blob, m.wsc, t.wsc);
     append_raw(blob, m.o3o, t.o3o);
     append_raw(blob, m.o3mt, t.o3mt);
+    append_raw(blob, m.o3mtv, t.o3mtv);
+    append_raw(blob, m.o3rowv, t.o3rowv);
+    append_raw(blob, m.o3rbeg, t.o3rbeg);
     append_raw(blob, m.o3base, t.o3base);
     append<float>(blob, m.o3w, t.o3w);
     append<float>(blob, m.o3ww, t.o3ww);
@@ -876,9 +906,10 @@ static void layout_arrays(const Ctx &c, WsLayout &L, size_t ncell, size_t nrec, 
     take(L.dEdA, ns * c.m.KAt * tsz);
     take(L.g, ns * cap * 3 * tsz);
     take(L.h, nn * cap * 3 * tsz);
-    take(L.red, (size_t)std::max(kReduceBlocks, n <= kGatherKickMax ? (n + 3) / 4 : 0) * 3 *
+    take(L.red, (size_t)std::max(kReduceBlocks, n <= kGatherKickMax ? (n + kGatherAtoms - 1) / kGatherAtoms : 0) * 3 *
                     sizeof(double));
-    take(L.dpart, ns * (size_t)(c.m.dp_stride > 0 ? c.m.dp_stride : 1) * tsz);
+    // (64 floats past the end: the sink of the contraction's masked lanes)
+    take(L.dpart, (ns * (size_t)(c.m.dp_stride > 0 ? c.m.dp_stride : 1) + 64) * tsz);
     if (nseg > 0) {
         take(L.seg_of, nn * sizeof(int));
         take(L.segs, (size_t)nseg * sizeof(SegGeo));
@@ -1098,9 +1129,13 @@ try {
         c.rev_blocks = std::max(1, std::atoi(e));
     if (const char *e = std::getenv("MLMIX_O3_MAX_SPLIT")) {
         int v = std::atoi(e);
-        if (v == 1 || v == 2 || v == 4 || v == 8)
+        if (v == 1 || v == 2 || v == 4 || v == 8 || v == 16)
             c.o3_max_split = v;
     }
+    if (const char *e = std::getenv("MLMIX_O3_VALU"))
+        c.o3v = std::atoi(e) ? 1 : 0;  // 0: matrix-core sparse stage (comparisons)
+    if (t.o3rows_max > kO3VMaxRows || t.o3rows_empty)
+        c.o3v = 0;  // a bin longer than the kernel's row registers hold, or an empty row
     if (const char *e = std::getenv("MLMIX_BASIS_CHUNKS"))
         c.basis_chunks = std::max(-1, std::min(1, std::atoi(e)));
     if (const char *e = std::getenv("MLMIX_BASIS_MFMA"))
@@ -1294,7 +1329,7 @@ static int compute_impl(mlmix_ctx *ctx, hipStream_t s, void *ws, const WsLayout 
                       (mode & MLMIX_SEEDED) ? 1 : 0, nullptr};
         if (red_out) {  // the previous step's energy partials (multi-step call)
             ra.red_part = at<double>(ws, L.red);
-            ra.red_nb = (L.n + 3) / 4;
+            ra.red_nb = (L.n + kGatherAtoms - 1) / kGatherAtoms;
             ra.red_out = red_out;
         }
         launch_neighbors(s, ws, L, b, c.r_list, pos, (mode & MLMIX_FORCE_REBUILD) ? 1 : 0,
@@ -1407,9 +1442,11 @@ static int compute_impl(mlmix_ctx *ctx, hipStream_t s, void *ws, const WsLayout 
         return MLMIX_OK;
     }
     {
-        StageTimer t(ctx, s, ST_GATHER);
+        // timed by the kernel's own events (a bracket on the stream would also
+        // hold the wait for the second stream's join)
+        StageTimer t(ctx, s, ST_GATHER, true);
         launch_gather_blend(s, c, ws, L, m != MLMIX_MODE_ALL_CHEAP, m != MLMIX_MODE_ALL_EXPENSIVE,
-                            lambda, forces, e_exp, f_exp, f_cheap, 1.0, kick, lang);
+                            lambda, forces, e_exp, f_exp, f_cheap, 1.0, kick, lang, t.k0, t.k1);
     }
     HIP_OK(hipGetLastError());
     return MLMIX_OK;

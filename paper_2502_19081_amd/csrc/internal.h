@@ -17,7 +17,8 @@ constexpr int kMaxCap = 256;
 constexpr int kMaxTriplet = 64;   // neighbours inside the 3-body cutoff per centre
 constexpr int kScanTile = 2048;   // elements per block in the device scans
 constexpr int kReduceBlocks = 256;
-constexpr int kO3MaxSplit = 8;    // workgroups sharing one 16-atom tile of the order-3 kernel
+constexpr int kO3VMaxRows = 128;  // rows of one bin of the vector-sparse FP32 contraction
+constexpr int kO3MaxSplit = 16;   // workgroups sharing one 16-atom tile of the order-3 kernel
 
 // Header words at the start of every workspace (int32 unless noted).
 enum HeaderWord {
@@ -137,7 +138,7 @@ struct DevModel {
     // offsets (bytes) into base
     size_t ylmK, c0, c0d, c1, c2s, W, pb, gm3, gidx, gofs, gval, u2, u3, up2, up3, dpoff, wsc;
     // tables of the matrix-core order-3 kernel (single species, <= 16 channels)
-    size_t o3o, o3mt, o3base, o3w, o3sw, o3order, o3wbeg, o3gs;
+    size_t o3o, o3mt, o3mtv, o3rowv, o3rbeg, o3base, o3w, o3sw, o3order, o3wbeg, o3gs;
     size_t o3ww;  // weight fragments of the wide form
     int dp_stride;  // partial-D entries per S atom (sum over blocks of nchan*(2 l3 + 1))
     int w_per_species;  // entries of W per centre species
@@ -176,18 +177,23 @@ struct Ctx {
     // workgroup cap of the cheap-potential kernel on the second stream
     // (grid-stride loop): -1 automatic, 0 uncapped. The best cap follows the
     // length of the expensive chain beside it; measured per mixed step on
-    // 8,193 atoms with the current chain and fork point: 148 / 138 / 137 /
-    // 137 us at 256 / 384 / 512 / 768 workgroups (an earlier, longer chain
-    // preferred 256). On 1,023,800 atoms caps of 1024 and 2048 measured no
-    // better than none (11.6 / 11.2 / 11.3 ms, same box). Automatic: 512
-    // below 262,144 atoms, uncapped above.
+    // 8,193 atoms (list kept within the skin, fork point 2): 160 / 129 / 111
+    // / 123 / 120 / 120 / 126 us at 128 / 192 / 256 / 384 / 512 / 1024
+    // workgroups / uncapped. On 1,023,800 atoms caps of 1024 and 2048
+    // measured no better than none (11.6 / 11.2 / 11.3 ms, same box).
+    // Automatic: 256 (one per compute unit) below 262,144 atoms, uncapped
+    // above.
     int side_blocks = -1;
     int rev_blocks = 1024;  // cap of the reverse-slot kernel when capped (256 / 1024 measured 153.0 / 152.4 us)
     int o3_nch2 = 0;       // row width of that kernel (channels rounded up to 4)
-    // largest tile split of that kernel: 4 measured best on the 8,193-atom
-    // cell (910 atoms in S: contraction 92 / 52 / 37 / 48 us at 1 / 2 / 4 / 8)
+    // largest tile split of the single-species forms and their waves per
+    // workgroup: for the FP32 vector-sparse form on the 8,193-atom cell (910
+    // atoms in S) 19.2 / 17.6 / 19.4 us at splits 4 / 8 / 16 with four waves,
+    // 16.7 / 18.3 / 18.2 us with eight; on 102,858 atoms in S 3.32 ms with
+    // four waves and 3.42 with eight
     int o3_max_split = 4;
-    int o3_waves = 4;      // waves per workgroup of the single-species form (4 or 8)
+    int o3_waves = 8;      // waves per workgroup of the single-species form (4 or 8)
+    int o3v = 1;           // FP32 single-species form with the vector sparse stage
     int ace_tile = 4;      // atoms per order-3 block workgroup (tuning)
     int ace_stage_w = 1;   // stage the block's weights in LDS (tuning)
     int device;
@@ -252,6 +258,7 @@ void launch_ace_pairgrad(hipStream_t s, const Ctx &c, void *ws, const WsLayout &
 void launch_ace_o3(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L,
                    hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 size_t o3_lds_bytes(const Ctx &c);
+size_t o3v_lds_bytes(const Ctx &c);
 void launch_ace_o3w(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L,
                     const int32_t *species, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 size_t o3w_lds_bytes(const Ctx &c);
@@ -267,7 +274,7 @@ void launch_uf3(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L, const 
 // ---- tail.hip ----
 // Closing half kick of a velocity-Verlet step and per-block energy partials,
 // fused into the force gather for systems up to kGatherKickMax atoms (one
-// partial per four atoms, summed by one workgroup).
+// partial per kGatherAtoms atoms, summed by one workgroup).
 // The skin check of the positions an integrator kernel has just drifted:
 // an atom that moved more than half the skin since the last list build
 // (minimum image, so a face crossing is no motion) raises H_MOVED, and the
@@ -313,6 +320,7 @@ struct KickArgs {
     DispCheck chk;     // skin check of the next step's drifted positions (next != 0)
 };
 constexpr int kGatherKickMax = 65536;
+constexpr int kGatherAtoms = 16;  // atoms per workgroup of the force gather (16 lanes each)
 
 constexpr double kKappa = 9.648533212e-3;     // eV/A/amu in A/fs^2
 constexpr double kBoltzmann = 8.617333262e-5;  // eV/K
@@ -329,7 +337,8 @@ struct LangevinArgs {
 void launch_gather_blend(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L, int use_exp,
                          int use_cheap, const double *lambda, double *forces, double *e_exp,
                          double *f_exp, double *f_cheap, double sign,
-                         const KickArgs *kick = nullptr, const LangevinArgs *lang = nullptr);
+                         const KickArgs *kick = nullptr, const LangevinArgs *lang = nullptr,
+                         hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 void launch_fill_f64(hipStream_t s, double *p, double v, size_t n);
 void launch_vv_kick_sums(hipStream_t s, void *ws, const WsLayout &L, double *vel,
                          const double *mass, const double *forces, double dt, const double *e_exp,

@@ -52,6 +52,10 @@ typedef __bf16 bf2v __attribute__((ext_vector_type(2)));
 struct O3Args {
     const int *e;         // entries: (packed A-row offsets, coefficient bits) pairs
     const int *mt;        // (first entry, groups of four) per (block, m3)
+    const int *mtv;       // (first entry, exact entry count) per (block, m3)
+    const int *rowv;      // bins as flat row lists: (first entry, count, block | m3 << 16, D column)
+    const int *rbeg;      // per split G: 4 G + 1 offsets (in rows) into rowv
+    float *sink;          // 64 floats past the partial-D buffer (masked lanes' stores)
     const int *base;      // first (block, m3) row of each block
     const float *w;       // weight fragments [block][NC][64][4]
     const float *sw;      // FP8 weight scales [block][16]
@@ -175,7 +179,7 @@ __device__ __forceinline__ void o3_sparse(const float *__restrict__ At, int L2, 
 }
 
 template <int QM, int NC, int NW>  // NW waves per workgroup (4 or 8)
-__global__ void __launch_bounds__(64 * NW, 1)
+__global__ void __launch_bounds__(64 * NW, NW == 4 ? 2 : 1)
     k_ace_o3(const int *__restrict__ hdr, O3Args a, const float *__restrict__ A,
              float *__restrict__ Dpart)
 {
@@ -385,6 +389,242 @@ __global__ void __launch_bounds__(64 * NW, 1)
             }
         }
     }
+}
+
+// ------------------------------------------------------ FP32, VALU sparse
+//
+// The FP32 form of the single-species contraction used by default: the same
+// tiles of 16 atoms and the same partial-D output, the work of a tile split
+// into per-wave bins of rows (block, m3) listed flat by the host, and the
+// sparse stage on the vector ALUs, leaving P directly in the registers the
+// dense stage reads (no P round trip through LDS, no wave barrier):
+//
+//  lane (t = atom, q):  P_t[a][NJ q + j] for every channel a and j < NJ =
+//                       nchp / 4 (NJ * nchp accumulators), summed over the
+//                       row's Gaunt entries e as g_e A_t[l1 m1_e][a]
+//                       A_t[l2 m2_e][NJ q + j]; the entries are
+//                       wave-uniform (one vector load per row, a row ahead,
+//                       read back lane by lane) and the A values of entry
+//                       e + 1 are read from LDS while entry e is accumulated;
+//  dense stage:         D[t][c] = sum_{a, j} P_t[a][NJ q + j]
+//                       W[a][NJ q + j][c] as nchp * NJ 16x16x4 MFMA steps
+//                       (K over exactly nchp^2 pairs), two accumulators in
+//                       a fixed alternation.
+//
+// Two or three waves per SIMD: the vector sparse stage of one runs beside
+// the matrix-core dense stage of another. (Interleaving the dense steps of a
+// row with the next row's vector work inside one wave needs P and the
+// weights twice in registers: one wave per SIMD at 16 channels, measured
+// slower, 4.4 against 3.3 ms on 102,858 atoms in S, and no faster at 12.)
+template <int NC, int NW>
+__global__ void __launch_bounds__(64 * NW, NC <= 12 ? 3 : 2)
+    k_ace_o3v(const int *__restrict__ hdr, O3Args a, const float *__restrict__ A,
+              float *__restrict__ Dpart)
+{
+#pragma clang fp contract(off)
+    constexpr int NTH = 64 * NW, NJ = NC / 4;
+    const int nS = hdr[H_NS];
+    const int ntile = (nS + kO3Atoms - 1) / kO3Atoms;
+    int G = 1, lg = 0;
+    while (G < a.max_split && ntile * G < (int)gridDim.x) {
+        G <<= 1;
+        ++lg;
+    }
+    const int nitem = ntile * G;
+    if ((int)blockIdx.x >= nitem)
+        return;  // uniform across the workgroup
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int m = lane & 15, q = lane >> 4;
+    const int nch = a.nch, L2 = a.L2;
+    const int astr = L2 * 16 + 4;  // LDS floats per atom
+    extern __shared__ __align__(16) char smem_raw[];
+    float *At = reinterpret_cast<float *>(smem_raw);  // [16][astr]
+    const float *At_t = At + (size_t)m * astr;       // this lane's atom (t = m)
+    const int *rbeg = a.rbeg + NW * (G - 1) + lg;
+    const int2 *etab = reinterpret_cast<const int2 *>(a.e);
+    const int4 *rows = reinterpret_cast<const int4 *>(a.rowv);
+
+    float P[NC][NJ];
+    float wf[NC][NJ];
+    f4v acc0, acc1;
+    f4v a1[2][NC / 4];
+    float a2[2][NJ];
+
+    for (int item = blockIdx.x; item < nitem; item += gridDim.x) {
+        const int tile = item >> lg, bin = (item & (G - 1)) * NW + wv;
+        const int r_lo = rbeg[bin], nr = rbeg[bin + 1] - r_lo;  // nr <= 128 (host check)
+        const int s0 = tile * kO3Atoms;
+        const int na = min(kO3Atoms, nS - s0);
+        // the bin's row records, two per lane (rows lane and 64 + lane)
+        int4 rec0 = make_int4(0, 0, 0, 0), rec1 = make_int4(0, 0, 0, 0);
+        if (lane < nr)
+            rec0 = rows[r_lo + lane];
+        if (64 + lane < nr)
+            rec1 = rows[r_lo + 64 + lane];
+        // field f of row k's record (wave-uniform)
+        auto field = [&](int k, int f) -> int {
+            const int4 &rc = k < 64 ? rec0 : rec1;
+            const int v = f == 0 ? rc.x : (f == 1 ? rc.y : (f == 2 ? rc.z : rc.w));
+            return __builtin_amdgcn_readlane(v, k & 63);
+        };
+        // a row's entries, one per lane: every lane loads (the table is padded
+        // by 32 entries past its end); lanes at or past the count are zeroed
+        // where the row starts (not here: that would wait for the load)
+        auto entries = [&](int k, int &ne) -> int2 {
+            ne = field(k, 1);
+            return etab[field(k, 0) + min(lane, 31)];
+        };
+        int pcur = -1;
+        // weight fragments of block p: lane (c = m, q) holds W[a = i][NJ q + j][c]
+        auto weights = [&](int p) {
+            const float *wsrc = a.w + ((size_t)p * NC * 64 + lane) * 4;
+#pragma unroll
+            for (int i = 0; i < NC; ++i)
+#pragma unroll
+                for (int j = 0; j < NJ; ++j)
+                    wf[i][j] = wsrc[i * 256 + j];
+            pcur = p;
+        };
+        // entries of the current and the next row alternate between two
+        // register sets by row parity (a copy of a loaded register would make
+        // the wave wait for the load where it is issued); the first row's
+        // entries and weights are read while the tile's A rows are staged
+        int neE[2] = {0, 0};
+        int2 entE[2];
+        if (nr > 0) {
+            weights(field(0, 2) & 0xffff);
+            entE[0] = entries(0, neE[0]);
+        }
+        __syncthreads();  // every wave is done with the previous tile's A
+        for (int r = tid; r < kO3Atoms * L2; r += NTH) {
+            const int t = r / L2, lm = r - t * L2;
+            f4v *dst = reinterpret_cast<f4v *>(At + (size_t)t * astr + lm * 16);
+            const f4v *src = reinterpret_cast<const f4v *>(A + (size_t)(s0 + t) * a.KAt + lm * NC);
+#pragma unroll
+            for (int c4 = 0; c4 < NC / 4; ++c4)
+                dst[c4] = t < na ? src[c4] : (f4v){0.f, 0.f, 0.f, 0.f};
+        }
+        __syncthreads();
+
+        // D of the last row: lane holds D[atom = 4 q + v][c = m]; lanes
+        // outside the tile or the channels (and every lane before the first
+        // row) write to a sink past the buffer's end, so that the stores need
+        // no branch
+        int dcol = 0;
+        auto store_d = [&](bool real) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int t = 4 * q + v;
+                float *dst = (real && t < na && m < nch)
+                                 ? Dpart + (size_t)(s0 + t) * a.dp_stride + dcol + m
+                                 : a.sink + lane;
+                *dst = acc0[v] + acc1[v];
+            }
+        };
+        acc0 = (f4v){0.f, 0.f, 0.f, 0.f};
+        acc1 = (f4v){0.f, 0.f, 0.f, 0.f};
+
+        // row k (entries in set H): its P on the vector ALUs, its D on the
+        // matrix cores (stored at the start of the next row, after that
+        // row's wait for its entries, so that the wait does not also wait
+        // for the stores)
+        auto row = [&](int k, auto hc) {
+            constexpr int H = decltype(hc)::value;
+            const int ne = neE[H];
+            const int2 ent = lane < ne ? entE[H] : make_int2(0, 0);
+            const int ox0 = __builtin_amdgcn_readlane(ent.x, 0);
+            __builtin_amdgcn_sched_barrier(0);
+            store_d(k > 0);
+            const int p = field(k, 2) & 0xffff;
+            dcol = field(k, 3);
+            // the block's weights (read while the sparse stage runs), then the
+            // next row's entries (a valid row past the end is read and not
+            // used)
+            if (p != pcur)
+                weights(p);
+            entE[H ^ 1] = entries(min(k + 1, nr - 1), neE[H ^ 1]);
+
+            // A values of entry e into register set h (entry lanes past the
+            // count hold zero offsets: in-bounds reads whose values are not
+            // used)
+            auto load = [&](int e, int h) {
+                const int ox = e == 0 ? ox0 : __builtin_amdgcn_readlane(ent.x, e);
+                const f4v *r1 = reinterpret_cast<const f4v *>(At_t + (ox & 0xffff));
+                const float *r2 = At_t + (ox >> 16) + NJ * q;
+#pragma unroll
+                for (int k4 = 0; k4 < NC / 4; ++k4)
+                    a1[h][k4] = r1[k4];
+                if constexpr (NJ == 4) {
+                    const f4v v = *reinterpret_cast<const f4v *>(r2);
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        a2[h][j] = v[j];
+                } else {
+#pragma unroll
+                    for (int j = 0; j < NJ; ++j)
+                        a2[h][j] = r2[j];
+                }
+            };
+            auto accumulate = [&](int e, int h, bool first) {
+                const float g = __int_as_float(__builtin_amdgcn_readlane(ent.y, e));
+                float b[NJ];
+#pragma unroll
+                for (int j = 0; j < NJ; ++j)
+                    b[j] = g * a2[h][j];
+#pragma unroll
+                for (int i = 0; i < NC; ++i)
+#pragma unroll
+                    for (int j = 0; j < NJ; ++j)
+                        P[i][j] = first ? a1[h][i / 4][i % 4] * b[j]
+                                        : fmaf(a1[h][i / 4][i % 4], b[j], P[i][j]);
+            };
+            // ---- sparse stage: two register sets, each load one entry ahead
+            // (scheduling barriers keep it ahead of the other set's
+            // arithmetic: the scheduler would sink it to its use). Every row
+            // has at least one entry (host check).
+            load(0, 0);
+            load(1, 1);
+            __builtin_amdgcn_sched_barrier(0);
+            accumulate(0, 0, true);
+            for (int e = 1; e < ne; e += 2) {
+                load(e + 1, 0);
+                __builtin_amdgcn_sched_barrier(0);
+                accumulate(e, 1, false);
+                if (e + 1 >= ne)
+                    break;
+                load(e + 2, 1);
+                __builtin_amdgcn_sched_barrier(0);
+                accumulate(e + 1, 0, false);
+            }
+            // ---- dense stage (matrix cores): lane (t = m, q) supplies
+            // P_t[i][NJ q + j], lane (c = m, q) the weight W[i][NJ q + j][c]
+            acc0 = (f4v){0.f, 0.f, 0.f, 0.f};
+            acc1 = (f4v){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int i = 0; i < NC; ++i)
+#pragma unroll
+                for (int j = 0; j < NJ; ++j) {
+                    if (((i * NJ + j) & 1) == 0)
+                        acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(P[i][j], wf[i][j], acc0, 0, 0, 0);
+                    else
+                        acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(P[i][j], wf[i][j], acc1, 0, 0, 0);
+                }
+        };
+        for (int k = 0; k < nr; k += 2) {
+            row(k, std::integral_constant<int, 0>());
+            if (k + 1 >= nr)
+                break;
+            row(k + 1, std::integral_constant<int, 1>());
+        }
+        if (nr > 0)
+            store_d(true);
+    }
+}
+
+size_t o3v_lds_bytes(const Ctx &c)
+{
+    return (size_t)kO3Atoms * (c.m.L2 * 16 + 4) * sizeof(float);
 }
 
 // ------------------------------------------------------------- wide form
@@ -705,6 +945,10 @@ void launch_ace_o3(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L, hip
     O3Args a;
     a.e = reinterpret_cast<const int *>(base + m.o3o);
     a.mt = reinterpret_cast<const int *>(base + m.o3mt);
+    a.mtv = reinterpret_cast<const int *>(base + m.o3mtv);
+    a.rowv = reinterpret_cast<const int *>(base + m.o3rowv);
+    a.rbeg = reinterpret_cast<const int *>(base + m.o3rbeg);
+    a.sink = at<float>(ws, L.dpart) + (size_t)std::max(L.scap, 1) * (m.dp_stride > 0 ? m.dp_stride : 1);
     a.base = reinterpret_cast<const int *>(base + m.o3base);
     a.w = reinterpret_cast<const float *>(base + m.o3w);
     a.sw = reinterpret_cast<const float *>(base + m.o3sw);
@@ -720,15 +964,44 @@ void launch_ace_o3(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L, hip
     a.KAt = m.KAt;
     a.dp_stride = m.dp_stride;
     a.max_split = c.o3_max_split;
+    const int *hdr = at<int>(ws, L.hdr);
+    const float *A = at<float>(ws, L.A);
+    float *D = at<float>(ws, L.dpart);
+    const long items = (((long)L.n + kO3Atoms - 1) / kO3Atoms) * kO3MaxSplit;
+    if (c.qmode == 0 && c.o3v) {
+        // FP32 with the vector sparse stage: as many resident workgroups as
+        // the registers allow (waves per SIMD: three up to 12 channels, else two)
+        const size_t lds = o3v_lds_bytes(c);
+        auto go = [&](auto nc) {
+            constexpr int NC = decltype(nc)::value;
+            auto launch = [&](auto nw) {
+                constexpr int NW = decltype(nw)::value;
+                const int per_cu = std::max(1, 4 * (NC <= 12 ? 3 : 2) / NW);
+                const int grid = (int)std::min<long>(std::max<long>(items, 1), 256L * per_cu);
+                if (ev0)
+                    hipExtLaunchKernelGGL(k_ace_o3v<NC, NW>, dim3(grid), dim3(64 * NW),
+                                          (uint32_t)lds, s, ev0, ev1, 0u, hdr, a, A, D);
+                else
+                    k_ace_o3v<NC, NW><<<grid, 64 * NW, lds, s>>>(hdr, a, A, D);
+            };
+            if (c.o3_waves == 8)
+                launch(std::integral_constant<int, 8>());
+            else
+                launch(std::integral_constant<int, 4>());
+        };
+        switch (m.nchp) {
+        case 4: go(std::integral_constant<int, 4>()); break;
+        case 8: go(std::integral_constant<int, 8>()); break;
+        case 12: go(std::integral_constant<int, 12>()); break;
+        default: go(std::integral_constant<int, 16>()); break;
+        }
+        return;
+    }
     const size_t lds = o3_lds_bytes(c);
     const int per_cu = lds <= 80 * 1024 ? 2 : 1;
     // persistent grid: one wave of resident workgroups; the kernel splits
     // tiles when S is small
-    const long items = (((long)L.n + kO3Atoms - 1) / kO3Atoms) * kO3MaxSplit;
     const int grid = (int)std::min<long>(std::max<long>(items, 1), 256L * per_cu);
-    const int *hdr = at<int>(ws, L.hdr);
-    const float *A = at<float>(ws, L.A);
-    float *D = at<float>(ws, L.dpart);
     auto go = [&](auto qm, auto nc) {
         constexpr int QM = decltype(qm)::value, NC = decltype(nc)::value;
         auto launch = [&](auto nw) {

@@ -3,14 +3,42 @@
 //
 // Gather: with g_ij = dE_i/dd_ij stored per (centre, row slot), the force is
 // F_i = sum_j (g_ij - g_ji), where g_ji sits in j's row at the reverse slot.
-// One wavefront per atom (lanes over row slots, fixed-order butterfly sum):
-// no atomics, so repeated runs and replicas evaluated alone or in a batch
-// give the same bits. The blend F = lambda F_exp + (1 - lambda) F_cheap is
-// fused into the same pass.
+// Sixteen lanes per atom (a DPP row: lanes over row slots, then a fixed-order
+// sum within the row), four atoms per wavefront: no atomics, so repeated
+// runs and replicas evaluated alone or in a batch give the same bits. The
+// blend F = lambda F_exp + (1 - lambda) F_cheap is fused into the same pass.
+#include <hip/hip_ext.h>
+
 #include "internal.h"
 #include "reduce.h"
 
 namespace mlmix {
+
+template <typename T>
+struct TypeTag {
+    using type = T;
+};
+
+// 64-bit value moved by a DPP lane pattern (two 32-bit moves)
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Sum over the 16 lanes of a DPP row in a fixed order (pairs, quads, halves,
+// rows); every lane of the row receives the same bits.
+__device__ __forceinline__ double row16_sum_d(double v)
+{
+    v += dpp_d<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+    v += dpp_d<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+    v += dpp_d<0x141>(v);  // row_half_mirror
+    v += dpp_d<0x140>(v);  // row_mirror
+    return v;
+}
 
 template <typename T, bool KICK, bool SEG>
 __global__ void __launch_bounds__(256)
@@ -22,16 +50,16 @@ __global__ void __launch_bounds__(256)
                    double *__restrict__ f_cheap, double sign, KickArgs ka, LangevinArgs la,
                    Seg sg)
 {
-    const int w = threadIdx.x >> 6;
-    const int i = blockIdx.x * 4 + w;
-    const int lane = threadIdx.x & 63;
+    const int ga = threadIdx.x >> 4;  // atom of the workgroup
+    const int i = blockIdx.x * kGatherAtoms + ga;
+    const int lane = threadIdx.x & 15;  // slot lane within the atom's row
     double ee = 0.0, ec = 0.0, ke = 0.0;  // energy terms of atom i (lane 0, KICK)
     if (i < n) {
         int c = cnt[i];
         int si = S_local[i];
         double fe0 = 0.0, fe1 = 0.0, fe2 = 0.0, fc0 = 0.0, fc1 = 0.0, fc2 = 0.0;
         const size_t rowo = (size_t)i * cap;
-        for (int slot = lane; slot < c; slot += 64) {
+        for (int slot = lane; slot < c; slot += 16) {
             int j = nbr[rowo + slot];
             int r = rev[rowo + slot];
             if (r < 0)
@@ -54,12 +82,12 @@ __global__ void __launch_bounds__(256)
                 fc2 += (double)a[2] - (double)bb[2];
             }
         }
-        fe0 = wave_sum_d(fe0);
-        fe1 = wave_sum_d(fe1);
-        fe2 = wave_sum_d(fe2);
-        fc0 = wave_sum_d(fc0);
-        fc1 = wave_sum_d(fc1);
-        fc2 = wave_sum_d(fc2);
+        fe0 = row16_sum_d(fe0);
+        fe1 = row16_sum_d(fe1);
+        fe2 = row16_sum_d(fe2);
+        fc0 = row16_sum_d(fc0);
+        fc1 = row16_sum_d(fc1);
+        fc2 = row16_sum_d(fc2);
         if (lane == 0) {
             double lam = lambda ? lambda[i] : 1.0;
             double om = 1.0 - lam;
@@ -94,7 +122,8 @@ __global__ void __launch_bounds__(256)
                 const double cf = 0.5 * ka.dt * kKappa / m;
                 double v2 = 0.0;
                 double xn[3];
-                const Box bx = seg_box<SEG, true>(ka.box, sg, i);
+                // (per lane: a wavefront holds four atoms, maybe of two systems)
+                const Box bx = seg_box<SEG>(ka.box, sg, i);
                 for (int q = 0; q < 3; ++q) {
                     // kicks and drifts as explicit fused multiply-adds, the same
                     // in every kernel that applies them (so fused and separate
@@ -132,16 +161,23 @@ __global__ void __launch_bounds__(256)
         // block partial; k_reduce_final sums the partials in a fixed order
         // (a last-block-done reduction in this kernel measured 61 us against
         // 12 + 4 us on 8,193 atoms: the per-block device-scope fences)
-        __shared__ double sh[3][4];
+        __shared__ double sh[3][kGatherAtoms];
         if (lane == 0) {
-            sh[0][w] = ee;
-            sh[1][w] = ec;
-            sh[2][w] = ke;
+            sh[0][ga] = ee;
+            sh[1][ga] = ec;
+            sh[2][ga] = ke;
         }
         __syncthreads();
-        if (threadIdx.x == 0)
-            for (int q = 0; q < 3; ++q)
-                ka.part[blockIdx.x * 3 + q] = (sh[q][0] + sh[q][1]) + (sh[q][2] + sh[q][3]);
+        if (threadIdx.x < 3) {
+            const int q = threadIdx.x;
+            double v[kGatherAtoms];
+            for (int k = 0; k < kGatherAtoms; ++k)
+                v[k] = sh[q][k];
+            for (int w = kGatherAtoms / 2; w > 0; w >>= 1)  // pairwise, fixed order
+                for (int k = 0; k < w; ++k)
+                    v[k] = v[k] + v[k + w];
+            ka.part[blockIdx.x * 3 + q] = v[0];
+        }
     }
 }
 
@@ -151,12 +187,12 @@ __global__ void __launch_bounds__(256) k_reduce_final(const double *__restrict__
 void launch_gather_blend(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L, int use_exp,
                          int use_cheap, const double *lambda, double *forces, double *e_exp,
                          double *f_exp, double *f_cheap, double sign, const KickArgs *kick,
-                         const LangevinArgs *lang)
+                         const LangevinArgs *lang, hipEvent_t ev0, hipEvent_t ev1)
 {
     int n = L.n;
     if (n == 0)
         return;
-    unsigned nb = (n + 3) / 4;
+    unsigned nb = (n + kGatherAtoms - 1) / kGatherAtoms;
     LangevinArgs la{};
     if (lang)
         la = *lang;
@@ -166,24 +202,32 @@ void launch_gather_blend(hipStream_t s, const Ctx &c, void *ws, const WsLayout &
         // a batch sums its energies per system in k_seg_sums instead
         ka.part = L.nseg == 0 ? at<double>(ws, L.red) : nullptr;
     }
-#define MLMIX_GATHER(T, K)                                                                        \
-    (L.nseg > 0 ? k_gather_blend<T, K, true> : k_gather_blend<T, K, false>)<<<nb, 256, 0, s>>>(n, L.cap, at<int>(ws, L.nbr), at<int>(ws, L.cnt),      \
-                                           at<int>(ws, L.rev), at<int>(ws, L.S_local),             \
-                                           at<T>(ws, L.g), at<T>(ws, L.h), use_exp, use_cheap,     \
-                                           lambda, forces, e_exp, f_exp, f_cheap, sign, ka, la, \
-                                           seg_args(ws, L))
-    if (c.prec == MLMIX_FP64) {
-        if (kick)
-            MLMIX_GATHER(double, true);
+    // ev0 / ev1: the kernel's own start and end (stage timing)
+    auto go = [&](auto kern, auto tc) {
+        using T = typename decltype(tc)::type;
+        if (ev0)
+            hipExtLaunchKernelGGL(kern, dim3(nb), dim3(256), 0, s, ev0, ev1, 0u, n, L.cap,
+                                  at<int>(ws, L.nbr), at<int>(ws, L.cnt), at<int>(ws, L.rev),
+                                  at<int>(ws, L.S_local), at<T>(ws, L.g), at<T>(ws, L.h), use_exp,
+                                  use_cheap, lambda, forces, e_exp, f_exp, f_cheap, sign, ka, la,
+                                  seg_args(ws, L));
         else
-            MLMIX_GATHER(double, false);
-    } else {
+            kern<<<nb, 256, 0, s>>>(n, L.cap, at<int>(ws, L.nbr), at<int>(ws, L.cnt),
+                                    at<int>(ws, L.rev), at<int>(ws, L.S_local), at<T>(ws, L.g),
+                                    at<T>(ws, L.h), use_exp, use_cheap, lambda, forces, e_exp,
+                                    f_exp, f_cheap, sign, ka, la, seg_args(ws, L));
+    };
+    auto by_kick = [&](auto tc) {
+        using T = typename decltype(tc)::type;
         if (kick)
-            MLMIX_GATHER(float, true);
+            go(L.nseg > 0 ? k_gather_blend<T, true, true> : k_gather_blend<T, true, false>, tc);
         else
-            MLMIX_GATHER(float, false);
-    }
-#undef MLMIX_GATHER
+            go(L.nseg > 0 ? k_gather_blend<T, false, true> : k_gather_blend<T, false, false>, tc);
+    };
+    if (c.prec == MLMIX_FP64)
+        by_kick(TypeTag<double>());
+    else
+        by_kick(TypeTag<float>());
     if (kick && !ka.defer && ka.part)
         k_reduce_final<<<1, 256, 0, s>>>(ka.part, (int)nb, ka.energies);
 }
