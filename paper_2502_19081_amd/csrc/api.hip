@@ -342,7 +342,8 @@ struct HostTables {
     int o3_nch2 = 0;
     std::vector<double> o3g, o3w, o3sw, o3gs;
     std::vector<int> o3o, o3mt, o3mtv, o3base, o3order, o3wbeg;
-    std::vector<int> o3rowv, o3rbeg;  // bins as flat row lists (vector-sparse FP32 form)
+    std::vector<int> o3rowv, o3rbeg;  // bins as flat row lists (vector-sparse form)
+    std::vector<double> o3wr;         // its reduced-precision weight fragments
     int o3rows_max = 0;               // longest such list
     bool o3rows_empty = false;        // some (block, m3) has no Gaunt entry
 };
@@ -485,6 +486,31 @@ static void build_o3(const mlmix_model_desc &d, HostTables &t, int waves)
                     }
                     t.o3w[(((p * nch2) + i) * 64 + l) * 4 + j] = v;
                 }
+    }
+    // reduced-precision fragments of the vector-sparse form (32-deep K steps):
+    // step s covers channels a = A_PER s .. A_PER s + A_PER - 1 (A_PER =
+    // min(8 / NJ, nch2)); for lane (c = l % 16, q = l / 16) value u < 8 is
+    // W[a = A_PER s + u / NJ][b = NJ q + u % NJ][c] for u < A_PER NJ, else
+    // zero; in the FP8 mode divided by the per-(block, c) scale.
+    // Stored [block][s][lane][8].
+    if (kind == 1) {
+        const int njv = nch2 / 4, aper = std::min(8 / njv, nch2), nst = nch2 / aper;
+        t.o3wr.assign(P * nst * 64 * 8, 0.0);
+        for (size_t p = 0; p < P; ++p)
+            for (int st = 0; st < nst; ++st)
+                for (int l = 0; l < 64; ++l)
+                    for (int u = 0; u < aper * njv; ++u) {
+                        const int c = l & 15, q = l >> 4;
+                        const int a = aper * st + u / njv, b = njv * q + u % njv;
+                        if (a >= nch || b >= nch || c >= nch)
+                            continue;
+                        double v = t.W[t.pb[p].w_off + ((size_t)a * nchp + b) * nchp + c];
+                        if (d.precision == MLMIX_FP8_CONTRACT) {
+                            const double sw = t.o3sw[p * 16 + c];
+                            v = sw > 0.0 ? v / sw : 0.0;
+                        }
+                        t.o3wr[(((p * nst) + st) * 64 + l) * 8 + u] = v;
+                    }
     }
     // work items to waves, for a tile's block list split over G = 1, 2, 4, 8
     // workgroups (4 G bins). An item is a range of m3 rows of one block: for
@@ -817,6 +843,7 @@ static std::vector<char> pack(const HostTables &t, DevModel &m)
     append_raw(blob, m.o3mtv, t.o3mtv);
     append_raw(blob, m.o3rowv, t.o3rowv);
     append_raw(blob, m.o3rbeg, t.o3rbeg);
+    append<float>(blob, m.o3wr, t.o3wr);
     append_raw(blob, m.o3base, t.o3base);
     append<float>(blob, m.o3w, t.o3w);
     append<float>(blob, m.o3ww, t.o3ww);

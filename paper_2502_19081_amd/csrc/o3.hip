@@ -56,6 +56,7 @@ struct O3Args {
     const int *rowv;      // bins as flat row lists: (first entry, count, block | m3 << 16, D column)
     const int *rbeg;      // per split G: 4 G + 1 offsets (in rows) into rowv
     float *sink;          // 64 floats past the partial-D buffer (masked lanes' stores)
+    const float *wr;      // reduced-precision fragments of the vector-sparse form
     const int *base;      // first (block, m3) row of each block
     const float *w;       // weight fragments [block][NC][64][4]
     const float *sw;      // FP8 weight scales [block][16]
@@ -391,9 +392,9 @@ __global__ void __launch_bounds__(64 * NW, NW == 4 ? 2 : 1)
     }
 }
 
-// ------------------------------------------------------ FP32, VALU sparse
+// ------------------------------------------------------ VALU sparse form
 //
-// The FP32 form of the single-species contraction used by default: the same
+// The single-species contraction used by default (every operand format): the same
 // tiles of 16 atoms and the same partial-D output, the work of a tile split
 // into per-wave bins of rows (block, m3) listed flat by the host, and the
 // sparse stage on the vector ALUs, leaving P directly in the registers the
@@ -407,22 +408,33 @@ __global__ void __launch_bounds__(64 * NW, NW == 4 ? 2 : 1)
 //                       read back lane by lane) and the A values of entry
 //                       e + 1 are read from LDS while entry e is accumulated;
 //  dense stage:         D[t][c] = sum_{a, j} P_t[a][NJ q + j]
-//                       W[a][NJ q + j][c] as nchp * NJ 16x16x4 MFMA steps
-//                       (K over exactly nchp^2 pairs), two accumulators in
-//                       a fixed alternation.
+//                       W[a][NJ q + j][c], two accumulators in a fixed
+//                       alternation: FP32 as nchp * NJ 16x16x4 MFMA steps
+//                       (K over exactly nchp^2 pairs); BF16 / FP8 as
+//                       nchp / A_PER 16x16x32 steps, step s taking the
+//                       channels a = A_PER s .. A_PER (s + 1) - 1 (A_PER =
+//                       min(8 / NJ, nchp)): lane (t, q) packs its values
+//                       P_t[a][NJ q + j] of those channels (zero padded to
+//                       eight), rounded to nearest even; FP8 E4M3 divides
+//                       them by the atom's scale max |P_t| / 240 over the
+//                       row (the four lanes of the atom compare theirs) and
+//                       the weights by the per-(block, c) scale max |W| / 240,
+//                       and multiplies both back into D.
 //
 // Two or three waves per SIMD: the vector sparse stage of one runs beside
 // the matrix-core dense stage of another. (Interleaving the dense steps of a
 // row with the next row's vector work inside one wave needs P and the
 // weights twice in registers: one wave per SIMD at 16 channels, measured
 // slower, 4.4 against 3.3 ms on 102,858 atoms in S, and no faster at 12.)
-template <int NC, int NW>
+template <int QM, int NC, int NW>
 __global__ void __launch_bounds__(64 * NW, NC <= 12 ? 3 : 2)
     k_ace_o3v(const int *__restrict__ hdr, O3Args a, const float *__restrict__ A,
               float *__restrict__ Dpart)
 {
 #pragma clang fp contract(off)
     constexpr int NTH = 64 * NW, NJ = NC / 4;
+    constexpr int APER = 8 / NJ < NC ? 8 / NJ : NC;  // channels a per 32-deep step
+    constexpr int NST = NC / APER;                   // 32-deep steps (BF16 / FP8)
     const int nS = hdr[H_NS];
     const int ntile = (nS + kO3Atoms - 1) / kO3Atoms;
     int G = 1, lg = 0;
@@ -446,7 +458,10 @@ __global__ void __launch_bounds__(64 * NW, NC <= 12 ? 3 : 2)
     const int4 *rows = reinterpret_cast<const int4 *>(a.rowv);
 
     float P[NC][NJ];
-    float wf[NC][NJ];
+    float wf[QM == 0 ? NC : 1][NJ];  // FP32 weight fragments
+    bf8v wb[QM == 1 ? NST : 1];      // BF16 weight fragments
+    long w8[QM == 2 ? NST : 1];      // FP8 weight fragments
+    float swc = 1.0f;                // FP8 weight scale of column c = m
     f4v acc0, acc1;
     f4v a1[2][NC / 4];
     float a2[2][NJ];
@@ -477,13 +492,37 @@ __global__ void __launch_bounds__(64 * NW, NC <= 12 ? 3 : 2)
         };
         int pcur = -1;
         // weight fragments of block p: lane (c = m, q) holds W[a = i][NJ q + j][c]
+        // (FP32), or the eight values of each 32-deep step (BF16 / FP8)
         auto weights = [&](int p) {
-            const float *wsrc = a.w + ((size_t)p * NC * 64 + lane) * 4;
+            if constexpr (QM == 0) {
+                const float *wsrc = a.w + ((size_t)p * NC * 64 + lane) * 4;
 #pragma unroll
-            for (int i = 0; i < NC; ++i)
+                for (int i = 0; i < NC; ++i)
 #pragma unroll
-                for (int j = 0; j < NJ; ++j)
-                    wf[i][j] = wsrc[i * 256 + j];
+                    for (int j = 0; j < NJ; ++j)
+                        wf[i][j] = wsrc[i * 256 + j];
+            } else {
+                const f4v *wsrc = reinterpret_cast<const f4v *>(a.wr) + ((size_t)p * NST * 64 + lane) * 2;
+#pragma unroll
+                for (int st = 0; st < NST; ++st) {
+                    const f4v x = wsrc[st * 128], y = wsrc[st * 128 + 1];
+                    if constexpr (QM == 1) {
+                        const bf2v p0 = __builtin_convertvector((f2v){x[0], x[1]}, bf2v);
+                        const bf2v p1 = __builtin_convertvector((f2v){x[2], x[3]}, bf2v);
+                        const bf2v p2 = __builtin_convertvector((f2v){y[0], y[1]}, bf2v);
+                        const bf2v p3 = __builtin_convertvector((f2v){y[2], y[3]}, bf2v);
+                        wb[st] = (bf8v){p0[0], p0[1], p1[0], p1[1], p2[0], p2[1], p3[0], p3[1]};
+                    } else {
+                        int lo = __builtin_amdgcn_cvt_pk_fp8_f32(x[0], x[1], 0, false);
+                        lo = __builtin_amdgcn_cvt_pk_fp8_f32(x[2], x[3], lo, true);
+                        int hi = __builtin_amdgcn_cvt_pk_fp8_f32(y[0], y[1], 0, false);
+                        hi = __builtin_amdgcn_cvt_pk_fp8_f32(y[2], y[3], hi, true);
+                        w8[st] = (long)(((unsigned long)(unsigned)hi << 32) | (unsigned)lo);
+                    }
+                }
+                if constexpr (QM == 2)
+                    swc = a.sw[p * 16 + m];
+            }
             pcur = p;
         };
         // entries of the current and the next row alternate between two
@@ -512,14 +551,18 @@ __global__ void __launch_bounds__(64 * NW, NC <= 12 ? 3 : 2)
         // row) write to a sink past the buffer's end, so that the stores need
         // no branch
         int dcol = 0;
+        float psc = 1.0f;  // FP8: this lane's atom scale of the last row
         auto store_d = [&](bool real) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int t = 4 * q + v;
+                float d = acc0[v] + acc1[v];
+                if constexpr (QM == 2)
+                    d = d * (__shfl(psc, t) * swc);  // atom t's scale sits in lane t
                 float *dst = (real && t < na && m < nch)
                                  ? Dpart + (size_t)(s0 + t) * a.dp_stride + dcol + m
                                  : a.sink + lane;
-                *dst = acc0[v] + acc1[v];
+                *dst = d;
             }
         };
         acc0 = (f4v){0.f, 0.f, 0.f, 0.f};
@@ -601,15 +644,59 @@ __global__ void __launch_bounds__(64 * NW, NC <= 12 ? 3 : 2)
             // P_t[i][NJ q + j], lane (c = m, q) the weight W[i][NJ q + j][c]
             acc0 = (f4v){0.f, 0.f, 0.f, 0.f};
             acc1 = (f4v){0.f, 0.f, 0.f, 0.f};
+            if constexpr (QM == 0) {
 #pragma unroll
-            for (int i = 0; i < NC; ++i)
+                for (int i = 0; i < NC; ++i)
 #pragma unroll
-                for (int j = 0; j < NJ; ++j) {
-                    if (((i * NJ + j) & 1) == 0)
-                        acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(P[i][j], wf[i][j], acc0, 0, 0, 0);
-                    else
-                        acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(P[i][j], wf[i][j], acc1, 0, 0, 0);
+                    for (int j = 0; j < NJ; ++j) {
+                        if (((i * NJ + j) & 1) == 0)
+                            acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(P[i][j], wf[i][j], acc0, 0, 0, 0);
+                        else
+                            acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(P[i][j], wf[i][j], acc1, 0, 0, 0);
+                    }
+            } else {
+                // eight values of step st: u < APER NJ -> P[APER st + u / NJ][u % NJ]
+                auto val = [&](int st, int u, float sc) -> float {
+                    return u < APER * NJ ? P[APER * st + u / NJ][u % NJ] * sc : 0.0f;
+                };
+                float inv = 1.0f;
+                if constexpr (QM == 2) {
+                    // the atom's scale: max |P_t| over its four lanes
+                    float mx = 0.0f;
+#pragma unroll
+                    for (int i = 0; i < NC; ++i)
+#pragma unroll
+                        for (int j = 0; j < NJ; ++j)
+                            mx = fmaxf(mx, fabsf(P[i][j]));
+                    mx = fmaxf(mx, __shfl_xor(mx, 16));
+                    mx = fmaxf(mx, __shfl_xor(mx, 32));
+                    psc = mx * (1.0f / 240.0f);
+                    inv = psc > 0.0f ? 1.0f / psc : 0.0f;
                 }
+#pragma unroll
+                for (int st = 0; st < NST; ++st) {
+                    f4v r;
+                    if constexpr (QM == 1) {
+                        const bf2v p0 = __builtin_convertvector((f2v){val(st, 0, 1.f), val(st, 1, 1.f)}, bf2v);
+                        const bf2v p1 = __builtin_convertvector((f2v){val(st, 2, 1.f), val(st, 3, 1.f)}, bf2v);
+                        const bf2v p2 = __builtin_convertvector((f2v){val(st, 4, 1.f), val(st, 5, 1.f)}, bf2v);
+                        const bf2v p3 = __builtin_convertvector((f2v){val(st, 6, 1.f), val(st, 7, 1.f)}, bf2v);
+                        const bf8v pv = {p0[0], p0[1], p1[0], p1[1], p2[0], p2[1], p3[0], p3[1]};
+                        r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(pv, wb[st], (st & 1) ? acc1 : acc0, 0, 0, 0);
+                    } else {
+                        int lo = __builtin_amdgcn_cvt_pk_fp8_f32(val(st, 0, inv), val(st, 1, inv), 0, false);
+                        lo = __builtin_amdgcn_cvt_pk_fp8_f32(val(st, 2, inv), val(st, 3, inv), lo, true);
+                        int hi = __builtin_amdgcn_cvt_pk_fp8_f32(val(st, 4, inv), val(st, 5, inv), 0, false);
+                        hi = __builtin_amdgcn_cvt_pk_fp8_f32(val(st, 6, inv), val(st, 7, inv), hi, true);
+                        const long pv = (long)(((unsigned long)(unsigned)hi << 32) | (unsigned)lo);
+                        r = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(pv, w8[st], (st & 1) ? acc1 : acc0, 0, 0, 0);
+                    }
+                    if (st & 1)
+                        acc1 = r;
+                    else
+                        acc0 = r;
+                }
+            }
         };
         for (int k = 0; k < nr; k += 2) {
             row(k, std::integral_constant<int, 0>());
@@ -948,6 +1035,7 @@ void launch_ace_o3(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L, hip
     a.mtv = reinterpret_cast<const int *>(base + m.o3mtv);
     a.rowv = reinterpret_cast<const int *>(base + m.o3rowv);
     a.rbeg = reinterpret_cast<const int *>(base + m.o3rbeg);
+    a.wr = reinterpret_cast<const float *>(base + m.o3wr);
     a.sink = at<float>(ws, L.dpart) + (size_t)std::max(L.scap, 1) * (m.dp_stride > 0 ? m.dp_stride : 1);
     a.base = reinterpret_cast<const int *>(base + m.o3base);
     a.w = reinterpret_cast<const float *>(base + m.o3w);
@@ -968,33 +1056,41 @@ void launch_ace_o3(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L, hip
     const float *A = at<float>(ws, L.A);
     float *D = at<float>(ws, L.dpart);
     const long items = (((long)L.n + kO3Atoms - 1) / kO3Atoms) * kO3MaxSplit;
-    if (c.qmode == 0 && c.o3v) {
-        // FP32 with the vector sparse stage: as many resident workgroups as
-        // the registers allow (waves per SIMD: three up to 12 channels, else two)
+    if (c.o3v) {
+        // the vector sparse stage: as many resident workgroups as the
+        // registers allow (waves per SIMD: three up to 12 channels, else two)
         const size_t lds = o3v_lds_bytes(c);
-        auto go = [&](auto nc) {
-            constexpr int NC = decltype(nc)::value;
+        auto go = [&](auto qm, auto nc) {
+            constexpr int QM = decltype(qm)::value, NC = decltype(nc)::value;
             auto launch = [&](auto nw) {
                 constexpr int NW = decltype(nw)::value;
                 const int per_cu = std::max(1, 4 * (NC <= 12 ? 3 : 2) / NW);
                 const int grid = (int)std::min<long>(std::max<long>(items, 1), 256L * per_cu);
                 if (ev0)
-                    hipExtLaunchKernelGGL(k_ace_o3v<NC, NW>, dim3(grid), dim3(64 * NW),
+                    hipExtLaunchKernelGGL(k_ace_o3v<QM, NC, NW>, dim3(grid), dim3(64 * NW),
                                           (uint32_t)lds, s, ev0, ev1, 0u, hdr, a, A, D);
                 else
-                    k_ace_o3v<NC, NW><<<grid, 64 * NW, lds, s>>>(hdr, a, A, D);
+                    k_ace_o3v<QM, NC, NW><<<grid, 64 * NW, lds, s>>>(hdr, a, A, D);
             };
             if (c.o3_waves == 8)
                 launch(std::integral_constant<int, 8>());
             else
                 launch(std::integral_constant<int, 4>());
         };
-        switch (m.nchp) {
-        case 4: go(std::integral_constant<int, 4>()); break;
-        case 8: go(std::integral_constant<int, 8>()); break;
-        case 12: go(std::integral_constant<int, 12>()); break;
-        default: go(std::integral_constant<int, 16>()); break;
-        }
+        auto by_width = [&](auto qm) {
+            switch (m.nchp) {
+            case 4: go(qm, std::integral_constant<int, 4>()); break;
+            case 8: go(qm, std::integral_constant<int, 8>()); break;
+            case 12: go(qm, std::integral_constant<int, 12>()); break;
+            default: go(qm, std::integral_constant<int, 16>()); break;
+            }
+        };
+        if (c.qmode == 1)
+            by_width(std::integral_constant<int, 1>());
+        else if (c.qmode == 2)
+            by_width(std::integral_constant<int, 2>());
+        else
+            by_width(std::integral_constant<int, 0>());
         return;
     }
     const size_t lds = o3_lds_bytes(c);
