@@ -22,6 +22,34 @@ struct Uf3Args {
     const T *p2, *p3;  // per-span B-spline polynomial coefficients [npts - 1][4][4]
 };
 
+// Four consecutive coefficients (16-byte aligned for float, two 16-byte
+// loads for double).
+__device__ __forceinline__ void load4(const float *p, float v[4])
+{
+    const float4 q = *reinterpret_cast<const float4 *>(p);
+    v[0] = q.x;
+    v[1] = q.y;
+    v[2] = q.z;
+    v[3] = q.w;
+}
+
+__device__ __forceinline__ void load4(const double *p, double v[4])
+{
+    const double2 q0 = *reinterpret_cast<const double2 *>(p);
+    const double2 q1 = *reinterpret_cast<const double2 *>(p + 2);
+    v[0] = q0.x;
+    v[1] = q0.y;
+    v[2] = q1.x;
+    v[3] = q1.y;
+}
+
+// Square root and reciprocal of the 3-body leg-pair distance: the hardware
+// instructions (1 ulp) in FP32, the correctly rounded ones in FP64.
+__device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double fast_sqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double fast_rcp(double x) { return 1.0 / x; }
+
 // The four non-zero clamped uniform cubic B-splines at x and their
 // derivatives from the per-span cubic coefficients (Horner, no division):
 // span sp = clamp(floor(x / h), 0, npts - 2), t = x / h - sp, basis r of the
@@ -37,7 +65,9 @@ __device__ __forceinline__ void bspline4p(T x, T ih, int npts, const T *__restri
     const T *c = poly + 16 * sp;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        const T a0 = c[4 * r], a1 = c[4 * r + 1], a2 = c[4 * r + 2], a3 = c[4 * r + 3];
+        T cr[4];
+        load4(c + 4 * r, cr);  // 16-byte aligned (spans of 16 values)
+        const T a0 = cr[0], a1 = cr[1], a2 = cr[2], a3 = cr[3];
         N[r] = ((a3 * t + a2) * t + a1) * t + a0;
         dN[r] = ((T(3) * a3 * t + T(2) * a2) * t + a1) * ih;
     }
@@ -80,27 +110,6 @@ __device__ __forceinline__ void wave_sync_lds_u()
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// Four consecutive coefficients (16-byte aligned for float, two 16-byte
-// loads for double).
-__device__ __forceinline__ void load4(const float *p, float v[4])
-{
-    const float4 q = *reinterpret_cast<const float4 *>(p);
-    v[0] = q.x;
-    v[1] = q.y;
-    v[2] = q.z;
-    v[3] = q.w;
-}
-
-__device__ __forceinline__ void load4(const double *p, double v[4])
-{
-    const double2 q0 = *reinterpret_cast<const double2 *>(p);
-    const double2 q1 = *reinterpret_cast<const double2 *>(p + 2);
-    v[0] = q0.x;
-    v[1] = q0.y;
-    v[2] = q1.x;
-    v[3] = q1.y;
 }
 
 // Per-wave LDS arrays of the cheap kernel, in elements of T: leg vectors d3
@@ -259,6 +268,7 @@ __global__ void __launch_bounds__(256)
         if (nb > 0) {
             const T *cz = c3x + (size_t)zi * nb * nb * (nb - 3) * 4;
             const int hh = n3 >> 1;
+            const float rn3 = 1.0f / (float)(n3 > 0 ? n3 : 1);
             const int ngrid = n3 * hh;
             const bool even = (n3 & 1) == 0;
             T gx = T(0), gy = T(0), gz = T(0);  // lane x < n3: leg x
@@ -266,7 +276,9 @@ __global__ void __launch_bounds__(256)
                 const int p = t0 + lane;
                 T cj0 = T(0), cj1 = T(0), cj2 = T(0), ck0 = T(0), ck1 = T(0), ck2 = T(0);
                 if (p < ngrid) {
-                    const int o = p / n3 + 1;
+                    // o = p / n3 + 1 without an integer division (the float
+                    // quotient of p + 1/2 sits at least 1/(2 n3) from an integer)
+                    const int o = (int)(((float)p + 0.5f) * rn3) + 1;
                     const int j = p - (o - 1) * n3;
                     if (!(even && o == hh && j >= hh)) {
                         int k = j + o;
@@ -275,7 +287,7 @@ __global__ void __launch_bounds__(256)
                         const T dj0 = d3[j * 3], dj1 = d3[j * 3 + 1], dj2 = d3[j * 3 + 2];
                         const T dk0 = d3[k * 3], dk1 = d3[k * 3 + 1], dk2 = d3[k * 3 + 2];
                         const T e0 = dk0 - dj0, e1 = dk1 - dj1, e2 = dk2 - dj2;
-                        const T rjk = sqrt(e0 * e0 + e1 * e1 + e2 * e2);
+                        const T rjk = fast_sqrt(e0 * e0 + e1 * e1 + e2 * e2);
                         int fs;
                         T Ns[4], dNs[4];
                         bspline4p<T>(rjk, a.ih3c, a.nk3, pp3, fs, Ns, dNs);
@@ -310,7 +322,7 @@ __global__ void __launch_bounds__(256)
                             V3 += Bj[pa] * u1;
                         }
                         Ep += V;
-                        const T irjk = T(1) / rjk;
+                        const T irjk = fast_rcp(rjk);
                         const T aj = V1 * ir3[j], ak = V2 * ir3[k], ajk = V3 * irjk;
                         cj0 = aj * dj0 - ajk * e0;
                         cj1 = aj * dj1 - ajk * e1;
