@@ -1322,7 +1322,10 @@ static int compute_impl(mlmix_ctx *ctx, hipStream_t s, void *ws, const WsLayout 
     const Ctx &c = ctx->c;
     int m = (int)(mode & 0xff);
     bool energy_only = (mode & MLMIX_ENERGY_ONLY) != 0;
-    bool fork = (mode & MLMIX_SINGLE_STREAM) == 0;
+    // the second stream only beside the expensive chain of a mixed step: in
+    // the all-cheap and all-expensive modes there is nothing for its kernels
+    // to overlap with, and the fork and join events cost more than they save
+    bool fork = (mode & MLMIX_SINGLE_STREAM) == 0 && m == MLMIX_MODE_MIXED;
     const bool masked = (mode & MLMIX_CHEAP_MASKED) != 0 && m == MLMIX_MODE_MIXED;
     SideStream sd;
     if (fork) {
