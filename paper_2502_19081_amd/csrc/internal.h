@@ -170,10 +170,11 @@ struct Ctx {
     int basis_mfma = 1;    // atomic basis and pair adjoint on the matrix cores (FP32)
     int basis_chunks = -1; // basis in 64-slot passes: -1 above 65,536 atoms, 0 never, 1 always
     // second-stream fork after the rows (0), after the basis (1), or recorded
-    // after the rows and issued after the compaction (2: a captured graph then
-    // keeps the expensive chain on the first hardware queue; 148-150 us
-    // against 153-155 us per step on 8,193 atoms, no difference on 1M atoms)
-    int fork_at = 2;
+    // after the rows and issued after the compaction (2). Measured per mixed
+    // step on 8,193 atoms with the vector-sparse contraction: 100.2 / 100.7 /
+    // 101.0 us at 0 against 106.7 / 105.9 / 105.6 us at 2 (alternating runs;
+    // an earlier, longer expensive chain preferred 2)
+    int fork_at = 0;
     // workgroup cap of the cheap-potential kernel on the second stream
     // (grid-stride loop): -1 automatic, 0 uncapped. The best cap follows the
     // length of the expensive chain beside it; measured per mixed step on
