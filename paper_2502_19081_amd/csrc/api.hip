@@ -928,6 +928,19 @@ static void layout_arrays(const Ctx &c, WsLayout &L, size_t ncell, size_t nrec, 
     take(L.M_idx, nn * sizeof(int));
     take(L.S_local, nn * sizeof(int));
     take(L.cand, nn);
+    // superblocks of about 8 A (at most 32 per dimension) for the region lists
+    if (nseg == 0) {
+        size_t nsb = 1;
+        for (int k = 0; k < 3; ++k) {
+            const double len = L.grid.cs[k] * L.grid.nc[k];
+            L.rgn[k] = std::max(1, std::min(32, (int)std::floor(len / 8.0)));
+            nsb *= (size_t)L.rgn[k];
+        }
+        take(L.rgrid, nsb * (kRegionGridCap + 1) * sizeof(int));
+    } else {
+        L.rgn[0] = L.rgn[1] = L.rgn[2] = 0;
+        take(L.rgrid, sizeof(int));
+    }
     const size_t ns = (size_t)(L.scap > 0 ? L.scap : 1);
     take(L.A, ns * c.m.KAt * tsz);
     take(L.dEdA, ns * c.m.KAt * tsz);

@@ -175,7 +175,30 @@ __device__ __forceinline__ void atom_lambda(const double *__restrict__ pos, int 
         a0 = G.off;
         na = G.n;
     }
-    for (int g = g0; g < g1; ++g) {
+    // single systems with many regions: only the regions listed for the
+    // atom's superblock (every region within the buffer prefilter distance
+    // of it); the largest blend value and the prefilter bit do not depend on
+    // the order in which regions are visited
+    const int *list = nullptr;
+    int nlist = -1;
+    if constexpr (!SEG) {
+        if (ra.rgrid) {
+            int sb = 0;
+            for (int k = 2; k >= 0; --k) {
+                double x = xi[k];
+                if (b.per[k])
+                    x = x - b.L[k] * floor(x / b.L[k]);
+                int q = (int)(x * ra.rgn[k] / b.L[k]);
+                q = q < 0 ? 0 : (q >= ra.rgn[k] ? ra.rgn[k] - 1 : q);
+                sb = sb * ra.rgn[k] + q;
+            }
+            list = ra.rgrid + (size_t)sb * (kRegionGridCap + 1);
+            nlist = list[0];  // -1: the list overflowed, every region
+        }
+    }
+    const int nvisit = nlist >= 0 ? nlist : g1 - g0;
+    for (int iv = 0; iv < nvisit; ++iv) {
+        const int g = nlist >= 0 ? list[1 + iv] : g0 + iv;
         mlmix_region r = ra.reg[g];
         if (r.type == MLMIX_REGION_SEEDED) {
             ++n_seeded;
@@ -243,6 +266,58 @@ __device__ __forceinline__ void atom_lambda(const double *__restrict__ pos, int 
     ra.cand[i] = (best == 0.0 && near) ? 1 : 0;
 }
 
+
+// Region lists per superblock (single systems with many geometric regions):
+// one thread per superblock of the box lists every region whose buffer
+// prefilter sphere (r_core + r_blend + r_buffer, plus a margin for rounding)
+// reaches the superblock's box (minimum image along periodic dimensions; an
+// axis region ignores its axis). A list longer than kRegionGridCap is marked
+// -1 and its atoms test every region.
+__global__ void __launch_bounds__(256) k_region_grid(const double *__restrict__ pos, int n, Box b,
+                                                     const mlmix_region *__restrict__ reg, int nreg,
+                                                     double r_buffer, int g0, int g1, int g2,
+                                                     int *__restrict__ lists)
+{
+#pragma clang fp contract(off)
+    const int sb = blockIdx.x * blockDim.x + threadIdx.x;
+    if (sb >= g0 * g1 * g2)
+        return;
+    const int q[3] = {sb % g0, (sb / g0) % g1, sb / (g0 * g1)};
+    const int gn[3] = {g0, g1, g2};
+    int *out = lists + (size_t)sb * (kRegionGridCap + 1);
+    int cnt = 0;
+    for (int g = 0; g < nreg; ++g) {
+        const mlmix_region r = reg[g];
+        double c[3] = {r.center[0], r.center[1], r.center[2]};
+        if (r.follow_atom >= 0 && r.follow_atom < n) {
+            c[0] = pos[r.follow_atom];
+            c[1] = pos[n + r.follow_atom];
+            c[2] = pos[2 * n + r.follow_atom];
+        }
+        double d2 = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            if (r.type == 1 && r.axis == k)
+                continue;
+            const double w = b.L[k] / gn[k];
+            const double mid = (q[k] + 0.5) * w;
+            double d = c[k] - mid;
+            if (b.per[k]) {
+                const double h = 0.5 * b.L[k];
+                d = d - b.L[k] * floor((d + h) / b.L[k]);  // into [-L/2, L/2)
+            }
+            d = fabs(d) - 0.5 * w;
+            if (d > 0.0)
+                d2 = d2 + d * d;
+        }
+        const double far = r.r_core + r.r_blend + r_buffer + 1.0e-3;
+        if (d2 < far * far) {
+            if (cnt < kRegionGridCap)
+                out[1 + cnt] = g;
+            ++cnt;
+        }
+    }
+    out[0] = cnt <= kRegionGridCap ? cnt : -1;
+}
 
 // One thread per atom: the mixing weight pass (every call), then, when the
 // list is rebuilt, cell binning into fixed-capacity buckets (g.bucket
@@ -693,6 +768,15 @@ void launch_neighbors(hipStream_t s, void *ws, const WsLayout &L, const Box &b, 
     RegionArgs r = ra;
     r.cand = at<uint8_t>(ws, L.cand);
     r.seedcore = at<uint8_t>(ws, L.seedcore);
+    if (L.nseg == 0 && ra.mode == MLMIX_MODE_MIXED && !ra.seeded && ra.nreg >= kRegionGridMin) {
+        const int nsb = L.rgn[0] * L.rgn[1] * L.rgn[2];
+        int *lists = at<int>(ws, L.rgrid);
+        k_region_grid<<<(nsb + 255) / 256, 256, 0, s>>>(pos, n, b, ra.reg, ra.nreg, ra.r_buffer,
+                                                         L.rgn[0], L.rgn[1], L.rgn[2], lists);
+        r.rgrid = lists;
+        for (int k = 0; k < 3; ++k)
+            r.rgn[k] = L.rgn[k];
+    }
     const Seg sg = seg_args(ws, L);
     if (L.nseg > 0)
         k_bin_bucket<true><<<(n + 255) / 256, 256, 0, s>>>(pos, n, b, g, force_rebuild, hdr, count,

@@ -113,6 +113,10 @@ struct WsLayout {
     size_t nbr, cnt, rev, ref_pos, S_idx, M_idx, S_local, cand;
     size_t A, dEdA, g, h, red, dpart;
     size_t seg_of, segs, seg_status, seg_red;  // batch workspaces only
+    // region lists per superblock of the box (single systems): rgn[k]
+    // superblocks along dimension k, each (count or -1, kRegionGridCap ids)
+    size_t rgrid;
+    int rgn[3];
     size_t total;
 };
 
@@ -209,6 +213,11 @@ __host__ __device__ inline int sp_clamp(int z, int ns) { return z < 0 ? 0 : (z >
 
 // Inputs and outputs of the per-atom mixing weight pass (lambda, masks and
 // buffer candidates), which runs inside the binning kernel.
+// Regions per superblock list, and the region count from which the mixing
+// weights use the lists (below it every atom tests every region)
+constexpr int kRegionGridCap = 31;
+constexpr int kRegionGridMin = 8;
+
 struct RegionArgs {
     int mode;
     const int32_t *species;
@@ -226,6 +235,8 @@ struct RegionArgs {
     const double *red_part;
     int red_nb;
     double *red_out;
+    const int *rgrid = nullptr;  // region lists per superblock (nullptr: every region)
+    int rgn[3] = {0, 0, 0};       // superblocks per dimension
 };
 constexpr int kMaxSeeded = 8;  // seeded regions per evaluation
 
