@@ -401,17 +401,18 @@ __global__ void __launch_bounds__(256)
 // APB S atoms per 256-thread workgroup (1: threads over the atomic-basis
 // entries, for small S where latency rules; 4: a wave per atom, lanes over
 // the entries, for large S where the staged tables are shared by four atoms):
-// D3 = sum over the l-blocks' partial D (fixed order), D2 from the order-2
+// D3 = sum of the partial-D columns of the (l3, m3) in the listed order (the
+// column set of the contraction that wrote them), D2 from the order-2
 // coefficients, dE/dA = c1 + 2 D2 + 3 D3 and E = c0 + sum A (c1 + D2 + D3).
-// The atom's A row, the block offsets, the per-l block ranges and (when
-// they fit, stage_c2) the order-2 coefficients transposed to [z][l][b][c]
-// are staged in LDS, so that a lane's loads are independent LDS reads plus
-// coalesced reads of the partial D.
+// The atom's A row, the column set and (when they fit, stage_c2) the
+// order-2 coefficients transposed to [z][l][b][c] are staged in LDS, so that
+// a lane's loads are independent LDS reads plus coalesced reads of the
+// partial D.
 template <typename T, int APB>
 __global__ void __launch_bounds__(256)
     k_ace_finalize(const int32_t *__restrict__ species, const int *__restrict__ S_idx,
-                   const int *__restrict__ hdr, AceArgs<T> a, const int *__restrict__ dp_off,
-                   int n_pb, int stage_c2, int dp_stride, const T *__restrict__ A,
+                   const int *__restrict__ hdr, AceArgs<T> a, DSumSel ds, int stage_c2,
+                   int dp_stride, const T *__restrict__ A,
                    const T *__restrict__ Dpart, T *__restrict__ dEdA, double *__restrict__ e_exp)
 {
     constexpr int TPA = 256 / APB;  // threads per atom
@@ -426,21 +427,30 @@ __global__ void __launch_bounds__(256)
     T *As = reinterpret_cast<T *>(smem_raw) + (size_t)sub * KAt;           // [APB][KAt]
     T *Ct = reinterpret_cast<T *>(smem_raw) + (size_t)APB * KAt;           // [ns][L1][b][c]
     const size_t nC = stage_c2 ? (size_t)a.ns * L1 * nch * nch : 0;
-    int *dpo = reinterpret_cast<int *>(Ct + nC);                           // [n_pb]
-    int *plo = dpo + n_pb, *phi = plo + L1;                                // [L1] each
+    const int L2 = L1 * L1;
+    int *tbl = reinterpret_cast<int *>(Ct + nC);  // [L2 + 1] run offsets, then the columns
+    const int *dcols = tbl + L2 + 1;
     __shared__ double esum[4];
+    // the column set: the split the vector-sparse contraction chose for this
+    // |S| (it chooses it the same way), else the per-(block, m3) set
+    const int *dset;
+    {
+        const int ntile = (nS + kO3Atoms - 1) / kO3Atoms;
+        int G = 1, lg = 0;
+        while (G < ds.max_split && ntile * G < ds.grid) {
+            G <<= 1;
+            ++lg;
+        }
+        dset = ds.tab + ds.off[lg];
+    }
     if (a.order >= 2)
         for (int e = tid; e < (int)nC; e += 256) {
             const int c = e % nch, r = e / nch;
             const int b = r % nch, zl = r / nch;
             Ct[e] = a.c2s[((size_t)zl * nch + c) * nch + b];
         }
-    for (int e = tid; e < n_pb; e += 256)
-        dpo[e] = dp_off[e];
-    if (tid < L1) {
-        plo[tid] = a.pb_lo[tid];
-        phi[tid] = a.pb_hi[tid];
-    }
+    for (int e = tid; e < L2 + 1 + dset[L2]; e += 256)
+        tbl[e] = dset[e];
     if (s < nS)
         for (int e = st; e < KAt; e += TPA)
             As[e] = A[(size_t)s * KAt + e];
@@ -480,16 +490,17 @@ __global__ void __launch_bounds__(256)
         if (a.order >= 3) {
             // all block loads first (independent), then the sum in block order
             constexpr int kPre = 16;
-            const int p0 = plo[l], np = phi[l] - p0;
+            const int k0 = tbl[lm], nk = tbl[lm + 1] - k0;
+            const int *cl = dcols + k0;
             T v[kPre];
 #pragma unroll
             for (int k = 0; k < kPre; ++k)
-                v[k] = k < np ? Ds[dpo[p0 + k] + m3 * nch + c] : T(0);
+                v[k] = k < nk ? Ds[cl[k] + c] : T(0);
 #pragma unroll
             for (int k = 0; k < kPre; ++k)
                 D3 += v[k];
-            for (int p = p0 + kPre; p < phi[l]; ++p)
-                D3 += Ds[dpo[p] + m3 * nch + c];
+            for (int k = kPre; k < nk; ++k)
+                D3 += Ds[cl[k] + c];
         }
         const T Av = As[e];
         dEdA[(size_t)s * KAt + e] = c1t + T(2) * D2 + T(3) * D3;
@@ -944,8 +955,20 @@ __global__ void __launch_bounds__(256)
         }
 }
 
+// The finalisation inside the pair adjoint (FIN): the wave computes its
+// atom's dE/dA from the partial D as the finalisation kernel does (same
+// terms, same order of the sums) instead of reading it back.
+struct FinArgs {
+    const float *A;      // [S][KAt] atomic basis
+    const float *Dpart;  // [S][dp_stride] partial D
+    int dp_stride;
+    DSumSel ds;          // the column set of the contraction that wrote it
+    double *e_exp;       // site energies (NULL: gradient only)
+};
+
 // Pair adjoint on the matrix cores (FP32 potentials): one wave per S atom.
-// G = dE/dA of the atom (times its weight) is staged transposed, [(z, n)][lm].
+// G = dE/dA of the atom (times its weight) is staged transposed, [(z, n)][lm]
+// (FIN: computed here from A and the partial D, with the site energy).
 // The valid pairs of the whole row (partner in S, inside the cutoff) are
 // compacted by ballot first (geometry in LDS), 64 per round, and lane q
 // builds the species-masked rows R and dR of compacted pair q;
@@ -953,14 +976,15 @@ __global__ void __launch_bounds__(256)
 // channels); each pair's lane then contracts its rows with the harmonics and
 // their gradients, g = rad u + (v - u (u.v)) / r with rad = sum S_D Y and
 // v = sum S_R grad_u Y, and writes g to its list slot (0 for other slots).
-template <int MT, int NT, bool SEG>
+template <int MT, int NT, bool SEG, bool FIN>
 __global__ void __launch_bounds__(256)
     k_ace_pairgrad_mfma(const double *__restrict__ pos, int n, Box b0,
                         const int32_t *__restrict__ species, int cap, const int *__restrict__ nbr,
                         const int *__restrict__ cnt, const int *__restrict__ S_idx,
                         const int *__restrict__ S_local, const int *__restrict__ hdr,
                         AceArgs<float> a, int wpb, const float *__restrict__ dEdA,
-                        const double *__restrict__ weights, float *__restrict__ g, Seg sg)
+                        const double *__restrict__ weights, float *__restrict__ g, Seg sg,
+                        FinArgs fa)
 {
     constexpr int RW = 16 * MT + 1, YW = 16 * NT + 1;
     constexpr int PAIR = 64 * RW * 2 > 64 * YW * 2 ? 64 * RW * 2 : 64 * YW * 2;
@@ -980,9 +1004,78 @@ __global__ void __launch_bounds__(256)
     const Box b = seg_box<SEG, true>(b0, sg, i);
     const float wgt = weights ? float(weights[i]) : 1.0f;
     const int nrad = a.nrad, nch = a.nchan, L2 = a.L2, nchp = a.nchp;
-    for (int e = lane; e < 16 * MT * 16 * NT; e += 64) {
-        const int ch = e / (16 * NT), lm = e - ch * (16 * NT);
-        Gt[ch * YW + lm] = (ch < nch && lm < L2) ? dEdA[(size_t)s * a.KAt + lm * nchp + ch] * wgt : 0.f;
+    if constexpr (FIN) {
+        // the atom's A row and the partial-D column set in the pair-row
+        // space (free until the first round), then per (channel, lm):
+        // dE/dA = c1 + 2 D2 + 3 D3 and the site energy c0 + sum A (c1 + D2 + D3)
+        const int z = sp_clamp(species[i], a.ns);
+        float *As = base;                                   // [L2][nchp]
+        int *tbl = reinterpret_cast<int *>(base + a.KAt);   // [L2 + 1] run offsets, columns
+        const int *dset;
+        {
+            const int ntile = (nS + kO3Atoms - 1) / kO3Atoms;
+            int G = 1, lg = 0;
+            while (G < fa.ds.max_split && ntile * G < fa.ds.grid) {
+                G <<= 1;
+                ++lg;
+            }
+            dset = fa.ds.tab + fa.ds.off[lg];
+        }
+        for (int e = lane; e < a.KAt; e += 64)
+            As[e] = fa.A[(size_t)s * a.KAt + e];
+        for (int e = lane; e < L2 + 1 + dset[L2]; e += 64)
+            tbl[e] = dset[e];
+        wave_sync_ace();
+        const float *Ds = fa.Dpart + (size_t)s * fa.dp_stride;
+        const int *dcols = tbl + L2 + 1;
+        double es = 0.0;
+        for (int e = lane; e < 16 * MT * 16 * NT; e += 64) {
+            const int ch = e / (16 * NT), lm = e - ch * (16 * NT);
+            float v = 0.f;
+            if (ch < nch && lm < L2) {
+                int l = (int)sqrtf((float)lm);
+                l -= (l * l > lm);
+                l += ((l + 1) * (l + 1) <= lm);
+                const float c1t = (l == 0) ? a.c1[z * nch + ch] : 0.f;
+                float D2 = 0.f, D3 = 0.f;
+                if (a.order >= 2) {
+                    const float *C = a.c2s + (((size_t)z * a.L1 + l) * nch + ch) * nch;
+                    const float *Al = As + lm * nchp;
+                    for (int bb = 0; bb < nch; ++bb)
+                        D2 += C[bb] * Al[bb];
+                }
+                if (a.order >= 3) {
+                    constexpr int kPre = 8;
+                    const int k0 = tbl[lm], nk = tbl[lm + 1] - k0;
+                    const int *cl = dcols + k0;
+                    float pv[kPre];
+#pragma unroll
+                    for (int k = 0; k < kPre; ++k)
+                        pv[k] = k < nk ? Ds[cl[k] + ch] : 0.f;
+#pragma unroll
+                    for (int k = 0; k < kPre; ++k)
+                        D3 += pv[k];
+                    for (int k = kPre; k < nk; ++k)
+                        D3 += Ds[cl[k] + ch];
+                }
+                v = c1t + 2.f * D2 + 3.f * D3;
+                es += (double)(As[lm * nchp + ch] * (c1t + D2 + D3));
+            }
+            Gt[ch * YW + lm] = v * wgt;
+        }
+        if (fa.e_exp) {
+#pragma unroll
+            for (int d = 32; d > 0; d >>= 1)
+                es += __shfl_xor(es, d);
+            if (lane == 0)
+                fa.e_exp[i] = (double)a.c0[z] + es;
+        }
+        wave_sync_ace();  // the pair rows overwrite As
+    } else {
+        for (int e = lane; e < 16 * MT * 16 * NT; e += 64) {
+            const int ch = e / (16 * NT), lm = e - ch * (16 * NT);
+            Gt[ch * YW + lm] = (ch < nch && lm < L2) ? dEdA[(size_t)s * a.KAt + lm * nchp + ch] * wgt : 0.f;
+        }
     }
     const int c = cnt[i];
     const int *row = nbr + (size_t)i * cap;
@@ -1145,35 +1238,76 @@ static void basis_mfma_launch(hipStream_t s, const Ctx &c, void *ws, const WsLay
 template <int MT, int NT>
 static void pairgrad_mfma_launch(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L,
                                  const Box &b, const double *pos, const int32_t *species,
-                                 const double *weights, const AceArgs<float> &a)
+                                 const double *weights, const AceArgs<float> &a,
+                                 const FinArgs *fin)
 {
     const size_t per = pairgrad_mfma_lds<MT, NT>();
     const int wpb = mfma_wpb(per);
-    auto kern = L.nseg > 0 ? k_ace_pairgrad_mfma<MT, NT, true> : k_ace_pairgrad_mfma<MT, NT, false>;
+    auto kern = fin ? (L.nseg > 0 ? k_ace_pairgrad_mfma<MT, NT, true, true>
+                                  : k_ace_pairgrad_mfma<MT, NT, false, true>)
+                    : (L.nseg > 0 ? k_ace_pairgrad_mfma<MT, NT, true, false>
+                                  : k_ace_pairgrad_mfma<MT, NT, false, false>);
     kern<<<(L.n + wpb - 1) / wpb, 64 * wpb, per * wpb, s>>>(
         pos, L.n, b, species, L.cap, at<int>(ws, L.nbr), at<int>(ws, L.cnt), at<int>(ws, L.S_idx),
         at<int>(ws, L.S_local), at<int>(ws, L.hdr), a, wpb, at<float>(ws, L.dEdA), weights,
-        at<float>(ws, L.g), seg_args(ws, L));
+        at<float>(ws, L.g), seg_args(ws, L), fin ? *fin : FinArgs{});
+}
+
+// (channel tiles, lm tiles) of the matrix-core basis / adjoint kernels: 0 if
+// the model is outside the instantiated range (then the VALU kernels run).
+// The adjoint's S rows take 64 x (16 nt + 1) floats per wave twice: from
+// three lm tiles on (lmax >= 5) one wave fits a SIMD and the VALU kernel
+// (2.3 KB per wave at lmax 5) measured faster (0.70 vs 1.49 ms on the
+// 1,023,800-atom cell).
+static int mfma_tiles(const Ctx &c, bool pair, int &mt, int &nt)
+{
+    mt = (c.m.nchan + 15) / 16;
+    nt = (c.m.L2 + 15) / 16;
+    if (pair && nt > 2)
+        return 0;
+    return mt >= 1 && mt <= 2 && nt >= 1 && nt <= 4;
+}
+
+// The pair adjoint computes dE/dA itself (the finalisation folded in): FP32
+// on the matrix cores, with the atom's A row and the partial-D column set
+// fitting the pair-row LDS space of a wave.
+bool ace_fin_fused(const Ctx &c)
+{
+    int mt, nt;
+    if (c.prec == MLMIX_FP64 || !c.basis_mfma || !c.fuse_fin || !mfma_tiles(c, true, mt, nt))
+        return false;
+    const int rw = 16 * mt + 1, yw = 16 * nt + 1;
+    const int pair = 64 * std::max(rw, yw) * 2;
+    return c.m.KAt + c.m.dsum_len <= pair;
+}
+
+static DSumSel dsum_sel(const Ctx &c, const WsLayout &L, bool fp32)
+{
+    DSumSel ds;
+    ds.tab = reinterpret_cast<const int *>(static_cast<char *>(c.m.base) + c.m.dsum);
+    const bool vsets = c.m.order >= 3 && c.m.n_pb > 0 && c.o3 == 1 && c.o3v && fp32;
+    for (int k = 0; k < kDSumBlocks; ++k)
+        ds.off[k] = c.m.dsum_off[vsets ? k : kDSumBlocks];
+    ds.grid = vsets ? o3v_grid(c, L.n) : 1;
+    ds.max_split = c.o3_max_split;
+    return ds;
 }
 
 // Dispatch over (channel tiles, lm tiles); false if the model is outside the
 // instantiated range (then the VALU kernels run).
 template <bool PAIR>
 static bool mfma_dispatch(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L, const Box &b,
-                          const double *pos, const int32_t *species, const double *weights)
+                          const double *pos, const int32_t *species, const double *weights,
+                          const FinArgs *fin = nullptr)
 {
     AceArgs<float> a = make_args<float>(c);
-    const int mt = (a.nchan + 15) / 16, nt = (a.L2 + 15) / 16;
-    // the adjoint's S rows take 64 x (16 nt + 1) floats per wave twice: from
-    // three lm tiles on (lmax >= 5) one wave fits a SIMD and the VALU kernel
-    // (2.3 KB per wave at lmax 5) measured faster (0.70 vs 1.49 ms on the
-    // 1,023,800-atom cell)
-    if (PAIR && nt > 2)
+    int mt, nt;
+    if (!mfma_tiles(c, PAIR, mt, nt))
         return false;
 #define O3_GO(M, N)                                                                    \
     if (mt == M && nt == N) {                                                          \
         if (PAIR)                                                                      \
-            pairgrad_mfma_launch<M, N>(s, c, ws, L, b, pos, species, weights, a);      \
+            pairgrad_mfma_launch<M, N>(s, c, ws, L, b, pos, species, weights, a, fin); \
         else                                                                           \
             basis_mfma_launch<M, N>(s, c, ws, L, b, pos, species, a);                  \
         return true;                                                                   \
@@ -1260,16 +1394,16 @@ static void finalize_t(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L,
                        const int32_t *species, double *e_exp)
 {
     AceArgs<T> a = make_args<T>(c);
-    pb_ranges(c, a.pb_lo, a.pb_hi);
-    const int *dp_off = reinterpret_cast<const int *>(static_cast<char *>(c.m.base) + c.m.dpoff);
     T *Dpart = at<T>(ws, L.dpart);
     const size_t nC = (size_t)c.m.ns * (c.m.lmax + 1) * c.m.nchan * c.m.nchan;
+    // the column set of the contraction that wrote the partial D
+    const DSumSel ds = dsum_sel(c, L, sizeof(T) == 4);
     // small systems: one atom per workgroup (8,193 atoms: 10.5 against 14.5 us);
     // large: four (1M atoms: 0.55 against 0.99 ms, the staged tables shared)
     // (a batched call keeps one atom per wave whatever its size, so that a
     // system's site energies do not depend on the batch it runs in)
     const int apb = (L.n <= 65536 && L.nseg == 0) ? 1 : 4;
-    size_t sm = (size_t)apb * c.m.KAt * sizeof(T) + (c.m.n_pb + 2 * (c.m.lmax + 1)) * sizeof(int) + 16;
+    size_t sm = (size_t)apb * c.m.KAt * sizeof(T) + (size_t)c.m.dsum_len * sizeof(int) + 16;
     int stage_c2 = 0;
     if (sm + nC * sizeof(T) <= 48 * 1024) {
         stage_c2 = 1;
@@ -1277,11 +1411,11 @@ static void finalize_t(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L,
     }
     if (apb == 1)
         k_ace_finalize<T, 1><<<L.n, 256, sm, s>>>(species, at<int>(ws, L.S_idx), at<int>(ws, L.hdr),
-                                                  a, dp_off, c.m.n_pb, stage_c2, c.m.dp_stride,
+                                                  a, ds, stage_c2, c.m.dp_stride,
                                                   at<T>(ws, L.A), Dpart, at<T>(ws, L.dEdA), e_exp);
     else
         k_ace_finalize<T, 4><<<(L.n + 3) / 4, 256, sm, s>>>(
-            species, at<int>(ws, L.S_idx), at<int>(ws, L.hdr), a, dp_off, c.m.n_pb, stage_c2,
+            species, at<int>(ws, L.S_idx), at<int>(ws, L.hdr), a, ds, stage_c2,
             c.m.dp_stride, at<T>(ws, L.A), Dpart, at<T>(ws, L.dEdA), e_exp);
 }
 
@@ -1346,11 +1480,20 @@ void launch_ace_finalize(hipStream_t s, const Ctx &c, void *ws, const WsLayout &
 }
 
 void launch_ace_pairgrad(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L, const Box &b,
-                         const double *pos, const int32_t *species, const double *weights)
+                         const double *pos, const int32_t *species, const double *weights,
+                         double *e_exp)
 {
     if (L.n == 0)
         return;
-    if (c.prec == MLMIX_FP64)
+    if (ace_fin_fused(c)) {
+        FinArgs fa;
+        fa.A = at<float>(ws, L.A);
+        fa.Dpart = at<float>(ws, L.dpart);
+        fa.dp_stride = c.m.dp_stride;
+        fa.ds = dsum_sel(c, L, true);
+        fa.e_exp = e_exp;
+        mfma_dispatch<true>(s, c, ws, L, b, pos, species, weights, &fa);
+    } else if (c.prec == MLMIX_FP64)
         pairgrad_t<double>(s, c, ws, L, b, pos, species, weights);
     else if (!(c.basis_mfma && mfma_dispatch<true>(s, c, ws, L, b, pos, species, weights)))
         pairgrad_t<float>(s, c, ws, L, b, pos, species, weights);

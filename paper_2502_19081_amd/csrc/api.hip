@@ -346,6 +346,12 @@ struct HostTables {
     std::vector<double> o3wr;         // its reduced-precision weight fragments
     int o3rows_max = 0;               // longest such list
     bool o3rows_empty = false;        // some (block, m3) has no Gaunt entry
+    // per split G of the vector-sparse form with summed runs: per (l3, m3)
+    // the partial-D columns its rows write (empty: one column per row)
+    std::vector<std::vector<std::vector<int>>> o3vsets;
+    std::vector<int> dsum;  // the column sets of every form (DevModel::dsum)
+    int dsum_off[kDSumSets] = {};
+    int dsum_len = 0;
 };
 
 // Tables of the per-wave matrix-core order-3 kernel (single-species models
@@ -370,6 +376,143 @@ struct HostTables {
 // species: for lane (c = l % 16, q = l / 16), channel tile ct and a, the
 // NJ = nchp / 4 values W[a][b = NJ q + j][c = 16 ct + c], j < NJ, padded to a
 // multiple of four, stored [species][block][a][ct][lane][NJ padded].
+// Bins of the vector-sparse form as flat row lists grouped by output: an
+// item is a run of the rows (p, m3) of one (l3, m3) over a range of the
+// blocks p of that l3, and a wave sums a run's products in its matrix
+// accumulators and stores one partial-D column for the run. The partial
+// buffer then holds one column per item where the other forms write one per
+// (block, m3), and the finalisation sums fewer of them. Items above a cut
+// (a fraction of a bin's even share of the cost) are split into block
+// ranges of near-even size, and go longest first onto the least loaded bin;
+// of the cuts tried, the one whose longest bin is shortest is kept. Each bin
+// runs its items in (l3, m3, first block) order. Columns are numbered in that order over the
+// whole tile, so that the columns of one (l3, m3) lie side by side. Per
+// split G = 1 .. 16: 4 G bins (waves x G workgroups), the offsets of the
+// bins' rows in o3rbeg, and the columns of each (l3, m3) in o3vsets.
+static void build_o3v_runs(HostTables &t, int lmax, int nch, int waves, long total,
+                           const std::vector<std::vector<int>> &rcost)
+{
+    const int P = (int)t.pb.size(), L2 = (lmax + 1) * (lmax + 1);
+    std::vector<int> plo(lmax + 1, 0), phi(lmax + 1, 0);  // blocks of each l3
+    for (int p = P - 1; p >= 0; --p)
+        plo[t.pb[p].l3] = p;
+    for (int p = 0; p < P; ++p)
+        phi[t.pb[p].l3] = p + 1;
+    t.o3rowv.clear();
+    t.o3rbeg.clear();
+    t.o3rows_max = 0;
+    struct Item {
+        long cost;
+        int l3, m3, lo, hi;
+    };
+    for (int G = 1; G <= kO3MaxSplit; G <<= 1) {
+        const int nb = waves * G;
+        // items cut at 1/2, 1/3, ... 1/8 of a bin's even share: the cut whose
+        // assignment has the least loaded longest bin (a run's store counts
+        // 2 nch), the coarser cut on ties
+        std::vector<Item> items;  // in (l3, m3, first block) order
+        std::vector<std::vector<int>> lists;
+        long best = -1;
+        for (int div : {2, 3, 4, 6, 8}) {
+            const long cap = std::max<long>(1, total / nb / div);
+            std::vector<Item> its;
+            for (int l3 = 0; l3 <= lmax; ++l3)
+                for (int m3 = 0; m3 < 2 * l3 + 1; ++m3) {
+                    long gc = 0;
+                    for (int p = plo[l3]; p < phi[l3]; ++p)
+                        gc += rcost[p][m3];
+                    const int k = (int)std::max<long>(
+                        1, std::min<long>(phi[l3] - plo[l3], (gc + cap - 1) / cap));
+                    int lo = plo[l3];
+                    for (int part = 0; part < k; ++part) {
+                        const int hi = lo + (phi[l3] - lo) / (k - part);
+                        long cst = 2 * nch;
+                        for (int p = lo; p < hi; ++p)
+                            cst += rcost[p][m3];
+                        its.push_back({cst, l3, m3, lo, hi});
+                        lo = hi;
+                    }
+                }
+            std::vector<int> idx(its.size());
+            for (size_t i = 0; i < its.size(); ++i)
+                idx[i] = (int)i;
+            std::stable_sort(idx.begin(), idx.end(),
+                             [&](int x, int y) { return its[x].cost > its[y].cost; });
+            std::vector<std::vector<int>> ls(nb);
+            std::vector<long> load(nb, 0);
+            for (int i : idx) {
+                int w = 0;
+                for (int k = 1; k < nb; ++k)
+                    if (load[k] < load[w])
+                        w = k;
+                ls[w].push_back(i);
+                load[w] += its[i].cost;
+            }
+            const long mx = *std::max_element(load.begin(), load.end());
+            if (best < 0 || mx < best) {
+                best = mx;
+                items.swap(its);
+                lists.swap(ls);
+            }
+        }
+        std::vector<std::vector<int>> cols(L2);
+        for (size_t i = 0; i < items.size(); ++i)
+            cols[items[i].l3 * items[i].l3 + items[i].m3].push_back((int)i * nch);
+        t.o3vsets.push_back(cols);
+        for (int w = 0; w < nb; ++w) {
+            t.o3rbeg.push_back((int)t.o3rowv.size() / 4);
+            std::sort(lists[w].begin(), lists[w].end());
+            int nrow = 0;
+            for (int i : lists[w]) {
+                const Item &it = items[i];
+                for (int p = it.lo; p < it.hi; ++p, ++nrow) {
+                    const int row = t.o3base[p] + it.m3;
+                    t.o3rowv.push_back(t.o3mtv[2 * row]);
+                    t.o3rowv.push_back(t.o3mtv[2 * row + 1]);
+                    t.o3rowv.push_back(p | (it.m3 << 16));
+                    t.o3rowv.push_back(i * nch);
+                }
+            }
+            t.o3rows_max = std::max(t.o3rows_max, nrow);
+        }
+        t.o3rbeg.push_back((int)t.o3rowv.size() / 4);
+    }
+}
+
+// Partial-D column sets for the finalisation, which sums into each (l3, m3)
+// the columns of its set in the listed order: one set per split G of the
+// vector-sparse form (its run columns, or the per-row columns when it keeps
+// one per row), then the per-(block, m3) set of the other forms (the blocks
+// of l3 in block order).
+static void build_dsum(const mlmix_model_desc &d, HostTables &t)
+{
+    const int lmax = d.ace_lmax, L2 = (lmax + 1) * (lmax + 1), nch = d.n_species * d.ace_n_rad;
+    t.dsum.clear();
+    t.dsum_len = 0;
+    auto put = [&](const std::vector<std::vector<int>> &cols) -> int {
+        const int off = (int)t.dsum.size();
+        int k = 0;
+        for (int lm = 0; lm < L2; ++lm) {
+            t.dsum.push_back(k);
+            k += (int)cols[lm].size();
+        }
+        t.dsum.push_back(k);
+        for (int lm = 0; lm < L2; ++lm)
+            t.dsum.insert(t.dsum.end(), cols[lm].begin(), cols[lm].end());
+        t.dsum_len = std::max(t.dsum_len, L2 + 1 + k);
+        return off;
+    };
+    std::vector<std::vector<int>> blocks(L2);
+    if (d.ace_order >= 3)
+        for (size_t p = 0; p < t.pb.size(); ++p)
+            for (int m3 = 0; m3 < 2 * t.pb[p].l3 + 1; ++m3)
+                blocks[t.pb[p].l3 * t.pb[p].l3 + m3].push_back(t.dpoff[p] + m3 * nch);
+    const int per_block = put(blocks);
+    for (int k = 0; k < kDSumBlocks; ++k)
+        t.dsum_off[k] = k < (int)t.o3vsets.size() ? put(t.o3vsets[k]) : per_block;
+    t.dsum_off[kDSumBlocks] = per_block;
+}
+
 static void build_o3(const mlmix_model_desc &d, HostTables &t, int waves)
 {
     const int nch = d.n_species * d.ace_n_rad, lmax = d.ace_lmax;
@@ -522,6 +665,13 @@ static void build_o3(const mlmix_model_desc &d, HostTables &t, int waves)
     long total = 0;
     for (size_t p = 0; p < P; ++p)
         total += cost[p];
+    // the vector-sparse FP32 and BF16 forms sum runs of rows on chip (below);
+    // the FP8 form scales each row's products by the row's own bound and
+    // keeps one partial-D column per (block, m3)
+    bool runs = kind == 1 && d.precision != MLMIX_FP8_CONTRACT;
+    if (const char *e = std::getenv("MLMIX_O3_RUNS"))
+        runs = runs && std::atoi(e) != 0;  // 0: one column per row (comparisons)
+    t.o3vsets.clear();
     t.o3order.clear();
     t.o3wbeg.clear();
     t.o3rowv.clear();
@@ -569,6 +719,8 @@ static void build_o3(const mlmix_model_desc &d, HostTables &t, int waves)
                 return px != py ? px < py : ((x >> 16) & 0xff) < ((y >> 16) & 0xff);
             });
             t.o3order.insert(t.o3order.end(), lists[w].begin(), lists[w].end());
+            if (runs)
+                continue;
             // the same bin as a flat list of rows (first entry, exact count,
             // block | m3 << 16, partial-D column of the row)
             int nrow = 0;
@@ -585,8 +737,11 @@ static void build_o3(const mlmix_model_desc &d, HostTables &t, int waves)
             t.o3rows_max = std::max(t.o3rows_max, nrow);
         }
         t.o3wbeg.push_back((int)t.o3order.size());
-        t.o3rbeg.push_back((int)t.o3rowv.size() / 4);
+        if (!runs)
+            t.o3rbeg.push_back((int)t.o3rowv.size() / 4);
     }
+    if (runs)
+        build_o3v_runs(t, lmax, nch, waves, total, rcost);
     // FP8 row-scale bound: sum of |g| over the row's entries
     t.o3gs.clear();
     for (size_t r = 0; r < t.o3mt.size() / 2; ++r) {
@@ -761,6 +916,7 @@ static int build_tables(const mlmix_model_desc &d, HostTables &t, int o3_waves)
             t.wsc[p * nchp + c] = mx > 0.0 ? mx / 240.0 : 0.0;
         }
     build_o3(d, t, o3_waves);
+    build_dsum(d, t);
     // cheap model
     int nb2 = d.uf3_n_knots2 + 2;
     t.up2 = bspline_span_poly(d.uf3_n_knots2);
@@ -851,6 +1007,7 @@ static std::vector<char> pack(const HostTables &t, DevModel &m)
     append_raw(blob, m.o3order, t.o3order);
     append_raw(blob, m.o3wbeg, t.o3wbeg);
     append<float>(blob, m.o3gs, t.o3gs);
+    append_raw(blob, m.dsum, t.dsum);
     return blob;
 }
 
@@ -1149,6 +1306,9 @@ try {
     c.max_gm3 = 0;
     c.max_ent_pb = 0;
     m.dp_stride = t.dp_stride;
+    for (int k = 0; k < kDSumSets; ++k)
+        m.dsum_off[k] = t.dsum_off[k];
+    m.dsum_len = t.dsum_len;
     for (const PBlock &p : t.pb)
         c.max_ent_pb = std::max(c.max_ent_pb, t.gm3[p.gm3_off + 2 * p.l3 + 1] - t.gm3[p.gm3_off]);
     for (int l = 0; l <= d.ace_lmax; ++l) {
@@ -1172,6 +1332,8 @@ try {
         if (v == 1 || v == 2 || v == 4 || v == 8 || v == 16)
             c.o3_max_split = v;
     }
+    if (const char *e = std::getenv("MLMIX_FUSE_FIN"))
+        c.fuse_fin = std::atoi(e) ? 1 : 0;  // 0: the finalisation as its own kernel (comparisons)
     if (const char *e = std::getenv("MLMIX_O3_VALU"))
         c.o3v = std::atoi(e) ? 1 : 0;  // 0: matrix-core sparse stage (comparisons)
     if (t.o3rows_max > kO3VMaxRows || t.o3rows_empty)
@@ -1467,13 +1629,16 @@ static int compute_impl(mlmix_ctx *ctx, hipStream_t s, void *ws, const WsLayout 
             StageTimer t(ctx, s, ST_CONTRACT, c.o3 && c.prec != MLMIX_FP64);
             launch_ace_contract(s, c, ws, L, species, t.k0, t.k1);
         }
-        {
+        // the finalisation runs inside the pair adjoint where that kernel
+        // can take it (the energy-only call keeps its own kernel)
+        const bool fused = !energy_only && ace_fin_fused(c);
+        if (!fused) {
             StageTimer t(ctx, s, ST_FIN);
             launch_ace_finalize(s, c, ws, L, species, e_exp);
         }
         if (!energy_only) {
             StageTimer t(ctx, s, ST_PAIR);
-            launch_ace_pairgrad(s, c, ws, L, b, pos, species, nullptr);
+            launch_ace_pairgrad(s, c, ws, L, b, pos, species, nullptr, fused ? e_exp : nullptr);
         }
     }
     // join
@@ -1641,7 +1806,7 @@ try {
     if (rc)
         return rc;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    launch_ace_pairgrad(s, ctx->c, ws, L, b, pos, species, grad_e);
+    launch_ace_pairgrad(s, ctx->c, ws, L, b, pos, species, grad_e, nullptr);
     launch_gather_blend(s, ctx->c, ws, L, 1, 0, nullptr, grad_pos, nullptr, nullptr, nullptr, -1.0);
     HIP_OK(hipGetLastError());
     return MLMIX_OK;

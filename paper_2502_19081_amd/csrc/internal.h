@@ -18,7 +18,12 @@ constexpr int kMaxTriplet = 64;   // neighbours inside the 3-body cutoff per cen
 constexpr int kScanTile = 2048;   // elements per block in the device scans
 constexpr int kReduceBlocks = 256;
 constexpr int kO3VMaxRows = 128;  // rows of one bin of the vector-sparse FP32 contraction
+constexpr int kO3Atoms = 16;      // S atoms per tile of the order-3 kernels
 constexpr int kO3MaxSplit = 16;   // workgroups sharing one 16-atom tile of the order-3 kernel
+// partial-D column sets of the order-3 sums: one per split G = 1 .. 16 of the
+// vector-sparse contraction, then the per-(block, m3) set of the other forms
+constexpr int kDSumSets = 6;
+constexpr int kDSumBlocks = 5;  // index of the per-(block, m3) set
 
 // Header words at the start of every workspace (int32 unless noted).
 enum HeaderWord {
@@ -145,8 +150,22 @@ struct DevModel {
     size_t o3o, o3mt, o3mtv, o3rowv, o3rbeg, o3wr, o3base, o3w, o3sw, o3order, o3wbeg, o3gs;
     size_t o3ww;  // weight fragments of the wide form
     int dp_stride;  // partial-D entries per S atom (sum over blocks of nchan*(2 l3 + 1))
+    // partial-D column lists: set k at dsum + dsum_off[k] holds L2 + 1 run
+    // offsets, then the columns (atom-relative, channel 0) summed into each
+    // (l3, m3) in that order; dsum_len = the longest set in ints
+    size_t dsum;
+    int dsum_off[kDSumSets], dsum_len;
     int w_per_species;  // entries of W per centre species
     int gm3_total, g_total;
+};
+
+// Which partial-D column set the finalisation sums: set off[lg] of tab for
+// the split G = 2^lg that the vector-sparse contraction chooses from |S|,
+// its grid and its split limit (every off[] the same set for the other forms).
+struct DSumSel {
+    const int *tab;
+    int off[kDSumBlocks];
+    int grid, max_split;
 };
 
 // One (l1 <= l2, l3) block of the order-3 contraction.
@@ -199,6 +218,7 @@ struct Ctx {
     int o3_max_split = 4;
     int o3_waves = 8;      // waves per workgroup of the single-species form (4 or 8)
     int o3v = 1;           // FP32 single-species form with the vector sparse stage
+    int fuse_fin = 1;      // the matrix-core pair adjoint does the finalisation
     int ace_tile = 4;      // atoms per order-3 block workgroup (tuning)
     int ace_stage_w = 1;   // stage the block's weights in LDS (tuning)
     int device;
@@ -263,14 +283,19 @@ void launch_ace_contract(hipStream_t s, const Ctx &c, void *ws, const WsLayout &
                          hipEvent_t ev1 = nullptr);
 void launch_ace_finalize(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L,
                          const int32_t *species, double *e_exp);
+// e_exp: where the pair adjoint writes the site energies when it does the
+// finalisation itself (ace_fin_fused; NULL: the gradient only)
 void launch_ace_pairgrad(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L, const Box &b,
-                         const double *pos, const int32_t *species, const double *weights);
+                         const double *pos, const int32_t *species, const double *weights,
+                         double *e_exp);
+bool ace_fin_fused(const Ctx &c);
 
 // ---- o3.hip ----
 void launch_ace_o3(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L,
                    hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 size_t o3_lds_bytes(const Ctx &c);
 size_t o3v_lds_bytes(const Ctx &c);
+int o3v_grid(const Ctx &c, int n);
 void launch_ace_o3w(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L,
                     const int32_t *species, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 size_t o3w_lds_bytes(const Ctx &c);

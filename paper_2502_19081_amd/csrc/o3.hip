@@ -70,7 +70,6 @@ struct O3Args {
     int max_split;  // largest G the kernel may choose (1, 2, 4 or 8)
 };
 
-constexpr int kO3Atoms = 16;
 constexpr int kO3MaxGroups = 8;  // entries of one (block, m3) row: at most 4 x 8
 
 // bytes of one P row per format (16-byte pad keeps rows 4 banks apart); the
@@ -578,9 +577,15 @@ __global__ void __launch_bounds__(64 * NW, NC <= 12 ? 3 : 2)
             const int2 ent = lane < ne ? entE[H] : make_int2(0, 0);
             const int ox0 = __builtin_amdgcn_readlane(ent.x, 0);
             __builtin_amdgcn_sched_barrier(0);
-            store_d(k > 0);
+            // a row whose column differs from the last row's opens a run: the
+            // last run's D is stored and the accumulators start from zero
+            // (FP8: every row is its own run, each with its own scale)
+            const int col = field(k, 3);
+            const bool fresh = QM == 2 || k == 0 || col != dcol;
+            if (fresh)
+                store_d(k > 0);
             const int p = field(k, 2) & 0xffff;
-            dcol = field(k, 3);
+            dcol = col;
             // the block's weights (read while the sparse stage runs), then the
             // next row's entries (a valid row past the end is read and not
             // used)
@@ -642,8 +647,10 @@ __global__ void __launch_bounds__(64 * NW, NC <= 12 ? 3 : 2)
             }
             // ---- dense stage (matrix cores): lane (t = m, q) supplies
             // P_t[i][NJ q + j], lane (c = m, q) the weight W[i][NJ q + j][c]
-            acc0 = (f4v){0.f, 0.f, 0.f, 0.f};
-            acc1 = (f4v){0.f, 0.f, 0.f, 0.f};
+            if (fresh) {
+                acc0 = (f4v){0.f, 0.f, 0.f, 0.f};
+                acc1 = (f4v){0.f, 0.f, 0.f, 0.f};
+            }
             if constexpr (QM == 0) {
 #pragma unroll
                 for (int i = 0; i < NC; ++i)
@@ -707,6 +714,17 @@ __global__ void __launch_bounds__(64 * NW, NC <= 12 ? 3 : 2)
         if (nr > 0)
             store_d(true);
     }
+}
+
+// grid of the vector-sparse contraction over a capacity of n S atoms: as
+// many resident workgroups as the registers allow (waves per SIMD: three up
+// to 12 channels, else two), at most one per (tile, split) item
+int o3v_grid(const Ctx &c, int n)
+{
+    const long items = (((long)n + kO3Atoms - 1) / kO3Atoms) * kO3MaxSplit;
+    const int nw = c.o3_waves == 8 ? 8 : 4;
+    const int per_cu = std::max(1, 4 * (c.m.nchp <= 12 ? 3 : 2) / nw);
+    return (int)std::min<long>(std::max<long>(items, 1), 256L * per_cu);
 }
 
 size_t o3v_lds_bytes(const Ctx &c)
@@ -1064,8 +1082,7 @@ void launch_ace_o3(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L, hip
             constexpr int QM = decltype(qm)::value, NC = decltype(nc)::value;
             auto launch = [&](auto nw) {
                 constexpr int NW = decltype(nw)::value;
-                const int per_cu = std::max(1, 4 * (NC <= 12 ? 3 : 2) / NW);
-                const int grid = (int)std::min<long>(std::max<long>(items, 1), 256L * per_cu);
+                const int grid = o3v_grid(c, L.n);
                 if (ev0)
                     hipExtLaunchKernelGGL(k_ace_o3v<QM, NC, NW>, dim3(grid), dim3(64 * NW),
                                           (uint32_t)lds, s, ev0, ev1, 0u, hdr, a, A, D);
