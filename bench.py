@@ -408,14 +408,18 @@ def fit_main(args):
 def replay_ms(model, sy, pos, sp, stage, reps):
     """Average duration (ms) of one stage's kernel: `reps` back-to-back
     launches on the state the last evaluation left in the workspace, two HIP
-    events around them on the launch stream (the current stream)."""
+    events around them on the launch stream (the current stream). The pair
+    adjoint writes the expensive site energies, the cheap potential the cheap
+    ones."""
     import ctypes
     import torch
     from paper_2502_19081_amd import binding as B
+    e_out = sy.e_exp if B.lib().mlmix_profile_stage_name(stage).decode() == "ace_pairgrad" \
+        else sy.e_cheap
     cur = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
     args = (model.handle, cur, ctypes.c_void_p(sy.ws.data_ptr()), sy.n,
             ctypes.c_void_p(pos.data_ptr()), ctypes.c_void_p(sp.data_ptr()),
-            ctypes.byref(sy.box), ctypes.c_void_p(sy.e_cheap.data_ptr()), stage)
+            ctypes.byref(sy.box), ctypes.c_void_p(e_out.data_ptr()), stage)
     B.check(B.lib().mlmix_profile_replay(*args, 10))
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -481,9 +485,9 @@ def main():
 
     dt = float(w.get("dt", 1.0))
 
-    def step(sy, pos, vel, sp, mode, rebuild=True):
+    def step(sy, pos, vel, sp, mode, rebuild=True, single=False):
         sy.vv_step(pos, vel, mass, sp, dt, r_buffer=w["r_buffer"], mode=mode,
-                   force_rebuild=rebuild, single_stream=args.single_stream,
+                   force_rebuild=rebuild, single_stream=args.single_stream or single,
                    cheap_masked=args.cheap_masked)
 
     en_buf = torch.zeros(max(args.graph_steps, 1), 3, dtype=torch.float64, device=dev)
@@ -499,7 +503,8 @@ def main():
                     force_rebuild=rebuild, single_stream=args.single_stream,
                     cheap_masked=args.cheap_masked, energies=en_buf[:k])
 
-    def run(mode, steps, warmup, stage_mask=0, latency=False, graph=False, rebuild=True):
+    def run(mode, steps, warmup, stage_mask=0, latency=False, graph=False, rebuild=True,
+            single=False):
         """Times `steps` steps. graph=True captures `chunk` consecutive steps
         (args.graph_steps when it divides `steps`, one step when latency is
         timed) in one HIP graph and replays it; otherwise the step's kernels
@@ -533,7 +538,7 @@ def main():
             if g is not None:
                 g.replay()
             else:
-                step(sy, pos, vel, sp, mode, rebuild)
+                step(sy, pos, vel, sp, mode, rebuild, single)
             if latency:
                 torch.cuda.synchronize()
                 lat.append(time.perf_counter() - ts)
@@ -545,17 +550,20 @@ def main():
         run.builds = sy.list_builds() - builds0  # list builds inside the timed region
         return (t1 - t0), prof, lat, sy
 
-    # 1. per-stage breakdown (every stage bracketed) to find the dominant kernel
+    # 1. per-stage breakdown (every stage bracketed) to find the dominant
+    # kernel: the steps run on one stream, so that each bracket holds its
+    # stage alone on the GPU (and the dispatch gap before it), not the
+    # cheap potential running beside it
     main_rebuild = args.rebuild_every_step
     n_break = max(10, args.steps // 4)
     _, prof_all, _, _ = run(B.MODE_MIXED, n_break, args.warmup,
-                               stage_mask=(1 << B.N_STAGES) - 1, rebuild=main_rebuild)
+                               stage_mask=(1 << B.N_STAGES) - 1, rebuild=main_rebuild,
+                               single=True)
     build_frac = run.builds / n_break  # list builds per step in the breakdown
     stage_ms = {k: v[0] / max(v[1], 1) for k, v in prof_all.items() if v[1]}
-    # with the second stream, the reverse slots and the cheap potential run
-    # beside the expensive chain under a workgroup cap (their event times
-    # measure the overlap, not their cost): the dominant kernel is taken from
-    # the chain that bounds the step
+    # in the timed steps the reverse slots and the cheap potential run on the
+    # second stream beside the expensive chain (the cheap potential has a
+    # roofline line of its own): the dominant kernel is taken from that chain
     side = set() if args.single_stream else {"uf3", "reverse_slots"}
     dominant = max((k for k in stage_ms if k not in side),
                    key=lambda k: stage_ms[k] * prof_all[k][1])
@@ -577,10 +585,10 @@ def main():
     # the state of one mixed step for the kernel replays below
     sy_r, pos_r, vel_r, sp_r = fresh(B.MODE_MIXED)
     step(sy_r, pos_r, vel_r, sp_r, B.MODE_MIXED)
-    if dominant == "ace_contract":
-        # the contraction's own duration: K back-to-back launches on the
-        # state of a mixed step, two events around them on its stream (the
-        # in-step bracket also holds the dispatch gap before the kernel)
+    if dominant == "ace_contract" or (dominant == "ace_pairgrad" and prec != "fp64"):
+        # the kernel's own duration: K back-to-back launches on the state of
+        # a mixed step, two events around them on its stream (the in-step
+        # bracket also holds the dispatch gap before the kernel)
         dom_avg_ms = replay_ms(model, sy_r, pos_r, sp_r, dom_bit, args.steps)
         dom_cnt = args.steps
         dom_method = ("K back-to-back launches on the state of a mixed step, HIP events on "
@@ -645,7 +653,7 @@ def main():
     S_mask[S_idx.cpu().numpy()] = True
     nbr, cnt = sy.neighbors()
     pc = pair_counts(w, nbr.cpu().numpy(), cnt.cpu().numpy(), S_mask)
-    fl = np.zeros(6)
+    fl = np.zeros(7)
     import ctypes
     B.check(B.lib().mlmix_model_flops(model.handle, fl.ctypes.data_as(ctypes.c_void_p)))
     gpu_forces = out["forces"].cpu().numpy().T.copy()
@@ -662,7 +670,10 @@ def main():
         "ace_contract": ("flops", fl[0] * nS),
         "ace_finalize": ("bytes", nS * (2 * KAt * tsz + dp_stride * tsz + 16)),
         "ace_basis": ("flops", fl[1] * pc["exp_pairs"]),
-        "ace_pairgrad": ("flops", fl[2] * pc["exp_pairs"]),
+        # with the finalisation folded in (no finalisation launches), its
+        # work per S atom too
+        "ace_pairgrad": ("flops", fl[2] * pc["exp_pairs"]
+                         + (fl[6] * nS if "ace_finalize" not in stage_ms else 0.0)),
         "uf3": ("flops", fl[3] * pc["cheap_pairs"] + fl[4] * pc["cheap_triplets"]),
         # HBM bytes per launch
         # per step: the displacement check (48 B per atom) unless every step
@@ -823,6 +834,8 @@ def main():
         "p50_step_ms": float(np.percentile(lat_ms, 50)) if lat_ms is not None else None,
         "p99_step_ms": float(np.percentile(lat_ms, 99)) if lat_ms is not None else None,
         "stage_ms_per_step": {k: round(v, 5) for k, v in stage_ms.items()},
+        "stage_timing": "every stage bracketed by HIP events in mixed steps run on one stream "
+                        "(each stage alone on the GPU; a bracket also holds the dispatch gap)",
         "stage_roofline": stage_roof,
         "roofline": roof,
         "second_stream_roofline": uf3_roof,

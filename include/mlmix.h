@@ -552,16 +552,20 @@ const char *mlmix_profile_stage_name(int32_t stage);
 /* Benchmark hook: launches the kernels of one stage reps times, back to back
  * on `stream`, on the data the last evaluation left in ws (every replay does
  * the same work). Stage 4 (the expensive order-3 contraction) reads and
- * writes workspace arrays only (pos, box and e_cheap may be NULL); stage 7
- * (the cheap potential, uncapped as on one stream) also reads pos [dev] and
- * box and writes e_cheap [dev] double[n]. Species as in mlmix_compute.
- * Timing these launches with two events gives the kernel's own duration
- * without the dispatch gap in front of it. Errors: MLMIX_E_ARG (NULL,
- * negative reps, another stage, n_atoms not the workspace's, a batch
- * workspace), MLMIX_E_STATE (workspace not initialised). */
+ * writes workspace arrays only (pos, box and e_out may be NULL); stage 6
+ * (the expensive pair adjoint, FP32/BF16/FP8 models; with the finalisation
+ * folded in where a step folds it in) also reads pos [dev] and box and
+ * writes the expensive site energies of S to e_out [dev] double[n]; stage 7
+ * (the cheap potential, uncapped as on one stream) reads pos and box and
+ * writes the cheap site energies to e_out [dev] double[n]. Species as in
+ * mlmix_compute. Timing these launches with two events gives the kernel's
+ * own duration without the dispatch gap in front of it. Errors: MLMIX_E_ARG
+ * (NULL, negative reps, another stage, stage 6 of an FP64 model, n_atoms not
+ * the workspace's, a batch workspace), MLMIX_E_STATE (workspace not
+ * initialised). */
 int mlmix_profile_replay(mlmix_ctx *ctx, void *stream, void *ws, int32_t n_atoms,
                          const double *pos, const int32_t *species, const mlmix_box *box,
-                         double *e_cheap, int32_t stage, int32_t reps);
+                         double *e_out, int32_t stage, int32_t reps);
 
 /* Achievable-peak probe: launches `blocks` workgroups of four waves, each
  * running `iters` rounds of eight independent FP32 16x16x4 matrix-core
@@ -571,11 +575,12 @@ int mlmix_profile_replay(mlmix_ctx *ctx, void *stream, void *ws, int32_t n_atoms
 int mlmix_probe_mfma_f32(void *stream, int32_t blocks, int32_t iters, float *sink, double *flops);
 
 /* Operation counts of the kernels as written, for roofline reporting
- * (out[6]): [0] expensive order-3 contraction per S atom, [1] atomic basis
+ * (out[7]): [0] expensive order-3 contraction per S atom, [1] atomic basis
  * per expensive pair, [2] pair adjoint per expensive pair, [3] cheap 2-body
  * per pair, [4] cheap 3-body per unordered pair of legs, [5] the part of [0]
  * spent in the dense order-3 stage (the stage whose operands the BF16/FP8
- * modes narrow). */
+ * modes narrow), [6] finalisation (dE/dA and site energy from A and the
+ * partial D) per S atom. */
 int mlmix_model_flops(const mlmix_ctx *ctx, double *out);
 
 /* Thread-local description of the last error. */

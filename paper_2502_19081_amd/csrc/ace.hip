@@ -955,9 +955,9 @@ __global__ void __launch_bounds__(256)
         }
 }
 
-// The finalisation inside the pair adjoint (FIN): the wave computes its
-// atom's dE/dA from the partial D as the finalisation kernel does (same
-// terms, same order of the sums) instead of reading it back.
+// The finalisation inside the pair adjoint (k_ace_pairgrad_wg): the
+// workgroup computes its atom's dE/dA from the partial D as the finalisation
+// kernel does (same terms, same order of the sums) instead of reading it back.
 struct FinArgs {
     const float *A;      // [S][KAt] atomic basis
     const float *Dpart;  // [S][dp_stride] partial D
@@ -967,8 +967,7 @@ struct FinArgs {
 };
 
 // Pair adjoint on the matrix cores (FP32 potentials): one wave per S atom.
-// G = dE/dA of the atom (times its weight) is staged transposed, [(z, n)][lm]
-// (FIN: computed here from A and the partial D, with the site energy).
+// G = dE/dA of the atom (times its weight) is staged transposed, [(z, n)][lm].
 // The valid pairs of the whole row (partner in S, inside the cutoff) are
 // compacted by ballot first (geometry in LDS), 64 per round, and lane q
 // builds the species-masked rows R and dR of compacted pair q;
@@ -976,15 +975,14 @@ struct FinArgs {
 // channels); each pair's lane then contracts its rows with the harmonics and
 // their gradients, g = rad u + (v - u (u.v)) / r with rad = sum S_D Y and
 // v = sum S_R grad_u Y, and writes g to its list slot (0 for other slots).
-template <int MT, int NT, bool SEG, bool FIN>
+template <int MT, int NT, bool SEG>
 __global__ void __launch_bounds__(256)
     k_ace_pairgrad_mfma(const double *__restrict__ pos, int n, Box b0,
                         const int32_t *__restrict__ species, int cap, const int *__restrict__ nbr,
                         const int *__restrict__ cnt, const int *__restrict__ S_idx,
                         const int *__restrict__ S_local, const int *__restrict__ hdr,
                         AceArgs<float> a, int wpb, const float *__restrict__ dEdA,
-                        const double *__restrict__ weights, float *__restrict__ g, Seg sg,
-                        FinArgs fa)
+                        const double *__restrict__ weights, float *__restrict__ g, Seg sg)
 {
     constexpr int RW = 16 * MT + 1, YW = 16 * NT + 1;
     constexpr int PAIR = 64 * RW * 2 > 64 * YW * 2 ? 64 * RW * 2 : 64 * YW * 2;
@@ -1004,78 +1002,9 @@ __global__ void __launch_bounds__(256)
     const Box b = seg_box<SEG, true>(b0, sg, i);
     const float wgt = weights ? float(weights[i]) : 1.0f;
     const int nrad = a.nrad, nch = a.nchan, L2 = a.L2, nchp = a.nchp;
-    if constexpr (FIN) {
-        // the atom's A row and the partial-D column set in the pair-row
-        // space (free until the first round), then per (channel, lm):
-        // dE/dA = c1 + 2 D2 + 3 D3 and the site energy c0 + sum A (c1 + D2 + D3)
-        const int z = sp_clamp(species[i], a.ns);
-        float *As = base;                                   // [L2][nchp]
-        int *tbl = reinterpret_cast<int *>(base + a.KAt);   // [L2 + 1] run offsets, columns
-        const int *dset;
-        {
-            const int ntile = (nS + kO3Atoms - 1) / kO3Atoms;
-            int G = 1, lg = 0;
-            while (G < fa.ds.max_split && ntile * G < fa.ds.grid) {
-                G <<= 1;
-                ++lg;
-            }
-            dset = fa.ds.tab + fa.ds.off[lg];
-        }
-        for (int e = lane; e < a.KAt; e += 64)
-            As[e] = fa.A[(size_t)s * a.KAt + e];
-        for (int e = lane; e < L2 + 1 + dset[L2]; e += 64)
-            tbl[e] = dset[e];
-        wave_sync_ace();
-        const float *Ds = fa.Dpart + (size_t)s * fa.dp_stride;
-        const int *dcols = tbl + L2 + 1;
-        double es = 0.0;
-        for (int e = lane; e < 16 * MT * 16 * NT; e += 64) {
-            const int ch = e / (16 * NT), lm = e - ch * (16 * NT);
-            float v = 0.f;
-            if (ch < nch && lm < L2) {
-                int l = (int)sqrtf((float)lm);
-                l -= (l * l > lm);
-                l += ((l + 1) * (l + 1) <= lm);
-                const float c1t = (l == 0) ? a.c1[z * nch + ch] : 0.f;
-                float D2 = 0.f, D3 = 0.f;
-                if (a.order >= 2) {
-                    const float *C = a.c2s + (((size_t)z * a.L1 + l) * nch + ch) * nch;
-                    const float *Al = As + lm * nchp;
-                    for (int bb = 0; bb < nch; ++bb)
-                        D2 += C[bb] * Al[bb];
-                }
-                if (a.order >= 3) {
-                    constexpr int kPre = 8;
-                    const int k0 = tbl[lm], nk = tbl[lm + 1] - k0;
-                    const int *cl = dcols + k0;
-                    float pv[kPre];
-#pragma unroll
-                    for (int k = 0; k < kPre; ++k)
-                        pv[k] = k < nk ? Ds[cl[k] + ch] : 0.f;
-#pragma unroll
-                    for (int k = 0; k < kPre; ++k)
-                        D3 += pv[k];
-                    for (int k = kPre; k < nk; ++k)
-                        D3 += Ds[cl[k] + ch];
-                }
-                v = c1t + 2.f * D2 + 3.f * D3;
-                es += (double)(As[lm * nchp + ch] * (c1t + D2 + D3));
-            }
-            Gt[ch * YW + lm] = v * wgt;
-        }
-        if (fa.e_exp) {
-#pragma unroll
-            for (int d = 32; d > 0; d >>= 1)
-                es += __shfl_xor(es, d);
-            if (lane == 0)
-                fa.e_exp[i] = (double)a.c0[z] + es;
-        }
-        wave_sync_ace();  // the pair rows overwrite As
-    } else {
-        for (int e = lane; e < 16 * MT * 16 * NT; e += 64) {
-            const int ch = e / (16 * NT), lm = e - ch * (16 * NT);
-            Gt[ch * YW + lm] = (ch < nch && lm < L2) ? dEdA[(size_t)s * a.KAt + lm * nchp + ch] * wgt : 0.f;
-        }
+    for (int e = lane; e < 16 * MT * 16 * NT; e += 64) {
+        const int ch = e / (16 * NT), lm = e - ch * (16 * NT);
+        Gt[ch * YW + lm] = (ch < nch && lm < L2) ? dEdA[(size_t)s * a.KAt + lm * nchp + ch] * wgt : 0.f;
     }
     const int c = cnt[i];
     const int *row = nbr + (size_t)i * cap;
@@ -1187,6 +1116,301 @@ __global__ void __launch_bounds__(256)
     }
 }
 
+// Pair adjoint with the finalisation, one workgroup of four waves per S atom
+// (single-precision modes). The work of one atom is spread over the
+// waves instead of resting on one wave's latency:
+//  1. every thread stages a share of the finalisation's tables into LDS (the
+//     A row, the species' order-2 matrices, the used prefix of the partial-D
+//     row, the column set), all loads in flight together; wave 0 meanwhile
+//     compacts the row's valid pairs (partner in S, inside the cutoff) by
+//     ballot into geo;
+//  2. G = dE/dA (times the atom's weight in a backward call), [(z, n)][lm],
+//     and the site energy from the staged tables, two to four elements per
+//     thread (dE/dA = c1 + 2 D2 + 3 D3; the same terms and sums as the
+//     finalisation kernel);
+//  3. per round of 64 compacted pairs: wave w builds the species-masked rows
+//     R and dR of pairs 16 w .. 16 w + 15 and their 16-row MFMA tiles S_R =
+//     R G and S_D = dR G (pairs x lm, K = channels) into the shared S rows;
+//  4. wave w contracts all 64 pairs' S rows with the harmonics of its share
+//     of the orders |m| ({0}, {1}, {2}, {3..lmax}: one share per wave, so
+//     the stream is uniform within a wave), leaving partial sums rad =
+//     sum S_D Y and v = sum S_R grad_u Y per pair; the four partials are
+//     added in wave order and g = rad u + (v - u (u.v)) / r goes to the
+//     pair's list slot (0 for slots without a valid pair).
+template <int MT, int NT, bool SEG>
+struct PairWgLds {
+    static constexpr int RW = 16 * MT + 1, YW = 16 * NT + 1;
+    static constexpr int S_ROWS = 64 * YW * 2;  // S_R, S_D of 64 pairs
+    static constexpr int P_ROWS = 64 * RW * 2;  // R, dR of 64 pairs (then the partial sums)
+    static constexpr int U = S_ROWS + P_ROWS;   // also the staging space of step 1
+    static constexpr int GT = 16 * MT * YW;
+    static constexpr int TBL = ((16 * NT + 1 + 256) + 63) / 64 * 64;  // column table (ints)
+    static constexpr int FLOATS = U + GT + 64 * 8 + TBL + 16;
+    static_assert(4 * 64 * 4 <= P_ROWS, "partial sums fit the R rows");
+};
+
+template <int MT, int NT, bool SEG>
+__global__ void __launch_bounds__(256)
+    k_ace_pairgrad_wg(const double *__restrict__ pos, int n, Box b0,
+                      const int32_t *__restrict__ species, int cap, const int *__restrict__ nbr,
+                      const int *__restrict__ cnt, const int *__restrict__ S_idx,
+                      const int *__restrict__ S_local, const int *__restrict__ hdr,
+                      AceArgs<float> a, const double *__restrict__ weights,
+                      float *__restrict__ g, Seg sg, FinArgs fa)
+{
+    using LY = PairWgLds<MT, NT, SEG>;
+    constexpr int RW = LY::RW, YW = LY::YW;
+    const int nS = hdr[H_NS];
+    const int s = blockIdx.x;
+    if (s >= nS)
+        return;  // uniform across the workgroup
+    extern __shared__ __align__(16) char smem_raw[];
+    float *U = reinterpret_cast<float *>(smem_raw);
+    float *SR = U, *SD = U + 64 * YW;                      // [64][YW] each
+    float *Rr = U + LY::S_ROWS, *Dr = Rr + 64 * RW;        // [64][RW] each
+    float *part = Rr;                                      // [4 waves][64 pairs][4] after the MFMAs
+    float *Gt = U + LY::U;                                 // [16 MT][YW]
+    PairGeo *geo = reinterpret_cast<PairGeo *>(Gt + LY::GT);  // [64]
+    int *tbl = reinterpret_cast<int *>(Gt + LY::GT + 64 * 8);  // [TBL]
+    double *red = reinterpret_cast<double *>(tbl + LY::TBL);   // [4] energy partials
+    int *nvs = reinterpret_cast<int *>(red + 4);               // valid pairs of the row
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int m16 = lane & 15, kg = lane >> 4;
+    const int i = S_idx[s];
+    const Box b = seg_box<SEG, true>(b0, sg, i);
+    const int nrad = a.nrad, nch = a.nchan, L2 = a.L2, nchp = a.nchp;
+    const int z = sp_clamp(species[i], a.ns);
+    const int c = cnt[i];
+    const int *row = nbr + (size_t)i * cap;
+    float *gs = g + (size_t)s * cap * 3;
+    const float wgt = weights ? float(weights[i]) : 1.0f;  // backward: dL/dE_i
+
+    // ---- 1. staging (all threads) and the pair compaction (wave 0)
+    int lg = 0;
+    {
+        const int ntile = (nS + kO3Atoms - 1) / kO3Atoms;
+        int G = 1;
+        while (G < fa.ds.max_split && ntile * G < fa.ds.grid) {
+            G <<= 1;
+            ++lg;
+        }
+    }
+    const int *dset = fa.ds.tab + fa.ds.off[lg];
+    const int nA = a.KAt;
+    const int nC = a.order >= 2 ? a.L1 * nch * nch : 0;
+    const int nD = a.order >= 3 ? fa.ds.span[lg] * nch : 0;
+    const int ntab = L2 + 1 + fa.ds.ncol[lg];
+    const int tot = nA + nC + nD;  // <= LY::U (host check)
+    float *As = U, *Cs = U + nA, *Dl = U + nA + nC;
+    {
+        const float *srcA = fa.A + (size_t)s * a.KAt;
+        const float *srcC = a.c2s + (size_t)z * a.L1 * nch * nch;
+        const float *srcD = fa.Dpart + (size_t)s * fa.dp_stride;
+        constexpr int SPL = (LY::U + 255) / 256;
+        float v[SPL];
+#pragma unroll
+        for (int k = 0; k < SPL; ++k) {
+            const int e = min(tid + 256 * k, tot - 1);  // clamped: every load is in bounds
+            const float *src =
+                e < nA ? srcA + e : (e < nA + nC ? srcC + (e - nA) : srcD + (e - nA - nC));
+            v[k] = *src;
+        }
+        constexpr int TPT = LY::TBL / 256 > 0 ? (LY::TBL + 255) / 256 : 1;
+        int tv[TPT];
+#pragma unroll
+        for (int k = 0; k < TPT; ++k)
+            tv[k] = dset[min(tid + 256 * k, ntab - 1)];
+#pragma unroll
+        for (int k = 0; k < SPL; ++k)
+            if (tid + 256 * k < LY::U)
+                U[tid + 256 * k] = v[k];
+#pragma unroll
+        for (int k = 0; k < TPT; ++k)
+            if (tid + 256 * k < LY::TBL)
+                tbl[tid + 256 * k] = tv[k];
+    }
+    int pp[4] = {-1, -1, -1, -1};
+    if (w == 0) {
+        const int nv_all = compact_pairs(pos, n, b, species, a.ns, row, c, S_local, i, a.rc2,
+                                         lane, 0, geo, pp);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int slot = lane + 64 * u;
+            if (slot < c && pp[u] < 0) {
+                gs[slot * 3 + 0] = 0.f;
+                gs[slot * 3 + 1] = 0.f;
+                gs[slot * 3 + 2] = 0.f;
+            }
+        }
+        if (lane == 0)
+            *nvs = nv_all;
+    }
+    __syncthreads();
+
+    // ---- 2. G = dE/dA and the site energy
+    {
+        const int *dcols = tbl + L2 + 1;
+        double es = 0.0;
+        static_assert((16 * MT * 16 * NT) % 256 == 0, "whole elements per thread");
+#pragma unroll
+        for (int it = 0; it < 16 * MT * 16 * NT / 256; ++it) {
+            const int e = tid + 256 * it;
+            const int ch = e / (16 * NT), lm = e - ch * (16 * NT);
+            float val = 0.f;
+            if (ch < nch && lm < L2) {
+                int l = (int)sqrtf((float)lm);
+                l -= (l * l > lm);
+                l += ((l + 1) * (l + 1) <= lm);
+                const float c1t = (l == 0) ? a.c1[z * nch + ch] : 0.f;
+                float D2 = 0.f, D3 = 0.f;
+                if (a.order >= 2) {
+                    const float *C = Cs + ((size_t)l * nch + ch) * nch;
+                    const float *Al = As + lm * nchp;
+                    for (int bb = 0; bb < nch; ++bb)
+                        D2 += C[bb] * Al[bb];
+                }
+                if (a.order >= 3) {
+                    constexpr int kPre = 8;
+                    const int k0 = tbl[lm], nk = tbl[lm + 1] - k0;
+                    const int *cl = dcols + k0;
+                    float pv[kPre];
+#pragma unroll
+                    for (int k = 0; k < kPre; ++k)
+                        pv[k] = k < nk ? Dl[cl[k] + ch] : 0.f;
+#pragma unroll
+                    for (int k = 0; k < kPre; ++k)
+                        D3 += pv[k];
+                    for (int k = kPre; k < nk; ++k)
+                        D3 += Dl[cl[k] + ch];
+                }
+                val = c1t + 2.f * D2 + 3.f * D3;
+                es += (double)(As[lm * nchp + ch] * (c1t + D2 + D3));
+            }
+            Gt[ch * YW + lm] = val * wgt;
+        }
+        if (fa.e_exp) {
+#pragma unroll
+            for (int d = 32; d > 0; d >>= 1)
+                es += __shfl_xor(es, d);
+            if (lane == 0)
+                red[w] = es;
+        }
+    }
+    __syncthreads();  // G ready; the staged tables are free for the pair rows
+    if (fa.e_exp && tid == 0)
+        fa.e_exp[i] = (double)a.c0[z] + (((red[0] + red[1]) + red[2]) + red[3]);
+    const int nv_all = *nvs;
+
+    // this wave's share of the orders |m|
+    const int m_lo = w, m_hi = w < 3 ? w : a.lmax;
+    for (int rnd = 0; 64 * rnd < nv_all; ++rnd) {
+        if (rnd > 0) {
+            __syncthreads();  // every wave is done with the last round's geo and S rows
+            if (w == 0)
+                pairs_round(pos, n, b, species, a.ns, row, i, lane, rnd, pp, geo);
+            __syncthreads();
+        }
+        const int nv = min(64, nv_all - 64 * rnd);
+        const int p0 = 16 * w;              // this wave's row tile
+        const int nvw = min(16, nv - p0);   // its valid pairs (may be <= 0)
+        // ---- 3. rows and the S tile of pairs p0 .. p0 + 15
+        if (nvw > 0) {
+            if (lane < 16) {
+                float *rr = Rr + (p0 + lane) * RW, *dr = Dr + (p0 + lane) * RW;
+                for (int ch = 0; ch < 16 * MT; ++ch) {
+                    rr[ch] = 0.f;
+                    dr[ch] = 0.f;
+                }
+                if (lane < nvw) {
+                    const PairGeo gq = geo[p0 + lane];
+                    float R[kMaxNrad], dR[kMaxNrad];
+                    radial<float>(nrad, gq.r, a.rc, R, dR);
+#pragma unroll
+                    for (int k = 0; k < kMaxNrad; ++k)
+                        if (k < nrad) {
+                            rr[gq.zj * nrad + k] = R[k];
+                            dr[gq.zj * nrad + k] = dR[k];
+                        }
+                }
+            }
+            wave_sync_ace();
+            f4v_t sr[NT], sd[NT];
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+                sr[nt] = (f4v_t){0.f, 0.f, 0.f, 0.f};
+                sd[nt] = (f4v_t){0.f, 0.f, 0.f, 0.f};
+            }
+#pragma unroll
+            for (int k0 = 0; k0 < 16 * MT; k0 += 4) {
+                const int kc = k0 + kg;
+                const float xr = Rr[(p0 + m16) * RW + kc];
+                const float xd = Dr[(p0 + m16) * RW + kc];
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) {
+                    const float gb = Gt[kc * YW + nt * 16 + m16];
+                    sr[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(xr, gb, sr[nt], 0, 0, 0);
+                    sd[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(xd, gb, sd[nt], 0, 0, 0);
+                }
+            }
+            // lane holds S[pair row = p0 + 4 kg + v][lm = 16 nt + m16]
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int sl = p0 + 4 * kg + v, lm = nt * 16 + m16;
+                    SR[sl * YW + lm] = sr[nt][v];
+                    SD[sl * YW + lm] = sd[nt][v];
+                }
+        }
+        __syncthreads();  // every S row written; the R rows are free for the partial sums
+        // ---- 4. this wave's orders for every pair of the round (lane = pair)
+        {
+            float rad = 0.f, vx = 0.f, vy = 0.f, vz = 0.f;
+            if (lane < nv && m_lo <= a.lmax) {
+                const PairGeo gq = geo[lane];
+                const float *srow = SR + lane * YW, *drow = SD + lane * YW;
+                ylm_stream<float>(
+                    a.lmax, gq.ux, gq.uy, gq.uz, a.K,
+                    [&](int lm, float Y, float yx, float yy, float yz) {
+                        const float sR = srow[lm], sD = drow[lm];
+                        rad += sD * Y;
+                        vx += sR * yx;
+                        vy += sR * yy;
+                        vz += sR * yz;
+                    },
+                    m_lo, m_hi);
+            }
+            float *pw = part + ((size_t)w * 64 + lane) * 4;
+            pw[0] = rad;
+            pw[1] = vx;
+            pw[2] = vy;
+            pw[3] = vz;
+        }
+        __syncthreads();
+        // ---- the four partials in wave order, g to the pair's slot (wave w:
+        // pairs p0 .. p0 + 15 of the round)
+        if (lane < 16 && p0 + lane < nv) {
+            const int q = p0 + lane;
+            float acc[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                acc[k] = part[(size_t)q * 4 + k];
+#pragma unroll
+            for (int ww = 1; ww < 4; ++ww)
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    acc[k] += part[((size_t)ww * 64 + q) * 4 + k];
+            const PairGeo gq = geo[q];
+            const float rad = acc[0], vx = acc[1], vy = acc[2], vz = acc[3];
+            const float ud = gq.ux * vx + gq.uy * vy + gq.uz * vz;
+            gs[gq.slot * 3 + 0] = rad * gq.ux + (vx - gq.ux * ud) * gq.ir;
+            gs[gq.slot * 3 + 1] = rad * gq.uy + (vy - gq.uy * ud) * gq.ir;
+            gs[gq.slot * 3 + 2] = rad * gq.uz + (vz - gq.uz * ud) * gq.ir;
+        }
+    }
+}
+
 template <int MT, int NT>
 static size_t basis_mfma_lds()
 {
@@ -1238,19 +1462,48 @@ static void basis_mfma_launch(hipStream_t s, const Ctx &c, void *ws, const WsLay
 template <int MT, int NT>
 static void pairgrad_mfma_launch(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L,
                                  const Box &b, const double *pos, const int32_t *species,
-                                 const double *weights, const AceArgs<float> &a,
-                                 const FinArgs *fin)
+                                 const double *weights, const AceArgs<float> &a)
 {
     const size_t per = pairgrad_mfma_lds<MT, NT>();
     const int wpb = mfma_wpb(per);
-    auto kern = fin ? (L.nseg > 0 ? k_ace_pairgrad_mfma<MT, NT, true, true>
-                                  : k_ace_pairgrad_mfma<MT, NT, false, true>)
-                    : (L.nseg > 0 ? k_ace_pairgrad_mfma<MT, NT, true, false>
-                                  : k_ace_pairgrad_mfma<MT, NT, false, false>);
+    auto kern = L.nseg > 0 ? k_ace_pairgrad_mfma<MT, NT, true> : k_ace_pairgrad_mfma<MT, NT, false>;
     kern<<<(L.n + wpb - 1) / wpb, 64 * wpb, per * wpb, s>>>(
         pos, L.n, b, species, L.cap, at<int>(ws, L.nbr), at<int>(ws, L.cnt), at<int>(ws, L.S_idx),
         at<int>(ws, L.S_local), at<int>(ws, L.hdr), a, wpb, at<float>(ws, L.dEdA), weights,
-        at<float>(ws, L.g), seg_args(ws, L), fin ? *fin : FinArgs{});
+        at<float>(ws, L.g), seg_args(ws, L));
+}
+
+// The workgroup pair adjoint with the folded finalisation: (channel tiles,
+// lm tiles) within its instantiated range and every table within its LDS.
+static bool pair_wg_tiles(const Ctx &c, int &mt, int &nt)
+{
+    mt = (c.m.nchan + 15) / 16;
+    nt = (c.m.L2 + 15) / 16;
+    if (!(mt >= 1 && mt <= 2 && nt >= 1 && nt <= 3))
+        return false;
+    int span = 0, ncol = 0;
+    for (int k = 0; k < kDSumSets; ++k) {
+        span = std::max(span, c.m.dsum_span[k]);
+        ncol = std::max(ncol, c.m.dsum_ncol[k]);
+    }
+    const int nch = c.m.nchan;
+    const int tot = c.m.KAt + (c.m.order >= 2 ? (c.m.lmax + 1) * nch * nch : 0) +
+                    (c.m.order >= 3 ? span * nch : 0);
+    const int u = 64 * (16 * nt + 1) * 2 + 64 * (16 * mt + 1) * 2;
+    const int tblcap = ((16 * nt + 1 + 256) + 63) / 64 * 64;
+    return tot >= 1 && tot <= u && c.m.L2 + 1 + ncol <= tblcap;
+}
+
+template <int MT, int NT>
+static void pairgrad_wg_launch(hipStream_t s, const WsLayout &L, const Box &b, const double *pos,
+                               const int32_t *species, void *ws, const AceArgs<float> &a,
+                               const double *weights, const FinArgs &fin)
+{
+    const size_t lds = (size_t)PairWgLds<MT, NT, false>::FLOATS * sizeof(float);
+    auto kern = L.nseg > 0 ? k_ace_pairgrad_wg<MT, NT, true> : k_ace_pairgrad_wg<MT, NT, false>;
+    kern<<<L.n, 256, lds, s>>>(pos, L.n, b, species, L.cap, at<int>(ws, L.nbr), at<int>(ws, L.cnt),
+                               at<int>(ws, L.S_idx), at<int>(ws, L.S_local), at<int>(ws, L.hdr), a,
+                               weights, at<float>(ws, L.g), seg_args(ws, L), fin);
 }
 
 // (channel tiles, lm tiles) of the matrix-core basis / adjoint kernels: 0 if
@@ -1268,17 +1521,18 @@ static int mfma_tiles(const Ctx &c, bool pair, int &mt, int &nt)
     return mt >= 1 && mt <= 2 && nt >= 1 && nt <= 4;
 }
 
-// The pair adjoint computes dE/dA itself (the finalisation folded in): FP32
-// on the matrix cores, with the atom's A row and the partial-D column set
-// fitting the pair-row LDS space of a wave.
-bool ace_fin_fused(const Ctx &c)
+// The pair adjoint computes dE/dA itself (the finalisation folded in) in
+// the single-precision modes, where the workgroup pair adjoint takes the
+// model, for systems whose few S atoms leave the GPU latency-bound (8,193
+// atoms: 15.0 against 23.2 us for the one-wave form); large systems keep the
+// finalisation kernel and the one-wave adjoint (1,023,800 atoms: 0.69 + 0.43
+// against 2.08 ms). A batched call takes the workgroup form whatever its
+// size, so that a system gives the same bits alone and in any batch.
+bool ace_fin_fused(const Ctx &c, const WsLayout &L)
 {
     int mt, nt;
-    if (c.prec == MLMIX_FP64 || !c.basis_mfma || !c.fuse_fin || !mfma_tiles(c, true, mt, nt))
-        return false;
-    const int rw = 16 * mt + 1, yw = 16 * nt + 1;
-    const int pair = 64 * std::max(rw, yw) * 2;
-    return c.m.KAt + c.m.dsum_len <= pair;
+    return c.prec != MLMIX_FP64 && c.basis_mfma && c.fuse_fin && pair_wg_tiles(c, mt, nt) &&
+           (L.nseg > 0 || L.n <= 65536);
 }
 
 static DSumSel dsum_sel(const Ctx &c, const WsLayout &L, bool fp32)
@@ -1286,8 +1540,11 @@ static DSumSel dsum_sel(const Ctx &c, const WsLayout &L, bool fp32)
     DSumSel ds;
     ds.tab = reinterpret_cast<const int *>(static_cast<char *>(c.m.base) + c.m.dsum);
     const bool vsets = c.m.order >= 3 && c.m.n_pb > 0 && c.o3 == 1 && c.o3v && fp32;
-    for (int k = 0; k < kDSumBlocks; ++k)
+    for (int k = 0; k < kDSumBlocks; ++k) {
         ds.off[k] = c.m.dsum_off[vsets ? k : kDSumBlocks];
+        ds.span[k] = c.m.dsum_span[vsets ? k : kDSumBlocks];
+        ds.ncol[k] = c.m.dsum_ncol[vsets ? k : kDSumBlocks];
+    }
     ds.grid = vsets ? o3v_grid(c, L.n) : 1;
     ds.max_split = c.o3_max_split;
     return ds;
@@ -1297,8 +1554,7 @@ static DSumSel dsum_sel(const Ctx &c, const WsLayout &L, bool fp32)
 // instantiated range (then the VALU kernels run).
 template <bool PAIR>
 static bool mfma_dispatch(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L, const Box &b,
-                          const double *pos, const int32_t *species, const double *weights,
-                          const FinArgs *fin = nullptr)
+                          const double *pos, const int32_t *species, const double *weights)
 {
     AceArgs<float> a = make_args<float>(c);
     int mt, nt;
@@ -1307,7 +1563,7 @@ static bool mfma_dispatch(hipStream_t s, const Ctx &c, void *ws, const WsLayout 
 #define O3_GO(M, N)                                                                    \
     if (mt == M && nt == N) {                                                          \
         if (PAIR)                                                                      \
-            pairgrad_mfma_launch<M, N>(s, c, ws, L, b, pos, species, weights, a, fin); \
+            pairgrad_mfma_launch<M, N>(s, c, ws, L, b, pos, species, weights, a);      \
         else                                                                           \
             basis_mfma_launch<M, N>(s, c, ws, L, b, pos, species, a);                  \
         return true;                                                                   \
@@ -1485,14 +1741,21 @@ void launch_ace_pairgrad(hipStream_t s, const Ctx &c, void *ws, const WsLayout &
 {
     if (L.n == 0)
         return;
-    if (ace_fin_fused(c)) {
+    if (ace_fin_fused(c, L)) {
         FinArgs fa;
         fa.A = at<float>(ws, L.A);
         fa.Dpart = at<float>(ws, L.dpart);
         fa.dp_stride = c.m.dp_stride;
         fa.ds = dsum_sel(c, L, true);
         fa.e_exp = e_exp;
-        mfma_dispatch<true>(s, c, ws, L, b, pos, species, weights, &fa);
+        const AceArgs<float> a = make_args<float>(c);
+        int mt, nt;
+        pair_wg_tiles(c, mt, nt);
+#define WG_GO(M, N)                                                        \
+    if (mt == M && nt == N)                                                \
+        pairgrad_wg_launch<M, N>(s, L, b, pos, species, ws, a, weights, fa);
+        WG_GO(1, 1) WG_GO(1, 2) WG_GO(1, 3) WG_GO(2, 1) WG_GO(2, 2) WG_GO(2, 3)
+#undef WG_GO
     } else if (c.prec == MLMIX_FP64)
         pairgrad_t<double>(s, c, ws, L, b, pos, species, weights);
     else if (!(c.basis_mfma && mfma_dispatch<true>(s, c, ws, L, b, pos, species, weights)))

@@ -46,7 +46,7 @@ struct mlmix_ctx {
     std::unordered_map<void *, SideStream> side;
     std::unordered_map<void *, std::vector<mlmix_segment>> batch;  // segments of batch workspaces
     uint32_t prof_mask = 0;
-    double flops[6] = {0, 0, 0, 0, 0, 0};
+    double flops[7] = {0, 0, 0, 0, 0, 0, 0};
     std::vector<PendingEvent> pending;
     std::vector<hipEvent_t> pool;
 };
@@ -351,6 +351,8 @@ struct HostTables {
     std::vector<std::vector<std::vector<int>>> o3vsets;
     std::vector<int> dsum;  // the column sets of every form (DevModel::dsum)
     int dsum_off[kDSumSets] = {};
+    int dsum_span[kDSumSets] = {};  // per set: 1 + its largest column / nchan
+    int dsum_ncol[kDSumSets] = {};  // per set: the number of columns it lists
     int dsum_len = 0;
 };
 
@@ -489,17 +491,22 @@ static void build_dsum(const mlmix_model_desc &d, HostTables &t)
     const int lmax = d.ace_lmax, L2 = (lmax + 1) * (lmax + 1), nch = d.n_species * d.ace_n_rad;
     t.dsum.clear();
     t.dsum_len = 0;
+    int span = 0, ncol = 0;
     auto put = [&](const std::vector<std::vector<int>> &cols) -> int {
         const int off = (int)t.dsum.size();
         int k = 0;
+        span = 0;
         for (int lm = 0; lm < L2; ++lm) {
             t.dsum.push_back(k);
             k += (int)cols[lm].size();
+            for (int col : cols[lm])
+                span = std::max(span, col / nch + 1);
         }
         t.dsum.push_back(k);
         for (int lm = 0; lm < L2; ++lm)
             t.dsum.insert(t.dsum.end(), cols[lm].begin(), cols[lm].end());
         t.dsum_len = std::max(t.dsum_len, L2 + 1 + k);
+        ncol = k;
         return off;
     };
     std::vector<std::vector<int>> blocks(L2);
@@ -508,9 +515,15 @@ static void build_dsum(const mlmix_model_desc &d, HostTables &t)
             for (int m3 = 0; m3 < 2 * t.pb[p].l3 + 1; ++m3)
                 blocks[t.pb[p].l3 * t.pb[p].l3 + m3].push_back(t.dpoff[p] + m3 * nch);
     const int per_block = put(blocks);
-    for (int k = 0; k < kDSumBlocks; ++k)
+    const int per_block_span = span, per_block_ncol = ncol;
+    for (int k = 0; k < kDSumBlocks; ++k) {
         t.dsum_off[k] = k < (int)t.o3vsets.size() ? put(t.o3vsets[k]) : per_block;
+        t.dsum_span[k] = k < (int)t.o3vsets.size() ? span : per_block_span;
+        t.dsum_ncol[k] = k < (int)t.o3vsets.size() ? ncol : per_block_ncol;
+    }
     t.dsum_off[kDSumBlocks] = per_block;
+    t.dsum_span[kDSumBlocks] = per_block_span;
+    t.dsum_ncol[kDSumBlocks] = per_block_ncol;
 }
 
 static void build_o3(const mlmix_model_desc &d, HostTables &t, int waves)
@@ -1301,13 +1314,21 @@ try {
         ctx->flops[4] = 444.0;  // cheap 3-body, per unordered leg pair (r_jk spline, 4x4x4
                                 // contraction with the three derivatives, two leg forces)
         ctx->flops[5] = dense;                                // dense order-3 stage, per S atom
+        // finalisation per S atom: per (channel, lm) the order-2 product
+        // (2 per channel), dE/dA = c1 + 2 D2 + 3 D3, the energy term and the
+        // weight (9), plus one add per listed partial-D column and channel
+        ctx->flops[6] = (double)nch * L2d * ((d.ace_order >= 2 ? 2.0 * nch : 0.0) + 9.0) +
+                        (d.ace_order >= 3 ? (double)t.dsum_ncol[0] * nch : 0.0);
     }
     c.max_ent = 0;
     c.max_gm3 = 0;
     c.max_ent_pb = 0;
     m.dp_stride = t.dp_stride;
-    for (int k = 0; k < kDSumSets; ++k)
+    for (int k = 0; k < kDSumSets; ++k) {
         m.dsum_off[k] = t.dsum_off[k];
+        m.dsum_span[k] = t.dsum_span[k];
+        m.dsum_ncol[k] = t.dsum_ncol[k];
+    }
     m.dsum_len = t.dsum_len;
     for (const PBlock &p : t.pb)
         c.max_ent_pb = std::max(c.max_ent_pb, t.gm3[p.gm3_off + 2 * p.l3 + 1] - t.gm3[p.gm3_off]);
@@ -1521,13 +1542,14 @@ static int compute_impl(mlmix_ctx *ctx, hipStream_t s, void *ws, const WsLayout 
     }
     hipStream_t s2 = fork ? sd.s : s;  // stream of the reverse slots and the cheap potential
     // workgroup cap of those two kernels when they run beside the expensive
-    // chain (leave it room: one workgroup per compute unit measured best for
-    // systems of some thousand atoms); on one stream or beside no expensive
-    // work they run uncapped
+    // chain (MLMIX_SIDE_BLOCKS; none by default: with the workgroup pair
+    // adjoint the expensive chain of an 8,193-atom step is short enough that
+    // the cheap potential needs the whole GPU beside it, 95.7 against
+    // 100.9 us per step with one workgroup per compute unit)
     const int rev_blocks = c.rev_blocks;
     const int side_blocks = (!fork || m == MLMIX_MODE_ALL_CHEAP)
                                 ? 0
-                                : (c.side_blocks >= 0 ? c.side_blocks : (L.n < 262144 ? 256 : 0));
+                                : (c.side_blocks >= 0 ? c.side_blocks : 0);
     {
         StageTimer t(ctx, s, ST_NBR);
         RegionArgs ra{m, species, c.m.ns, regions, n_regions, r_buffer, lambda, flags, nullptr,
@@ -1631,7 +1653,7 @@ static int compute_impl(mlmix_ctx *ctx, hipStream_t s, void *ws, const WsLayout 
         }
         // the finalisation runs inside the pair adjoint where that kernel
         // can take it (the energy-only call keeps its own kernel)
-        const bool fused = !energy_only && ace_fin_fused(c);
+        const bool fused = !energy_only && ace_fin_fused(c, L);
         if (!fused) {
             StageTimer t(ctx, s, ST_FIN);
             launch_ace_finalize(s, c, ws, L, species, e_exp);
@@ -2520,16 +2542,18 @@ try {
 
 extern "C" int mlmix_profile_replay(mlmix_ctx *ctx, void *stream, void *ws, int32_t n_atoms,
                                     const double *pos, const int32_t *species,
-                                    const mlmix_box *box, double *e_cheap, int32_t stage,
+                                    const mlmix_box *box, double *e_out, int32_t stage,
                                     int32_t reps)
 try {
     if (!ctx || !ws || !species || reps < 0)
         return fail(MLMIX_E_ARG, "NULL argument or negative count");
-    if (stage != ST_CONTRACT && stage != ST_UF3)
-        return fail(MLMIX_E_ARG, "only the order-3 contraction (stage 4) and the cheap "
-                                 "potential (stage 7) can be replayed");
-    if (stage == ST_UF3 && (!pos || !box || !e_cheap))
-        return fail(MLMIX_E_ARG, "the cheap potential needs pos, box and e_cheap");
+    if (stage != ST_CONTRACT && stage != ST_PAIR && stage != ST_UF3)
+        return fail(MLMIX_E_ARG, "only the order-3 contraction (stage 4), the pair adjoint "
+                                 "(stage 6) and the cheap potential (stage 7) can be replayed");
+    if ((stage == ST_UF3 || stage == ST_PAIR) && (!pos || !box || !e_out))
+        return fail(MLMIX_E_ARG, "the pair adjoint and the cheap potential need pos, box and e_out");
+    if (stage == ST_PAIR && ctx->c.prec == MLMIX_FP64)
+        return fail(MLMIX_E_ARG, "the pair adjoint replays in the single-precision modes only");
     WsLayout L;
     {
         std::lock_guard<std::mutex> g(ctx->mu);
@@ -2543,7 +2567,7 @@ try {
     if (L.nseg > 0)
         return fail(MLMIX_E_ARG, "replays take a single-system workspace");
     Box b{};
-    if (stage == ST_UF3) {
+    if (stage != ST_CONTRACT) {
         int rc = check_box(ctx, box, b);
         if (rc)
             return rc;
@@ -2552,8 +2576,11 @@ try {
     for (int r = 0; r < reps; ++r) {
         if (stage == ST_CONTRACT)
             launch_ace_contract(s, ctx->c, ws, L, species);
+        else if (stage == ST_PAIR)  // with the finalisation where a step folds it in
+            launch_ace_pairgrad(s, ctx->c, ws, L, b, pos, species, nullptr,
+                                ace_fin_fused(ctx->c, L) ? e_out : nullptr);
         else  // uncapped, as on one stream
-            launch_uf3(s, ctx->c, ws, L, b, pos, species, e_cheap, 0);
+            launch_uf3(s, ctx->c, ws, L, b, pos, species, e_out, 0);
     }
     HIP_OK(hipGetLastError());
     return MLMIX_OK;
@@ -2613,7 +2640,7 @@ extern "C" int mlmix_model_flops(const mlmix_ctx *ctx, double *out)
 try {
     if (!ctx || !out)
         return fail(MLMIX_E_ARG, "NULL argument");
-    for (int i = 0; i < 6; ++i)
+    for (int i = 0; i < 7; ++i)
         out[i] = ctx->flops[i];
     return MLMIX_OK;
 } catch (...) {

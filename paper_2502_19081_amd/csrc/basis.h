@@ -73,13 +73,16 @@ __host__ __device__ inline T inv_small(int k)
 // gradients with respect to (x, y, z) of the polynomial extension, streamed
 // in (m, l) order: Y_lm = K_lm Q_l^|m|(z) {C_m, 1, S_|m|}, Q_l^m = d^m P_l/dz^m
 // by the three-term recurrence, C_m + i S_m = (x + i y)^m, dQ_l^m/dz = Q_l^{m+1}.
+// Only the orders m_lo <= |m| <= m_hi are emitted (the same values as the
+// full stream gives for them).
 template <typename T, typename F>
 __host__ __device__ inline void ylm_stream(int lmax, T x, T y, T z, const T *__restrict__ K,
-                                           F &&emit)
+                                           F &&emit, int m_lo = 0, int m_hi = 1 << 30)
 {
     T Cm = T(1), Sm = T(0), Cp = T(0), Sp = T(0);
     T dfm = T(1);
-    for (int m = 0; m <= lmax; ++m) {
+    const int mtop = m_hi < lmax ? m_hi : lmax;
+    for (int m = 0; m <= mtop; ++m) {
         if (m > 0) {
             T c = x * Cm - y * Sm;
             T s = x * Sm + y * Cm;
@@ -89,6 +92,8 @@ __host__ __device__ inline void ylm_stream(int lmax, T x, T y, T z, const T *__r
             Sm = s;
             dfm *= T(2 * m - 1);
         }
+        if (m < m_lo)
+            continue;
         T dfm1 = dfm * T(2 * m + 1);
         T qa1 = T(0), qa2 = T(0), qb1 = T(0), qb2 = T(0);
         for (int l = m; l <= lmax; ++l) {

@@ -152,9 +152,10 @@ struct DevModel {
     int dp_stride;  // partial-D entries per S atom (sum over blocks of nchan*(2 l3 + 1))
     // partial-D column lists: set k at dsum + dsum_off[k] holds L2 + 1 run
     // offsets, then the columns (atom-relative, channel 0) summed into each
-    // (l3, m3) in that order; dsum_len = the longest set in ints
+    // (l3, m3) in that order; dsum_len = the longest set in ints; the
+    // columns of set k lie in the first dsum_span[k] * nchan entries of a row
     size_t dsum;
-    int dsum_off[kDSumSets], dsum_len;
+    int dsum_off[kDSumSets], dsum_span[kDSumSets], dsum_ncol[kDSumSets], dsum_len;
     int w_per_species;  // entries of W per centre species
     int gm3_total, g_total;
 };
@@ -165,6 +166,8 @@ struct DevModel {
 struct DSumSel {
     const int *tab;
     int off[kDSumBlocks];
+    int span[kDSumBlocks];  // the set's columns lie in [0, span * nchan) of a row
+    int ncol[kDSumBlocks];  // columns listed in the set (its table: L2 + 1 + ncol ints)
     int grid, max_split;
 };
 
@@ -194,19 +197,20 @@ struct Ctx {
     int basis_chunks = -1; // basis in 64-slot passes: -1 above 65,536 atoms, 0 never, 1 always
     // second-stream fork after the rows (0), after the basis (1), or recorded
     // after the rows and issued after the compaction (2). Measured per mixed
-    // step on 8,193 atoms with the vector-sparse contraction: 100.2 / 100.7 /
-    // 101.0 us at 0 against 106.7 / 105.9 / 105.6 us at 2 (alternating runs;
-    // an earlier, longer expensive chain preferred 2)
-    int fork_at = 0;
+    // step on 8,193 atoms with the workgroup pair adjoint and the cheap
+    // potential uncapped: 95.5 / 95.8 / 95.7 us at 2 against 101.0 / 101.5 /
+    // 101.8 us at 0 (alternating runs; the one-wave adjoint's longer chain
+    // preferred 0)
+    int fork_at = 2;
     // workgroup cap of the cheap-potential kernel on the second stream
     // (grid-stride loop): -1 automatic, 0 uncapped. The best cap follows the
-    // length of the expensive chain beside it; measured per mixed step on
-    // 8,193 atoms (list kept within the skin, fork point 2): 160 / 129 / 111
-    // / 123 / 120 / 120 / 126 us at 128 / 192 / 256 / 384 / 512 / 1024
-    // workgroups / uncapped. On 1,023,800 atoms caps of 1024 and 2048
-    // measured no better than none (11.6 / 11.2 / 11.3 ms, same box).
-    // Automatic: 256 (one per compute unit) below 262,144 atoms, uncapped
-    // above.
+    // length of the expensive chain beside it. With the one-wave pair adjoint,
+    // per mixed step on 8,193 atoms: 160 / 129 / 111 / 123 / 120 / 120 / 126
+    // us at 128 / 192 / 256 / 384 / 512 / 1024 workgroups / uncapped; with
+    // the shorter chain of the workgroup pair adjoint (fork point 2): 95.7 /
+    // 96.1 us uncapped / 768 against 100.9 us at 256. On 1,023,800 atoms caps
+    // of 1024 and 2048 measured no better than none (11.6 / 11.2 / 11.3 ms).
+    // Automatic: uncapped.
     int side_blocks = -1;
     int rev_blocks = 1024;  // cap of the reverse-slot kernel when capped (256 / 1024 measured 153.0 / 152.4 us)
     int o3_nch2 = 0;       // row width of that kernel (channels rounded up to 4)
@@ -288,7 +292,7 @@ void launch_ace_finalize(hipStream_t s, const Ctx &c, void *ws, const WsLayout &
 void launch_ace_pairgrad(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L, const Box &b,
                          const double *pos, const int32_t *species, const double *weights,
                          double *e_exp);
-bool ace_fin_fused(const Ctx &c);
+bool ace_fin_fused(const Ctx &c, const WsLayout &L);
 
 // ---- o3.hip ----
 void launch_ace_o3(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L,
