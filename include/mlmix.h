@@ -63,11 +63,14 @@ extern "C" {
  * contraction (the coupled products P of two atomic-basis blocks against the
  * weights), whose operands are rounded to BF16 or scaled to FP8 with FP32
  * accumulation on the matrix cores. FP8 is OCP E4M3 with two kinds of
- * scale, neither data-dependent across atoms: each row of P (one atom, one
- * (l1, l2, l3) block, one m3) is divided by the bound
- * sum|Gaunt| x max_m1|A_l1| x max_m2|A_l2| / 240 of its entries, and each
- * output channel c of a block's weights by max|W(., c)| / 240; the product
- * is rescaled in FP32 after the accumulation. */
+ * scale, neither shared across atoms: each row of P (one atom, one
+ * (l1, l2, l3) block, one m3) is divided by its own largest magnitude / 240
+ * (by the bound sum|Gaunt| x max_m1|A_l1| x max_m2|A_l2| / 240 in the
+ * matrix-core sparse form, used when a model's rows do not fit the default
+ * vector form), and each output channel c of a block's weights by
+ * max|W(., c)| / 240; each row's product is multiplied back by both scales
+ * in FP32 after its accumulation, before it joins the FP32 sum over the
+ * rows that share an output (l3, m3). */
 #define MLMIX_FP64 0
 #define MLMIX_FP32 1
 #define MLMIX_BF16_CONTRACT 2
