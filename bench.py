@@ -151,6 +151,8 @@ def cpu_model():
 
 
 KERNEL_SOURCES = {"ace_contract": ["paper_2502_19081_amd/csrc/o3.hip", "paper_2502_19081_amd/csrc/internal.h"],
+                  "ace_pairgrad": ["paper_2502_19081_amd/csrc/ace.hip", "paper_2502_19081_amd/csrc/basis.h",
+                                   "paper_2502_19081_amd/csrc/internal.h"],
                   "uf3": ["paper_2502_19081_amd/csrc/uf3.hip", "paper_2502_19081_amd/csrc/internal.h"]}
 
 
