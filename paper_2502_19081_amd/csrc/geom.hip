@@ -801,7 +801,11 @@ void launch_neighbors(hipStream_t s, void *ws, const WsLayout &L, const Box &b, 
 
 // Reverse slots of a rebuilt list (skipped on the device when the list was
 // kept); needed by the force gather only, so it may run beside the potentials.
-// Uncapped form: one thread per (i, s), early-exit binary search in row j.
+// Uncapped form: one thread per (i, s), early-exit binary search in row j,
+// over a grid of at most kRevFlatBlocks workgroups that strides over the
+// slots (a kept list then costs a few microseconds instead of the dispatch of
+// one workgroup per 256 slots: 1M atoms x 128 slots are 512k workgroups).
+constexpr unsigned kRevFlatBlocks = 16384;
 __global__ void __launch_bounds__(256) k_reverse_flat(int n, int cap, const int *__restrict__ nbr,
                                                       const int *__restrict__ cnt,
                                                       int *__restrict__ rev,
@@ -809,33 +813,37 @@ __global__ void __launch_bounds__(256) k_reverse_flat(int n, int cap, const int 
 {
     if (hdr[H_REBUILD] == 0)
         return;
-    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < (size_t)ncell)
-        count[t] = 0;
-    if (t >= (size_t)n * cap)
-        return;
-    // 32-bit division whenever the index fits (64-bit division is slow)
-    const int i = t < 0xffffffffull ? (int)((unsigned)t / (unsigned)cap) : (int)(t / cap);
-    const int sl = (int)(t - (size_t)i * cap);
-    int r = -1;
-    if (sl < cnt[i]) {
-        const int j = nbr[t];
-        const int *rowj = nbr + (size_t)j * cap;
-        int lo = 0, hi = cnt[j] - 1;
-        while (lo <= hi) {
-            const int mid = (lo + hi) >> 1;
-            const int v = rowj[mid];
-            if (v == i) {
-                r = mid;
-                break;
+    const size_t nslot = (size_t)n * cap;
+    const size_t tot = nslot > (size_t)ncell ? nslot : (size_t)ncell;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < tot; t += stride) {
+        if (t < (size_t)ncell)
+            count[t] = 0;
+        if (t >= nslot)
+            continue;
+        // 32-bit division whenever the index fits (64-bit division is slow)
+        const int i = t < 0xffffffffull ? (int)((unsigned)t / (unsigned)cap) : (int)(t / cap);
+        const int sl = (int)(t - (size_t)i * cap);
+        int r = -1;
+        if (sl < cnt[i]) {
+            const int j = nbr[t];
+            const int *rowj = nbr + (size_t)j * cap;
+            int lo = 0, hi = cnt[j] - 1;
+            while (lo <= hi) {
+                const int mid = (lo + hi) >> 1;
+                const int v = rowj[mid];
+                if (v == i) {
+                    r = mid;
+                    break;
+                }
+                if (v < i)
+                    lo = mid + 1;
+                else
+                    hi = mid - 1;
             }
-            if (v < i)
-                lo = mid + 1;
-            else
-                hi = mid - 1;
         }
+        rev[t] = r;
     }
-    rev[t] = r;
 }
 
 void launch_reverse(hipStream_t s, void *ws, const WsLayout &L, int side_blocks)
@@ -847,7 +855,7 @@ void launch_reverse(hipStream_t s, void *ws, const WsLayout &L, int side_blocks)
     // beside the expensive chain: a wave per atom, grid-stride
     const size_t tot = std::max((size_t)n * L.cap, (size_t)L.grid.ncell);
     if (side_blocks <= 0 || (tot + 255) / 256 <= (size_t)side_blocks) {
-        k_reverse_flat<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(
+        k_reverse_flat<<<(unsigned)std::min<size_t>((tot + 255) / 256, kRevFlatBlocks), 256, 0, s>>>(
             n, L.cap, at<int>(ws, L.nbr), at<int>(ws, L.cnt), at<int>(ws, L.rev),
             at<int>(ws, L.cell_count), L.grid.ncell, at<int>(ws, L.hdr));
         return;
