@@ -599,6 +599,114 @@ __global__ void __launch_bounds__(256)
     }
 }
 
+// The same pair adjoint in FP32 with two S atoms per wave (32 lanes each) for
+// large systems: each half first lists its row's valid pairs (partner in S,
+// inside the cutoff) in LDS by ballot, then its 32 lanes take the listed
+// pairs 32 at a time, recomputing the geometry; invalid slots get a zero
+// gradient from their owner lane. At lmax 5 and 26 pairs in a row of 64 slots
+// this keeps about 80 % of the lanes on the harmonic work instead of 40 %.
+template <bool SEG>
+__global__ void __launch_bounds__(256)
+    k_ace_pairgrad_h(const double *__restrict__ pos, int n, Box b0,
+                     const int32_t *__restrict__ species, int cap, const int *__restrict__ nbr,
+                     const int *__restrict__ cnt, const int *__restrict__ S_idx,
+                     const int *__restrict__ S_local, const int *__restrict__ hdr,
+                     AceArgs<float> a, const float *__restrict__ dEdA,
+                     const double *__restrict__ weights, float *__restrict__ g, Seg sg)
+{
+    const int nS = hdr[H_NS];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int half = lane >> 5, hl = lane & 31;
+    const int s0 = (blockIdx.x * 4 + w) * 2;
+    if (s0 >= nS)
+        return;  // uniform across the wave; no block barrier in this kernel
+    const int s = s0 + half;
+    const bool live = s < nS;
+    extern __shared__ __align__(16) char smem_raw[];
+    // per wave: dE/dA rows of its two atoms, then the two pair lists
+    float *dAs = reinterpret_cast<float *>(smem_raw) + (size_t)w * (2 * a.KAt + 2 * cap);
+    int *lst = reinterpret_cast<int *>(dAs + 2 * a.KAt);
+    float *dA = dAs + half * a.KAt;
+    int *pl = lst + half * cap;
+    const int i = live ? S_idx[s] : 0;
+    const Box b = seg_box<SEG, false>(b0, sg, i);
+    const float wgt = (weights && live) ? float(weights[i]) : 1.0f;
+    if (live)
+        for (int e = hl; e < a.KAt; e += 32)
+            dA[e] = dEdA[(size_t)s * a.KAt + e] * wgt;
+    const int c = live ? cnt[i] : 0;
+    const int cmax = max(c, __shfl_xor(c, 32));
+    const int *row = nbr + (size_t)i * cap;
+    float *gs = g + (size_t)s * cap * 3;
+    // 1. the valid pairs of each half's row, listed in slot order
+    int nv = 0;
+    for (int base = 0; base < cmax; base += 32) {
+        const int slot = base + hl;
+        bool ok = false;
+        if (slot < c) {
+            const int j = row[slot];
+            if (S_local[j] >= 0) {
+                double d[3];
+                pair_disp_d(pos, n, i, j, b, d);
+                ok = norm2_d(d) < a.rc2;
+            }
+            if (!ok) {
+                gs[slot * 3 + 0] = 0.f;
+                gs[slot * 3 + 1] = 0.f;
+                gs[slot * 3 + 2] = 0.f;
+            }
+        }
+        const unsigned long long m = __ballot(ok);
+        const unsigned hm = (unsigned)(m >> (32 * half));
+        if (ok)
+            pl[nv + __popc(hm & ((1u << hl) - 1u))] = slot;
+        nv += __popc(hm);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // 2. the listed pairs, 32 per round in each half
+    const int nvmax = max(nv, __shfl_xor(nv, 32));
+    for (int base = 0; base < nvmax; base += 32) {
+        const int k = base + hl;
+        if (k >= nv)
+            continue;
+        const int slot = pl[k];
+        const int j = row[slot];
+        double d[3];
+        pair_disp_d(pos, n, i, j, b, d);
+        const double rd = sqrt(norm2_d(d));
+        const double ird = 1.0 / rd;
+        const float r = float(rd);
+        const float ux = float(d[0] * ird), uy = float(d[1] * ird), uz = float(d[2] * ird);
+        float R[kMaxNrad], dR[kMaxNrad];
+        radial<float>(a.nrad, r, a.rc, R, dR);
+        const float *col = dA + sp_clamp(species[j], a.ns) * a.nrad;
+        float rad = 0.f, vx = 0.f, vy = 0.f, vz = 0.f;
+        const int nchp = a.nchp, nrad = a.nrad;
+        ylm_stream<float>(a.lmax, ux, uy, uz, a.K, [&](int lm, float Y, float yx, float yy, float yz) {
+            float sR = 0.f, sD = 0.f;
+            const float *cl = col + lm * nchp;
+#pragma unroll
+            for (int q = 0; q < kMaxNrad; ++q)
+                if (q < nrad) {
+                    const float v = cl[q];
+                    sR += v * R[q];
+                    sD += v * dR[q];
+                }
+            rad += sD * Y;
+            vx += sR * yx;
+            vy += sR * yy;
+            vz += sR * yz;
+        });
+        const float ud = ux * vx + uy * vy + uz * vz;
+        const float ir = float(ird);
+        gs[slot * 3 + 0] = rad * ux + (vx - ux * ud) * ir;
+        gs[slot * 3 + 1] = rad * uy + (vy - uy * ud) * ir;
+        gs[slot * 3 + 2] = rad * uz + (vz - uz * ud) * ir;
+    }
+}
+
 template <typename T>
 static AceArgs<T> make_args(const Ctx &c)
 {
@@ -1681,6 +1789,18 @@ static void pairgrad_t(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L,
 {
     AceArgs<T> a = make_args<T>(c);
     int n = L.n;
+    if constexpr (sizeof(T) == 4) {
+        if (c.pair_half) {
+            // two atoms per wave, four waves per workgroup
+            const size_t sm = (size_t)4 * (2 * a.KAt + 2 * L.cap) * sizeof(float);
+            auto kern = L.nseg > 0 ? k_ace_pairgrad_h<true> : k_ace_pairgrad_h<false>;
+            kern<<<(n + 7) / 8, 256, sm, s>>>(
+                pos, n, b, species, L.cap, at<int>(ws, L.nbr), at<int>(ws, L.cnt),
+                at<int>(ws, L.S_idx), at<int>(ws, L.S_local), at<int>(ws, L.hdr), a,
+                at<float>(ws, L.dEdA), weights, at<float>(ws, L.g), seg_args(ws, L));
+            return;
+        }
+    }
     const int wpb = 4;
     size_t sm = (size_t)wpb * a.KAt * sizeof(T) + 16;
     auto kern = L.nseg > 0 ? k_ace_pairgrad<T, true> : k_ace_pairgrad<T, false>;

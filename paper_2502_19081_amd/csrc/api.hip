@@ -1361,6 +1361,8 @@ try {
         c.o3v = 0;  // a bin longer than the kernel's row registers hold, or an empty row
     if (const char *e = std::getenv("MLMIX_BASIS_CHUNKS"))
         c.basis_chunks = std::max(-1, std::min(1, std::atoi(e)));
+    if (const char *e = std::getenv("MLMIX_PAIR_HALF"))
+        c.pair_half = std::atoi(e) ? 1 : 0;  // 0: one atom per wave (comparisons)
     if (const char *e = std::getenv("MLMIX_BASIS_MFMA"))
         c.basis_mfma = std::atoi(e) ? 1 : 0;  // VALU kernels (comparisons)
     if (const char *e = std::getenv("MLMIX_ACE_O3")) {

@@ -195,6 +195,7 @@ struct Ctx {
     int max_lds = 65536;   // dynamic LDS a workgroup may use on this device
     int basis_mfma = 1;    // atomic basis and pair adjoint on the matrix cores (FP32)
     int basis_chunks = -1; // basis in 64-slot passes: -1 above 65,536 atoms, 0 never, 1 always
+    int pair_half = 1;     // FP32 vector pair adjoint with two atoms per wave (0: one)
     // second-stream fork after the rows (0), after the basis (1), or recorded
     // after the rows and issued after the compaction (2). Measured per mixed
     // step on 8,193 atoms with the workgroup pair adjoint and the cheap
