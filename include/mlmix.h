@@ -70,7 +70,10 @@ extern "C" {
  * vector form), and each output channel c of a block's weights by
  * max|W(., c)| / 240; each row's product is multiplied back by both scales
  * in FP32 after its accumulation, before it joins the FP32 sum over the
- * rows that share an output (l3, m3). */
+ * rows that share an output (l3, m3). The BF16 mode takes models of at most
+ * 32 channels (species x radial functions) of correlation order 3, the FP8
+ * mode single-species models of at most 16; mlmix_create returns MLMIX_E_ARG
+ * for other models in these modes. */
 #define MLMIX_FP64 0
 #define MLMIX_FP32 1
 #define MLMIX_BF16_CONTRACT 2

@@ -339,6 +339,7 @@ struct HostTables {
     int o3_kind = 0;  // 1 single-species narrow form, 2 wide form
     bool o3_wide_ready = false;  // wide-form weight fragments built
     std::vector<double> o3ww;
+    std::vector<int32_t> o3wwb;  // BF16 wide-form fragments, two values per int
     int o3_nch2 = 0;
     std::vector<double> o3g, o3w, o3sw, o3gs;
     std::vector<int> o3o, o3mt, o3mtv, o3base, o3order, o3wbeg;
@@ -526,6 +527,17 @@ static void build_dsum(const mlmix_model_desc &d, HostTables &t)
     t.dsum_ncol[kDSumBlocks] = per_block_ncol;
 }
 
+// BF16 bits of a float, rounded to nearest with ties to even (the rounding
+// the device's conversion applies to the products it packs).
+static uint32_t bf16_bits(float f)
+{
+    uint32_t u;
+    std::memcpy(&u, &f, sizeof(u));
+    if ((u & 0x7fffffffu) > 0x7f800000u)
+        return (u >> 16) | 0x40u;  // NaN stays NaN
+    return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+
 static void build_o3(const mlmix_model_desc &d, HostTables &t, int waves)
 {
     const int nch = d.n_species * d.ace_n_rad, lmax = d.ace_lmax;
@@ -536,7 +548,8 @@ static void build_o3(const mlmix_model_desc &d, HostTables &t, int waves)
     if (d.ace_order < 3 || t.pb.empty() || d.precision == MLMIX_FP64)
         return;
     const bool narrow_ok = d.n_species == 1 && nch <= 16;
-    const bool wide_ok = !narrow_ok && nch <= 32 && d.precision == MLMIX_FP32;
+    const bool wide_ok = !narrow_ok && nch <= 32 &&
+                         (d.precision == MLMIX_FP32 || d.precision == MLMIX_BF16_CONTRACT);
     if (!narrow_ok && !wide_ok)
         return;
     const int kind = narrow_ok ? 1 : 2;
@@ -611,6 +624,38 @@ static void build_o3(const mlmix_model_desc &d, HostTables &t, int waves)
                                         NJP) + j] = v;
                             }
         t.o3_wide_ready = true;
+    }
+    if (kind == 2 && d.precision == MLMIX_BF16_CONTRACT) {
+        // BF16 fragments of the wide form's dense stage: per pass of eight
+        // channels a (a0 = 8 pa), the pass's K values kk = (a - a0) nchp + b
+        // in 32-deep steps; lane (c = 16 ct + l % 16, q = l / 16) holds
+        // W[a][b][c] of kk = 32 st + 8 q + u, u < 8, rounded to nearest even
+        const int ns = d.n_species, np = (nchp + 7) / 8, nstm = nchp / 4;
+        t.o3wwb.assign((size_t)ns * P * np * NT * nstm * 64 * 4, 0);
+        for (int z = 0; z < ns; ++z)
+            for (size_t p = 0; p < P; ++p)
+                for (int pa = 0; pa < np; ++pa) {
+                    const int a0 = 8 * pa, kp = std::min(8, nchp - a0) * nchp;
+                    for (int ct = 0; ct < NT; ++ct)
+                        for (int st = 0; st < nstm; ++st)
+                            for (int l = 0; l < 64; ++l) {
+                                const int c = 16 * ct + (l & 15), q = l >> 4;
+                                uint32_t bits[8];
+                                for (int u = 0; u < 8; ++u) {
+                                    const int kk = 32 * st + 8 * q + u;
+                                    double v = 0.0;
+                                    const int a = a0 + kk / nchp, b = kk % nchp;
+                                    if (kk < kp && a < nch && b < nch && c < nch)
+                                        v = t.W[(size_t)z * t.w_per_species + t.pb[p].w_off +
+                                                ((size_t)a * nchp + b) * nchp + c];
+                                    bits[u] = bf16_bits((float)v);
+                                }
+                                int32_t *dst = &t.o3wwb[(((((((size_t)z * P + p) * np + pa) * NT + ct) *
+                                                            nstm + st) * 64 + l) * 4)];
+                                for (int k = 0; k < 4; ++k)
+                                    dst[k] = (int32_t)(bits[2 * k] | (bits[2 * k + 1] << 16));
+                            }
+                }
     }
     if (kind == 2) {
         t.o3sw.assign(P * 16, 1.0);
@@ -1016,6 +1061,7 @@ static std::vector<char> pack(const HostTables &t, DevModel &m)
     append_raw(blob, m.o3base, t.o3base);
     append<float>(blob, m.o3w, t.o3w);
     append<float>(blob, m.o3ww, t.o3ww);
+    append_raw(blob, m.o3wwb, t.o3wwb);
     append<float>(blob, m.o3sw, t.o3sw);
     append_raw(blob, m.o3order, t.o3order);
     append_raw(blob, m.o3wbeg, t.o3wbeg);
@@ -1206,9 +1252,8 @@ try {
         d.precision != MLMIX_BF16_CONTRACT && d.precision != MLMIX_FP8_CONTRACT)
         return fail(MLMIX_E_ARG, "precision must be MLMIX_FP64, MLMIX_FP32, MLMIX_BF16_CONTRACT or "
                                  "MLMIX_FP8_CONTRACT");
-    if ((d.precision == MLMIX_BF16_CONTRACT || d.precision == MLMIX_FP8_CONTRACT) &&
-        d.n_species != 1)
-        return fail(MLMIX_E_ARG, "the BF16/FP8 contraction modes support one species");
+    if (d.precision == MLMIX_FP8_CONTRACT && d.n_species != 1)
+        return fail(MLMIX_E_ARG, "the FP8 contraction mode supports one species");
     if (d.ace_n_rad < 1 || d.ace_n_rad > kMaxNrad || d.ace_lmax < 0 || d.ace_lmax > kMaxLmax ||
         d.ace_order < 1 || d.ace_order > 3 || !(d.ace_rcut > 0.0))
         return fail(MLMIX_E_ARG, "ACE sizes out of range (n_rad 1..16, lmax 0..6, order 1..3)");
@@ -1383,9 +1428,10 @@ try {
         (void)hipGetLastError();
         c.o3 = 0;  // the wide form does not fit this device: VALU blocks
     }
-    if (c.qmode != 0 && c.o3 != 1) {
-        return fail(MLMIX_E_ARG, "the BF16/FP8 contraction modes need a single-species model "
-                                 "with at most 16 radial channels and correlation order 3");
+    if ((c.qmode == 2 && c.o3 != 1) || (c.qmode == 1 && c.o3 == 0)) {
+        return fail(MLMIX_E_ARG, "the FP8 contraction mode needs a single-species model with at "
+                                 "most 16 channels, the BF16 mode a model of at most 32 channels "
+                                 "(species x radial functions), both correlation order 3");
     }
     std::vector<char> blob = c.prec == MLMIX_FP64 ? pack<double>(t, m) : pack<float>(t, m);
     m.bytes = blob.size();

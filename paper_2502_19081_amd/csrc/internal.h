@@ -148,7 +148,8 @@ struct DevModel {
     size_t ylmK, c0, c0d, c1, c2s, W, pb, gm3, gidx, gofs, gval, u2, u3, up2, up3, dpoff, wsc;
     // tables of the matrix-core order-3 kernel (single species, <= 16 channels)
     size_t o3o, o3mt, o3mtv, o3rowv, o3rbeg, o3wr, o3base, o3w, o3sw, o3order, o3wbeg, o3gs;
-    size_t o3ww;  // weight fragments of the wide form
+    size_t o3ww;   // weight fragments of the wide form
+    size_t o3wwb;  // its BF16 fragments (BF16 mode: eight values per lane and 32-deep step)
     int dp_stride;  // partial-D entries per S atom (sum over blocks of nchan*(2 l3 + 1))
     // partial-D column lists: set k at dsum + dsum_off[k] holds L2 + 1 run
     // offsets, then the columns (atom-relative, channel 0) summed into each

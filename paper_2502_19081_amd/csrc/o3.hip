@@ -48,6 +48,7 @@ typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
 typedef __bf16 bf4v __attribute__((ext_vector_type(4)));
 typedef float f2v __attribute__((ext_vector_type(2)));
 typedef __bf16 bf2v __attribute__((ext_vector_type(2)));
+typedef int i4v __attribute__((ext_vector_type(4)));
 
 struct O3Args {
     const int *e;         // entries: (packed A-row offsets, coefficient bits) pairs
@@ -753,15 +754,21 @@ size_t o3v_lds_bytes(const Ctx &c)
 //                zeroed: an atom's accumulator then receives the same
 //                nonzero terms in the same order as in a one-species tile
 //                (adding exact zeros changes no bits).
+//                BF16 (QM = 1): the pass's K values kk = (a - a0) nchp + b
+//                in 16x16x32 steps, lane (atom m, q) packing P_m at kk =
+//                32 st + 8 q .. + 7 (zero past the pass) rounded to nearest
+//                even, against BF16 fragments of W prepared by the host.
 struct O3WArgs {
     const int *e;       // entries (A-row offsets 16 NT channels apart, coefficient bits)
     const int *mt;      // (first entry, groups of four) per (block, m3)
     const int *base;    // first (block, m3) row of each block
     const float *w;     // [species][block][a][ct][64 lanes][NJ padded to 4]
+    const int *wb;      // BF16: [species][block][pass][ct][step][64 lanes][4 ints = 8 values]
     const int *order;   // work items per split, as the single-species form
     const int *wbeg;
     const int *dp_off;  // per-block offset in the partial buffer
     int n_pb, nch, L2, KAt, dp_stride, max_split, ns;
+    int np, nstm;       // BF16: passes of eight channels a, steps per pass at most
 };
 
 constexpr int kO3wAH = 8;  // channels a per dense pass of the wide form
@@ -793,7 +800,7 @@ __device__ __forceinline__ void o3w_sparse(const float *__restrict__ At, int L2,
     }
 }
 
-template <int NC>  // channels rounded up to a multiple of four (<= 32)
+template <int QM, int NC>  // QM 0 FP32, 1 BF16 dense stage; NC channels rounded up to 4 (<= 32)
 __global__ void __launch_bounds__(256, 1)
     k_ace_o3w(const int *__restrict__ hdr, const int32_t *__restrict__ species,
               const int *__restrict__ S_idx, O3WArgs a, const float *__restrict__ A,
@@ -902,6 +909,40 @@ __global__ void __launch_bounds__(256, 1)
                             }
                         }
                         wave_sync_lds();
+                        if constexpr (QM == 1) {
+                            const int pa = a0 / kO3wAH;
+                            const int kp = min(kO3wAH, NC - a0) * NC;  // K values of the pass
+                            const float *prow = reinterpret_cast<const float *>(Pw + (size_t)m * ROWB);
+                            for (int z = 0; z < a.ns; ++z) {
+                                if (!((zmask >> z) & 1u))
+                                    continue;  // uniform
+                                const bool mine = zrow == z;
+                                const int *wsrc = a.wb + ((((size_t)z * a.n_pb + p) * a.np + pa) * NT) *
+                                                             a.nstm * 64 * 4;
+#pragma unroll
+                                for (int st = 0; st < NC / 4; ++st) {
+                                    if (32 * st >= kp)
+                                        break;  // uniform
+                                    const int k0 = 32 * st + 8 * q;
+                                    float x[8];
+#pragma unroll
+                                    for (int u = 0; u < 8; ++u)
+                                        x[u] = (mine && k0 + u < kp) ? prow[k0 + u] : 0.0f;
+                                    const bf2v p0 = __builtin_convertvector((f2v){x[0], x[1]}, bf2v);
+                                    const bf2v p1 = __builtin_convertvector((f2v){x[2], x[3]}, bf2v);
+                                    const bf2v p2 = __builtin_convertvector((f2v){x[4], x[5]}, bf2v);
+                                    const bf2v p3 = __builtin_convertvector((f2v){x[6], x[7]}, bf2v);
+                                    const bf8v pv = {p0[0], p0[1], p1[0], p1[1], p2[0], p2[1], p3[0], p3[1]};
+#pragma unroll
+                                    for (int ct = 0; ct < NT; ++ct) {
+                                        const i4v wi = *reinterpret_cast<const i4v *>(
+                                            wsrc + (((size_t)ct * a.nstm + st) * 64 + lane) * 4);
+                                        acc[ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                            pv, __builtin_bit_cast(bf8v, wi), acc[ct], 0, 0, 0);
+                                    }
+                                }
+                            }
+                        } else
                         for (int z = 0; z < a.ns; ++z) {
                             if (!((zmask >> z) & 1u))
                                 continue;  // uniform
@@ -970,8 +1011,9 @@ hipError_t o3w_prepare(const Ctx &c)
     const int lds = (int)o3w_lds_bytes(c);
     auto set = [&](auto nc) {
         constexpr int NC = decltype(nc)::value;
-        return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_ace_o3w<NC>),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        const void *f = c.qmode == 1 ? reinterpret_cast<const void *>(&k_ace_o3w<1, NC>)
+                                     : reinterpret_cast<const void *>(&k_ace_o3w<0, NC>);
+        return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     };
     switch (c.m.nchp) {
     case 4: return set(std::integral_constant<int, 4>());
@@ -995,6 +1037,9 @@ void launch_ace_o3w(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L,
     a.mt = reinterpret_cast<const int *>(base + m.o3mt);
     a.base = reinterpret_cast<const int *>(base + m.o3base);
     a.w = reinterpret_cast<const float *>(base + m.o3ww);
+    a.wb = reinterpret_cast<const int *>(base + m.o3wwb);
+    a.np = (m.nchp + 7) / 8;
+    a.nstm = m.nchp / 4;
     a.order = reinterpret_cast<const int *>(base + m.o3order);
     a.wbeg = reinterpret_cast<const int *>(base + m.o3wbeg);
     a.dp_off = reinterpret_cast<const int *>(base + m.dpoff);
@@ -1015,11 +1060,12 @@ void launch_ace_o3w(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L,
     float *D = at<float>(ws, L.dpart);
     auto go = [&](auto nc) {
         constexpr int NC = decltype(nc)::value;
+        auto kern = c.qmode == 1 ? k_ace_o3w<1, NC> : k_ace_o3w<0, NC>;
         if (ev0)
-            hipExtLaunchKernelGGL(k_ace_o3w<NC>, dim3(grid), dim3(256), (uint32_t)lds, s, ev0, ev1,
-                                  0u, hdr, species, S_idx, a, A, D);
+            hipExtLaunchKernelGGL(kern, dim3(grid), dim3(256), (uint32_t)lds, s, ev0, ev1, 0u, hdr,
+                                  species, S_idx, a, A, D);
         else
-            k_ace_o3w<NC><<<grid, 256, lds, s>>>(hdr, species, S_idx, a, A, D);
+            kern<<<grid, 256, lds, s>>>(hdr, species, S_idx, a, A, D);
     };
     switch (m.nchp) {
     case 4: go(std::integral_constant<int, 4>()); break;

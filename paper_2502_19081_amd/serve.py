@@ -580,10 +580,12 @@ def main(argv=None):
                     help="the per-replica server (each replica's step on its own stream, "
                          "ticks in lockstep) instead of the batched one")
     ap.add_argument("--slots", type=int, default=16, help="slots of the per-replica server")
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16"],
+                    help="operand format of the order-3 contraction (FP32 elsewhere)")
     ap.add_argument("--out", default="")
     args = ap.parse_args(argv)
     from gen import workloads as W
-    model = core.Model(W.c4_model(), precision="fp32")
+    model = core.Model(W.c4_model(), precision=args.precision)
     rate = args.rate
     calib = None
     if args.load > 0:
@@ -611,7 +613,8 @@ def main(argv=None):
     rep = srv.report(wall)
     sizes = np.array([r.n for r in reps])
     rep.update({"workload": "W(001)+He impact replicas, log-uniform 2,000-20,000 atoms, "
-                            "dt 0.2 fs, 8 A sphere following He, two-species FP32 potentials",
+                            "dt 0.2 fs, 8 A sphere following He, two-species potentials",
+                "precision": args.precision,
                 "server": "per-replica streams" if args.per_replica_streams else "batched",
                 "graph": not args.eager,
                 "steps_per_replica": args.steps, "arrival_rate_hz": rate, "load": args.load,
