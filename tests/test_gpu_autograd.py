@@ -75,6 +75,35 @@ def test_adjoint_matches_oracle_weighted_gradient(precision, tol):
                                atol=1e-9 if precision == "fp64" else 1e-3)
 
 
+def test_adjoint_large_system_kernels_fp32():
+    # above 65,536 atoms the forward keeps the finalisation kernel and the
+    # backward runs the vector pair adjoint with two S atoms per wave
+    # (lmax 5, 16 channels, 4 vacancy spheres in a 34^3-cell bcc crystal)
+    import torch
+    from paper_2502_19081_amd.autograd import expensive_energy
+    w = W.c5(n=34, n_vac=4)
+    n = len(w["pos"])
+    assert n > 65536
+    print(f"case weighted adjoint n={n} fp32 (large-system kernels)", flush=True)
+    _, sy, pos, sp = _system(w, "fp32")
+    rng = np.random.default_rng(6)
+    wts = rng.normal(size=n)
+    p = pos.clone().requires_grad_(True)
+    e = expensive_energy(p, sy, sp, w["r_buffer"])
+    (e * torch.from_numpy(wts).cuda()).sum().backward()
+    g = p.grad.detach().cpu().numpy().T
+    target = np.zeros(n, bool)
+    target[:8] = True  # lists, lambda and S are global; few cheap forces needed
+    ref = O.mixed(w, target=target)
+    in_S = (ref["flags"] & 5) != 0
+    _, f_w = O.ace(w["model"], w["pos"], w["species"], w["L"], w["periodic"], ref["offs"], ref["nbr"],
+                   in_S=in_S, weights=wts)
+    err = np.abs(g - (-f_w)).max()
+    print(f"  |S| = {int(in_S.sum())}, max |dG| = {err:.3e} (scale {np.abs(f_w).max():.3f})",
+          flush=True)
+    assert err < 1e-4
+
+
 def test_backward_refuses_stale_forward():
     import torch
     from paper_2502_19081_amd.autograd import expensive_energy
