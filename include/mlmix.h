@@ -358,10 +358,11 @@ int mlmix_energy_reduce(mlmix_ctx *ctx, void *stream, void *ws, int32_t n_atoms,
  * regions. Every kernel takes its atom's box, cell grid and regions from the
  * table, neighbour rows never cross systems, and each system's results are
  * the same bits alone and in any batch (launch shapes that change the
- * rounding do not depend on the batch's size or composition). Systems share
- * the neighbour-list rebuild decision (an atom of any system moving more
- * than skin/2 rebuilds every list), dt, r_buffer and the mode; seeded
- * regions and MLMIX_ENERGY_ONLY are not available. */
+ * rounding do not depend on the batch's size or composition). Each system
+ * keeps or rebuilds its own neighbour list (its list is rebuilt when one of
+ * its atoms moved more than skin/2 since its last build, or on a forced
+ * rebuild, which applies to all); the systems share dt, r_buffer and the
+ * mode; seeded regions and MLMIX_ENERGY_ONLY are not available. */
 typedef struct {
     int32_t offset;        /* first atom of the system in the batch arrays (the
                               segments tile [0, n_atoms) in order) */
@@ -416,6 +417,21 @@ int mlmix_batch_vv_steps(mlmix_ctx *ctx, void *stream, void *ws, int32_t n_atoms
                          double *e_cheap, double *lambda, uint8_t *flags, int32_t *n_expensive,
                          double *energies);
 
+/* After mlmix_batch_init of a new batch: takes over, from the old batch
+ * workspace ws_old, the neighbour-list state of the systems the new batch
+ * keeps, so that each keeps or rebuilds its list as it would have in the old
+ * batch (its bits then do not depend on the batch being rebuilt around it).
+ * seg_map [host] int32[n_segments of ws_new]: the old segment index of each
+ * new segment, or -1 for a system new to the batch (its list is built by the
+ * next call). Rows, counts, reverse slots and reference positions are copied
+ * (row indices moved to the new offsets) with the systems' built and moved
+ * flags. Waits for `stream` (call it outside graph capture). Errors:
+ * MLMIX_E_ARG (NULL, the same workspace twice, different row capacities, a
+ * map entry out of range or used twice, a kept system whose atom count
+ * changed), MLMIX_E_STATE (a workspace not initialised as a batch). */
+int mlmix_batch_carry_lists(mlmix_ctx *ctx, void *stream, void *ws_new, const void *ws_old,
+                            const int32_t *seg_map);
+
 /* As mlmix_status for a batch workspace, and segment_bits [host]
  * int32[n_segments] (may be NULL) receives each system's own MLMIX_STATUS_*
  * bits (so that a failing replica can be evicted alone). */
@@ -432,7 +448,8 @@ int mlmix_status(mlmix_ctx *ctx, void *stream, void *ws, int32_t *status_bits,
 
 /* Waits for `stream`, then *builds [host] receives the number of neighbour-
  * list builds on the workspace since mlmix_workspace_init / mlmix_batch_init
- * (forced or triggered by the skin check). */
+ * (forced or triggered by the skin check; for a batch, the calls in which
+ * some system's list was rebuilt). */
 int mlmix_list_builds(mlmix_ctx *ctx, void *stream, void *ws, int32_t *builds);
 
 /* Test hooks (device -> device copies, enqueued on stream): the neighbour

@@ -108,6 +108,7 @@ SIGNATURES = {
     "mlmix_get_neighbors": (ctypes.c_int, [_vp, _vp, _vp, _i32, _vp, _vp]),
     "mlmix_get_index_sets": (ctypes.c_int, [_vp, _vp, _vp, _i32, _vp, _vp]),
     "mlmix_model_flops": (ctypes.c_int, [_vp, _vp]),
+    "mlmix_batch_carry_lists": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "mlmix_gaunt_table": (ctypes.c_int, [_i32, _vp]),
     "mlmix_fit_n_params": (ctypes.c_int, [_vp, ctypes.POINTER(_i32)]),
     "mlmix_fit_design": (ctypes.c_int, [_vp, _vp, _vp, _i32, _vp, _vp, ctypes.POINTER(Box), _vp,

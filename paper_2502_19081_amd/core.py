@@ -361,9 +361,11 @@ class Batch:
                     flags=self.flags, n_exp=self.n_exp, energies=self.energies)
 
     def vv_steps(self, pos, vel, mass, species, dt, n_steps, r_buffer=0.0, mode=B.MODE_MIXED,
-                 force_rebuild=True, single_stream=False, cheap_masked=False, energies=None):
+                 force_rebuild=False, single_stream=False, cheap_masked=False, energies=None):
         """n_steps velocity-Verlet steps of every system; returns the
-        (n_steps, n_systems, 3) energy sums (expensive, cheap, kinetic)."""
+        (n_steps, n_systems, 3) energy sums (expensive, cheap, kinetic).
+        Each system keeps its neighbour list until one of its own atoms
+        moved half the skin (force_rebuild: every list every step)."""
         if energies is None:
             energies = torch.zeros(n_steps, self.nseg, 3, dtype=torch.float64,
                                    device=self.device)
@@ -385,6 +387,21 @@ class Batch:
             B.check(rc)
         return [int(bits[k]) for k in range(self.nseg)], int(req.value), rc
 
+
+    def carry_lists_from(self, old, seg_map):
+        """Takes over the neighbour-list state of the systems this batch keeps
+        from the batch `old` (seg_map[k]: old index of system k, or -1)."""
+        m = (ctypes.c_int32 * max(self.nseg, 1))(*[int(v) for v in seg_map])
+        B.check(B.lib().mlmix_batch_carry_lists(self.model.handle, _stream(), _p(self.ws),
+                                                _p(old.ws), m))
+
+    def list_builds(self):
+        """Calls since the batch was set up in which some system's neighbour
+        list was rebuilt."""
+        b = ctypes.c_int32()
+        B.check(B.lib().mlmix_list_builds(self.model.handle, _stream(), _p(self.ws),
+                                          ctypes.byref(b)))
+        return int(b.value)
     def slice(self, k):
         """Atom range of system k in the batch arrays."""
         return slice(self.offsets[k], self.offsets[k] + self.sizes[k])

@@ -1170,6 +1170,8 @@ static void layout_arrays(const Ctx &c, WsLayout &L, size_t ncell, size_t nrec, 
         take(L.seg_of, nn * sizeof(int));
         take(L.segs, (size_t)nseg * sizeof(SegGeo));
         take(L.seg_status, (size_t)nseg * sizeof(int));
+        take(L.seg_flag, (size_t)nseg * 4 * sizeof(int));
+        take(L.seg_map, (size_t)nseg * sizeof(int));
         take(L.seg_red, nn * sizeof(double));  // per-atom kinetic energy of the step
     }
     L.total = off;
@@ -2151,6 +2153,7 @@ try {
     k_zero_i32<<<1, H_COUNT, 0, s>>>(at<int>(ws, L.hdr), H_COUNT);
     k_zero_i32<<<(L.grid.ncell + 255) / 256, 256, 0, s>>>(at<int>(ws, L.cell_count), L.grid.ncell);
     k_zero_i32<<<(L.nseg + 255) / 256, 256, 0, s>>>(at<int>(ws, L.seg_status), L.nseg);
+    k_zero_i32<<<(4 * L.nseg + 255) / 256, 256, 0, s>>>(at<int>(ws, L.seg_flag), 4 * L.nseg);
     HIP_OK(hipGetLastError());
     // the segment table (the host copy is released when this call returns)
     HIP_OK(hipMemcpyAsync(at<SegGeo>(ws, L.segs), geo.data(), geo.size() * sizeof(SegGeo),
@@ -2185,6 +2188,52 @@ static int batch_lookup(mlmix_ctx *ctx, void *ws, int32_t n_atoms, int32_t n_reg
         if ((long long)q.region_offset + q.n_regions > (long long)n_regions)
             return fail(MLMIX_E_ARG, "a segment's regions reach past n_regions");
     return MLMIX_OK;
+}
+
+extern "C" int mlmix_batch_carry_lists(mlmix_ctx *ctx, void *stream, void *ws_new,
+                                       const void *ws_old, const int32_t *seg_map)
+try {
+    if (!ctx || !ws_new || !ws_old || !seg_map)
+        return fail(MLMIX_E_ARG, "NULL argument");
+    WsLayout Ln, Lo;
+    std::vector<mlmix_segment> sn, so;
+    {
+        std::lock_guard<std::mutex> g(ctx->mu);
+        auto in = ctx->ws.find(ws_new), io = ctx->ws.find(const_cast<void *>(ws_old));
+        auto bn = ctx->batch.find(ws_new), bo = ctx->batch.find(const_cast<void *>(ws_old));
+        if (in == ctx->ws.end() || io == ctx->ws.end() || bn == ctx->batch.end() ||
+            bo == ctx->batch.end() || in->second.nseg == 0 || io->second.nseg == 0)
+            return fail(MLMIX_E_STATE, "both workspaces must be initialised with mlmix_batch_init");
+        Ln = in->second;
+        Lo = io->second;
+        sn = bn->second;
+        so = bo->second;
+    }
+    if (ws_new == ws_old)
+        return fail(MLMIX_E_ARG, "the two workspaces must differ");
+    if (Ln.cap != Lo.cap)
+        return fail(MLMIX_E_ARG, "the two workspaces have different row capacities");
+    std::vector<int> used(so.size(), 0);
+    for (size_t k = 0; k < sn.size(); ++k) {
+        const int ko = seg_map[k];
+        if (ko < -1 || ko >= (int)so.size())
+            return fail(MLMIX_E_ARG, "seg_map entry out of range");
+        if (ko < 0)
+            continue;
+        if (used[ko]++)
+            return fail(MLMIX_E_ARG, "an old segment mapped twice");
+        if (so[ko].n_atoms != sn[k].n_atoms)
+            return fail(MLMIX_E_ARG, "a kept system changed its atom count");
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIP_OK(hipMemcpyAsync(at<int>(ws_new, Ln.seg_map), seg_map, sn.size() * sizeof(int),
+                          hipMemcpyHostToDevice, s));
+    launch_carry_lists(s, ws_new, Ln, ws_old, Lo);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipStreamSynchronize(s));  // the host map is the caller's
+    return MLMIX_OK;
+} catch (...) {
+    return host_exception();
 }
 
 static int check_batch_mode(uint32_t mode)

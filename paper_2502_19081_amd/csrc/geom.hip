@@ -118,8 +118,11 @@ __global__ void __launch_bounds__(256) k_displacement(const double *__restrict__
         }
         d2 = d2 + d * d;
     }
-    if (!(d2 <= thr2))
+    if (!(d2 <= thr2)) {
         hdr[H_MOVED] = 1;
+        if constexpr (SEG)
+            sg.flag[4 * sg.of[i] + kSegMoved] = 1;
+    }
 }
 
 // ------------------------------------------------ lambda, cell lists
@@ -357,11 +360,24 @@ __global__ void __launch_bounds__(256) k_bin_bucket(const double *__restrict__ p
     }
     if (i < n)
         atom_lambda<SEG>(pos, n, b, i, ra, hdr, sg);
-    const int rebuild = (force || hdr[H_BUILT] == 0 || hdr[H_MOVED] != 0) ? 1 : 0;
+    int rebuild = (force || hdr[H_BUILT] == 0 || hdr[H_MOVED] != 0) ? 1 : 0;
     if (blockIdx.x == 0 && threadIdx.x == 0)
-        hdr[H_REBUILD] = rebuild;
+        hdr[H_REBUILD] = rebuild;  // some list is rebuilt (in a batch: some system's)
+    if constexpr (SEG) {
+        // a batch: every system keeps or rebuilds its own list, so that its
+        // bits do not depend on the systems beside it; the system's first
+        // atom publishes the decision for the row and reverse-slot kernels
+        rebuild = 0;
+        if (i < n) {
+            const int k = sg.of[i];
+            const int *f = sg.flag + 4 * k;
+            rebuild = (force || f[kSegBuilt] == 0 || f[kSegMoved] != 0) ? 1 : 0;
+            if (i == sg.geo[k].off)
+                sg.flag[4 * k + kSegRebuild] = rebuild;
+        }
+    }
     if (!rebuild)
-        return;  // uniform
+        return;  // uniform for a single system
     if (i >= n)
         return;
     double x[3];
@@ -480,7 +496,7 @@ __global__ void __launch_bounds__(256) k_neighbors(const double *__restrict__ po
                                                    const uint8_t *__restrict__ cand, Seg sg)
 {
 #pragma clang fp contract(off)
-    const int rebuild = hdr[H_REBUILD];
+    int rebuild = hdr[H_REBUILD];
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         hdr[H_MOVED] = 0;  // for the next call's displacement check
         if (rebuild) {
@@ -491,6 +507,20 @@ __global__ void __launch_bounds__(256) k_neighbors(const double *__restrict__ po
     const int w = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     const int i = blockIdx.x * 4 + w;
+    if constexpr (SEG) {
+        // the decision of the atom's own system (published by the binning
+        // kernel); the wave of its first atom clears the system's moved flag
+        // and marks its list built
+        if (i < n) {
+            const int k = __builtin_amdgcn_readfirstlane(sg.of[i]);
+            rebuild = sg.flag[4 * k + kSegRebuild];
+            if (i == sg.geo[k].off && lane == 0) {
+                sg.flag[4 * k + kSegMoved] = 0;
+                if (rebuild)
+                    sg.flag[4 * k + kSegBuilt] = 1;
+            }
+        }
+    }
     if (rebuild == 0) {
         // kept list: this call's buffer test over the kept row (the same
         // test as the rebuild path below): a candidate joins the buffer when
@@ -686,7 +716,8 @@ template <int U>
 __global__ void __launch_bounds__(256) k_reverse(int n, int cap, int P, const int *__restrict__ nbr,
                                                  const int *__restrict__ cnt,
                                                  int *__restrict__ rev, int *__restrict__ count,
-                                                 int ncell, int *hdr)
+                                                 int ncell, int *hdr, const int *__restrict__ seg_of,
+                                                 const int *__restrict__ seg_flag)
 {
     if (hdr[H_REBUILD] == 0)
         return;
@@ -695,6 +726,8 @@ __global__ void __launch_bounds__(256) k_reverse(int n, int cap, int P, const in
         count[c] = 0;
     const int lane = threadIdx.x & 63;
     for (int i = blockIdx.x * 4 + (threadIdx.x >> 6); i < n; i += gridDim.x * 4) {
+        if (seg_of && seg_flag[4 * seg_of[i] + kSegRebuild] == 0)
+            continue;  // a batch system that kept its list keeps its slots (uniform)
         const int ci = cnt[i];
         const int *rowi = nbr + (size_t)i * cap;
         int j[U], cj[U], pos[U];
@@ -742,7 +775,10 @@ __global__ void __launch_bounds__(256) k_reverse(int n, int cap, int P, const in
 DispCheck disp_check_args(void *ws, const WsLayout &L, double skin)
 {
     const double thr = 0.5 * skin;
-    return DispCheck{at<double>(ws, L.ref_pos), thr * thr, at<int>(ws, L.hdr)};
+    if (L.nseg > 0)
+        return DispCheck{at<double>(ws, L.ref_pos), thr * thr, at<int>(ws, L.hdr),
+                         at<int>(ws, L.seg_of), at<int>(ws, L.seg_flag)};
+    return DispCheck{at<double>(ws, L.ref_pos), thr * thr, at<int>(ws, L.hdr), nullptr, nullptr};
 }
 
 void launch_neighbors(hipStream_t s, void *ws, const WsLayout &L, const Box &b, double r_list,
@@ -809,7 +845,9 @@ constexpr unsigned kRevFlatBlocks = 16384;
 __global__ void __launch_bounds__(256) k_reverse_flat(int n, int cap, const int *__restrict__ nbr,
                                                       const int *__restrict__ cnt,
                                                       int *__restrict__ rev,
-                                                      int *__restrict__ count, int ncell, int *hdr)
+                                                      int *__restrict__ count, int ncell, int *hdr,
+                                                      const int *__restrict__ seg_of,
+                                                      const int *__restrict__ seg_flag)
 {
     if (hdr[H_REBUILD] == 0)
         return;
@@ -823,6 +861,8 @@ __global__ void __launch_bounds__(256) k_reverse_flat(int n, int cap, const int 
             continue;
         // 32-bit division whenever the index fits (64-bit division is slow)
         const int i = t < 0xffffffffull ? (int)((unsigned)t / (unsigned)cap) : (int)(t / cap);
+        if (seg_of && seg_flag[4 * seg_of[i] + kSegRebuild] == 0)
+            continue;  // a batch system that kept its list keeps its slots
         const int sl = (int)(t - (size_t)i * cap);
         int r = -1;
         if (sl < cnt[i]) {
@@ -851,13 +891,14 @@ void launch_reverse(hipStream_t s, void *ws, const WsLayout &L, int side_blocks)
     const int n = L.n;
     if (n == 0)
         return;
+    const Seg sg = seg_args(ws, L);  // batch: per-system decisions
     // uncapped: one thread per slot (measured faster on 1M atoms); capped
     // beside the expensive chain: a wave per atom, grid-stride
     const size_t tot = std::max((size_t)n * L.cap, (size_t)L.grid.ncell);
     if (side_blocks <= 0 || (tot + 255) / 256 <= (size_t)side_blocks) {
         k_reverse_flat<<<(unsigned)std::min<size_t>((tot + 255) / 256, kRevFlatBlocks), 256, 0, s>>>(
             n, L.cap, at<int>(ws, L.nbr), at<int>(ws, L.cnt), at<int>(ws, L.rev),
-            at<int>(ws, L.cell_count), L.grid.ncell, at<int>(ws, L.hdr));
+            at<int>(ws, L.cell_count), L.grid.ncell, at<int>(ws, L.hdr), sg.of, sg.flag);
         return;
     }
     unsigned nblk = (unsigned)((n + 3) / 4);
@@ -866,7 +907,7 @@ void launch_reverse(hipStream_t s, void *ws, const WsLayout &L, int side_blocks)
 #define MLMIX_REV(U)                                                                              \
     k_reverse<U><<<nblk, 256, 0, s>>>(n, L.cap, L.P, at<int>(ws, L.nbr), at<int>(ws, L.cnt),       \
                                       at<int>(ws, L.rev), at<int>(ws, L.cell_count), L.grid.ncell, \
-                                      at<int>(ws, L.hdr))
+                                      at<int>(ws, L.hdr), sg.of, sg.flag)
     switch ((L.cap + 63) / 64) {
     case 1: MLMIX_REV(1); break;
     case 2: MLMIX_REV(2); break;

@@ -77,7 +77,12 @@ struct Seg {
     const int *of;
     const SegGeo *geo;
     int *status;
+    // per-segment list state [nseg][4]: 0 an atom moved more than half the
+    // skin since the segment's last build, 1 built, 2 rebuild in this call:
+    // every system of a batch keeps or rebuilds its list by its own atoms
+    int *flag;
 };
+constexpr int kSegMoved = 0, kSegBuilt = 1, kSegRebuild = 2;
 
 // Kernels that need an atom's box or grid take a template flag SEG: false
 // for a single system (no segment code at all, the box stays a kernel
@@ -117,7 +122,7 @@ struct WsLayout {
     size_t hdr, cell_count, cell_atoms, scan_part, seedcore;
     size_t nbr, cnt, rev, ref_pos, S_idx, M_idx, S_local, cand;
     size_t A, dEdA, g, h, red, dpart;
-    size_t seg_of, segs, seg_status, seg_red;  // batch workspaces only
+    size_t seg_of, segs, seg_status, seg_red, seg_flag, seg_map;  // batch workspaces only
     // region lists per superblock of the box (single systems): rgn[k]
     // superblocks along dimension k, each (count or -1, kRegionGridCap ids)
     size_t rgrid;
@@ -131,8 +136,9 @@ inline T *at(void *ws, size_t off) { return reinterpret_cast<T *>(static_cast<ch
 inline Seg seg_args(void *ws, const WsLayout &L)
 {
     if (L.nseg == 0)
-        return Seg{nullptr, nullptr, nullptr};
-    return Seg{at<int>(ws, L.seg_of), at<SegGeo>(ws, L.segs), at<int>(ws, L.seg_status)};
+        return Seg{nullptr, nullptr, nullptr, nullptr};
+    return Seg{at<int>(ws, L.seg_of), at<SegGeo>(ws, L.segs), at<int>(ws, L.seg_status),
+               at<int>(ws, L.seg_flag)};
 }
 
 // Model tables on the device, in the arithmetic type of the context.
@@ -326,6 +332,8 @@ struct DispCheck {
     const double *ref;  // positions at the last build (SoA)
     double thr2;        // (skin / 2)^2
     int *hdr;
+    const int *seg_of;  // batch: the atom's segment, whose moved flag is raised too
+    int *seg_flag;
 };
 
 template <bool SEG>
@@ -342,8 +350,11 @@ __device__ __forceinline__ void disp_check(const DispCheck &dc, const double x[3
         }
         d2 = d2 + d * d;
     }
-    if (!(d2 <= dc.thr2))
+    if (!(d2 <= dc.thr2)) {
         dc.hdr[H_MOVED] = 1;
+        if constexpr (SEG)
+            dc.seg_flag[4 * dc.seg_of[i] + kSegMoved] = 1;
+    }
 }
 
 DispCheck disp_check_args(void *ws, const WsLayout &L, double skin);
@@ -393,6 +404,12 @@ void launch_vv_kick_drift(hipStream_t s, void *ws, const WsLayout &L, const Box 
                           int drift, const DispCheck *chk = nullptr);
 void launch_copy_i32(hipStream_t s, int32_t *dst, const int32_t *src, size_t n);
 void launch_seg_fill(hipStream_t s, void *ws, const WsLayout &L);
+// Neighbour-list state of the systems a new batch keeps from an old one
+// (rows with their atom indices moved to the new offsets, counts, reverse
+// slots, reference positions, per-system built and moved flags); seg_map of
+// the new workspace holds each new segment's old index or -1.
+void launch_carry_lists(hipStream_t s, void *ws_new, const WsLayout &Ln, const void *ws_old,
+                        const WsLayout &Lo);
 void launch_seg_sums(hipStream_t s, void *ws, const WsLayout &L, const double *e_exp,
                      const double *e_cheap, const double *ke, const uint8_t *flags, double *out,
                      int32_t *counts);

@@ -409,7 +409,7 @@ void launch_vv_kick_drift(hipStream_t s, void *ws, const WsLayout &L, const Box 
 {
     if (L.n == 0)
         return;
-    const DispCheck dc = chk ? *chk : DispCheck{nullptr, 0.0, nullptr};
+    const DispCheck dc = chk ? *chk : DispCheck{nullptr, 0.0, nullptr, nullptr, nullptr};
     (L.nseg > 0 ? k_vv<true> : k_vv<false>)<<<(L.n + 255) / 256, 256, 0, s>>>(
         L.n, b, pos, vel, mass, forces, dt, drift, seg_args(ws, L), dc);
 }
@@ -429,6 +429,55 @@ void launch_seg_fill(hipStream_t s, void *ws, const WsLayout &L)
 {
     if (L.nseg > 0)
         k_seg_fill<<<L.nseg, 256, 0, s>>>(at<SegGeo>(ws, L.segs), at<int>(ws, L.seg_of));
+}
+
+// List state of the systems a new batch keeps from an old one: one
+// workgroup per new segment, skipped for a segment new to the batch. A kept
+// system's rows hold its atoms' batch indices, which move by the difference
+// of its offsets; padding (-1) stays.
+__global__ void __launch_bounds__(256) k_carry_lists(
+    const SegGeo *__restrict__ geo_n, const int *__restrict__ map, int n_new, int cap,
+    int *__restrict__ nbr_n, int *__restrict__ cnt_n, int *__restrict__ rev_n,
+    double *__restrict__ ref_n, int *__restrict__ flag_n, const SegGeo *__restrict__ geo_o,
+    int n_old, const int *__restrict__ nbr_o, const int *__restrict__ cnt_o,
+    const int *__restrict__ rev_o, const double *__restrict__ ref_o,
+    const int *__restrict__ flag_o)
+{
+    const int k = blockIdx.x;
+    const int ko = map[k];
+    if (ko < 0)
+        return;  // uniform: a system new to the batch builds its list
+    const SegGeo Gn = geo_n[k], Go = geo_o[ko];
+    const int shift = Gn.off - Go.off;
+    const size_t rows = (size_t)Gn.n * cap;
+    for (size_t t = threadIdx.x; t < rows; t += blockDim.x) {
+        const int v = nbr_o[(size_t)Go.off * cap + t];
+        nbr_n[(size_t)Gn.off * cap + t] = v >= 0 ? v + shift : v;
+        rev_n[(size_t)Gn.off * cap + t] = rev_o[(size_t)Go.off * cap + t];
+    }
+    for (int t = threadIdx.x; t < Gn.n; t += blockDim.x) {
+        cnt_n[Gn.off + t] = cnt_o[Go.off + t];
+        for (int q = 0; q < 3; ++q)
+            ref_n[(size_t)q * n_new + Gn.off + t] = ref_o[(size_t)q * n_old + Go.off + t];
+    }
+    if (threadIdx.x == 0) {
+        flag_n[4 * k + kSegMoved] = flag_o[4 * ko + kSegMoved];
+        flag_n[4 * k + kSegBuilt] = flag_o[4 * ko + kSegBuilt];
+    }
+}
+
+void launch_carry_lists(hipStream_t s, void *ws_new, const WsLayout &Ln, const void *ws_old,
+                        const WsLayout &Lo)
+{
+    if (Ln.nseg == 0)
+        return;
+    void *wo = const_cast<void *>(ws_old);
+    k_carry_lists<<<Ln.nseg, 256, 0, s>>>(
+        at<SegGeo>(ws_new, Ln.segs), at<int>(ws_new, Ln.seg_map), Ln.n, Ln.cap,
+        at<int>(ws_new, Ln.nbr), at<int>(ws_new, Ln.cnt), at<int>(ws_new, Ln.rev),
+        at<double>(ws_new, Ln.ref_pos), at<int>(ws_new, Ln.seg_flag), at<SegGeo>(wo, Lo.segs), Lo.n,
+        at<int>(wo, Lo.nbr), at<int>(wo, Lo.cnt), at<int>(wo, Lo.rev), at<double>(wo, Lo.ref_pos),
+        at<int>(wo, Lo.seg_flag));
 }
 
 // Energy sums and set sizes of every system of a batch: one workgroup per

@@ -350,6 +350,7 @@ class BatchServer:
         dev = self.device
         keep = [r for r in self.active if r not in leaving]
         old = self.batch
+        old_index = {id(r): self.active.index(r) for r in keep}
         parts = {"pos": [], "vel": [], "mass": [], "species": []}
         with torch.cuda.stream(self.stream):
             for r in keep:
@@ -378,10 +379,14 @@ class BatchServer:
                        for r in self.active]
             s_cap = sum(min(self.s_cap_per_replica, r.n) for r in self.active)
             self.batch = core.Batch(self.model, systems, cap=self.cap, s_cap=s_cap, device=dev)
+            # the kept replicas keep their neighbour lists (each list is kept
+            # or rebuilt by its own replica's atoms, as it would be alone)
+            if old is not None and keep:
+                self.batch.carry_lists_from(old, [old_index.get(id(r), -1) for r in self.active])
             # forces of the current state (the step needs F(x) on entry; a
             # replica's forces are the same bits in any batch)
             self.batch.compute(self.pos, self.species, r_buffer=self.r_buffer,
-                               mode=B.MODE_MIXED, force_rebuild=True)
+                               mode=B.MODE_MIXED)
             self.energies = torch.zeros(1, len(self.active), 3, dtype=torch.float64, device=dev)
             if self.use_graph:
                 g = torch.cuda.CUDAGraph()
@@ -394,8 +399,10 @@ class BatchServer:
         self._need_start = True
 
     def _step(self):
+        # every system keeps its neighbour list until one of its own atoms
+        # moved half the skin (its bits do not depend on its batch-mates)
         self.batch.vv_steps(self.pos, self.vel, self.mass, self.species, self.active[0].dt, 1,
-                            r_buffer=self.r_buffer, mode=self.active[0].mode, force_rebuild=True,
+                            r_buffer=self.r_buffer, mode=self.active[0].mode,
                             energies=self.energies)
 
     def _retire(self, r, k, now):

@@ -109,7 +109,8 @@ def test_batch_trajectory_equals_single_system_path():
     systems, pos, sp, vel, mass = _batch_inputs(ws, model)
     bt = core.Batch(model, systems, cap=128)
     bt.compute(pos, sp, r_buffer=5.0, force_rebuild=True)
-    E = bt.vv_steps(pos, vel, mass, sp, 0.2, steps, r_buffer=5.0).cpu().numpy()
+    E = bt.vv_steps(pos, vel, mass, sp, 0.2, steps, r_buffer=5.0,
+                    force_rebuild=True).cpu().numpy()
     bt.status()
     for k, w in enumerate(ws):
         _, sy, p1, s1 = core.system_for(w, model=model, cap=128)
@@ -154,6 +155,46 @@ def test_batch_alone_equals_in_other_batches():
     for name in ("mix_a", "mix_b"):
         for key in res["alone"]:
             assert np.array_equal(res["alone"][key], res[name][key]), (name, key)
+
+
+def test_batch_systems_keep_their_own_lists():
+    # a replica whose He atom moves fast beside a 600 K cube with a few He
+    # atoms: the two rebuild their lists at different steps; every system
+    # keeps or rebuilds by its own atoms, so each trajectory equals, bit for
+    # bit, the single-system path with kept lists
+    import torch
+    from paper_2502_19081_amd import core
+    ws = [W.c4_replica(3, n_target=2000), _periodic_cube(W.c4_model())]
+    steps, dt = 40, 0.5
+    print(f"case batch kept lists per system, {steps} steps at {dt} fs", flush=True)
+    model = core.Model(ws[0]["model"], precision="fp32")
+    systems, pos, sp, vel, mass = _batch_inputs(ws, model)
+    bt = core.Batch(model, systems, cap=128)
+    bt.compute(pos, sp, r_buffer=5.0, force_rebuild=True)
+    bt.vv_steps(pos, vel, mass, sp, dt, steps, r_buffer=5.0, force_rebuild=False)
+    bt.status()
+    builds_batch = bt.list_builds()
+    builds = []
+    for k, w in enumerate(ws):
+        _, sy, p1, s1 = core.system_for(w, model=model, cap=128)
+        v1 = torch.from_numpy(np.ascontiguousarray(w["vel"].T)).cuda()
+        m1 = torch.from_numpy(w["masses"][w["species"]].astype(np.float64)).cuda()
+        sy.compute(p1, s1, r_buffer=5.0, force_rebuild=True)
+        sy.vv_steps(p1, v1, m1, s1, dt, steps, r_buffer=5.0, force_rebuild=False)
+        sy.status()
+        builds.append(sy.list_builds())
+        sl = bt.slice(k)
+        assert np.array_equal(pos[:, sl].cpu().numpy(), p1.cpu().numpy()), k
+        assert np.array_equal(vel[:, sl].cpu().numpy(), v1.cpu().numpy()), k
+        assert np.array_equal(bt.forces[:, sl].cpu().numpy(), sy.forces.cpu().numpy()), k
+    print(f"  list builds: batch {builds_batch}, replica alone {builds[0]}, cube alone {builds[1]}",
+          flush=True)
+    # the batch rebuilt some system's list in calls where another system
+    # kept its own (so the per-system decisions were exercised), and no more
+    # often than one of them or the other did
+    assert builds[0] > 1 and builds[1] > 1
+    assert max(builds) <= builds_batch <= builds[0] + builds[1] - 1
+    assert min(builds) < builds_batch
 
 
 def test_batch_fp64_energy_sums_against_oracle():
