@@ -50,6 +50,20 @@ __device__ __forceinline__ double fast_sqrt(double x) { return sqrt(x); }
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double fast_rcp(double x) { return 1.0 / x; }
 
+// Length of a pair and its inverse from the FP64 squared length (whose
+// cutoff tests stay in FP64): the hardware instructions on the FP32 value in
+// FP32, the correctly rounded FP64 ones in FP64.
+__device__ __forceinline__ void pair_len(double r2, float &r, float &ir)
+{
+    r = __builtin_amdgcn_sqrtf((float)r2);
+    ir = __builtin_amdgcn_rcpf(r);
+}
+__device__ __forceinline__ void pair_len(double r2, double &r, double &ir)
+{
+    r = sqrt(r2);
+    ir = 1.0 / r;
+}
+
 // The four non-zero clamped uniform cubic B-splines at x and their
 // derivatives from the per-span cubic coefficients (Horner, no division):
 // span sp = clamp(floor(x / h), 0, npts - 2), t = x / h - sp, basis r of the
@@ -218,9 +232,10 @@ __global__ void __launch_bounds__(256)
             const double r2 = rr2[u];
             hx[u] = hy[u] = hz[u] = T(0);
             leg[u] = -1;
+            T r = T(1), ir = T(1);
+            if (r2 < a.rc2sq || (nb > 0 && r2 < a.rc3sq))
+                pair_len(r2, r, ir);
             if (r2 < a.rc2sq) {
-                const double rd = sqrt(r2);
-                const T r = T(rd);
                 int f;
                 T N[4], dN[4];
                 bspline4p<T>(r, a.ih2, a.nk2, pp2, f, N, dN);
@@ -232,7 +247,7 @@ __global__ void __launch_bounds__(256)
                     dV += cc[q] * dN[q];
                 }
                 Ep += T(0.5) * V;
-                const T sc = T(0.5) * dV / r;
+                const T sc = T(0.5) * dV * ir;
                 hx[u] = sc * T(dd[u][0]);
                 hy[u] = sc * T(dd[u][1]);
                 hz[u] = sc * T(dd[u][2]);
@@ -241,15 +256,14 @@ __global__ void __launch_bounds__(256)
             const unsigned long long mask = __ballot(in3);
             const int p = n3 + __popcll(mask & ((1ull << lane) - 1ull));
             if (in3 && p < kMaxTriplet) {
-                const double rd = sqrt(r2);
                 d3[p * 3 + 0] = T(dd[u][0]);
                 d3[p * 3 + 1] = T(dd[u][1]);
                 d3[p * 3 + 2] = T(dd[u][2]);
-                ir3[p] = T(1.0 / rd);
+                ir3[p] = ir;
                 leg[u] = p;
                 int f;
                 T N[4], dN[4];
-                bspline4p<T>(T(rd), a.ih3, a.nk3, pp3, f, N, dN);
+                bspline4p<T>(r, a.ih3, a.nk3, pp3, f, N, dN);
                 f3[p] = f;
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
@@ -269,99 +283,163 @@ __global__ void __launch_bounds__(256)
             const T *cz = c3x + (size_t)zi * nb * nb * (nb - 3) * 4;
             const int hh = n3 >> 1;
             const float rn3 = 1.0f / (float)(n3 > 0 ? n3 : 1);
-            const int ngrid = n3 * hh;
             const bool even = (n3 & 1) == 0;
+            // V3 of the leg pair (j, k) added to the energy; dV3/dd_ij and
+            // dV3/dd_ik returned in cj, ck
+            auto leg_pair = [&](const int j, const int k, T cj[3], T ck[3]) {
+                const T dj0 = d3[j * 3], dj1 = d3[j * 3 + 1], dj2 = d3[j * 3 + 2];
+                const T dk0 = d3[k * 3], dk1 = d3[k * 3 + 1], dk2 = d3[k * 3 + 2];
+                const int fj = f3[j], fk = f3[k];
+                T Bj[4], dBj[4], Bk[4], dBk[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    Bj[q] = B3[j * 4 + q];
+                    dBj[q] = dB3[j * 4 + q];
+                    Bk[q] = B3[k * 4 + q];
+                    dBk[q] = dB3[k * 4 + q];
+                }
+                const T e0 = dk0 - dj0, e1 = dk1 - dj1, e2 = dk2 - dj2;
+                const T rjk = fast_sqrt(e0 * e0 + e1 * e1 + e2 * e2);
+                int fs;
+                T Ns[4], dNs[4];
+                bspline4p<T>(rjk, a.ih3c, a.nk3, pp3, fs, Ns, dNs);
+                // contract the r_jk basis first, then leg k, then leg j
+                T V = T(0), V1 = T(0), V2 = T(0), V3 = T(0);
+#pragma unroll
+                for (int pa = 0; pa < 4; ++pa) {
+                    T u0 = T(0), uk = T(0), u1 = T(0);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        T cr[4];
+                        load4(cz + ((((fj + pa) * nb + (fk + q)) * (nb - 3) + fs) << 2), cr);
+                        const T s0 = ((cr[0] * Ns[0] + cr[1] * Ns[1]) + cr[2] * Ns[2]) + cr[3] * Ns[3];
+                        const T s1 = ((cr[0] * dNs[0] + cr[1] * dNs[1]) + cr[2] * dNs[2]) + cr[3] * dNs[3];
+                        u0 += s0 * Bk[q];
+                        uk += s0 * dBk[q];
+                        u1 += s1 * Bk[q];
+                    }
+                    V += Bj[pa] * u0;
+                    V1 += dBj[pa] * u0;
+                    V2 += Bj[pa] * uk;
+                    V3 += Bj[pa] * u1;
+                }
+                Ep += V;
+                const T irjk = fast_rcp(rjk);
+                const T aj = V1 * ir3[j], ak = V2 * ir3[k], ajk = V3 * irjk;
+                cj[0] = aj * dj0 - ajk * e0;
+                cj[1] = aj * dj1 - ajk * e1;
+                cj[2] = aj * dj2 - ajk * e2;
+                ck[0] = ak * dk0 + ajk * e0;
+                ck[1] = ak * dk1 + ajk * e1;
+                ck[2] = ak * dk2 + ajk * e2;
+            };
             T gx = T(0), gy = T(0), gz = T(0);  // lane x < n3: leg x
-            for (int t0 = 0; t0 < ngrid; t0 += 64) {
-                const int p = t0 + lane;
-                T cj0 = T(0), cj1 = T(0), cj2 = T(0), ck0 = T(0), ck1 = T(0), ck2 = T(0);
-                if (p < ngrid) {
-                    // o = p / n3 + 1 without an integer division (the float
-                    // quotient of p + 1/2 sits at least 1/(2 n3) from an integer)
-                    const int o = (int)(((float)p + 0.5f) * rn3) + 1;
-                    const int j = p - (o - 1) * n3;
-                    if (!(even && o == hh && j >= hh)) {
-                        int k = j + o;
-                        if (k >= n3)
-                            k -= n3;
-                        const T dj0 = d3[j * 3], dj1 = d3[j * 3 + 1], dj2 = d3[j * 3 + 2];
-                        const T dk0 = d3[k * 3], dk1 = d3[k * 3 + 1], dk2 = d3[k * 3 + 2];
-                        const T e0 = dk0 - dj0, e1 = dk1 - dj1, e2 = dk2 - dj2;
-                        const T rjk = fast_sqrt(e0 * e0 + e1 * e1 + e2 * e2);
-                        int fs;
-                        T Ns[4], dNs[4];
-                        bspline4p<T>(rjk, a.ih3c, a.nk3, pp3, fs, Ns, dNs);
-                        const int fj = f3[j], fk = f3[k];
-                        T Bj[4], dBj[4], Bk[4], dBk[4];
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) {
-                            Bj[q] = B3[j * 4 + q];
-                            dBj[q] = dB3[j * 4 + q];
-                            Bk[q] = B3[k * 4 + q];
-                            dBk[q] = dB3[k * 4 + q];
+            // Two layouts of the unordered pairs {x, x + o} (o = 1..n3/2) on
+            // the lanes, whichever takes fewer rounds of 64:
+            //  blocks: lane x + n3 s (s < S = 64 / n3) takes offsets
+            //   o = s + 1 + r S in round r; in a round the lanes of one block
+            //   have distinct second legs, so lane x + n3 s keeps the
+            //   first-leg term of its pair and receives the second-leg term
+            //   of the pair (x - o, x) of its block through one LDS slot
+            //   (no search); the S partial sums of a leg are added at the end;
+            //  cyclic: pair p = (o - 1) n3 + j on lane p mod 64 of round
+            //   p / 64; each leg lane collects its terms from the round's
+            //   slots by offset.
+            const int S = n3 > 0 ? 64 / n3 : 1;
+            const int ngrid = n3 * hh;
+            const bool blocks = n3 > 0 && (hh + S - 1) / S <= (ngrid + 63) / 64;
+            if (blocks) {
+                const int sb = (int)(((float)lane + 0.5f) * rn3);  // lane / n3
+                const int x = lane - sb * n3;
+                const bool lane_in = sb < S;
+                const int nr = (hh + S - 1) / S;
+                for (int r = 0; r < nr; ++r) {
+                    const int o = sb + 1 + r * S;
+                    // second leg (x + o) mod n3; a block past the last offset
+                    // has no pairs and maps every lane to its own slot
+                    int k = x + (o <= hh ? o : 0);
+                    if (k >= n3)
+                        k -= n3;
+                    T cj[3] = {T(0), T(0), T(0)}, ck[3] = {T(0), T(0), T(0)};
+                    if (lane_in && o <= hh && !(even && o == hh && x >= hh))
+                        leg_pair(x, k, cj, ck);
+                    if (lane_in) {
+                        gx += cj[0];
+                        gy += cj[1];
+                        gz += cj[2];
+                        rb[(k + sb * n3) * 3 + 0] = ck[0];
+                        rb[(k + sb * n3) * 3 + 1] = ck[1];
+                        rb[(k + sb * n3) * 3 + 2] = ck[2];
+                    }
+                    wave_sync_lds_u();
+                    if (lane_in) {
+                        gx += rb[lane * 3 + 0];
+                        gy += rb[lane * 3 + 1];
+                        gz += rb[lane * 3 + 2];
+                    }
+                    wave_sync_lds_u();
+                }
+                // partial sums of leg x from the blocks s = 1..S-1
+                if (lane_in) {
+                    rb[lane * 3 + 0] = gx;
+                    rb[lane * 3 + 1] = gy;
+                    rb[lane * 3 + 2] = gz;
+                }
+                wave_sync_lds_u();
+                if (lane < n3)
+                    for (int s2 = 1; s2 < S; ++s2) {
+                        gx += rb[(lane + s2 * n3) * 3 + 0];
+                        gy += rb[(lane + s2 * n3) * 3 + 1];
+                        gz += rb[(lane + s2 * n3) * 3 + 2];
+                    }
+                wave_sync_lds_u();
+            } else {
+                for (int t0 = 0; t0 < ngrid; t0 += 64) {
+                    const int p = t0 + lane;
+                    T cj[3] = {T(0), T(0), T(0)}, ck[3] = {T(0), T(0), T(0)};
+                    if (p < ngrid) {
+                        // o = p / n3 + 1 without an integer division (the float
+                        // quotient of p + 1/2 sits at least 1/(2 n3) from an integer)
+                        const int o = (int)(((float)p + 0.5f) * rn3) + 1;
+                        const int j = p - (o - 1) * n3;
+                        if (!(even && o == hh && j >= hh)) {
+                            int k = j + o;
+                            if (k >= n3)
+                                k -= n3;
+                            leg_pair(j, k, cj, ck);
                         }
-                        // contract the r_jk basis first, then leg k, then leg j
-                        T V = T(0), V1 = T(0), V2 = T(0), V3 = T(0);
-#pragma unroll
-                        for (int pa = 0; pa < 4; ++pa) {
-                            T u0 = T(0), uk = T(0), u1 = T(0);
-#pragma unroll
-                            for (int q = 0; q < 4; ++q) {
-                                T cr[4];
-                                load4(cz + ((((fj + pa) * nb + (fk + q)) * (nb - 3) + fs) << 2), cr);
-                                const T s0 = ((cr[0] * Ns[0] + cr[1] * Ns[1]) + cr[2] * Ns[2]) + cr[3] * Ns[3];
-                                const T s1 =
-                                    ((cr[0] * dNs[0] + cr[1] * dNs[1]) + cr[2] * dNs[2]) + cr[3] * dNs[3];
-                                u0 += s0 * Bk[q];
-                                uk += s0 * dBk[q];
-                                u1 += s1 * Bk[q];
+                    }
+                    rb[lane * 6 + 0] = cj[0];
+                    rb[lane * 6 + 1] = cj[1];
+                    rb[lane * 6 + 2] = cj[2];
+                    rb[lane * 6 + 3] = ck[0];
+                    rb[lane * 6 + 4] = ck[1];
+                    rb[lane * 6 + 5] = ck[2];
+                    wave_sync_lds_u();
+                    if (lane < n3) {
+                        const int x = lane;
+                        for (int o = 1; o <= hh; ++o) {
+                            // pair (x, x + o): x is the first leg
+                            const int q1 = (o - 1) * n3 + x - t0;
+                            if (!(even && o == hh && x >= hh) && q1 >= 0 && q1 < 64) {
+                                gx += rb[q1 * 6 + 0];
+                                gy += rb[q1 * 6 + 1];
+                                gz += rb[q1 * 6 + 2];
                             }
-                            V += Bj[pa] * u0;
-                            V1 += dBj[pa] * u0;
-                            V2 += Bj[pa] * uk;
-                            V3 += Bj[pa] * u1;
-                        }
-                        Ep += V;
-                        const T irjk = fast_rcp(rjk);
-                        const T aj = V1 * ir3[j], ak = V2 * ir3[k], ajk = V3 * irjk;
-                        cj0 = aj * dj0 - ajk * e0;
-                        cj1 = aj * dj1 - ajk * e1;
-                        cj2 = aj * dj2 - ajk * e2;
-                        ck0 = ak * dk0 + ajk * e0;
-                        ck1 = ak * dk1 + ajk * e1;
-                        ck2 = ak * dk2 + ajk * e2;
-                    }
-                }
-                rb[lane * 6 + 0] = cj0;
-                rb[lane * 6 + 1] = cj1;
-                rb[lane * 6 + 2] = cj2;
-                rb[lane * 6 + 3] = ck0;
-                rb[lane * 6 + 4] = ck1;
-                rb[lane * 6 + 5] = ck2;
-                wave_sync_lds_u();
-                if (lane < n3) {
-                    const int x = lane;
-                    for (int o = 1; o <= hh; ++o) {
-                        // pair (x, x + o): x is the first leg
-                        const int q1 = (o - 1) * n3 + x - t0;
-                        if (!(even && o == hh && x >= hh) && q1 >= 0 && q1 < 64) {
-                            gx += rb[q1 * 6 + 0];
-                            gy += rb[q1 * 6 + 1];
-                            gz += rb[q1 * 6 + 2];
-                        }
-                        // pair (x - o, x): x is the second leg
-                        int jp = x - o;
-                        if (jp < 0)
-                            jp += n3;
-                        const int q2 = (o - 1) * n3 + jp - t0;
-                        if (!(even && o == hh && jp >= hh) && q2 >= 0 && q2 < 64) {
-                            gx += rb[q2 * 6 + 3];
-                            gy += rb[q2 * 6 + 4];
-                            gz += rb[q2 * 6 + 5];
+                            // pair (x - o, x): x is the second leg
+                            int jp = x - o;
+                            if (jp < 0)
+                                jp += n3;
+                            const int q2 = (o - 1) * n3 + jp - t0;
+                            if (!(even && o == hh && jp >= hh) && q2 >= 0 && q2 < 64) {
+                                gx += rb[q2 * 6 + 3];
+                                gy += rb[q2 * 6 + 4];
+                                gz += rb[q2 * 6 + 5];
+                            }
                         }
                     }
+                    wave_sync_lds_u();
                 }
-                wave_sync_lds_u();
             }
             // leg sums back to the lanes that own the legs' slots
             if (lane < n3) {

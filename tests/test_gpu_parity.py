@@ -70,6 +70,36 @@ def test_tiny_nonperiodic_cylinder_fp64():
     _check(w, "mixed", "fp64")
 
 
+@pytest.mark.parametrize("scale,rcut3,sigma", [(1.15, 3.2, 0.3), (0.8, 4.0, 0.3), (0.82, 4.2, 0.35)])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_three_body_leg_counts(scale, rcut3, sigma, precision):
+    """Strongly jittered bcc cells, stretched or compressed, with the 3-body
+    cutoff set so that the per-atom counts of 3-body legs span 1-8 (stretched)
+    or the mid twenties to about forty (compressed): the cheap kernel's two
+    layouts of the leg pairs (offset blocks, and 64 pairs per round for the
+    counts where blocks would take more rounds), including blocks that hold
+    no pair, all carry atoms."""
+    w = W.tiny(seed=7, n_species=2, cells=4, sigma=sigma)
+    w["pos"] = w["pos"] * scale
+    w["L"] = w["L"] * scale
+    w["model"]["uf3"]["rcut3"] = rcut3
+    d = w["pos"][None, :, :] - w["pos"][:, None, :]
+    d -= w["L"] * np.round(d / w["L"])
+    r2 = (d ** 2).sum(-1)
+    np.fill_diagonal(r2, np.inf)
+    n3 = (r2 < rcut3 ** 2).sum(1)
+    s = 64 // np.maximum(n3, 1)
+    blocks = -(-(n3 // 2) // s) <= -(-(n3 * (n3 // 2)) // 64)
+    print(f"  legs {n3.min()}..{n3.max()}, {blocks.sum()} atoms in blocks, "
+          f"{(~blocks).sum()} cyclic", flush=True)
+    assert n3.max() <= 64
+    if scale > 1:
+        assert n3.min() <= 2 and n3.max() <= 8
+    else:
+        assert blocks.any() and (~blocks).any()
+    _check(w, "all_cheap", precision)
+
+
 def test_c2_fp32_mixed():
     _check(W.c2(), "mixed", "fp32")
 
