@@ -80,6 +80,15 @@ __host__ __device__ constexpr int o3_row_bytes(int qm, int nc)
     return qm == 0 ? 4 * (nc < 8 ? nc : 8) * nc + 16 : 4 * nc * 4 * (qm == 1 ? 2 : 1) + 16;
 }
 
+// Workgroup b of a grid of gd runs on XCD b mod 8 (round-robin dispatch);
+// numbering the workgroups XCD by XCD (a bijection when gd is a multiple of
+// 8) puts consecutive work items, the splits of one tile, on one XCD, so
+// the tile's A rows come from that XCD's L2 after the first fetch.
+__device__ __forceinline__ int xcd_major(int b, int gd)
+{
+    return (gd & 7) ? b : (b & 7) * (gd >> 3) + (b >> 3);
+}
+
 __device__ __forceinline__ void wave_sync_lds()
 {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -443,7 +452,8 @@ __global__ void __launch_bounds__(64 * NW, NC <= 12 ? 3 : 2)
         ++lg;
     }
     const int nitem = ntile * G;
-    if ((int)blockIdx.x >= nitem)
+    const int vb = xcd_major(blockIdx.x, gridDim.x);
+    if (vb >= nitem)
         return;  // uniform across the workgroup
     const int tid = threadIdx.x, lane = tid & 63;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -466,7 +476,7 @@ __global__ void __launch_bounds__(64 * NW, NC <= 12 ? 3 : 2)
     f4v a1[2][NC / 4];
     float a2[2][NJ];
 
-    for (int item = blockIdx.x; item < nitem; item += gridDim.x) {
+    for (int item = vb; item < nitem; item += gridDim.x) {
         const int tile = item >> lg, bin = (item & (G - 1)) * NW + wv;
         const int r_lo = rbeg[bin], nr = rbeg[bin + 1] - r_lo;  // nr <= 128 (host check)
         const int s0 = tile * kO3Atoms;
