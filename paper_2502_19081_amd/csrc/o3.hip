@@ -829,7 +829,8 @@ __global__ void __launch_bounds__(256, 1)
         ++lg;
     }
     const int nitem = ntile * G;
-    if ((int)blockIdx.x >= nitem)
+    const int vb = xcd_major(blockIdx.x, gridDim.x);
+    if (vb >= nitem)
         return;  // uniform across the workgroup
     const int tid = threadIdx.x, lane = tid & 63;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -843,7 +844,7 @@ __global__ void __launch_bounds__(256, 1)
     const int *wbeg = a.wbeg + 4 * (G - 1) + lg;
     const size_t wz = (size_t)a.n_pb * NC * NT * 64 * NJP;  // weight floats per species
 
-    for (int item = blockIdx.x; item < nitem; item += gridDim.x) {
+    for (int item = vb; item < nitem; item += gridDim.x) {
         const int tile = item >> lg, bin = ((item & (G - 1)) << 2) + wv;
         const int w_lo = wbeg[bin], w_hi = wbeg[bin + 1];
         const int s0 = tile * kO3Atoms;
