@@ -1275,10 +1275,104 @@ __global__ void __launch_bounds__(256) k_cmp_apply(const uint8_t *__restrict__ f
     }
 }
 
+// Small systems (at most kCmpSmallBlocks blocks of 256 atoms): one atom per
+// thread and one launch with one round of loads. Each block counts the flags
+// before it (at most 16 words of four flags per thread, all issued at once)
+// and ranks its own atoms by wave ballots; the same S, M and counts as the
+// tiled passes.
+constexpr int kCmpSmallBlocks = 64;
+
+__global__ void __launch_bounds__(256) k_cmp_small(const uint8_t *__restrict__ flags, int n,
+                                                   int *hdr, int32_t *n_expensive,
+                                                   int *__restrict__ S_idx,
+                                                   int *__restrict__ M_idx,
+                                                   int *__restrict__ S_local, int scap)
+{
+    __shared__ int cS[4], cM[4], bS[4], bM[4];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int i = (int)blockIdx.x * 256 + tid;
+    const uint8_t f = i < n ? flags[i] : (uint8_t)0;
+    const int lim = (int)blockIdx.x * 256;  // flags before this block
+    int os = 0, om = 0;
+    if ((reinterpret_cast<uintptr_t>(flags) & 3) == 0) {
+        const uint32_t *fw = reinterpret_cast<const uint32_t *>(flags);
+        uint32_t v[kCmpSmallBlocks / 4];
+#pragma unroll
+        for (int k = 0; k < kCmpSmallBlocks / 4; ++k) {
+            const int e = k * 256 + tid;
+            v[k] = e < lim / 4 ? fw[e] : 0u;
+        }
+#pragma unroll
+        for (int k = 0; k < kCmpSmallBlocks / 4; ++k)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const uint32_t b = (v[k] >> (8 * q)) & 0xffu;
+                os += (b & 5u) ? 1 : 0;
+                om += (b & 1u) ? 1 : 0;
+            }
+    } else {
+        for (int e = tid; e < lim; e += 256) {
+            const uint8_t b = flags[e];
+            os += (b & 5) ? 1 : 0;
+            om += (b & 1) ? 1 : 0;
+        }
+    }
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) {
+        os += __shfl_xor(os, d);
+        om += __shfl_xor(om, d);
+    }
+    const bool inS = (f & 5) != 0, inM = (f & 1) != 0;
+    const unsigned long long mS = __ballot(inS), mM = __ballot(inM);
+    const unsigned long long lt = (1ull << lane) - 1ull;
+    if (lane == 0) {
+        cS[w] = __popcll(mS);
+        cM[w] = __popcll(mM);
+        bS[w] = os;
+        bM[w] = om;
+    }
+    __syncthreads();
+    int es = __popcll(mS & lt), em = __popcll(mM & lt), tS = 0, tM = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        es += bS[k] + (k < w ? cS[k] : 0);
+        em += bM[k] + (k < w ? cM[k] : 0);
+        tS += bS[k] + cS[k];
+        tM += bM[k] + cM[k];
+    }
+    if (i < n) {
+        if (inS) {
+            S_idx[es] = i;
+            S_local[i] = es < scap ? es : -1;
+        } else {
+            S_local[i] = -1;
+        }
+        if (inM)
+            M_idx[em] = i;
+    }
+    if (blockIdx.x == gridDim.x - 1 && tid == 0) {
+        hdr[H_NS] = tS < scap ? tS : scap;
+        if (tS > scap)
+            atomicOr(&hdr[H_STATUS], MLMIX_STATUS_S_OVERFLOW);
+        hdr[H_NM] = tM;
+        if (n_expensive) {
+            n_expensive[0] = tS;
+            n_expensive[1] = tM;
+        }
+    }
+}
+
 void launch_compact(hipStream_t s, void *ws, const WsLayout &L, uint8_t *flags,
                     int32_t *n_expensive)
 {
     int n = L.n;
+    if (n <= kCmpSmallBlocks * 256) {
+        const int nb = n > 0 ? (n + 255) / 256 : 1;
+        k_cmp_small<<<nb, 256, 0, s>>>(flags, n, at<int>(ws, L.hdr), n_expensive,
+                                       at<int>(ws, L.S_idx), at<int>(ws, L.M_idx),
+                                       at<int>(ws, L.S_local), L.scap);
+        return;
+    }
     int nb = (n + kScanTile - 1) / kScanTile;
     if (nb < 1)
         nb = 1;
