@@ -80,15 +80,6 @@ __host__ __device__ constexpr int o3_row_bytes(int qm, int nc)
     return qm == 0 ? 4 * (nc < 8 ? nc : 8) * nc + 16 : 4 * nc * 4 * (qm == 1 ? 2 : 1) + 16;
 }
 
-// Workgroup b of a grid of gd runs on XCD b mod 8 (round-robin dispatch);
-// numbering the workgroups XCD by XCD (a bijection when gd is a multiple of
-// 8) puts consecutive work items, the splits of one tile, on one XCD, so
-// the tile's A rows come from that XCD's L2 after the first fetch.
-__device__ __forceinline__ int xcd_major(int b, int gd)
-{
-    return (gd & 7) ? b : (b & 7) * (gd >> 3) + (b >> 3);
-}
-
 __device__ __forceinline__ void wave_sync_lds()
 {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -452,6 +443,8 @@ __global__ void __launch_bounds__(64 * NW, NC <= 12 ? 3 : 2)
         ++lg;
     }
     const int nitem = ntile * G;
+    // the splits of one tile on one XCD: its A rows come from that XCD's L2
+    // after the first fetch
     const int vb = xcd_major(blockIdx.x, gridDim.x);
     if (vb >= nitem)
         return;  // uniform across the workgroup
@@ -829,6 +822,8 @@ __global__ void __launch_bounds__(256, 1)
         ++lg;
     }
     const int nitem = ntile * G;
+    // the splits of one tile on one XCD: its A rows come from that XCD's L2
+    // after the first fetch
     const int vb = xcd_major(blockIdx.x, gridDim.x);
     if (vb >= nitem)
         return;  // uniform across the workgroup

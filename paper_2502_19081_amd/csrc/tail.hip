@@ -50,8 +50,14 @@ __global__ void __launch_bounds__(256)
                    double *__restrict__ f_cheap, double sign, KickArgs ka, LangevinArgs la,
                    Seg sg)
 {
+    // workgroup vb takes atoms 16 vb ...; small systems number the
+    // workgroups XCD by XCD (the grid is then padded to a multiple of 8)
+    const int nbk = (n + kGatherAtoms - 1) / kGatherAtoms;
+    const int vb = n <= kGatherXcdMax ? xcd_major(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    if (vb >= nbk)
+        return;  // uniform across the workgroup (padding)
     const int ga = threadIdx.x >> 4;  // atom of the workgroup
-    const int i = blockIdx.x * kGatherAtoms + ga;
+    const int i = vb * kGatherAtoms + ga;
     const int lane = threadIdx.x & 15;  // slot lane within the atom's row
     double ee = 0.0, ec = 0.0, ke = 0.0;  // energy terms of atom i (lane 0, KICK)
     if (i < n) {
@@ -176,7 +182,7 @@ __global__ void __launch_bounds__(256)
             for (int w = kGatherAtoms / 2; w > 0; w >>= 1)  // pairwise, fixed order
                 for (int k = 0; k < w; ++k)
                     v[k] = v[k] + v[k + w];
-            ka.part[blockIdx.x * 3 + q] = v[0];
+            ka.part[vb * 3 + q] = v[0];
         }
     }
 }
@@ -193,6 +199,7 @@ void launch_gather_blend(hipStream_t s, const Ctx &c, void *ws, const WsLayout &
     if (n == 0)
         return;
     unsigned nb = (n + kGatherAtoms - 1) / kGatherAtoms;
+    const unsigned grid = n <= kGatherXcdMax ? (nb + 7) / 8 * 8 : nb;
     LangevinArgs la{};
     if (lang)
         la = *lang;
@@ -206,13 +213,13 @@ void launch_gather_blend(hipStream_t s, const Ctx &c, void *ws, const WsLayout &
     auto go = [&](auto kern, auto tc) {
         using T = typename decltype(tc)::type;
         if (ev0)
-            hipExtLaunchKernelGGL(kern, dim3(nb), dim3(256), 0, s, ev0, ev1, 0u, n, L.cap,
+            hipExtLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, s, ev0, ev1, 0u, n, L.cap,
                                   at<int>(ws, L.nbr), at<int>(ws, L.cnt), at<int>(ws, L.rev),
                                   at<int>(ws, L.S_local), at<T>(ws, L.g), at<T>(ws, L.h), use_exp,
                                   use_cheap, lambda, forces, e_exp, f_exp, f_cheap, sign, ka, la,
                                   seg_args(ws, L));
         else
-            kern<<<nb, 256, 0, s>>>(n, L.cap, at<int>(ws, L.nbr), at<int>(ws, L.cnt),
+            kern<<<grid, 256, 0, s>>>(n, L.cap, at<int>(ws, L.nbr), at<int>(ws, L.cnt),
                                     at<int>(ws, L.rev), at<int>(ws, L.S_local), at<T>(ws, L.g),
                                     at<T>(ws, L.h), use_exp, use_cheap, lambda, forces, e_exp,
                                     f_exp, f_cheap, sign, ka, la, seg_args(ws, L));
