@@ -375,10 +375,6 @@ struct KickArgs {
 };
 constexpr int kGatherKickMax = 65536;
 constexpr int kGatherAtoms = 16;  // atoms per workgroup of the force gather (16 lanes each)
-// Systems up to this many atoms run the force gather XCD by XCD (the rows
-// around a workgroup's atoms then stay in one L2).
-constexpr int kGatherXcdMax = 65536;
-
 // Workgroup b of a grid of gd runs on XCD b mod 8 (round-robin dispatch);
 // numbering the workgroups XCD by XCD (a bijection when gd is a multiple of
 // 8) gives each XCD a contiguous range of work items.

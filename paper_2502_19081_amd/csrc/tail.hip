@@ -50,10 +50,12 @@ __global__ void __launch_bounds__(256)
                    double *__restrict__ f_cheap, double sign, KickArgs ka, LangevinArgs la,
                    Seg sg)
 {
-    // workgroup vb takes atoms 16 vb ...; small systems number the
-    // workgroups XCD by XCD (the grid is then padded to a multiple of 8)
+    // workgroup vb takes atoms 16 vb ...; the workgroups are numbered XCD by
+    // XCD (the grid is padded to a multiple of 8), so each XCD takes a
+    // contiguous range of atoms and the partner rows around it stay in its
+    // L2
     const int nbk = (n + kGatherAtoms - 1) / kGatherAtoms;
-    const int vb = n <= kGatherXcdMax ? xcd_major(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    const int vb = xcd_major(blockIdx.x, gridDim.x);
     if (vb >= nbk)
         return;  // uniform across the workgroup (padding)
     const int ga = threadIdx.x >> 4;  // atom of the workgroup
@@ -199,7 +201,7 @@ void launch_gather_blend(hipStream_t s, const Ctx &c, void *ws, const WsLayout &
     if (n == 0)
         return;
     unsigned nb = (n + kGatherAtoms - 1) / kGatherAtoms;
-    const unsigned grid = n <= kGatherXcdMax ? (nb + 7) / 8 * 8 : nb;
+    const unsigned grid = (nb + 7) / 8 * 8;
     LangevinArgs la{};
     if (lang)
         la = *lang;
