@@ -307,6 +307,7 @@ void launch_ace_o3(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L,
                    hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 size_t o3_lds_bytes(const Ctx &c);
 size_t o3v_lds_bytes(const Ctx &c);
+int o3v_waves(const Ctx &c, int n);
 int o3v_grid(const Ctx &c, int n);
 void launch_ace_o3w(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L,
                     const int32_t *species, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
@@ -374,6 +375,9 @@ struct KickArgs {
     DispCheck chk;     // skin check of the next step's drifted positions (next != 0)
 };
 constexpr int kGatherKickMax = 65536;
+// S capacities above this run the vector-sparse contraction in four-wave
+// workgroups (two bins of the eight-wave table per wave)
+constexpr int kO3FourWaveMin = 65536;
 constexpr int kGatherAtoms = 16;  // atoms per workgroup of the force gather (16 lanes each)
 // Workgroup b of a grid of gd runs on XCD b mod 8 (round-robin dispatch);
 // numbering the workgroups XCD by XCD (a bijection when gd is a multiple of

@@ -426,7 +426,7 @@ __global__ void __launch_bounds__(64 * NW, NW == 4 ? 2 : 1)
 // row with the next row's vector work inside one wave needs P and the
 // weights twice in registers: one wave per SIMD at 16 channels, measured
 // slower, 4.4 against 3.3 ms on 102,858 atoms in S, and no faster at 12.)
-template <int QM, int NC, int NW>
+template <int QM, int NC, int NW, int BPW>  // BPW bins of the eight-wave table per wave
 __global__ void __launch_bounds__(64 * NW, NC <= 12 ? 3 : 2)
     k_ace_o3v(const int *__restrict__ hdr, O3Args a, const float *__restrict__ A,
               float *__restrict__ Dpart)
@@ -456,7 +456,7 @@ __global__ void __launch_bounds__(64 * NW, NC <= 12 ? 3 : 2)
     extern __shared__ __align__(16) char smem_raw[];
     float *At = reinterpret_cast<float *>(smem_raw);  // [16][astr]
     const float *At_t = At + (size_t)m * astr;       // this lane's atom (t = m)
-    const int *rbeg = a.rbeg + NW * (G - 1) + lg;
+    const int *rbeg = a.rbeg + NW * BPW * (G - 1) + lg;  // the table's bins: NW BPW per split
     const int2 *etab = reinterpret_cast<const int2 *>(a.e);
     const int4 *rows = reinterpret_cast<const int4 *>(a.rowv);
 
@@ -469,8 +469,9 @@ __global__ void __launch_bounds__(64 * NW, NC <= 12 ? 3 : 2)
     f4v a1[2][NC / 4];
     float a2[2][NJ];
 
-    for (int item = vb; item < nitem; item += gridDim.x) {
-        const int tile = item >> lg, bin = (item & (G - 1)) * NW + wv;
+    for (int item = vb; item < nitem; item += gridDim.x)
+    for (int bb = 0; bb < BPW; ++bb) {  // the wave's bins of this item, in order
+        const int tile = item >> lg, bin = ((item & (G - 1)) * NW + wv) * BPW + bb;
         const int r_lo = rbeg[bin], nr = rbeg[bin + 1] - r_lo;  // nr <= 128 (host check)
         const int s0 = tile * kO3Atoms;
         const int na = min(kO3Atoms, nS - s0);
@@ -538,16 +539,18 @@ __global__ void __launch_bounds__(64 * NW, NC <= 12 ? 3 : 2)
             weights(field(0, 2) & 0xffff);
             entE[0] = entries(0, neE[0]);
         }
-        __syncthreads();  // every wave is done with the previous tile's A
-        for (int r = tid; r < kO3Atoms * L2; r += NTH) {
-            const int t = r / L2, lm = r - t * L2;
-            f4v *dst = reinterpret_cast<f4v *>(At + (size_t)t * astr + lm * 16);
-            const f4v *src = reinterpret_cast<const f4v *>(A + (size_t)(s0 + t) * a.KAt + lm * NC);
+        if (bb == 0) {  // the tile's A rows, once per item (bb is uniform)
+            __syncthreads();  // every wave is done with the previous tile's A
+            for (int r = tid; r < kO3Atoms * L2; r += NTH) {
+                const int t = r / L2, lm = r - t * L2;
+                f4v *dst = reinterpret_cast<f4v *>(At + (size_t)t * astr + lm * 16);
+                const f4v *src = reinterpret_cast<const f4v *>(A + (size_t)(s0 + t) * a.KAt + lm * NC);
 #pragma unroll
-            for (int c4 = 0; c4 < NC / 4; ++c4)
-                dst[c4] = t < na ? src[c4] : (f4v){0.f, 0.f, 0.f, 0.f};
+                for (int c4 = 0; c4 < NC / 4; ++c4)
+                    dst[c4] = t < na ? src[c4] : (f4v){0.f, 0.f, 0.f, 0.f};
+            }
+            __syncthreads();
         }
-        __syncthreads();
 
         // D of the last row: lane holds D[atom = 4 q + v][c = m]; lanes
         // outside the tile or the channels (and every lane before the first
@@ -723,10 +726,19 @@ __global__ void __launch_bounds__(64 * NW, NC <= 12 ? 3 : 2)
 // grid of the vector-sparse contraction over a capacity of n S atoms: as
 // many resident workgroups as the registers allow (waves per SIMD: three up
 // to 12 channels, else two), at most one per (tile, split) item
+// waves per workgroup of the vector-sparse contraction for a capacity of n
+// S atoms: eight by default; large systems run four-wave workgroups that
+// take the eight-wave table's bins two per wave (more, smaller workgroups
+// balance the many tiles better)
+int o3v_waves(const Ctx &c, int n)
+{
+    return c.o3_waves == 8 && n > kO3FourWaveMin ? 4 : c.o3_waves;
+}
+
 int o3v_grid(const Ctx &c, int n)
 {
     const long items = (((long)n + kO3Atoms - 1) / kO3Atoms) * kO3MaxSplit;
-    const int nw = c.o3_waves == 8 ? 8 : 4;
+    const int nw = o3v_waves(c, n) == 8 ? 8 : 4;
     const int per_cu = std::max(1, 4 * (c.m.nchp <= 12 ? 3 : 2) / nw);
     return (int)std::min<long>(std::max<long>(items, 1), 256L * per_cu);
 }
@@ -1132,19 +1144,22 @@ void launch_ace_o3(hipStream_t s, const Ctx &c, void *ws, const WsLayout &L, hip
         const size_t lds = o3v_lds_bytes(c);
         auto go = [&](auto qm, auto nc) {
             constexpr int QM = decltype(qm)::value, NC = decltype(nc)::value;
-            auto launch = [&](auto nw) {
-                constexpr int NW = decltype(nw)::value;
+            auto launch = [&](auto nw, auto bpw) {
+                constexpr int NW = decltype(nw)::value, BPW = decltype(bpw)::value;
                 const int grid = o3v_grid(c, L.n);
                 if (ev0)
-                    hipExtLaunchKernelGGL(k_ace_o3v<QM, NC, NW>, dim3(grid), dim3(64 * NW),
+                    hipExtLaunchKernelGGL(k_ace_o3v<QM, NC, NW, BPW>, dim3(grid), dim3(64 * NW),
                                           (uint32_t)lds, s, ev0, ev1, 0u, hdr, a, A, D);
                 else
-                    k_ace_o3v<QM, NC, NW><<<grid, 64 * NW, lds, s>>>(hdr, a, A, D);
+                    k_ace_o3v<QM, NC, NW, BPW><<<grid, 64 * NW, lds, s>>>(hdr, a, A, D);
             };
-            if (c.o3_waves == 8)
-                launch(std::integral_constant<int, 8>());
+            // the bins were built for c.o3_waves waves per workgroup
+            if (c.o3_waves != 8)
+                launch(std::integral_constant<int, 4>(), std::integral_constant<int, 1>());
+            else if (o3v_waves(c, L.n) == 4)
+                launch(std::integral_constant<int, 4>(), std::integral_constant<int, 2>());
             else
-                launch(std::integral_constant<int, 4>());
+                launch(std::integral_constant<int, 8>(), std::integral_constant<int, 1>());
         };
         auto by_width = [&](auto qm) {
             switch (m.nchp) {
